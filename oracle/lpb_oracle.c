@@ -1,0 +1,1852 @@
+/*
+ * lpb_oracle.c -- TEST INFRASTRUCTURE ONLY.
+ *
+ * Plain, slow, FP64 CPU oracle for the layered-media linearized
+ * Poisson-Boltzmann (screened Coulomb / Yukawa) potential and its fast
+ * multipole method, written from B. Wang, W. Z. Zhang, W. Cai, "Fast Multipole
+ * Method for 3-D Linearized Poisson-Boltzmann Equation in Layered Media"
+ * (arXiv 2002.01334).  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library; the GPU product path
+ * never does.  It shares no code, header, table or constant generator with
+ * the GPU library.
+ *
+ * Contents (paper section / equation each function follows):
+ *   - special functions: modified spherical Bessel i_n, k_n (Sec. 3.1),
+ *     normalised associated Legendre P^_n^m, spherical harmonics Y_n^m
+ *     (Sec. 3.1 definition), Gaunt integrals of three harmonics (Thm 3.2/3.3),
+ *     Gauss-Legendre nodes.
+ *   - reaction densities sigma^{ab}_{ll'} of the three-layer medium
+ *     (eqs. densitythreelayer1-3), in an overflow-free scaled form.
+ *   - direct O(N^2) sum of the layered Green's function (eqs. potential1,
+ *     totalinteraction, generalcomponents, zexponential), reaction parts by
+ *     composite Gauss-Legendre quadrature of the Sommerfeld integrals after
+ *     the angular integral is done with the J_n identity (Sec. 3.5).
+ *   - CPU FMM (Algorithms 1 and 2): free-space Yukawa FMM with the addition
+ *     theorem operators (eqs. melecoeffree, metole, metome), and one FMM per
+ *     reaction component over equivalent polarization sources
+ *     (eqs. equivpolarcoord, melayerupgoingimage, lelayerimage) whose M2L
+ *     operators come from quadrature of the initial values, the forward
+ *     recurrence (eq. recurrence1), the Legendre-product expansion
+ *     (eq. metoletableform) and eq. coefintable.
+ *
+ * Readings of places where the printed text is garbled or silent are listed
+ * at each use (sigma typos, index order of the translation sums, Gaunt
+ * prefactors, the spurious factorial in C^s, the garbled factorial in C~^s).
+ *
+ * Parity pins: every function here is checked by tests/test_oracle_*.py
+ * against closed forms, identities or library routines; see the test files.
+ */
+#include <complex.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+typedef double complex cplx;
+
+#define ORC_PI 3.14159265358979323846
+#define ORC_HMAX 16        /* bits per dimension of the fine cell code       */
+#define ORC_MAXDEPTH 12    /* deepest tree level the oracle builds           */
+#define ORC_PMAX 20        /* largest expansion order supported              */
+#define ORC_NGL 16         /* Gauss-Legendre points per quadrature panel     */
+#define ORC_MAXL 8         /* most interfaces                                */
+
+/* ------------------------------------------------------------------------ */
+/* factorials and small helpers                                             */
+/* ------------------------------------------------------------------------ */
+
+static double g_fact[171];
+static double g_gl16_x[ORC_NGL], g_gl16_w[ORC_NGL];
+#define ORC_NGAUNT 64
+static double g_gl64_x[ORC_NGAUNT], g_gl64_w[ORC_NGAUNT];
+
+void orc_gauss_legendre(int n, double* x, double* w);
+
+#define ORC_GNMAX (2 * ORC_PMAX)
+static double g_plm64[ORC_NGAUNT][(ORC_GNMAX + 1) * (ORC_GNMAX + 2) / 2];
+void orc_plm(int nmax, double x, double* out);
+
+__attribute__((constructor)) static void orc_init(void)
+{
+    g_fact[0] = 1.0;
+    for (int k = 1; k <= 170; ++k) g_fact[k] = g_fact[k - 1] * (double)k;
+    orc_gauss_legendre(ORC_NGL, g_gl16_x, g_gl16_w);
+    orc_gauss_legendre(ORC_NGAUNT, g_gl64_x, g_gl64_w);
+    for (int k = 0; k < ORC_NGAUNT; ++k) orc_plm(ORC_GNMAX, g_gl64_x[k], g_plm64[k]);
+}
+
+static double fact(int n) { return (n < 0 || n > 170) ? NAN : g_fact[n]; }
+static double sgn_pow(int k) { return (k % 2 == 0) ? 1.0 : -1.0; } /* (-1)^k */
+static int iabs(int k) { return k < 0 ? -k : k; }
+static int idx_nm(int n, int m) { return n * n + n + m; } /* m = -n..n */
+
+/* i^k for integer k */
+static cplx ipow(int k)
+{
+    int r = ((k % 4) + 4) % 4;
+    if (r == 0) return 1.0;
+    if (r == 1) return I;
+    if (r == 2) return -1.0;
+    return -I;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Gauss-Legendre nodes on [-1,1] by Newton iteration on P_n                */
+/* ------------------------------------------------------------------------ */
+void orc_gauss_legendre(int n, double* x, double* w)
+{
+    for (int i = 0; i < n; ++i) {
+        double z = cos(ORC_PI * (i + 0.75) / (n + 0.5));
+        double p1 = 0, p2 = 0, dp = 0;
+        for (int it = 0; it < 100; ++it) {
+            p1 = 1.0;
+            p2 = 0.0;
+            for (int j = 1; j <= n; ++j) {
+                double p3 = p2;
+                p2 = p1;
+                p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+            }
+            dp = n * (z * p1 - p2) / (z * z - 1.0);
+            double dz = p1 / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        p1 = 1.0;
+        p2 = 0.0;
+        for (int j = 1; j <= n; ++j) {
+            double p3 = p2;
+            p2 = p1;
+            p1 = ((2.0 * j - 1.0) * z * p2 - (j - 1.0) * p3) / j;
+        }
+        dp = n * (z * p1 - p2) / (z * z - 1.0);
+        x[i] = z;
+        w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Modified spherical Bessel functions (Sec. 3.1: i_n(z) = i^{-n} j_n(iz),  */
+/* k_n(z) = -(pi/2) i^n h_n^(1)(iz), so k_0(x) = (pi/2) e^{-x}/x).          */
+/* ------------------------------------------------------------------------ */
+
+/* i_n(x) from its power series sum_k x^{n+2k} / (2^k k! (2n+2k+1)!!);
+ * all terms are positive, so the sum has no cancellation. */
+double orc_bessel_i(int n, double x)
+{
+    if (x == 0.0) return n == 0 ? 1.0 : 0.0;
+    double term = 1.0;
+    for (int k = 1; k <= n; ++k) term *= x / (2.0 * k + 1.0);
+    double sum = term;
+    for (int k = 1; k < 2000; ++k) {
+        term *= x * x / (2.0 * k * (2.0 * n + 2.0 * k + 1.0));
+        sum += term;
+        if (term < 1e-18 * sum) break;
+    }
+    return sum;
+}
+
+/* k_n(x) = (pi/(2x)) e^{-x} sum_{k=0}^n (n+k)! / (k! (n-k)!) (2x)^{-k}. */
+double orc_bessel_k(int n, double x)
+{
+    double s = 0.0;
+    for (int k = 0; k <= n; ++k) s += fact(n + k) / (fact(k) * fact(n - k)) * pow(2.0 * x, -k);
+    return ORC_PI / (2.0 * x) * exp(-x) * s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Normalised associated Legendre functions and spherical harmonics         */
+/* (Sec. 3.1): Y_n^m = P^_n^m(cos t) e^{i m p},                             */
+/* P^_n^m = sqrt((2n+1)/(4 pi) (n-m)!/(n+m)!) (1-x^2)^{m/2} d^m P_n / dx^m  */
+/* for m >= 0, and P^_n^{-m} = (-1)^m P^_n^m, so Y_n^{-m} = (-1)^m conj Y.  */
+/* The paper's (-1)^m convention factor cancels in every product used by    */
+/* the method (an expansion coefficient always meets its conjugate).        */
+/* ------------------------------------------------------------------------ */
+static double cnm(int n, int m) { return sqrt((2.0 * n + 1.0) / (4.0 * ORC_PI) * fact(n - m) / fact(n + m)); }
+
+/* out[n(n+1)/2 + m] = P^_n^m(x), 0 <= m <= n <= nmax, |x| <= 1 */
+void orc_plm(int nmax, double x, double* out)
+{
+    double s = sqrt(fmax(0.0, 1.0 - x * x));
+    double pmm = 1.0; /* (2m-1)!! s^m */
+    for (int m = 0; m <= nmax; ++m) {
+        if (m > 0) pmm *= (2.0 * m - 1.0) * s;
+        double p0 = pmm, p1 = 0.0;
+        out[m * (m + 1) / 2 + m] = cnm(m, m) * p0;
+        if (m + 1 <= nmax) {
+            p1 = (2.0 * m + 1.0) * x * p0;
+            out[(m + 1) * (m + 2) / 2 + m] = cnm(m + 1, m) * p1;
+        }
+        for (int n = m + 2; n <= nmax; ++n) {
+            double pn = ((2.0 * n - 1.0) * x * p1 - (n + m - 1.0) * p0) / (double)(n - m);
+            p0 = p1;
+            p1 = pn;
+            out[n * (n + 1) / 2 + m] = cnm(n, m) * pn;
+        }
+    }
+}
+
+/* Y_n^m at the direction of (vx,vy,vz) for n <= nmax, all m; index n^2+n+m.
+ * The zero vector is given theta = phi = 0. */
+void orc_ylm(int nmax, double vx, double vy, double vz, double* re, double* im)
+{
+    double r = sqrt(vx * vx + vy * vy + vz * vz);
+    double ct = r > 0 ? vz / r : 1.0;
+    double ph = (vx == 0.0 && vy == 0.0) ? 0.0 : atan2(vy, vx);
+    double* P = (double*)malloc(sizeof(double) * (nmax + 1) * (nmax + 2) / 2);
+    orc_plm(nmax, ct, P);
+    for (int n = 0; n <= nmax; ++n)
+        for (int m = 0; m <= n; ++m) {
+            double v = P[n * (n + 1) / 2 + m];
+            re[idx_nm(n, m)] = v * cos(m * ph);
+            im[idx_nm(n, m)] = v * sin(m * ph);
+            if (m > 0) {
+                re[idx_nm(n, -m)] = sgn_pow(m) * v * cos(m * ph);
+                im[idx_nm(n, -m)] = -sgn_pow(m) * v * sin(m * ph);
+            }
+        }
+    free(P);
+}
+
+static void ylm_c(int nmax, double vx, double vy, double vz, cplx* Y)
+{
+    int K = (nmax + 1) * (nmax + 1);
+    double* re = (double*)malloc(sizeof(double) * 2 * K);
+    orc_ylm(nmax, vx, vy, vz, re, re + K);
+    for (int k = 0; k < K; ++k) Y[k] = re[k] + I * re[K + k];
+    free(re);
+}
+
+/* Gaunt integral G = int Y_{n1}^{m1} Y_{n2}^{m2} Y_{n3}^{m3} dOmega (no
+ * conjugations, the harmonics above).  The azimuthal integral is 2 pi when
+ * m1+m2+m3 = 0 and zero otherwise; the polar integrand is then a polynomial
+ * of degree n1+n2+n3 in cos(theta), integrated exactly by 64-point
+ * Gauss-Legendre (exact to degree 127). */
+double orc_gaunt(int n1, int m1, int n2, int m2, int n3, int m3)
+{
+    if (m1 + m2 + m3 != 0) return 0.0;
+    if (iabs(m1) > n1 || iabs(m2) > n2 || iabs(m3) > n3) return 0.0;
+    if (n1 > ORC_GNMAX || n2 > ORC_GNMAX || n3 > ORC_GNMAX || n1 + n2 + n3 > 2 * ORC_NGAUNT - 1) return NAN;
+    double f1 = m1 < 0 ? sgn_pow(-m1) : 1.0, f2 = m2 < 0 ? sgn_pow(-m2) : 1.0, f3 = m3 < 0 ? sgn_pow(-m3) : 1.0;
+    int i1 = n1 * (n1 + 1) / 2 + iabs(m1), i2 = n2 * (n2 + 1) / 2 + iabs(m2), i3 = n3 * (n3 + 1) / 2 + iabs(m3);
+    double s = 0.0;
+    for (int k = 0; k < ORC_NGAUNT; ++k) s += g_gl64_w[k] * g_plm64[k][i1] * g_plm64[k][i2] * g_plm64[k][i3];
+    return 2.0 * ORC_PI * f1 * f2 * f3 * s;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Layered medium                                                           */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int L;                      /* number of interfaces; layers 0..L      */
+    double eps[ORC_MAXL + 1];
+    double lam[ORC_MAXL + 1];
+    double d[ORC_MAXL];         /* d_0 > d_1 > ... > d_{L-1}              */
+} layers_t;
+
+static int layer_of(const layers_t* Ly, double z)
+{
+    int l = 0;
+    for (int k = 0; k < Ly->L; ++k)
+        if (Ly->d[k] > z) l = k + 1;
+    return l;
+}
+
+/* Reaction densities sigma^{ab}_{l lp}(lrho) of the three-layer medium,
+ * eqs. densitythreelayer1-3, with these readings of the printed text:
+ *  - the closed forms assume d_0 = 0; written here with the middle-layer
+ *    thickness D = d_0 - d_1 (cosh(-d_1 t) -> cosh(D t), e^{-d_1 t} -> e^{D t});
+ *  - sigma^{11}_{10}: the numerator factor printed lambda_1 lambda_1z is read
+ *    eps_1 lambda_1z (matches the transmission conditions);
+ *  - sigma^{21}_{11}: the printed '+' in (eps1 l1z + eps0 l0z) is read '-',
+ *    which makes it equal to sigma^{12}_{11} as the transmission conditions
+ *    require;
+ *  - every numerator and kappa are multiplied by 2 e^{-D l1z} so nothing
+ *    overflows for large lrho (cosh -> 1+x^2, sinh -> 1-x^2, e^{D l1z} -> 2,
+ *    no exponential -> 2x with x = e^{-D l1z}).
+ * Returns NAN for an invalid (l, lp, a, b). */
+double orc_sigma3(const double* eps, const double* lam, double d0, double d1, int l, int lp, int a, int b,
+                  double lrho)
+{
+    double D = d0 - d1;
+    double e0 = eps[0], e1 = eps[1], e2 = eps[2];
+    double z0 = sqrt(lam[0] * lam[0] + lrho * lrho);
+    double z1 = sqrt(lam[1] * lam[1] + lrho * lrho);
+    double z2 = sqrt(lam[2] * lam[2] + lrho * lrho);
+    double x = exp(-D * z1);
+    double x2 = x * x;
+    double kap = e1 * z1 * (e0 * z0 + e2 * z2) * (1.0 + x2) + (e1 * e1 * z1 * z1 + e0 * e2 * z0 * z2) * (1.0 - x2);
+    int key = ((l * 3 + lp) * 2 + (a - 1)) * 2 + (b - 1);
+#define SKEY(L_, LP_, A_, B_) ((((L_)*3 + (LP_)) * 2 + ((A_)-1)) * 2 + ((B_)-1))
+    switch (key) {
+    /* source in the top layer */
+    case SKEY(0, 0, 1, 1):
+        return (e1 * z1 * (e0 * z0 - e2 * z2) * (1.0 + x2) - (e1 * e1 * z1 * z1 - e0 * e2 * z0 * z2) * (1.0 - x2)) /
+               (e0 * kap);
+    case SKEY(1, 0, 1, 1): return 2.0 * x * e0 * z1 * (e1 * z1 - e2 * z2) / (e0 * kap);
+    case SKEY(1, 0, 2, 1): return 2.0 * e0 * z1 * (e1 * z1 + e2 * z2) / (e0 * kap);
+    case SKEY(2, 0, 2, 1): return 2.0 * x * 2.0 * e0 * e1 * z1 * z2 / (e0 * kap);
+    /* source in the middle layer */
+    case SKEY(0, 1, 1, 1): return 2.0 * x * e1 * z0 * (e1 * z1 - e2 * z2) / (e1 * kap);
+    case SKEY(0, 1, 1, 2): return 2.0 * e1 * z0 * (e1 * z1 + e2 * z2) / (e1 * kap);
+    case SKEY(1, 1, 1, 1): return 2.0 * (e1 * z1 - e2 * z2) * (e1 * z1 + e0 * z0) / (2.0 * e1 * kap);
+    case SKEY(1, 1, 1, 2): return 2.0 * x * (e1 * z1 - e2 * z2) * (e1 * z1 - e0 * z0) / (2.0 * e1 * kap);
+    case SKEY(1, 1, 2, 1): return 2.0 * x * (e1 * z1 - e2 * z2) * (e1 * z1 - e0 * z0) / (2.0 * e1 * kap);
+    case SKEY(1, 1, 2, 2): return 2.0 * (e1 * z1 + e2 * z2) * (e1 * z1 - e0 * z0) / (2.0 * e1 * kap);
+    case SKEY(2, 1, 2, 1): return 2.0 * e1 * z2 * (e0 * z0 + e1 * z1) / (e1 * kap);
+    case SKEY(2, 1, 2, 2): return 2.0 * x * e1 * z2 * (e1 * z1 - e0 * z0) / (e1 * kap);
+    /* source in the bottom layer */
+    case SKEY(0, 2, 1, 2): return 2.0 * x * 2.0 * e1 * z1 * e2 * z0 / (e2 * kap);
+    case SKEY(1, 2, 2, 2): return 2.0 * x * e2 * z1 * (e1 * z1 - e0 * z0) / (e2 * kap);
+    case SKEY(1, 2, 1, 2): return 2.0 * e2 * z1 * (e0 * z0 + e1 * z1) / (e2 * kap);
+    case SKEY(2, 2, 2, 2):
+        return (e1 * z1 * (e2 * z2 - e0 * z0) * (1.0 + x2) - (e1 * e1 * z1 * z1 - e0 * e2 * z0 * z2) * (1.0 - x2)) /
+               (e2 * kap);
+    default: return NAN;
+    }
+#undef SKEY
+}
+
+static double sigma(const layers_t* Ly, int l, int lp, int a, int b, double lrho)
+{
+    return orc_sigma3(Ly->eps, Ly->lam, Ly->d[0], Ly->d[1], l, lp, a, b, lrho);
+}
+
+/* A reaction component (l, lp, a, b) exists iff a=1 -> l<L, a=2 -> l>0,
+ * b=1 -> lp<L, b=2 -> lp>0 (eqs. reactioncomponent, decomposition2). */
+static int comp_valid(const layers_t* Ly, int l, int lp, int a, int b)
+{
+    if (a == 1 && l >= Ly->L) return 0;
+    if (a == 2 && l <= 0) return 0;
+    if (b == 1 && lp >= Ly->L) return 0;
+    if (b == 2 && lp <= 0) return 0;
+    return 1;
+}
+
+/* distance of a target at height z from the interface its component uses,
+ * tau_1(z) = z - d_l, tau_2(z) = d_{l-1} - z (eq. zexponential) */
+static double tau_t(const layers_t* Ly, int l, int a, double z) { return a == 1 ? z - Ly->d[l] : Ly->d[l - 1] - z; }
+/* tau'_1(z') = z' - d_lp, tau'_2(z') = d_{lp-1} - z' */
+static double tau_s(const layers_t* Ly, int lp, int b, double zp) { return b == 1 ? zp - Ly->d[lp] : Ly->d[lp - 1] - zp; }
+
+/* ------------------------------------------------------------------------ */
+/* Composite Gauss-Legendre quadrature on [0, X_max] for the Sommerfeld-    */
+/* type integrals of Sec. 3.5.  The integrands behave like                  */
+/* lrho^npow J_m(lrho rho) e^{-c lrho} times smooth factors; X_max is where */
+/* the envelope lrho^npow e^{-c lrho} has fallen to tol of its peak.  Panel */
+/* widths resolve half a Bessel period (pi/rho), the exponential (4/c), the */
+/* branch points of sqrt(lambda^2 + lrho^2) near the origin (lam_min) and   */
+/* the poles of sigma at |lrho| ~ pi/(2 D) (D = thickest finite layer).     */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int n;
+    double* x;
+    double* w;
+} nodes_t;
+
+static double xmax_envelope(double c, int npow, double tol)
+{
+    double lt = log(tol);
+    if (npow == 0) return -lt / c;
+    double xs = npow / c;
+    double step = 1.0 / c;
+    double hi = xs + step;
+    while (npow * log(hi / xs) - c * (hi - xs) > lt) {
+        step *= 2.0;
+        hi = xs + step;
+    }
+    double lo = xs;
+    for (int it = 0; it < 200; ++it) {
+        double mid = 0.5 * (lo + hi);
+        if (npow * log(mid / xs) - c * (mid - xs) > lt) lo = mid;
+        else hi = mid;
+    }
+    return hi;
+}
+
+static void build_nodes(nodes_t* nd, double rho, double c, int npow, double lam_min, double dmax, double tol)
+{
+    double X = xmax_envelope(c, npow, tol);
+    double w0 = lam_min;
+    if (dmax > 0 && ORC_PI / (2.0 * dmax) < w0) w0 = ORC_PI / (2.0 * dmax);
+    int cap = 1024;
+    nd->x = (double*)malloc(sizeof(double) * cap * ORC_NGL);
+    nd->w = (double*)malloc(sizeof(double) * cap * ORC_NGL);
+    nd->n = 0;
+    double a = 0.0;
+    int np = 0;
+    while (a < X) {
+        double w = a > w0 ? a : w0;
+        if (4.0 / c < w) w = 4.0 / c;
+        if (rho > 0 && ORC_PI / rho < w) w = ORC_PI / rho;
+        if (np == cap) {
+            cap *= 2;
+            nd->x = (double*)realloc(nd->x, sizeof(double) * cap * ORC_NGL);
+            nd->w = (double*)realloc(nd->w, sizeof(double) * cap * ORC_NGL);
+        }
+        for (int k = 0; k < ORC_NGL; ++k) {
+            nd->x[nd->n] = a + 0.5 * w * (g_gl16_x[k] + 1.0);
+            nd->w[nd->n] = 0.5 * w * g_gl16_w[k];
+            nd->n++;
+        }
+        a += w;
+        np++;
+    }
+}
+
+static void free_nodes(nodes_t* nd)
+{
+    free(nd->x);
+    free(nd->w);
+}
+
+static double layers_lam_min(const layers_t* Ly)
+{
+    double m = Ly->lam[0];
+    for (int k = 1; k <= Ly->L; ++k) m = fmin(m, Ly->lam[k]);
+    return m;
+}
+
+static double layers_dmax(const layers_t* Ly)
+{
+    double m = 0.0;
+    for (int k = 1; k < Ly->L; ++k) m = fmax(m, Ly->d[k - 1] - Ly->d[k]);
+    return m;
+}
+
+#define ORC_TOL 1e-16
+
+/* ------------------------------------------------------------------------ */
+/* Green's function components                                              */
+/* ------------------------------------------------------------------------ */
+
+/* free space part e^{-lambda r} / (4 pi eps r) (eq. layeredGreensfun) */
+static double green_free(double lam, double eps, double r) { return exp(-lam * r) / (4.0 * ORC_PI * eps * r); }
+
+/* Reaction component u^{ab}_{l lp}(r, r') (eq. generalcomponents) with the
+ * angular integral done by the J_n identity (Sec. 3.5):
+ *   u = (1/4pi) int_0^inf lrho J_0(lrho rho) e^{-l_z tau_a(z) - l'_z tau'_b(z')}
+ *                         sigma^{ab}_{l lp}(lrho) / l_z dlrho. */
+double orc_reaction_u(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
+                      double x, double y, double z, double xp, double yp, double zp)
+{
+    layers_t Ly;
+    Ly.L = L;
+    for (int k = 0; k <= L; ++k) {
+        Ly.eps[k] = eps[k];
+        Ly.lam[k] = lam[k];
+    }
+    for (int k = 0; k < L; ++k) Ly.d[k] = d[k];
+    if (L != 2 || !comp_valid(&Ly, l, lp, a, b)) return NAN;
+    double rho = hypot(x - xp, y - yp);
+    double tt = tau_t(&Ly, l, a, z), ts = tau_s(&Ly, lp, b, zp);
+    nodes_t nd;
+    build_nodes(&nd, rho, tt + ts, 1, layers_lam_min(&Ly), layers_dmax(&Ly), ORC_TOL);
+    double s = 0.0;
+    for (int k = 0; k < nd.n; ++k) {
+        double t = nd.x[k];
+        double lz = sqrt(lam[l] * lam[l] + t * t), lzp = sqrt(lam[lp] * lam[lp] + t * t);
+        s += nd.w[k] * t * jn(0, t * rho) * exp(-lz * tt - lzp * ts) * sigma(&Ly, l, lp, a, b, t) / lz;
+    }
+    free_nodes(&nd);
+    return s / (4.0 * ORC_PI);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Direct O(N^2) summation (eqs. potential1 / totalinteraction):             */
+/*   Phi_l(r_i) = sum_{j != i, j in layer l} Q_j e^{-lam_l r}/(4 pi eps_l r)  */
+/*              + sum_{all j} Q_j sum_{valid (a,b)} u^{ab}_{l l_j}(r_i, r_j)  */
+/* The free part excludes j = i; the reaction part includes it (the image   */
+/* of a charge is never at the charge).                                     */
+/* ------------------------------------------------------------------------ */
+static int fill_layers(layers_t* Ly, int nlayers, const double* eps, const double* lam, const double* d)
+{
+    if (nlayers < 1 || nlayers > ORC_MAXL + 1) return -1;
+    Ly->L = nlayers - 1;
+    for (int k = 0; k < nlayers; ++k) {
+        Ly->eps[k] = eps[k];
+        Ly->lam[k] = lam[k];
+    }
+    for (int k = 0; k < Ly->L; ++k) Ly->d[k] = d[k];
+    return 0;
+}
+
+int orc_direct_sum(int nlayers, const double* eps, const double* lam, const double* d, int64_t n, const double* x,
+                   const double* y, const double* z, const double* q, int64_t nt, const int64_t* tidx, double* phi,
+                   int nthreads)
+{
+    layers_t Ly;
+    if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
+    if (Ly.L != 2 && Ly.L != 0) return -2;
+    int* lay = (int*)malloc(sizeof(int) * n);
+    for (int64_t j = 0; j < n; ++j) lay[j] = layer_of(&Ly, z[j]);
+    double lmin = layers_lam_min(&Ly), dmax = layers_dmax(&Ly);
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t ti = 0; ti < nt; ++ti) {
+        int64_t i = tidx ? tidx[ti] : ti;
+        int l = lay[i];
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            int lp = lay[j];
+            double rho = hypot(x[i] - x[j], y[i] - y[j]);
+            if (lp == l && j != i) {
+                double r = sqrt(rho * rho + (z[i] - z[j]) * (z[i] - z[j]));
+                acc += q[j] * green_free(lam[l], eps[l], r);
+            }
+            if (Ly.L == 0) continue;
+            /* all valid reaction components of this (target, source) pair */
+            double tt[4], ts[4], cmin = INFINITY;
+            int ab[4][2], nc = 0;
+            for (int a = 1; a <= 2; ++a)
+                for (int b = 1; b <= 2; ++b)
+                    if (comp_valid(&Ly, l, lp, a, b)) {
+                        ab[nc][0] = a;
+                        ab[nc][1] = b;
+                        tt[nc] = tau_t(&Ly, l, a, z[i]);
+                        ts[nc] = tau_s(&Ly, lp, b, z[j]);
+                        cmin = fmin(cmin, tt[nc] + ts[nc]);
+                        nc++;
+                    }
+            nodes_t nd;
+            build_nodes(&nd, rho, cmin, 1, lmin, dmax, ORC_TOL);
+            double s = 0.0;
+            for (int k = 0; k < nd.n; ++k) {
+                double t = nd.x[k];
+                double lz = sqrt(lam[l] * lam[l] + t * t), lzp = sqrt(lam[lp] * lam[lp] + t * t);
+                double g = 0.0;
+                for (int c = 0; c < nc; ++c)
+                    g += exp(-lz * tt[c] - lzp * ts[c]) * sigma(&Ly, l, lp, ab[c][0], ab[c][1], t);
+                s += nd.w[k] * t * jn(0, t * rho) * g / lz;
+            }
+            free_nodes(&nd);
+            acc += q[j] * s / (4.0 * ORC_PI);
+        }
+        phi[ti] = acc;
+    }
+    free(lay);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Free-space translation operators (Theorems 3.1-3.3).                     */
+/* With the harmonics above, for |r| < |b|:                                 */
+/*   i_n Y_n^m(r+b) = sum_{nu,mu} Sh_{n nu}^{m mu}(b) i_nu Y_nu^mu(r),      */
+/*   k_n Y_n^m(r+b) = sum_{nu,mu} S_{n nu}^{m mu}(b) i_nu Y_nu^mu(r),       */
+/*   Sh = 4 pi sum_q          i_q(lam b) Y_q^{m-mu}(b^) G_q,                */
+/*   S  = 4 pi sum_q (-1)^{n+q} k_q(lam b) Y_q^{m-mu}(b^) G_q,              */
+/*   G_q = int Y_n^m conj(Y_nu^mu) conj(Y_q^{m-mu}) dOmega.                 */
+/* The printed prefactors of the separation matrices (4pi(-1)^{nu-n+m+q}    */
+/* and 2 pi^2 (-1)^{m+nu+1}) hold only under an unstated Gaunt convention;  */
+/* these forms are pinned by the addition-theorem tests instead.            */
+/* Translations (eqs. metole, metome; the sums run over nu, mu):            */
+/*   M2L: L_nm  = sum S_{nu n}^{mu m}(rc_t - rc_s) M_{nu mu}                */
+/*   M2M: M~_nm = sum conj(Sh_{n nu}^{m mu}(rc_s - rc~_s)) M_{nu mu}        */
+/*   L2L: L~_nm = sum Sh_{nu n}^{mu m}(rc~_t - rc_t) L_{nu mu}              */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int p, K;
+    double* G; /* G[(row*K + col)*(2p+1) + q] = G_q(n,m; nu,mu), row = idx(n,m), col = idx(nu,mu) */
+} gaunt_tab_t;
+
+static void gaunt_tab_init(gaunt_tab_t* T, int p)
+{
+    T->p = p;
+    T->K = (p + 1) * (p + 1);
+    int nq = 2 * p + 1;
+    T->G = (double*)calloc((size_t)T->K * T->K * nq, sizeof(double));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu)
+                    for (int q = 0; q <= 2 * p; ++q) {
+                        if (q < iabs(n - nu) || q > n + nu || (n + nu + q) % 2) continue;
+                        if (iabs(m - mu) > q) continue;
+                        /* conj(Y_nu^mu) = (-1)^mu Y_nu^{-mu}; conj(Y_q^{m-mu}) = (-1)^{m-mu} Y_q^{mu-m} */
+                        double g = sgn_pow(iabs(m)) * orc_gaunt(n, m, nu, -mu, q, mu - m);
+                        T->G[((size_t)idx_nm(n, m) * T->K + idx_nm(nu, mu)) * nq + q] = g;
+                    }
+}
+
+static void gaunt_tab_free(gaunt_tab_t* T) { free(T->G); }
+
+/* Dense operator A (K x K complex, row-major, A[row*K+col]) for one of:
+ *   kind 0: M2M, A_{(n,m),(nu,mu)} = conj(Sh_{n nu}^{m mu}(b))
+ *   kind 1: L2L, A_{(n,m),(nu,mu)} = Sh_{nu n}^{mu m}(b)
+ *   kind 2: M2L, A_{(n,m),(nu,mu)} = S_{nu n}^{mu m}(b)                    */
+static void free_operator(const gaunt_tab_t* T, int kind, double lam, double bx, double by, double bz, cplx* A)
+{
+    int p = T->p, K = T->K, nq = 2 * p + 1;
+    double b = sqrt(bx * bx + by * by + bz * bz);
+    int K2 = (2 * p + 1) * (2 * p + 1);
+    cplx* Yb = (cplx*)malloc(sizeof(cplx) * K2);
+    ylm_c(2 * p, bx, by, bz, Yb);
+    double rad[2 * ORC_PMAX + 1];
+    for (int q = 0; q <= 2 * p; ++q) rad[q] = (kind == 2) ? orc_bessel_k(q, lam * b) : orc_bessel_i(q, lam * b);
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu) {
+                    /* (N,Mm) is the first index pair of Sh/S, (V,U) the second */
+                    int N, Mm, V, U;
+                    if (kind == 0) { N = n; Mm = m; V = nu; U = mu; }
+                    else { N = nu; Mm = mu; V = n; U = m; }
+                    cplx s = 0.0;
+                    const double* G = &T->G[((size_t)idx_nm(N, Mm) * K + idx_nm(V, U)) * nq];
+                    for (int q = iabs(N - V); q <= N + V; q += 2) {
+                        if (iabs(Mm - U) > q || G[q] == 0.0) continue;
+                        double f = (kind == 2) ? sgn_pow(N + q) : 1.0;
+                        s += f * rad[q] * Yb[idx_nm(q, Mm - U)] * G[q];
+                    }
+                    s *= 4.0 * ORC_PI;
+                    A[(size_t)idx_nm(n, m) * K + idx_nm(nu, mu)] = (kind == 0) ? conj(s) : s;
+                }
+    free(Yb);
+}
+
+static void apply_op(int K, const cplx* A, const cplx* x, cplx* y /* += */)
+{
+    for (int r = 0; r < K; ++r) {
+        cplx s = 0.0;
+        for (int c = 0; c < K; ++c) s += A[(size_t)r * K + c] * x[c];
+        y[r] += s;
+    }
+}
+
+/* P2M (eq. melecoeffree): M_nm += q 4 pi i_n(lam |r'-c|) conj(Y_n^m(r'-c)) */
+static void p2m_one(int p, double lam, double q, double dx, double dy, double dz, cplx* M)
+{
+    int K = (p + 1) * (p + 1);
+    cplx* Y = (cplx*)malloc(sizeof(cplx) * K);
+    ylm_c(p, dx, dy, dz, Y);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    for (int n = 0; n <= p; ++n) {
+        double in = orc_bessel_i(n, lam * r);
+        for (int m = -n; m <= n; ++m) M[idx_nm(n, m)] += q * 4.0 * ORC_PI * in * conj(Y[idx_nm(n, m)]);
+    }
+    free(Y);
+}
+
+/* L2P (eq. freespace3dlocexp / lelayerimage): sum_nm L_nm i_n(lam|r-c|) Y_n^m(r-c) */
+static double l2p_one(int p, double lam, const cplx* L, double dx, double dy, double dz)
+{
+    int K = (p + 1) * (p + 1);
+    cplx* Y = (cplx*)malloc(sizeof(cplx) * K);
+    ylm_c(p, dx, dy, dz, Y);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    cplx s = 0.0;
+    for (int n = 0; n <= p; ++n) {
+        double in = orc_bessel_i(n, lam * r);
+        for (int m = -n; m <= n; ++m) s += L[idx_nm(n, m)] * in * Y[idx_nm(n, m)];
+    }
+    free(Y);
+    return creal(s);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Reaction M2L operators (Sec. 3.5).                                       */
+/* ------------------------------------------------------------------------ */
+
+/* a^j_{nm} (m >= 0): coefficient of x^{2j-n-m} in c_nm d^m P_n/dx^m */
+static double a_coef(int n, int m, int j)
+{
+    if (2 * j - n - m < 0) return 0.0;
+    return sgn_pow(n - j) * fact(2 * j) * cnm(n, m) / (pow(2.0, n) * fact(j) * fact(n - j) * fact(2 * j - n - m));
+}
+
+/* b^s_{nm} = sum_{j=q}^{n} (-1)^s a^j_{nm} (j-r)! / (s! (j-r-s)!),
+ * r = floor((n+m)/2), q = max(ceil((n+m)/2), s+r)  (m >= 0) */
+static double b_coef(int n, int m, int s)
+{
+    int r = (n + m) / 2;
+    int q = (n + m + 1) / 2;
+    if (s + r > q) q = s + r;
+    double acc = 0.0;
+    for (int j = q; j <= n; ++j) acc += sgn_pow(s) * a_coef(n, m, j) * fact(j - r) / (fact(s) * fact(j - r - s));
+    return acc;
+}
+
+static double tau_sign(int m) { return m >= 0 ? 1.0 : sgn_pow(-m); }
+
+/* C^s_{n nu m mu} of the Legendre-product expansion
+ *   P^_n^m(l_z/l) P^_nu^mu(l'_z/l') = sum_s C^s lrho^{|m|+|mu|+2s} (l/l_z)^i (l'/l'_z)^j,
+ * with the printed extra factor (|m|+|mu|+2s)! dropped: with it the
+ * expansion does not reproduce the product (pinned by a test). */
+static cplx c_coef(int n, int nu, int m, int mu, int s, double lam, double lamp)
+{
+    int am = iabs(m), amu = iabs(mu);
+    int r = (n + am) / 2, rp = (nu + amu) / 2;
+    int t0 = s - nu + rp;
+    if (t0 < 0) t0 = 0;
+    int t1 = s < n - r ? s : n - r;
+    cplx acc = 0.0;
+    for (int t = t0; t <= t1; ++t) {
+        cplx den = ipow(am + 2 * t) * pow(lam, am + 2 * t) * ipow(amu + 2 * (s - t)) * pow(lamp, amu + 2 * (s - t));
+        acc += tau_sign(m) * tau_sign(mu) * b_coef(n, am, t) * b_coef(nu, amu, s - t) / den;
+    }
+    return acc;
+}
+
+/* C~^s = sqrt((|m|-m+|mu|+mu+2s+1)! (|m|+m+|mu|-mu+2s+1)!) C^s
+ * (the printed "\pounds!" is read as a factorial sign). */
+static cplx ct_coef(int n, int nu, int m, int mu, int s, double lam, double lamp)
+{
+    int am = iabs(m), amu = iabs(mu);
+    return sqrt(fact(am - m + amu + mu + 2 * s + 1) * fact(am + m + amu - mu + 2 * s + 1)) *
+           c_coef(n, nu, m, mu, s, lam, lamp);
+}
+
+typedef struct {
+    layers_t Ly;
+    int l, lp, a, b;
+} rcomp_t;
+
+/* Z^+(z,z') = e^{-l_z (z - d_l) - l'_z (d_l - z')}           (a = 1)
+ * Z^-(z,z') = e^{-l_z (d_{l-1} - z) - l'_z (z' - d_{l-1})}   (a = 2)     (eq. zexpkernel) */
+static double zkern(const rcomp_t* C, double lz, double lzp, double zt, double zs)
+{
+    const layers_t* Ly = &C->Ly;
+    if (C->a == 1) return exp(-lz * (zt - Ly->d[C->l]) - lzp * (Ly->d[C->l] - zs));
+    return exp(-lz * (Ly->d[C->l - 1] - zt) - lzp * (zs - Ly->d[C->l - 1]));
+}
+
+static double zsep(const rcomp_t* C, double zt, double zs)
+{
+    const layers_t* Ly = &C->Ly;
+    if (C->a == 1) return (zt - Ly->d[C->l]) + (Ly->d[C->l] - zs);
+    return (Ly->d[C->l - 1] - zt) + (zs - Ly->d[C->l - 1]);
+}
+
+static double a_n(int n) { return sqrt((double)n * (n + 1.0)); }
+
+/* Scaled Sommerfeld integrals S^n Sc_{n m, ij}(rho, zt, zs) (eq. M2Ltable and
+ * its scaled form) for 0 <= m <= n <= nmax, i, j in {0,1}:
+ *   tab[((i*2+j)*(nmax+1) + n)*(nmax+1) + m].
+ * Initial values m = 0 (n = 0..nmax) and m = 1 (n = 1..nmax) by composite
+ * Gauss-Legendre quadrature; the rest by the forward recurrence
+ * (eq. recurrence1):
+ *   S^n Sc_{n,m+1} = (2m / a_{n+m}) (S/rho) S^{n-1} Sc_{n-1,m}
+ *                    - (a_{n-m}/a_{n+m}) S^n Sc_{n,m-1},  n >= m+1,
+ * with a_k = sqrt(k(k+1)).  For rho = 0, Sc_{n,m>0} = 0.  The recurrence is
+ * used only where the stability bound 2m/a_{n+m} < rho/S holds, as it does
+ * for every M2L pair of the tree (rho = 0 or rho >= S).  Returns 1 if that
+ * bound was violated somewhere. */
+static int sommerfeld_table(const rcomp_t* C, double rho, double zt, double zs, double S, int nmax, double* tab)
+{
+    const layers_t* Ly = &C->Ly;
+    int N1 = nmax + 1;
+    double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
+    memset(tab, 0, sizeof(double) * 4 * N1 * N1);
+    nodes_t nd;
+    build_nodes(&nd, rho, zsep(C, zt, zs), nmax, layers_lam_min(Ly), layers_dmax(Ly), ORC_TOL);
+    for (int k = 0; k < nd.n; ++k) {
+        double t = nd.x[k];
+        double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+        double base = nd.w[k] * zkern(C, lz, lzp, zt, zs) * sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz;
+        double j0 = jn(0, t * rho), j1 = jn(1, t * rho);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                double f = base * (i ? lt / lz : 1.0) * (j ? ls / lzp : 1.0);
+                double* T = tab + (size_t)(i * 2 + j) * N1 * N1;
+                double pw = 1.0; /* (t S)^n */
+                for (int n = 0; n <= nmax; ++n) {
+                    T[n * N1 + 0] += f * pw * j0 / fact(n); /* sqrt(n! n!) = n! */
+                    if (n >= 1) T[n * N1 + 1] += f * pw * j1 / sqrt(fact(n + 1) * fact(n - 1));
+                    pw *= t * S;
+                }
+            }
+    }
+    free_nodes(&nd);
+    int unstable = 0;
+    for (int ij = 0; ij < 4; ++ij) {
+        double* T = tab + (size_t)ij * N1 * N1;
+        if (rho == 0.0) {
+            for (int n = 0; n <= nmax; ++n)
+                for (int m = 1; m <= n; ++m) T[n * N1 + m] = 0.0;
+            continue;
+        }
+        for (int m = 1; m < nmax; ++m)
+            for (int n = m + 1; n <= nmax; ++n) {
+                if (2.0 * m / a_n(n + m) >= rho / S) unstable = 1;
+                T[n * N1 + m + 1] = 2.0 * m / a_n(n + m) * (S / rho) * T[(n - 1) * N1 + m] -
+                                    a_n(n - m) / a_n(n + m) * T[n * N1 + m - 1];
+            }
+    }
+    return unstable;
+}
+
+/* Table of C~^s for all (n,m,nu,mu,s) of one component. */
+typedef struct {
+    int p, smax;
+    cplx* v; /* [(idx(n,m)*K + idx(nu,mu))*(smax+1) + s] */
+} ctab_t;
+
+static void ctab_init(ctab_t* T, int p, double lam, double lamp)
+{
+    int K = (p + 1) * (p + 1);
+    T->p = p;
+    T->smax = 2 * p + 2;
+    T->v = (cplx*)calloc((size_t)K * K * (T->smax + 1), sizeof(cplx));
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu) {
+                    int r = (n + iabs(m)) / 2, rp = (nu + iabs(mu)) / 2;
+                    for (int s = 0; s <= (n - r) + (nu - rp); ++s)
+                        T->v[((size_t)idx_nm(n, m) * K + idx_nm(nu, mu)) * (T->smax + 1) + s] =
+                            ct_coef(n, nu, m, mu, s, lam, lamp);
+                }
+}
+
+/* I_{nm,nu mu} (eq. uniformintegral) assembled from the scaled table by
+ * eq. metoletableform: I = i^{mu-m} sum_s C~^s Sc_{|m|+|mu|+2s+1, mu-m, ij},
+ * i = (n+|m|) mod 2, j = (nu+|mu|) mod 2, Sc_{N,-M} = (-1)^M Sc_{N,M}. */
+static cplx assemble_I(const ctab_t* CT, const double* tab, int nmax, double S, int n, int m, int nu, int mu)
+{
+    int K = (CT->p + 1) * (CT->p + 1);
+    int N1 = nmax + 1;
+    int i = (n + iabs(m)) % 2, j = (nu + iabs(mu)) % 2;
+    int r = (n + iabs(m)) / 2, rp = (nu + iabs(mu)) / 2;
+    const double* T = tab + (size_t)(i * 2 + j) * N1 * N1;
+    const cplx* cv = &CT->v[((size_t)idx_nm(n, m) * K + idx_nm(nu, mu)) * (CT->smax + 1)];
+    cplx acc = 0.0;
+    for (int s = 0; s <= (n - r) + (nu - rp); ++s) {
+        int Nn = iabs(m) + iabs(mu) + 2 * s + 1;
+        int M = mu - m;
+        double sc = T[Nn * N1 + iabs(M)] * (M < 0 ? sgn_pow(-M) : 1.0) / pow(S, Nn);
+        acc += cv[s] * sc;
+    }
+    return ipow(mu - m) * acc;
+}
+
+/* Reaction M2L operator (eq. coefintable):
+ *   T^{1b}_{nm,nu mu} = (-1)^n          e^{i(mu-m) phi_st} I^{1b}_{nm,nu mu}(rho_st, zc_t, zc_s)
+ *   T^{2b}_{nm,nu mu} = (-1)^{nu+m+mu}  e^{i(mu-m) phi_st} I^{2b}_{nm,nu mu}(rho_st, zc_t, zc_s)
+ * given the phi-independent part I (K x K). */
+static void reaction_T_from_I(const rcomp_t* C, int p, const cplx* Imat, double phi, cplx* A)
+{
+    int K = (p + 1) * (p + 1);
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu) {
+                    double sg = (C->a == 1) ? sgn_pow(n) : sgn_pow(nu + iabs(m) + iabs(mu));
+                    int r = idx_nm(n, m), c = idx_nm(nu, mu);
+                    A[(size_t)r * K + c] = sg * cexp(I * (mu - m) * phi) * Imat[(size_t)r * K + c];
+                }
+}
+
+static void reaction_I_matrix(const rcomp_t* C, const ctab_t* CT, int p, double rho, double zt, double zs, double S,
+                              cplx* Imat, int* unstable)
+{
+    int nmax = 2 * p + 3, K = (p + 1) * (p + 1);
+    double* tab = (double*)malloc(sizeof(double) * 4 * (nmax + 1) * (nmax + 1));
+    int u = sommerfeld_table(C, rho, zt, zs, S, nmax, tab);
+    if (unstable) *unstable |= u;
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu)
+                    Imat[(size_t)idx_nm(n, m) * K + idx_nm(nu, mu)] = assemble_I(CT, tab, nmax, S, n, m, nu, mu);
+    free(tab);
+}
+
+/* Test-only cross-check: I_{nm,nu mu} by direct quadrature of eq.
+ * uniformintegral with Q = P^_n^m(l_z/l) P^_nu^mu(l'_z/l') evaluated as the
+ * associated Legendre function beyond [-1,1] on the branch
+ * (1-w^2)^{1/2} = -i sqrt(w^2-1) (Prop. 3.2 and eq. branch). */
+static cplx plm_big(int n, int m, double w, double lrho_over_lam)
+{
+    int am = iabs(m);
+    /* d^am P_n / dw^am by the three-term recurrence in n */
+    double p0 = 1.0;
+    for (int k = 1; k <= am; ++k) p0 *= (2.0 * k - 1.0);
+    double val;
+    if (n == am) val = p0;
+    else {
+        double p1 = (2.0 * am + 1.0) * w * p0;
+        for (int k = am + 2; k <= n; ++k) {
+            double pk = ((2.0 * k - 1.0) * w * p1 - (k + am - 1.0) * p0) / (double)(k - am);
+            p0 = p1;
+            p1 = pk;
+        }
+        val = p1;
+    }
+    cplx root = cpow(-I * lrho_over_lam, am);
+    return tau_sign(m) * cnm(n, am) * root * val;
+}
+
+static cplx reaction_I_direct_one(const rcomp_t* C, int n, int m, int nu, int mu, double rho, double zt, double zs)
+{
+    const layers_t* Ly = &C->Ly;
+    double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
+    nodes_t nd;
+    build_nodes(&nd, rho, zsep(C, zt, zs), n + nu + 2, layers_lam_min(Ly), layers_dmax(Ly), ORC_TOL);
+    cplx acc = 0.0;
+    for (int k = 0; k < nd.n; ++k) {
+        double t = nd.x[k];
+        double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+        cplx Q = plm_big(n, m, lz / lt, t / lt) * plm_big(nu, mu, lzp / ls, t / ls);
+        acc += nd.w[k] * t * jn(mu - m, t * rho) * zkern(C, lz, lzp, zt, zs) *
+               sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz * Q;
+    }
+    free_nodes(&nd);
+    return ipow(mu - m) * acc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Tree (shared definition with the GPU library, written separately):      */
+/*  root cube (cx,cy,cz) +- R; fine cell of a point                         */
+/*    t = ((x - cx) + R) / (2R),  ix = clamp(floor(t * 2^16), 0, 2^16-1),   */
+/*  level-l cell = fine cell >> (16 - l); depth H = the smallest l with     */
+/*  N_src <= cap * #non-empty source boxes(l) and the same for targets      */
+/*  (H <= 12); uniform depth; V-list at level l >= 2: non-empty source      */
+/*  boxes that are children of the neighbours of the target's parent and    */
+/*  not adjacent to the target; U-list at level H: adjacent or equal boxes. */
+/* ------------------------------------------------------------------------ */
+static uint32_t fine_cell(double x, double c, double R)
+{
+    double t = ((x - c) + R) / (2.0 * R);
+    double f = floor(t * 65536.0);
+    if (f < 0) f = 0;
+    if (f > 65535) f = 65535;
+    return (uint32_t)f;
+}
+
+static uint64_t morton_key(uint32_t ix, uint32_t iy, uint32_t iz, int level)
+{
+    uint64_t k = 0;
+    for (int bit = level - 1; bit >= 0; --bit) {
+        k = (k << 3) | (uint64_t)(((ix >> bit) & 1u) << 2) | (uint64_t)(((iy >> bit) & 1u) << 1) |
+            (uint64_t)((iz >> bit) & 1u);
+    }
+    return k;
+}
+
+typedef struct {
+    int n;
+    uint32_t *cx, *cy, *cz; /* fine cells */
+} cells_t;
+
+typedef struct {
+    int nb;
+    uint64_t* key;          /* sorted distinct box keys at this level */
+    int* start;             /* for the leaf level: point list offsets (nb+1) */
+} boxlev_t;
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return x < y ? -1 : (x > y ? 1 : 0);
+}
+
+static void distinct_boxes(const cells_t* C, int level, boxlev_t* B)
+{
+    uint64_t* k = (uint64_t*)malloc(sizeof(uint64_t) * (C->n > 0 ? C->n : 1));
+    int sh = ORC_HMAX - level;
+    for (int i = 0; i < C->n; ++i) k[i] = morton_key(C->cx[i] >> sh, C->cy[i] >> sh, C->cz[i] >> sh, level);
+    qsort(k, C->n, sizeof(uint64_t), cmp_u64);
+    int nb = 0;
+    for (int i = 0; i < C->n; ++i)
+        if (i == 0 || k[i] != k[i - 1]) k[nb++] = k[i];
+    B->nb = nb;
+    B->key = k;
+    B->start = NULL;
+}
+
+static int find_box(const boxlev_t* B, uint64_t key)
+{
+    int lo = 0, hi = B->nb - 1;
+    while (lo <= hi) {
+        int mid = (lo + hi) / 2;
+        if (B->key[mid] == key) return mid;
+        if (B->key[mid] < key) lo = mid + 1;
+        else hi = mid - 1;
+    }
+    return -1;
+}
+
+static void key_coords(uint64_t key, int level, int* ix, int* iy, int* iz)
+{
+    int x = 0, y = 0, z = 0;
+    for (int bit = 0; bit < level; ++bit) {
+        z |= (int)((key >> (3 * bit)) & 1u) << bit;
+        y |= (int)((key >> (3 * bit + 1)) & 1u) << bit;
+        x |= (int)((key >> (3 * bit + 2)) & 1u) << bit;
+    }
+    *ix = x;
+    *iy = y;
+    *iz = z;
+}
+
+/* ------------------------------------------------------------------------ */
+/* One FMM (Algorithm 1 for a reaction component, the classic Yukawa FMM   */
+/* for a free-space component) on the uniform tree above.                  */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    int kind; /* 0 free, 1 reaction */
+    rcomp_t rc;
+    double lam_s, lam_t, far_factor; /* far_factor multiplies L2P */
+    double eps_t;
+} fmmspec_t;
+
+typedef struct {
+    int depth;
+    int nleaf_t, nleaf_s;
+    long long m2l_pairs, p2p_pairs;
+    int unstable;
+} fmmstat_t;
+
+static int sort_by_key_cmp_idx(const void* a, const void* b)
+{
+    const uint64_t* x = (const uint64_t*)a;
+    const uint64_t* y = (const uint64_t*)b;
+    if (x[0] != y[0]) return x[0] < y[0] ? -1 : 1;
+    return x[1] < y[1] ? -1 : (x[1] > y[1] ? 1 : 0);
+}
+
+/* points of a leaf level grouped by box: order[] = point indices sorted by (key, index) */
+static void leaf_lists(const cells_t* C, int H, const boxlev_t* B, int* order, int* start)
+{
+    uint64_t* kv = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (C->n > 0 ? C->n : 1));
+    int sh = ORC_HMAX - H;
+    for (int i = 0; i < C->n; ++i) {
+        kv[2 * i] = morton_key(C->cx[i] >> sh, C->cy[i] >> sh, C->cz[i] >> sh, H);
+        kv[2 * i + 1] = (uint64_t)i;
+    }
+    qsort(kv, C->n, 2 * sizeof(uint64_t), sort_by_key_cmp_idx);
+    int b = 0;
+    start[0] = 0;
+    for (int i = 0; i < C->n; ++i) {
+        order[i] = (int)kv[2 * i + 1];
+        while (B->key[b] != kv[2 * i]) start[++b] = i;
+    }
+    for (int k = b + 1; k <= B->nb; ++k) start[k] = C->n;
+    free(kv);
+}
+
+static void box_center(double cx, double cy, double cz, double R, int level, int ix, int iy, int iz, double* c)
+{
+    double h = 2.0 * R / (double)(1 << level);
+    c[0] = (cx - R) + (ix + 0.5) * h;
+    c[1] = (cy - R) + (iy + 0.5) * h;
+    c[2] = (cz - R) + (iz + 0.5) * h;
+}
+
+static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx, const double* sy, const double* sz,
+                   const double* sq, const int64_t* sid, int nt, const double* tx, const double* ty,
+                   const double* tz, const int64_t* tid, double cx, double cy, double cz, double R,
+                   const gaunt_tab_t* GT, const ctab_t* CT, double* phi, fmmstat_t* st)
+{
+    int K = (p + 1) * (p + 1);
+    memset(phi, 0, sizeof(double) * nt);
+    memset(st, 0, sizeof(*st));
+    if (nt == 0 || ns == 0) return 0;
+    cells_t Cs, Ct;
+    Cs.n = ns;
+    Ct.n = nt;
+    Cs.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * ns);
+    Cs.cy = Cs.cx + ns;
+    Cs.cz = Cs.cy + ns;
+    Ct.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * nt);
+    Ct.cy = Ct.cx + nt;
+    Ct.cz = Ct.cy + nt;
+    for (int i = 0; i < ns; ++i) {
+        Cs.cx[i] = fine_cell(sx[i], cx, R);
+        Cs.cy[i] = fine_cell(sy[i], cy, R);
+        Cs.cz[i] = fine_cell(sz[i], cz, R);
+    }
+    for (int i = 0; i < nt; ++i) {
+        Ct.cx[i] = fine_cell(tx[i], cx, R);
+        Ct.cy[i] = fine_cell(ty[i], cy, R);
+        Ct.cz[i] = fine_cell(tz[i], cz, R);
+    }
+    boxlev_t SB[ORC_MAXDEPTH + 1], TB[ORC_MAXDEPTH + 1];
+    int H = -1;
+    for (int l = 0; l <= ORC_MAXDEPTH; ++l) {
+        distinct_boxes(&Cs, l, &SB[l]);
+        distinct_boxes(&Ct, l, &TB[l]);
+        if ((long long)ns <= (long long)cap * SB[l].nb && (long long)nt <= (long long)cap * TB[l].nb) {
+            H = l;
+            break;
+        }
+    }
+    if (H < 0) H = ORC_MAXDEPTH;
+    st->depth = H;
+    st->nleaf_s = SB[H].nb;
+    st->nleaf_t = TB[H].nb;
+
+    int* sorder = (int*)malloc(sizeof(int) * ns);
+    int* sstart = (int*)malloc(sizeof(int) * (SB[H].nb + 1));
+    int* torder = (int*)malloc(sizeof(int) * nt);
+    int* tstart = (int*)malloc(sizeof(int) * (TB[H].nb + 1));
+    leaf_lists(&Cs, H, &SB[H], sorder, sstart);
+    leaf_lists(&Ct, H, &TB[H], torder, tstart);
+
+    /* ---------------- far field (levels >= 2) ---------------- */
+    if (H >= 2) {
+        cplx* ME[ORC_MAXDEPTH + 1];
+        cplx* LE[ORC_MAXDEPTH + 1];
+        for (int l = 0; l <= H; ++l) {
+            ME[l] = (l >= 2) ? (cplx*)calloc((size_t)SB[l].nb * K, sizeof(cplx)) : NULL;
+            LE[l] = (l >= 2) ? (cplx*)calloc((size_t)TB[l].nb * K, sizeof(cplx)) : NULL;
+        }
+        /* P2M at the leaves (eq. melecoeffree / melayerupgoingimage) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (int b = 0; b < SB[H].nb; ++b) {
+            int ix, iy, iz;
+            double c[3];
+            key_coords(SB[H].key[b], H, &ix, &iy, &iz);
+            box_center(cx, cy, cz, R, H, ix, iy, iz, c);
+            for (int k = sstart[b]; k < sstart[b + 1]; ++k) {
+                int j = sorder[k];
+                p2m_one(p, F->lam_s, sq[j], sx[j] - c[0], sy[j] - c[1], sz[j] - c[2], &ME[H][(size_t)b * K]);
+            }
+        }
+        /* M2M, levels H-1 .. 2 (eq. metome) */
+        cplx* Aop = (cplx*)malloc(sizeof(cplx) * (size_t)K * K * 8);
+        for (int l = H - 1; l >= 2; --l) {
+            double hc = 2.0 * R / (double)(1 << (l + 1));
+            for (int o = 0; o < 8; ++o) {
+                /* child octant o = (ox,oy,oz) bits; b = c_child - c_parent */
+                int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+                free_operator(GT, 0, F->lam_s, (ox - 0.5) * hc, (oy - 0.5) * hc, (oz - 0.5) * hc,
+                              &Aop[(size_t)o * K * K]);
+            }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+            for (int b = 0; b < SB[l].nb; ++b) {
+                for (int o = 0; o < 8; ++o) {
+                    int c = find_box(&SB[l + 1], (SB[l].key[b] << 3) | (uint64_t)o);
+                    if (c < 0) continue;
+                    apply_op(K, &Aop[(size_t)o * K * K], &ME[l + 1][(size_t)c * K], &ME[l][(size_t)b * K]);
+                }
+            }
+        }
+        /* downward pass: L2L from the parent, then the V-list M2L */
+        for (int l = 2; l <= H; ++l) {
+            double h = 2.0 * R / (double)(1 << l);
+            if (l >= 3) {
+                for (int o = 0; o < 8; ++o) {
+                    int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+                    /* b = c~_t (child) - c_t (parent) */
+                    free_operator(GT, 1, F->lam_t, (ox - 0.5) * h, (oy - 0.5) * h, (oz - 0.5) * h,
+                                  &Aop[(size_t)o * K * K]);
+                }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+                for (int b = 0; b < TB[l].nb; ++b) {
+                    int pb = find_box(&TB[l - 1], TB[l].key[b] >> 3);
+                    int o = (int)(TB[l].key[b] & 7u);
+                    apply_op(K, &Aop[(size_t)o * K * K], &LE[l - 1][(size_t)pb * K], &LE[l][(size_t)b * K]);
+                }
+            }
+            /* V-list M2L.  Pass 1 lists the pairs of this level; pass 2
+             * builds each distinct operator once (free: per offset; reaction:
+             * the phi-independent part per (dx^2+dy^2, target z-row, source
+             * z-row), then the phase per (dx, dy)); pass 3 applies them. */
+            int nside = 1 << l;
+            int nkeys = (F->kind == 1) ? 49 * nside * nside : 343;
+            int nikeys = (F->kind == 1) ? 19 * nside * nside : 0;
+            int cap_p = 1024, np_ = 0;
+            int* pt = (int*)malloc(sizeof(int) * cap_p);
+            int* ps = (int*)malloc(sizeof(int) * cap_p);
+            int* pk = (int*)malloc(sizeof(int) * cap_p);
+            int* tfirst = (int*)malloc(sizeof(int) * (TB[l].nb + 1));
+            double* krep = (double*)malloc(sizeof(double) * 6 * nkeys); /* representative centres */
+            char* kused = (char*)calloc((size_t)nkeys, 1);
+            char* iused = (char*)calloc((size_t)(nikeys > 0 ? nikeys : 1), 1);
+            for (int b = 0; b < TB[l].nb; ++b) {
+                tfirst[b] = np_;
+                int tx_, ty_, tz_;
+                key_coords(TB[l].key[b], l, &tx_, &ty_, &tz_);
+                double ct[3];
+                box_center(cx, cy, cz, R, l, tx_, ty_, tz_, ct);
+                int px = tx_ >> 1, py = ty_ >> 1, pz = tz_ >> 1;
+                for (int qx = px - 1; qx <= px + 1; ++qx)
+                    for (int qy = py - 1; qy <= py + 1; ++qy)
+                        for (int qz = pz - 1; qz <= pz + 1; ++qz) {
+                            if (qx < 0 || qy < 0 || qz < 0 || qx >= nside / 2 || qy >= nside / 2 || qz >= nside / 2)
+                                continue;
+                            for (int o = 0; o < 8; ++o) {
+                                int sx_ = 2 * qx + ((o >> 2) & 1), sy_ = 2 * qy + ((o >> 1) & 1),
+                                    sz_ = 2 * qz + (o & 1);
+                                int dx = sx_ - tx_, dy = sy_ - ty_, dz = sz_ - tz_;
+                                if (iabs(dx) <= 1 && iabs(dy) <= 1 && iabs(dz) <= 1) continue;
+                                int sb = find_box(&SB[l], morton_key(sx_, sy_, sz_, l));
+                                if (sb < 0) continue;
+                                int key;
+                                if (F->kind == 0) key = ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3);
+                                else key = (((dx + 3) * 7 + (dy + 3)) * nside + tz_) * nside + sz_;
+                                if (!kused[key]) {
+                                    double cs[3];
+                                    box_center(cx, cy, cz, R, l, sx_, sy_, sz_, cs);
+                                    kused[key] = 1;
+                                    for (int k = 0; k < 3; ++k) {
+                                        krep[6 * key + k] = ct[k];
+                                        krep[6 * key + 3 + k] = cs[k];
+                                    }
+                                    if (F->kind == 1) iused[((dx * dx + dy * dy) * nside + tz_) * nside + sz_] = 1;
+                                }
+                                if (np_ == cap_p) {
+                                    cap_p *= 2;
+                                    pt = (int*)realloc(pt, sizeof(int) * cap_p);
+                                    ps = (int*)realloc(ps, sizeof(int) * cap_p);
+                                    pk = (int*)realloc(pk, sizeof(int) * cap_p);
+                                }
+                                pt[np_] = b;
+                                ps[np_] = sb;
+                                pk[np_] = key;
+                                np_++;
+                            }
+                        }
+            }
+            tfirst[TB[l].nb] = np_;
+            st->m2l_pairs += np_;
+            cplx** ops = (cplx**)calloc((size_t)nkeys, sizeof(cplx*));
+            cplx** iops = (cplx**)calloc((size_t)(nikeys > 0 ? nikeys : 1), sizeof(cplx*));
+            int unstable = 0;
+            if (F->kind == 1) {
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : unstable)
+#endif
+                for (int ik = 0; ik < nikeys; ++ik) {
+                    if (!iused[ik]) continue;
+                    int sz_ = ik % nside, tz_ = (ik / nside) % nside, d2 = ik / (nside * nside);
+                    double zt = (cz - R) + (tz_ + 0.5) * h, zs = (cz - R) + (sz_ + 0.5) * h;
+                    double rho = h * sqrt((double)d2);
+                    iops[ik] = (cplx*)malloc(sizeof(cplx) * (size_t)K * K);
+                    int uu = 0;
+                    reaction_I_matrix(&F->rc, CT, p, rho, zt, zs, h, iops[ik], &uu);
+                    unstable |= uu;
+                }
+            }
+            st->unstable |= unstable;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+            for (int key = 0; key < nkeys; ++key) {
+                if (!kused[key]) continue;
+                const double* ct = &krep[6 * key];
+                const double* cs = ct + 3;
+                ops[key] = (cplx*)malloc(sizeof(cplx) * (size_t)K * K);
+                if (F->kind == 0) {
+                    free_operator(GT, 2, F->lam_t, ct[0] - cs[0], ct[1] - cs[1], ct[2] - cs[2], ops[key]);
+                } else {
+                    int sz_ = key % nside, tz_ = (key / nside) % nside, dxy = key / (nside * nside);
+                    int dx = dxy / 7 - 3, dy = dxy % 7 - 3;
+                    double ph = (dx == 0 && dy == 0) ? 0.0 : atan2(ct[1] - cs[1], ct[0] - cs[0]);
+                    reaction_T_from_I(&F->rc, p, iops[((dx * dx + dy * dy) * nside + tz_) * nside + sz_], ph,
+                                      ops[key]);
+                }
+            }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+            for (int b = 0; b < TB[l].nb; ++b)
+                for (int k = tfirst[b]; k < tfirst[b + 1]; ++k)
+                    apply_op(K, ops[pk[k]], &ME[l][(size_t)ps[k] * K], &LE[l][(size_t)b * K]);
+            for (int k = 0; k < nkeys; ++k) free(ops[k]);
+            for (int k = 0; k < nikeys; ++k) free(iops[k]);
+            free(ops);
+            free(iops);
+            free(pt);
+            free(ps);
+            free(pk);
+            free(tfirst);
+            free(krep);
+            free(kused);
+            free(iused);
+        }
+        /* L2P at the leaves */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+        for (int b = 0; b < TB[H].nb; ++b) {
+            int ix, iy, iz;
+            double c[3];
+            key_coords(TB[H].key[b], H, &ix, &iy, &iz);
+            box_center(cx, cy, cz, R, H, ix, iy, iz, c);
+            for (int k = tstart[b]; k < tstart[b + 1]; ++k) {
+                int i = torder[k];
+                phi[i] += F->far_factor *
+                          l2p_one(p, F->lam_t, &LE[H][(size_t)b * K], tx[i] - c[0], ty[i] - c[1], tz[i] - c[2]);
+            }
+        }
+        free(Aop);
+        for (int l = 0; l <= H; ++l) {
+            free(ME[l]);
+            free(LE[l]);
+        }
+    }
+
+    /* ---------------- near field (U-list at level H) ---------------- */
+    const layers_t* Ly = &F->rc.Ly;
+    double lmin = layers_lam_min(Ly), dmax = layers_dmax(Ly);
+    int nside = 1 << H;
+    long long npp = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : npp)
+#endif
+    for (int b = 0; b < TB[H].nb; ++b) {
+        int tx_, ty_, tz_;
+        key_coords(TB[H].key[b], H, &tx_, &ty_, &tz_);
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    int sx_ = tx_ + dx, sy_ = ty_ + dy, sz_ = tz_ + dz;
+                    if (sx_ < 0 || sy_ < 0 || sz_ < 0 || sx_ >= nside || sy_ >= nside || sz_ >= nside) continue;
+                    int sb = find_box(&SB[H], morton_key(sx_, sy_, sz_, H));
+                    if (sb < 0) continue;
+                    for (int kt = tstart[b]; kt < tstart[b + 1]; ++kt) {
+                        int i = torder[kt];
+                        double acc = 0.0;
+                        for (int ks = sstart[sb]; ks < sstart[sb + 1]; ++ks) {
+                            int j = sorder[ks];
+                            if (F->kind == 0) {
+                                if (sid[j] == tid[i]) continue;
+                                double r = sqrt((tx[i] - sx[j]) * (tx[i] - sx[j]) + (ty[i] - sy[j]) * (ty[i] - sy[j]) +
+                                                (tz[i] - sz[j]) * (tz[i] - sz[j]));
+                                acc += sq[j] * green_free(F->lam_t, F->eps_t, r);
+                            } else {
+                                /* u~^{ab}(r, r'_ab) = I_00 with Q_00 = 1/(4 pi) (Algorithm 1, last step) */
+                                const rcomp_t* C = &F->rc;
+                                double rho = hypot(tx[i] - sx[j], ty[i] - sy[j]);
+                                double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
+                                nodes_t nd;
+                                build_nodes(&nd, rho, zsep(C, tz[i], sz[j]), 1, lmin, dmax, ORC_TOL);
+                                double s = 0.0;
+                                for (int k = 0; k < nd.n; ++k) {
+                                    double t = nd.x[k];
+                                    double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+                                    s += nd.w[k] * t * jn(0, t * rho) * zkern(C, lz, lzp, tz[i], sz[j]) *
+                                         sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz;
+                                }
+                                free_nodes(&nd);
+                                acc += sq[j] * s / (4.0 * ORC_PI);
+                            }
+                            npp++;
+                        }
+                        phi[i] += acc;
+                    }
+                }
+    }
+    st->p2p_pairs = npp;
+
+    for (int l = 0; l <= H; ++l) {
+        free(SB[l].key);
+        free(TB[l].key);
+    }
+    free(sorder);
+    free(sstart);
+    free(torder);
+    free(tstart);
+    free(Cs.cx);
+    free(Ct.cx);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Algorithm 2: all free-space and reaction components, summed.             */
+/* Components are enumerated as: free l = 0..L; then (a,b) = (1,1) for      */
+/* l = 0..L-1, l' = 0..L-1; (1,2) for l = 0..L-1, l' = 1..L; (2,1) for      */
+/* l = 1..L, l' = 0..L-1; (2,2) for l = 1..L, l' = 1..L.                    */
+/* ------------------------------------------------------------------------ */
+int orc_num_components(int nlayers)
+{
+    int L = nlayers - 1;
+    return (L + 1) + 4 * L * L;
+}
+
+/* Describe component c: out[0]=kind, out[1]=l, out[2]=lp, out[3]=a, out[4]=b */
+int orc_component(int nlayers, int c, int* out)
+{
+    int L = nlayers - 1;
+    if (c < 0) return -1;
+    if (c <= L) {
+        out[0] = 0;
+        out[1] = c;
+        out[2] = c;
+        out[3] = 0;
+        out[4] = 0;
+        return 0;
+    }
+    c -= L + 1;
+    for (int a = 1; a <= 2; ++a)
+        for (int b = 1; b <= 2; ++b) {
+            int l0 = (a == 1) ? 0 : 1, lp0 = (b == 1) ? 0 : 1;
+            for (int l = l0; l < l0 + L; ++l)
+                for (int lp = lp0; lp < lp0 + L; ++lp) {
+                    if (c == 0) {
+                        out[0] = 1;
+                        out[1] = l;
+                        out[2] = lp;
+                        out[3] = a;
+                        out[4] = b;
+                        return 0;
+                    }
+                    c--;
+                }
+        }
+    return -1;
+}
+
+/* Root cube of a component: free -> the bounding cube of the layer's
+ * charges; reaction -> centred (in z) on the interface between targets and
+ * images (Sec. 3.5: the largest box is divided in half by the interface),
+ * centred in x,y on the bounding box of targets and sources. */
+static void root_free(int n, const double* x, const double* y, const double* z, double* c, double* R)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int i = 0; i < n; ++i) {
+        double v[3] = {x[i], y[i], z[i]};
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fmin(lo[k], v[k]);
+            hi[k] = fmax(hi[k], v[k]);
+        }
+    }
+    double r = 0.0;
+    for (int k = 0; k < 3; ++k) {
+        c[k] = 0.5 * (lo[k] + hi[k]);
+        r = fmax(r, 0.5 * (hi[k] - lo[k]));
+    }
+    *R = r > 0 ? r : 0.5;
+}
+
+static void root_reaction(int nt, const double* tx, const double* ty, const double* tz, int ns, const double* sx,
+                          const double* sy, const double* sz_img, double zi, double* c, double* R)
+{
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
+    double r = 0.0;
+    for (int i = 0; i < nt; ++i) {
+        lo[0] = fmin(lo[0], tx[i]);
+        hi[0] = fmax(hi[0], tx[i]);
+        lo[1] = fmin(lo[1], ty[i]);
+        hi[1] = fmax(hi[1], ty[i]);
+        r = fmax(r, fabs(tz[i] - zi));
+    }
+    for (int i = 0; i < ns; ++i) {
+        lo[0] = fmin(lo[0], sx[i]);
+        hi[0] = fmax(hi[0], sx[i]);
+        lo[1] = fmin(lo[1], sy[i]);
+        hi[1] = fmax(hi[1], sy[i]);
+        r = fmax(r, fabs(sz_img[i] - zi));
+    }
+    c[0] = 0.5 * (lo[0] + hi[0]);
+    c[1] = 0.5 * (lo[1] + hi[1]);
+    c[2] = zi;
+    r = fmax(r, 0.5 * (hi[0] - lo[0]));
+    r = fmax(r, 0.5 * (hi[1] - lo[1]));
+    *R = r > 0 ? r : 0.5;
+}
+
+/* Full layered FMM (Algorithm 2).  phi[n] receives the potential at every
+ * charge in input order; comp_phi (nullable) [ncomp][n] receives each
+ * component's contribution; stats (nullable) [ncomp][6] receives
+ * depth, target leaves, source leaves, M2L pairs, P2P pairs, recurrence
+ * stability violation flag. */
+int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, int64_t n, const double* x,
+            const double* y, const double* z, const double* q, int p, int leaf_cap, int nthreads, double* phi,
+            double* comp_phi, double* stats)
+{
+    layers_t Ly;
+    if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
+    if (Ly.L != 2 && Ly.L != 0) return -2;
+    if (p < 0 || p > ORC_PMAX || leaf_cap < 1) return -3;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+    int ncomp = orc_num_components(nlayers);
+    int* lay = (int*)malloc(sizeof(int) * (n > 0 ? n : 1));
+    for (int64_t i = 0; i < n; ++i) lay[i] = layer_of(&Ly, z[i]);
+    memset(phi, 0, sizeof(double) * n);
+    if (comp_phi) memset(comp_phi, 0, sizeof(double) * n * ncomp);
+    gaunt_tab_t GT;
+    gaunt_tab_init(&GT, p);
+    for (int c = 0; c < ncomp; ++c) {
+        int desc[5];
+        orc_component(nlayers, c, desc);
+        int kind = desc[0], l = desc[1], lp = desc[2], a = desc[3], b = desc[4];
+        /* gather targets (layer l) and sources (layer lp) */
+        int nt = 0, ns = 0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (lay[i] == l) nt++;
+            if (lay[i] == lp) ns++;
+        }
+        double* buf = (double*)malloc(sizeof(double) * (3 * nt + 4 * ns + nt + 1));
+        double *tx = buf, *ty = tx + nt, *tz = ty + nt, *sx = tz + nt, *sy = sx + ns, *sz = sy + ns, *sq = sz + ns;
+        double* ph = sq + ns;
+        int64_t* tid = (int64_t*)malloc(sizeof(int64_t) * (nt + ns + 1));
+        int64_t* sid = tid + nt;
+        int it = 0, is = 0;
+        double zi = 0.0;
+        if (kind == 1) zi = (a == 1) ? Ly.d[l] : Ly.d[l - 1];
+        for (int64_t i = 0; i < n; ++i) {
+            if (lay[i] == l) {
+                tx[it] = x[i];
+                ty[it] = y[i];
+                tz[it] = z[i];
+                tid[it++] = i;
+            }
+            if (lay[i] == lp) {
+                sx[is] = x[i];
+                sy[is] = y[i];
+                if (kind == 0) sz[is] = z[i];
+                else {
+                    /* equivalent polarization coordinate (eq. equivpolarcoord, with the
+                     * source's own z in place of the printed z_{lj}) */
+                    double ts = tau_s(&Ly, lp, b, z[i]);
+                    sz[is] = (a == 1) ? Ly.d[l] - ts : Ly.d[l - 1] + ts;
+                }
+                sq[is] = q[i];
+                sid[is++] = i;
+            }
+        }
+        fmmspec_t F;
+        memset(&F, 0, sizeof(F));
+        F.kind = kind;
+        F.rc.Ly = Ly;
+        F.rc.l = l;
+        F.rc.lp = lp;
+        F.rc.a = a;
+        F.rc.b = b;
+        F.lam_t = Ly.lam[l];
+        F.lam_s = Ly.lam[lp];
+        F.eps_t = Ly.eps[l];
+        /* free space: e^{-lam r}/(4 pi eps r) = (lam / (2 pi^2 eps)) k_0(lam r) */
+        F.far_factor = (kind == 0) ? Ly.lam[l] / (2.0 * ORC_PI * ORC_PI * Ly.eps[l]) : 1.0;
+        double ctr[3], R;
+        if (kind == 0) root_free(nt, tx, ty, tz, ctr, &R);
+        else root_reaction(nt, tx, ty, tz, ns, sx, sy, sz, zi, ctr, &R);
+        ctab_t CT;
+        CT.v = NULL;
+        if (kind == 1) ctab_init(&CT, p, Ly.lam[l], Ly.lam[lp]);
+        fmmstat_t st;
+        run_fmm(&F, p, leaf_cap, ns, sx, sy, sz, sq, sid, nt, tx, ty, tz, tid, ctr[0], ctr[1], ctr[2], R, &GT,
+                kind == 1 ? &CT : NULL, ph, &st);
+        if (CT.v) free(CT.v);
+        for (int k = 0; k < nt; ++k) {
+            phi[tid[k]] += ph[k];
+            if (comp_phi) comp_phi[(size_t)c * n + tid[k]] = ph[k];
+        }
+        if (stats) {
+            double* s = stats + (size_t)c * 6;
+            s[0] = st.depth;
+            s[1] = st.nleaf_t;
+            s[2] = st.nleaf_s;
+            s[3] = (double)st.m2l_pairs;
+            s[4] = (double)st.p2p_pairs;
+            s[5] = st.unstable;
+        }
+        free(buf);
+        free(tid);
+    }
+    gaunt_tab_free(&GT);
+    free(lay);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Single-source expansion chains used by the operator pins.                */
+/* ------------------------------------------------------------------------ */
+
+/* Free space: source r', ME centre cs, (optional) M2M to cs2, M2L to LE
+ * centre ct, (optional) L2L to ct2, evaluate at r; returns the expansion of
+ * k_0(lam |r - r'|).  mode bit 0: do M2M (cs -> cs2); bit 1: do L2L. */
+double orc_free_chain(int p, double lam, const double* rs, const double* cs, const double* cs2, const double* ct,
+                      const double* ct2, const double* r, int mode)
+{
+    int K = (p + 1) * (p + 1);
+    gaunt_tab_t GT;
+    gaunt_tab_init(&GT, p);
+    cplx* M = (cplx*)calloc(K, sizeof(cplx));
+    cplx* M2 = (cplx*)calloc(K, sizeof(cplx));
+    cplx* L = (cplx*)calloc(K, sizeof(cplx));
+    cplx* L2 = (cplx*)calloc(K, sizeof(cplx));
+    cplx* A = (cplx*)malloc(sizeof(cplx) * K * K);
+    p2m_one(p, lam, 1.0, rs[0] - cs[0], rs[1] - cs[1], rs[2] - cs[2], M);
+    const double* c_me = cs;
+    if (mode & 1) {
+        free_operator(&GT, 0, lam, cs[0] - cs2[0], cs[1] - cs2[1], cs[2] - cs2[2], A);
+        apply_op(K, A, M, M2);
+        memcpy(M, M2, sizeof(cplx) * K);
+        c_me = cs2;
+    }
+    free_operator(&GT, 2, lam, ct[0] - c_me[0], ct[1] - c_me[1], ct[2] - c_me[2], A);
+    apply_op(K, A, M, L);
+    const double* c_le = ct;
+    if (mode & 2) {
+        free_operator(&GT, 1, lam, ct2[0] - ct[0], ct2[1] - ct[1], ct2[2] - ct[2], A);
+        apply_op(K, A, L, L2);
+        memcpy(L, L2, sizeof(cplx) * K);
+        c_le = ct2;
+    }
+    double v = l2p_one(p, lam, L, r[0] - c_le[0], r[1] - c_le[1], r[2] - c_le[2]);
+    free(M);
+    free(M2);
+    free(L);
+    free(L2);
+    free(A);
+    gaunt_tab_free(&GT);
+    return v;
+}
+
+/* Free-space addition theorems evaluated directly (pins for the operators):
+ * which = 0: returns sum_{nu<=p,mu} Sh_{n nu}^{m mu}(b) i_nu Y_nu^mu(r) (complex, out[2])
+ * which = 1: returns sum_{nu<=p,mu} S_{n nu}^{m mu}(b) i_nu Y_nu^mu(r)                  */
+void orc_addition_sum(int p, int pq, double lam, int n, int m, const double* b, const double* r, int which,
+                      double* out)
+{
+    /* build the operators at order pq >= n for the rows, truncating columns at p */
+    int P = pq > p ? pq : p;
+    int K = (P + 1) * (P + 1);
+    gaunt_tab_t GT;
+    gaunt_tab_init(&GT, P);
+    cplx* A = (cplx*)malloc(sizeof(cplx) * K * K);
+    /* kind 1 gives A_{(n,m),(nu,mu)} = Sh_{nu n}^{mu m}; take the transpose entries */
+    free_operator(&GT, which == 0 ? 1 : 2, lam, b[0], b[1], b[2], A);
+    cplx* Y = (cplx*)malloc(sizeof(cplx) * K);
+    ylm_c(P, r[0], r[1], r[2], Y);
+    double rr = sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    cplx s = 0.0;
+    for (int nu = 0; nu <= p; ++nu)
+        for (int mu = -nu; mu <= nu; ++mu)
+            s += A[(size_t)idx_nm(nu, mu) * K + idx_nm(n, m)] * orc_bessel_i(nu, lam * rr) * Y[idx_nm(nu, mu)];
+    out[0] = creal(s);
+    out[1] = cimag(s);
+    free(A);
+    free(Y);
+    gaunt_tab_free(&GT);
+}
+
+/* Reaction component, single source: the image of r' (equivalent
+ * polarization coordinate), ME about the image centre cs (which must lie on
+ * the image side), M2L to the target centre ct, LE evaluated at r.  Returns
+ * the expansion value of u^{ab}_{l lp}(r, r'). */
+double orc_reaction_chain(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
+                          int p, const double* rs, const double* cs, const double* ct, const double* r, int* unstable)
+{
+    rcomp_t C;
+    fill_layers(&C.Ly, L + 1, eps, lam, d);
+    C.l = l;
+    C.lp = lp;
+    C.a = a;
+    C.b = b;
+    if (L != 2 || !comp_valid(&C.Ly, l, lp, a, b)) return NAN;
+    int K = (p + 1) * (p + 1);
+    double ts = tau_s(&C.Ly, lp, b, rs[2]);
+    double zimg = (a == 1) ? C.Ly.d[l] - ts : C.Ly.d[l - 1] + ts;
+    cplx* M = (cplx*)calloc(K, sizeof(cplx));
+    cplx* Lc = (cplx*)calloc(K, sizeof(cplx));
+    cplx* Im = (cplx*)malloc(sizeof(cplx) * K * K);
+    cplx* A = (cplx*)malloc(sizeof(cplx) * K * K);
+    p2m_one(p, lam[lp], 1.0, rs[0] - cs[0], rs[1] - cs[1], zimg - cs[2], M);
+    ctab_t CT;
+    ctab_init(&CT, p, lam[l], lam[lp]);
+    double rho = hypot(ct[0] - cs[0], ct[1] - cs[1]);
+    double ph = (ct[0] == cs[0] && ct[1] == cs[1]) ? 0.0 : atan2(ct[1] - cs[1], ct[0] - cs[0]);
+    /* the scaling length S only rescales intermediate values; use the centre separation */
+    double S = fmin(fabs(ct[2] - cs[2]), rho > 0 ? rho : INFINITY);
+    int uu = 0;
+    reaction_I_matrix(&C, &CT, p, rho, ct[2], cs[2], S, Im, &uu);
+    if (unstable) *unstable = uu;
+    reaction_T_from_I(&C, p, Im, ph, A);
+    apply_op(K, A, M, Lc);
+    double v = l2p_one(p, lam[l], Lc, r[0] - ct[0], r[1] - ct[1], r[2] - ct[2]);
+    free(M);
+    free(Lc);
+    free(Im);
+    free(A);
+    free(CT.v);
+    return v;
+}
+
+/* Recurrence-versus-direct-quadrature pin: I_{nm,nu mu} of a component at
+ * (rho, zt, zs) from the recurrence path (eq. metoletableform) and from
+ * direct quadrature with Q = P^ P^.  out: [re_rec, im_rec, re_dir, im_dir]. */
+void orc_reaction_I_pair(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
+                         int p, double rho, double zt, double zs, double S, int n, int m, int nu, int mu, double* out)
+{
+    rcomp_t C;
+    fill_layers(&C.Ly, L + 1, eps, lam, d);
+    C.l = l;
+    C.lp = lp;
+    C.a = a;
+    C.b = b;
+    int nmax = 2 * p + 3;
+    double* tab = (double*)malloc(sizeof(double) * 4 * (nmax + 1) * (nmax + 1));
+    sommerfeld_table(&C, rho, zt, zs, S, nmax, tab);
+    ctab_t CT;
+    ctab_init(&CT, p, lam[l], lam[lp]);
+    cplx v = assemble_I(&CT, tab, nmax, S, n, m, nu, mu);
+    cplx w = reaction_I_direct_one(&C, n, m, nu, mu, rho, zt, zs);
+    out[0] = creal(v);
+    out[1] = cimag(v);
+    out[2] = creal(w);
+    out[3] = cimag(w);
+    free(tab);
+    free(CT.v);
+}
+
+/* Raw scaled Sommerfeld table (for the recurrence pins):
+ * out[((i*2+j)*(nmax+1)+n)*(nmax+1)+m] = S^n Sc_{nm,ij}; mode 0 = recurrence
+ * path, mode 1 = every entry by direct quadrature of eq. M2Ltable. */
+int orc_sommerfeld_table(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
+                         double rho, double zt, double zs, double S, int nmax, int mode, double* out)
+{
+    rcomp_t C;
+    fill_layers(&C.Ly, L + 1, eps, lam, d);
+    C.l = l;
+    C.lp = lp;
+    C.a = a;
+    C.b = b;
+    if (mode == 0) return sommerfeld_table(&C, rho, zt, zs, S, nmax, out);
+    const layers_t* Ly = &C.Ly;
+    int N1 = nmax + 1;
+    double lt = Ly->lam[l], ls = Ly->lam[lp];
+    memset(out, 0, sizeof(double) * 4 * N1 * N1);
+    nodes_t nd;
+    build_nodes(&nd, rho, zsep(&C, zt, zs), nmax, layers_lam_min(Ly), layers_dmax(Ly), ORC_TOL);
+    for (int k = 0; k < nd.n; ++k) {
+        double t = nd.x[k];
+        double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+        double base = nd.w[k] * zkern(&C, lz, lzp, zt, zs) * sigma(Ly, l, lp, a, b, t) / lz;
+        for (int m = 0; m <= nmax; ++m) {
+            double jm = jn(m, t * rho);
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    double f = base * (i ? lt / lz : 1.0) * (j ? ls / lzp : 1.0) * jm;
+                    for (int n = m; n <= nmax; ++n)
+                        out[((i * 2 + j) * N1 + n) * N1 + m] +=
+                            f * pow(t * S, n) / sqrt(fact(n + m) * fact(n - m));
+                }
+        }
+    }
+    free_nodes(&nd);
+    return 0;
+}
+
+/* Legendre-product expansion pin: returns sum_s C^s lrho^{|m|+|mu|+2s}
+ * (l/l_z)^i (l'/l'_z)^j and the product P^_n^m(l_z/l) P^_nu^mu(l'_z/l')
+ * evaluated directly; out = [re_exp, im_exp, re_dir, im_dir]. */
+void orc_legendre_product(int n, int m, int nu, int mu, double lam, double lamp, double lrho, double* out)
+{
+    double lz = sqrt(lam * lam + lrho * lrho), lzp = sqrt(lamp * lamp + lrho * lrho);
+    int i = (n + iabs(m)) % 2, j = (nu + iabs(mu)) % 2;
+    int r = (n + iabs(m)) / 2, rp = (nu + iabs(mu)) / 2;
+    cplx s = 0.0;
+    for (int k = 0; k <= (n - r) + (nu - rp); ++k)
+        s += c_coef(n, nu, m, mu, k, lam, lamp) * pow(lrho, iabs(m) + iabs(mu) + 2 * k);
+    s *= pow(lam / lz, i) * pow(lamp / lzp, j);
+    cplx dct = plm_big(n, m, lz / lam, lrho / lam) * plm_big(nu, mu, lzp / lamp, lrho / lamp);
+    out[0] = creal(s);
+    out[1] = cimag(s);
+    out[2] = creal(dct);
+    out[3] = cimag(dct);
+}
+
+/* Associated Legendre beyond [-1,1] on the paper's branch (for Prop. 3.2 pin) */
+void orc_plm_beyond(int n, int m, double w, double* out)
+{
+    cplx v = plm_big(n, m, w, sqrt(w * w - 1.0));
+    out[0] = creal(v);
+    out[1] = cimag(v);
+}
+
+/* Tree summary of one component, for the tree-equality parity test:
+ * out_depth, and for every target / source point its leaf Morton key. */
+int orc_component_tree(int nlayers, const double* eps, const double* lam, const double* d, int64_t n,
+                       const double* x, const double* y, const double* z, int comp, int leaf_cap, int* depth,
+                       int64_t* nt_out, int64_t* ns_out, uint64_t* tkeys, uint64_t* skeys, double* root)
+{
+    layers_t Ly;
+    if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
+    int desc[5];
+    if (orc_component(nlayers, comp, desc)) return -1;
+    int kind = desc[0], l = desc[1], lp = desc[2], a = desc[3], b = desc[4];
+    int nt = 0, ns = 0;
+    double* buf = (double*)malloc(sizeof(double) * 6 * (n + 1));
+    double *tx = buf, *ty = tx + n, *tz = ty + n, *sx = tz + n, *sy = sx + n, *sz = sy + n;
+    for (int64_t i = 0; i < n; ++i) {
+        int li = layer_of(&Ly, z[i]);
+        if (li == l) {
+            tx[nt] = x[i];
+            ty[nt] = y[i];
+            tz[nt++] = z[i];
+        }
+        if (li == lp) {
+            sx[ns] = x[i];
+            sy[ns] = y[i];
+            if (kind == 0) sz[ns] = z[i];
+            else {
+                double ts = tau_s(&Ly, lp, b, z[i]);
+                sz[ns] = (a == 1) ? Ly.d[l] - ts : Ly.d[l - 1] + ts;
+            }
+            ns++;
+        }
+    }
+    double c[3], R;
+    if (kind == 0) root_free(nt, tx, ty, tz, c, &R);
+    else root_reaction(nt, tx, ty, tz, ns, sx, sy, sz, (a == 1) ? Ly.d[l] : Ly.d[l - 1], c, &R);
+    cells_t Cs, Ct;
+    Cs.n = ns;
+    Ct.n = nt;
+    Cs.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (ns + 1));
+    Cs.cy = Cs.cx + ns;
+    Cs.cz = Cs.cy + ns;
+    Ct.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (nt + 1));
+    Ct.cy = Ct.cx + nt;
+    Ct.cz = Ct.cy + nt;
+    for (int i = 0; i < ns; ++i) {
+        Cs.cx[i] = fine_cell(sx[i], c[0], R);
+        Cs.cy[i] = fine_cell(sy[i], c[1], R);
+        Cs.cz[i] = fine_cell(sz[i], c[2], R);
+    }
+    for (int i = 0; i < nt; ++i) {
+        Ct.cx[i] = fine_cell(tx[i], c[0], R);
+        Ct.cy[i] = fine_cell(ty[i], c[1], R);
+        Ct.cz[i] = fine_cell(tz[i], c[2], R);
+    }
+    int H = ORC_MAXDEPTH;
+    for (int lv = 0; lv <= ORC_MAXDEPTH; ++lv) {
+        boxlev_t SB, TB;
+        distinct_boxes(&Cs, lv, &SB);
+        distinct_boxes(&Ct, lv, &TB);
+        int ok = (long long)ns <= (long long)leaf_cap * SB.nb && (long long)nt <= (long long)leaf_cap * TB.nb;
+        free(SB.key);
+        free(TB.key);
+        if (ok) {
+            H = lv;
+            break;
+        }
+    }
+    int sh = ORC_HMAX - H;
+    for (int i = 0; i < nt; ++i) tkeys[i] = morton_key(Ct.cx[i] >> sh, Ct.cy[i] >> sh, Ct.cz[i] >> sh, H);
+    for (int i = 0; i < ns; ++i) skeys[i] = morton_key(Cs.cx[i] >> sh, Cs.cy[i] >> sh, Cs.cz[i] >> sh, H);
+    *depth = H;
+    *nt_out = nt;
+    *ns_out = ns;
+    root[0] = c[0];
+    root[1] = c[1];
+    root[2] = c[2];
+    root[3] = R;
+    free(buf);
+    free(Cs.cx);
+    free(Ct.cx);
+    return 0;
+}

@@ -1,0 +1,161 @@
+"""Seeded synthetic inputs for the layered-media workloads.
+
+This module holds only random-number generation and geometry recipes (no
+arithmetic of the method); tests, the benchmark and the oracle checks all
+draw their charges from here.
+
+Generator: SplitMix64 (Steele, Lea, Flood 2014).  Draw k (k = 0, 1, ...) of a
+stream seeded with s is mix(s + (k+1) * 0x9E3779B97F4A7C15) with the
+published finaliser; a uniform double is (draw >> 11) * 2^-53.  Gaussians use
+Box-Muller on two consecutive uniforms.
+
+Workload recipe (the paper's three-layer test problem, Sec. 4, re-centred
+in unit cubes): interfaces z = 0 and z = -1.2; layer 0 charges uniform in
+[-0.5,0.5]^2 x [0.1,1.1], layer 1 in [-0.5,0.5]^2 x [-1.1,-0.1], layer 2 in
+[-0.5,0.5]^2 x [-2.3,-1.3] (centres (0,0,0.6), (0,0,-0.6), (0,0,-1.8) as in
+the paper, 0.1 clearance from every interface); charges q ~ U[-1,1].
+Per layer the draws are x, y, z, q for charge 0, then charge 1, and so on;
+layers are drawn in order 0, 1, 2 from one stream.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+_GAMMA = np.uint64(0x9E3779B97F4A7C15)
+_M1 = np.uint64(0xBF58476D1CE4E5B9)
+_M2 = np.uint64(0x94D049BB133111EB)
+
+
+class SplitMix64:
+    """Counter form of SplitMix64: draw k = mix(seed + (k+1)*gamma)."""
+
+    def __init__(self, seed: int):
+        self.seed = np.uint64(seed & 0xFFFFFFFFFFFFFFFF)
+        self.k = 0
+
+    def draws(self, count: int) -> np.ndarray:
+        with np.errstate(over="ignore"):
+            idx = np.arange(self.k + 1, self.k + 1 + count, dtype=np.uint64)
+            z = self.seed + idx * _GAMMA
+            z = (z ^ (z >> np.uint64(30))) * _M1
+            z = (z ^ (z >> np.uint64(27))) * _M2
+            z = z ^ (z >> np.uint64(31))
+        self.k += count
+        return z
+
+    def uniform(self, count: int) -> np.ndarray:
+        return (self.draws(count) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
+@dataclasses.dataclass
+class LayeredProblem:
+    eps: np.ndarray
+    lam: np.ndarray
+    d: np.ndarray        # interfaces, strictly decreasing
+    x: np.ndarray
+    y: np.ndarray
+    z: np.ndarray
+    q: np.ndarray
+    layer: np.ndarray    # layer index of each charge
+
+    @property
+    def n(self) -> int:
+        return len(self.x)
+
+
+EPS3 = (1.0, 2.0, 4.0)
+LAM3 = (1.2, 1.5, 2.0)
+D3 = (0.0, -1.2)
+# z-ranges of the unit cubes of the three layers
+ZBOX3 = ((0.1, 1.1), (-1.1, -0.1), (-2.3, -1.3))
+
+
+def _uniform_block(rng: SplitMix64, n: int, lo, hi):
+    u = rng.uniform(4 * n).reshape(n, 4)
+    x = lo[0] + (hi[0] - lo[0]) * u[:, 0]
+    y = lo[1] + (hi[1] - lo[1]) * u[:, 1]
+    z = lo[2] + (hi[2] - lo[2]) * u[:, 2]
+    q = -1.0 + 2.0 * u[:, 3]
+    return x, y, z, q
+
+
+def _gauss_block(rng: SplitMix64, n: int, lo, hi, sigma: float):
+    """Gaussian about the cube centre, redrawn until inside the cube."""
+    lo = np.asarray(lo, float)
+    hi = np.asarray(hi, float)
+    c = 0.5 * (lo + hi)
+    out = np.empty((n, 3))
+    filled = 0
+    while filled < n:
+        need = n - filled
+        u = rng.uniform(6 * need).reshape(need, 6)
+        r1 = np.sqrt(-2.0 * np.log(np.maximum(u[:, 0::2], 2.0 ** -53)))
+        g = r1 * np.cos(2.0 * np.pi * u[:, 1::2])
+        pts = c + sigma * g
+        ok = np.all((pts >= lo) & (pts <= hi), axis=1)
+        k = int(ok.sum())
+        out[filled:filled + k] = pts[ok]
+        filled += k
+    q = -1.0 + 2.0 * rng.uniform(n)
+    return out[:, 0], out[:, 1], out[:, 2], q
+
+
+def three_layer(per_layer, seed: int = 0, clustered_fraction: float = 0.0, sigma: float = 0.1,
+                eps=EPS3, lam=LAM3) -> LayeredProblem:
+    """Charges in the three unit cubes (per_layer an int or 3 ints)."""
+    if np.isscalar(per_layer):
+        per_layer = (int(per_layer),) * 3
+    rng = SplitMix64(seed)
+    xs, ys, zs, qs, ls = [], [], [], [], []
+    for l, n in enumerate(per_layer):
+        lo = (-0.5, -0.5, ZBOX3[l][0])
+        hi = (0.5, 0.5, ZBOX3[l][1])
+        nc = int(round(clustered_fraction * n))
+        x, y, z, q = _uniform_block(rng, n - nc, lo, hi)
+        if nc:
+            gx, gy, gz, gq = _gauss_block(rng, nc, lo, hi, sigma)
+            x, y, z, q = (np.concatenate(a) for a in ((x, gx), (y, gy), (z, gz), (q, gq)))
+        xs.append(x); ys.append(y); zs.append(z); qs.append(q); ls.append(np.full(n, l, np.int32))
+    return LayeredProblem(np.array(eps, float), np.array(lam, float), np.array(D3, float),
+                          np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(qs),
+                          np.concatenate(ls))
+
+
+def batch_system(k: int, nmin: float = 1e3, nmax: float = 5e4) -> LayeredProblem:
+    """System k of the batched workload: seed 1000+k; N_total log-uniform in
+    [nmin, nmax], split floor(N/3) per layer with the remainder in layer 0;
+    eps ~ U[1,80], lambda ~ U[0.5,3] per layer; middle thickness D ~ U[0.8,2],
+    interfaces (0, -D); middle cube side min(1, D-0.2) centred at -D/2; top and
+    bottom unit cubes at 0.1 clearance."""
+    rng = SplitMix64(1000 + k)
+    u = rng.uniform(8)
+    ntot = int(np.exp(np.log(nmin) + (np.log(nmax) - np.log(nmin)) * u[0]))
+    eps = 1.0 + 79.0 * u[1:4]
+    lam = 0.5 + 2.5 * u[4:7]
+    D = 0.8 + 1.2 * u[7]
+    per = [ntot // 3] * 3
+    per[0] += ntot - 3 * (ntot // 3)
+    side = min(1.0, D - 0.2)
+    boxes = [((-0.5, -0.5, 0.1), (0.5, 0.5, 1.1)),
+             ((-side / 2, -side / 2, -D / 2 - side / 2), (side / 2, side / 2, -D / 2 + side / 2)),
+             ((-0.5, -0.5, -D - 1.1), (0.5, 0.5, -D - 0.1))]
+    xs, ys, zs, qs, ls = [], [], [], [], []
+    for l in range(3):
+        x, y, z, q = _uniform_block(rng, per[l], boxes[l][0], boxes[l][1])
+        xs.append(x); ys.append(y); zs.append(z); qs.append(q); ls.append(np.full(per[l], l, np.int32))
+    return LayeredProblem(eps, lam, np.array([0.0, -D]), np.concatenate(xs), np.concatenate(ys),
+                          np.concatenate(zs), np.concatenate(qs), np.concatenate(ls))
+
+
+def sample_targets(prob: LayeredProblem, per_layer: int, seed: int = 1) -> np.ndarray:
+    """per_layer distinct charge indices from each layer (sorted)."""
+    rng = SplitMix64(seed)
+    out = []
+    for l in range(len(prob.eps)):
+        idx = np.nonzero(prob.layer == l)[0]
+        k = min(per_layer, len(idx))
+        keys = rng.draws(len(idx))
+        out.append(idx[np.argsort(keys, kind="stable")[:k]])
+    return np.sort(np.concatenate(out))
