@@ -1,0 +1,173 @@
+/*
+ * lpb.h -- C ABI of the MI355X layered-media linearized Poisson-Boltzmann
+ * (screened Coulomb) fast multipole library.
+ *
+ * Problem (Wang, Zhang, Cai, "Fast Multipole Method for 3-D Linearized
+ * Poisson-Boltzmann Equation in Layered Media", Sec. 2): layers l = 0..L
+ * stacked top to bottom, interfaces z = d_0 > d_1 > ... > d_{L-1}; layer l
+ * has dielectric constant eps_l > 0 and inverse Debye length lambda_l > 0.
+ * For charges Q_j at r_j strictly inside the layers, the library returns
+ *
+ *   Phi(r_i) = sum_{j != i, same layer} Q_j e^{-lambda_l |r_i-r_j|} / (4 pi eps_l |r_i-r_j|)
+ *            + sum_{all j} Q_j u^react_{l l'}(r_i, r_j)                       (eq. potential1)
+ *
+ * where u^react is the reaction part of the layered Green's function
+ * (eqs. layeredGreensfun, reactioncomponent).  The free-space part is a
+ * Yukawa FMM per layer; every reaction component (l, l', a, b) is an FMM over
+ * equivalent polarization sources (Sec. 3.3-3.5, Algorithms 1 and 2).
+ *
+ * Conventions
+ *  - Every function returns lpb_status (0 = LPB_OK, < 0 = error) except
+ *    lpb_last_error / lpb_destroy / lpb_default_options.  No exception or
+ *    abort crosses the ABI; on error the message is available from
+ *    lpb_last_error(ctx) until the next call on that context.
+ *  - Pointers marked "host or device" may be either; the flag `on_device`
+ *    tells which (1 = device memory of the context's GPU, 0 = host memory).
+ *    The caller owns every array it passes and the library never frees it.
+ *  - A context belongs to one GPU and one HIP stream (lpb_options.stream,
+ *    NULL = the null stream).  Calls on one context are not thread-safe.
+ *  - Call order: lpb_set_layers, then lpb_build_tree, then lpb_evaluate
+ *    (repeatable with new charges).  Calling lpb_set_layers again rebuilds
+ *    the plan for the stored charge positions; lpb_build_tree again replaces
+ *    them.  Anything else returns LPB_ESTATE.
+ *  - Precision: LPB_FP64 runs every stage in double precision.  LPB_MIXED
+ *    runs P2M/M2M/M2L/L2L/L2P/P2P in single precision with double-precision
+ *    Bessel ratios and double-precision operator generation (quadrature,
+ *    recurrence, translation coefficients); the output is double in both.
+ */
+#ifndef LPB_H
+#define LPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lpb_ctx lpb_ctx;
+
+typedef enum {
+    LPB_OK = 0,
+    LPB_EINVAL = -1,   /* bad argument (null pointer, size, non-monotone interfaces, eps/lambda <= 0) */
+    LPB_ERANGE = -2,   /* charge on or too close to an interface, p or leaf_cap out of range */
+    LPB_ENOMEM = -3,   /* device or host allocation failed */
+    LPB_EDEVICE = -4,  /* HIP runtime error */
+    LPB_ESTATE = -5,   /* wrong call order */
+    LPB_ENUMERIC = -6  /* NaN/Inf input, quadrature budget exceeded, recurrence stability bound violated */
+} lpb_status;
+
+typedef enum { LPB_FP64 = 0, LPB_MIXED = 1 } lpb_precision;
+
+#define LPB_MAX_P 20
+#define LPB_MAX_LAYERS 9
+
+typedef struct {
+    int p;                  /* expansion order: degrees n = 0..p (1 <= p <= LPB_MAX_P); default 10 */
+    int leaf_cap;           /* target mean charges per leaf (tree depth rule, see lpb_build_tree); default 50 */
+    int precision;          /* lpb_precision; default LPB_FP64 */
+    double quad_tol;        /* relative cut of the Sommerfeld quadrature envelope; default 1e-16 */
+    double iface_tol;       /* minimum distance of a charge from an interface; default 1e-9 */
+    int device;             /* HIP device ordinal; default 0 */
+    void* stream;           /* hipStream_t for all work; NULL = null stream */
+    int stages;             /* diagnostics: bit 0 far field (P2M..L2P), bit 1 near field; default 3 (both) */
+} lpb_options;
+
+typedef struct {
+    int n_fmm;              /* free-space + reaction FMMs in the plan */
+    int max_depth;          /* deepest tree level over all FMMs */
+    int64_t n_m2l_pairs;    /* V-list pairs */
+    int64_t n_p2p_pairs;    /* near-field charge pairs (free + reaction) */
+    int64_t n_react_p2p_pairs; /* near-field reaction pairs (each a Sommerfeld quadrature) */
+    int64_t n_operators;    /* translation operators generated */
+    int64_t operator_bytes; /* device bytes held by operators */
+    double t_build_ms;      /* last lpb_build_tree (host tree + upload) */
+    double t_opgen_ms;      /* last operator generation (GPU, FP64) */
+    double t_eval_ms;       /* last lpb_evaluate, stream time between its first and last kernel */
+} lpb_stats;
+
+/* Fill *opt with the defaults listed above.  Never fails. */
+void lpb_default_options(lpb_options* opt);
+
+/* Create a context on opt->device.  opt may be NULL (defaults).
+ * Errors: LPB_EINVAL (out == NULL), LPB_ERANGE (p, leaf_cap), LPB_EDEVICE,
+ * LPB_ENOMEM.  On error *out is NULL. */
+lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out);
+
+/* Set the layered medium (Sec. 2.1): n_layers = L+1 layers (1..LPB_MAX_LAYERS),
+ * eps[n_layers] > 0, lambda[n_layers] > 0, interfaces[L] strictly decreasing
+ * (d_0 > d_1 > ...); all host pointers.  The reaction densities sigma^{ab}_{l l'}
+ * are obtained on the GPU by solving the transmission conditions.
+ * Invalidates operators (regenerated by the next evaluate). */
+lpb_status lpb_set_layers(lpb_ctx* ctx, int n_layers, const double* eps, const double* lambda,
+                          const double* interfaces);
+
+/* Set the charge positions of one system (host or device, n doubles each)
+ * and build the plan: the layer of every charge, the images (equivalent
+ * polarization coordinates, eq. equivpolarcoord) of every reaction
+ * component, and one uniform octree per FMM: root cube = bounding cube of
+ * the layer (free space) or a cube whose mid-plane is the interface between
+ * targets and images (reaction); depth = smallest level at which sources
+ * and targets both average at most leaf_cap per non-empty box; V-lists and
+ * U-lists as in the classic FMM.  Requires lpb_set_layers first (the layer
+ * of a charge depends on the interfaces).  Errors: LPB_ERANGE if a charge
+ * lies within iface_tol of an interface, LPB_ENUMERIC for NaN/Inf. */
+lpb_status lpb_build_tree(lpb_ctx* ctx, int64_t n, const double* x, const double* y, const double* z, int on_device);
+
+/* Evaluate Phi at every charge (input order) for charges q[n]; q and phi are
+ * host or device memory as on_device says.  Runs Algorithm 2 on the
+ * context's stream and waits for it.  Generates the translation operators
+ * first if the layers or the tree changed.  phi may not alias q. */
+lpb_status lpb_evaluate(lpb_ctx* ctx, const double* q, double* phi, int on_device);
+
+/* Batched form: one context holding n_sys independent layered systems, all
+ * evaluated by the same stage launches (each stage covers every FMM of every
+ * system).  Set up with lpb_set_systems + lpb_build_trees (arrays of
+ * per-system pointers); evaluate with lpb_evaluate_batch.  A context is
+ * either single-system (set_layers/build_tree/evaluate) or batched. */
+lpb_status lpb_set_systems(lpb_ctx* ctx, int n_sys, const int* n_layers, const double* const* eps,
+                           const double* const* lambda, const double* const* interfaces);
+lpb_status lpb_build_trees(lpb_ctx* ctx, int n_sys, const int64_t* n, const double* const* x,
+                           const double* const* y, const double* const* z, int on_device);
+lpb_status lpb_evaluate_batch(lpb_ctx* ctx, int n_sys, const double* const* q, double* const* phi, int on_device);
+
+/* Counters and timings of the last calls.  Errors: LPB_EINVAL. */
+lpb_status lpb_get_stats(const lpb_ctx* ctx, lpb_stats* stats);
+
+/* Description of FMM number `fmm` of system `sys` in the plan (0 <= fmm < n_fmm):
+ * desc[0] = kind (0 free space, 1 reaction), desc[1] = target layer l,
+ * desc[2] = source layer l', desc[3] = a, desc[4] = b (0 for free space),
+ * desc[5] = depth H; root[4] = centre x, y, z and half side R;
+ * if tkeys/skeys are not NULL they receive, for the targets / sources of
+ * that FMM in increasing charge-index order, the Morton key of their leaf at
+ * level H (cell index per axis = floor(((x - cx) + R) / (2R) * 2^16) clamped
+ * to [0, 65535], shifted right by 16 - H; bits interleaved x, y, z from the
+ * most significant level down); *nt, *ns receive the counts.  Host memory. */
+lpb_status lpb_fmm_info(const lpb_ctx* ctx, int sys, int fmm, int* desc, double* root, int64_t* nt, int64_t* ns,
+                        uint64_t* tkeys, uint64_t* skeys);
+
+/* Diagnostic: copy the per-component potentials of the last evaluate to
+ * host memory out[nslots * n_total] (component slot k of charge i at
+ * out[k * n_total + i], charges of all systems concatenated in system order;
+ * slot 0 is the free-space part, slots 1.. the reaction components that
+ * target the charge's layer in the order of Algorithm 2).  *nslots receives
+ * the slot count; out may be NULL to query it. */
+lpb_status lpb_debug_parts(const lpb_ctx* ctx, double* out, int* nslots);
+
+/* Message of the last failed call on ctx (owned by ctx).  ctx == NULL gives
+ * the message of the last failed lpb_create in this thread. */
+const char* lpb_last_error(const lpb_ctx* ctx);
+
+/* Free the context and all device memory it holds.  NULL is a no-op. */
+void lpb_destroy(lpb_ctx* ctx);
+
+/* Host-side diagnostic: the Gaunt integral int Y_{n1}^{m1} Y_{n2}^{m2} Y_{n3}^{m3} dOmega
+ * (harmonics Y_n^m = P^_n^m(cos t) e^{i m p}, no Condon-Shortley phase) the
+ * library tabulates for its translation operators (Theorems 3.2, 3.3).
+ * Runs on the host only. */
+double lpb_host_gaunt(int n1, int m1, int n2, int m2, int n3, int m3);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LPB_H */

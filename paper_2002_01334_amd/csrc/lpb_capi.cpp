@@ -1,0 +1,711 @@
+// lpb_capi.cpp -- the C ABI of include/lpb.h: context, validation, device
+// memory, plan upload, operator generation and evaluation on the stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "lpb_eval.h"
+#include "lpb_internal.h"
+#include "lpb_opgen.h"
+
+using namespace lpb;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace
+
+struct lpb_ctx {
+    lpb_options opt{};
+    hipStream_t stream = nullptr;
+    std::string err;
+    // problem
+    bool have_layers = false, have_tree = false, batched = false;
+    std::vector<Medium> media;
+    std::vector<std::vector<double>> xs, ys, zs;
+    Plan plan;
+    bool ops_dirty = true;
+    // host tables (depend on p only)
+    std::vector<double> btab, gtab;
+    // device memory
+    std::vector<DevBuf> plan_bufs;   // freed on every plan rebuild
+    std::vector<DevBuf> op_bufs;     // freed on every operator rebuild
+    DevBuf d_btab, d_gtab, d_glx, d_glw, d_flag;
+    double* d_q = nullptr;
+    double* d_phi = nullptr;
+    void* d_pool_eval = nullptr;
+    // kernel arguments
+    EvalArgs<double> a64{};
+    EvalArgs<float> a32{};
+    EvalSched sched{};
+    OpgenInputs og{};
+    lpb_stats stats{};
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;
+};
+
+namespace {
+
+lpb_status fail(lpb_ctx* c, lpb_status s, const std::string& msg)
+{
+    if (c) c->err = msg;
+    else g_create_error = msg;
+    return s;
+}
+
+#define HIPCHK(c, call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail((c), e_ == hipErrorOutOfMemory ? LPB_ENOMEM : LPB_EDEVICE,                   \
+                        std::string(#call) + ": " + hipGetErrorString(e_));                          \
+    } while (0)
+
+void free_bufs(std::vector<DevBuf>& v)
+{
+    for (auto& b : v)
+        if (b.ptr) (void)hipFree(b.ptr);
+    v.clear();
+}
+
+template <typename T>
+lpb_status dalloc(lpb_ctx* c, std::vector<DevBuf>& pool, size_t n, T** out)
+{
+    *out = nullptr;
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess) return fail(c, LPB_ENOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    pool.push_back({p, bytes});
+    *out = (T*)p;
+    return LPB_OK;
+}
+
+template <typename T>
+lpb_status upload(lpb_ctx* c, std::vector<DevBuf>& pool, const std::vector<T>& v, T** out)
+{
+    lpb_status s = dalloc<T>(c, pool, v.size(), out);
+    if (s != LPB_OK) return s;
+    if (!v.empty()) {
+        hipError_t e = hipMemcpy(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("hipMemcpy: ") + hipGetErrorString(e));
+    }
+    return LPB_OK;
+}
+
+// b^t_{nm} of the Legendre-product expansion (Sec. 3.5):
+//   a^j_{nm} = (-1)^{n-j} (2j)! c_nm / (2^n j! (n-j)! (2j-n-m)!),
+//   b^t_{nm} = sum_{j=q}^{n} (-1)^t a^j_{nm} (j-r)! / (t! (j-r-t)!),
+//   r = floor((n+m)/2), q = max(ceil((n+m)/2), t+r),  c_nm = sqrt((2n+1)/(4 pi) (n-m)!/(n+m)!).
+void make_btab(int p, std::vector<double>& b)
+{
+    auto f = [](int n) {
+        long double v = 1.0L;
+        for (int k = 2; k <= n; ++k) v *= k;
+        return v;
+    };
+    const int BT = p + 1;
+    b.assign((size_t)(p + 1) * (p + 2) / 2 * BT, 0.0);
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            long double c = std::sqrt((2.0L * n + 1.0L) / (4.0L * 3.14159265358979323846264338327950288L) * f(n - m) / f(n + m));
+            int r = (n + m) / 2;
+            for (int t = 0; t <= n - r; ++t) {
+                int q = std::max((n + m + 1) / 2, t + r);
+                long double acc = 0.0L;
+                for (int j = q; j <= n; ++j) {
+                    long double a = (((n - j) & 1) ? -1.0L : 1.0L) * f(2 * j) * c /
+                                    (std::pow(2.0L, n) * f(j) * f(n - j) * f(2 * j - n - m));
+                    acc += ((t & 1) ? -1.0L : 1.0L) * a * f(j - r) / (f(t) * f(j - r - t));
+                }
+                b[(size_t)(n * (n + 1) / 2 + m) * BT + t] = (double)acc;
+            }
+        }
+}
+
+// G(n,m;nu,mu;q) = int Y_n^m conj(Y_nu^mu) conj(Y_q^{m-mu}) = (-1)^m gaunt(n,m; nu,-mu; q,mu-m)
+void make_gtab(int p, std::vector<double>& g)
+{
+    const int K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2, NQ = 2 * p + 1;
+    g.assign((size_t)Kp * K * NQ, 0.0);
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu)
+                    for (int q = std::abs(n - nu); q <= n + nu; q += 2) {
+                        if (std::abs(m - mu) > q) continue;
+                        double v = ((m & 1) ? -1.0 : 1.0) * host_gaunt(n, m, nu, -mu, q, mu - m);
+                        g[((size_t)(n * (n + 1) / 2 + m) * K + (nu * nu + nu + mu)) * NQ + q] = v;
+                    }
+}
+
+lpb_status build_and_upload(lpb_ctx* c);
+
+lpb_status check_layers(lpb_ctx* c, int nl, const double* eps, const double* lam, const double* d, Medium& M)
+{
+    if (nl < 1 || nl > LPB_MAX_LAYERS || nl - 1 > LPB_MAXL) return fail(c, LPB_EINVAL, "n_layers out of range");
+    if (!eps || !lam || (nl > 1 && !d)) return fail(c, LPB_EINVAL, "null layer array");
+    M = Medium{};
+    M.L = nl - 1;
+    for (int k = 0; k < nl; ++k) {
+        if (!std::isfinite(eps[k]) || !std::isfinite(lam[k])) return fail(c, LPB_ENUMERIC, "non-finite eps/lambda");
+        if (eps[k] <= 0.0 || lam[k] <= 0.0) return fail(c, LPB_EINVAL, "eps and lambda must be > 0");
+        M.eps[k] = eps[k];
+        M.lam[k] = lam[k];
+    }
+    for (int k = 0; k + 1 < nl; ++k) {
+        if (!std::isfinite(d[k])) return fail(c, LPB_ENUMERIC, "non-finite interface");
+        if (k > 0 && !(d[k] < d[k - 1])) return fail(c, LPB_EINVAL, "interfaces must be strictly decreasing");
+        M.d[k] = d[k];
+    }
+    return LPB_OK;
+}
+
+lpb_status read_coords(lpb_ctx* c, int64_t n, const double* x, const double* y, const double* z, int on_device,
+                       std::vector<double>& X, std::vector<double>& Y, std::vector<double>& Z)
+{
+    if (n < 0) return fail(c, LPB_EINVAL, "negative n");
+    if (n > 0 && (!x || !y || !z)) return fail(c, LPB_EINVAL, "null coordinate array");
+    X.resize(n);
+    Y.resize(n);
+    Z.resize(n);
+    if (n == 0) return LPB_OK;
+    if (on_device) {
+        HIPCHK(c, hipMemcpy(X.data(), x, n * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(Y.data(), y, n * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(c, hipMemcpy(Z.data(), z, n * sizeof(double), hipMemcpyDeviceToHost));
+    } else {
+        std::memcpy(X.data(), x, n * sizeof(double));
+        std::memcpy(Y.data(), y, n * sizeof(double));
+        std::memcpy(Z.data(), z, n * sizeof(double));
+    }
+    return LPB_OK;
+}
+
+template <typename F, typename V>
+lpb_status up_field(lpb_ctx* c, const F*& field, const std::vector<V>& vec)
+{
+    V* tmp = nullptr;
+    lpb_status s = upload(c, c->plan_bufs, vec, &tmp);
+    field = tmp;
+    return s;
+}
+
+template <typename T>
+lpb_status upload_points(lpb_ctx* c, const std::vector<double>& u3, int n, const T** x, const T** y, const T** z)
+{
+    std::vector<T> a(n), b(n), d(n);
+    for (int i = 0; i < n; ++i) {
+        a[i] = (T)u3[i];
+        b[i] = (T)u3[(size_t)n + i];
+        d[i] = (T)u3[2 * (size_t)n + i];
+    }
+    T *px, *py, *pz;
+    lpb_status s;
+    if ((s = upload(c, c->plan_bufs, a, &px)) != LPB_OK) return s;
+    if ((s = upload(c, c->plan_bufs, b, &py)) != LPB_OK) return s;
+    if ((s = upload(c, c->plan_bufs, d, &pz)) != LPB_OK) return s;
+    *x = px;
+    *y = py;
+    *z = pz;
+    return LPB_OK;
+}
+
+template <typename T>
+lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
+{
+    Plan& P = c->plan;
+    lpb_status s;
+    A = EvalArgs<T>{};
+    A.p = P.p;
+    A.K = P.K;
+    A.nslots = P.nslots;
+    A.ncharges = P.ncharges;
+    A.n_src = (int)P.s_cidx.size();
+    A.quad_tol = c->opt.quad_tol;
+    // FMM records
+    std::vector<FmmDev> fd(P.fmm.size());
+    for (size_t i = 0; i < P.fmm.size(); ++i) {
+        const FmmDesc& F = P.fmm[i];
+        FmmDev& D = fd[i];
+        D.kind = F.kind; D.H = F.H; D.flip = F.flip; D.medium = F.sys;
+        D.l = F.l; D.lp = F.lp; D.a = F.a; D.b = F.b;
+        D.R = F.R; D.lam_s = F.lam_s; D.lam_t = F.lam_t; D.far_factor = F.far_factor; D.eps_t = F.eps_t;
+        for (int l = 0; l <= kMaxDepth; ++l) { D.me_off[l] = F.me_off[l]; D.le_off[l] = F.le_off[l]; }
+    }
+    FmmDev* dfmm;
+    Medium* dmed;
+    if ((s = upload(c, c->plan_bufs, fd, &dfmm)) != LPB_OK) return s;
+    if ((s = upload(c, c->plan_bufs, P.media, &dmed)) != LPB_OK) return s;
+    A.fmm = dfmm;
+    A.media = dmed;
+#define UP(field, vec)                                                     \
+    if ((s = up_field(c, A.field, vec)) != LPB_OK) return s;
+    UP(s_cidx, P.s_cidx);
+    UP(sl_start, P.sl_start);
+    UP(sl_me, P.sl_me);
+    UP(sl_fmm, P.sl_fmm);
+    UP(sl_h, P.sl_h);
+    UP(sl_ctr, P.sl_ctr);
+    UP(t_cidx, P.t_cidx);
+    UP(t_out, P.t_out);
+    UP(tl_start, P.tl_start);
+    UP(tl_le, P.tl_le);
+    UP(tl_fmm, P.tl_fmm);
+    UP(tl_h, P.tl_h);
+    UP(tl_ctr, P.tl_ctr);
+    UP(m2m_parent, P.m2m_parent);
+    UP(m2m_ptr, P.m2m_ptr);
+    UP(m2m_child, P.m2m_child);
+    UP(m2m_op, P.m2m_op);
+    UP(l2l_child, P.l2l_child);
+    UP(l2l_parent, P.l2l_parent);
+    UP(l2l_op, P.l2l_op);
+    UP(m2l_ptr, P.m2l_ptr);
+    UP(m2l_src, P.m2l_src);
+    UP(m2l_op, P.m2l_op);
+    UP(p2p_ptr, P.p2p_ptr);
+    UP(p2p_src, P.p2p_src);
+    // work lists
+    std::vector<int> p2m, l2p, pfree, rleaf, rslot, m2lb;
+    for (size_t i = 0; i < P.sl_me.size(); ++i)
+        if (P.sl_me[i] >= 0) p2m.push_back((int)i);
+    for (size_t i = 0; i < P.tl_le.size(); ++i) {
+        if (P.tl_le[i] >= 0) l2p.push_back((int)i);
+        bool has_u = P.p2p_ptr[i + 1] > P.p2p_ptr[i];
+        if (!has_u) continue;
+        if (P.fmm[P.tl_fmm[i]].kind == 0) pfree.push_back((int)i);
+        else
+            for (int j = P.tl_start[i]; j < P.tl_start[i + 1]; ++j) {
+                rleaf.push_back((int)i);
+                rslot.push_back(j);
+            }
+    }
+    for (int i = 0; i < P.n_le; ++i)
+        if (P.m2l_ptr[i + 1] > P.m2l_ptr[i]) m2lb.push_back(i);
+    UP(p2m_leaves, p2m);
+    UP(l2p_leaves, l2p);
+    UP(p2p_free_leaves, pfree);
+    UP(react_tgt_leaf, rleaf);
+    UP(react_tgt_slot, rslot);
+    UP(m2l_boxes, m2lb);
+#undef UP
+    A.n_react_targets = (int)rleaf.size();
+    c->sched.n_p2m = (int)p2m.size();
+    c->sched.n_l2p = (int)l2p.size();
+    c->sched.n_p2p_free = (int)pfree.size();
+    c->sched.n_m2l_boxes = (int)m2lb.size();
+    for (int l = 0; l <= kMaxDepth + 1; ++l) {
+        c->sched.m2m_level_ptr[l] = P.m2m_level_ptr[l];
+        c->sched.l2l_level_ptr[l] = P.l2l_level_ptr[l];
+    }
+    if ((s = upload_points<T>(c, P.s_u, (int)P.s_cidx.size(), &A.s_ux, &A.s_uy, &A.s_uz)) != LPB_OK) return s;
+    if ((s = upload_points<T>(c, P.t_u, (int)P.t_cidx.size(), &A.t_ux, &A.t_uy, &A.t_uz)) != LPB_OK) return s;
+    T* qs;
+    if ((s = dalloc<T>(c, c->plan_bufs, P.s_cidx.size(), &qs)) != LPB_OK) return s;
+    A.qs = qs;
+    T *me, *le;
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_me * P.K, &me)) != LPB_OK) return s;
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_le * P.K, &le)) != LPB_OK) return s;
+    A.me = me;
+    A.le = le;
+    A.n_le = P.n_le;
+    double* parts;
+    if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.nslots * P.ncharges, &parts)) != LPB_OK) return s;
+    A.parts = parts;
+    if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.ncharges, &c->d_q)) != LPB_OK) return s;
+    if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.ncharges, &c->d_phi)) != LPB_OK) return s;
+    A.q = c->d_q;
+    A.phi = c->d_phi;
+    A.gl_x = (const double*)c->d_glx.ptr;
+    A.gl_w = (const double*)c->d_glw.ptr;
+    return LPB_OK;
+}
+
+lpb_status build_and_upload(lpb_ctx* c)
+{
+    auto t0 = std::chrono::steady_clock::now();
+    free_bufs(c->plan_bufs);
+    free_bufs(c->op_bufs);
+    c->ops_dirty = true;
+    c->have_tree = false;
+    Plan& P = c->plan;
+    P.p = c->opt.p;
+    P.K = (P.p + 1) * (P.p + 1);
+    P.leaf_cap = c->opt.leaf_cap;
+    int st = 0;
+    std::string msg = build_plan(P, c->media, c->xs, c->ys, c->zs, c->opt.iface_tol, &st);
+    if (st != LPB_OK) return fail(c, (lpb_status)st, msg);
+    lpb_status s = (c->opt.precision == LPB_MIXED) ? fill_args<float>(c, c->a32) : fill_args<double>(c, c->a64);
+    if (s != LPB_OK) return s;
+    c->have_tree = true;
+    c->stats.n_fmm = (int)P.fmm.size();
+    c->stats.max_depth = P.max_depth;
+    c->stats.n_m2l_pairs = P.n_m2l_pairs;
+    c->stats.n_p2p_pairs = P.n_p2p_pairs;
+    c->stats.n_react_p2p_pairs = P.n_react_p2p_pairs;
+    c->stats.n_operators = (int64_t)P.ops.size();
+    c->stats.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return LPB_OK;
+}
+
+lpb_status generate_operators(lpb_ctx* c)
+{
+    Plan& P = c->plan;
+    free_bufs(c->op_bufs);
+    const int K = P.K, Kp = (P.p + 1) * (P.p + 2) / 2;
+    lpb_status s;
+    std::vector<int> freel, reactl, rfl, rfidx(P.fmm.size(), -1);
+    for (size_t i = 0; i < P.ops.size(); ++i) (P.ops[i].type == OP_M2L_REACT ? reactl : freel).push_back((int)i);
+    for (size_t i = 0; i < P.fmm.size(); ++i)
+        if (P.fmm[i].kind == 1) {
+            rfidx[i] = (int)rfl.size();
+            rfl.push_back((int)i);
+        }
+    OpgenInputs& g = c->og;
+    g = OpgenInputs{};
+    g.p = P.p;
+    g.n_ops = (int)P.ops.size();
+    g.n_rkeys = (int)P.rkeys.size();
+    g.n_rf = (int)rfl.size();
+    g.n_free = (int)freel.size();
+    g.n_react = (int)reactl.size();
+    g.quad_tol = c->opt.quad_tol;
+    OpDesc* dops;
+    RKey* drk;
+    int *dfl, *drl, *drf, *drfi;
+    if ((s = upload(c, c->op_bufs, P.ops, &dops)) != LPB_OK) return s;
+    if ((s = upload(c, c->op_bufs, P.rkeys, &drk)) != LPB_OK) return s;
+    if ((s = upload(c, c->op_bufs, freel, &dfl)) != LPB_OK) return s;
+    if ((s = upload(c, c->op_bufs, reactl, &drl)) != LPB_OK) return s;
+    if ((s = upload(c, c->op_bufs, rfl, &drf)) != LPB_OK) return s;
+    if ((s = upload(c, c->op_bufs, rfidx, &drfi)) != LPB_OK) return s;
+    g.d_ops = dops; g.d_rkeys = drk; g.d_free_list = dfl; g.d_react_list = drl; g.d_rf_list = drf; g.d_rf_index = drfi;
+    g.d_fmm = (c->opt.precision == LPB_MIXED) ? c->a32.fmm : c->a64.fmm;
+    g.d_media = (c->opt.precision == LPB_MIXED) ? c->a32.media : c->a64.media;
+    g.d_btab = (const double*)c->d_btab.ptr;
+    g.d_gtab = (const double*)c->d_gtab.ptr;
+    const int N1 = 2 * P.p + 4;
+    if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_rf * Kp * K * (P.p + 2), &g.d_dtab)) != LPB_OK) return s;
+    if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_rkeys * 4 * N1 * N1, &g.d_stab)) != LPB_OK) return s;
+    if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_ops * K * K, &g.d_pool)) != LPB_OK) return s;
+    if (g.n_rkeys > 0) HIPCHK(c, hipMemsetAsync(g.d_stab, 0, sizeof(double) * (size_t)g.n_rkeys * 4 * N1 * N1, c->stream));
+    g.d_pool32 = nullptr;
+    if (c->opt.precision == LPB_MIXED)
+        if ((s = dalloc<float>(c, c->op_bufs, (size_t)g.n_ops * K * K, &g.d_pool32)) != LPB_OK) return s;
+    g.d_flag = (int*)c->d_flag.ptr;
+    HIPCHK(c, hipMemsetAsync(g.d_flag, 0, sizeof(int), c->stream));
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, opgen_run(g, c->stream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    int flag = 0;
+    HIPCHK(c, hipMemcpyAsync(&flag, g.d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.t_opgen_ms = ms;
+    if (flag & 1) return fail(c, LPB_ENUMERIC, "Sommerfeld quadrature panel budget exceeded");
+    if (flag & 2) return fail(c, LPB_ENUMERIC, "forward recurrence stability bound violated");
+    if (c->opt.precision == LPB_MIXED) {
+        c->a32.pool = g.d_pool32;
+        // the FP64 pool is no longer needed
+        for (auto& b : c->op_bufs)
+            if (b.ptr == (void*)g.d_pool) {
+                (void)hipFree(b.ptr);
+                b.ptr = nullptr;
+            }
+        c->stats.operator_bytes = (int64_t)g.n_ops * K * K * (int64_t)sizeof(float);
+    } else {
+        c->a64.pool = g.d_pool;
+        c->stats.operator_bytes = (int64_t)g.n_ops * K * K * (int64_t)sizeof(double);
+    }
+    c->ops_dirty = false;
+    return LPB_OK;
+}
+
+lpb_status run_eval(lpb_ctx* c)
+{
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    hipError_t e = (c->opt.precision == LPB_MIXED) ? eval_run<float>(c->a32, c->sched, c->opt.stages, c->stream)
+                                                   : eval_run<double>(c->a64, c->sched, c->opt.stages, c->stream);
+    if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    return LPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lpb_default_options(lpb_options* opt)
+{
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    opt->p = 10;
+    opt->leaf_cap = 50;
+    opt->precision = LPB_FP64;
+    opt->quad_tol = 1e-16;
+    opt->iface_tol = 1e-9;
+    opt->device = 0;
+    opt->stream = nullptr;
+    opt->stages = 3;
+}
+
+lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
+{
+    if (!out) return fail(nullptr, LPB_EINVAL, "out is NULL");
+    *out = nullptr;
+    lpb_options o;
+    lpb_default_options(&o);
+    if (opt) o = *opt;
+    if (o.p < 1 || o.p > LPB_MAX_P) return fail(nullptr, LPB_ERANGE, "p out of range");
+    if (o.leaf_cap < 1) return fail(nullptr, LPB_ERANGE, "leaf_cap must be >= 1");
+    if (o.precision != LPB_FP64 && o.precision != LPB_MIXED) return fail(nullptr, LPB_EINVAL, "bad precision");
+    if (!(o.quad_tol > 0.0 && o.quad_tol < 1e-3)) return fail(nullptr, LPB_EINVAL, "quad_tol out of range");
+    if (!(o.iface_tol >= 0.0)) return fail(nullptr, LPB_EINVAL, "iface_tol must be >= 0");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(nullptr, LPB_EDEVICE, "no HIP device available");
+    if (o.device < 0 || o.device >= ndev) return fail(nullptr, LPB_EINVAL, "device ordinal out of range");
+    std::unique_ptr<lpb_ctx> c(new lpb_ctx());
+    c->opt = o;
+    c->stream = (hipStream_t)o.stream;
+    e = hipSetDevice(o.device);
+    if (e != hipSuccess) return fail(nullptr, LPB_EDEVICE, hipGetErrorString(e));
+    if (opgen_upload_constants() != hipSuccess) return fail(nullptr, LPB_EDEVICE, "constant upload failed");
+    make_btab(o.p, c->btab);
+    make_gtab(o.p, c->gtab);
+    auto up = [&](const std::vector<double>& v, DevBuf& b) -> bool {
+        b.bytes = v.size() * sizeof(double);
+        if (hipMalloc(&b.ptr, std::max<size_t>(b.bytes, 8)) != hipSuccess) return false;
+        return hipMemcpy(b.ptr, v.data(), b.bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    double glx[20], glw[20];
+    gauss_legendre20(glx, glw);
+    if (!up(c->btab, c->d_btab) || !up(c->gtab, c->d_gtab) || !up(std::vector<double>(glx, glx + 20), c->d_glx) ||
+        !up(std::vector<double>(glw, glw + 20), c->d_glw))
+        return fail(nullptr, LPB_ENOMEM, "table upload failed");
+    if (hipMalloc(&c->d_flag.ptr, 64) != hipSuccess) return fail(nullptr, LPB_ENOMEM, "flag alloc failed");
+    if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
+        return fail(nullptr, LPB_EDEVICE, "event create failed");
+    *out = c.release();
+    return LPB_OK;
+}
+
+lpb_status lpb_set_layers(lpb_ctx* c, int n_layers, const double* eps, const double* lambda, const double* interfaces)
+{
+    if (!c) return LPB_EINVAL;
+    if (c->batched) return fail(c, LPB_ESTATE, "context is batched; use lpb_set_systems");
+    Medium M;
+    lpb_status s = check_layers(c, n_layers, eps, lambda, interfaces, M);
+    if (s != LPB_OK) return s;
+    HIPCHK(c, hipSetDevice(c->opt.device));
+    c->media.assign(1, M);
+    c->have_layers = true;
+    c->ops_dirty = true;
+    if (c->xs.size() == 1) return build_and_upload(c);
+    return LPB_OK;
+}
+
+lpb_status lpb_build_tree(lpb_ctx* c, int64_t n, const double* x, const double* y, const double* z, int on_device)
+{
+    if (!c) return LPB_EINVAL;
+    if (c->batched) return fail(c, LPB_ESTATE, "context is batched; use lpb_build_trees");
+    if (!c->have_layers) return fail(c, LPB_ESTATE, "lpb_set_layers must come first");
+    HIPCHK(c, hipSetDevice(c->opt.device));
+    std::vector<double> X, Y, Z;
+    lpb_status s = read_coords(c, n, x, y, z, on_device, X, Y, Z);
+    if (s != LPB_OK) return s;
+    c->xs.assign(1, std::move(X));
+    c->ys.assign(1, std::move(Y));
+    c->zs.assign(1, std::move(Z));
+    s = build_and_upload(c);
+    if (s != LPB_OK) {
+        c->xs.clear(); c->ys.clear(); c->zs.clear();
+    }
+    return s;
+}
+
+static lpb_status evaluate_common(lpb_ctx* c, int nsys, const double* const* q, double* const* phi, int on_device)
+{
+    HIPCHK(c, hipSetDevice(c->opt.device));
+    Plan& P = c->plan;
+    for (int s = 0; s < nsys; ++s) {
+        int64_t n = P.sys_charge_off[s + 1] - P.sys_charge_off[s];
+        if (n > 0 && (!q[s] || !phi[s])) return fail(c, LPB_EINVAL, "null q or phi");
+    }
+    if (c->ops_dirty) {
+        lpb_status st = generate_operators(c);
+        if (st != LPB_OK) return st;
+    }
+    for (int s = 0; s < nsys; ++s) {
+        int64_t n = P.sys_charge_off[s + 1] - P.sys_charge_off[s];
+        if (n == 0) continue;
+        HIPCHK(c, hipMemcpyAsync(c->d_q + P.sys_charge_off[s], q[s], n * sizeof(double),
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, c->stream));
+    }
+    lpb_status st = run_eval(c);
+    if (st != LPB_OK) return st;
+    for (int s = 0; s < nsys; ++s) {
+        int64_t n = P.sys_charge_off[s + 1] - P.sys_charge_off[s];
+        if (n == 0) continue;
+        HIPCHK(c, hipMemcpyAsync(phi[s], c->d_phi + P.sys_charge_off[s], n * sizeof(double),
+                                 on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.t_eval_ms = ms;
+    return LPB_OK;
+}
+
+lpb_status lpb_evaluate(lpb_ctx* c, const double* q, double* phi, int on_device)
+{
+    if (!c) return LPB_EINVAL;
+    if (c->batched) return fail(c, LPB_ESTATE, "context is batched; use lpb_evaluate_batch");
+    if (!c->have_layers || !c->have_tree) return fail(c, LPB_ESTATE, "set_layers and build_tree must come first");
+    if (q && phi && (const void*)q == (const void*)phi) return fail(c, LPB_EINVAL, "phi aliases q");
+    return evaluate_common(c, 1, &q, &phi, on_device);
+}
+
+lpb_status lpb_set_systems(lpb_ctx* c, int n_sys, const int* n_layers, const double* const* eps,
+                           const double* const* lambda, const double* const* interfaces)
+{
+    if (!c) return LPB_EINVAL;
+    if (n_sys < 1 || !n_layers || !eps || !lambda || !interfaces) return fail(c, LPB_EINVAL, "bad system arrays");
+    std::vector<Medium> ms(n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+        lpb_status st = check_layers(c, n_layers[s], eps[s], lambda[s], interfaces[s], ms[s]);
+        if (st != LPB_OK) return st;
+    }
+    HIPCHK(c, hipSetDevice(c->opt.device));
+    c->batched = true;
+    c->media = ms;
+    c->have_layers = true;
+    c->ops_dirty = true;
+    if ((int)c->xs.size() == n_sys) return build_and_upload(c);
+    c->xs.clear(); c->ys.clear(); c->zs.clear();
+    c->have_tree = false;
+    return LPB_OK;
+}
+
+lpb_status lpb_build_trees(lpb_ctx* c, int n_sys, const int64_t* n, const double* const* x, const double* const* y,
+                           const double* const* z, int on_device)
+{
+    if (!c) return LPB_EINVAL;
+    if (!c->batched || !c->have_layers) return fail(c, LPB_ESTATE, "lpb_set_systems must come first");
+    if (n_sys != (int)c->media.size() || !n || !x || !y || !z) return fail(c, LPB_EINVAL, "bad system arrays");
+    HIPCHK(c, hipSetDevice(c->opt.device));
+    std::vector<std::vector<double>> X(n_sys), Y(n_sys), Z(n_sys);
+    for (int s = 0; s < n_sys; ++s) {
+        lpb_status st = read_coords(c, n[s], x[s], y[s], z[s], on_device, X[s], Y[s], Z[s]);
+        if (st != LPB_OK) return st;
+    }
+    c->xs = std::move(X);
+    c->ys = std::move(Y);
+    c->zs = std::move(Z);
+    lpb_status st = build_and_upload(c);
+    if (st != LPB_OK) { c->xs.clear(); c->ys.clear(); c->zs.clear(); }
+    return st;
+}
+
+lpb_status lpb_evaluate_batch(lpb_ctx* c, int n_sys, const double* const* q, double* const* phi, int on_device)
+{
+    if (!c) return LPB_EINVAL;
+    if (!c->batched || !c->have_tree) return fail(c, LPB_ESTATE, "lpb_set_systems and lpb_build_trees must come first");
+    if (n_sys != c->plan.nsys || !q || !phi) return fail(c, LPB_EINVAL, "bad system arrays");
+    return evaluate_common(c, n_sys, q, phi, on_device);
+}
+
+lpb_status lpb_get_stats(const lpb_ctx* c, lpb_stats* stats)
+{
+    if (!c || !stats) return LPB_EINVAL;
+    *stats = c->stats;
+    return LPB_OK;
+}
+
+lpb_status lpb_fmm_info(const lpb_ctx* c, int sys, int fmm, int* desc, double* root, int64_t* nt, int64_t* ns,
+                        uint64_t* tkeys, uint64_t* skeys)
+{
+    if (!c) return LPB_EINVAL;
+    const Plan& P = c->plan;
+    if (!c->have_tree || sys < 0 || sys >= P.nsys) return LPB_EINVAL;
+    // FMMs of this system in plan order
+    int k = -1, found = -1;
+    for (size_t i = 0; i < P.fmm.size(); ++i)
+        if (P.fmm[i].sys == sys && ++k == fmm) {
+            found = (int)i;
+            break;
+        }
+    if (found < 0) return LPB_EINVAL;
+    const FmmDesc& F = P.fmm[found];
+    if (desc) {
+        desc[0] = F.kind; desc[1] = F.l; desc[2] = F.lp; desc[3] = F.a; desc[4] = F.b; desc[5] = F.H;
+    }
+    if (root) { root[0] = F.cx; root[1] = F.cy; root[2] = F.cz; root[3] = F.R; }
+    if (nt) *nt = F.ntgt;
+    if (ns) *ns = F.nsrc;
+    // point ranges of this FMM: leaves are contiguous per FMM
+    auto gather = [&](const std::vector<int>& lfmm, const std::vector<int>& lstart, const std::vector<int>& cidx,
+                      const std::vector<uint64_t>& okey, uint64_t* out) {
+        std::vector<std::pair<int, uint64_t>> v;
+        for (size_t l = 0; l < lfmm.size(); ++l)
+            if (lfmm[l] == found)
+                for (int j = lstart[l]; j < lstart[l + 1]; ++j) v.push_back({cidx[j], okey[j]});
+        std::sort(v.begin(), v.end());
+        for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].second;
+    };
+    if (tkeys) gather(P.tl_fmm, P.tl_start, P.t_cidx, P.t_okey, tkeys);
+    if (skeys) gather(P.sl_fmm, P.sl_start, P.s_cidx, P.s_okey, skeys);
+    return LPB_OK;
+}
+
+lpb_status lpb_debug_parts(const lpb_ctx* c, double* out, int* nslots)
+{
+    if (!c || !nslots) return LPB_EINVAL;
+    *nslots = c->plan.nslots;
+    if (!out || !c->have_tree) return LPB_OK;
+    const double* parts = (c->opt.precision == LPB_MIXED) ? c->a32.parts : c->a64.parts;
+    size_t n = (size_t)c->plan.nslots * c->plan.ncharges;
+    if (n && hipMemcpy(out, parts, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return LPB_EDEVICE;
+    return LPB_OK;
+}
+
+const char* lpb_last_error(const lpb_ctx* c)
+{
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+void lpb_destroy(lpb_ctx* c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->opt.device);
+    (void)hipDeviceSynchronize();
+    free_bufs(c->plan_bufs);
+    free_bufs(c->op_bufs);
+    for (DevBuf* b : {&c->d_btab, &c->d_gtab, &c->d_glx, &c->d_glw, &c->d_flag})
+        if (b->ptr) (void)hipFree(b->ptr);
+    if (c->ev0) (void)hipEventDestroy(c->ev0);
+    if (c->ev1) (void)hipEventDestroy(c->ev1);
+    delete c;
+}
+
+double lpb_host_gaunt(int n1, int m1, int n2, int m2, int n3, int m3)
+{
+    if (n1 < 0 || n2 < 0 || n3 < 0 || std::abs(m1) > n1 || std::abs(m2) > n2 || std::abs(m3) > n3) return 0.0;
+    return host_gaunt(n1, m1, n2, m2, n3, m3);
+}
+
+}  // extern "C"

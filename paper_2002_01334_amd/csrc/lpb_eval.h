@@ -1,0 +1,54 @@
+// lpb_eval.h -- argument block of the evaluation kernels.
+#pragma once
+#include "lpb_internal.h"
+
+namespace lpb {
+
+template <typename T>
+struct EvalArgs {
+    int p, K, nslots;
+    int64_t ncharges;
+    const FmmDev* fmm;
+    const Medium* media;
+    // sources (sorted by FMM, leaf)
+    int n_src;
+    const int* s_cidx;
+    const T *s_ux, *s_uy, *s_uz;
+    T* qs;
+    const double* q;
+    const int *sl_start, *sl_me, *sl_fmm;
+    const double *sl_h, *sl_ctr;
+    // targets
+    const T *t_ux, *t_uy, *t_uz;
+    const int *t_cidx, *t_out;
+    const int *tl_start, *tl_le, *tl_fmm;
+    const double *tl_h, *tl_ctr;
+    // expansions and operators
+    T* me;
+    T* le;
+    int n_le;
+    const T* pool;
+    // work lists
+    const int *p2m_leaves, *l2p_leaves, *p2p_free_leaves;
+    const int *m2m_parent, *m2m_ptr, *m2m_child, *m2m_op;
+    const int *l2l_child, *l2l_parent, *l2l_op;
+    const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;
+    const int *p2p_ptr, *p2p_src;
+    int n_react_targets;
+    const int *react_tgt_leaf, *react_tgt_slot;
+    const double *gl_x, *gl_w;
+    double quad_tol;
+    double* parts;
+    double* phi;
+};
+
+struct EvalSched {
+    int n_p2m, n_l2p, n_p2p_free, n_m2l_boxes;
+    int m2m_level_ptr[kMaxDepth + 2];
+    int l2l_level_ptr[kMaxDepth + 2];
+};
+
+template <typename T>
+hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st);
+
+}  // namespace lpb

@@ -1,0 +1,134 @@
+// lpb_internal.h -- plan (trees, lists, operator descriptors) shared by the
+// host plan builder, the operator generator and the evaluation kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/lpb.h"
+#include "lpb_math.h"
+
+namespace lpb {
+
+constexpr int kMaxDepth = 12;   // deepest tree level
+constexpr int kCellBits = 16;   // fine cell bits per axis
+
+enum OpType { OP_M2M = 0, OP_L2L = 1, OP_M2L_FREE = 2, OP_M2L_REACT = 3 };
+
+// One FMM of the plan: a free-space Yukawa FMM of layer l (kind 0) or the
+// reaction component (l, lp, a, b) over equivalent polarization sources
+// (kind 1).  All geometry below is in the FMM's canonical frame: origin at
+// the root centre, z flipped (flip = -1) for a = 2 so that targets always lie
+// above the interface (canonical z > 0) and images below.
+struct FmmDesc {
+    int sys, kind, l, lp, a, b;
+    double cx, cy, cz, R;     // root centre (original frame) and half side
+    int flip;                 // +1 or -1
+    int H;                    // depth
+    double lam_s, lam_t;      // source-side and target-side lambda
+    double far_factor;        // multiplies the far field (free space: lam/(2 pi^2 eps))
+    double eps_t;             // eps of the target layer (free-space near field)
+    int slot;                 // output slot of this FMM's targets
+    int me_off[kMaxDepth + 1], me_cnt[kMaxDepth + 1];   // ME boxes of each level (global index range)
+    int le_off[kMaxDepth + 1], le_cnt[kMaxDepth + 1];
+    int nsrc, ntgt;
+    int layers_id;            // which layered medium (system) for sigma
+};
+
+// Device-resident description of one medium for the reaction densities.
+struct Medium {
+    int L;
+    double eps[LPB_MAXL + 1];
+    double lam[LPB_MAXL + 1];
+    double d[LPB_MAXL];
+};
+
+// Per-FMM record used by the kernels (device).
+struct FmmDev {
+    int kind;
+    int H;
+    int flip;
+    int medium;
+    int l, lp, a, b;
+    double R;
+    double lam_s, lam_t;
+    double far_factor, eps_t;
+    int me_off[kMaxDepth + 1];
+    int le_off[kMaxDepth + 1];
+};
+
+// Operator descriptor (generation input).
+struct OpDesc {
+    int type;        // OpType
+    int fmm;
+    int level;       // level of the box the operator writes (M2M: parent level; L2L, M2L: target level)
+    int rkey;        // reaction geometry key (OP_M2L_REACT) or -1
+    double bx, by, bz;  // free ops: translation vector b of the addition theorem (canonical frame)
+    double phi;      // reaction: azimuth of (target centre - source centre)
+};
+
+// Reaction geometry key: phi-independent part of a reaction M2L operator.
+struct RKey {
+    int fmm, level;
+    double rho, zt, zs;   // canonical: zt > 0 (target centre height), zs < 0 (source centre)
+    double S;             // box side (scaling length of the paper's scaled integrals)
+};
+
+// Host-side plan (built by build_plan, uploaded by the context).
+struct Plan {
+    int p = 10, K = 121, leaf_cap = 50;
+    int nsys = 0;
+    std::vector<int64_t> sys_charge_off;   // nsys + 1
+    std::vector<Medium> media;             // per system
+    std::vector<FmmDesc> fmm;
+    int nslots = 1;                        // output slots per charge
+    int64_t ncharges = 0;
+    int max_depth = 0;
+    // points (sources and targets sorted by FMM, then leaf)
+    std::vector<int> s_cidx, t_cidx;       // global charge index
+    std::vector<double> s_u, t_u;          // 3 x n, relative to the leaf centre (canonical frame), SoA
+    std::vector<int> t_out;                // index into parts: slot * ncharges + cidx
+    // leaves
+    std::vector<int> sl_start, sl_me, sl_fmm, sl_level;   // source leaves (sl_start has n+1)
+    std::vector<int> tl_start, tl_le, tl_fmm;             // target leaves
+    std::vector<double> sl_h, tl_h;                       // leaf box side
+    std::vector<double> sl_ctr, tl_ctr;                   // leaf centres (canonical local frame), 3 per leaf
+    std::vector<uint64_t> s_okey, t_okey;                 // leaf Morton key of each point, original frame (diagnostics)
+    // boxes
+    int n_me = 0, n_le = 0;
+    std::vector<int> me_fmm, me_level, le_fmm, le_level;
+    // M2M: CSR by parent ME box (levels >= 2), children ME + operator
+    std::vector<int> m2m_parent, m2m_ptr, m2m_child, m2m_op;
+    std::vector<int> m2m_level_ptr;   // parents of level l at [m2m_level_ptr[l], m2m_level_ptr[l+1])
+    // L2L: child LE box -> parent LE box + operator, grouped by level
+    std::vector<int> l2l_child, l2l_parent, l2l_op;
+    std::vector<int> l2l_level_ptr;
+    // M2L: CSR by target LE box
+    std::vector<int> m2l_ptr, m2l_src, m2l_op;   // m2l_ptr has n_le+1
+    // near field: CSR by target leaf over source leaves
+    std::vector<int> p2p_ptr, p2p_src;
+    int64_t n_p2p_pairs = 0, n_react_p2p_pairs = 0, n_m2l_pairs = 0;
+    // operators
+    std::vector<OpDesc> ops;
+    std::vector<RKey> rkeys;
+};
+
+// Build the plan for all systems (host).  Returns an error message or "".
+std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vector<std::vector<double>>& xs,
+                       const std::vector<std::vector<double>>& ys, const std::vector<std::vector<double>>& zs,
+                       double iface_tol, int* status);
+
+// Layer of height z: number of interfaces above z.
+inline int layer_of(const Medium& m, double z)
+{
+    int l = 0;
+    for (int k = 0; k < m.L; ++k)
+        if (m.d[k] > z) l = k + 1;
+    return l;
+}
+
+double host_gaunt(int n1, int m1, int n2, int m2, int n3, int m3);
+
+}  // namespace lpb

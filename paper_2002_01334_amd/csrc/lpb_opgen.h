@@ -1,0 +1,34 @@
+// lpb_opgen.h -- host interface of the FP64 operator generator.
+#pragma once
+#include "lpb_internal.h"
+
+namespace lpb {
+
+struct OpgenInputs {
+    int p;
+    int n_ops, n_rkeys, n_rf;
+    const OpDesc* d_ops;
+    const RKey* d_rkeys;
+    const FmmDev* d_fmm;
+    const Medium* d_media;
+    const int* d_free_list;
+    int n_free;
+    const int* d_react_list;
+    int n_react;
+    const int* d_rf_list;     // reaction FMM ids (n_rf)
+    const int* d_rf_index;    // fmm id -> position in rf_list (-1 for free space)
+    const double* d_btab;     // b^t_{nm} of the Legendre-product expansion
+    const double* d_gtab;     // Gaunt integrals G(n,m;nu,mu;q)
+    double* d_dtab;           // D_s table per reaction FMM (output)
+    double* d_stab;           // scaled Sommerfeld integral tables per geometry key (output)
+    double* d_pool;           // FP64 operators (output)
+    float* d_pool32;          // FP32 copy (output, may be null)
+    int* d_flag;              // bit 0: quadrature budget exceeded, bit 1: recurrence bound violated
+    double quad_tol;
+};
+
+hipError_t opgen_upload_constants();
+hipError_t opgen_run(const OpgenInputs& in, hipStream_t st);
+void gauss_legendre20(double* x, double* w);
+
+}  // namespace lpb
