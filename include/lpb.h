@@ -71,6 +71,7 @@ typedef struct {
     int device;             /* HIP device ordinal; default 0 */
     void* stream;           /* hipStream_t for all work; NULL = null stream */
     int stages;             /* diagnostics: bit 0 far field (P2M..L2P), bit 1 near field; default 3 (both) */
+    int timing;             /* 1 = record stream events between stages (lpb_stats.t_stage_ms); default 0 */
 } lpb_options;
 
 typedef struct {
@@ -84,6 +85,10 @@ typedef struct {
     double t_build_ms;      /* last lpb_build_tree (host tree + upload) */
     double t_opgen_ms;      /* last operator generation (GPU, FP64) */
     double t_eval_ms;       /* last lpb_evaluate, stream time between its first and last kernel */
+    /* per-stage stream time of the last evaluate when options.timing = 1:
+     * [0] charge gather + clears, [1] P2M, [2] M2M, [3] M2L, [4] L2L, [5] L2P,
+     * [6] free-space near field, [7] reaction near field, [8] component sum */
+    double t_stage_ms[9];
 } lpb_stats;
 
 /* Fill *opt with the defaults listed above.  Never fails. */

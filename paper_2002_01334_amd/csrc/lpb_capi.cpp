@@ -53,6 +53,7 @@ struct lpb_ctx {
     OpgenInputs og{};
     lpb_stats stats{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
+    hipEvent_t evs[10] = {};
 };
 
 namespace {
@@ -437,8 +438,9 @@ lpb_status generate_operators(lpb_ctx* c)
 lpb_status run_eval(lpb_ctx* c)
 {
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    hipError_t e = (c->opt.precision == LPB_MIXED) ? eval_run<float>(c->a32, c->sched, c->opt.stages, c->stream)
-                                                   : eval_run<double>(c->a64, c->sched, c->opt.stages, c->stream);
+    hipEvent_t* ev = c->opt.timing ? c->evs : nullptr;
+    hipError_t e = (c->opt.precision == LPB_MIXED) ? eval_run<float>(c->a32, c->sched, c->opt.stages, c->stream, ev)
+                                                   : eval_run<double>(c->a64, c->sched, c->opt.stages, c->stream, ev);
     if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     return LPB_OK;
@@ -460,6 +462,7 @@ void lpb_default_options(lpb_options* opt)
     opt->device = 0;
     opt->stream = nullptr;
     opt->stages = 3;
+    opt->timing = 0;
 }
 
 lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
@@ -499,6 +502,8 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (hipMalloc(&c->d_flag.ptr, 64) != hipSuccess) return fail(nullptr, LPB_ENOMEM, "flag alloc failed");
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
         return fail(nullptr, LPB_EDEVICE, "event create failed");
+    for (auto& e : c->evs)
+        if (hipEventCreate(&e) != hipSuccess) return fail(nullptr, LPB_EDEVICE, "event create failed");
     *out = c.release();
     return LPB_OK;
 }
@@ -567,6 +572,12 @@ static lpb_status evaluate_common(lpb_ctx* c, int nsys, const double* const* q, 
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.t_eval_ms = ms;
+    if (c->opt.timing)
+        for (int k = 0; k < 9; ++k) {
+            float t = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&t, c->evs[k], c->evs[k + 1]));
+            c->stats.t_stage_ms[k] = t;
+        }
     return LPB_OK;
 }
 
@@ -699,6 +710,8 @@ void lpb_destroy(lpb_ctx* c)
         if (b->ptr) (void)hipFree(b->ptr);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
+    for (auto& e : c->evs)
+        if (e) (void)hipEventDestroy(e);
     delete c;
 }
 

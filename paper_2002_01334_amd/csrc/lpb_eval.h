@@ -49,6 +49,6 @@ struct EvalSched {
 };
 
 template <typename T>
-hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st);
+hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev);
 
 }  // namespace lpb

@@ -39,7 +39,7 @@ __device__ inline void bessel_ratio(int p, double lam, double r2, const double* 
 // One 64-lane block per source leaf; lanes own points, the per-point
 // coefficient rows are staged in LDS and summed per coefficient.
 template <typename T>
-__global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A)
+__global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 {
     extern __shared__ unsigned char smem_raw[];
     const int p = A.p, K = A.K;
@@ -47,9 +47,10 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A)
     const int me = A.sl_me[leaf];
     const FmmDev& F = A.fmm[A.sl_fmm[leaf]];
     const double h = A.sl_h[leaf];
-    T* coef = reinterpret_cast<T*>(smem_raw);                 // [K][65] (padded rows)
-    T* rre = coef + (size_t)K * 65;                            // [Kp][64]
-    T* rim = rre + (size_t)((p + 1) * (p + 2) / 2) * 64;
+    const int CS = CH + 1;                                     // padded row stride
+    T* coef = reinterpret_cast<T*>(smem_raw);                  // [K][CH+1]
+    T* rre = coef + (size_t)K * CS;                            // [Kp][CH]
+    T* rim = rre + (size_t)((p + 1) * (p + 2) / 2) * CH;
     __shared__ double inv_ith[LPB_MAX_P + 1];
     const int lane = threadIdx.x;
     if (lane == 0) {
@@ -63,33 +64,31 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A)
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = T(0);
     const T hinv = (T)(1.0 / h);
-    for (int base = s0; base < s1; base += 64) {
+    for (int base = s0; base < s1; base += CH) {
         int j = base + lane;
-        if (j < s1) {
+        if (lane < CH && j < s1) {
             T ux = A.s_ux[j], uy = A.s_uy[j], uz = A.s_uz[j], q = A.qs[j];
             double r2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
             double g[LPB_MAX_P + 2];
             bessel_ratio(p, F.lam_s, r2, inv_ith, g);
             // solid harmonics R_n^m(u/h) into per-lane LDS columns
-            solid_harmonics_lds<T>(p, ux * hinv, uy * hinv, uz * hinv, rre + lane, rim + lane, 64);
+            solid_harmonics_lds<T>(p, ux * hinv, uy * hinv, uz * hinv, rre + lane, rim + lane, CH);
             for (int n = 0; n <= p; ++n) {
                 T gq = (T)g[n] * q;
                 for (int m = 0; m <= n; ++m) {
-                    coef[(size_t)ire(n, m) * 65 + lane] = gq * rre[(size_t)ipk(n, m) * 64 + lane];
-                    if (m > 0) coef[(size_t)iim(n, m) * 65 + lane] = -gq * rim[(size_t)ipk(n, m) * 64 + lane];
+                    coef[(size_t)ire(n, m) * CS + lane] = gq * rre[(size_t)ipk(n, m) * CH + lane];
+                    if (m > 0) coef[(size_t)iim(n, m) * CS + lane] = -gq * rim[(size_t)ipk(n, m) * CH + lane];
                 }
             }
-        } else {
-            for (int k = 0; k < K; ++k) coef[(size_t)k * 65 + lane] = T(0);
         }
         __syncthreads();
-        int cnt = min(64, s1 - base);
+        int cnt = min(CH, s1 - base);
 #pragma unroll
         for (int kk = 0; kk < 8; ++kk) {
             int k = lane + 64 * kk;
             if (k < K) {
                 T s = T(0);
-                for (int jj = 0; jj < cnt; ++jj) s += coef[(size_t)k * 65 + jj];
+                for (int jj = 0; jj < cnt; ++jj) s += coef[(size_t)k * CS + jj];
                 acc[kk] += s;
             }
         }
@@ -167,7 +166,7 @@ __global__ void k_l2l(EvalArgs<T> A, int cbeg)
 // L2P (eqs. freespace3dlocexp, lelayerimage), scaled:
 //   Phi = far_factor * sum_n g_n(r) [Lh_n0 R_n^0 + 2 sum_{m>0} Re(Lh_nm R_n^m)](u/h)
 template <typename T>
-__global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A)
+__global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
 {
     extern __shared__ unsigned char smem_raw[];
     const int p = A.p, K = A.K;
@@ -176,8 +175,8 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A)
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double h = A.tl_h[leaf];
     T* Ls = reinterpret_cast<T*>(smem_raw);                       // [K]
-    T* rre = Ls + K;                                              // [Kp][64]
-    T* rim = rre + (size_t)((p + 1) * (p + 2) / 2) * 64;
+    T* rre = Ls + K;                                              // [Kp][CH]
+    T* rim = rre + (size_t)((p + 1) * (p + 2) / 2) * CH;
     __shared__ double inv_ith[LPB_MAX_P + 1];
     const int lane = threadIdx.x;
     if (lane == 0) {
@@ -189,18 +188,19 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A)
     __syncthreads();
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const T hinv = (T)(1.0 / h);
-    for (int j = t0 + lane; j < t1; j += 64) {
+    if (lane >= CH) return;
+    for (int j = t0 + lane; j < t1; j += CH) {
         T ux = A.t_ux[j], uy = A.t_uy[j], uz = A.t_uz[j];
         double r2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         double g[LPB_MAX_P + 2];
         bessel_ratio(p, F.lam_t, r2, inv_ith, g);
-        solid_harmonics_lds<T>(p, ux * hinv, uy * hinv, uz * hinv, rre + lane, rim + lane, 64);
+        solid_harmonics_lds<T>(p, ux * hinv, uy * hinv, uz * hinv, rre + lane, rim + lane, CH);
         T phi = T(0);
         for (int n = 0; n <= p; ++n) {
-            T s = Ls[ire(n, 0)] * rre[(size_t)ipk(n, 0) * 64 + lane];
+            T s = Ls[ire(n, 0)] * rre[(size_t)ipk(n, 0) * CH + lane];
             T s2 = T(0);
             for (int m = 1; m <= n; ++m)
-                s2 += Ls[ire(n, m)] * rre[(size_t)ipk(n, m) * 64 + lane] - Ls[iim(n, m)] * rim[(size_t)ipk(n, m) * 64 + lane];
+                s2 += Ls[ire(n, m)] * rre[(size_t)ipk(n, m) * CH + lane] - Ls[iim(n, m)] * rim[(size_t)ipk(n, m) * CH + lane];
             phi += (T)g[n] * (s + T(2) * s2);
         }
         A.parts[A.t_out[j]] = (double)phi * F.far_factor;
@@ -341,43 +341,65 @@ __global__ void k_sum(int64_t n, int nslots, const double* __restrict__ parts, d
 
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st)
+hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev)
 {
+#define LPB_MARK(k) \
+    if (ev) (void)hipEventRecord(ev[k], st)
     const int K = A.K, p = A.p;
     const int Kp = (p + 1) * (p + 2) / 2;
     const int bsz = ((K + 63) / 64) * 64;
+    LPB_MARK(0);
     if (A.n_src > 0) hipLaunchKernelGGL(k_gather_q<T>, dim3((A.n_src + 255) / 256), dim3(256), 0, st, A.n_src, A.s_cidx, A.q, A.qs);
     hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, st, (size_t)A.nslots * A.ncharges, A.parts);
     if (A.n_le > 0) hipLaunchKernelGGL(k_zero<T>, dim3(1024), dim3(256), 0, st, (size_t)A.n_le * K, A.le);
     const bool far = stages & 1, near = stages & 2;
+    LPB_MARK(1);
     // upward pass
+    // point chunks sized so that a block's LDS stays under 40 KB (several blocks per CU)
+    auto pick_ch = [&](size_t per_ch, size_t fixed) {
+        int ch = 64;
+        while (ch > 8 && fixed + per_ch * ch > 40u * 1024u) ch >>= 1;
+        return ch;
+    };
     if (far && S.n_p2m > 0) {
-        size_t sm = sizeof(T) * (size_t)K * 65 + 2 * sizeof(T) * (size_t)Kp * 64;
-        hipLaunchKernelGGL(k_p2m<T>, dim3(S.n_p2m), dim3(64), sm, st, A);
+        int ch = pick_ch(sizeof(T) * ((size_t)K + 2 * Kp), sizeof(T) * (size_t)K);
+        size_t sm = sizeof(T) * ((size_t)K * (ch + 1) + 2 * (size_t)Kp * ch);
+        hipLaunchKernelGGL(k_p2m<T>, dim3(S.n_p2m), dim3(64), sm, st, A, ch);
     }
+    LPB_MARK(2);
     for (int l = kMaxDepth; l >= 0; --l) {
         int b = S.m2m_level_ptr[l], e = S.m2m_level_ptr[l + 1];
         if (far && e > b) hipLaunchKernelGGL(k_m2m<T>, dim3(e - b), dim3(bsz), sizeof(T) * K, st, A, b);
     }
     // V-list translations (all levels), then the downward pass
+    LPB_MARK(3);
     if (far && S.n_m2l_boxes > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(S.n_m2l_boxes), dim3(bsz), sizeof(T) * K, st, A);
+    LPB_MARK(4);
     for (int l = 0; l <= kMaxDepth; ++l) {
         int b = S.l2l_level_ptr[l], e = S.l2l_level_ptr[l + 1];
         if (far && e > b) hipLaunchKernelGGL(k_l2l<T>, dim3(e - b), dim3(bsz), sizeof(T) * K, st, A, b);
     }
+    LPB_MARK(5);
     if (far && S.n_l2p > 0) {
-        size_t sm = sizeof(T) * (size_t)K + 2 * sizeof(T) * (size_t)Kp * 64;
-        hipLaunchKernelGGL(k_l2p<T>, dim3(S.n_l2p), dim3(64), sm, st, A);
+        int ch = pick_ch(2 * sizeof(T) * (size_t)Kp, sizeof(T) * (size_t)K);
+        size_t sm = sizeof(T) * ((size_t)K + 2 * (size_t)Kp * ch);
+        hipLaunchKernelGGL(k_l2p<T>, dim3(S.n_l2p), dim3(64), sm, st, A, ch);
     }
     // near field
+    LPB_MARK(6);
     if (near && S.n_p2p_free > 0) hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, st, A);
+    LPB_MARK(7);
     if (near && A.n_react_targets > 0)
         hipLaunchKernelGGL(k_p2p_react<T>, dim3((A.n_react_targets + 63) / 64), dim3(64), 0, st, A);
-    hipLaunchKernelGGL(k_sum, dim3((unsigned)((A.ncharges + 255) / 256)), dim3(256), 0, st, A.ncharges, A.nslots, A.parts, A.phi);
+    LPB_MARK(8);
+    if (A.ncharges > 0)
+        hipLaunchKernelGGL(k_sum, dim3((unsigned)((A.ncharges + 255) / 256)), dim3(256), 0, st, A.ncharges, A.nslots, A.parts, A.phi);
+    LPB_MARK(9);
+#undef LPB_MARK
     return hipGetLastError();
 }
 
-template hipError_t eval_run<double>(const EvalArgs<double>&, const EvalSched&, int, hipStream_t);
-template hipError_t eval_run<float>(const EvalArgs<float>&, const EvalSched&, int, hipStream_t);
+template hipError_t eval_run<double>(const EvalArgs<double>&, const EvalSched&, int, hipStream_t, hipEvent_t*);
+template hipError_t eval_run<float>(const EvalArgs<float>&, const EvalSched&, int, hipStream_t, hipEvent_t*);
 
 }  // namespace lpb

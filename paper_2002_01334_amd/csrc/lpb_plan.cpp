@@ -46,13 +46,28 @@ uint64_t morton(uint32_t ix, uint32_t iy, uint32_t iz, int l)
     return k;
 }
 
+// spread the low 16 bits of v to every third bit
+inline uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0xffffu;
+    x = (x | (x << 16)) & 0x0000ff0000ffull;
+    x = (x | (x << 8)) & 0x00f00f00f00full;
+    x = (x | (x << 4)) & 0x0c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x249249249249ull;
+    return x;
+}
+
+// Morton key of a fine cell (16 levels): same bit order as morton(.., 16)
+inline uint64_t morton_fine(uint32_t ix, uint32_t iy, uint32_t iz) { return (spread3(ix) << 2) | (spread3(iy) << 1) | spread3(iz); }
+
 inline uint64_t cellkey(int ix, int iy, int iz)
 {
     return ((uint64_t)(uint32_t)ix << 42) | ((uint64_t)(uint32_t)iy << 21) | (uint64_t)(uint32_t)iz;
 }
 
 struct Pt {
-    uint32_t c[3];   // fine cells, original frame
+    uint64_t fkey;   // Morton key of the fine cell (canonical frame)
+    uint32_t c[3];   // fine cells (canonical frame)
     double x, y, z;  // original frame (z = image z for reaction sources)
     int cidx;        // global charge index
     int local;       // index within the system
@@ -229,17 +244,24 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                     q.c[2] = fine_cell(q.z, F.cz, F.R);
                     if (F.flip < 0) q.c[2] = 65535u - q.c[2];   // canonical frame: mirror z
                 }
+            // fine Morton keys; one sort per point set, then every level is a prefix
+            for (auto* V : {&T, &S})
+                for (auto& q : *V) q.fkey = morton_fine(q.c[0], q.c[1], q.c[2]);
+            auto byfine = [](const Pt& A, const Pt& B) { return A.fkey != B.fkey ? A.fkey < B.fkey : A.cidx < B.cidx; };
+            std::sort(T.begin(), T.end(), byfine);
+            std::sort(S.begin(), S.end(), byfine);
+            auto count_level = [](const std::vector<Pt>& V, int lv) {
+                int sh = 3 * (kCellBits - lv);
+                int64_t n = V.empty() ? 0 : 1;
+                for (size_t i = 1; i < V.size(); ++i)
+                    if ((V[i].fkey >> sh) != (V[i - 1].fkey >> sh)) ++n;
+                return n;
+            };
             // depth
             int H = kMaxDepth;
             for (int lv = 0; lv <= kMaxDepth; ++lv) {
-                auto count = [&](const std::vector<Pt>& V) {
-                    std::vector<uint64_t> k(V.size());
-                    int sh = kCellBits - lv;
-                    for (size_t i = 0; i < V.size(); ++i) k[i] = morton(V[i].c[0] >> sh, V[i].c[1] >> sh, V[i].c[2] >> sh, lv);
-                    std::sort(k.begin(), k.end());
-                    return (int64_t)(std::unique(k.begin(), k.end()) - k.begin());
-                };
-                if ((int64_t)S.size() <= (int64_t)cap * count(S) && (int64_t)T.size() <= (int64_t)cap * count(T)) {
+                if ((int64_t)S.size() <= (int64_t)cap * count_level(S, lv) &&
+                    (int64_t)T.size() <= (int64_t)cap * count_level(T, lv)) {
                     H = lv;
                     break;
                 }
@@ -249,35 +271,21 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
             const int fid = (int)P.fmm.size();
             F.nsrc = (int)S.size();
             F.ntgt = (int)T.size();
-            // sort points by leaf key then charge index
             int shH = kCellBits - H;
-            auto leafkey = [&](const Pt& q) { return morton(q.c[0] >> shH, q.c[1] >> shH, q.c[2] >> shH, H); };
-            auto byleaf = [&](const Pt& A, const Pt& B) {
-                uint64_t ka = leafkey(A), kb = leafkey(B);
-                return ka != kb ? ka < kb : A.cidx < B.cidx;
-            };
-            std::sort(T.begin(), T.end(), byleaf);
-            std::sort(S.begin(), S.end(), byleaf);
-            // boxes per level
+            // boxes per level, in Morton order (prefixes of the sorted fine keys)
             std::vector<BoxSet> SB(H + 1), TB(H + 1);
             auto make_boxes = [&](const std::vector<Pt>& V, std::vector<BoxSet>& B) {
                 for (int lv = 0; lv <= H; ++lv) {
                     int sh = kCellBits - lv;
-                    std::vector<std::pair<uint64_t, uint64_t>> kk(V.size());
-                    for (size_t i = 0; i < V.size(); ++i) {
-                        uint32_t a = V[i].c[0] >> sh, b = V[i].c[1] >> sh, c = V[i].c[2] >> sh;
-                        kk[i] = {morton(a, b, c, lv), cellkey(a, b, c)};
-                    }
-                    std::sort(kk.begin(), kk.end());
-                    kk.erase(std::unique(kk.begin(), kk.end()), kk.end());
                     BoxSet& bs = B[lv];
-                    for (auto& e : kk) {
-                        int ix = (int)(e.second >> 42), iy = (int)((e.second >> 21) & 0x1fffff), iz = (int)(e.second & 0x1fffff);
-                        bs.idx[e.second] = (int)bs.mkey.size();
-                        bs.mkey.push_back(e.first);
-                        bs.ix.push_back(ix);
-                        bs.iy.push_back(iy);
-                        bs.iz.push_back(iz);
+                    for (size_t i = 0; i < V.size(); ++i) {
+                        if (i > 0 && (V[i].fkey >> (3 * sh)) == (V[i - 1].fkey >> (3 * sh))) continue;
+                        uint32_t a = V[i].c[0] >> sh, b = V[i].c[1] >> sh, c = V[i].c[2] >> sh;
+                        bs.idx[cellkey(a, b, c)] = (int)bs.mkey.size();
+                        bs.mkey.push_back(V[i].fkey >> (3 * sh));
+                        bs.ix.push_back((int)a);
+                        bs.iy.push_back((int)b);
+                        bs.iz.push_back((int)c);
                     }
                 }
             };

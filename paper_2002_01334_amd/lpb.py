@@ -27,16 +27,20 @@ _PD = ctypes.POINTER(ctypes.c_double)
 
 class Options(ctypes.Structure):
     _fields_ = [("p", _I), ("leaf_cap", _I), ("precision", _I), ("quad_tol", _D), ("iface_tol", _D),
-                ("device", _I), ("stream", _P), ("stages", _I)]
+                ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_fmm", _I), ("max_depth", _I), ("n_m2l_pairs", _L), ("n_p2p_pairs", _L),
                 ("n_react_p2p_pairs", _L), ("n_operators", _L), ("operator_bytes", _L),
-                ("t_build_ms", _D), ("t_opgen_ms", _D), ("t_eval_ms", _D)]
+                ("t_build_ms", _D), ("t_opgen_ms", _D), ("t_eval_ms", _D), ("t_stage_ms", _D * 9)]
+
+    STAGES = ["setup", "p2m", "m2m", "m2l", "l2l", "l2p", "p2p_free", "p2p_react", "sum"]
 
     def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "t_stage_ms"}
+        d["t_stage_ms"] = dict(zip(self.STAGES, list(self.t_stage_ms)))
+        return d
 
 
 EXPORTS = ["lpb_default_options", "lpb_create", "lpb_set_layers", "lpb_build_tree", "lpb_evaluate",
@@ -113,7 +117,7 @@ class Context:
     """One lpb context (one GPU, one stream)."""
 
     def __init__(self, p=10, leaf_cap=50, precision=LPB_FP64, quad_tol=1e-16, iface_tol=1e-9, device=0,
-                 stream=None, stages=3):
+                 stream=None, stages=3, timing=0):
         L = load()
         opt = Options()
         L.lpb_default_options(ctypes.byref(opt))
@@ -125,6 +129,7 @@ class Context:
         opt.device = device
         opt.stream = stream
         opt.stages = stages
+        opt.timing = timing
         h = _P()
         rc = L.lpb_create(ctypes.byref(opt), ctypes.byref(h))
         if rc != LPB_OK:

@@ -1,0 +1,272 @@
+"""GPU parity tests: the HIP path through the C ABI against the CPU oracle.
+
+Bars (derived in the design doc): FP64 GPU vs oracle FMM on the same tree, relative
+l2 error per layer and per component <= 1e-10; tree structure bit-exact;
+GPU FP64 vs oracle direct sum within the truncation error of p; mixed
+precision vs FP64 <= 1e-6; batched vs single-system FP64 bit-identical.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2002_01334_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lpb():
+    import torch
+
+    assert torch.cuda.is_available(), "GPU tests need an MI355X"
+    from paper_2002_01334_amd import lpb as m
+
+    m.load()
+    return m
+
+
+def err2(a, b, layer, nl=3):
+    out = []
+    for l in range(nl):
+        m = layer == l
+        if m.sum() == 0:
+            continue
+        nb = np.linalg.norm(b[m])
+        out.append(np.linalg.norm(a[m] - b[m]) / nb if nb > 0 else np.linalg.norm(a[m]))
+    return max(out)
+
+
+def slot_map(nl):
+    m, ctr = {}, [1] * nl
+    for c in range(O.num_components(nl)):
+        kind, l, lp, a, b = O.component(nl, c)
+        if kind == 0:
+            m[c] = (l, 0)
+        else:
+            m[c] = (l, ctr[l])
+            ctr[l] += 1
+    return m
+
+
+def run(lpb, prob, p, leaf_cap, precision=0, device=False):
+    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision)
+    ctx.set_layers(prob.eps, prob.lam, prob.d)
+    if device:
+        import torch
+
+        t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device="cuda:0") for k in "xyzq"}
+        ctx.build_tree(t["x"], t["y"], t["z"])
+        phi = ctx.evaluate(t["q"]).cpu().numpy()
+    else:
+        ctx.build_tree(prob.x, prob.y, prob.z)
+        phi = ctx.evaluate(prob.q)
+    return ctx, phi
+
+
+@pytest.fixture(scope="module")
+def c1():
+    prob = inputs.three_layer(200, seed=0)
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    return prob, ly, O.direct_sum(ly, prob.x, prob.y, prob.z, prob.q)
+
+
+@pytest.mark.parametrize("leaf_cap", [8, 50])
+def test_tree_matches_oracle(lpb, c1, leaf_cap):
+    prob, ly, _ = c1
+    ctx, _ = run(lpb, prob, 2, leaf_cap)
+    for c in range(O.num_components(3)):
+        info = ctx.fmm_info(c, keys=True)
+        d, tk, sk, root = O.component_tree(ly, prob.x, prob.y, prob.z, c, leaf_cap=leaf_cap)
+        kind, l, lp, a, b = O.component(3, c)
+        assert (info["kind"], info["l"], info["lp"], info["a"], info["b"]) == (kind, l, lp, a, b)
+        assert info["depth"] == d
+        assert np.array_equal(info["root"], root)
+        assert np.array_equal(info["tkeys"], tk) and np.array_equal(info["skeys"], sk)
+    ctx.close()
+
+
+@pytest.mark.parametrize("p,leaf_cap", [(4, 8), (10, 8), (10, 50), (6, 3)])
+def test_fp64_matches_oracle_fmm_per_component(lpb, c1, p, leaf_cap):
+    prob, ly, _ = c1
+    ctx, phi = run(lpb, prob, p, leaf_cap)
+    parts = ctx.debug_parts()
+    st = ctx.stats()
+    ctx.close()
+    ref, cphi, ost = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=leaf_cap, components=True)
+    assert err2(phi, ref, prob.layer) <= 1e-10
+    sm = slot_map(3)
+    for c in range(cphi.shape[0]):
+        l, s = sm[c]
+        m = prob.layer == l
+        assert np.linalg.norm(parts[s][m] - cphi[c][m]) <= 1e-10 * np.linalg.norm(cphi[c][m]), c
+    assert st["n_m2l_pairs"] == int(ost[:, 3].sum())
+    # the library's count includes the n excluded self pairs of the free-space near field
+    assert st["n_p2p_pairs"] == int(ost[:, 4].sum()) + prob.n
+
+
+def test_fp64_converges_to_direct_sum(lpb, c1):
+    prob, ly, direct = c1
+    errs = []
+    for p in (3, 6, 10):
+        ctx, phi = run(lpb, prob, p, 8)
+        ctx.close()
+        errs.append(err2(phi, direct, prob.layer))
+    assert errs[0] < 1e-2 and errs[1] < errs[0] / 10 and errs[2] < errs[1] / 10 and errs[2] < 1e-5, errs
+
+
+def test_mixed_matches_fp64(lpb, c1):
+    prob, _, _ = c1
+    ctx, phi64 = run(lpb, prob, 10, 8)
+    ctx.close()
+    ctx, phi32 = run(lpb, prob, 10, 8, precision=lpb.LPB_MIXED)
+    ctx.close()
+    assert err2(phi32, phi64, prob.layer) <= 1e-6
+
+
+def test_device_pointers_and_repeat_are_bitwise_identical(lpb, c1):
+    prob, _, _ = c1
+    ctx, a = run(lpb, prob, 8, 8)
+    b = ctx.evaluate(prob.q)
+    ctx.close()
+    ctx, c = run(lpb, prob, 8, 8, device=True)
+    ctx.close()
+    assert np.array_equal(a, b) and np.array_equal(a, c)
+
+
+def test_c2_fp64_matches_oracle_fmm_and_sampled_direct_sum(lpb):
+    # 1e4 charges per layer, p = 10, leaf cap 50: several tiles per level and ragged leaves
+    prob = inputs.three_layer(10_000, seed=0)
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    ctx, phi = run(lpb, prob, 10, 50)
+    ctx.close()
+    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 10, leaf_cap=50)
+    assert err2(phi, ref, prob.layer) <= 1e-10
+    idx = inputs.sample_targets(prob, 30, seed=1)
+    direct = O.direct_sum(ly, prob.x, prob.y, prob.z, prob.q, targets=idx)
+    assert err2(phi[idx], direct, prob.layer[idx]) <= 2e-5
+    ctx, phi32 = run(lpb, prob, 10, 50, precision=lpb.LPB_MIXED)
+    ctx.close()
+    assert err2(phi32, phi, prob.layer) <= 1e-6
+
+
+def test_batch_matches_single_systems_bitwise(lpb):
+    probs = [inputs.three_layer(n, seed=s) for n, s in ((150, 3), (90, 4), (220, 5))]
+    probs[1].eps = np.array([2.0, 30.0, 5.0])
+    probs[1].lam = np.array([0.7, 2.5, 1.1])
+    probs[2].d = np.array([0.05, -1.15])
+    singles = []
+    for pr in probs:
+        ctx, phi = run(lpb, pr, 7, 8)
+        ctx.close()
+        singles.append(phi)
+    ctx = lpb.Context(p=7, leaf_cap=8)
+    ctx.set_systems([p.eps for p in probs], [p.lam for p in probs], [p.d for p in probs])
+    ctx.build_trees([p.x for p in probs], [p.y for p in probs], [p.z for p in probs])
+    outs = ctx.evaluate_batch([p.q for p in probs])
+    ctx.close()
+    for a, b in zip(outs, singles):
+        assert np.array_equal(a, b)
+
+
+def test_edge_cases(lpb):
+    # one layer (free space only) against a numpy direct sum
+    rng = np.random.default_rng(0)
+    x, y, z = rng.uniform(-1, 1, (3, 300))
+    q = rng.uniform(-1, 1, 300)
+    ctx = lpb.Context(p=10, leaf_cap=8)
+    ctx.set_layers([2.0], [0.8], [])
+    ctx.build_tree(x, y, z)
+    phi = ctx.evaluate(q)
+    P = np.stack([x, y, z], 1)
+    R = np.linalg.norm(P[:, None] - P[None], axis=2)
+    np.fill_diagonal(R, np.inf)
+    ref = (np.exp(-0.8 * R) / (4 * np.pi * 2.0 * R)) @ q
+    e_direct = float(np.linalg.norm(phi - ref) / np.linalg.norm(ref))
+    assert e_direct < 1e-5
+    ofmm = O.fmm(O.Layers([2.0], [0.8], []), x, y, z, q, 10, leaf_cap=8)
+    e_fmm = float(np.linalg.norm(phi - ofmm) / np.linalg.norm(ofmm))
+    assert e_fmm <= 1e-10
+    # empty input
+    ctx.build_tree(np.zeros(0), np.zeros(0), np.zeros(0))
+    assert ctx.evaluate(np.zeros(0)).shape == (0,)
+    ctx.close()
+    # ragged: empty middle layer, a single charge in the bottom layer
+    prob = inputs.three_layer((120, 0, 1), seed=9)
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    ctx, phi = run(lpb, prob, 6, 8)
+    ctx.close()
+    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 6, leaf_cap=8)
+    assert np.linalg.norm(phi - ref) <= 1e-10 * np.linalg.norm(ref)
+    # error paths: charge on an interface, NaN, call order, bad layers
+    ctx = lpb.Context(p=4)
+    with pytest.raises(lpb.LpbError) as e:
+        ctx.evaluate(np.zeros(3))
+    assert e.value.status == lpb.LPB_ESTATE
+    with pytest.raises(lpb.LpbError) as e:
+        ctx.set_layers([1.0, 2.0], [1.0, -1.0], [0.0])
+    assert e.value.status == lpb.LPB_EINVAL
+    with pytest.raises(lpb.LpbError) as e:
+        ctx.set_layers([1.0, 2.0, 3.0], [1.0, 1.0, 1.0], [0.0, 0.5])
+    assert e.value.status == lpb.LPB_EINVAL
+    ctx.set_layers([1.0, 2.0], [1.0, 1.5], [0.0])
+    with pytest.raises(lpb.LpbError) as e:
+        ctx.build_tree(np.array([0.1, 0.2]), np.array([0.0, 0.1]), np.array([0.3, 0.0]))
+    assert e.value.status == lpb.LPB_ERANGE
+    with pytest.raises(lpb.LpbError) as e:
+        ctx.build_tree(np.array([0.1, np.nan]), np.array([0.0, 0.1]), np.array([0.3, -0.2]))
+    assert e.value.status == lpb.LPB_ENUMERIC
+    ctx.close()
+
+
+@pytest.mark.parametrize("p", [1, 15])
+def test_extreme_orders(lpb, c1, p):
+    prob, ly, _ = c1
+    ctx, phi = run(lpb, prob, p, 8)
+    ctx.close()
+    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=8)
+    assert err2(phi, ref, prob.layer) <= 1e-10
+
+
+def test_full_size_homogeneous_and_free_part(lpb):
+    """3e6 charges (the benchmark's workload and launch configuration): with
+    identical layers the layered potential must equal the free-space sum over
+    all charges (every reaction component contributes), checked at sampled
+    targets against a direct free-space sum; with the benchmark medium the
+    free-space slot must match a direct free-space sum over the layer."""
+    import torch
+
+    prob = inputs.three_layer(1_000_000, seed=0)
+    idx = inputs.sample_targets(prob, 10, seed=1)
+    P = np.stack([prob.x, prob.y, prob.z], 1)
+
+    def free_sum(lam, eps, targets, same_layer_only):
+        out = np.zeros(len(targets))
+        for k, i in enumerate(targets):
+            m = (prob.layer == prob.layer[i]) if same_layer_only else slice(None)
+            d = np.linalg.norm(P[m] - P[i], axis=1)
+            qq = prob.q[m]
+            keep = d > 0
+            out[k] = np.sum(qq[keep] * np.exp(-lam * d[keep]) / (4 * np.pi * eps * d[keep]))
+        return out
+
+    hom = inputs.three_layer(1_000_000, seed=0, eps=(2.0, 2.0, 2.0), lam=(1.5, 1.5, 1.5))
+    ref_h = free_sum(1.5, 2.0, idx, False)
+    t = {k: torch.tensor(getattr(hom, k), dtype=torch.float64, device="cuda:0") for k in "xyzq"}
+    for prec, tol in ((lpb.LPB_FP64, 2e-5), (lpb.LPB_MIXED, 2e-5)):
+        ctx = lpb.Context(p=10, leaf_cap=50, precision=prec)
+        ctx.set_layers(hom.eps, hom.lam, hom.d)
+        ctx.build_tree(t["x"], t["y"], t["z"])
+        phi = ctx.evaluate(t["q"]).cpu().numpy()
+        ctx.close()
+        assert err2(phi[idx], ref_h, prob.layer[idx]) <= tol
+    # benchmark medium: free-space component (slot 0) at the sampled targets
+    ctx = lpb.Context(p=10, leaf_cap=50, precision=lpb.LPB_MIXED)
+    ctx.set_layers(prob.eps, prob.lam, prob.d)
+    ctx.build_tree(prob.x, prob.y, prob.z)
+    ctx.evaluate(prob.q)
+    free = ctx.debug_parts()[0][idx]
+    ctx.close()
+    for k, i in enumerate(idx[:6]):
+        l = prob.layer[i]
+        ref = free_sum(prob.lam[l], prob.eps[l], [i], True)[0]
+        assert abs(free[k] - ref) <= 1e-4 * abs(ref)
