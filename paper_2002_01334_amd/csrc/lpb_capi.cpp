@@ -231,6 +231,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     A = EvalArgs<T>{};
     A.p = P.p;
     A.K = P.K;
+    A.KP = (P.K + 15) / 16 * 16;
     A.nslots = P.nslots;
     A.ncharges = P.ncharges;
     A.n_src = (int)P.s_cidx.size();
@@ -278,6 +279,32 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(m2l_op, P.m2l_op);
     UP(p2p_ptr, P.p2p_ptr);
     UP(p2p_src, P.p2p_src);
+    UP(tiles, P.tiles);
+    UP(tfl, P.tfl);
+    UP(grid_me, P.grid_me);
+    UP(grid_le, P.grid_le);
+    UP(optab, P.optab);
+    UP(oct_codes, P.oct_codes);
+    UP(swz_index, P.swz_index);
+    {
+        // solid-harmonic recurrence tables (see lpb_math.h)
+        std::vector<T> amm(P.p + 1), al((P.p + 1) * (P.p + 2) / 2, T(0)), be((P.p + 1) * (P.p + 2) / 2, T(0));
+        double a = 0.28209479177387814;
+        for (int m = 0; m <= P.p; ++m) {
+            if (m > 0) a *= std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+            amm[m] = (T)a;
+            if (m + 1 <= P.p) al[ipk(m + 1, m)] = (T)std::sqrt(2.0 * m + 3.0);
+            for (int n = m + 2; n <= P.p; ++n) {
+                double nn = (double)n * n, mm = (double)m * m;
+                al[ipk(n, m)] = (T)std::sqrt((4.0 * nn - 1.0) / (nn - mm));
+                be[ipk(n, m)] = (T)std::sqrt(((n - 1.0) * (n - 1.0) - mm) * (2.0 * n + 1.0) / ((nn - mm) * (2.0 * n - 3.0)));
+            }
+        }
+        UP(sh_amm, amm);
+        UP(sh_alpha, al);
+        UP(sh_beta, be);
+    }
+    A.n_tiles = (int)P.tiles.size();
     // work lists
     std::vector<int> p2m, l2p, pfree, rleaf, rslot, m2lb;
     for (size_t i = 0; i < P.sl_me.size(); ++i)
@@ -317,8 +344,10 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     if ((s = dalloc<T>(c, c->plan_bufs, P.s_cidx.size(), &qs)) != LPB_OK) return s;
     A.qs = qs;
     T *me, *le;
-    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_me * P.K, &me)) != LPB_OK) return s;
-    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_le * P.K, &le)) != LPB_OK) return s;
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_me * A.KP, &me)) != LPB_OK) return s;
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_le * A.KP, &le)) != LPB_OK) return s;
+    // the padding rows k >= K of the expansions are read by the tiled M2L and must stay zero
+    HIPCHK(c, hipMemset(me, 0, sizeof(T) * std::max<size_t>((size_t)P.n_me * A.KP, 1)));
     A.me = me;
     A.le = le;
     A.n_le = P.n_le;
@@ -406,6 +435,18 @@ lpb_status generate_operators(lpb_ctx* c)
     if (c->opt.precision == LPB_MIXED)
         if ((s = dalloc<float>(c, c->op_bufs, (size_t)g.n_ops * K * K, &g.d_pool32)) != LPB_OK) return s;
     g.d_flag = (int*)c->d_flag.ptr;
+    g.KP = (K + 15) / 16 * 16;
+    g.n_swz = (int)P.swz_ops.size();
+    int* dswz;
+    if ((s = upload(c, c->op_bufs, P.swz_ops, &dswz)) != LPB_OK) return s;
+    g.d_swz_ops = dswz;
+    g.d_swz64 = nullptr;
+    g.d_swz32 = nullptr;
+    if (c->opt.precision == LPB_MIXED) {
+        if ((s = dalloc<float>(c, c->op_bufs, (size_t)g.n_swz * g.KP * g.KP, &g.d_swz32)) != LPB_OK) return s;
+    } else {
+        if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_swz * g.KP * g.KP, &g.d_swz64)) != LPB_OK) return s;
+    }
     HIPCHK(c, hipMemsetAsync(g.d_flag, 0, sizeof(int), c->stream));
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, opgen_run(g, c->stream));
@@ -420,6 +461,7 @@ lpb_status generate_operators(lpb_ctx* c)
     if (flag & 2) return fail(c, LPB_ENUMERIC, "forward recurrence stability bound violated");
     if (c->opt.precision == LPB_MIXED) {
         c->a32.pool = g.d_pool32;
+        c->a32.pool_swz = g.d_swz32;
         // the FP64 pool is no longer needed
         for (auto& b : c->op_bufs)
             if (b.ptr == (void*)g.d_pool) {
@@ -429,6 +471,7 @@ lpb_status generate_operators(lpb_ctx* c)
         c->stats.operator_bytes = (int64_t)g.n_ops * K * K * (int64_t)sizeof(float);
     } else {
         c->a64.pool = g.d_pool;
+        c->a64.pool_swz = g.d_swz64;
         c->stats.operator_bytes = (int64_t)g.n_ops * K * K * (int64_t)sizeof(double);
     }
     c->ops_dirty = false;

@@ -7,6 +7,7 @@ namespace lpb {
 template <typename T>
 struct EvalArgs {
     int p, K, nslots;
+    int KP;             // padded coefficient stride of ME/LE rows (multiple of 16, >= K)
     int64_t ncharges;
     const FmmDev* fmm;
     const Medium* media;
@@ -40,6 +41,16 @@ struct EvalArgs {
     double quad_tol;
     double* parts;
     double* phi;
+    // tiled free-space M2L
+    int n_tiles;
+    const Tile* tiles;
+    const TileFL* tfl;
+    const int *grid_me, *grid_le, *optab, *oct_codes;
+    const T* pool_swz;          // operators in the MFMA operand layout, KP x KP each
+    // solid-harmonic recurrence coefficients (packed (n,m) index):
+    //   R_m^m = amm[m] (x+iy)^m, R_n^m = alpha z R_{n-1}^m - beta |v|^2 R_{n-2}^m
+    const T *sh_amm, *sh_alpha, *sh_beta;
+    const int* swz_index;       // op -> position in pool_swz
 };
 
 struct EvalSched {

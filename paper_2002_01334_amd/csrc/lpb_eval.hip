@@ -36,8 +36,11 @@ __device__ inline void bessel_ratio(int p, double lam, double r2, const double* 
 // ---------------------------------------------------------------------------
 // P2M (eqs. melecoeffree, melayerupgoingimage), scaled:
 //   Mh_nm = sum_j q_j g_n(r_j) conj(R_n^m(u_j / h)),  u_j = source - box centre.
-// One 64-lane block per source leaf; lanes own points, the per-point
-// coefficient rows are staged in LDS and summed per coefficient.
+// One 64-lane block per source leaf; each lane owns a point of the current
+// chunk, runs the solid-harmonic recurrence (coefficients from the tables
+// sh_amm/sh_alpha/sh_beta, read at wave-uniform addresses) and writes its
+// point's weighted coefficient row into LDS; then each lane sums whole
+// coefficient rows over the chunk.  The Bessel ratios are formed in FP64.
 template <typename T>
 __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 {
@@ -49,8 +52,7 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
     const double h = A.sl_h[leaf];
     const int CS = CH + 1;                                     // padded row stride
     T* coef = reinterpret_cast<T*>(smem_raw);                  // [K][CH+1]
-    T* rre = coef + (size_t)K * CS;                            // [Kp][CH]
-    T* rim = rre + (size_t)((p + 1) * (p + 2) / 2) * CH;
+    T* gl = coef + (size_t)K * CS;                             // [p+1][CH]
     __shared__ double inv_ith[LPB_MAX_P + 1];
     const int lane = threadIdx.x;
     if (lane == 0) {
@@ -64,20 +66,56 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = T(0);
     const T hinv = (T)(1.0 / h);
+    const T* __restrict__ amm_t = A.sh_amm;
+    const T* __restrict__ al_t = A.sh_alpha;
+    const T* __restrict__ be_t = A.sh_beta;
     for (int base = s0; base < s1; base += CH) {
         int j = base + lane;
         if (lane < CH && j < s1) {
             T ux = A.s_ux[j], uy = A.s_uy[j], uz = A.s_uz[j], q = A.qs[j];
-            double r2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-            double g[LPB_MAX_P + 2];
-            bessel_ratio(p, F.lam_s, r2, inv_ith, g);
-            // solid harmonics R_n^m(u/h) into per-lane LDS columns
-            solid_harmonics_lds<T>(p, ux * hinv, uy * hinv, uz * hinv, rre + lane, rim + lane, CH);
-            for (int n = 0; n <= p; ++n) {
-                T gq = (T)g[n] * q;
-                for (int m = 0; m <= n; ++m) {
-                    coef[(size_t)ire(n, m) * CS + lane] = gq * rre[(size_t)ipk(n, m) * CH + lane];
-                    if (m > 0) coef[(size_t)iim(n, m) * CS + lane] = -gq * rim[(size_t)ipk(n, m) * CH + lane];
+            double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+            {
+                // g_n = it_n(lam r)/it_n(lam h) (FP64), times q, into the lane's LDS column
+                double t = F.lam_s * F.lam_s * r2d;
+                double a = itilde_series(p + 1, t), bb = itilde_series(p, t);
+                gl[(size_t)p * CH + lane] = (T)(bb * inv_ith[p]) * q;
+                for (int n = p; n >= 1; --n) {
+                    double c = bb + t * a / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
+                    gl[(size_t)(n - 1) * CH + lane] = (T)(c * inv_ith[n - 1]) * q;
+                    a = bb;
+                    bb = c;
+                }
+            }
+            T x = ux * hinv, y = uy * hinv, z = uz * hinv;
+            T r2 = x * x + y * y + z * z;
+            T wr = T(1), wi = T(0);
+            for (int m = 0; m <= p; ++m) {
+                if (m > 0) {
+                    T nr = wr * x - wi * y;
+                    wi = wr * y + wi * x;
+                    wr = nr;
+                }
+                T pr = amm_t[m] * wr, pi = amm_t[m] * wi;
+                T gq = gl[(size_t)m * CH + lane];
+                coef[(size_t)ire(m, m) * CS + lane] = gq * pr;
+                if (m > 0) coef[(size_t)iim(m, m) * CS + lane] = -gq * pi;
+                if (m + 1 > p) continue;
+                T al = al_t[ipk(m + 1, m)];
+                T qr = al * z * pr, qi = al * z * pi;
+                gq = gl[(size_t)(m + 1) * CH + lane];
+                coef[(size_t)ire(m + 1, m) * CS + lane] = gq * qr;
+                if (m > 0) coef[(size_t)iim(m + 1, m) * CS + lane] = -gq * qi;
+                for (int n = m + 2; n <= p; ++n) {
+                    T a = al_t[ipk(n, m)], b = be_t[ipk(n, m)];
+                    T sr = a * z * qr - b * r2 * pr;
+                    T si = a * z * qi - b * r2 * pi;
+                    gq = gl[(size_t)n * CH + lane];
+                    coef[(size_t)ire(n, m) * CS + lane] = gq * sr;
+                    if (m > 0) coef[(size_t)iim(n, m) * CS + lane] = -gq * si;
+                    pr = qr;
+                    pi = qi;
+                    qr = sr;
+                    qi = si;
                 }
             }
         }
@@ -87,9 +125,9 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
         for (int kk = 0; kk < 8; ++kk) {
             int k = lane + 64 * kk;
             if (k < K) {
-                T s = T(0);
-                for (int jj = 0; jj < cnt; ++jj) s += coef[(size_t)k * CS + jj];
-                acc[kk] += s;
+                T sum = T(0);
+                for (int jj = 0; jj < cnt; ++jj) sum += coef[(size_t)k * CS + jj];
+                acc[kk] += sum;
             }
         }
         __syncthreads();
@@ -97,7 +135,7 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 #pragma unroll
     for (int kk = 0; kk < 8; ++kk) {
         int k = lane + 64 * kk;
-        if (k < K) A.me[(size_t)me * K + k] = acc[kk];
+        if (k < K) A.me[(size_t)me * A.KP + k] = acc[kk];
     }
 }
 
@@ -106,12 +144,12 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 //   out[row] (+)= sum_pairs sum_c Op[c*K + row] * in[c]
 // used for M2M (CSR by parent), M2L (CSR by target) and L2L (one pair).
 template <typename T>
-__device__ inline void apply_pairs(int K, const T* __restrict__ pool, const T* __restrict__ invec, const int* __restrict__ src,
-                                   const int* __restrict__ op, int b, int e, T* xs, T& acc)
+__device__ inline void apply_pairs(int K, int KP, const T* __restrict__ pool, const T* __restrict__ invec,
+                                   const int* __restrict__ src, const int* __restrict__ op, int b, int e, T* xs, T& acc)
 {
     const int row = threadIdx.x;
     for (int k = b; k < e; ++k) {
-        const T* v = invec + (size_t)src[k] * K;
+        const T* v = invec + (size_t)src[k] * KP;
         for (int c = threadIdx.x; c < K; c += blockDim.x) xs[c] = v[c];
         __syncthreads();
         if (row < K) {
@@ -136,8 +174,8 @@ __global__ void k_m2m(EvalArgs<T> A, int pbeg)
     T* xs = reinterpret_cast<T*>(smem_raw);
     const int pi = pbeg + blockIdx.x;
     T acc = T(0);
-    apply_pairs<T>(A.K, A.pool, A.me, A.m2m_child, A.m2m_op, A.m2m_ptr[pi], A.m2m_ptr[pi + 1], xs, acc);
-    if ((int)threadIdx.x < A.K) A.me[(size_t)A.m2m_parent[pi] * A.K + threadIdx.x] = acc;
+    apply_pairs<T>(A.K, A.KP, A.pool, A.me, A.m2m_child, A.m2m_op, A.m2m_ptr[pi], A.m2m_ptr[pi + 1], xs, acc);
+    if ((int)threadIdx.x < A.K) A.me[(size_t)A.m2m_parent[pi] * A.KP + threadIdx.x] = acc;
 }
 
 template <typename T>
@@ -147,8 +185,8 @@ __global__ void k_m2l(EvalArgs<T> A)
     T* xs = reinterpret_cast<T*>(smem_raw);
     const int le = A.m2l_boxes[blockIdx.x];
     T acc = T(0);
-    apply_pairs<T>(A.K, A.pool, A.me, A.m2l_src, A.m2l_op, A.m2l_ptr[le], A.m2l_ptr[le + 1], xs, acc);
-    if ((int)threadIdx.x < A.K) A.le[(size_t)le * A.K + threadIdx.x] = acc;
+    apply_pairs<T>(A.K, A.KP, A.pool, A.me, A.m2l_src, A.m2l_op, A.m2l_ptr[le], A.m2l_ptr[le + 1], xs, acc);
+    if ((int)threadIdx.x < A.K) A.le[(size_t)le * A.KP + threadIdx.x] += acc;
 }
 
 template <typename T>
@@ -158,25 +196,189 @@ __global__ void k_l2l(EvalArgs<T> A, int cbeg)
     T* xs = reinterpret_cast<T*>(smem_raw);
     const int ci = cbeg + blockIdx.x;
     T acc = T(0);
-    apply_pairs<T>(A.K, A.pool, A.le, A.l2l_parent + ci, A.l2l_op + ci, 0, 1, xs, acc);
-    if ((int)threadIdx.x < A.K) A.le[(size_t)A.l2l_child[ci] * A.K + threadIdx.x] += acc;
+    apply_pairs<T>(A.K, A.KP, A.pool, A.le, A.l2l_parent + ci, A.l2l_op + ci, 0, 1, xs, acc);
+    if ((int)threadIdx.x < A.K) A.le[(size_t)A.l2l_child[ci] * A.KP + threadIdx.x] += acc;
+}
+
+// ---------------------------------------------------------------------------
+// Tiled free-space M2L on the matrix cores.  A tile is 64 target boxes of one
+// (FMM, level) that share a child octant inside a 4x4x4 block of parents, so
+// all of them have the same 189 V-list offsets d and operators A_d.  For each
+// d the tile computes  L[:, tile] += A_d * M[:, tile + d]  as a (KP x KP) x
+// (KP x 64) product with 16x16x4 MFMA (FP32 or FP64), the 64 gathered source
+// expansions staged in LDS, the operator streamed from memory in the MFMA
+// operand layout.  Four waves split the 16-row blocks of the output; results
+// accumulate in registers over all 189 offsets and are added to LE once.
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
+template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+
+__device__ inline Vec4<float>::type mfma16(float a, float b, Vec4<float>::type c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ inline Vec4<double>::type mfma16(double a, double b, Vec4<double>::type c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+// output row (within a 16x16 block) of accumulator element r in lane l
+__device__ inline int mfma_row(float, int l, int r) { return 4 * (l >> 4) + r; }
+__device__ inline int mfma_row(double, int l, int r) { return (l >> 4) + 4 * r; }
+
+template <typename T, int RB>
+__global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
+{
+    typedef typename Vec4<T>::type V4;
+    constexpr int NT = 64, CB = 4;
+    constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);   // padded LDS row (bank spread)
+    extern __shared__ unsigned char smem_raw[];
+    T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
+    __shared__ int s_src[NT];
+    __shared__ int s_le[NT];
+    const int K = A.K, KP = A.KP, KB = KP / 16;
+    const Tile tile = A.tiles[blockIdx.x];
+    const TileFL fl = A.tfl[tile.fl];
+    const int nside = fl.nside;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
+    // per-offset products accumulate in `acc`; the sum over the 189 offsets is
+    // compensated (Kahan) in `tot`/`cmp`, which keeps FP32 error at the level
+    // of a single offset's product
+    V4 acc[RB][CB], tot[RB][CB], cmp[RB][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
+    // target coordinates of column j
+    auto tcoord = [&](int j, int& tx, int& ty, int& tz) {
+        tx = 2 * (tile.px0 + (j >> 4)) + ox;
+        ty = 2 * (tile.py0 + ((j >> 2) & 3)) + oy;
+        tz = 2 * (tile.pz0 + (j & 3)) + oz;
+    };
+    if (tid < NT) {
+        int tx, ty, tz;
+        tcoord(tid, tx, ty, tz);
+        s_le[tid] = (tx < nside && ty < nside && tz < nside)
+                        ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
+    }
+    const int* codes = A.oct_codes + tile.octant * kVOffsets;
+    for (int d = 0; d < kVOffsets; ++d) {
+        const int code = codes[d];
+        const int dx = code / 49 - 3, dy = (code / 7) % 7 - 3, dz = code % 7 - 3;
+        const int op = A.optab[fl.optab_off + code];
+        __syncthreads();
+        if (tid < NT) {
+            int tx, ty, tz;
+            tcoord(tid, tx, ty, tz);
+            int sx = tx + dx, sy = ty + dy, sz = tz + dz;
+            int me = -1;
+            if (s_le[tid] >= 0 && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
+                me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
+            s_src[tid] = me;
+        }
+        __syncthreads();
+        // gather: 4 threads per target column, contiguous k
+        {
+            const int j = tid >> 2, part = tid & 3;
+            const int me = s_src[j];
+            const T* src = A.me + (size_t)(me < 0 ? 0 : me) * KP;
+            for (int k = part; k < KP; k += 4) Bs[k * NTP + j] = (me >= 0) ? src[k] : T(0);
+        }
+        __syncthreads();
+        const T* Aw = A.pool_swz + (size_t)A.swz_index[op] * KP * KP;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+        for (int s4 = 0; s4 < KB; ++s4) {
+            V4 a4[RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                int rbg = w * RB + rb;
+                if (rbg < KB) a4[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4) * 64 + l) * 4);
+                else a4[rb] = V4{0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int ss = 0; ss < 4; ++ss) {
+                const int kk = 16 * s4 + 4 * ss + (l >> 4);
+                T b[CB];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) b[cb] = Bs[kk * NTP + cb * 16 + (l & 15)];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    if (w * RB + rb < KB) {
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                if (sizeof(T) == 4) {
+                    V4 y = acc[rb][cb] - cmp[rb][cb];
+                    V4 t = tot[rb][cb] + y;
+                    cmp[rb][cb] = (t - tot[rb][cb]) - y;
+                    tot[rb][cb] = t;
+                } else {
+                    tot[rb][cb] += acc[rb][cb];
+                }
+            }
+    }
+    // accumulate into the local expansions
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        int rbg = w * RB + rb;
+        if (rbg >= KB) continue;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            int j = cb * 16 + (l & 15);
+            int le = s_le[j];
+            if (le < 0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = rbg * 16 + mfma_row(T(0), l, r);
+                if (row < K) A.le[(size_t)le * KP + row] += tot[rb][cb][r];
+            }
+        }
+    }
+}
+
+template <typename T>
+static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
+{
+    const int KB = A.KP / 16, RB = (KB + 3) / 4;
+    const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
+    dim3 g(A.n_tiles), b(256);
+    switch (RB) {
+    case 1: hipLaunchKernelGGL((k_m2l_tile<T, 1>), g, b, sm, st, A); break;
+    case 2: hipLaunchKernelGGL((k_m2l_tile<T, 2>), g, b, sm, st, A); break;
+    case 3: hipLaunchKernelGGL((k_m2l_tile<T, 3>), g, b, sm, st, A); break;
+    case 4: hipLaunchKernelGGL((k_m2l_tile<T, 4>), g, b, sm, st, A); break;
+    case 5: hipLaunchKernelGGL((k_m2l_tile<T, 5>), g, b, sm, st, A); break;
+    case 6: hipLaunchKernelGGL((k_m2l_tile<T, 6>), g, b, sm, st, A); break;
+    default: hipLaunchKernelGGL((k_m2l_tile<T, 7>), g, b, sm, st, A); break;
+    }
 }
 
 // ---------------------------------------------------------------------------
 // L2P (eqs. freespace3dlocexp, lelayerimage), scaled:
 //   Phi = far_factor * sum_n g_n(r) [Lh_n0 R_n^0 + 2 sum_{m>0} Re(Lh_nm R_n^m)](u/h)
+// One 64-lane block per target leaf, a lane per target; the leaf's local
+// expansion is read at wave-uniform addresses, the Bessel ratios (FP64) sit
+// in the lane's LDS column.
 template <typename T>
 __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
 {
     extern __shared__ unsigned char smem_raw[];
-    const int p = A.p, K = A.K;
+    const int p = A.p;
     const int leaf = A.l2p_leaves[blockIdx.x];
     const int le = A.tl_le[leaf];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double h = A.tl_h[leaf];
-    T* Ls = reinterpret_cast<T*>(smem_raw);                       // [K]
-    T* rre = Ls + K;                                              // [Kp][CH]
-    T* rim = rre + (size_t)((p + 1) * (p + 2) / 2) * CH;
+    T* gl = reinterpret_cast<T*>(smem_raw);                       // [p+1][CH]
     __shared__ double inv_ith[LPB_MAX_P + 1];
     const int lane = threadIdx.x;
     if (lane == 0) {
@@ -184,24 +386,57 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
         itilde_all(p, F.lam_t * F.lam_t * h * h, t);
         for (int n = 0; n <= p; ++n) inv_ith[n] = 1.0 / t[n];
     }
-    for (int k = lane; k < K; k += 64) Ls[k] = A.le[(size_t)le * K + k];
     __syncthreads();
+    if (lane >= CH) return;
+    const T* __restrict__ Ls = A.le + (size_t)le * A.KP;
+    const T* __restrict__ amm_t = A.sh_amm;
+    const T* __restrict__ al_t = A.sh_alpha;
+    const T* __restrict__ be_t = A.sh_beta;
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const T hinv = (T)(1.0 / h);
-    if (lane >= CH) return;
     for (int j = t0 + lane; j < t1; j += CH) {
         T ux = A.t_ux[j], uy = A.t_uy[j], uz = A.t_uz[j];
-        double r2 = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-        double g[LPB_MAX_P + 2];
-        bessel_ratio(p, F.lam_t, r2, inv_ith, g);
-        solid_harmonics_lds<T>(p, ux * hinv, uy * hinv, uz * hinv, rre + lane, rim + lane, CH);
+        double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
+        {
+            double t = F.lam_t * F.lam_t * r2d;
+            double a = itilde_series(p + 1, t), bb = itilde_series(p, t);
+            gl[(size_t)p * CH + lane] = (T)(bb * inv_ith[p]);
+            for (int n = p; n >= 1; --n) {
+                double c = bb + t * a / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
+                gl[(size_t)(n - 1) * CH + lane] = (T)(c * inv_ith[n - 1]);
+                a = bb;
+                bb = c;
+            }
+        }
+        T x = ux * hinv, y = uy * hinv, z = uz * hinv;
+        T r2 = x * x + y * y + z * z;
+        T wr = T(1), wi = T(0);
         T phi = T(0);
-        for (int n = 0; n <= p; ++n) {
-            T s = Ls[ire(n, 0)] * rre[(size_t)ipk(n, 0) * CH + lane];
-            T s2 = T(0);
-            for (int m = 1; m <= n; ++m)
-                s2 += Ls[ire(n, m)] * rre[(size_t)ipk(n, m) * CH + lane] - Ls[iim(n, m)] * rim[(size_t)ipk(n, m) * CH + lane];
-            phi += (T)g[n] * (s + T(2) * s2);
+        for (int m = 0; m <= p; ++m) {
+            if (m > 0) {
+                T nr = wr * x - wi * y;
+                wi = wr * y + wi * x;
+                wr = nr;
+            }
+            const T two = (m > 0) ? T(2) : T(1);
+            T pr = amm_t[m] * wr, pi = amm_t[m] * wi;
+            T sm = gl[(size_t)m * CH + lane] * (Ls[ire(m, m)] * pr - (m > 0 ? Ls[iim(m, m)] * pi : T(0)));
+            if (m + 1 <= p) {
+                T al = al_t[ipk(m + 1, m)];
+                T qr = al * z * pr, qi = al * z * pi;
+                sm += gl[(size_t)(m + 1) * CH + lane] * (Ls[ire(m + 1, m)] * qr - (m > 0 ? Ls[iim(m + 1, m)] * qi : T(0)));
+                for (int n = m + 2; n <= p; ++n) {
+                    T a = al_t[ipk(n, m)], b = be_t[ipk(n, m)];
+                    T sr = a * z * qr - b * r2 * pr;
+                    T si = a * z * qi - b * r2 * pi;
+                    sm += gl[(size_t)n * CH + lane] * (Ls[ire(n, m)] * sr - (m > 0 ? Ls[iim(n, m)] * si : T(0)));
+                    pr = qr;
+                    pi = qi;
+                    qr = sr;
+                    qi = si;
+                }
+            }
+            phi += two * sm;
         }
         A.parts[A.t_out[j]] = (double)phi * F.far_factor;
     }
@@ -351,19 +586,19 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     LPB_MARK(0);
     if (A.n_src > 0) hipLaunchKernelGGL(k_gather_q<T>, dim3((A.n_src + 255) / 256), dim3(256), 0, st, A.n_src, A.s_cidx, A.q, A.qs);
     hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, st, (size_t)A.nslots * A.ncharges, A.parts);
-    if (A.n_le > 0) hipLaunchKernelGGL(k_zero<T>, dim3(1024), dim3(256), 0, st, (size_t)A.n_le * K, A.le);
+    if (A.n_le > 0) hipLaunchKernelGGL(k_zero<T>, dim3(1024), dim3(256), 0, st, (size_t)A.n_le * A.KP, A.le);
     const bool far = stages & 1, near = stages & 2;
     LPB_MARK(1);
     // upward pass
-    // point chunks sized so that a block's LDS stays under 40 KB (several blocks per CU)
+    // point chunks sized so that a block's LDS stays under 24 KB (several blocks per CU)
     auto pick_ch = [&](size_t per_ch, size_t fixed) {
         int ch = 64;
-        while (ch > 8 && fixed + per_ch * ch > 40u * 1024u) ch >>= 1;
+        while (ch > 8 && fixed + per_ch * ch > 24u * 1024u) ch >>= 1;
         return ch;
     };
     if (far && S.n_p2m > 0) {
-        int ch = pick_ch(sizeof(T) * ((size_t)K + 2 * Kp), sizeof(T) * (size_t)K);
-        size_t sm = sizeof(T) * ((size_t)K * (ch + 1) + 2 * (size_t)Kp * ch);
+        int ch = pick_ch(sizeof(T) * ((size_t)K + p + 1), sizeof(T) * (size_t)K);
+        size_t sm = sizeof(T) * ((size_t)K * (ch + 1) + (size_t)(p + 1) * ch);
         hipLaunchKernelGGL(k_p2m<T>, dim3(S.n_p2m), dim3(64), sm, st, A, ch);
     }
     LPB_MARK(2);
@@ -373,6 +608,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     }
     // V-list translations (all levels), then the downward pass
     LPB_MARK(3);
+    if (far && A.n_tiles > 0) launch_m2l_tile<T>(A, st);
     if (far && S.n_m2l_boxes > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(S.n_m2l_boxes), dim3(bsz), sizeof(T) * K, st, A);
     LPB_MARK(4);
     for (int l = 0; l <= kMaxDepth; ++l) {
@@ -381,9 +617,8 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     }
     LPB_MARK(5);
     if (far && S.n_l2p > 0) {
-        int ch = pick_ch(2 * sizeof(T) * (size_t)Kp, sizeof(T) * (size_t)K);
-        size_t sm = sizeof(T) * ((size_t)K + 2 * (size_t)Kp * ch);
-        hipLaunchKernelGGL(k_l2p<T>, dim3(S.n_l2p), dim3(64), sm, st, A, ch);
+        size_t sm = sizeof(T) * (size_t)(p + 1) * 64;
+        hipLaunchKernelGGL(k_l2p<T>, dim3(S.n_l2p), dim3(64), sm, st, A, 64);
     }
     // near field
     LPB_MARK(6);

@@ -14,6 +14,9 @@ namespace lpb {
 
 constexpr int kMaxDepth = 12;   // deepest tree level
 constexpr int kCellBits = 16;   // fine cell bits per axis
+constexpr int kTileMaxLevel = 8;  // free-space levels up to this one use the tiled MFMA M2L
+constexpr int kTilePB = 4;        // parents per axis of an M2L tile (4^3 parents -> 64 target boxes)
+constexpr int kVOffsets = 189;    // V-list offsets of one child octant
 
 enum OpType { OP_M2M = 0, OP_L2L = 1, OP_M2L_FREE = 2, OP_M2L_REACT = 3 };
 
@@ -76,6 +79,18 @@ struct RKey {
     double S;             // box side (scaling length of the paper's scaled integrals)
 };
 
+// Tiled free-space M2L: one record per (free FMM, level) with dense box grids,
+// and tiles of 64 target boxes sharing a child octant (so that all of them
+// have the same 189 V-list offsets and operators).
+struct TileFL {
+    int fmm, level, nside;
+    int grid_off;     // into grid_me / grid_le (nside^3 entries each)
+    int optab_off;    // into optab (343 entries: offset code -> operator)
+};
+struct Tile {
+    int fl, octant, px0, py0, pz0;
+};
+
 // Host-side plan (built by build_plan, uploaded by the context).
 struct Plan {
     int p = 10, K = 121, leaf_cap = 50;
@@ -113,6 +128,13 @@ struct Plan {
     // operators
     std::vector<OpDesc> ops;
     std::vector<RKey> rkeys;
+    // tiled free-space M2L
+    std::vector<TileFL> tfl;
+    std::vector<Tile> tiles;
+    std::vector<int> grid_me, grid_le, optab;
+    std::vector<int> oct_codes;    // 8 x 189 offset codes ((dx+3)*7+(dy+3))*7+(dz+3)
+    std::vector<int> swz_ops;      // operators stored in the MFMA operand layout (free-space M2L)
+    std::vector<int> swz_index;    // op -> position in swz_ops (-1 if none)
 };
 
 // Build the plan for all systems (host).  Returns an error message or "".

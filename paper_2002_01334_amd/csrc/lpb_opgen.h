@@ -25,6 +25,12 @@ struct OpgenInputs {
     float* d_pool32;          // FP32 copy (output, may be null)
     int* d_flag;              // bit 0: quadrature budget exceeded, bit 1: recurrence bound violated
     double quad_tol;
+    // free-space M2L operators in the MFMA operand layout (KP x KP each)
+    int KP;
+    int n_swz;
+    const int* d_swz_ops;
+    double* d_swz64;          // FP64 mode
+    float* d_swz32;           // mixed mode
 };
 
 hipError_t opgen_upload_constants();

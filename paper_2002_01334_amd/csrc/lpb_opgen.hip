@@ -438,6 +438,27 @@ __global__ void __launch_bounds__(256) k_free_op(int p, const int* __restrict__ 
     }
 }
 
+// Free-space M2L operators in the operand layout of the 16x16x4 MFMA:
+//   out[((rb*KB + s4)*64 + lane)*4 + ss] = A[row = 16 rb + lane%16][k = 16 s4 + 4 ss + lane/16]
+// (zero outside K x K), KB = KP/16.  A is the column-major FP64 operator.
+template <typename T>
+__global__ void k_swizzle(int K, int KP, int nsw, const int* __restrict__ ops, const double* __restrict__ pool,
+                          T* __restrict__ out)
+{
+    const int KB = KP / 16;
+    size_t per = (size_t)KP * KP;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per * nsw) return;
+    int o = (int)(idx / per);
+    size_t e = idx % per;
+    int ss = (int)(e & 3), lane = (int)((e >> 2) & 63);
+    size_t rest = e >> 8;
+    int s4 = (int)(rest % KB), rb = (int)(rest / KB);
+    int row = 16 * rb + (lane & 15), k = 16 * s4 + 4 * ss + (lane >> 4);
+    double v = (row < K && k < K) ? pool[(size_t)ops[o] * K * K + (size_t)k * K + row] : 0.0;
+    out[idx] = (T)v;
+}
+
 __global__ void k_to_float(size_t n, const double* __restrict__ a, float* __restrict__ b)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -515,6 +536,16 @@ hipError_t opgen_run(const OpgenInputs& in, hipStream_t st)
     if (in.d_pool32) {
         size_t n = (size_t)in.n_ops * K * K;
         hipLaunchKernelGGL(k_to_float, dim3(2048), dim3(256), 0, st, n, in.d_pool, in.d_pool32);
+    }
+    if (in.n_swz > 0) {
+        size_t n = (size_t)in.KP * in.KP * in.n_swz;
+        unsigned blocks = (unsigned)((n + 255) / 256);
+        if (in.d_swz32)
+            hipLaunchKernelGGL(k_swizzle<float>, dim3(blocks), dim3(256), 0, st, K, in.KP, in.n_swz, in.d_swz_ops,
+                               in.d_pool, in.d_swz32);
+        else
+            hipLaunchKernelGGL(k_swizzle<double>, dim3(blocks), dim3(256), 0, st, K, in.KP, in.n_swz, in.d_swz_ops,
+                               in.d_pool, in.d_swz64);
     }
     return hipGetLastError();
 }

@@ -141,7 +141,18 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.me_fmm.clear(); P.me_level.clear(); P.le_fmm.clear(); P.le_level.clear();
     P.n_me = P.n_le = 0;
     P.ops.clear(); P.rkeys.clear();
+    P.tfl.clear(); P.tiles.clear(); P.grid_me.clear(); P.grid_le.clear(); P.optab.clear();
     P.n_p2p_pairs = P.n_react_p2p_pairs = P.n_m2l_pairs = 0;
+    P.oct_codes.clear();
+    for (int o = 0; o < 8; ++o) {
+        int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+        for (int dx = -2 - ox; dx <= 3 - ox; ++dx)
+            for (int dy = -2 - oy; dy <= 3 - oy; ++dy)
+                for (int dz = -2 - oz; dz <= 3 - oz; ++dz) {
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                    P.oct_codes.push_back(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
+                }
+    }
     // per-level staging (levels are contiguous across FMMs in the final arrays)
     struct M2MRec { int parent, child, op; };
     struct L2LRec { int child, parent, op; };
@@ -415,7 +426,69 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                 }
             // M2L (V-lists) with operator de-duplication
             std::unordered_map<uint64_t, int> opmap, rkmap;
+            auto free_op = [&](int lv, int dx, int dy, int dz) {
+                uint64_t key = ((uint64_t)lv << 16) | (uint64_t)(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
+                auto f = opmap.find(key);
+                if (f != opmap.end()) return f->second;
+                double h = hlev(lv);
+                OpDesc d{};
+                d.type = OP_M2L_FREE;
+                d.fmm = fid;
+                d.level = lv;
+                d.rkey = -1;
+                d.bx = -dx * h;   // b = c_t - c_s
+                d.by = -dy * h;
+                d.bz = -dz * h;
+                int op = (int)P.ops.size();
+                P.ops.push_back(d);
+                opmap[key] = op;
+                return op;
+            };
+            // tiled levels of a free-space FMM: dense grids, operator table, tiles
+            int tiled_max = (cp.kind == 0) ? std::min(H, kTileMaxLevel) : 1;
+            for (int lv = 2; lv <= tiled_max; ++lv) {
+                int nside = 1 << lv;
+                TileFL t{};
+                t.fmm = fid;
+                t.level = lv;
+                t.nside = nside;
+                t.grid_off = (int)P.grid_me.size();
+                t.optab_off = (int)P.optab.size();
+                P.grid_me.resize(P.grid_me.size() + (size_t)nside * nside * nside, -1);
+                P.grid_le.resize(P.grid_le.size() + (size_t)nside * nside * nside, -1);
+                for (int k = 0; k < (int)SB[lv].mkey.size(); ++k)
+                    P.grid_me[t.grid_off + ((size_t)SB[lv].ix[k] * nside + SB[lv].iy[k]) * nside + SB[lv].iz[k]] = F.me_off[lv] + k;
+                for (int k = 0; k < (int)TB[lv].mkey.size(); ++k)
+                    P.grid_le[t.grid_off + ((size_t)TB[lv].ix[k] * nside + TB[lv].iy[k]) * nside + TB[lv].iz[k]] = F.le_off[lv] + k;
+                P.optab.resize(P.optab.size() + 343, -1);
+                for (int dx = -3; dx <= 3; ++dx)
+                    for (int dy = -3; dy <= 3; ++dy)
+                        for (int dz = -3; dz <= 3; ++dz) {
+                            if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                            P.optab[t.optab_off + ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)] = free_op(lv, dx, dy, dz);
+                        }
+                int fl = (int)P.tfl.size();
+                P.tfl.push_back(t);
+                int np = nside / 2;
+                for (int bx = 0; bx < np; bx += kTilePB)
+                    for (int by = 0; by < np; by += kTilePB)
+                        for (int bz = 0; bz < np; bz += kTilePB)
+                            for (int o = 0; o < 8; ++o) {
+                                bool any = false;
+                                for (int i = 0; i < kTilePB && !any; ++i)
+                                    for (int j = 0; j < kTilePB && !any; ++j)
+                                        for (int k = 0; k < kTilePB && !any; ++k) {
+                                            int tx = 2 * (bx + i) + ((o >> 2) & 1), ty = 2 * (by + j) + ((o >> 1) & 1),
+                                                tz = 2 * (bz + k) + (o & 1);
+                                            if (tx < nside && ty < nside && tz < nside &&
+                                                P.grid_le[t.grid_off + ((size_t)tx * nside + ty) * nside + tz] >= 0)
+                                                any = true;
+                                        }
+                                if (any) P.tiles.push_back({fl, o, bx, by, bz});
+                            }
+            }
             for (int lv = 2; lv <= H; ++lv) {
+                const bool tiled = lv <= tiled_max;
                 int nside = 1 << lv;
                 double h = hlev(lv);
                 for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
@@ -434,21 +507,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                                     if (it == SB[lv].idx.end()) continue;
                                     int op;
                                     if (cp.kind == 0) {
-                                        uint64_t key = ((uint64_t)lv << 16) | (uint64_t)(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
-                                        auto f = opmap.find(key);
-                                        if (f == opmap.end()) {
-                                            OpDesc d{};
-                                            d.type = OP_M2L_FREE;
-                                            d.fmm = fid;
-                                            d.level = lv;
-                                            d.rkey = -1;
-                                            d.bx = -dx * h;   // b = c_t - c_s
-                                            d.by = -dy * h;
-                                            d.bz = -dz * h;
-                                            op = (int)P.ops.size();
-                                            P.ops.push_back(d);
-                                            opmap[key] = op;
-                                        } else op = f->second;
+                                        op = free_op(lv, dx, dy, dz);
                                     } else {
                                         uint64_t key = ((uint64_t)lv << 48) | ((uint64_t)(dx + 3) << 40) | ((uint64_t)(dy + 3) << 32) |
                                                        ((uint64_t)tz << 16) | (uint64_t)sz;
@@ -481,7 +540,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                                             opmap[key] = op;
                                         } else op = f->second;
                                     }
-                                    m2l_by_le[le].push_back({F.me_off[lv] + it->second, op});
+                                    if (!tiled) m2l_by_le[le].push_back({F.me_off[lv] + it->second, op});
                                     P.n_m2l_pairs++;
                                 }
                             }
@@ -565,6 +624,13 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         }
         P.m2l_ptr.push_back((int)P.m2l_src.size());
     }
+    P.swz_ops.clear();
+    P.swz_index.assign(P.ops.size(), -1);
+    for (size_t i = 0; i < P.ops.size(); ++i)
+        if (P.ops[i].type == OP_M2L_FREE) {
+            P.swz_index[i] = (int)P.swz_ops.size();
+            P.swz_ops.push_back((int)i);
+        }
     P.p2p_ptr.assign(1, 0); P.p2p_src.clear();
     p2p_by_tl.resize(P.tl_le.size());
     for (auto& v : p2p_by_tl) {
