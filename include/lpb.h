@@ -78,6 +78,7 @@ typedef struct {
     int n_fmm;              /* free-space + reaction FMMs in the plan */
     int max_depth;          /* deepest tree level over all FMMs */
     int64_t n_m2l_pairs;    /* V-list pairs */
+    int64_t n_m2l_tile_pairs; /* V-list pairs evaluated by the tiled matrix-core M2L (free space) */
     int64_t n_p2p_pairs;    /* near-field charge pairs (free + reaction) */
     int64_t n_react_p2p_pairs; /* near-field reaction pairs (each a Sommerfeld quadrature) */
     int64_t n_operators;    /* translation operators generated */
@@ -86,9 +87,10 @@ typedef struct {
     double t_opgen_ms;      /* last operator generation (GPU, FP64) */
     double t_eval_ms;       /* last lpb_evaluate, stream time between its first and last kernel */
     /* per-stage stream time of the last evaluate when options.timing = 1:
-     * [0] charge gather + clears, [1] P2M, [2] M2M, [3] M2L, [4] L2L, [5] L2P,
-     * [6] free-space near field, [7] reaction near field, [8] component sum */
-    double t_stage_ms[9];
+     * [0] charge gather + clears, [1] P2M, [2] M2M, [3] tiled M2L (free space),
+     * [4] list M2L (reaction, deep levels), [5] L2L, [6] L2P,
+     * [7] free-space near field, [8] reaction near field, [9] component sum */
+    double t_stage_ms[10];
 } lpb_stats;
 
 /* Fill *opt with the defaults listed above.  Never fails. */

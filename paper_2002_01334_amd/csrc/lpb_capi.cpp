@@ -53,7 +53,7 @@ struct lpb_ctx {
     OpgenInputs og{};
     lpb_stats stats{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
-    hipEvent_t evs[10] = {};
+    hipEvent_t evs[11] = {};
 };
 
 namespace {
@@ -383,6 +383,7 @@ lpb_status build_and_upload(lpb_ctx* c)
     c->stats.n_fmm = (int)P.fmm.size();
     c->stats.max_depth = P.max_depth;
     c->stats.n_m2l_pairs = P.n_m2l_pairs;
+    c->stats.n_m2l_tile_pairs = P.n_m2l_tile_pairs;
     c->stats.n_p2p_pairs = P.n_p2p_pairs;
     c->stats.n_react_p2p_pairs = P.n_react_p2p_pairs;
     c->stats.n_operators = (int64_t)P.ops.size();
@@ -616,7 +617,7 @@ static lpb_status evaluate_common(lpb_ctx* c, int nsys, const double* const* q, 
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.t_eval_ms = ms;
     if (c->opt.timing)
-        for (int k = 0; k < 9; ++k) {
+        for (int k = 0; k < 10; ++k) {
             float t = 0.f;
             HIPCHK(c, hipEventElapsedTime(&t, c->evs[k], c->evs[k + 1]));
             c->stats.t_stage_ms[k] = t;

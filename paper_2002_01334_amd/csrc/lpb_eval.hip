@@ -609,27 +609,28 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     // V-list translations (all levels), then the downward pass
     LPB_MARK(3);
     if (far && A.n_tiles > 0) launch_m2l_tile<T>(A, st);
-    if (far && S.n_m2l_boxes > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(S.n_m2l_boxes), dim3(bsz), sizeof(T) * K, st, A);
     LPB_MARK(4);
+    if (far && S.n_m2l_boxes > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(S.n_m2l_boxes), dim3(bsz), sizeof(T) * K, st, A);
+    LPB_MARK(5);
     for (int l = 0; l <= kMaxDepth; ++l) {
         int b = S.l2l_level_ptr[l], e = S.l2l_level_ptr[l + 1];
         if (far && e > b) hipLaunchKernelGGL(k_l2l<T>, dim3(e - b), dim3(bsz), sizeof(T) * K, st, A, b);
     }
-    LPB_MARK(5);
+    LPB_MARK(6);
     if (far && S.n_l2p > 0) {
         size_t sm = sizeof(T) * (size_t)(p + 1) * 64;
         hipLaunchKernelGGL(k_l2p<T>, dim3(S.n_l2p), dim3(64), sm, st, A, 64);
     }
     // near field
-    LPB_MARK(6);
-    if (near && S.n_p2p_free > 0) hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, st, A);
     LPB_MARK(7);
+    if (near && S.n_p2p_free > 0) hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, st, A);
+    LPB_MARK(8);
     if (near && A.n_react_targets > 0)
         hipLaunchKernelGGL(k_p2p_react<T>, dim3((A.n_react_targets + 63) / 64), dim3(64), 0, st, A);
-    LPB_MARK(8);
+    LPB_MARK(9);
     if (A.ncharges > 0)
         hipLaunchKernelGGL(k_sum, dim3((unsigned)((A.ncharges + 255) / 256)), dim3(256), 0, st, A.ncharges, A.nslots, A.parts, A.phi);
-    LPB_MARK(9);
+    LPB_MARK(10);
 #undef LPB_MARK
     return hipGetLastError();
 }

@@ -124,7 +124,7 @@ struct Plan {
     std::vector<int> m2l_ptr, m2l_src, m2l_op;   // m2l_ptr has n_le+1
     // near field: CSR by target leaf over source leaves
     std::vector<int> p2p_ptr, p2p_src;
-    int64_t n_p2p_pairs = 0, n_react_p2p_pairs = 0, n_m2l_pairs = 0;
+    int64_t n_p2p_pairs = 0, n_react_p2p_pairs = 0, n_m2l_pairs = 0, n_m2l_tile_pairs = 0;
     // operators
     std::vector<OpDesc> ops;
     std::vector<RKey> rkeys;

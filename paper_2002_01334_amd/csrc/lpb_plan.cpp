@@ -142,7 +142,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.n_me = P.n_le = 0;
     P.ops.clear(); P.rkeys.clear();
     P.tfl.clear(); P.tiles.clear(); P.grid_me.clear(); P.grid_le.clear(); P.optab.clear();
-    P.n_p2p_pairs = P.n_react_p2p_pairs = P.n_m2l_pairs = 0;
+    P.n_p2p_pairs = P.n_react_p2p_pairs = P.n_m2l_pairs = P.n_m2l_tile_pairs = 0;
     P.oct_codes.clear();
     for (int o = 0; o < 8; ++o) {
         int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
@@ -541,6 +541,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                                         } else op = f->second;
                                     }
                                     if (!tiled) m2l_by_le[le].push_back({F.me_off[lv] + it->second, op});
+                                    else P.n_m2l_tile_pairs++;
                                     P.n_m2l_pairs++;
                                 }
                             }
