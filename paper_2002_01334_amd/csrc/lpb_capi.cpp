@@ -304,6 +304,31 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
         UP(sh_alpha, al);
         UP(sh_beta, be);
     }
+    {
+        // Bessel-ratio tables: factors of the it_n recurrence and series (p only) and
+        // 1/it_n(lam h) for every FMM and level, source and target lambda
+        const int NSER = 40, S0 = LPB_MAX_P + 2, S1 = S0 + NSER + 1;
+        std::vector<double> tb(S1 + NSER + 1, 0.0);
+        for (int n = 0; n <= P.p + 1; ++n) tb[n] = 1.0 / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
+        for (int k = 1; k <= NSER; ++k) {
+            tb[S0 + k] = 1.0 / (2.0 * k * (2.0 * P.p + 2.0 * k + 1.0));
+            tb[S1 + k] = 1.0 / (2.0 * k * (2.0 * (P.p + 1) + 2.0 * k + 1.0));
+        }
+        const size_t per = (size_t)(kMaxDepth + 1) * (LPB_MAX_P + 1);
+        std::vector<double> is(P.fmm.size() * per, 1.0), it(P.fmm.size() * per, 1.0);
+        double buf[LPB_MAX_P + 2];
+        for (size_t f = 0; f < P.fmm.size(); ++f)
+            for (int lv = 0; lv <= kMaxDepth; ++lv) {
+                double h = 2.0 * P.fmm[f].R / (double)(1 << lv);
+                itilde_all(P.p, P.fmm[f].lam_s * P.fmm[f].lam_s * h * h, buf);
+                for (int n = 0; n <= P.p; ++n) is[f * per + lv * (LPB_MAX_P + 1) + n] = 1.0 / buf[n];
+                itilde_all(P.p, P.fmm[f].lam_t * P.fmm[f].lam_t * h * h, buf);
+                for (int n = 0; n <= P.p; ++n) it[f * per + lv * (LPB_MAX_P + 1) + n] = 1.0 / buf[n];
+            }
+        UP(bes_tab, tb);
+        UP(ith_s, is);
+        UP(ith_t, it);
+    }
     A.n_tiles = (int)P.tiles.size();
     // work lists
     std::vector<int> p2m, l2p, pfree, rleaf, rslot, m2lb;

@@ -50,6 +50,9 @@ struct EvalArgs {
     // solid-harmonic recurrence coefficients (packed (n,m) index):
     //   R_m^m = amm[m] (x+iy)^m, R_n^m = alpha z R_{n-1}^m - beta |v|^2 R_{n-2}^m
     const T *sh_amm, *sh_alpha, *sh_beta;
+    // Bessel-ratio tables (FP64): p-dependent recurrence/series factors, and
+    // 1/it_n(lam h) per FMM and level for the source (ith_s) and target (ith_t) lambda
+    const double *bes_tab, *ith_s, *ith_t;
     const int* swz_index;       // op -> position in pool_swz
 };
 

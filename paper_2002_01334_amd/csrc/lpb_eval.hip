@@ -33,6 +33,50 @@ __device__ inline void bessel_ratio(int p, double lam, double r2, const double* 
     for (int n = 0; n <= p; ++n) g[n] *= inv_ith[n];
 }
 
+// Bessel-ratio tables (FP64, built on the host): A.bes_tab[LPB_TB_REC + n] =
+// 1/((2n+1)(2n+3)), A.bes_tab[LPB_TB_S0 + k] = 1/(2k(2p+2k+1)),
+// A.bes_tab[LPB_TB_S1 + k] = 1/(2k(2p+2k+3)), and per FMM and level
+// 1/it_n(lam h) (A.ith_s for the source-side lambda, A.ith_t for the target side).
+#define LPB_NSER 40
+#define LPB_TB_REC 0
+#define LPB_TB_S0 (LPB_MAX_P + 2)
+#define LPB_TB_S1 (LPB_TB_S0 + LPB_NSER + 1)
+#define LPB_TB_SIZE (LPB_TB_S1 + LPB_NSER + 1)
+
+// it_N(x) series with the tabulated factors (t = x^2); large arguments (boxes
+// much wider than the Debye length) continue with the explicit factors
+__device__ inline double itilde_series_tab(double t, const double* f, int N)
+{
+    double term = 1.0, sum = 1.0;
+    for (int k = 1; k <= LPB_NSER; ++k) {
+        term *= t * f[k];
+        sum += term;
+        if (term <= 1e-17 * sum) return sum;
+    }
+    for (int k = LPB_NSER + 1; k < 4000; ++k) {
+        term *= 0.5 * t / ((double)k * (2.0 * N + 2.0 * k + 1.0));
+        sum += term;
+        if (term <= 1e-17 * sum) break;
+    }
+    return sum;
+}
+
+// g_n = it_n(lam r)/it_n(lam h) * scale, n = 0..p, written to out[n * stride];
+// tb: the p-dependent tables, ith: 1/it_n(lam h) of the box level
+template <typename T>
+__device__ inline void bessel_ratio_col(int p, double t, const double* __restrict__ tb, const double* __restrict__ ith,
+                                        T scale, T* out, int stride)
+{
+    double a = itilde_series_tab(t, tb + LPB_TB_S1, p + 1), bb = itilde_series_tab(t, tb + LPB_TB_S0, p);
+    out[(size_t)p * stride] = (T)(bb * ith[p]) * scale;
+    for (int n = p; n >= 1; --n) {
+        double c = bb + t * a * tb[LPB_TB_REC + n];
+        out[(size_t)(n - 1) * stride] = (T)(c * ith[n - 1]) * scale;
+        a = bb;
+        bb = c;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // P2M (eqs. melecoeffree, melayerupgoingimage), scaled:
 //   Mh_nm = sum_j q_j g_n(r_j) conj(R_n^m(u_j / h)),  u_j = source - box centre.
@@ -53,14 +97,9 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
     const int CS = CH + 1;                                     // padded row stride
     T* coef = reinterpret_cast<T*>(smem_raw);                  // [K][CH+1]
     T* gl = coef + (size_t)K * CS;                             // [p+1][CH]
-    __shared__ double inv_ith[LPB_MAX_P + 1];
     const int lane = threadIdx.x;
-    if (lane == 0) {
-        double t[LPB_MAX_P + 2];
-        itilde_all(p, F.lam_s * F.lam_s * h * h, t);
-        for (int n = 0; n <= p; ++n) inv_ith[n] = 1.0 / t[n];
-    }
-    __syncthreads();
+    const double* __restrict__ tb = A.bes_tab;
+    const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
     const int s0 = A.sl_start[leaf], s1 = A.sl_start[leaf + 1];
     T acc[8];
 #pragma unroll
@@ -74,18 +113,8 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
         if (lane < CH && j < s1) {
             T ux = A.s_ux[j], uy = A.s_uy[j], uz = A.s_uz[j], q = A.qs[j];
             double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-            {
-                // g_n = it_n(lam r)/it_n(lam h) (FP64), times q, into the lane's LDS column
-                double t = F.lam_s * F.lam_s * r2d;
-                double a = itilde_series(p + 1, t), bb = itilde_series(p, t);
-                gl[(size_t)p * CH + lane] = (T)(bb * inv_ith[p]) * q;
-                for (int n = p; n >= 1; --n) {
-                    double c = bb + t * a / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
-                    gl[(size_t)(n - 1) * CH + lane] = (T)(c * inv_ith[n - 1]) * q;
-                    a = bb;
-                    bb = c;
-                }
-            }
+            // g_n = it_n(lam r)/it_n(lam h) (FP64), times q, into the lane's LDS column
+            bessel_ratio_col<T>(p, F.lam_s * F.lam_s * r2d, tb, ith, q, gl + lane, CH);
             T x = ux * hinv, y = uy * hinv, z = uz * hinv;
             T r2 = x * x + y * y + z * z;
             T wr = T(1), wi = T(0);
@@ -229,11 +258,10 @@ template <typename T, int RB>
 __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
 {
     typedef typename Vec4<T>::type V4;
-    constexpr int NT = 64, CB = 4;
+    constexpr int NT = 64, CB = 4, GMAX = 4 * RB;
     constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);   // padded LDS row (bank spread)
     extern __shared__ unsigned char smem_raw[];
     T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
-    __shared__ int s_src[NT];
     __shared__ int s_le[NT];
     const int K = A.K, KP = A.KP, KB = KP / 16;
     const Tile tile = A.tiles[blockIdx.x];
@@ -242,14 +270,13 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
     // per-offset products accumulate in `acc`; the sum over the 189 offsets is
-    // compensated (Kahan) in `tot`/`cmp`, which keeps FP32 error at the level
-    // of a single offset's product
+    // compensated (Kahan, FP32) in `tot`/`cmp`, which keeps the FP32 error at the
+    // level of a single offset's product
     V4 acc[RB][CB], tot[RB][CB], cmp[RB][CB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
-    // target coordinates of column j
     auto tcoord = [&](int j, int& tx, int& ty, int& tz) {
         tx = 2 * (tile.px0 + (j >> 4)) + ox;
         ty = 2 * (tile.py0 + ((j >> 2) & 3)) + oy;
@@ -261,42 +288,57 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
         s_le[tid] = (tx < nside && ty < nside && tz < nside)
                         ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
     }
+    __syncthreads();
+    // gather role of this thread: target column gj, rows 16 i + 4 gpart .. +3
+    const int gj = tid >> 2, gpart = tid & 3;
+    int gtx, gty, gtz;
+    tcoord(gj, gtx, gty, gtz);
+    const bool gvalid = s_le[gj] >= 0;
     const int* codes = A.oct_codes + tile.octant * kVOffsets;
-    for (int d = 0; d < kVOffsets; ++d) {
+    V4 greg[GMAX];
+    auto fetch = [&](int d) {
         const int code = codes[d];
-        const int dx = code / 49 - 3, dy = (code / 7) % 7 - 3, dz = code % 7 - 3;
-        const int op = A.optab[fl.optab_off + code];
-        __syncthreads();
-        if (tid < NT) {
-            int tx, ty, tz;
-            tcoord(tid, tx, ty, tz);
-            int sx = tx + dx, sy = ty + dy, sz = tz + dz;
-            int me = -1;
-            if (s_le[tid] >= 0 && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
-                me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
-            s_src[tid] = me;
+        const int sx = gtx + code / 49 - 3, sy = gty + (code / 7) % 7 - 3, sz = gtz + code % 7 - 3;
+        int me = -1;
+        if (gvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
+            me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
+        const T* src = A.me + (size_t)(me < 0 ? 0 : me) * KP + 4 * gpart;
+#pragma unroll
+        for (int i = 0; i < GMAX; ++i)
+            greg[i] = (me >= 0 && i < KB) ? *reinterpret_cast<const V4*>(src + 16 * i) : V4{0, 0, 0, 0};
+    };
+    fetch(0);
+    for (int d = 0; d < kVOffsets; ++d) {
+        __syncthreads();   // every wave is done with the previous offset's B
+#pragma unroll
+        for (int i = 0; i < GMAX; ++i) {
+            if (i < KB) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
+            }
         }
         __syncthreads();
-        // gather: 4 threads per target column, contiguous k
-        {
-            const int j = tid >> 2, part = tid & 3;
-            const int me = s_src[j];
-            const T* src = A.me + (size_t)(me < 0 ? 0 : me) * KP;
-            for (int k = part; k < KP; k += 4) Bs[k * NTP + j] = (me >= 0) ? src[k] : T(0);
-        }
-        __syncthreads();
+        const int op = A.optab[fl.optab_off + codes[d]];
+        if (d + 1 < kVOffsets) fetch(d + 1);   // next offset's sources load during this offset's products
         const T* Aw = A.pool_swz + (size_t)A.swz_index[op] * KP * KP;
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+        V4 an[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            int rbg = w * RB + rb;
+            an[rb] = (rbg < KB) ? *reinterpret_cast<const V4*>(Aw + ((size_t)rbg * KB * 64 + l) * 4) : V4{0, 0, 0, 0};
+        }
         for (int s4 = 0; s4 < KB; ++s4) {
             V4 a4[RB];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb) {
+                a4[rb] = an[rb];
                 int rbg = w * RB + rb;
-                if (rbg < KB) a4[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4) * 64 + l) * 4);
-                else a4[rb] = V4{0, 0, 0, 0};
+                if (rbg < KB && s4 + 1 < KB)
+                    an[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4 + 1) * 64 + l) * 4);
             }
 #pragma unroll
             for (int ss = 0; ss < 4; ++ss) {
@@ -379,15 +421,10 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double h = A.tl_h[leaf];
     T* gl = reinterpret_cast<T*>(smem_raw);                       // [p+1][CH]
-    __shared__ double inv_ith[LPB_MAX_P + 1];
     const int lane = threadIdx.x;
-    if (lane == 0) {
-        double t[LPB_MAX_P + 2];
-        itilde_all(p, F.lam_t * F.lam_t * h * h, t);
-        for (int n = 0; n <= p; ++n) inv_ith[n] = 1.0 / t[n];
-    }
-    __syncthreads();
     if (lane >= CH) return;
+    const double* __restrict__ tb = A.bes_tab;
+    const double* __restrict__ ith = A.ith_t + ((size_t)A.tl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
     const T* __restrict__ Ls = A.le + (size_t)le * A.KP;
     const T* __restrict__ amm_t = A.sh_amm;
     const T* __restrict__ al_t = A.sh_alpha;
@@ -397,17 +434,7 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
     for (int j = t0 + lane; j < t1; j += CH) {
         T ux = A.t_ux[j], uy = A.t_uy[j], uz = A.t_uz[j];
         double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
-        {
-            double t = F.lam_t * F.lam_t * r2d;
-            double a = itilde_series(p + 1, t), bb = itilde_series(p, t);
-            gl[(size_t)p * CH + lane] = (T)(bb * inv_ith[p]);
-            for (int n = p; n >= 1; --n) {
-                double c = bb + t * a / ((2.0 * n + 1.0) * (2.0 * n + 3.0));
-                gl[(size_t)(n - 1) * CH + lane] = (T)(c * inv_ith[n - 1]);
-                a = bb;
-                bb = c;
-            }
-        }
+        bessel_ratio_col<T>(p, F.lam_t * F.lam_t * r2d, tb, ith, T(1), gl + lane, CH);
         T x = ux * hinv, y = uy * hinv, z = uz * hinv;
         T r2 = x * x + y * y + z * z;
         T wr = T(1), wi = T(0);
@@ -445,60 +472,75 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
 // ---------------------------------------------------------------------------
 // Free-space near field (eq. freereactioncomponents, j != i):
 //   Phi_i += sum_{j in U(i), j != i} q_j e^{-lam r}/(4 pi eps r)
-// One 64-lane block per target leaf; lanes own targets, sources staged in LDS.
-// FP32 sums use Kahan compensation.
+// (the self term is the pair at distance 0; charges must be distinct points)
+// One 64-lane block per target leaf.  All U-list sources (up to 1024 at a
+// time) are staged in LDS with their offset from the target leaf centre;
+// two lanes share a target and split the sources, and combine at the end.
+// FP32: hardware exp2/rsqrt and Kahan-compensated sums.
+__device__ inline float pair_kernel(float r2, float lam_log2e) { float ri = __frsqrt_rn(r2); return exp2f(-lam_log2e * (r2 * ri)) * ri; }
+__device__ inline double pair_kernel(double r2, double lam) { double r = sqrt(r2); return exp(-lam * r) / r; }
+
 template <typename T>
 __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
 {
-    __shared__ T sx[64], sy[64], sz[64], sq[64];
-    __shared__ int sc[64];
+    constexpr int SMAX = 512;
+    __shared__ T sx[SMAX], sy[SMAX], sz[SMAX], sq[SMAX];
     const int leaf = A.p2p_free_leaves[blockIdx.x];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
-    const T lam = (T)F.lam_t;
+    const T lamk = (sizeof(T) == 4) ? (T)(F.lam_t * 1.4426950408889634) : (T)F.lam_t;
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
-    for (int base = t0; base < t1; base += 64) {
-        int j = base + threadIdx.x;
+    const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
+    const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
+    for (int base = t0; base < t1; base += 32) {
+        int j = base + tl;
         bool act = j < t1;
         T x = act ? A.t_ux[j] : T(0), y = act ? A.t_uy[j] : T(0), z = act ? A.t_uz[j] : T(0);
-        int ci = act ? A.t_cidx[j] : -1;
         T sum = T(0), comp = T(0);
-        for (int k = A.p2p_ptr[leaf]; k < A.p2p_ptr[leaf + 1]; ++k) {
-            int sl = A.p2p_src[k];
-            // offset of the source leaf centre from the target leaf centre
-            T ox = (T)(A.sl_ctr[3 * sl] - tcx), oy = (T)(A.sl_ctr[3 * sl + 1] - tcy), oz = (T)(A.sl_ctr[3 * sl + 2] - tcz);
-            const int s0 = A.sl_start[sl], s1 = A.sl_start[sl + 1];
-            for (int sb = s0; sb < s1; sb += 64) {
-                int s = sb + threadIdx.x;
-                __syncthreads();
-                if (s < s1) {
-                    sx[threadIdx.x] = A.s_ux[s] + ox;
-                    sy[threadIdx.x] = A.s_uy[s] + oy;
-                    sz[threadIdx.x] = A.s_uz[s] + oz;
-                    sq[threadIdx.x] = A.qs[s];
-                    sc[threadIdx.x] = A.s_cidx[s];
+        int k = k0, s = (k0 < k1) ? A.sl_start[A.p2p_src[k0]] : 0;
+        while (k < k1) {
+            // stage up to SMAX sources, continuing across source leaves
+            int n = 0;
+            __syncthreads();
+            while (k < k1 && n < SMAX) {
+                int sl = A.p2p_src[k];
+                int se = A.sl_start[sl + 1];
+                int take = min(se - s, SMAX - n);
+                T ox = (T)(A.sl_ctr[3 * sl] - tcx), oy = (T)(A.sl_ctr[3 * sl + 1] - tcy), oz = (T)(A.sl_ctr[3 * sl + 2] - tcz);
+                for (int i = lane; i < take; i += 64) {
+                    sx[n + i] = A.s_ux[s + i] + ox;
+                    sy[n + i] = A.s_uy[s + i] + oy;
+                    sz[n + i] = A.s_uz[s + i] + oz;
+                    sq[n + i] = A.qs[s + i];
                 }
-                __syncthreads();
-                int cnt = min(64, s1 - sb);
-                if (act) {
-                    for (int jj = 0; jj < cnt; ++jj) {
-                        T dx = x - sx[jj], dy = y - sy[jj], dz = z - sz[jj];
-                        T r2 = dx * dx + dy * dy + dz * dz;
-                        T ri = (sc[jj] == ci) ? T(0) : T(1) / sqrt(r2);
-                        T v = sq[jj] * exp(-lam * (r2 * ri)) * ri;
-                        if (sizeof(T) == 4) {
-                            T yk = v - comp;
-                            T tk = sum + yk;
-                            comp = (tk - sum) - yk;
-                            sum = tk;
-                        } else {
-                            sum += v;
-                        }
+                n += take;
+                s += take;
+                if (s >= se) {
+                    ++k;
+                    if (k < k1) s = A.sl_start[A.p2p_src[k]];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                for (int jj = half; jj < n; jj += 2) {
+                    T dx = x - sx[jj], dy = y - sy[jj], dz = z - sz[jj];
+                    T r2 = dx * dx + dy * dy + dz * dz;
+                    // the target itself (r = 0) is the only coincident source of a free-space FMM
+                    T v = (r2 > T(0)) ? sq[jj] * pair_kernel(r2, lamk) : T(0);
+                    if (sizeof(T) == 4) {
+                        T yk = v - comp;
+                        T tk = sum + yk;
+                        comp = (tk - sum) - yk;
+                        sum = tk;
+                    } else {
+                        sum += v;
                     }
                 }
             }
         }
-        if (act) A.parts[A.t_out[j]] += (double)sum / (4.0 * LPB_PI * F.eps_t);
+        // combine the two halves (lane l and l+32 share a target)
+        T other = __shfl_xor(sum - comp, 32, 64);
+        if (act && half == 0) A.parts[A.t_out[j]] += ((double)(sum - comp) + (double)other) / (4.0 * LPB_PI * F.eps_t);
     }
 }
 

@@ -34,7 +34,7 @@ namespace lpb {
 LPB_HD double itilde_series(int n, double t)
 {
     double term = 1.0, sum = 1.0;
-    for (int k = 1; k < 200; ++k) {
+    for (int k = 1; k < 4000; ++k) {
         term *= 0.5 * t / ((double)k * (2.0 * n + 2.0 * k + 1.0));
         sum += term;
         if (term <= 1e-17 * sum) break;
