@@ -76,7 +76,8 @@ def cpu_baseline(per_layer, p, leaf_cap):
 
     prob = inputs.three_layer(per_layer, seed=0)
     ly = oracle.Layers(prob.eps, prob.lam, prob.d)
-    cores = os.cpu_count() or 1
+    # the host share of one GPU is at most 16 threads, whatever the machine reports
+    cores = max(1, min(16, len(os.sched_getaffinity(0))))
     t0 = time.perf_counter()
     oracle.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=leaf_cap, nthreads=cores)
     dt = time.perf_counter() - t0
@@ -94,8 +95,10 @@ def main():
     ap.add_argument("--p", type=int, default=10)
     ap.add_argument("--leaf-cap", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample-per-layer", type=int, default=10_000)
+    ap.add_argument("--cpu-sample-per-layer", type=int, default=200_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path would shard by "
@@ -107,6 +110,15 @@ def main():
     from paper_2002_01334_amd import inputs, lpb
 
     lpb.load()
+    if args.calib_copy_mib > 0:
+        n = args.calib_copy_mib * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr, flush=True)
+        del src, dst
     prob = inputs.three_layer(args.per_layer, seed=0)
     print(f"[bench] workload: 3 layers, {prob.n} charges, p={args.p}", file=sys.stderr, flush=True)
     mixed = time_context(lpb, torch, prob, args.p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup)
