@@ -1044,9 +1044,12 @@ static void box_center(double cx, double cy, double cz, double R, int level, int
     c[2] = (cz - R) + (iz + 0.5) * h;
 }
 
+/* pre_s, pre_t: fine cells of the sources and targets (computed here from the
+ * coordinates and the root cube when NULL); Hfix >= 0 imposes the depth. */
 static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx, const double* sy, const double* sz,
                    const double* sq, const int64_t* sid, int nt, const double* tx, const double* ty,
                    const double* tz, const int64_t* tid, double cx, double cy, double cz, double R,
+                   const cells_t* pre_s, const cells_t* pre_t, int Hfix,
                    const gaunt_tab_t* GT, const ctab_t* CT, double* phi, fmmstat_t* st)
 {
     int K = (p + 1) * (p + 1);
@@ -1063,21 +1066,22 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
     Ct.cy = Ct.cx + nt;
     Ct.cz = Ct.cy + nt;
     for (int i = 0; i < ns; ++i) {
-        Cs.cx[i] = fine_cell(sx[i], cx, R);
-        Cs.cy[i] = fine_cell(sy[i], cy, R);
-        Cs.cz[i] = fine_cell(sz[i], cz, R);
+        Cs.cx[i] = pre_s ? pre_s->cx[i] : fine_cell(sx[i], cx, R);
+        Cs.cy[i] = pre_s ? pre_s->cy[i] : fine_cell(sy[i], cy, R);
+        Cs.cz[i] = pre_s ? pre_s->cz[i] : fine_cell(sz[i], cz, R);
     }
     for (int i = 0; i < nt; ++i) {
-        Ct.cx[i] = fine_cell(tx[i], cx, R);
-        Ct.cy[i] = fine_cell(ty[i], cy, R);
-        Ct.cz[i] = fine_cell(tz[i], cz, R);
+        Ct.cx[i] = pre_t ? pre_t->cx[i] : fine_cell(tx[i], cx, R);
+        Ct.cy[i] = pre_t ? pre_t->cy[i] : fine_cell(ty[i], cy, R);
+        Ct.cz[i] = pre_t ? pre_t->cz[i] : fine_cell(tz[i], cz, R);
     }
     boxlev_t SB[ORC_MAXDEPTH + 1], TB[ORC_MAXDEPTH + 1];
     int H = -1;
     for (int l = 0; l <= ORC_MAXDEPTH; ++l) {
         distinct_boxes(&Cs, l, &SB[l]);
         distinct_boxes(&Ct, l, &TB[l]);
-        if ((long long)ns <= (long long)cap * SB[l].nb && (long long)nt <= (long long)cap * TB[l].nb) {
+        if (Hfix >= 0 ? l == Hfix
+                      : ((long long)ns <= (long long)cap * SB[l].nb && (long long)nt <= (long long)cap * TB[l].nb)) {
             H = l;
             break;
         }
@@ -1406,10 +1410,8 @@ int orc_component(int nlayers, int c, int* out)
     return -1;
 }
 
-/* Root cube of a component: free -> the bounding cube of the layer's
- * charges; reaction -> centred (in z) on the interface between targets and
- * images (Sec. 3.5: the largest box is divided in half by the interface),
- * centred in x,y on the bounding box of targets and sources. */
+/* Root cube of a free-space component: the bounding cube of the layer's
+ * charges. */
 static void root_free(int n, const double* x, const double* y, const double* z, double* c, double* R)
 {
     double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -1428,31 +1430,106 @@ static void root_free(int n, const double* x, const double* y, const double* z, 
     *R = r > 0 ? r : 0.5;
 }
 
-static void root_reaction(int nt, const double* tx, const double* ty, const double* tz, int ns, const double* sx,
-                          const double* sy, const double* sz_img, double zi, double* c, double* R)
+/* Common grid of the reaction components of one medium.  In the frame of a
+ * reaction component whose interface is z = 0 with the targets above it
+ * (mirrored in z when the interface is the upper one, a = 2), every target
+ * sits at height tau_a of its own layer and every equivalent source at depth
+ * -tau'_b of its layer (eq. equivpolarcoord), independently of the other
+ * layer of the component.  One root cube and one depth therefore serve all
+ * of them (Sec. 3.5: the largest box is halved by the interface):
+ *   centre x, y: middle of the bounding box of all charges; z: the interface;
+ *   half side R: the largest of the half x and y extents and of every
+ *     distance tau of a charge to an interface of its own layer;
+ *   depth: the smallest l <= 12 at which every point set (layer, side) with
+ *     N charges, placed at +tau (targets) and at -tau (images), has
+ *     N <= cap * (non-empty boxes at level l).
+ * Cells: fine_cell(x, cx, R), fine_cell(y, cy, R), fine_cell(+-tau, 0, R);
+ * for a = 2 the z cell is mirrored (65535 - c) into the original orientation. */
+typedef struct {
+    double cx, cy, R;
+    int H;
+} rgrid_t;
+
+static int side_valid(const layers_t* Ly, int l, int s) { return s == 1 ? l < Ly->L : l > 0; }
+
+static void reaction_grid(const layers_t* Ly, int64_t n, const double* x, const double* y, const double* z,
+                          const int* lay, int cap, rgrid_t* G)
 {
-    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
-    double r = 0.0;
-    for (int i = 0; i < nt; ++i) {
-        lo[0] = fmin(lo[0], tx[i]);
-        hi[0] = fmax(hi[0], tx[i]);
-        lo[1] = fmin(lo[1], ty[i]);
-        hi[1] = fmax(hi[1], ty[i]);
-        r = fmax(r, fabs(tz[i] - zi));
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, r = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        lo[0] = fmin(lo[0], x[i]);
+        hi[0] = fmax(hi[0], x[i]);
+        lo[1] = fmin(lo[1], y[i]);
+        hi[1] = fmax(hi[1], y[i]);
+        for (int sd = 1; sd <= 2; ++sd)
+            if (side_valid(Ly, lay[i], sd)) r = fmax(r, fabs(tau_s(Ly, lay[i], sd, z[i])));
     }
-    for (int i = 0; i < ns; ++i) {
-        lo[0] = fmin(lo[0], sx[i]);
-        hi[0] = fmax(hi[0], sx[i]);
-        lo[1] = fmin(lo[1], sy[i]);
-        hi[1] = fmax(hi[1], sy[i]);
-        r = fmax(r, fabs(sz_img[i] - zi));
-    }
-    c[0] = 0.5 * (lo[0] + hi[0]);
-    c[1] = 0.5 * (lo[1] + hi[1]);
-    c[2] = zi;
+    G->cx = 0.5 * (lo[0] + hi[0]);
+    G->cy = 0.5 * (lo[1] + hi[1]);
     r = fmax(r, 0.5 * (hi[0] - lo[0]));
     r = fmax(r, 0.5 * (hi[1] - lo[1]));
-    *R = r > 0 ? r : 0.5;
+    G->R = r > 0 ? r : 0.5;
+    G->H = 0;
+    /* depth: every (layer, side) set, as targets (+tau) and as images (-tau) */
+    for (int l = 0; l <= Ly->L; ++l)
+        for (int sd = 1; sd <= 2; ++sd) {
+            if (!side_valid(Ly, l, sd)) continue;
+            int m = 0;
+            for (int64_t i = 0; i < n; ++i) m += lay[i] == l;
+            if (m == 0) continue;
+            for (int sg = -1; sg <= 1; sg += 2) {
+                cells_t C;
+                C.n = m;
+                C.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * m);
+                C.cy = C.cx + m;
+                C.cz = C.cy + m;
+                int k = 0;
+                for (int64_t i = 0; i < n; ++i)
+                    if (lay[i] == l) {
+                        C.cx[k] = fine_cell(x[i], G->cx, G->R);
+                        C.cy[k] = fine_cell(y[i], G->cy, G->R);
+                        C.cz[k++] = fine_cell(sg * tau_s(Ly, l, sd, z[i]), 0.0, G->R);
+                    }
+                int lv = 0;
+                for (; lv < ORC_MAXDEPTH; ++lv) {
+                    boxlev_t B;
+                    distinct_boxes(&C, lv, &B);
+                    int ok = (long long)m <= (long long)cap * B.nb;
+                    free(B.key);
+                    if (ok) break;
+                }
+                if (lv > G->H) G->H = lv;
+                free(C.cx);
+            }
+        }
+}
+
+/* Fine cells of the targets (layer l, side a) and images (layer lp, side b)
+ * of a reaction component on the common grid, in the original orientation. */
+static void reaction_cells(const layers_t* Ly, const rgrid_t* G, int l, int lp, int a, int b, int nt,
+                           const double* tx, const double* ty, const double* tz, int ns, const double* sx,
+                           const double* sy, const double* sz_orig, cells_t* Ct, cells_t* Cs)
+{
+    Ct->n = nt;
+    Ct->cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (nt + 1));
+    Ct->cy = Ct->cx + nt;
+    Ct->cz = Ct->cy + nt;
+    Cs->n = ns;
+    Cs->cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (ns + 1));
+    Cs->cy = Cs->cx + ns;
+    Cs->cz = Cs->cy + ns;
+    for (int i = 0; i < nt; ++i) {
+        Ct->cx[i] = fine_cell(tx[i], G->cx, G->R);
+        Ct->cy[i] = fine_cell(ty[i], G->cy, G->R);
+        uint32_t c = fine_cell(tau_t(Ly, l, a, tz[i]), 0.0, G->R);
+        Ct->cz[i] = (a == 2) ? 65535u - c : c;
+    }
+    for (int i = 0; i < ns; ++i) {
+        Cs->cx[i] = fine_cell(sx[i], G->cx, G->R);
+        Cs->cy[i] = fine_cell(sy[i], G->cy, G->R);
+        uint32_t c = fine_cell(-tau_s(Ly, lp, b, sz_orig[i]), 0.0, G->R);
+        Cs->cz[i] = (a == 2) ? 65535u - c : c;
+    }
 }
 
 /* Full layered FMM (Algorithm 2).  phi[n] receives the potential at every
@@ -1478,6 +1555,9 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
     if (comp_phi) memset(comp_phi, 0, sizeof(double) * n * ncomp);
     gaunt_tab_t GT;
     gaunt_tab_init(&GT, p);
+    rgrid_t G;
+    memset(&G, 0, sizeof(G));
+    if (Ly.L > 0) reaction_grid(&Ly, n, x, y, z, lay, leaf_cap, &G);
     for (int c = 0; c < ncomp; ++c) {
         int desc[5];
         orc_component(nlayers, c, desc);
@@ -1488,9 +1568,10 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
             if (lay[i] == l) nt++;
             if (lay[i] == lp) ns++;
         }
-        double* buf = (double*)malloc(sizeof(double) * (3 * nt + 4 * ns + nt + 1));
+        double* buf = (double*)malloc(sizeof(double) * (3 * nt + 5 * ns + nt + 1));
         double *tx = buf, *ty = tx + nt, *tz = ty + nt, *sx = tz + nt, *sy = sx + ns, *sz = sy + ns, *sq = sz + ns;
         double* ph = sq + ns;
+        double* szo = ph + nt;   /* sources' own z */
         int64_t* tid = (int64_t*)malloc(sizeof(int64_t) * (nt + ns + 1));
         int64_t* sid = tid + nt;
         int it = 0, is = 0;
@@ -1506,6 +1587,7 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
             if (lay[i] == lp) {
                 sx[is] = x[i];
                 sy[is] = y[i];
+                szo[is] = z[i];
                 if (kind == 0) sz[is] = z[i];
                 else {
                     /* equivalent polarization coordinate (eq. equivpolarcoord, with the
@@ -1531,15 +1613,26 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
         /* free space: e^{-lam r}/(4 pi eps r) = (lam / (2 pi^2 eps)) k_0(lam r) */
         F.far_factor = (kind == 0) ? Ly.lam[l] / (2.0 * ORC_PI * ORC_PI * Ly.eps[l]) : 1.0;
         double ctr[3], R;
+        cells_t Cs, Ct;
+        Cs.cx = Ct.cx = NULL;
         if (kind == 0) root_free(nt, tx, ty, tz, ctr, &R);
-        else root_reaction(nt, tx, ty, tz, ns, sx, sy, sz, zi, ctr, &R);
+        else {
+            ctr[0] = G.cx;
+            ctr[1] = G.cy;
+            ctr[2] = zi;
+            R = G.R;
+            reaction_cells(&Ly, &G, l, lp, a, b, nt, tx, ty, tz, ns, sx, sy, szo, &Ct, &Cs);
+        }
         ctab_t CT;
         CT.v = NULL;
         if (kind == 1) ctab_init(&CT, p, Ly.lam[l], Ly.lam[lp]);
         fmmstat_t st;
-        run_fmm(&F, p, leaf_cap, ns, sx, sy, sz, sq, sid, nt, tx, ty, tz, tid, ctr[0], ctr[1], ctr[2], R, &GT,
+        run_fmm(&F, p, leaf_cap, ns, sx, sy, sz, sq, sid, nt, tx, ty, tz, tid, ctr[0], ctr[1], ctr[2], R,
+                kind == 1 ? &Cs : NULL, kind == 1 ? &Ct : NULL, kind == 1 ? G.H : -1, &GT,
                 kind == 1 ? &CT : NULL, ph, &st);
         if (CT.v) free(CT.v);
+        free(Cs.cx);
+        free(Ct.cx);
         for (int k = 0; k < nt; ++k) {
             phi[tid[k]] += ph[k];
             if (comp_phi) comp_phi[(size_t)c * n + tid[k]] = ph[k];
@@ -1780,10 +1873,12 @@ int orc_component_tree(int nlayers, const double* eps, const double* lam, const 
     if (orc_component(nlayers, comp, desc)) return -1;
     int kind = desc[0], l = desc[1], lp = desc[2], a = desc[3], b = desc[4];
     int nt = 0, ns = 0;
-    double* buf = (double*)malloc(sizeof(double) * 6 * (n + 1));
-    double *tx = buf, *ty = tx + n, *tz = ty + n, *sx = tz + n, *sy = sx + n, *sz = sy + n;
+    double* buf = (double*)malloc(sizeof(double) * 7 * (n + 1));
+    double *tx = buf, *ty = tx + n, *tz = ty + n, *sx = tz + n, *sy = sx + n, *sz = sy + n, *szo = sz + n;
+    int* lay = (int*)malloc(sizeof(int) * (n + 1));
     for (int64_t i = 0; i < n; ++i) {
         int li = layer_of(&Ly, z[i]);
+        lay[i] = li;
         if (li == l) {
             tx[nt] = x[i];
             ty[nt] = y[i];
@@ -1792,6 +1887,7 @@ int orc_component_tree(int nlayers, const double* eps, const double* lam, const 
         if (li == lp) {
             sx[ns] = x[i];
             sy[ns] = y[i];
+            szo[ns] = z[i];
             if (kind == 0) sz[ns] = z[i];
             else {
                 double ts = tau_s(&Ly, lp, b, z[i]);
@@ -1801,40 +1897,51 @@ int orc_component_tree(int nlayers, const double* eps, const double* lam, const 
         }
     }
     double c[3], R;
-    if (kind == 0) root_free(nt, tx, ty, tz, c, &R);
-    else root_reaction(nt, tx, ty, tz, ns, sx, sy, sz, (a == 1) ? Ly.d[l] : Ly.d[l - 1], c, &R);
     cells_t Cs, Ct;
-    Cs.n = ns;
-    Ct.n = nt;
-    Cs.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (ns + 1));
-    Cs.cy = Cs.cx + ns;
-    Cs.cz = Cs.cy + ns;
-    Ct.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (nt + 1));
-    Ct.cy = Ct.cx + nt;
-    Ct.cz = Ct.cy + nt;
-    for (int i = 0; i < ns; ++i) {
-        Cs.cx[i] = fine_cell(sx[i], c[0], R);
-        Cs.cy[i] = fine_cell(sy[i], c[1], R);
-        Cs.cz[i] = fine_cell(sz[i], c[2], R);
-    }
-    for (int i = 0; i < nt; ++i) {
-        Ct.cx[i] = fine_cell(tx[i], c[0], R);
-        Ct.cy[i] = fine_cell(ty[i], c[1], R);
-        Ct.cz[i] = fine_cell(tz[i], c[2], R);
-    }
     int H = ORC_MAXDEPTH;
-    for (int lv = 0; lv <= ORC_MAXDEPTH; ++lv) {
-        boxlev_t SB, TB;
-        distinct_boxes(&Cs, lv, &SB);
-        distinct_boxes(&Ct, lv, &TB);
-        int ok = (long long)ns <= (long long)leaf_cap * SB.nb && (long long)nt <= (long long)leaf_cap * TB.nb;
-        free(SB.key);
-        free(TB.key);
-        if (ok) {
-            H = lv;
-            break;
+    if (kind == 0) {
+        root_free(nt, tx, ty, tz, c, &R);
+        Cs.n = ns;
+        Ct.n = nt;
+        Cs.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (ns + 1));
+        Cs.cy = Cs.cx + ns;
+        Cs.cz = Cs.cy + ns;
+        Ct.cx = (uint32_t*)malloc(sizeof(uint32_t) * 3 * (nt + 1));
+        Ct.cy = Ct.cx + nt;
+        Ct.cz = Ct.cy + nt;
+        for (int i = 0; i < ns; ++i) {
+            Cs.cx[i] = fine_cell(sx[i], c[0], R);
+            Cs.cy[i] = fine_cell(sy[i], c[1], R);
+            Cs.cz[i] = fine_cell(sz[i], c[2], R);
         }
+        for (int i = 0; i < nt; ++i) {
+            Ct.cx[i] = fine_cell(tx[i], c[0], R);
+            Ct.cy[i] = fine_cell(ty[i], c[1], R);
+            Ct.cz[i] = fine_cell(tz[i], c[2], R);
+        }
+        for (int lv = 0; lv <= ORC_MAXDEPTH; ++lv) {
+            boxlev_t SB, TB;
+            distinct_boxes(&Cs, lv, &SB);
+            distinct_boxes(&Ct, lv, &TB);
+            int ok = (long long)ns <= (long long)leaf_cap * SB.nb && (long long)nt <= (long long)leaf_cap * TB.nb;
+            free(SB.key);
+            free(TB.key);
+            if (ok) {
+                H = lv;
+                break;
+            }
+        }
+    } else {
+        rgrid_t G;
+        reaction_grid(&Ly, n, x, y, z, lay, leaf_cap, &G);
+        c[0] = G.cx;
+        c[1] = G.cy;
+        c[2] = (a == 1) ? Ly.d[l] : Ly.d[l - 1];
+        R = G.R;
+        H = G.H;
+        reaction_cells(&Ly, &G, l, lp, a, b, nt, tx, ty, tz, ns, sx, sy, szo, &Ct, &Cs);
     }
+    free(lay);
     int sh = ORC_HMAX - H;
     for (int i = 0; i < nt; ++i) tkeys[i] = morton_key(Ct.cx[i] >> sh, Ct.cy[i] >> sh, Ct.cz[i] >> sh, H);
     for (int i = 0; i < ns; ++i) skeys[i] = morton_key(Cs.cx[i] >> sh, Cs.cy[i] >> sh, Cs.cz[i] >> sh, H);

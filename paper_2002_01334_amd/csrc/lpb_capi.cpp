@@ -279,6 +279,9 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(m2l_op, P.m2l_op);
     UP(p2p_ptr, P.p2p_ptr);
     UP(p2p_src, P.p2p_src);
+    UP(rp_ptr, P.rp_ptr);
+    UP(rp_fmm, P.rp_fmm);
+    UP(rp_src, P.rp_src);
     UP(tiles, P.tiles);
     UP(tfl, P.tfl);
     UP(grid_me, P.grid_me);
@@ -336,10 +339,8 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
         if (P.sl_me[i] >= 0) p2m.push_back((int)i);
     for (size_t i = 0; i < P.tl_le.size(); ++i) {
         if (P.tl_le[i] >= 0) l2p.push_back((int)i);
-        bool has_u = P.p2p_ptr[i + 1] > P.p2p_ptr[i];
-        if (!has_u) continue;
-        if (P.fmm[P.tl_fmm[i]].kind == 0) pfree.push_back((int)i);
-        else
+        if (P.p2p_ptr[i + 1] > P.p2p_ptr[i]) pfree.push_back((int)i);
+        if (P.rp_ptr[i + 1] > P.rp_ptr[i])
             for (int j = P.tl_start[i]; j < P.tl_start[i + 1]; ++j) {
                 rleaf.push_back((int)i);
                 rslot.push_back(j);
@@ -736,18 +737,18 @@ lpb_status lpb_fmm_info(const lpb_ctx* c, int sys, int fmm, int* desc, double* r
     if (root) { root[0] = F.cx; root[1] = F.cy; root[2] = F.cz; root[3] = F.R; }
     if (nt) *nt = F.ntgt;
     if (ns) *ns = F.nsrc;
-    // point ranges of this FMM: leaves are contiguous per FMM
-    auto gather = [&](const std::vector<int>& lfmm, const std::vector<int>& lstart, const std::vector<int>& cidx,
-                      const std::vector<uint64_t>& okey, uint64_t* out) {
+    // leaf keys of the points of this FMM's trees (leaves are contiguous per
+    // tree), in the FMM's original orientation, ordered by charge index
+    auto gather = [&](const TreeDesc& T, const std::vector<int>& lstart, const std::vector<int>& cidx,
+                      const std::vector<uint64_t>& lcell, uint64_t* out) {
         std::vector<std::pair<int, uint64_t>> v;
-        for (size_t l = 0; l < lfmm.size(); ++l)
-            if (lfmm[l] == found)
-                for (int j = lstart[l]; j < lstart[l + 1]; ++j) v.push_back({cidx[j], okey[j]});
+        for (int l = T.leaf0; l < T.leaf0 + T.nleaf; ++l)
+            for (int j = lstart[l]; j < lstart[l + 1]; ++j) v.push_back({cidx[j], leaf_key(lcell[j], F.H, F.flip)});
         std::sort(v.begin(), v.end());
         for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].second;
     };
-    if (tkeys) gather(P.tl_fmm, P.tl_start, P.t_cidx, P.t_okey, tkeys);
-    if (skeys) gather(P.sl_fmm, P.sl_start, P.s_cidx, P.s_okey, skeys);
+    if (tkeys) gather(P.trees[F.tgt_tree], P.tl_start, P.t_cidx, P.t_lcell, tkeys);
+    if (skeys) gather(P.trees[F.src_tree], P.sl_start, P.s_cidx, P.s_lcell, skeys);
     return LPB_OK;
 }
 

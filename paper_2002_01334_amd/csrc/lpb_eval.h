@@ -35,6 +35,7 @@ struct EvalArgs {
     const int *l2l_child, *l2l_parent, *l2l_op;
     const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;
     const int *p2p_ptr, *p2p_src;
+    const int *rp_ptr, *rp_fmm, *rp_src;   // reaction near field: per target leaf, (FMM, source leaf)
     int n_react_targets;
     const int *react_tgt_leaf, *react_tgt_slot;
     const double *gl_x, *gl_w;

@@ -549,7 +549,8 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
 //   u~ = (1/4pi) int_0^inf lrho J_0(lrho rho) e^{-l_z zt + l'_z zs} sigma(lrho) / l_z dlrho
 // (canonical frame: zt > 0 target height, zs < 0 image depth), by composite
 // 20-point Gauss-Legendre on panels chosen as for the M2L initial values.
-// FP64 always.  One thread per target.
+// FP64 always.  One thread per target, over the (component, source leaf)
+// pairs of its leaf (every component of the leaf's target tree).
 template <typename T>
 __global__ void k_p2p_react(EvalArgs<T> A)
 {
@@ -557,21 +558,21 @@ __global__ void k_p2p_react(EvalArgs<T> A)
     if (idx >= A.n_react_targets) return;
     const int leaf = A.react_tgt_leaf[idx];
     const int j = A.react_tgt_slot[idx];
-    const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
-    const Medium& Md = A.media[F.medium];
-    double lmin = Md.lam[0], dmax = 0.0;
-    for (int k = 1; k <= Md.L; ++k) lmin = fmin(lmin, Md.lam[k]);
-    for (int k = 1; k < Md.L; ++k) dmax = fmax(dmax, Md.d[k - 1] - Md.d[k]);
-    double w0 = lmin;
-    if (dmax > 0.0 && LPB_PI / (2.0 * dmax) < w0) w0 = LPB_PI / (2.0 * dmax);
     const double tx = A.tl_ctr[3 * leaf] + (double)A.t_ux[j];
     const double ty = A.tl_ctr[3 * leaf + 1] + (double)A.t_uy[j];
     const double tz = A.tl_ctr[3 * leaf + 2] + (double)A.t_uz[j];
-    const double lt = F.lam_t, ls = F.lam_s;
     const double lt_tol = log(A.quad_tol);
     double total = 0.0;
-    for (int k = A.p2p_ptr[leaf]; k < A.p2p_ptr[leaf + 1]; ++k) {
-        int sl = A.p2p_src[k];
+    for (int k = A.rp_ptr[leaf]; k < A.rp_ptr[leaf + 1]; ++k) {
+        const FmmDev& F = A.fmm[A.rp_fmm[k]];
+        const Medium& Md = A.media[F.medium];
+        double lmin = Md.lam[0], dmax = 0.0;
+        for (int kk = 1; kk <= Md.L; ++kk) lmin = fmin(lmin, Md.lam[kk]);
+        for (int kk = 1; kk < Md.L; ++kk) dmax = fmax(dmax, Md.d[kk - 1] - Md.d[kk]);
+        double w0 = lmin;
+        if (dmax > 0.0 && LPB_PI / (2.0 * dmax) < w0) w0 = LPB_PI / (2.0 * dmax);
+        const double lt = F.lam_t, ls = F.lam_s;
+        int sl = A.rp_src[k];
         for (int s = A.sl_start[sl]; s < A.sl_start[sl + 1]; ++s) {
             double sxp = A.sl_ctr[3 * sl] + (double)A.s_ux[s];
             double syp = A.sl_ctr[3 * sl + 1] + (double)A.s_uy[s];
@@ -623,7 +624,6 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
 #define LPB_MARK(k) \
     if (ev) (void)hipEventRecord(ev[k], st)
     const int K = A.K, p = A.p;
-    const int Kp = (p + 1) * (p + 2) / 2;
     const int bsz = ((K + 63) / 64) * 64;
     LPB_MARK(0);
     if (A.n_src > 0) hipLaunchKernelGGL(k_gather_q<T>, dim3((A.n_src + 255) / 256), dim3(256), 0, st, A.n_src, A.s_cidx, A.q, A.qs);

@@ -34,10 +34,21 @@ struct FmmDesc {
     double far_factor;        // multiplies the far field (free space: lam/(2 pi^2 eps))
     double eps_t;             // eps of the target layer (free-space near field)
     int slot;                 // output slot of this FMM's targets
-    int me_off[kMaxDepth + 1], me_cnt[kMaxDepth + 1];   // ME boxes of each level (global index range)
-    int le_off[kMaxDepth + 1], le_cnt[kMaxDepth + 1];
+    int me_off[kMaxDepth + 1];   // first ME box of each level (global index), -1 below level 2
+    int le_off[kMaxDepth + 1];
     int nsrc, ntgt;
     int layers_id;            // which layered medium (system) for sigma
+    int src_tree, tgt_tree;   // the (possibly shared) trees of its sources and targets
+};
+
+// A point set on its uniform octree: the sources of an FMM (ME boxes) or its
+// targets (LE boxes).  Reaction components share the trees of their
+// (layer, side) sets; the representative FMM lends lambda and root.
+struct TreeDesc {
+    int target;   // 0 source tree, 1 target tree
+    int rep;      // representative FMM
+    int H;
+    int leaf0, nleaf;
 };
 
 // Device-resident description of one medium for the reaction densities.
@@ -98,6 +109,7 @@ struct Plan {
     std::vector<int64_t> sys_charge_off;   // nsys + 1
     std::vector<Medium> media;             // per system
     std::vector<FmmDesc> fmm;
+    std::vector<TreeDesc> trees;
     int nslots = 1;                        // output slots per charge
     int64_t ncharges = 0;
     int max_depth = 0;
@@ -106,14 +118,13 @@ struct Plan {
     std::vector<double> s_u, t_u;          // 3 x n, relative to the leaf centre (canonical frame), SoA
     std::vector<int> t_out;                // index into parts: slot * ncharges + cidx
     // leaves
-    std::vector<int> sl_start, sl_me, sl_fmm, sl_level;   // source leaves (sl_start has n+1)
-    std::vector<int> tl_start, tl_le, tl_fmm;             // target leaves
+    std::vector<int> sl_start, sl_me, sl_fmm, sl_tree;    // source leaves (sl_start has n+1); sl_fmm: representative
+    std::vector<int> tl_start, tl_le, tl_fmm, tl_tree;    // target leaves
     std::vector<double> sl_h, tl_h;                       // leaf box side
     std::vector<double> sl_ctr, tl_ctr;                   // leaf centres (canonical local frame), 3 per leaf
-    std::vector<uint64_t> s_okey, t_okey;                 // leaf Morton key of each point, original frame (diagnostics)
+    std::vector<uint64_t> s_lcell, t_lcell;               // leaf cell of each point (canonical, diagnostics)
     // boxes
     int n_me = 0, n_le = 0;
-    std::vector<int> me_fmm, me_level, le_fmm, le_level;
     // M2M: CSR by parent ME box (levels >= 2), children ME + operator
     std::vector<int> m2m_parent, m2m_ptr, m2m_child, m2m_op;
     std::vector<int> m2m_level_ptr;   // parents of level l at [m2m_level_ptr[l], m2m_level_ptr[l+1])
@@ -122,8 +133,10 @@ struct Plan {
     std::vector<int> l2l_level_ptr;
     // M2L: CSR by target LE box
     std::vector<int> m2l_ptr, m2l_src, m2l_op;   // m2l_ptr has n_le+1
-    // near field: CSR by target leaf over source leaves
+    // near field: CSR by target leaf over free-space source leaves, and over
+    // (reaction FMM, source leaf) pairs
     std::vector<int> p2p_ptr, p2p_src;
+    std::vector<int> rp_ptr, rp_fmm, rp_src;
     int64_t n_p2p_pairs = 0, n_react_p2p_pairs = 0, n_m2l_pairs = 0, n_m2l_tile_pairs = 0;
     // operators
     std::vector<OpDesc> ops;
@@ -152,5 +165,9 @@ inline int layer_of(const Medium& m, double z)
 }
 
 double host_gaunt(int n1, int m1, int n2, int m2, int n3, int m3);
+
+// Morton key at level H of a leaf cell (cellkey packing), with the z cell
+// mirrored when flip < 0 (original orientation of an a = 2 component).
+uint64_t leaf_key(uint64_t lcell, int H, int flip);
 
 }  // namespace lpb

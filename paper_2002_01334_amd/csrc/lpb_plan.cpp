@@ -3,20 +3,24 @@
 // interaction lists and the operator descriptors.
 //
 // Tree rule (identical in meaning to the oracle's, written independently):
-//   root cube: free space -> centre of the bounding box of the layer's
-//     charges, half side = half the largest extent; reaction -> centred in z
-//     on the interface between targets and images (Sec. 3.5: the largest box
-//     is divided in half by that interface), centred in x,y on the bounding
-//     box of targets and sources, half side = max of |z - interface| and the
-//     half x,y extents.
-//   fine cell per axis: floor(((x - c) + R) / (2R) * 65536) clamped to
-//     [0, 65535]; the level-l cell is the fine cell >> (16 - l).
-//   depth H: smallest l (<= 12) with N_src <= cap * (non-empty source boxes at
-//     l) and N_tgt <= cap * (non-empty target boxes at l).
+//   free space: root cube = centre of the bounding box of the layer's
+//     charges, half side = half the largest extent; depth H = smallest l
+//     (<= 12) with N <= cap * (non-empty boxes at l).
+//   reaction components: one grid per medium.  In a component's frame
+//     (interface at z = 0, targets above it, mirrored for a = 2) targets sit
+//     at +tau and images at -tau (distance to an interface of their own
+//     layer).  Root: centre x, y of the bounding box of all charges, z on
+//     the interface (Sec. 3.5: the largest box is halved by it), half side =
+//     max of the half x, y extents and every tau; depth = the largest of the
+//     per-set rule over all (layer, side) sets, as images and as targets.
+//   fine cell per axis: floor((w + R) / (2R) * 65536) clamped to [0, 65535]
+//     with w the canonical coordinate relative to the root centre; the
+//     level-l cell is the fine cell >> (16 - l).
 //   V-list (levels >= 2): source boxes that are children of the neighbours
 //     of the target's parent and not adjacent to the target; U-list at level
 //     H: the target's neighbours and itself.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <unordered_map>
@@ -68,19 +72,9 @@ inline uint64_t cellkey(int ix, int iy, int iz)
 struct Pt {
     uint64_t fkey;   // Morton key of the fine cell (canonical frame)
     uint32_t c[3];   // fine cells (canonical frame)
-    double x, y, z;  // original frame (z = image z for reaction sources)
+    double w[3];     // canonical coordinates relative to the root centre
     int cidx;        // global charge index
-    int local;       // index within the system
 };
-
-bool comp_valid(int L, int l, int lp, int a, int b)
-{
-    if (a == 1 && l >= L) return false;
-    if (a == 2 && l <= 0) return false;
-    if (b == 1 && lp >= L) return false;
-    if (b == 2 && lp <= 0) return false;
-    return true;
-}
 
 struct BoxSet {
     // level-l boxes of one point set: canonical cell coords sorted by Morton key
@@ -89,13 +83,334 @@ struct BoxSet {
     std::unordered_map<uint64_t, int> idx;   // cellkey -> position
 };
 
+// One point set on its uniform octree, as built into the plan.
+struct TreeB {
+    std::vector<BoxSet> B;       // levels 0..H
+    int off[kMaxDepth + 1];      // global ME (source tree) or LE (target tree) index of each level, -1 below 2
+    int leaf0 = 0, nleaf = 0;    // its leaves in sl_* (source) or tl_* (target)
+    int id = -1;                 // index into Plan::trees
+};
+
+// Staging shared by the tree and list builders.
+struct Staging {
+    std::vector<std::vector<std::array<int, 3>>> m2m_by_level{(size_t)kMaxDepth + 1};   // parent, child, op
+    std::vector<std::vector<std::array<int, 3>>> l2l_by_level{(size_t)kMaxDepth + 1};   // child, parent, op
+    std::vector<std::vector<std::pair<int, int>>> m2l_by_le;    // per LE box: (source ME, op)
+    std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: free-space source leaves
+    std::vector<std::vector<std::pair<int, int>>> rp_by_tl;     // per target leaf: (reaction FMM, source leaf)
+    std::vector<double> s_ux, s_uy, s_uz, t_ux, t_uy, t_uz;
+};
+
+inline int count_level(const std::vector<Pt>& V, int lv)
+{
+    int sh = 3 * (kCellBits - lv);
+    int n = V.empty() ? 0 : 1;
+    for (size_t i = 1; i < V.size(); ++i)
+        if ((V[i].fkey >> sh) != (V[i - 1].fkey >> sh)) ++n;
+    return n;
+}
+
+// smallest level (<= kMaxDepth) at which N <= cap * (non-empty boxes); V sorted by fkey
+inline int depth_rule(const std::vector<Pt>& V, int cap)
+{
+    for (int lv = 0; lv < kMaxDepth; ++lv)
+        if ((int64_t)V.size() <= (int64_t)cap * count_level(V, lv)) return lv;
+    return kMaxDepth;
+}
+
+void set_cells(std::vector<Pt>& V, double R)
+{
+    for (auto& q : V) {
+        for (int d = 0; d < 3; ++d) q.c[d] = fine_cell(q.w[d], 0.0, R);
+        q.fkey = morton_fine(q.c[0], q.c[1], q.c[2]);
+    }
+    std::sort(V.begin(), V.end(), [](const Pt& A, const Pt& B) { return A.fkey != B.fkey ? A.fkey < B.fkey : A.cidx < B.cidx; });
+}
+
+// Add one tree (boxes, leaves, points, and its M2M or L2L operators and lists)
+// to the plan.  rep: the FMM whose lambda and root the tree's operators use.
+void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bool target, int rep, int slot,
+              TreeB& T)
+{
+    T.B.assign(H + 1, BoxSet{});
+    for (int lv = 0; lv <= H; ++lv) {
+        int sh = kCellBits - lv;
+        BoxSet& bs = T.B[lv];
+        for (size_t i = 0; i < V.size(); ++i) {
+            if (i > 0 && (V[i].fkey >> (3 * sh)) == (V[i - 1].fkey >> (3 * sh))) continue;
+            uint32_t a = V[i].c[0] >> sh, b = V[i].c[1] >> sh, c = V[i].c[2] >> sh;
+            bs.idx[cellkey(a, b, c)] = (int)bs.mkey.size();
+            bs.mkey.push_back(V[i].fkey >> (3 * sh));
+            bs.ix.push_back((int)a);
+            bs.iy.push_back((int)b);
+            bs.iz.push_back((int)c);
+        }
+    }
+    T.id = (int)P.trees.size();
+    TreeDesc td{};
+    td.target = target ? 1 : 0;
+    td.rep = rep;
+    td.H = H;
+    for (int lv = 0; lv <= kMaxDepth; ++lv) T.off[lv] = -1;
+    for (int lv = 2; lv <= H; ++lv) {
+        int n = (int)T.B[lv].mkey.size();
+        if (target) {
+            T.off[lv] = P.n_le;
+            P.n_le += n;
+        } else {
+            T.off[lv] = P.n_me;
+            P.n_me += n;
+        }
+    }
+    if (target) S.m2l_by_le.resize(P.n_le);
+    auto hlev = [&](int lv) { return 2.0 * R / (double)(1 << lv); };
+    auto centre = [&](int lv, int i) { return -R + (i + 0.5) * hlev(lv); };   // canonical, relative to the root centre
+    const int shH = kCellBits - H;
+    // leaves and points
+    T.leaf0 = target ? (int)P.tl_le.size() : (int)P.sl_me.size();
+    int cur = -1;
+    for (size_t k = 0; k < V.size(); ++k) {
+        uint32_t a = V[k].c[0] >> shH, b = V[k].c[1] >> shH, c = V[k].c[2] >> shH;
+        int bi = T.B[H].idx[cellkey(a, b, c)];
+        if (bi != cur) {
+            if (target) {
+                if (cur >= 0) P.tl_start.push_back((int)P.t_cidx.size());
+                P.tl_le.push_back(H >= 2 ? T.off[H] + bi : -1);
+                P.tl_fmm.push_back(rep);
+                P.tl_tree.push_back(T.id);
+                P.tl_h.push_back(hlev(H));
+                for (uint32_t v : {a, b, c}) P.tl_ctr.push_back(centre(H, (int)v));
+            } else {
+                if (cur >= 0) P.sl_start.push_back((int)P.s_cidx.size());
+                P.sl_me.push_back(H >= 2 ? T.off[H] + bi : -1);
+                P.sl_fmm.push_back(rep);
+                P.sl_tree.push_back(T.id);
+                P.sl_h.push_back(hlev(H));
+                for (uint32_t v : {a, b, c}) P.sl_ctr.push_back(centre(H, (int)v));
+            }
+            cur = bi;
+        }
+        double ux = V[k].w[0] - centre(H, (int)a), uy = V[k].w[1] - centre(H, (int)b), uz = V[k].w[2] - centre(H, (int)c);
+        if (target) {
+            P.t_cidx.push_back(V[k].cidx);
+            P.t_lcell.push_back(cellkey(a, b, c));
+            P.t_out.push_back(slot);   // finalised with ncharges
+            S.t_ux.push_back(ux); S.t_uy.push_back(uy); S.t_uz.push_back(uz);
+        } else {
+            P.s_cidx.push_back(V[k].cidx);
+            P.s_lcell.push_back(cellkey(a, b, c));
+            S.s_ux.push_back(ux); S.s_uy.push_back(uy); S.s_uz.push_back(uz);
+        }
+    }
+    if (!V.empty()) {
+        if (target) P.tl_start.push_back((int)P.t_cidx.size());
+        else P.sl_start.push_back((int)P.s_cidx.size());
+    }
+    T.nleaf = (target ? (int)P.tl_le.size() : (int)P.sl_me.size()) - T.leaf0;
+    td.leaf0 = T.leaf0;
+    td.nleaf = T.nleaf;
+    P.trees.push_back(td);
+    if (target) S.p2p_by_tl.resize(P.tl_le.size()), S.rp_by_tl.resize(P.tl_le.size());
+    // translation operators (b = child centre - parent centre) and their lists
+    int lo = target ? 3 : 2, hi = target ? H : H - 1;
+    for (int lv = lo; lv <= hi; ++lv) {
+        double hc = hlev(target ? lv : lv + 1);
+        int opo[8];
+        for (int o = 0; o < 8; ++o) {
+            OpDesc d{};
+            d.type = target ? OP_L2L : OP_M2M;
+            d.fmm = rep;
+            d.level = lv;
+            d.rkey = -1;
+            d.bx = (((o >> 2) & 1) - 0.5) * hc;
+            d.by = (((o >> 1) & 1) - 0.5) * hc;
+            d.bz = ((o & 1) - 0.5) * hc;
+            opo[o] = (int)P.ops.size();
+            P.ops.push_back(d);
+        }
+        if (target) {
+            for (int k = 0; k < (int)T.B[lv].mkey.size(); ++k) {
+                int ix = T.B[lv].ix[k], iy = T.B[lv].iy[k], iz = T.B[lv].iz[k];
+                int pk = T.B[lv - 1].idx.at(cellkey(ix >> 1, iy >> 1, iz >> 1));
+                int o = ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1);
+                S.l2l_by_level[lv].push_back({T.off[lv] + k, T.off[lv - 1] + pk, opo[o]});
+            }
+        } else {
+            for (int k = 0; k < (int)T.B[lv].mkey.size(); ++k) {
+                int px = T.B[lv].ix[k], py = T.B[lv].iy[k], pz = T.B[lv].iz[k];
+                for (int o = 0; o < 8; ++o) {
+                    auto it = T.B[lv + 1].idx.find(cellkey(2 * px + ((o >> 2) & 1), 2 * py + ((o >> 1) & 1), 2 * pz + (o & 1)));
+                    if (it == T.B[lv + 1].idx.end()) continue;
+                    S.m2m_by_level[lv].push_back({T.off[lv] + k, T.off[lv + 1] + it->second, opo[o]});
+                }
+            }
+        }
+    }
+}
+
+// V-lists (M2L, with operator de-duplication and the tiled levels of a
+// free-space FMM) and U-lists of one FMM between its source and target trees.
+void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
+{
+    FmmDesc& F = P.fmm[fid];
+    const int H = F.H;
+    const double R = F.R;
+    auto hlev = [&](int lv) { return 2.0 * R / (double)(1 << lv); };
+    auto centre = [&](int lv, int i) { return -R + (i + 0.5) * hlev(lv); };
+    const std::vector<BoxSet>& SB = ST.B;
+    const std::vector<BoxSet>& TB = TT.B;
+    std::unordered_map<uint64_t, int> opmap, rkmap;
+    auto free_op = [&](int lv, int dx, int dy, int dz) {
+        uint64_t key = ((uint64_t)lv << 16) | (uint64_t)(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
+        auto f = opmap.find(key);
+        if (f != opmap.end()) return f->second;
+        double h = hlev(lv);
+        OpDesc d{};
+        d.type = OP_M2L_FREE;
+        d.fmm = fid;
+        d.level = lv;
+        d.rkey = -1;
+        d.bx = -dx * h;   // b = c_t - c_s
+        d.by = -dy * h;
+        d.bz = -dz * h;
+        int op = (int)P.ops.size();
+        P.ops.push_back(d);
+        opmap[key] = op;
+        return op;
+    };
+    // tiled levels of a free-space FMM: dense grids, operator table, tiles
+    int tiled_max = (F.kind == 0) ? std::min(H, kTileMaxLevel) : 1;
+    for (int lv = 2; lv <= tiled_max; ++lv) {
+        int nside = 1 << lv;
+        TileFL t{};
+        t.fmm = fid;
+        t.level = lv;
+        t.nside = nside;
+        t.grid_off = (int)P.grid_me.size();
+        t.optab_off = (int)P.optab.size();
+        P.grid_me.resize(P.grid_me.size() + (size_t)nside * nside * nside, -1);
+        P.grid_le.resize(P.grid_le.size() + (size_t)nside * nside * nside, -1);
+        for (int k = 0; k < (int)SB[lv].mkey.size(); ++k)
+            P.grid_me[t.grid_off + ((size_t)SB[lv].ix[k] * nside + SB[lv].iy[k]) * nside + SB[lv].iz[k]] = ST.off[lv] + k;
+        for (int k = 0; k < (int)TB[lv].mkey.size(); ++k)
+            P.grid_le[t.grid_off + ((size_t)TB[lv].ix[k] * nside + TB[lv].iy[k]) * nside + TB[lv].iz[k]] = TT.off[lv] + k;
+        P.optab.resize(P.optab.size() + 343, -1);
+        for (int dx = -3; dx <= 3; ++dx)
+            for (int dy = -3; dy <= 3; ++dy)
+                for (int dz = -3; dz <= 3; ++dz) {
+                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                    P.optab[t.optab_off + ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)] = free_op(lv, dx, dy, dz);
+                }
+        int fl = (int)P.tfl.size();
+        P.tfl.push_back(t);
+        int np = nside / 2;
+        for (int bx = 0; bx < np; bx += kTilePB)
+            for (int by = 0; by < np; by += kTilePB)
+                for (int bz = 0; bz < np; bz += kTilePB)
+                    for (int o = 0; o < 8; ++o) {
+                        bool any = false;
+                        for (int i = 0; i < kTilePB && !any; ++i)
+                            for (int j = 0; j < kTilePB && !any; ++j)
+                                for (int k = 0; k < kTilePB && !any; ++k) {
+                                    int tx = 2 * (bx + i) + ((o >> 2) & 1), ty = 2 * (by + j) + ((o >> 1) & 1),
+                                        tz = 2 * (bz + k) + (o & 1);
+                                    if (tx < nside && ty < nside && tz < nside &&
+                                        P.grid_le[t.grid_off + ((size_t)tx * nside + ty) * nside + tz] >= 0)
+                                        any = true;
+                                }
+                        if (any) P.tiles.push_back({fl, o, bx, by, bz});
+                    }
+    }
+    for (int lv = 2; lv <= H; ++lv) {
+        const bool tiled = lv <= tiled_max;
+        int nside = 1 << lv;
+        double h = hlev(lv);
+        for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
+            int tx = TB[lv].ix[k], ty = TB[lv].iy[k], tz = TB[lv].iz[k];
+            int le = TT.off[lv] + k;
+            for (int qx = (tx >> 1) - 1; qx <= (tx >> 1) + 1; ++qx)
+                for (int qy = (ty >> 1) - 1; qy <= (ty >> 1) + 1; ++qy)
+                    for (int qz = (tz >> 1) - 1; qz <= (tz >> 1) + 1; ++qz) {
+                        if (qx < 0 || qy < 0 || qz < 0 || qx >= nside / 2 || qy >= nside / 2 || qz >= nside / 2) continue;
+                        for (int o = 0; o < 8; ++o) {
+                            int sx = 2 * qx + ((o >> 2) & 1), sy = 2 * qy + ((o >> 1) & 1), sz = 2 * qz + (o & 1);
+                            int dx = sx - tx, dy = sy - ty, dz = sz - tz;
+                            if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
+                            auto it = SB[lv].idx.find(cellkey(sx, sy, sz));
+                            if (it == SB[lv].idx.end()) continue;
+                            int op;
+                            if (F.kind == 0) {
+                                op = free_op(lv, dx, dy, dz);
+                            } else {
+                                uint64_t key = ((uint64_t)lv << 48) | ((uint64_t)(dx + 3) << 40) | ((uint64_t)(dy + 3) << 32) |
+                                               ((uint64_t)tz << 16) | (uint64_t)sz;
+                                auto f = opmap.find(key);
+                                if (f == opmap.end()) {
+                                    int d2 = dx * dx + dy * dy;
+                                    uint64_t rk = ((uint64_t)lv << 48) | ((uint64_t)d2 << 32) | ((uint64_t)tz << 16) | (uint64_t)sz;
+                                    int rki;
+                                    auto g = rkmap.find(rk);
+                                    if (g == rkmap.end()) {
+                                        RKey r{};
+                                        r.fmm = fid;
+                                        r.level = lv;
+                                        r.rho = h * std::sqrt((double)d2);
+                                        r.zt = centre(lv, tz);
+                                        r.zs = centre(lv, sz);
+                                        r.S = h;
+                                        rki = (int)P.rkeys.size();
+                                        P.rkeys.push_back(r);
+                                        rkmap[rk] = rki;
+                                    } else rki = g->second;
+                                    OpDesc d{};
+                                    d.type = OP_M2L_REACT;
+                                    d.fmm = fid;
+                                    d.level = lv;
+                                    d.rkey = rki;
+                                    d.phi = (dx == 0 && dy == 0) ? 0.0 : std::atan2((double)-dy, (double)-dx);
+                                    op = (int)P.ops.size();
+                                    P.ops.push_back(d);
+                                    opmap[key] = op;
+                                } else op = f->second;
+                            }
+                            if (!tiled) S.m2l_by_le[le].push_back({ST.off[lv] + it->second, op});
+                            else P.n_m2l_tile_pairs++;
+                            P.n_m2l_pairs++;
+                        }
+                    }
+        }
+    }
+    // U-lists at the leaf level (target leaf order equals the level-H box order)
+    int nside = 1 << H;
+    for (int k = 0; k < TT.nleaf; ++k) {
+        int tx = TB[H].ix[k], ty = TB[H].iy[k], tz = TB[H].iz[k];
+        int tl = TT.leaf0 + k;
+        int nt = P.tl_start[tl + 1] - P.tl_start[tl];
+        for (int dx = -1; dx <= 1; ++dx)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dz = -1; dz <= 1; ++dz) {
+                    int sx = tx + dx, sy = ty + dy, sz = tz + dz;
+                    if (sx < 0 || sy < 0 || sz < 0 || sx >= nside || sy >= nside || sz >= nside) continue;
+                    auto it = SB[H].idx.find(cellkey(sx, sy, sz));
+                    if (it == SB[H].idx.end()) continue;
+                    int sl = ST.leaf0 + it->second;
+                    int64_t pairs = (int64_t)nt * (P.sl_start[sl + 1] - P.sl_start[sl]);
+                    P.n_p2p_pairs += pairs;
+                    if (F.kind == 0) S.p2p_by_tl[tl].push_back(sl);
+                    else {
+                        S.rp_by_tl[tl].push_back({fid, sl});
+                        P.n_react_p2p_pairs += pairs;
+                    }
+                }
+    }
+}
+
 }  // namespace
 
 std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vector<std::vector<double>>& xs,
                        const std::vector<std::vector<double>>& ys, const std::vector<std::vector<double>>& zs,
                        double iface_tol, int* status)
 {
-    const int p = P.p;
     const int cap = P.leaf_cap;
     *status = LPB_OK;
     P.nsys = (int)media.size();
@@ -103,14 +418,17 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.sys_charge_off.assign(P.nsys + 1, 0);
     for (int s = 0; s < P.nsys; ++s) P.sys_charge_off[s + 1] = P.sys_charge_off[s] + (int64_t)xs[s].size();
     P.ncharges = P.sys_charge_off[P.nsys];
-    if (P.ncharges > (int64_t)0x7fffffff / 16) {
+    if (P.ncharges > (int64_t)0x7fffffff / 4) {
         *status = LPB_ERANGE;
         return "too many charges for 32-bit slot indices";
     }
     int maxL = 0;
     for (auto& m : media) maxL = std::max(maxL, m.L);
-    P.nslots = 1 + 4 * maxL;
+    // output slots: 0 free space, 1 reaction through the lower interface of
+    // the target's layer (a = 1), 2 through the upper one (a = 2)
+    P.nslots = maxL > 0 ? 3 : 1;
     P.fmm.clear();
+    P.trees.clear();
     P.max_depth = 0;
 
     // ---- validation and layer classification ----
@@ -135,10 +453,9 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
 
     // ---- accumulators of the plan ----
     P.s_cidx.clear(); P.t_cidx.clear(); P.s_u.clear(); P.t_u.clear(); P.t_out.clear();
-    P.sl_start.assign(1, 0); P.sl_me.clear(); P.sl_fmm.clear(); P.sl_level.clear(); P.sl_h.clear();
-    P.tl_start.assign(1, 0); P.tl_le.clear(); P.tl_fmm.clear(); P.tl_h.clear();
-    P.sl_ctr.clear(); P.tl_ctr.clear(); P.s_okey.clear(); P.t_okey.clear();
-    P.me_fmm.clear(); P.me_level.clear(); P.le_fmm.clear(); P.le_level.clear();
+    P.sl_start.assign(1, 0); P.sl_me.clear(); P.sl_fmm.clear(); P.sl_tree.clear(); P.sl_h.clear();
+    P.tl_start.assign(1, 0); P.tl_le.clear(); P.tl_fmm.clear(); P.tl_tree.clear(); P.tl_h.clear();
+    P.sl_ctr.clear(); P.tl_ctr.clear(); P.s_lcell.clear(); P.t_lcell.clear();
     P.n_me = P.n_le = 0;
     P.ops.clear(); P.rkeys.clear();
     P.tfl.clear(); P.tiles.clear(); P.grid_me.clear(); P.grid_le.clear(); P.optab.clear();
@@ -153,454 +470,178 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                     P.oct_codes.push_back(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
                 }
     }
-    // per-level staging (levels are contiguous across FMMs in the final arrays)
-    struct M2MRec { int parent, child, op; };
-    struct L2LRec { int child, parent, op; };
-    std::vector<std::vector<M2MRec>> m2m_by_level(kMaxDepth + 1);
-    std::vector<std::vector<L2LRec>> l2l_by_level(kMaxDepth + 1);
-    std::vector<std::vector<std::pair<int, int>>> m2l_by_le;   // per LE box: (src ME, op)
-    std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: source leaves
-    std::vector<double> s_ux, s_uy, s_uz, t_ux, t_uy, t_uz;
+    Staging S;
 
     for (int s = 0; s < P.nsys; ++s) {
         const Medium& m = media[s];
         const int L = m.L;
         const int64_t coff = P.sys_charge_off[s];
+        std::vector<std::vector<int>> members(L + 1);
+        for (size_t i = 0; i < xs[s].size(); ++i) members[layer[s][i]].push_back((int)i);
+        auto base_desc = [&](int kind, int l, int lp, int a, int b) {
+            FmmDesc F{};
+            F.sys = s; F.kind = kind; F.l = l; F.lp = lp; F.a = a; F.b = b;
+            F.lam_s = m.lam[lp];
+            F.lam_t = m.lam[l];
+            F.eps_t = m.eps[l];
+            F.far_factor = (kind == 0) ? m.lam[l] / (2.0 * LPB_PI * LPB_PI * m.eps[l]) : 1.0;
+            F.flip = (kind == 1 && a == 2) ? -1 : 1;
+            F.layers_id = s;
+            F.nsrc = (int)members[lp].size();
+            F.ntgt = (int)members[l].size();
+            return F;
+        };
+
+        // ---- free-space FMM of every layer: its own bounding cube and depth ----
+        for (int l = 0; l <= L; ++l) {
+            const auto& mem = members[l];
+            if (mem.empty()) continue;
+            FmmDesc F = base_desc(0, l, l, 0, 0);
+            F.slot = 0;
+            double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int i : mem) {
+                double v[3] = {xs[s][i], ys[s][i], zs[s][i]};
+                for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], v[d]); hi[d] = std::max(hi[d], v[d]); }
+            }
+            F.cx = 0.5 * (lo[0] + hi[0]);
+            F.cy = 0.5 * (lo[1] + hi[1]);
+            F.cz = 0.5 * (lo[2] + hi[2]);
+            double r = 0.0;
+            for (int d = 0; d < 3; ++d) r = std::max(r, 0.5 * (hi[d] - lo[d]));
+            F.R = r > 0 ? r : 0.5;
+            std::vector<Pt> V(mem.size());
+            for (size_t k = 0; k < mem.size(); ++k) {
+                int i = mem[k];
+                V[k].w[0] = xs[s][i] - F.cx;
+                V[k].w[1] = ys[s][i] - F.cy;
+                V[k].w[2] = zs[s][i] - F.cz;
+                V[k].cidx = (int)(coff + i);
+            }
+            set_cells(V, F.R);
+            F.H = depth_rule(V, cap);
+            P.max_depth = std::max(P.max_depth, F.H);
+            const int fid = (int)P.fmm.size();
+            P.fmm.push_back(F);
+            TreeB ST, TT;
+            add_tree(P, S, V, F.H, F.R, false, fid, 0, ST);
+            add_tree(P, S, V, F.H, F.R, true, fid, 0, TT);
+            for (int lv = 0; lv <= kMaxDepth; ++lv) {
+                P.fmm[fid].me_off[lv] = ST.off[lv];
+                P.fmm[fid].le_off[lv] = TT.off[lv];
+            }
+            P.fmm[fid].src_tree = ST.id;
+            P.fmm[fid].tgt_tree = TT.id;
+            add_lists(P, S, fid, ST, TT);
+        }
+        if (L == 0) continue;
+
+        // ---- reaction components: one grid for all of them ----
+        // In the frame of a component (interface at z = 0, targets above it,
+        // mirrored for a = 2) a target of layer l sits at +tau_a(z) and an
+        // equivalent source of layer lp at -tau'_b(z') (eq. equivpolarcoord):
+        // both depend only on their own layer and side, so each (layer, side)
+        // point set has one source tree and one target tree, shared by all
+        // components that use it, on a common root cube and depth.
+        auto side_ok = [&](int l, int sd) { return sd == 1 ? l < L : l > 0; };
+        auto tau = [&](int l, int sd, double z) { return sd == 1 ? z - m.d[l] : m.d[l - 1] - z; };
+        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, r = 0.0;
+        for (size_t i = 0; i < xs[s].size(); ++i) {
+            lo[0] = std::min(lo[0], xs[s][i]); hi[0] = std::max(hi[0], xs[s][i]);
+            lo[1] = std::min(lo[1], ys[s][i]); hi[1] = std::max(hi[1], ys[s][i]);
+            for (int sd = 1; sd <= 2; ++sd)
+                if (side_ok(layer[s][i], sd)) r = std::max(r, std::fabs(tau(layer[s][i], sd, zs[s][i])));
+        }
+        if (xs[s].empty()) continue;
+        const double gcx = 0.5 * (lo[0] + hi[0]), gcy = 0.5 * (lo[1] + hi[1]);
+        r = std::max(r, 0.5 * (hi[0] - lo[0]));
+        r = std::max(r, 0.5 * (hi[1] - lo[1]));
+        const double R = r > 0 ? r : 0.5;
+        // point sets: [l][sd][0 = images at -tau, 1 = targets at +tau]
+        std::vector<std::array<std::array<std::vector<Pt>, 2>, 3>> sets(L + 1);
+        int H = 0;
+        for (int l = 0; l <= L; ++l)
+            for (int sd = 1; sd <= 2; ++sd) {
+                if (!side_ok(l, sd) || members[l].empty()) continue;
+                for (int tg = 0; tg < 2; ++tg) {
+                    auto& V = sets[l][sd][tg];
+                    V.resize(members[l].size());
+                    for (size_t k = 0; k < members[l].size(); ++k) {
+                        int i = members[l][k];
+                        double t = tau(l, sd, zs[s][i]);
+                        V[k].w[0] = xs[s][i] - gcx;
+                        V[k].w[1] = ys[s][i] - gcy;
+                        V[k].w[2] = tg ? t : -t;
+                        V[k].cidx = (int)(coff + i);
+                    }
+                    set_cells(V, R);
+                    H = std::max(H, depth_rule(V, cap));
+                }
+            }
+        P.max_depth = std::max(P.max_depth, H);
         // components in Algorithm 2 order
-        struct C { int kind, l, lp, a, b; };
-        std::vector<C> comps;
-        for (int l = 0; l <= L; ++l) comps.push_back({0, l, l, 0, 0});
+        std::vector<int> comp_fid;
         for (int a = 1; a <= 2; ++a)
             for (int b = 1; b <= 2; ++b)
                 for (int l = (a == 1 ? 0 : 1); l < (a == 1 ? L : L + 1); ++l)
-                    for (int lp = (b == 1 ? 0 : 1); lp < (b == 1 ? L : L + 1); ++lp) comps.push_back({1, l, lp, a, b});
-        std::vector<int> slot_ctr(L + 1, 1);
-        std::vector<std::vector<int>> members(L + 1);
-        for (size_t i = 0; i < xs[s].size(); ++i) members[layer[s][i]].push_back((int)i);
-
-        for (const C& cp : comps) {
-            int slot = (cp.kind == 0) ? 0 : slot_ctr[cp.l]++;
-            const auto& tgt = members[cp.l];
-            const auto& src = members[cp.lp];
-            if (tgt.empty() || src.empty()) continue;
-            FmmDesc F{};
-            F.sys = s;
-            F.kind = cp.kind;
-            F.l = cp.l;
-            F.lp = cp.lp;
-            F.a = cp.a;
-            F.b = cp.b;
-            F.slot = slot;
-            F.lam_s = m.lam[cp.lp];
-            F.lam_t = m.lam[cp.l];
-            F.eps_t = m.eps[cp.l];
-            F.far_factor = (cp.kind == 0) ? m.lam[cp.l] / (2.0 * LPB_PI * LPB_PI * m.eps[cp.l]) : 1.0;
-            F.flip = (cp.kind == 1 && cp.a == 2) ? -1 : 1;
-            F.layers_id = s;
-            // points; reaction sources are images (eq. equivpolarcoord, with the source's own z)
-            std::vector<Pt> T(tgt.size()), S(src.size());
-            for (size_t k = 0; k < tgt.size(); ++k) {
-                int i = tgt[k];
-                T[k].x = xs[s][i]; T[k].y = ys[s][i]; T[k].z = zs[s][i];
-                T[k].cidx = (int)(coff + i);
-                T[k].local = i;
-            }
-            double zi = 0.0;
-            if (cp.kind == 1) zi = (cp.a == 1) ? m.d[cp.l] : m.d[cp.l - 1];
-            for (size_t k = 0; k < src.size(); ++k) {
-                int i = src[k];
-                S[k].x = xs[s][i]; S[k].y = ys[s][i];
-                double z = zs[s][i];
-                if (cp.kind == 1) {
-                    double ts = (cp.b == 1) ? z - m.d[cp.lp] : m.d[cp.lp - 1] - z;
-                    z = (cp.a == 1) ? m.d[cp.l] - ts : m.d[cp.l - 1] + ts;
-                }
-                S[k].z = z;
-                S[k].cidx = (int)(coff + i);
-                S[k].local = i;
-            }
-            // root cube
-            if (cp.kind == 0) {
-                double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
-                for (auto& q : T) {
-                    double v[3] = {q.x, q.y, q.z};
-                    for (int d = 0; d < 3; ++d) { lo[d] = std::min(lo[d], v[d]); hi[d] = std::max(hi[d], v[d]); }
-                }
-                F.cx = 0.5 * (lo[0] + hi[0]);
-                F.cy = 0.5 * (lo[1] + hi[1]);
-                F.cz = 0.5 * (lo[2] + hi[2]);
-                double r = 0.0;
-                for (int d = 0; d < 3; ++d) r = std::max(r, 0.5 * (hi[d] - lo[d]));
-                F.R = r > 0 ? r : 0.5;
-            } else {
-                double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY};
-                double r = 0.0;
-                for (auto* V : {&T, &S})
-                    for (auto& q : *V) {
-                        lo[0] = std::min(lo[0], q.x); hi[0] = std::max(hi[0], q.x);
-                        lo[1] = std::min(lo[1], q.y); hi[1] = std::max(hi[1], q.y);
-                        r = std::max(r, std::fabs(q.z - zi));
+                    for (int lp = (b == 1 ? 0 : 1); lp < (b == 1 ? L : L + 1); ++lp) {
+                        if (members[l].empty() || members[lp].empty()) continue;
+                        FmmDesc F = base_desc(1, l, lp, a, b);
+                        F.slot = a;
+                        F.cx = gcx;
+                        F.cy = gcy;
+                        F.cz = (a == 1) ? m.d[l] : m.d[l - 1];
+                        F.R = R;
+                        F.H = H;
+                        comp_fid.push_back((int)P.fmm.size());
+                        P.fmm.push_back(F);
                     }
-                F.cx = 0.5 * (lo[0] + hi[0]);
-                F.cy = 0.5 * (lo[1] + hi[1]);
-                F.cz = zi;
-                r = std::max(r, 0.5 * (hi[0] - lo[0]));
-                r = std::max(r, 0.5 * (hi[1] - lo[1]));
-                F.R = r > 0 ? r : 0.5;
-            }
-            for (auto* V : {&T, &S})
-                for (auto& q : *V) {
-                    q.c[0] = fine_cell(q.x, F.cx, F.R);
-                    q.c[1] = fine_cell(q.y, F.cy, F.R);
-                    q.c[2] = fine_cell(q.z, F.cz, F.R);
-                    if (F.flip < 0) q.c[2] = 65535u - q.c[2];   // canonical frame: mirror z
-                }
-            // fine Morton keys; one sort per point set, then every level is a prefix
-            for (auto* V : {&T, &S})
-                for (auto& q : *V) q.fkey = morton_fine(q.c[0], q.c[1], q.c[2]);
-            auto byfine = [](const Pt& A, const Pt& B) { return A.fkey != B.fkey ? A.fkey < B.fkey : A.cidx < B.cidx; };
-            std::sort(T.begin(), T.end(), byfine);
-            std::sort(S.begin(), S.end(), byfine);
-            auto count_level = [](const std::vector<Pt>& V, int lv) {
-                int sh = 3 * (kCellBits - lv);
-                int64_t n = V.empty() ? 0 : 1;
-                for (size_t i = 1; i < V.size(); ++i)
-                    if ((V[i].fkey >> sh) != (V[i - 1].fkey >> sh)) ++n;
-                return n;
-            };
-            // depth
-            int H = kMaxDepth;
+        // shared trees; the first component using a tree lends it lambda and root
+        std::vector<std::array<TreeB, 3>> src_t(L + 1), tgt_t(L + 1);
+        for (int fid : comp_fid) {
+            FmmDesc& F = P.fmm[fid];
+            if (src_t[F.lp][F.b].id < 0) add_tree(P, S, sets[F.lp][F.b][0], H, R, false, fid, 0, src_t[F.lp][F.b]);
+            if (tgt_t[F.l][F.a].id < 0) add_tree(P, S, sets[F.l][F.a][1], H, R, true, fid, F.a, tgt_t[F.l][F.a]);
+        }
+        for (int fid : comp_fid) {
+            FmmDesc& F = P.fmm[fid];
+            const TreeB& ST = src_t[F.lp][F.b];
+            const TreeB& TT = tgt_t[F.l][F.a];
             for (int lv = 0; lv <= kMaxDepth; ++lv) {
-                if ((int64_t)S.size() <= (int64_t)cap * count_level(S, lv) &&
-                    (int64_t)T.size() <= (int64_t)cap * count_level(T, lv)) {
-                    H = lv;
-                    break;
-                }
+                F.me_off[lv] = ST.off[lv];
+                F.le_off[lv] = TT.off[lv];
             }
-            F.H = H;
-            P.max_depth = std::max(P.max_depth, H);
-            const int fid = (int)P.fmm.size();
-            F.nsrc = (int)S.size();
-            F.ntgt = (int)T.size();
-            int shH = kCellBits - H;
-            // boxes per level, in Morton order (prefixes of the sorted fine keys)
-            std::vector<BoxSet> SB(H + 1), TB(H + 1);
-            auto make_boxes = [&](const std::vector<Pt>& V, std::vector<BoxSet>& B) {
-                for (int lv = 0; lv <= H; ++lv) {
-                    int sh = kCellBits - lv;
-                    BoxSet& bs = B[lv];
-                    for (size_t i = 0; i < V.size(); ++i) {
-                        if (i > 0 && (V[i].fkey >> (3 * sh)) == (V[i - 1].fkey >> (3 * sh))) continue;
-                        uint32_t a = V[i].c[0] >> sh, b = V[i].c[1] >> sh, c = V[i].c[2] >> sh;
-                        bs.idx[cellkey(a, b, c)] = (int)bs.mkey.size();
-                        bs.mkey.push_back(V[i].fkey >> (3 * sh));
-                        bs.ix.push_back((int)a);
-                        bs.iy.push_back((int)b);
-                        bs.iz.push_back((int)c);
-                    }
-                }
-            };
-            make_boxes(S, SB);
-            make_boxes(T, TB);
-            // global ME / LE indices for levels >= 2
-            for (int lv = 0; lv <= kMaxDepth; ++lv) {
-                F.me_off[lv] = F.le_off[lv] = -1;
-                F.me_cnt[lv] = F.le_cnt[lv] = 0;
-            }
-            for (int lv = 2; lv <= H; ++lv) {
-                F.me_off[lv] = P.n_me;
-                F.me_cnt[lv] = (int)SB[lv].mkey.size();
-                for (int k = 0; k < F.me_cnt[lv]; ++k) { P.me_fmm.push_back(fid); P.me_level.push_back(lv); }
-                P.n_me += F.me_cnt[lv];
-                F.le_off[lv] = P.n_le;
-                F.le_cnt[lv] = (int)TB[lv].mkey.size();
-                for (int k = 0; k < F.le_cnt[lv]; ++k) { P.le_fmm.push_back(fid); P.le_level.push_back(lv); }
-                P.n_le += F.le_cnt[lv];
-            }
-            m2l_by_le.resize(P.n_le);
-            auto hlev = [&](int lv) { return 2.0 * F.R / (double)(1 << lv); };
-            auto centre = [&](int lv, int i) { return -F.R + (i + 0.5) * hlev(lv); };   // canonical local frame
-            // ---- points and leaves ----
-            const int sl0 = (int)P.sl_me.size();
-            {
-                int cur = -1;
-                for (size_t k = 0; k < S.size(); ++k) {
-                    uint32_t a = S[k].c[0] >> shH, b = S[k].c[1] >> shH, c = S[k].c[2] >> shH;
-                    int bi = SB[H].idx[cellkey(a, b, c)];
-                    if (bi != cur) {
-                        if (cur >= 0) P.sl_start.push_back((int)P.s_cidx.size());
-                        cur = bi;
-                        P.sl_me.push_back(H >= 2 ? F.me_off[H] + bi : -1);
-                        P.sl_fmm.push_back(fid);
-                        P.sl_level.push_back(H);
-                        P.sl_h.push_back(hlev(H));
-                        P.sl_ctr.push_back(centre(H, (int)a));
-                        P.sl_ctr.push_back(centre(H, (int)b));
-                        P.sl_ctr.push_back(centre(H, (int)c));
-                    }
-                    P.s_cidx.push_back(S[k].cidx);
-                    P.s_okey.push_back(morton(a, b, F.flip < 0 ? (uint32_t)((1 << H) - 1) - c : c, H));
-                    double zl = (double)F.flip * (S[k].z - F.cz);
-                    s_ux.push_back((S[k].x - F.cx) - centre(H, (int)a));
-                    s_uy.push_back((S[k].y - F.cy) - centre(H, (int)b));
-                    s_uz.push_back(zl - centre(H, (int)c));
-                }
-                P.sl_start.push_back((int)P.s_cidx.size());
-            }
-            const int tl0 = (int)P.tl_le.size();
-            {
-                int cur = -1;
-                for (size_t k = 0; k < T.size(); ++k) {
-                    uint32_t a = T[k].c[0] >> shH, b = T[k].c[1] >> shH, c = T[k].c[2] >> shH;
-                    int bi = TB[H].idx[cellkey(a, b, c)];
-                    if (bi != cur) {
-                        if (cur >= 0) P.tl_start.push_back((int)P.t_cidx.size());
-                        cur = bi;
-                        P.tl_le.push_back(H >= 2 ? F.le_off[H] + bi : -1);
-                        P.tl_fmm.push_back(fid);
-                        P.tl_h.push_back(hlev(H));
-                        P.tl_ctr.push_back(centre(H, (int)a));
-                        P.tl_ctr.push_back(centre(H, (int)b));
-                        P.tl_ctr.push_back(centre(H, (int)c));
-                    }
-                    P.t_cidx.push_back(T[k].cidx);
-                    P.t_okey.push_back(morton(a, b, F.flip < 0 ? (uint32_t)((1 << H) - 1) - c : c, H));
-                    P.t_out.push_back(slot);   // finalised below with ncharges
-                    double zl = (double)F.flip * (T[k].z - F.cz);
-                    t_ux.push_back((T[k].x - F.cx) - centre(H, (int)a));
-                    t_uy.push_back((T[k].y - F.cy) - centre(H, (int)b));
-                    t_uz.push_back(zl - centre(H, (int)c));
-                }
-                P.tl_start.push_back((int)P.t_cidx.size());
-            }
-            // ---- operators: M2M (parent level lv, octant), L2L (child level lv, octant) ----
-            int m2m_op[kMaxDepth + 1][8], l2l_op[kMaxDepth + 1][8];
-            for (int lv = 2; lv < H; ++lv)
-                for (int o = 0; o < 8; ++o) {
-                    double hc = hlev(lv + 1);
-                    OpDesc d{};
-                    d.type = OP_M2M;
-                    d.fmm = fid;
-                    d.level = lv;
-                    d.rkey = -1;
-                    // b = child centre - parent centre
-                    d.bx = (((o >> 2) & 1) - 0.5) * hc;
-                    d.by = (((o >> 1) & 1) - 0.5) * hc;
-                    d.bz = ((o & 1) - 0.5) * hc;
-                    m2m_op[lv][o] = (int)P.ops.size();
-                    P.ops.push_back(d);
-                }
-            for (int lv = 3; lv <= H; ++lv)
-                for (int o = 0; o < 8; ++o) {
-                    double hc = hlev(lv);
-                    OpDesc d{};
-                    d.type = OP_L2L;
-                    d.fmm = fid;
-                    d.level = lv;
-                    d.rkey = -1;
-                    d.bx = (((o >> 2) & 1) - 0.5) * hc;
-                    d.by = (((o >> 1) & 1) - 0.5) * hc;
-                    d.bz = ((o & 1) - 0.5) * hc;
-                    l2l_op[lv][o] = (int)P.ops.size();
-                    P.ops.push_back(d);
-                }
-            // M2M lists
-            for (int lv = 2; lv < H; ++lv) {
-                for (int k = 0; k < (int)SB[lv].mkey.size(); ++k) {
-                    int px = SB[lv].ix[k], py = SB[lv].iy[k], pz = SB[lv].iz[k];
-                    for (int o = 0; o < 8; ++o) {
-                        int cx = 2 * px + ((o >> 2) & 1), cy = 2 * py + ((o >> 1) & 1), cz = 2 * pz + (o & 1);
-                        auto it = SB[lv + 1].idx.find(cellkey(cx, cy, cz));
-                        if (it == SB[lv + 1].idx.end()) continue;
-                        m2m_by_level[lv].push_back({F.me_off[lv] + k, F.me_off[lv + 1] + it->second, m2m_op[lv][o]});
-                    }
-                }
-            }
-            // L2L lists
-            for (int lv = 3; lv <= H; ++lv)
-                for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
-                    int ix = TB[lv].ix[k], iy = TB[lv].iy[k], iz = TB[lv].iz[k];
-                    int pk = TB[lv - 1].idx.at(cellkey(ix >> 1, iy >> 1, iz >> 1));
-                    int o = ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1);
-                    l2l_by_level[lv].push_back({F.le_off[lv] + k, F.le_off[lv - 1] + pk, l2l_op[lv][o]});
-                }
-            // M2L (V-lists) with operator de-duplication
-            std::unordered_map<uint64_t, int> opmap, rkmap;
-            auto free_op = [&](int lv, int dx, int dy, int dz) {
-                uint64_t key = ((uint64_t)lv << 16) | (uint64_t)(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
-                auto f = opmap.find(key);
-                if (f != opmap.end()) return f->second;
-                double h = hlev(lv);
-                OpDesc d{};
-                d.type = OP_M2L_FREE;
-                d.fmm = fid;
-                d.level = lv;
-                d.rkey = -1;
-                d.bx = -dx * h;   // b = c_t - c_s
-                d.by = -dy * h;
-                d.bz = -dz * h;
-                int op = (int)P.ops.size();
-                P.ops.push_back(d);
-                opmap[key] = op;
-                return op;
-            };
-            // tiled levels of a free-space FMM: dense grids, operator table, tiles
-            int tiled_max = (cp.kind == 0) ? std::min(H, kTileMaxLevel) : 1;
-            for (int lv = 2; lv <= tiled_max; ++lv) {
-                int nside = 1 << lv;
-                TileFL t{};
-                t.fmm = fid;
-                t.level = lv;
-                t.nside = nside;
-                t.grid_off = (int)P.grid_me.size();
-                t.optab_off = (int)P.optab.size();
-                P.grid_me.resize(P.grid_me.size() + (size_t)nside * nside * nside, -1);
-                P.grid_le.resize(P.grid_le.size() + (size_t)nside * nside * nside, -1);
-                for (int k = 0; k < (int)SB[lv].mkey.size(); ++k)
-                    P.grid_me[t.grid_off + ((size_t)SB[lv].ix[k] * nside + SB[lv].iy[k]) * nside + SB[lv].iz[k]] = F.me_off[lv] + k;
-                for (int k = 0; k < (int)TB[lv].mkey.size(); ++k)
-                    P.grid_le[t.grid_off + ((size_t)TB[lv].ix[k] * nside + TB[lv].iy[k]) * nside + TB[lv].iz[k]] = F.le_off[lv] + k;
-                P.optab.resize(P.optab.size() + 343, -1);
-                for (int dx = -3; dx <= 3; ++dx)
-                    for (int dy = -3; dy <= 3; ++dy)
-                        for (int dz = -3; dz <= 3; ++dz) {
-                            if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-                            P.optab[t.optab_off + ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)] = free_op(lv, dx, dy, dz);
-                        }
-                int fl = (int)P.tfl.size();
-                P.tfl.push_back(t);
-                int np = nside / 2;
-                for (int bx = 0; bx < np; bx += kTilePB)
-                    for (int by = 0; by < np; by += kTilePB)
-                        for (int bz = 0; bz < np; bz += kTilePB)
-                            for (int o = 0; o < 8; ++o) {
-                                bool any = false;
-                                for (int i = 0; i < kTilePB && !any; ++i)
-                                    for (int j = 0; j < kTilePB && !any; ++j)
-                                        for (int k = 0; k < kTilePB && !any; ++k) {
-                                            int tx = 2 * (bx + i) + ((o >> 2) & 1), ty = 2 * (by + j) + ((o >> 1) & 1),
-                                                tz = 2 * (bz + k) + (o & 1);
-                                            if (tx < nside && ty < nside && tz < nside &&
-                                                P.grid_le[t.grid_off + ((size_t)tx * nside + ty) * nside + tz] >= 0)
-                                                any = true;
-                                        }
-                                if (any) P.tiles.push_back({fl, o, bx, by, bz});
-                            }
-            }
-            for (int lv = 2; lv <= H; ++lv) {
-                const bool tiled = lv <= tiled_max;
-                int nside = 1 << lv;
-                double h = hlev(lv);
-                for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
-                    int tx = TB[lv].ix[k], ty = TB[lv].iy[k], tz = TB[lv].iz[k];
-                    int le = F.le_off[lv] + k;
-                    for (int qx = (tx >> 1) - 1; qx <= (tx >> 1) + 1; ++qx)
-                        for (int qy = (ty >> 1) - 1; qy <= (ty >> 1) + 1; ++qy)
-                            for (int qz = (tz >> 1) - 1; qz <= (tz >> 1) + 1; ++qz) {
-                                if (qx < 0 || qy < 0 || qz < 0 || qx >= nside / 2 || qy >= nside / 2 || qz >= nside / 2)
-                                    continue;
-                                for (int o = 0; o < 8; ++o) {
-                                    int sx = 2 * qx + ((o >> 2) & 1), sy = 2 * qy + ((o >> 1) & 1), sz = 2 * qz + (o & 1);
-                                    int dx = sx - tx, dy = sy - ty, dz = sz - tz;
-                                    if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-                                    auto it = SB[lv].idx.find(cellkey(sx, sy, sz));
-                                    if (it == SB[lv].idx.end()) continue;
-                                    int op;
-                                    if (cp.kind == 0) {
-                                        op = free_op(lv, dx, dy, dz);
-                                    } else {
-                                        uint64_t key = ((uint64_t)lv << 48) | ((uint64_t)(dx + 3) << 40) | ((uint64_t)(dy + 3) << 32) |
-                                                       ((uint64_t)tz << 16) | (uint64_t)sz;
-                                        auto f = opmap.find(key);
-                                        if (f == opmap.end()) {
-                                            int d2 = dx * dx + dy * dy;
-                                            uint64_t rk = ((uint64_t)lv << 48) | ((uint64_t)d2 << 32) | ((uint64_t)tz << 16) | (uint64_t)sz;
-                                            int rki;
-                                            auto g = rkmap.find(rk);
-                                            if (g == rkmap.end()) {
-                                                RKey r{};
-                                                r.fmm = fid;
-                                                r.level = lv;
-                                                r.rho = h * std::sqrt((double)d2);
-                                                r.zt = centre(lv, tz);
-                                                r.zs = centre(lv, sz);
-                                                r.S = h;
-                                                rki = (int)P.rkeys.size();
-                                                P.rkeys.push_back(r);
-                                                rkmap[rk] = rki;
-                                            } else rki = g->second;
-                                            OpDesc d{};
-                                            d.type = OP_M2L_REACT;
-                                            d.fmm = fid;
-                                            d.level = lv;
-                                            d.rkey = rki;
-                                            d.phi = (dx == 0 && dy == 0) ? 0.0 : std::atan2((double)-dy, (double)-dx);
-                                            op = (int)P.ops.size();
-                                            P.ops.push_back(d);
-                                            opmap[key] = op;
-                                        } else op = f->second;
-                                    }
-                                    if (!tiled) m2l_by_le[le].push_back({F.me_off[lv] + it->second, op});
-                                    else P.n_m2l_tile_pairs++;
-                                    P.n_m2l_pairs++;
-                                }
-                            }
-                }
-            }
-            // U-lists at the leaf level
-            {
-                int nside = 1 << H;
-                int ntl = (int)TB[H].mkey.size();
-                // target leaf order equals TB[H] order (both sorted by Morton key)
-                p2p_by_tl.resize(tl0 + ntl);
-                for (int k = 0; k < ntl; ++k) {
-                    int tx = TB[H].ix[k], ty = TB[H].iy[k], tz = TB[H].iz[k];
-                    int nt = P.tl_start[tl0 + k + 1] - P.tl_start[tl0 + k];
-                    for (int dx = -1; dx <= 1; ++dx)
-                        for (int dy = -1; dy <= 1; ++dy)
-                            for (int dz = -1; dz <= 1; ++dz) {
-                                int sx = tx + dx, sy = ty + dy, sz = tz + dz;
-                                if (sx < 0 || sy < 0 || sz < 0 || sx >= nside || sy >= nside || sz >= nside) continue;
-                                auto it = SB[H].idx.find(cellkey(sx, sy, sz));
-                                if (it == SB[H].idx.end()) continue;
-                                int sl = sl0 + it->second;
-                                p2p_by_tl[tl0 + k].push_back(sl);
-                                int64_t pairs = (int64_t)nt * (P.sl_start[sl + 1] - P.sl_start[sl]);
-                                P.n_p2p_pairs += pairs;
-                                if (cp.kind == 1) P.n_react_p2p_pairs += pairs;
-                            }
-                }
-            }
-            P.fmm.push_back(F);
+            F.src_tree = ST.id;
+            F.tgt_tree = TT.id;
+            add_lists(P, S, fid, ST, TT);
         }
     }
     // ---- finalise flattened arrays ----
-    P.s_u.resize(3 * s_ux.size());
-    for (size_t i = 0; i < s_ux.size(); ++i) {
-        P.s_u[i] = s_ux[i];
-        P.s_u[s_ux.size() + i] = s_uy[i];
-        P.s_u[2 * s_ux.size() + i] = s_uz[i];
+    P.s_u.resize(3 * S.s_ux.size());
+    for (size_t i = 0; i < S.s_ux.size(); ++i) {
+        P.s_u[i] = S.s_ux[i];
+        P.s_u[S.s_ux.size() + i] = S.s_uy[i];
+        P.s_u[2 * S.s_ux.size() + i] = S.s_uz[i];
     }
-    P.t_u.resize(3 * t_ux.size());
-    for (size_t i = 0; i < t_ux.size(); ++i) {
-        P.t_u[i] = t_ux[i];
-        P.t_u[t_ux.size() + i] = t_uy[i];
-        P.t_u[2 * t_ux.size() + i] = t_uz[i];
+    P.t_u.resize(3 * S.t_ux.size());
+    for (size_t i = 0; i < S.t_ux.size(); ++i) {
+        P.t_u[i] = S.t_ux[i];
+        P.t_u[S.t_ux.size() + i] = S.t_uy[i];
+        P.t_u[2 * S.t_ux.size() + i] = S.t_uz[i];
     }
     for (size_t i = 0; i < P.t_out.size(); ++i) P.t_out[i] = (int)(P.t_out[i] * P.ncharges + P.t_cidx[i]);
     P.m2m_parent.clear(); P.m2m_ptr.assign(1, 0); P.m2m_child.clear(); P.m2m_op.clear();
     P.m2m_level_ptr.assign(kMaxDepth + 2, 0);
     for (int lv = 0; lv <= kMaxDepth; ++lv) {
         P.m2m_level_ptr[lv] = (int)P.m2m_parent.size();
-        auto& v = m2m_by_level[lv];
-        std::stable_sort(v.begin(), v.end(), [](const M2MRec& a, const M2MRec& b) { return a.parent < b.parent; });
+        auto& v = S.m2m_by_level[lv];
+        std::stable_sort(v.begin(), v.end(), [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
         for (size_t i = 0; i < v.size(); ++i) {
-            if (i == 0 || v[i].parent != v[i - 1].parent) {
+            if (i == 0 || v[i][0] != v[i - 1][0]) {
                 if (i > 0) P.m2m_ptr.push_back((int)P.m2m_child.size());
-                P.m2m_parent.push_back(v[i].parent);
+                P.m2m_parent.push_back(v[i][0]);
             }
-            P.m2m_child.push_back(v[i].child);
-            P.m2m_op.push_back(v[i].op);
+            P.m2m_child.push_back(v[i][1]);
+            P.m2m_op.push_back(v[i][2]);
         }
         if (!v.empty()) P.m2m_ptr.push_back((int)P.m2m_child.size());
     }
@@ -609,17 +650,17 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.l2l_level_ptr.assign(kMaxDepth + 2, 0);
     for (int lv = 0; lv <= kMaxDepth; ++lv) {
         P.l2l_level_ptr[lv] = (int)P.l2l_child.size();
-        for (auto& r : l2l_by_level[lv]) {
-            P.l2l_child.push_back(r.child);
-            P.l2l_parent.push_back(r.parent);
-            P.l2l_op.push_back(r.op);
+        for (auto& r : S.l2l_by_level[lv]) {
+            P.l2l_child.push_back(r[0]);
+            P.l2l_parent.push_back(r[1]);
+            P.l2l_op.push_back(r[2]);
         }
     }
     P.l2l_level_ptr[kMaxDepth + 1] = (int)P.l2l_child.size();
     P.m2l_ptr.assign(1, 0); P.m2l_src.clear(); P.m2l_op.clear();
-    m2l_by_le.resize(P.n_le);
+    S.m2l_by_le.resize(P.n_le);
     for (int i = 0; i < P.n_le; ++i) {
-        for (auto& e : m2l_by_le[i]) {
+        for (auto& e : S.m2l_by_le[i]) {
             P.m2l_src.push_back(e.first);
             P.m2l_op.push_back(e.second);
         }
@@ -633,13 +674,26 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
             P.swz_ops.push_back((int)i);
         }
     P.p2p_ptr.assign(1, 0); P.p2p_src.clear();
-    p2p_by_tl.resize(P.tl_le.size());
-    for (auto& v : p2p_by_tl) {
-        for (int sl : v) P.p2p_src.push_back(sl);
+    P.rp_ptr.assign(1, 0); P.rp_fmm.clear(); P.rp_src.clear();
+    S.p2p_by_tl.resize(P.tl_le.size());
+    S.rp_by_tl.resize(P.tl_le.size());
+    for (size_t t = 0; t < P.tl_le.size(); ++t) {
+        for (int sl : S.p2p_by_tl[t]) P.p2p_src.push_back(sl);
         P.p2p_ptr.push_back((int)P.p2p_src.size());
+        for (auto& e : S.rp_by_tl[t]) {
+            P.rp_fmm.push_back(e.first);
+            P.rp_src.push_back(e.second);
+        }
+        P.rp_ptr.push_back((int)P.rp_src.size());
     }
-    (void)p;
     return "";
+}
+
+uint64_t leaf_key(uint64_t lcell, int H, int flip)
+{
+    uint32_t a = (uint32_t)(lcell >> 42) & 0x1fffffu, b = (uint32_t)(lcell >> 21) & 0x1fffffu, c = (uint32_t)lcell & 0x1fffffu;
+    if (flip < 0) c = (uint32_t)((1 << H) - 1) - c;
+    return morton(a, b, c, H);
 }
 
 // ---------------------------------------------------------------------------
