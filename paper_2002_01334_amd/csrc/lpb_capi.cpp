@@ -267,13 +267,10 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(tl_fmm, P.tl_fmm);
     UP(tl_h, P.tl_h);
     UP(tl_ctr, P.tl_ctr);
-    UP(m2m_parent, P.m2m_parent);
-    UP(m2m_ptr, P.m2m_ptr);
-    UP(m2m_child, P.m2m_child);
-    UP(m2m_op, P.m2m_op);
-    UP(l2l_child, P.l2l_child);
-    UP(l2l_parent, P.l2l_parent);
-    UP(l2l_op, P.l2l_op);
+    UP(bw_term_ptr, P.bw_term_ptr);
+    UP(bw_op, P.bw_op);
+    UP(bw_src, P.bw_src);
+    UP(bw_dst, P.bw_dst);
     UP(m2l_ptr, P.m2l_ptr);
     UP(m2l_src, P.m2l_src);
     UP(m2l_op, P.m2l_op);
@@ -361,9 +358,11 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     c->sched.n_p2p_free = (int)pfree.size();
     c->sched.n_m2l_boxes = (int)m2lb.size();
     for (int l = 0; l <= kMaxDepth + 1; ++l) {
-        c->sched.m2m_level_ptr[l] = P.m2m_level_ptr[l];
-        c->sched.l2l_level_ptr[l] = P.l2l_level_ptr[l];
+        c->sched.bm2m_lv[l] = P.bm2m_lv[l];
+        c->sched.bl2l_lv[l] = P.bl2l_lv[l];
     }
+    c->sched.bm2l_w0 = P.bm2l_w0;
+    c->sched.bm2l_w1 = P.bm2l_w1;
     if ((s = upload_points<T>(c, P.s_u, (int)P.s_cidx.size(), &A.s_ux, &A.s_uy, &A.s_uz)) != LPB_OK) return s;
     if ((s = upload_points<T>(c, P.t_u, (int)P.t_cidx.size(), &A.t_ux, &A.t_uy, &A.t_uz)) != LPB_OK) return s;
     T* qs;
@@ -377,6 +376,10 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     A.me = me;
     A.le = le;
     A.n_le = P.n_le;
+    T* scr = nullptr;
+    if (!P.m2l_src.empty())
+        if ((s = dalloc<T>(c, c->plan_bufs, P.m2l_src.size() * (size_t)A.KP, &scr)) != LPB_OK) return s;
+    A.m2l_scratch = scr;
     double* parts;
     if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.nslots * P.ncharges, &parts)) != LPB_OK) return s;
     A.parts = parts;
@@ -459,8 +462,6 @@ lpb_status generate_operators(lpb_ctx* c)
     if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_ops * K * K, &g.d_pool)) != LPB_OK) return s;
     if (g.n_rkeys > 0) HIPCHK(c, hipMemsetAsync(g.d_stab, 0, sizeof(double) * (size_t)g.n_rkeys * 4 * N1 * N1, c->stream));
     g.d_pool32 = nullptr;
-    if (c->opt.precision == LPB_MIXED)
-        if ((s = dalloc<float>(c, c->op_bufs, (size_t)g.n_ops * K * K, &g.d_pool32)) != LPB_OK) return s;
     g.d_flag = (int*)c->d_flag.ptr;
     g.KP = (K + 15) / 16 * 16;
     g.n_swz = (int)P.swz_ops.size();
@@ -486,20 +487,19 @@ lpb_status generate_operators(lpb_ctx* c)
     c->stats.t_opgen_ms = ms;
     if (flag & 1) return fail(c, LPB_ENUMERIC, "Sommerfeld quadrature panel budget exceeded");
     if (flag & 2) return fail(c, LPB_ENUMERIC, "forward recurrence stability bound violated");
+    // the kernels read the operators in the MFMA operand layout only; the
+    // FP64 master copy is no longer needed
+    for (auto& b : c->op_bufs)
+        if (b.ptr == (void*)g.d_pool) {
+            (void)hipFree(b.ptr);
+            b.ptr = nullptr;
+        }
     if (c->opt.precision == LPB_MIXED) {
-        c->a32.pool = g.d_pool32;
         c->a32.pool_swz = g.d_swz32;
-        // the FP64 pool is no longer needed
-        for (auto& b : c->op_bufs)
-            if (b.ptr == (void*)g.d_pool) {
-                (void)hipFree(b.ptr);
-                b.ptr = nullptr;
-            }
-        c->stats.operator_bytes = (int64_t)g.n_ops * K * K * (int64_t)sizeof(float);
+        c->stats.operator_bytes = (int64_t)g.n_swz * g.KP * g.KP * (int64_t)sizeof(float);
     } else {
-        c->a64.pool = g.d_pool;
         c->a64.pool_swz = g.d_swz64;
-        c->stats.operator_bytes = (int64_t)g.n_ops * K * K * (int64_t)sizeof(double);
+        c->stats.operator_bytes = (int64_t)g.n_swz * g.KP * g.KP * (int64_t)sizeof(double);
     }
     c->ops_dirty = false;
     return LPB_OK;

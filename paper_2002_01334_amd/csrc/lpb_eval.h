@@ -24,16 +24,16 @@ struct EvalArgs {
     const int *t_cidx, *t_out;
     const int *tl_start, *tl_le, *tl_fmm;
     const double *tl_h, *tl_ctr;
-    // expansions and operators
+    // expansions
     T* me;
     T* le;
     int n_le;
-    const T* pool;
     // work lists
     const int *p2m_leaves, *l2p_leaves, *p2p_free_leaves;
-    const int *m2m_parent, *m2m_ptr, *m2m_child, *m2m_op;
-    const int *l2l_child, *l2l_parent, *l2l_op;
     const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;
+    // batched translations (M2M, L2L, untiled V-list pairs): see Plan
+    const int *bw_term_ptr, *bw_op, *bw_src, *bw_dst;
+    T* m2l_scratch;     // one KP row per untiled V-list pair
     const int *p2p_ptr, *p2p_src;
     const int *rp_ptr, *rp_fmm, *rp_src;   // reaction near field: per target leaf, (FMM, source leaf)
     int n_react_targets;
@@ -59,8 +59,9 @@ struct EvalArgs {
 
 struct EvalSched {
     int n_p2m, n_l2p, n_p2p_free, n_m2l_boxes;
-    int m2m_level_ptr[kMaxDepth + 2];
-    int l2l_level_ptr[kMaxDepth + 2];
+    int bm2m_lv[kMaxDepth + 2];
+    int bl2l_lv[kMaxDepth + 2];
+    int bm2l_w0, bm2l_w1;
 };
 
 template <typename T>

@@ -169,67 +169,6 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 }
 
 // ---------------------------------------------------------------------------
-// Dense real-form operator application, one block per output box:
-//   out[row] (+)= sum_pairs sum_c Op[c*K + row] * in[c]
-// used for M2M (CSR by parent), M2L (CSR by target) and L2L (one pair).
-template <typename T>
-__device__ inline void apply_pairs(int K, int KP, const T* __restrict__ pool, const T* __restrict__ invec,
-                                   const int* __restrict__ src, const int* __restrict__ op, int b, int e, T* xs, T& acc)
-{
-    const int row = threadIdx.x;
-    for (int k = b; k < e; ++k) {
-        const T* v = invec + (size_t)src[k] * KP;
-        for (int c = threadIdx.x; c < K; c += blockDim.x) xs[c] = v[c];
-        __syncthreads();
-        if (row < K) {
-            const T* O = pool + (size_t)op[k] * K * K;
-            T s0 = T(0), s1 = T(0);
-            int c = 0;
-            for (; c + 1 < K; c += 2) {
-                s0 += O[(size_t)c * K + row] * xs[c];
-                s1 += O[(size_t)(c + 1) * K + row] * xs[c + 1];
-            }
-            if (c < K) s0 += O[(size_t)c * K + row] * xs[c];
-            acc += s0 + s1;
-        }
-        __syncthreads();
-    }
-}
-
-template <typename T>
-__global__ void k_m2m(EvalArgs<T> A, int pbeg)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);
-    const int pi = pbeg + blockIdx.x;
-    T acc = T(0);
-    apply_pairs<T>(A.K, A.KP, A.pool, A.me, A.m2m_child, A.m2m_op, A.m2m_ptr[pi], A.m2m_ptr[pi + 1], xs, acc);
-    if ((int)threadIdx.x < A.K) A.me[(size_t)A.m2m_parent[pi] * A.KP + threadIdx.x] = acc;
-}
-
-template <typename T>
-__global__ void k_m2l(EvalArgs<T> A)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);
-    const int le = A.m2l_boxes[blockIdx.x];
-    T acc = T(0);
-    apply_pairs<T>(A.K, A.KP, A.pool, A.me, A.m2l_src, A.m2l_op, A.m2l_ptr[le], A.m2l_ptr[le + 1], xs, acc);
-    if ((int)threadIdx.x < A.K) A.le[(size_t)le * A.KP + threadIdx.x] += acc;
-}
-
-template <typename T>
-__global__ void k_l2l(EvalArgs<T> A, int cbeg)
-{
-    extern __shared__ unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);
-    const int ci = cbeg + blockIdx.x;
-    T acc = T(0);
-    apply_pairs<T>(A.K, A.KP, A.pool, A.le, A.l2l_parent + ci, A.l2l_op + ci, 0, 1, xs, acc);
-    if ((int)threadIdx.x < A.K) A.le[(size_t)A.l2l_child[ci] * A.KP + threadIdx.x] += acc;
-}
-
-// ---------------------------------------------------------------------------
 // Tiled free-space M2L on the matrix cores.  A tile is 64 target boxes of one
 // (FMM, level) that share a child octant inside a 4x4x4 block of parents, so
 // all of them have the same 189 V-list offsets d and operators A_d.  For each
@@ -253,6 +192,72 @@ __device__ inline Vec4<double>::type mfma16(double a, double b, Vec4<double>::ty
 // output row (within a 16x16 block) of accumulator element r in lane l
 __device__ inline int mfma_row(float, int l, int r) { return 4 * (l >> 4) + r; }
 __device__ inline int mfma_row(double, int l, int r) { return (l >> 4) + 4 * r; }
+
+// acc[rb][cb] = A (rows 16 (w RB + rb) ..) x B (LDS, columns 16 cb ..), with
+// A in the swizzled operand layout (the next 16-column slab of A loads while
+// the current one is multiplied)
+template <typename T, int RB, int CB>
+__device__ __attribute__((always_inline)) inline void mma_block(const T* __restrict__ Aw, const T* Bs, int NTP, int KB, int w, int l,
+                                 typename Vec4<T>::type (&acc)[RB][CB])
+{
+    typedef typename Vec4<T>::type V4;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+    V4 an[RB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        int rbg = w * RB + rb;
+        an[rb] = (rbg < KB) ? *reinterpret_cast<const V4*>(Aw + ((size_t)rbg * KB * 64 + l) * 4) : V4{0, 0, 0, 0};
+    }
+    for (int s4 = 0; s4 < KB; ++s4) {
+        V4 a4[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            a4[rb] = an[rb];
+            int rbg = w * RB + rb;
+            if (rbg < KB && s4 + 1 < KB)
+                an[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4 + 1) * 64 + l) * 4);
+        }
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) {
+            const int kk = 16 * s4 + 4 * ss + (l >> 4);
+            T b[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) b[cb] = Bs[kk * NTP + cb * 16 + (l & 15)];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                if (w * RB + rb < KB) {
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
+                }
+            }
+        }
+    }
+}
+
+// tot += acc, compensated (Kahan) in FP32 so that a sum over many terms keeps
+// the error of a single product
+template <typename T, int RB, int CB>
+__device__ __attribute__((always_inline)) inline void accumulate(const typename Vec4<T>::type (&acc)[RB][CB], typename Vec4<T>::type (&tot)[RB][CB],
+                                  typename Vec4<T>::type (&cmp)[RB][CB])
+{
+    typedef typename Vec4<T>::type V4;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            if (sizeof(T) == 4) {
+                V4 y = acc[rb][cb] - cmp[rb][cb];
+                V4 t = tot[rb][cb] + y;
+                cmp[rb][cb] = (t - tot[rb][cb]) - y;
+                tot[rb][cb] = t;
+            } else {
+                tot[rb][cb] += acc[rb][cb];
+            }
+        }
+}
 
 template <typename T, int RB>
 __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
@@ -385,6 +390,114 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
                 if (row < K) A.le[(size_t)le * KP + row] += tot[rb][cb][r];
             }
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched dense translations on the matrix cores: M2M (eq. metome, one term
+// per child octant), L2L (one term, 64 children of one octant) and the V-list
+// pairs outside the tiled levels (one term, up to 64 pairs of one operator).
+// Work item w computes for its 64 columns j
+//   y_j = sum_t A_{op_t} x_{src_t[j]}     (x = 0 for a missing source)
+// and stores y_j (mode 0) or adds it (mode 1) to row dst[j] of `out`.
+// Sources are gathered into LDS as in the tiled M2L, the next term's sources
+// load during the current term's products.
+template <typename T, int RB>
+__global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
+                                                 const int* __restrict__ term_op, const int* __restrict__ term_src,
+                                                 const int* __restrict__ dst, int wbase, int mode, int K, int KP,
+                                                 const T* __restrict__ pool_swz)
+{
+    typedef typename Vec4<T>::type V4;
+    constexpr int NT = 64, CB = 4, GMAX = 4 * RB;
+    constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);
+    extern __shared__ unsigned char smem_raw[];
+    T* Bs = reinterpret_cast<T*>(smem_raw);   // [KP][NTP]
+    const int KB = KP / 16;
+    const int wi = wbase + blockIdx.x;
+    const int t0 = term_ptr[wi], t1 = term_ptr[wi + 1];
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int gj = tid >> 2, gpart = tid & 3;
+    V4 acc[RB][CB], tot[RB][CB], cmp[RB][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
+    V4 greg[GMAX];
+    auto fetch = [&](int t) {
+        const int sidx = term_src[(size_t)t * NT + gj];
+        const T* src = in + (size_t)(sidx < 0 ? 0 : sidx) * KP + 4 * gpart;
+#pragma unroll
+        for (int i = 0; i < GMAX; ++i)
+            greg[i] = (sidx >= 0 && i < KB) ? *reinterpret_cast<const V4*>(src + 16 * i) : V4{0, 0, 0, 0};
+    };
+    if (t0 < t1) fetch(t0);
+    for (int t = t0; t < t1; ++t) {
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < GMAX; ++i) {
+            if (i < KB) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
+            }
+        }
+        __syncthreads();
+        const T* Aw = pool_swz + (size_t)term_op[t] * KP * KP;
+        if (t + 1 < t1) fetch(t + 1);
+        mma_block<T, RB, CB>(Aw, Bs, NTP, KB, w, l, acc);
+        accumulate<T, RB, CB>(acc, tot, cmp);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        int rbg = w * RB + rb;
+        if (rbg >= KB) continue;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int d = dst[(size_t)wi * NT + cb * 16 + (l & 15)];
+            if (d < 0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = rbg * 16 + mfma_row(T(0), l, r);
+                if (row >= K) continue;
+                if (mode == 0) out[(size_t)d * KP + row] = tot[rb][cb][r];
+                else out[(size_t)d * KP + row] += tot[rb][cb][r];
+            }
+        }
+    }
+}
+
+template <typename T>
+static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, T* out, int mode, hipStream_t st)
+{
+    if (w1 <= w0) return;
+    const int KB = A.KP / 16, RB = (KB + 3) / 4;
+    const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
+    dim3 g(w1 - w0), b(256);
+#define LPB_BATCHED(R) \
+    hipLaunchKernelGGL((k_batched<T, R>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, A.K, A.KP, A.pool_swz)
+    switch (RB) {
+    case 1: LPB_BATCHED(1); break;
+    case 2: LPB_BATCHED(2); break;
+    case 3: LPB_BATCHED(3); break;
+    case 4: LPB_BATCHED(4); break;
+    case 5: LPB_BATCHED(5); break;
+    case 6: LPB_BATCHED(6); break;
+    default: LPB_BATCHED(7); break;
+    }
+#undef LPB_BATCHED
+}
+
+// V-list pairs outside the tiled levels: LE[box] += sum of the box's pair rows
+// of the scratch, in list order (deterministic)
+template <typename T>
+__global__ void k_m2l_reduce(EvalArgs<T> A)
+{
+    const int le = A.m2l_boxes[blockIdx.x];
+    const int k0 = A.m2l_ptr[le], k1 = A.m2l_ptr[le + 1];
+    for (int row = threadIdx.x; row < A.K; row += blockDim.x) {
+        T s = T(0);
+        for (int k = k0; k < k1; ++k) s += A.m2l_scratch[(size_t)k * A.KP + row];
+        A.le[(size_t)le * A.KP + row] += s;
     }
 }
 
@@ -624,7 +737,6 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
 #define LPB_MARK(k) \
     if (ev) (void)hipEventRecord(ev[k], st)
     const int K = A.K, p = A.p;
-    const int bsz = ((K + 63) / 64) * 64;
     LPB_MARK(0);
     if (A.n_src > 0) hipLaunchKernelGGL(k_gather_q<T>, dim3((A.n_src + 255) / 256), dim3(256), 0, st, A.n_src, A.s_cidx, A.q, A.qs);
     hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, st, (size_t)A.nslots * A.ncharges, A.parts);
@@ -644,20 +756,17 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
         hipLaunchKernelGGL(k_p2m<T>, dim3(S.n_p2m), dim3(64), sm, st, A, ch);
     }
     LPB_MARK(2);
-    for (int l = kMaxDepth; l >= 0; --l) {
-        int b = S.m2m_level_ptr[l], e = S.m2m_level_ptr[l + 1];
-        if (far && e > b) hipLaunchKernelGGL(k_m2m<T>, dim3(e - b), dim3(bsz), sizeof(T) * K, st, A, b);
-    }
+    for (int l = kMaxDepth; l >= 0 && far; --l) launch_batched<T>(A, S.bm2m_lv[l], S.bm2m_lv[l + 1], A.me, A.me, 0, st);
     // V-list translations (all levels), then the downward pass
     LPB_MARK(3);
     if (far && A.n_tiles > 0) launch_m2l_tile<T>(A, st);
     LPB_MARK(4);
-    if (far && S.n_m2l_boxes > 0) hipLaunchKernelGGL(k_m2l<T>, dim3(S.n_m2l_boxes), dim3(bsz), sizeof(T) * K, st, A);
-    LPB_MARK(5);
-    for (int l = 0; l <= kMaxDepth; ++l) {
-        int b = S.l2l_level_ptr[l], e = S.l2l_level_ptr[l + 1];
-        if (far && e > b) hipLaunchKernelGGL(k_l2l<T>, dim3(e - b), dim3(bsz), sizeof(T) * K, st, A, b);
+    if (far && S.bm2l_w1 > S.bm2l_w0) {
+        launch_batched<T>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.m2l_scratch, 0, st);
+        hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(128), 0, st, A);
     }
+    LPB_MARK(5);
+    for (int l = 0; l <= kMaxDepth && far; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.le, 1, st);
     LPB_MARK(6);
     if (far && S.n_l2p > 0) {
         size_t sm = sizeof(T) * (size_t)(p + 1) * 64;

@@ -125,14 +125,15 @@ struct Plan {
     std::vector<uint64_t> s_lcell, t_lcell;               // leaf cell of each point (canonical, diagnostics)
     // boxes
     int n_me = 0, n_le = 0;
-    // M2M: CSR by parent ME box (levels >= 2), children ME + operator
-    std::vector<int> m2m_parent, m2m_ptr, m2m_child, m2m_op;
-    std::vector<int> m2m_level_ptr;   // parents of level l at [m2m_level_ptr[l], m2m_level_ptr[l+1])
-    // L2L: child LE box -> parent LE box + operator, grouped by level
-    std::vector<int> l2l_child, l2l_parent, l2l_op;
-    std::vector<int> l2l_level_ptr;
     // M2L: CSR by target LE box
     std::vector<int> m2l_ptr, m2l_src, m2l_op;   // m2l_ptr has n_le+1
+    // batched dense translations on the matrix cores: work item w has terms
+    // [bw_term_ptr[w], bw_term_ptr[w+1]), term t = operator bw_op[t] and 64
+    // source rows bw_src[64 t + j]; 64 destination rows bw_dst[64 w + j] (-1: none)
+    std::vector<int> bw_term_ptr, bw_op, bw_src, bw_dst;
+    std::vector<int> bm2m_lv, bl2l_lv;   // work items of M2M (parent level) / L2L (child level) l: [v[l], v[l+1])
+    int bm2l_w0 = 0, bm2l_w1 = 0;        // V-list pairs outside the tiled levels, grouped by operator;
+                                         // destination = the pair's position in m2l_src (scratch row)
     // near field: CSR by target leaf over free-space source leaves, and over
     // (reaction FMM, source leaf) pairs
     std::vector<int> p2p_ptr, p2p_src;
@@ -146,8 +147,8 @@ struct Plan {
     std::vector<Tile> tiles;
     std::vector<int> grid_me, grid_le, optab;
     std::vector<int> oct_codes;    // 8 x 189 offset codes ((dx+3)*7+(dy+3))*7+(dz+3)
-    std::vector<int> swz_ops;      // operators stored in the MFMA operand layout (free-space M2L)
-    std::vector<int> swz_index;    // op -> position in swz_ops (-1 if none)
+    std::vector<int> swz_ops;      // operators stored in the MFMA operand layout (all of them)
+    std::vector<int> swz_index;    // op -> position in swz_ops
 };
 
 // Build the plan for all systems (host).  Returns an error message or "".

@@ -91,10 +91,16 @@ struct TreeB {
     int id = -1;                 // index into Plan::trees
 };
 
+// One batched work item (64 columns).
+struct BWork {
+    std::vector<int> op;    // per term
+    std::vector<int> src;   // 64 per term
+    std::array<int, 64> dst;
+};
+
 // Staging shared by the tree and list builders.
 struct Staging {
-    std::vector<std::vector<std::array<int, 3>>> m2m_by_level{(size_t)kMaxDepth + 1};   // parent, child, op
-    std::vector<std::vector<std::array<int, 3>>> l2l_by_level{(size_t)kMaxDepth + 1};   // child, parent, op
+    std::vector<std::vector<BWork>> bm2m{(size_t)kMaxDepth + 1}, bl2l{(size_t)kMaxDepth + 1};
     std::vector<std::vector<std::pair<int, int>>> m2l_by_le;    // per LE box: (source ME, op)
     std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: free-space source leaves
     std::vector<std::vector<std::pair<int, int>>> rp_by_tl;     // per target leaf: (reaction FMM, source leaf)
@@ -228,21 +234,45 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
             opo[o] = (int)P.ops.size();
             P.ops.push_back(d);
         }
+        const int n = (int)T.B[lv].mkey.size();
         if (target) {
-            for (int k = 0; k < (int)T.B[lv].mkey.size(); ++k) {
+            // L2L: children of one octant share the operator; 64 per work item
+            std::vector<int> byo[8];
+            for (int k = 0; k < n; ++k) {
                 int ix = T.B[lv].ix[k], iy = T.B[lv].iy[k], iz = T.B[lv].iz[k];
-                int pk = T.B[lv - 1].idx.at(cellkey(ix >> 1, iy >> 1, iz >> 1));
-                int o = ((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1);
-                S.l2l_by_level[lv].push_back({T.off[lv] + k, T.off[lv - 1] + pk, opo[o]});
+                byo[((ix & 1) << 2) | ((iy & 1) << 1) | (iz & 1)].push_back(k);
             }
-        } else {
-            for (int k = 0; k < (int)T.B[lv].mkey.size(); ++k) {
-                int px = T.B[lv].ix[k], py = T.B[lv].iy[k], pz = T.B[lv].iz[k];
-                for (int o = 0; o < 8; ++o) {
-                    auto it = T.B[lv + 1].idx.find(cellkey(2 * px + ((o >> 2) & 1), 2 * py + ((o >> 1) & 1), 2 * pz + (o & 1)));
-                    if (it == T.B[lv + 1].idx.end()) continue;
-                    S.m2m_by_level[lv].push_back({T.off[lv] + k, T.off[lv + 1] + it->second, opo[o]});
+            for (int o = 0; o < 8; ++o)
+                for (size_t c0 = 0; c0 < byo[o].size(); c0 += 64) {
+                    BWork wk;
+                    wk.dst.fill(-1);
+                    wk.op.assign(1, opo[o]);
+                    wk.src.assign(64, -1);
+                    for (size_t j = 0; j < 64 && c0 + j < byo[o].size(); ++j) {
+                        int k = byo[o][c0 + j];
+                        int ix = T.B[lv].ix[k], iy = T.B[lv].iy[k], iz = T.B[lv].iz[k];
+                        wk.src[j] = T.off[lv - 1] + T.B[lv - 1].idx.at(cellkey(ix >> 1, iy >> 1, iz >> 1));
+                        wk.dst[j] = T.off[lv] + k;
+                    }
+                    S.bl2l[lv].push_back(std::move(wk));
                 }
+        } else {
+            // M2M: 64 parents per work item, one term per child octant
+            for (int c0 = 0; c0 < n; c0 += 64) {
+                BWork wk;
+                wk.dst.fill(-1);
+                wk.op.assign(opo, opo + 8);
+                wk.src.assign(8 * 64, -1);
+                for (int j = 0; j < 64 && c0 + j < n; ++j) {
+                    int k = c0 + j;
+                    int px = T.B[lv].ix[k], py = T.B[lv].iy[k], pz = T.B[lv].iz[k];
+                    wk.dst[j] = T.off[lv] + k;
+                    for (int o = 0; o < 8; ++o) {
+                        auto it = T.B[lv + 1].idx.find(cellkey(2 * px + ((o >> 2) & 1), 2 * py + ((o >> 1) & 1), 2 * pz + (o & 1)));
+                        if (it != T.B[lv + 1].idx.end()) wk.src[64 * o + j] = T.off[lv + 1] + it->second;
+                    }
+                }
+                S.bm2m[lv].push_back(std::move(wk));
             }
         }
     }
@@ -629,34 +659,6 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         P.t_u[2 * S.t_ux.size() + i] = S.t_uz[i];
     }
     for (size_t i = 0; i < P.t_out.size(); ++i) P.t_out[i] = (int)(P.t_out[i] * P.ncharges + P.t_cidx[i]);
-    P.m2m_parent.clear(); P.m2m_ptr.assign(1, 0); P.m2m_child.clear(); P.m2m_op.clear();
-    P.m2m_level_ptr.assign(kMaxDepth + 2, 0);
-    for (int lv = 0; lv <= kMaxDepth; ++lv) {
-        P.m2m_level_ptr[lv] = (int)P.m2m_parent.size();
-        auto& v = S.m2m_by_level[lv];
-        std::stable_sort(v.begin(), v.end(), [](const std::array<int, 3>& a, const std::array<int, 3>& b) { return a[0] < b[0]; });
-        for (size_t i = 0; i < v.size(); ++i) {
-            if (i == 0 || v[i][0] != v[i - 1][0]) {
-                if (i > 0) P.m2m_ptr.push_back((int)P.m2m_child.size());
-                P.m2m_parent.push_back(v[i][0]);
-            }
-            P.m2m_child.push_back(v[i][1]);
-            P.m2m_op.push_back(v[i][2]);
-        }
-        if (!v.empty()) P.m2m_ptr.push_back((int)P.m2m_child.size());
-    }
-    P.m2m_level_ptr[kMaxDepth + 1] = (int)P.m2m_parent.size();
-    P.l2l_child.clear(); P.l2l_parent.clear(); P.l2l_op.clear();
-    P.l2l_level_ptr.assign(kMaxDepth + 2, 0);
-    for (int lv = 0; lv <= kMaxDepth; ++lv) {
-        P.l2l_level_ptr[lv] = (int)P.l2l_child.size();
-        for (auto& r : S.l2l_by_level[lv]) {
-            P.l2l_child.push_back(r[0]);
-            P.l2l_parent.push_back(r[1]);
-            P.l2l_op.push_back(r[2]);
-        }
-    }
-    P.l2l_level_ptr[kMaxDepth + 1] = (int)P.l2l_child.size();
     P.m2l_ptr.assign(1, 0); P.m2l_src.clear(); P.m2l_op.clear();
     S.m2l_by_le.resize(P.n_le);
     for (int i = 0; i < P.n_le; ++i) {
@@ -666,13 +668,52 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         }
         P.m2l_ptr.push_back((int)P.m2l_src.size());
     }
-    P.swz_ops.clear();
-    P.swz_index.assign(P.ops.size(), -1);
-    for (size_t i = 0; i < P.ops.size(); ++i)
-        if (P.ops[i].type == OP_M2L_FREE) {
-            P.swz_index[i] = (int)P.swz_ops.size();
-            P.swz_ops.push_back((int)i);
+    // batched work items: M2M and L2L per level, then the V-list pairs outside
+    // the tiled levels grouped by operator
+    P.bw_term_ptr.assign(1, 0); P.bw_op.clear(); P.bw_src.clear(); P.bw_dst.clear();
+    auto push_work = [&](const BWork& wk) {
+        P.bw_op.insert(P.bw_op.end(), wk.op.begin(), wk.op.end());
+        P.bw_src.insert(P.bw_src.end(), wk.src.begin(), wk.src.end());
+        P.bw_dst.insert(P.bw_dst.end(), wk.dst.begin(), wk.dst.end());
+        P.bw_term_ptr.push_back((int)P.bw_op.size());
+    };
+    P.bm2m_lv.assign(kMaxDepth + 2, 0);
+    P.bl2l_lv.assign(kMaxDepth + 2, 0);
+    for (int lv = 0; lv <= kMaxDepth; ++lv) {
+        P.bm2m_lv[lv] = (int)P.bw_term_ptr.size() - 1;
+        for (auto& wk : S.bm2m[lv]) push_work(wk);
+    }
+    P.bm2m_lv[kMaxDepth + 1] = (int)P.bw_term_ptr.size() - 1;
+    for (int lv = 0; lv <= kMaxDepth; ++lv) {
+        P.bl2l_lv[lv] = (int)P.bw_term_ptr.size() - 1;
+        for (auto& wk : S.bl2l[lv]) push_work(wk);
+    }
+    P.bl2l_lv[kMaxDepth + 1] = (int)P.bw_term_ptr.size() - 1;
+    P.bm2l_w0 = (int)P.bw_term_ptr.size() - 1;
+    {
+        std::vector<std::pair<int, int>> byop(P.m2l_op.size());   // (op, pair position)
+        for (size_t k = 0; k < P.m2l_op.size(); ++k) byop[k] = {P.m2l_op[k], (int)k};
+        std::sort(byop.begin(), byop.end());
+        for (size_t i = 0; i < byop.size();) {
+            size_t e = i;
+            while (e < byop.size() && e - i < 64 && byop[e].first == byop[i].first) ++e;
+            BWork wk;
+            wk.dst.fill(-1);
+            wk.op.assign(1, byop[i].first);
+            wk.src.assign(64, -1);
+            for (size_t j = i; j < e; ++j) {
+                wk.src[j - i] = P.m2l_src[byop[j].second];
+                wk.dst[j - i] = byop[j].second;
+            }
+            push_work(wk);
+            i = e;
         }
+    }
+    P.bm2l_w1 = (int)P.bw_term_ptr.size() - 1;
+    // every operator is stored in the MFMA operand layout
+    P.swz_ops.resize(P.ops.size());
+    P.swz_index.resize(P.ops.size());
+    for (size_t i = 0; i < P.ops.size(); ++i) P.swz_ops[i] = P.swz_index[i] = (int)i;
     P.p2p_ptr.assign(1, 0); P.p2p_src.clear();
     P.rp_ptr.assign(1, 0); P.rp_fmm.clear(); P.rp_src.clear();
     S.p2p_by_tl.resize(P.tl_le.size());
