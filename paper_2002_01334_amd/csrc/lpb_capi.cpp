@@ -369,13 +369,16 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     if ((s = dalloc<T>(c, c->plan_bufs, P.s_cidx.size(), &qs)) != LPB_OK) return s;
     A.qs = qs;
     T *me, *le;
-    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_me * A.KP, &me)) != LPB_OK) return s;
-    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_le * A.KP, &le)) != LPB_OK) return s;
+    // one extra zero row after the last box of each (missing sources of the batched products read it)
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)(P.n_me + 1) * A.KP, &me)) != LPB_OK) return s;
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)(P.n_le + 1) * A.KP, &le)) != LPB_OK) return s;
+    HIPCHK(c, hipMemset(le, 0, sizeof(T) * (size_t)(P.n_le + 1) * A.KP));
     // the padding rows k >= K of the expansions are read by the tiled M2L and must stay zero
-    HIPCHK(c, hipMemset(me, 0, sizeof(T) * std::max<size_t>((size_t)P.n_me * A.KP, 1)));
+    HIPCHK(c, hipMemset(me, 0, sizeof(T) * (size_t)(P.n_me + 1) * A.KP));
     A.me = me;
     A.le = le;
     A.n_le = P.n_le;
+    A.n_me = P.n_me;
     T* scr = nullptr;
     if (!P.m2l_src.empty())
         if ((s = dalloc<T>(c, c->plan_bufs, P.m2l_src.size() * (size_t)A.KP, &scr)) != LPB_OK) return s;

@@ -24,10 +24,10 @@ struct EvalArgs {
     const int *t_cidx, *t_out;
     const int *tl_start, *tl_le, *tl_fmm;
     const double *tl_h, *tl_ctr;
-    // expansions
+    // expansions: n_me (n_le) rows of KP, plus a zero row at index n_me (n_le)
     T* me;
     T* le;
-    int n_le;
+    int n_le, n_me;
     // work lists
     const int *p2m_leaves, *l2p_leaves, *p2p_free_leaves;
     const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;

@@ -205,20 +205,21 @@ __device__ __attribute__((always_inline)) inline void mma_block(const T* __restr
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+    // row blocks past KB repeat the last one (their rows are >= K, never stored)
     V4 an[RB];
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        int rbg = w * RB + rb;
-        an[rb] = (rbg < KB) ? *reinterpret_cast<const V4*>(Aw + ((size_t)rbg * KB * 64 + l) * 4) : V4{0, 0, 0, 0};
+        int rbg = min(w * RB + rb, KB - 1);
+        an[rb] = *reinterpret_cast<const V4*>(Aw + ((size_t)rbg * KB * 64 + l) * 4);
     }
     for (int s4 = 0; s4 < KB; ++s4) {
         V4 a4[RB];
+        const int s4n = min(s4 + 1, KB - 1);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             a4[rb] = an[rb];
-            int rbg = w * RB + rb;
-            if (rbg < KB && s4 + 1 < KB)
-                an[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4 + 1) * 64 + l) * 4);
+            int rbg = min(w * RB + rb, KB - 1);
+            an[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4n) * 64 + l) * 4);
         }
 #pragma unroll
         for (int ss = 0; ss < 4; ++ss) {
@@ -227,12 +228,9 @@ __device__ __attribute__((always_inline)) inline void mma_block(const T* __restr
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) b[cb] = Bs[kk * NTP + cb * 16 + (l & 15)];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                if (w * RB + rb < KB) {
+            for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
-                }
-            }
+                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
         }
     }
 }
@@ -406,7 +404,7 @@ template <typename T, int RB>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
                                                  const int* __restrict__ dst, int wbase, int mode, int K, int KP,
-                                                 const T* __restrict__ pool_swz)
+                                                 const T* __restrict__ pool_swz, int zrow)
 {
     typedef typename Vec4<T>::type V4;
     constexpr int NT = 64, CB = 4, GMAX = 4 * RB;
@@ -426,10 +424,9 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     V4 greg[GMAX];
     auto fetch = [&](int t) {
         const int sidx = term_src[(size_t)t * NT + gj];
-        const T* src = in + (size_t)(sidx < 0 ? 0 : sidx) * KP + 4 * gpart;
+        const T* src = in + (size_t)(sidx < 0 ? zrow : sidx) * KP + 4 * gpart;   // missing: the zero row
 #pragma unroll
-        for (int i = 0; i < GMAX; ++i)
-            greg[i] = (sidx >= 0 && i < KB) ? *reinterpret_cast<const V4*>(src + 16 * i) : V4{0, 0, 0, 0};
+        for (int i = 0; i < GMAX; ++i) greg[i] = (i < KB) ? *reinterpret_cast<const V4*>(src + 16 * i) : V4{0, 0, 0, 0};
     };
     if (t0 < t1) fetch(t0);
     for (int t = t0; t < t1; ++t) {
@@ -467,14 +464,14 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
 }
 
 template <typename T>
-static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, T* out, int mode, hipStream_t st)
+static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, int zrow, T* out, int mode, hipStream_t st)
 {
     if (w1 <= w0) return;
     const int KB = A.KP / 16, RB = (KB + 3) / 4;
     const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
     dim3 g(w1 - w0), b(256);
 #define LPB_BATCHED(R) \
-    hipLaunchKernelGGL((k_batched<T, R>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, A.K, A.KP, A.pool_swz)
+    hipLaunchKernelGGL((k_batched<T, R>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, A.K, A.KP, A.pool_swz, zrow)
     switch (RB) {
     case 1: LPB_BATCHED(1); break;
     case 2: LPB_BATCHED(2); break;
@@ -501,12 +498,171 @@ __global__ void k_m2l_reduce(EvalArgs<T> A)
     }
 }
 
+// The same product with the number of 16-row blocks KB fixed at compile
+// time (p <= 15): the 16-column slabs of the operator stream through a ring
+// of D register slabs, so every load is issued D slabs (D * RB * 4 MFMAs)
+// ahead of its use, continuing across offsets into the next operator.
+template <typename T, int KB>
+__global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
+{
+    typedef typename Vec4<T>::type V4;
+    constexpr int RB = (KB + 3) / 4;
+    constexpr int NWACT = (KB + RB - 1) / RB;   // waves that own row blocks (the others only gather)
+    constexpr int D = (sizeof(T) == 4 && RB <= 2) ? ((KB % 4 == 0) ? 4 : ((KB % 2 == 0) ? 2 : 1))
+                                                  : ((KB % 2 == 0) ? 2 : 1);
+    constexpr int NT = 64, CB = 4, KP = 16 * KB;
+    constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);   // padded LDS row (bank spread)
+    extern __shared__ unsigned char smem_raw[];
+    T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
+    __shared__ int s_le[NT];
+    const int K = A.K;
+    const Tile tile = A.tiles[blockIdx.x];
+    const TileFL fl = A.tfl[tile.fl];
+    const int nside = fl.nside;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
+    V4 acc[RB][CB], tot[RB][CB], cmp[RB][CB];
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
+    auto tcoord = [&](int j, int& tx, int& ty, int& tz) {
+        tx = 2 * (tile.px0 + (j >> 4)) + ox;
+        ty = 2 * (tile.py0 + ((j >> 2) & 3)) + oy;
+        tz = 2 * (tile.pz0 + (j & 3)) + oz;
+    };
+    if (tid < NT) {
+        int tx, ty, tz;
+        tcoord(tid, tx, ty, tz);
+        s_le[tid] = (tx < nside && ty < nside && tz < nside)
+                        ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
+    }
+    __syncthreads();
+    const int gj = tid >> 2, gpart = tid & 3;
+    int gtx, gty, gtz;
+    tcoord(gj, gtx, gty, gtz);
+    const bool gvalid = s_le[gj] >= 0;
+    const int* codes = A.oct_codes + tile.octant * kVOffsets;
+    V4 greg[KB];
+    auto fetch = [&](int d) {
+        const int code = codes[d];
+        const int sx = gtx + code / 49 - 3, sy = gty + (code / 7) % 7 - 3, sz = gtz + code % 7 - 3;
+        int me = -1;
+        if (gvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
+            me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
+        // a missing source reads the zero row
+        const T* src = A.me + (size_t)(me < 0 ? A.n_me : me) * KP + 4 * gpart;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) greg[i] = *reinterpret_cast<const V4*>(src + 16 * i);
+    };
+    auto opA = [&](int d) { return A.pool_swz + (size_t)A.swz_index[A.optab[fl.optab_off + codes[d]]] * KP * KP; };
+    V4 ring[D][RB];
+    // row blocks past KB (last active wave only) repeat the last block; their
+    // rows are >= K and never stored
+    auto loadA = [&](const T* Aw, int s4, V4 (&dst)[RB]) {
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int rbg = min(w * RB + rb, KB - 1);
+            dst[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4) * 64 + l) * 4);
+        }
+    };
+    const T* Aw = opA(0);
+    if (w < NWACT) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) loadA(Aw, i, ring[i]);
+    }
+    fetch(0);
+    for (int d = 0; d < kVOffsets; ++d) {
+        __syncthreads();   // every wave is done with the previous offset's B
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
+        }
+        __syncthreads();
+        const bool more = d + 1 < kVOffsets;
+        const T* Awn = more ? opA(d + 1) : Aw;
+        if (more) fetch(d + 1);   // next offset's sources load during this offset's products
+        if (w < NWACT) {          // wave-uniform; the product loop itself has no branches
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+#pragma unroll
+            for (int s4 = 0; s4 < KB; ++s4) {
+                V4 a4[RB];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) a4[rb] = ring[s4 % D][rb];
+                if (s4 + D < KB) loadA(Aw, s4 + D, ring[s4 % D]);
+                else loadA(Awn, s4 + D - KB, ring[s4 % D]);   // (the last offset reloads its own operator)
+#pragma unroll
+                for (int ss = 0; ss < 4; ++ss) {
+                    const int kk = 16 * s4 + 4 * ss + (l >> 4);
+                    T b[CB];
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) b[cb] = Bs[kk * NTP + cb * 16 + (l & 15)];
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
+                }
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    if (sizeof(T) == 4) {
+                        V4 y = acc[rb][cb] - cmp[rb][cb];
+                        V4 t = tot[rb][cb] + y;
+                        cmp[rb][cb] = (t - tot[rb][cb]) - y;
+                        tot[rb][cb] = t;
+                    } else {
+                        tot[rb][cb] += acc[rb][cb];
+                    }
+                }
+        }
+        Aw = Awn;
+    }
+    if (w >= NWACT) return;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) {
+        int rbg = w * RB + rb;
+        if (rbg >= KB) continue;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            int j = cb * 16 + (l & 15);
+            int le = s_le[j];
+            if (le < 0) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                int row = rbg * 16 + mfma_row(T(0), l, r);
+                if (row < K) A.le[(size_t)le * KP + row] += tot[rb][cb][r];
+            }
+        }
+    }
+}
+
 template <typename T>
 static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
 {
     const int KB = A.KP / 16, RB = (KB + 3) / 4;
     const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
     dim3 g(A.n_tiles), b(256);
+#define LPB_TKB(N) \
+    case N: hipLaunchKernelGGL((k_m2l_tile_kb<T, N>), g, b, sm, st, A); return;
+    switch (KB) {
+        LPB_TKB(1) LPB_TKB(2) LPB_TKB(3) LPB_TKB(4) LPB_TKB(5) LPB_TKB(6)
+        LPB_TKB(7) LPB_TKB(8) LPB_TKB(9) LPB_TKB(10) LPB_TKB(11) LPB_TKB(12)
+    default: break;
+    }
+    // FP64 at KB > 12 would spill registers: it takes the generic kernel below
+    if constexpr (sizeof(T) == 4) {
+        switch (KB) {
+            LPB_TKB(13) LPB_TKB(14) LPB_TKB(15) LPB_TKB(16)
+        default: break;
+        }
+    }
+#undef LPB_TKB
     switch (RB) {
     case 1: hipLaunchKernelGGL((k_m2l_tile<T, 1>), g, b, sm, st, A); break;
     case 2: hipLaunchKernelGGL((k_m2l_tile<T, 2>), g, b, sm, st, A); break;
@@ -756,17 +912,17 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
         hipLaunchKernelGGL(k_p2m<T>, dim3(S.n_p2m), dim3(64), sm, st, A, ch);
     }
     LPB_MARK(2);
-    for (int l = kMaxDepth; l >= 0 && far; --l) launch_batched<T>(A, S.bm2m_lv[l], S.bm2m_lv[l + 1], A.me, A.me, 0, st);
+    for (int l = kMaxDepth; l >= 0 && far; --l) launch_batched<T>(A, S.bm2m_lv[l], S.bm2m_lv[l + 1], A.me, A.n_me, A.me, 0, st);
     // V-list translations (all levels), then the downward pass
     LPB_MARK(3);
     if (far && A.n_tiles > 0) launch_m2l_tile<T>(A, st);
     LPB_MARK(4);
     if (far && S.bm2l_w1 > S.bm2l_w0) {
-        launch_batched<T>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.m2l_scratch, 0, st);
+        launch_batched<T>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
         hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(128), 0, st, A);
     }
     LPB_MARK(5);
-    for (int l = 0; l <= kMaxDepth && far; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.le, 1, st);
+    for (int l = 0; l <= kMaxDepth && far; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.n_le, A.le, 1, st);
     LPB_MARK(6);
     if (far && S.n_l2p > 0) {
         size_t sm = sizeof(T) * (size_t)(p + 1) * 64;
