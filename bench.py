@@ -11,10 +11,17 @@ value = charges/sec of the mixed-precision form (FP32 bulk, FP64 Bessel and
 operator generation).  The plain FP64 GPU path is timed beside it
 (fp64_value) and the mixed result's per-layer relative l2 error against it is
 reported (rel_err_vs_fp64, gate 1e-6).
+
+Other workloads (--workload): clustered (1e5 charges per layer, half of them
+Gaussian with sigma 0.1 about the cube centre; default p = 6) and batch (256
+independent systems of uneven sizes and random media evaluated by one batched
+call; default p = 8).  --p overrides the order (e.g. 15 on the default
+workload).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -36,6 +43,27 @@ def err2_per_layer(a, b, layer):
     return [float(np.linalg.norm(a[layer == l] - b[layer == l]) / np.linalg.norm(b[layer == l])) for l in range(3)]
 
 
+def _time_evals(ctx, torch, run, steps, warmup):
+    """warmup untimed calls (the first also generates the operators), then
+    `steps` timed calls; per-call and per-stage times from the library's HIP
+    events on its stream, wall time around the whole loop."""
+    for _ in range(max(1, warmup)):
+        run()
+    torch.cuda.synchronize()
+    stage = {k: 0.0 for k in ctx.stats()["t_stage_ms"]}
+    evals = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        run()
+        s = ctx.stats()
+        evals.append(s["t_eval_ms"])
+        for k, v in s["t_stage_ms"].items():
+            stage[k] += v / steps
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    return float(np.mean(evals)), stage, wall
+
+
 def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup):
     dev = torch.device("cuda:0")
     t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device=dev) for k in ("x", "y", "z", "q")}
@@ -46,44 +74,66 @@ def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup):
     ctx.build_tree(t["x"], t["y"], t["z"])
     t_build = time.perf_counter() - t0
     phi = torch.empty_like(t["q"])
-    for _ in range(max(1, warmup)):          # the first call also generates the operators
-        ctx.evaluate(t["q"], phi)
-    torch.cuda.synchronize()
-    st0 = ctx.stats()
-    stage = {k: 0.0 for k in st0["t_stage_ms"]}
-    evals = []
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        ctx.evaluate(t["q"], phi)
-        s = ctx.stats()
-        evals.append(s["t_eval_ms"])
-        for k, v in s["t_stage_ms"].items():
-            stage[k] += v / steps
-    torch.cuda.synchronize()
-    wall = (time.perf_counter() - t0) / steps
+    ms, stage, wall = _time_evals(ctx, torch, lambda: ctx.evaluate(t["q"], phi), steps, warmup)
     out = phi.cpu().numpy()
     stats = ctx.stats()
     ctx.close()
-    return {"wall_s": wall, "eval_ms": float(np.mean(evals)), "stage_ms": stage, "stats": stats,
-            "t_build_s": t_build, "phi": out}
+    return {"wall_s": wall, "eval_ms": ms, "stage_ms": stage, "stats": stats, "t_build_s": t_build, "phi": out}
 
 
-def cpu_baseline(per_layer, p, leaf_cap):
-    """The oracle FMM (plain C, FP64, all host threads) on a bounded sample."""
+def time_batch(lpb, torch, probs, p, leaf_cap, precision, steps, warmup):
+    dev = torch.device("cuda:0")
+    ts = [{k: torch.tensor(getattr(pr, k), dtype=torch.float64, device=dev) for k in ("x", "y", "z", "q")}
+          for pr in probs]
+    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=1,
+                      stream=torch.cuda.current_stream().cuda_stream)
+    ctx.set_systems([pr.eps for pr in probs], [pr.lam for pr in probs], [pr.d for pr in probs])
+    t0 = time.perf_counter()
+    ctx.build_trees([t["x"] for t in ts], [t["y"] for t in ts], [t["z"] for t in ts])
+    t_build = time.perf_counter() - t0
+    outs = [torch.empty_like(t["q"]) for t in ts]
+    qs = [t["q"] for t in ts]
+    ms, stage, wall = _time_evals(ctx, torch, lambda: ctx.evaluate_batch(qs, outs), steps, warmup)
+    res = [o.cpu().numpy() for o in outs]
+    stats = ctx.stats()
+    ctx.close()
+    return {"wall_s": wall, "eval_ms": ms, "stage_ms": stage, "stats": stats, "t_build_s": t_build, "phi": res}
+
+
+def cpu_baseline(probs, p, leaf_cap, what):
+    """The oracle FMM (plain C, FP64, OpenMP) on a bounded sample of the workload."""
     import oracle
-    from paper_2002_01334_amd import inputs
 
-    prob = inputs.three_layer(per_layer, seed=0)
-    ly = oracle.Layers(prob.eps, prob.lam, prob.d)
     # the host share of one GPU is at most 16 threads, whatever the machine reports
     cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    n = 0
     t0 = time.perf_counter()
-    oracle.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=leaf_cap, nthreads=cores)
+    for prob in probs:
+        ly = oracle.Layers(prob.eps, prob.lam, prob.d)
+        oracle.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=leaf_cap, nthreads=cores)
+        n += prob.n
     dt = time.perf_counter() - t0
-    return {"value": prob.n / dt, "unit": "charges/s", "cores": cores, "kind": "oracle",
-            "sample": f"oracle CPU FMM (FP64, OpenMP) on {prob.n} charges ({per_layer}/layer, same recipe, p={p}, "
-                      f"leaf cap {leaf_cap}); {dt:.1f} s"}
+    return {"value": n / dt, "unit": "charges/s", "cores": cores, "kind": "oracle",
+            "sample": f"oracle CPU FMM (FP64, OpenMP) on {what}: {n} charges, p={p}, leaf cap {leaf_cap}; {dt:.1f} s"}
+
+
+def kernel_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary,
+    if the evaluation kernels' source is unchanged since it was taken."""
+    prof = os.path.join(ROOT, "profiles", "hbm_traffic_3layer_3e6_p10.md")
+    src = os.path.join(ROOT, "paper_2002_01334_amd", "csrc", "lpb_eval.hip")
+    try:
+        text = open(prof).read()
+        blk = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except (OSError, IndexError, ValueError):
+        return None
+    if blk.get("source_sha256") != sha:
+        return None
+    for k in blk.get("kernels", []):
+        if k["stage"] == kernel:
+            return k["bytes_per_launch"]
+    return None
 
 
 def main():
@@ -91,11 +141,15 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--per-layer", type=int, default=1_000_000)
-    ap.add_argument("--p", type=int, default=10)
+    ap.add_argument("--workload", choices=("uniform", "clustered", "batch"), default="uniform",
+                    help="uniform: 1e6 charges per layer in unit cubes (default); clustered: 1e5 per layer, half "
+                         "Gaussian (sigma 0.1); batch: 256 independent systems of uneven sizes")
+    ap.add_argument("--per-layer", type=int, default=None)
+    ap.add_argument("--systems", type=int, default=256)
+    ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--leaf-cap", type=int, default=50)
     ap.add_argument("--fp64-steps", type=int, default=5)
-    ap.add_argument("--cpu-sample-per-layer", type=int, default=200_000)
+    ap.add_argument("--cpu-sample", type=int, default=None, help="charges per layer of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device-to-device copy of this many MiB first (HBM counter calibration)")
@@ -104,6 +158,10 @@ def main():
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path would shard by "
               "assigning independent FMMs to GPUs, see DESIGN.md", file=sys.stderr)
         sys.exit(2)
+    wl = args.workload
+    p = args.p if args.p is not None else {"uniform": 10, "clustered": 6, "batch": 8}[wl]
+    per_layer = args.per_layer if args.per_layer is not None else {"uniform": 1_000_000, "clustered": 100_000,
+                                                                   "batch": 0}[wl]
 
     import torch
 
@@ -119,18 +177,47 @@ def main():
         torch.cuda.synchronize()
         print(f"[bench] calibration copy: {n * 8} bytes read, {n * 8} bytes written", file=sys.stderr, flush=True)
         del src, dst
-    prob = inputs.three_layer(args.per_layer, seed=0)
-    print(f"[bench] workload: 3 layers, {prob.n} charges, p={args.p}", file=sys.stderr, flush=True)
-    mixed = time_context(lpb, torch, prob, args.p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup)
-    print(f"[bench] mixed: {mixed['eval_ms']:.2f} ms/eval, stages {mixed['stage_ms']}", file=sys.stderr, flush=True)
-    fp64 = time_context(lpb, torch, prob, args.p, args.leaf_cap, lpb.LPB_FP64, args.fp64_steps, 1)
-    print(f"[bench] fp64: {fp64['eval_ms']:.2f} ms/eval, stages {fp64['stage_ms']}", file=sys.stderr, flush=True)
-    rel = err2_per_layer(mixed["phi"], fp64["phi"], prob.layer)
+
+    if wl == "batch":
+        probs = [inputs.batch_system(k) for k in range(args.systems)]
+        ntot = sum(pr.n for pr in probs)
+        desc = (f"{args.systems} independent 3-layer systems (system k: seed 1000+k, N log-uniform in [1e3,5e4], "
+                f"eps~U[1,80], lambda~U[0.5,3], middle thickness~U[0.8,2]), one batched evaluation")
+        print(f"[bench] workload: {args.systems} systems, {ntot} charges, p={p}", file=sys.stderr, flush=True)
+        mixed = time_batch(lpb, torch, probs, p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup)
+        print(f"[bench] mixed: {mixed['eval_ms']:.2f} ms/eval, stages {mixed['stage_ms']}", file=sys.stderr, flush=True)
+        fp64 = time_batch(lpb, torch, probs, p, args.leaf_cap, lpb.LPB_FP64, args.fp64_steps, 1)
+        print(f"[bench] fp64: {fp64['eval_ms']:.2f} ms/eval, stages {fp64['stage_ms']}", file=sys.stderr, flush=True)
+        rel = [max(err2_per_layer(a, b, pr.layer)) for a, b, pr in zip(mixed["phi"], fp64["phi"], probs)]
+        rel_layers = None
+        sample = []
+        for pr in probs:
+            if sum(x.n for x in sample) >= (args.cpu_sample or 300_000):
+                break
+            sample.append(pr)
+        sample_what = f"the first {len(sample)} systems of the batch"
+    else:
+        clustered = wl == "clustered"
+        prob = inputs.three_layer(per_layer, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)
+        ntot = prob.n
+        desc = (f"3-layer medium eps=(1,2,4) lambda=(1.2,1.5,2.0) d=(0,-1.2), {per_layer}/layer "
+                + ("50% uniform + 50% Gaussian (sigma 0.1) in unit cubes" if clustered else "uniform unit cubes")
+                + ", q~U[-1,1], seed 0")
+        print(f"[bench] workload: 3 layers, {ntot} charges, p={p}", file=sys.stderr, flush=True)
+        mixed = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup)
+        print(f"[bench] mixed: {mixed['eval_ms']:.2f} ms/eval, stages {mixed['stage_ms']}", file=sys.stderr, flush=True)
+        fp64 = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_FP64, args.fp64_steps, 1)
+        print(f"[bench] fp64: {fp64['eval_ms']:.2f} ms/eval, stages {fp64['stage_ms']}", file=sys.stderr, flush=True)
+        rel_layers = err2_per_layer(mixed["phi"], fp64["phi"], prob.layer)
+        rel = rel_layers
+        cs = args.cpu_sample or (200_000 if not clustered else 100_000)
+        sample = [inputs.three_layer(cs, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)]
+        sample_what = f"the same recipe at {cs} charges per layer"
 
     st = mixed["stats"]
-    K = (args.p + 1) ** 2
+    K = (p + 1) ** 2
     stage = mixed["stage_ms"]
-    # dominant kernel and its algorithmic work per launch
+    # dominant kernel and its algorithmic work per launch (one launch per evaluation)
     work = {
         "m2l_tile": (2.0 * K * K * st["n_m2l_tile_pairs"], "mfma", "2K^2 flops per V-list pair (real-form dense product)"),
         "p2p_free": (FLOPS_PER_P2P_PAIR * (st["n_p2p_pairs"] - st["n_react_p2p_pairs"]), "alu",
@@ -140,16 +227,18 @@ def main():
     flops, bound, per = work[dom]
     achieved = flops / (stage[dom] * 1e-3) / 1e12
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32, "traffic": None,
+            "frac": achieved / PEAK_FP32,
+            "traffic": kernel_traffic(dom) if (wl == "uniform" and per_layer == 1_000_000 and p == 10) else None,
             "work": f"{flops:.4g} algorithmic flops per launch ({per})"}
-    fp64_roof = {"kernel": "m2l_tile", "achieved": 2.0 * K * K * st["n_m2l_tile_pairs"] / (fp64["stage_ms"]["m2l_tile"] * 1e-3) / 1e12,
+    fp64_roof = {"kernel": "m2l_tile",
+                 "achieved": 2.0 * K * K * st["n_m2l_tile_pairs"] / (max(fp64["stage_ms"]["m2l_tile"], 1e-9) * 1e-3) / 1e12,
                  "peak": PEAK_FP64, "unit": "TFLOP/s"}
     fp64_roof["frac"] = fp64_roof["achieved"] / PEAK_FP64
 
     ms = mixed["eval_ms"]
     line = {
-        "metric": "charges/sec (3-layer potential, p=10): mixed-batched vs FP64 at <=1e-6 rel err",
-        "value": prob.n / (ms * 1e-3),
+        "metric": f"charges/sec (3-layer potential, p={p}): mixed-batched vs FP64 at <=1e-6 rel err",
+        "value": ntot / (ms * 1e-3),
         "unit": "charges/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -160,24 +249,24 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": f"3-layer medium eps=(1,2,4) lambda=(1.2,1.5,2.0) d=(0,-1.2), "
-                               f"{args.per_layer}/layer uniform unit cubes, q~U[-1,1], seed 0",
-                   "charges": prob.n, "p": args.p, "leaf_cap": args.leaf_cap, "precision": "mixed"},
-        "fp64_value": prob.n / (fp64["eval_ms"] * 1e-3),
+        "config": {"workload": desc, "charges": ntot, "p": p, "leaf_cap": args.leaf_cap, "precision": "mixed"},
+        "fp64_value": ntot / (fp64["eval_ms"] * 1e-3),
         "fp64_ms_per_step": fp64["eval_ms"],
         "speedup_vs_fp64": fp64["eval_ms"] / ms,
         "rel_err_vs_fp64": max(rel),
-        "rel_err_vs_fp64_per_layer": rel,
         "wall_ms_per_step": mixed["wall_s"] * 1e3,
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "fp64_stage_ms": {k: round(v, 4) for k, v in fp64["stage_ms"].items()},
         "setup": {"tree_build_s": mixed["t_build_s"], "opgen_ms": st["t_opgen_ms"], "n_m2l_pairs": st["n_m2l_pairs"],
-                  "n_p2p_pairs": st["n_p2p_pairs"], "n_operators": st["n_operators"], "max_depth": st["max_depth"]},
+                  "n_p2p_pairs": st["n_p2p_pairs"], "n_operators": st["n_operators"],
+                  "operator_bytes": st["operator_bytes"], "max_depth": st["max_depth"]},
         "roofline": roof,
         "fp64_roofline": fp64_roof,
     }
+    if rel_layers is not None:
+        line["rel_err_vs_fp64_per_layer"] = rel_layers
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(args.cpu_sample_per_layer, args.p, args.leaf_cap)
+        line["cpu_baseline"] = cpu_baseline(sample, p, args.leaf_cap, sample_what)
     print(json.dumps(line), flush=True)
 
 

@@ -204,22 +204,30 @@ lpb_status up_field(lpb_ctx* c, const F*& field, const std::vector<V>& vec)
 }
 
 template <typename T>
-lpb_status upload_points(lpb_ctx* c, const std::vector<double>& u3, int n, const T** x, const T** y, const T** z)
+lpb_status upload_points(lpb_ctx* c, const std::vector<double>& u3, int n, const T** x, const T** y, const T** z,
+                         const T** lx, const T** ly, const T** lz)
 {
-    std::vector<T> a(n), b(n), d(n);
-    for (int i = 0; i < n; ++i) {
-        a[i] = (T)u3[i];
-        b[i] = (T)u3[(size_t)n + i];
-        d[i] = (T)u3[2 * (size_t)n + i];
-    }
-    T *px, *py, *pz;
+    // FP32: hi = (float)u and lo = (float)(u - hi), so hi + lo carries u to ~2^-48 relative
+    const T** hi[3] = {x, y, z};
+    const T** lo[3] = {lx, ly, lz};
     lpb_status s;
-    if ((s = upload(c, c->plan_bufs, a, &px)) != LPB_OK) return s;
-    if ((s = upload(c, c->plan_bufs, b, &py)) != LPB_OK) return s;
-    if ((s = upload(c, c->plan_bufs, d, &pz)) != LPB_OK) return s;
-    *x = px;
-    *y = py;
-    *z = pz;
+    for (int d = 0; d < 3; ++d) {
+        std::vector<T> h(n), l(n);
+        for (int i = 0; i < n; ++i) {
+            double u = u3[(size_t)d * n + i];
+            h[i] = (T)u;
+            l[i] = (T)(u - (double)h[i]);
+        }
+        T* ph;
+        if ((s = upload(c, c->plan_bufs, h, &ph)) != LPB_OK) return s;
+        *hi[d] = ph;
+        *lo[d] = nullptr;
+        if (sizeof(T) == 4) {
+            T* pl;
+            if ((s = upload(c, c->plan_bufs, l, &pl)) != LPB_OK) return s;
+            *lo[d] = pl;
+        }
+    }
     return LPB_OK;
 }
 
@@ -363,8 +371,12 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     }
     c->sched.bm2l_w0 = P.bm2l_w0;
     c->sched.bm2l_w1 = P.bm2l_w1;
-    if ((s = upload_points<T>(c, P.s_u, (int)P.s_cidx.size(), &A.s_ux, &A.s_uy, &A.s_uz)) != LPB_OK) return s;
-    if ((s = upload_points<T>(c, P.t_u, (int)P.t_cidx.size(), &A.t_ux, &A.t_uy, &A.t_uz)) != LPB_OK) return s;
+    if ((s = upload_points<T>(c, P.s_u, (int)P.s_cidx.size(), &A.s_ux, &A.s_uy, &A.s_uz, &A.s_lx, &A.s_ly, &A.s_lz)) !=
+        LPB_OK)
+        return s;
+    if ((s = upload_points<T>(c, P.t_u, (int)P.t_cidx.size(), &A.t_ux, &A.t_uy, &A.t_uz, &A.t_lx, &A.t_ly, &A.t_lz)) !=
+        LPB_OK)
+        return s;
     T* qs;
     if ((s = dalloc<T>(c, c->plan_bufs, P.s_cidx.size(), &qs)) != LPB_OK) return s;
     A.qs = qs;

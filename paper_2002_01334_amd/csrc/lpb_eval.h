@@ -15,12 +15,14 @@ struct EvalArgs {
     int n_src;
     const int* s_cidx;
     const T *s_ux, *s_uy, *s_uz;
+    const T *s_lx, *s_ly, *s_lz;   // FP32: low parts (u - (double)hi) of the offsets; FP64: null
     T* qs;
     const double* q;
     const int *sl_start, *sl_me, *sl_fmm;
     const double *sl_h, *sl_ctr;
     // targets
     const T *t_ux, *t_uy, *t_uz;
+    const T *t_lx, *t_ly, *t_lz;
     const int *t_cidx, *t_out;
     const int *tl_start, *tl_le, *tl_fmm;
     const double *tl_h, *tl_ctr;

@@ -813,6 +813,101 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
     }
 }
 
+// FP32 form.  Every position relative to the target leaf centre is carried as
+// hi + lo (two FP32 numbers; sources formed in FP64 while staging), so the
+// difference of two close points keeps its relative accuracy: FP32 positions
+// alone would lose eps32 * h / r of it for a pair at distance r in a leaf of
+// side h.  The first U-list leaf is the target's own (the r = 0 self pair is
+// excluded there only); terms are summed in groups of four and the group
+// sums are added with Kahan compensation.
+__device__ inline float p2p_term32(float4 hs, float4 ls, float xh, float yh, float zh, float xl, float yl, float zl,
+                                   float lamk)
+{
+    float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y), dz = (zh - hs.z) + (zl - ls.z);
+    float r2 = dx * dx + dy * dy + dz * dz;
+    float ri = __frsqrt_rn(r2);
+    return hs.w * exp2f(-lamk * (r2 * ri)) * ri;
+}
+
+__global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
+{
+    constexpr int SMAX = 256;
+    __shared__ float4 sh[SMAX];   // x, y, z (hi) and q
+    __shared__ float4 sl[SMAX];   // x, y, z (lo)
+    const int leaf = A.p2p_free_leaves[blockIdx.x];
+    const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
+    const float lamk = (float)(F.lam_t * 1.4426950408889634);
+    const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
+    const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
+    const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
+    const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
+    const int nself = A.sl_start[A.p2p_src[k0] + 1] - A.sl_start[A.p2p_src[k0]];
+    for (int base = t0; base < t1; base += 32) {
+        const int j = base + tl;
+        const bool act = j < t1;
+        const float xh = act ? A.t_ux[j] : 0.f, yh = act ? A.t_uy[j] : 0.f, zh = act ? A.t_uz[j] : 0.f;
+        const float xl = act ? A.t_lx[j] : 0.f, yl = act ? A.t_ly[j] : 0.f, zl = act ? A.t_lz[j] : 0.f;
+        float sum = 0.f, comp = 0.f;
+        auto kahan = [&](float v) {
+            float y = v - comp;
+            float t = sum + y;
+            comp = (t - sum) - y;
+            sum = t;
+        };
+        int k = k0, s = A.sl_start[A.p2p_src[k0]], staged = 0;
+        while (k < k1) {
+            // stage up to SMAX sources, continuing across source leaves
+            int n = 0;
+            __syncthreads();
+            while (k < k1 && n < SMAX) {
+                const int sl_i = A.p2p_src[k];
+                const int se = A.sl_start[sl_i + 1];
+                const int take = min(se - s, SMAX - n);
+                const double ox = A.sl_ctr[3 * sl_i] - tcx, oy = A.sl_ctr[3 * sl_i + 1] - tcy,
+                             oz = A.sl_ctr[3 * sl_i + 2] - tcz;
+                for (int i = lane; i < take; i += 64) {
+                    const double X = ((double)A.s_ux[s + i] + (double)A.s_lx[s + i]) + ox;
+                    const double Y = ((double)A.s_uy[s + i] + (double)A.s_ly[s + i]) + oy;
+                    const double Z = ((double)A.s_uz[s + i] + (double)A.s_lz[s + i]) + oz;
+                    const float hx = (float)X, hy = (float)Y, hz = (float)Z;
+                    sh[n + i] = make_float4(hx, hy, hz, A.qs[s + i]);
+                    sl[n + i] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), 0.f);
+                }
+                n += take;
+                s += take;
+                if (s >= se) {
+                    ++k;
+                    if (k < k1) s = A.sl_start[A.p2p_src[k]];
+                }
+            }
+            __syncthreads();
+            if (act) {
+                // staged sources below nself belong to the target's own leaf
+                const int ns = min(max(nself - staged, 0), n);
+                for (int jj = half; jj < ns; jj += 2) {
+                    const float4 hs = sh[jj], ls = sl[jj];
+                    float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y), dz = (zh - hs.z) + (zl - ls.z);
+                    float r2 = dx * dx + dy * dy + dz * dz;
+                    if (r2 > 0.f) kahan(p2p_term32(hs, ls, xh, yh, zh, xl, yl, zl, lamk));
+                }
+                int jj = ns + ((half - ns) & 1);
+                for (; jj + 6 < n; jj += 8) {
+                    float g = p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl, lamk) +
+                              p2p_term32(sh[jj + 2], sl[jj + 2], xh, yh, zh, xl, yl, zl, lamk);
+                    g += p2p_term32(sh[jj + 4], sl[jj + 4], xh, yh, zh, xl, yl, zl, lamk) +
+                         p2p_term32(sh[jj + 6], sl[jj + 6], xh, yh, zh, xl, yl, zl, lamk);
+                    kahan(g);
+                }
+                for (; jj < n; jj += 2) kahan(p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl, lamk));
+            }
+            staged += n;
+        }
+        // combine the two halves (lane l and l+32 share a target)
+        const float other = __shfl_xor(sum - comp, 32, 64);
+        if (act && half == 0) A.parts[A.t_out[j]] += ((double)(sum - comp) + (double)other) / (4.0 * LPB_PI * F.eps_t);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Reaction near field (Algorithm 1, last step): every pair is the integral
 //   u~ = (1/4pi) int_0^inf lrho J_0(lrho rho) e^{-l_z zt + l'_z zs} sigma(lrho) / l_z dlrho
@@ -930,7 +1025,10 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     }
     // near field
     LPB_MARK(7);
-    if (near && S.n_p2p_free > 0) hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, st, A);
+    if (near && S.n_p2p_free > 0) {
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL(k_p2p_free32, dim3(S.n_p2p_free), dim3(64), 0, st, A);
+        else hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, st, A);
+    }
     LPB_MARK(8);
     if (near && A.n_react_targets > 0)
         hipLaunchKernelGGL(k_p2p_react<T>, dim3((A.n_react_targets + 63) / 64), dim3(64), 0, st, A);

@@ -410,16 +410,19 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                     }
         }
     }
-    // U-lists at the leaf level (target leaf order equals the level-H box order)
+    // U-lists at the leaf level (target leaf order equals the level-H box order);
+    // the target's own box comes first
     int nside = 1 << H;
+    static const int kUOrder[27][3] = {
+        {0, 0, 0},   {-1, -1, -1}, {-1, -1, 0}, {-1, -1, 1}, {-1, 0, -1}, {-1, 0, 0}, {-1, 0, 1}, {-1, 1, -1}, {-1, 1, 0},
+        {-1, 1, 1},  {0, -1, -1},  {0, -1, 0},  {0, -1, 1},  {0, 0, -1},  {0, 0, 1},  {0, 1, -1}, {0, 1, 0},   {0, 1, 1},
+        {1, -1, -1}, {1, -1, 0},   {1, -1, 1},  {1, 0, -1},  {1, 0, 0},   {1, 0, 1},  {1, 1, -1}, {1, 1, 0},   {1, 1, 1}};
     for (int k = 0; k < TT.nleaf; ++k) {
         int tx = TB[H].ix[k], ty = TB[H].iy[k], tz = TB[H].iz[k];
         int tl = TT.leaf0 + k;
         int nt = P.tl_start[tl + 1] - P.tl_start[tl];
-        for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dz = -1; dz <= 1; ++dz) {
-                    int sx = tx + dx, sy = ty + dy, sz = tz + dz;
+        for (const auto& du : kUOrder) {
+                    int sx = tx + du[0], sy = ty + du[1], sz = tz + du[2];
                     if (sx < 0 || sy < 0 || sz < 0 || sx >= nside || sy >= nside || sz >= nside) continue;
                     auto it = SB[H].idx.find(cellkey(sx, sy, sz));
                     if (it == SB[H].idx.end()) continue;
@@ -431,7 +434,7 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                         S.rp_by_tl[tl].push_back({fid, sl});
                         P.n_react_p2p_pairs += pairs;
                     }
-                }
+        }
     }
 }
 

@@ -273,3 +273,66 @@ def test_full_size_homogeneous_and_free_part(lpb):
         l = prob.layer[i]
         ref = free_sum(prob.lam[l], prob.eps[l], [i], True)[0]
         assert abs(free[k] - ref) <= 1e-4 * abs(ref)
+
+
+@pytest.fixture(scope="module")
+def c3():
+    """1e5 charges per layer, half uniform and half Gaussian (sigma 0.1), with
+    the oracle direct sum at 4 sampled targets per layer."""
+    prob = inputs.three_layer(100_000, seed=0, clustered_fraction=0.5, sigma=0.1)
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    idx = inputs.sample_targets(prob, 4, seed=1)
+    return prob, idx, O.direct_sum(ly, prob.x, prob.y, prob.z, prob.q, targets=idx)
+
+
+@pytest.mark.parametrize("p,tol", [(6, 5e-4), (12, 3e-6)])
+def test_c3_clustered_mixed_vs_fp64_and_direct(lpb, c3, p, tol):
+    prob, idx, direct = c3
+    ctx, phi64 = run(lpb, prob, p, 50, device=True)
+    ctx.close()
+    ctx, phi32 = run(lpb, prob, p, 50, precision=lpb.LPB_MIXED, device=True)
+    ctx.close()
+    e_mixed = err2(phi32, phi64, prob.layer)
+    e_direct = err2(phi64[idx], direct, prob.layer[idx])
+    print(f"C3 p={p}: mixed vs FP64 {e_mixed:.3e}, FP64 vs direct (sampled) {e_direct:.3e}")
+    assert e_mixed <= 1e-6
+    assert e_direct <= tol
+
+
+def test_c4_batch_mixed_vs_fp64_per_system():
+    """The first 32 systems of the batched workload (uneven sizes, random media)
+    at p = 8: mixed batched vs FP64 batched per system and layer, and the FP64
+    batch equal bit for bit to single-system contexts for three of them."""
+    from paper_2002_01334_amd import lpb as L
+
+    L.load()
+    probs = [inputs.batch_system(k) for k in range(32)]
+
+    def batch(prec):
+        ctx = L.Context(p=8, leaf_cap=50, precision=prec)
+        ctx.set_systems([q.eps for q in probs], [q.lam for q in probs], [q.d for q in probs])
+        ctx.build_trees([q.x for q in probs], [q.y for q in probs], [q.z for q in probs])
+        out = ctx.evaluate_batch([q.q for q in probs])
+        ctx.close()
+        return out
+
+    o64, o32 = batch(L.LPB_FP64), batch(L.LPB_MIXED)
+    worst = max(err2(a, b, q.layer) for a, b, q in zip(o32, o64, probs))
+    print(f"C4 (32 systems) mixed vs FP64 worst per-system error {worst:.3e}")
+    assert worst <= 1e-6
+    for k in (0, 7, 31):
+        ctx, phi = run(L, probs[k], 8, 50)
+        ctx.close()
+        assert np.array_equal(phi, o64[k]), k
+
+
+def test_full_size_p15_mixed_vs_fp64(lpb):
+    """3e6 charges at p = 15: mixed vs FP64 within 1e-6 per layer."""
+    prob = inputs.three_layer(1_000_000, seed=0)
+    ctx, phi64 = run(lpb, prob, 15, 50, device=True)
+    ctx.close()
+    ctx, phi32 = run(lpb, prob, 15, 50, precision=lpb.LPB_MIXED, device=True)
+    ctx.close()
+    e = err2(phi32, phi64, prob.layer)
+    print(f"3e6 p=15 mixed vs FP64 {e:.3e}")
+    assert e <= 1e-6
