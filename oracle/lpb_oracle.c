@@ -1442,7 +1442,8 @@ static void root_free(int n, const double* x, const double* y, const double* z, 
  *     distance tau of a charge to an interface of its own layer;
  *   depth: the smallest l <= 12 at which every point set (layer, side) with
  *     N charges, placed at +tau (targets) and at -tau (images), has
- *     N <= cap * (non-empty boxes at level l).
+ *     N <= cap * (non-empty boxes at level l); then raised (by at most 3
+ *     levels, to at most 12) until the box side 2R/2^l is <= the smallest tau.
  * Cells: fine_cell(x, cx, R), fine_cell(y, cy, R), fine_cell(+-tau, 0, R);
  * for a = 2 the z cell is mirrored (65535 - c) into the original orientation. */
 typedef struct {
@@ -1455,14 +1456,18 @@ static int side_valid(const layers_t* Ly, int l, int s) { return s == 1 ? l < Ly
 static void reaction_grid(const layers_t* Ly, int64_t n, const double* x, const double* y, const double* z,
                           const int* lay, int cap, rgrid_t* G)
 {
-    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, r = 0.0;
+    double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, r = 0.0, tmin = INFINITY;
     for (int64_t i = 0; i < n; ++i) {
         lo[0] = fmin(lo[0], x[i]);
         hi[0] = fmax(hi[0], x[i]);
         lo[1] = fmin(lo[1], y[i]);
         hi[1] = fmax(hi[1], y[i]);
         for (int sd = 1; sd <= 2; ++sd)
-            if (side_valid(Ly, lay[i], sd)) r = fmax(r, fabs(tau_s(Ly, lay[i], sd, z[i])));
+            if (side_valid(Ly, lay[i], sd)) {
+                double t = fabs(tau_s(Ly, lay[i], sd, z[i]));
+                r = fmax(r, t);
+                tmin = fmin(tmin, t);
+            }
     }
     G->cx = 0.5 * (lo[0] + hi[0]);
     G->cy = 0.5 * (lo[1] + hi[1]);
@@ -1502,6 +1507,16 @@ static void reaction_grid(const layers_t* Ly, int64_t n, const double* x, const 
                 free(C.cx);
             }
         }
+    /* separation: with leaves no wider than the smallest distance tau of a
+     * charge to an interface of its layer, every target and every image lies
+     * at least one box away from the interface plane, so no reaction U-list
+     * pair remains (Remark 1: the reaction near field is rare).  At most 3
+     * levels are added to the occupancy depth for this. */
+    int hs = 0;
+    while (hs < ORC_MAXDEPTH && 2.0 * G->R / (double)(1 << hs) > tmin) ++hs;
+    int hcap = G->H + 3 < ORC_MAXDEPTH ? G->H + 3 : ORC_MAXDEPTH;
+    if (hs > hcap) hs = hcap;
+    if (hs > G->H) G->H = hs;
 }
 
 /* Fine cells of the targets (layer l, side a) and images (layer lp, side b)

@@ -14,7 +14,8 @@ namespace lpb {
 
 constexpr int kMaxDepth = 12;   // deepest tree level
 constexpr int kCellBits = 16;   // fine cell bits per axis
-constexpr int kTileMaxLevel = 8;  // free-space levels up to this one use the tiled MFMA M2L
+constexpr int kTileMinLevel = 4;  // free-space levels kTileMinLevel..kTileMaxLevel use the tiled MFMA M2L
+constexpr int kTileMaxLevel = 8;  // (coarser grids are mostly boundary: their pairs go to the batched kernel)
 constexpr int kTilePB = 4;        // parents per axis of an M2L tile (4^3 parents -> 64 target boxes)
 constexpr int kVOffsets = 189;    // V-list offsets of one child octant
 

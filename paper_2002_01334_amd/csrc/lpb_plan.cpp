@@ -12,7 +12,8 @@
 //     layer).  Root: centre x, y of the bounding box of all charges, z on
 //     the interface (Sec. 3.5: the largest box is halved by it), half side =
 //     max of the half x, y extents and every tau; depth = the largest of the
-//     per-set rule over all (layer, side) sets, as images and as targets.
+//     per-set rule over all (layer, side) sets, as images and as targets,
+//     raised (by at most 3 levels) until the box side is <= the smallest tau.
 //   fine cell per axis: floor((w + R) / (2R) * 65536) clamped to [0, 65535]
 //     with w the canonical coordinate relative to the root centre; the
 //     level-l cell is the fine cell >> (16 - l).
@@ -309,8 +310,9 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         return op;
     };
     // tiled levels of a free-space FMM: dense grids, operator table, tiles
-    int tiled_max = (F.kind == 0) ? std::min(H, kTileMaxLevel) : 1;
-    for (int lv = 2; lv <= tiled_max; ++lv) {
+    const int tiled_min = std::max(2, kTileMinLevel);
+    const int tiled_max = (F.kind == 0) ? std::min(H, kTileMaxLevel) : 1;
+    for (int lv = tiled_min; lv <= tiled_max; ++lv) {
         int nside = 1 << lv;
         TileFL t{};
         t.fmm = fid;
@@ -352,7 +354,7 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                     }
     }
     for (int lv = 2; lv <= H; ++lv) {
-        const bool tiled = lv <= tiled_max;
+        const bool tiled = lv >= tiled_min && lv <= tiled_max;
         int nside = 1 << lv;
         double h = hlev(lv);
         for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
@@ -577,12 +579,16 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         // components that use it, on a common root cube and depth.
         auto side_ok = [&](int l, int sd) { return sd == 1 ? l < L : l > 0; };
         auto tau = [&](int l, int sd, double z) { return sd == 1 ? z - m.d[l] : m.d[l - 1] - z; };
-        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, r = 0.0;
+        double lo[2] = {INFINITY, INFINITY}, hi[2] = {-INFINITY, -INFINITY}, r = 0.0, tmin = INFINITY;
         for (size_t i = 0; i < xs[s].size(); ++i) {
             lo[0] = std::min(lo[0], xs[s][i]); hi[0] = std::max(hi[0], xs[s][i]);
             lo[1] = std::min(lo[1], ys[s][i]); hi[1] = std::max(hi[1], ys[s][i]);
             for (int sd = 1; sd <= 2; ++sd)
-                if (side_ok(layer[s][i], sd)) r = std::max(r, std::fabs(tau(layer[s][i], sd, zs[s][i])));
+                if (side_ok(layer[s][i], sd)) {
+                    double t = std::fabs(tau(layer[s][i], sd, zs[s][i]));
+                    r = std::max(r, t);
+                    tmin = std::min(tmin, t);
+                }
         }
         if (xs[s].empty()) continue;
         const double gcx = 0.5 * (lo[0] + hi[0]), gcy = 0.5 * (lo[1] + hi[1]);
@@ -610,6 +616,15 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                     H = std::max(H, depth_rule(V, cap));
                 }
             }
+        // separation: leaves no wider than the smallest tau keep every target and
+        // image one box away from the interface plane, so reaction U-lists are
+        // empty (Remark 1); at most 3 levels above the occupancy depth
+        {
+            int hs = 0;
+            while (hs < kMaxDepth && 2.0 * R / (double)(1 << hs) > tmin) ++hs;
+            hs = std::min(hs, std::min(H + 3, kMaxDepth));
+            H = std::max(H, hs);
+        }
         P.max_depth = std::max(P.max_depth, H);
         // components in Algorithm 2 order
         std::vector<int> comp_fid;

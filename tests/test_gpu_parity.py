@@ -336,3 +336,30 @@ def test_full_size_p15_mixed_vs_fp64(lpb):
     e = err2(phi32, phi64, prob.layer)
     print(f"3e6 p=15 mixed vs FP64 {e:.3e}")
     assert e <= 1e-6
+
+
+def test_reaction_near_field_next_to_interfaces(lpb):
+    """Charges within 2e-3 of an interface keep reaction U-list pairs (the
+    separation depth is capped), so the reaction near field is exercised; FP64
+    per output slot and the pair count against the oracle FMM on the same tree."""
+    prob = inputs.three_layer(150, seed=11)
+    moved = {0: 0.002, 150: -0.003, 151: -1.198, 300: -1.202}
+    for i, zz in moved.items():
+        prob.z[i] = zz
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    ctx, phi = run(lpb, prob, 6, 8)
+    parts = ctx.debug_parts()
+    st = ctx.stats()
+    ctx.close()
+    ref, cphi, ost = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 6, leaf_cap=8, components=True)
+    assert st["n_react_p2p_pairs"] > 0
+    assert st["n_p2p_pairs"] == int(ost[:, 4].sum()) + prob.n
+    assert err2(phi, ref, prob.layer) <= 1e-10
+    sm = slot_map(3)
+    for l in range(3):
+        m = prob.layer == l
+        for s_ in (1, 2):
+            comps = [c for c in range(cphi.shape[0]) if sm[c] == (l, s_)]
+            if comps:
+                r = cphi[comps].sum(axis=0)[m]
+                assert np.linalg.norm(parts[s_][m] - r) <= 1e-10 * np.linalg.norm(r), (l, s_)

@@ -44,11 +44,19 @@ def test_fmm_components_sum_and_targets(orc, small):
         assert np.all(cphi[c][pr.layer != l] == 0.0)
 
 
-def test_fmm_without_far_field_equals_direct_sum(orc, small):
-    # with a leaf cap above every layer's size the tree has depth <= 1: every
-    # interaction is near field and the FMM reduces to the direct sum
-    pr, ly, ref = small
-    phi, cphi, st = orc.fmm(ly, pr.x, pr.y, pr.z, pr.q, 4, leaf_cap=1000, components=True)
+def test_fmm_without_far_field_equals_direct_sum(orc):
+    # every charge 0.625 from the interfaces of its layer and x, y within +-0.3:
+    # the reaction grid's half side equals the smallest tau, so with a leaf cap
+    # above every layer's size every tree has depth <= 1, every interaction is
+    # near field and the FMM reduces to the direct sum
+    rng = np.random.default_rng(3)
+    n = 40
+    x, y = rng.uniform(-0.3, 0.3, (2, 3 * n))
+    z = np.repeat([0.625, -0.625, -1.875], n)
+    q = rng.uniform(-1, 1, 3 * n)
+    ly = orc.Layers((1.0, 2.0, 4.0), (1.2, 1.5, 2.0), (0.0, -1.25))
+    ref = orc.direct_sum(ly, x, y, z, q)
+    phi, cphi, st = orc.fmm(ly, x, y, z, q, 4, leaf_cap=1000, components=True)
     assert np.all(st[:, 0] <= 1)
     assert np.allclose(phi, ref, rtol=1e-12, atol=1e-14)
 
