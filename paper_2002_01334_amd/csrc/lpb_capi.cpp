@@ -292,6 +292,22 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(grid_me, P.grid_me);
     UP(grid_le, P.grid_le);
     UP(optab, P.optab);
+    {
+        // signs of the real-form coefficients under x -> -x (Re (-1)^m, Im -(-1)^m),
+        // y -> -y (Re +1, Im -1) and z -> -z ((-1)^(n+m)); code bits 1 x, 2 y, 4 z
+        std::vector<T> sg((size_t)8 * A.KP, T(1));
+        for (int code = 0; code < 8; ++code)
+            for (int n = 0; n <= P.p; ++n)
+                for (int m = 0; m <= n; ++m) {
+                    double re = 1.0, im = 1.0;
+                    if (code & 1) { re *= (m & 1) ? -1.0 : 1.0; im *= (m & 1) ? 1.0 : -1.0; }
+                    if (code & 2) im = -im;
+                    if (code & 4) { double z = ((n + m) & 1) ? -1.0 : 1.0; re *= z; im *= z; }
+                    sg[(size_t)code * A.KP + ire(n, m)] = (T)re;
+                    if (m > 0) sg[(size_t)code * A.KP + iim(n, m)] = (T)im;
+                }
+        UP(refl_sign, sg);
+    }
     UP(oct_codes, P.oct_codes);
     UP(swz_index, P.swz_index);
     {

@@ -50,6 +50,7 @@ struct EvalArgs {
     const TileFL* tfl;
     const int *grid_me, *grid_le, *optab, *oct_codes;
     const T* pool_swz;          // operators in the MFMA operand layout, KP x KP each
+    const T* refl_sign;         // [8][KP]: diagonal of D for each reflection code (padding rows +1)
     // solid-harmonic recurrence coefficients (packed (n,m) index):
     //   R_m^m = amm[m] (x+iy)^m, R_n^m = alpha z R_{n-1}^m - beta |v|^2 R_{n-2}^m
     const T *sh_amm, *sh_alpha, *sh_beta;

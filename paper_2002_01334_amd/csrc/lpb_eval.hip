@@ -313,15 +313,17 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
     fetch(0);
     for (int d = 0; d < kVOffsets; ++d) {
         __syncthreads();   // every wave is done with the previous offset's B
+        const int ent = A.optab[fl.optab_off + codes[d]];
+        const int op = ent & ((1 << kReflShift) - 1);
+        const T* sg = A.refl_sign + (size_t)(ent >> kReflShift) * KP;
 #pragma unroll
         for (int i = 0; i < GMAX; ++i) {
             if (i < KB) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
+                for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e] * sg[16 * i + 4 * gpart + e];
             }
         }
         __syncthreads();
-        const int op = A.optab[fl.optab_off + codes[d]];
         if (d + 1 < kVOffsets) fetch(d + 1);   // next offset's sources load during this offset's products
         const T* Aw = A.pool_swz + (size_t)A.swz_index[op] * KP * KP;
 #pragma unroll
@@ -357,6 +359,15 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
                     }
                 }
             }
+        }
+        // result rows: the second sign flip of D A D
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            V4 sr;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sr[r] = sg[min(w * RB + rb, KB - 1) * 16 + mfma_row(T(0), l, r)];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] *= sr;
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
@@ -555,7 +566,10 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
 #pragma unroll
         for (int i = 0; i < KB; ++i) greg[i] = *reinterpret_cast<const V4*>(src + 16 * i);
     };
-    auto opA = [&](int d) { return A.pool_swz + (size_t)A.swz_index[A.optab[fl.optab_off + codes[d]]] * KP * KP; };
+    auto opent = [&](int d) { return A.optab[fl.optab_off + codes[d]]; };
+    auto opA = [&](int d) {
+        return A.pool_swz + (size_t)A.swz_index[opent(d) & ((1 << kReflShift) - 1)] * KP * KP;
+    };
     V4 ring[D][RB];
     // row blocks past KB (last active wave only) repeat the last block; their
     // rows are >= K and never stored
@@ -573,11 +587,12 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
     }
     fetch(0);
     for (int d = 0; d < kVOffsets; ++d) {
+        const T* sg = A.refl_sign + (size_t)(opent(d) >> kReflShift) * KP;
         __syncthreads();   // every wave is done with the previous offset's B
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
+            for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e] * sg[16 * i + 4 * gpart + e];
         }
         __syncthreads();
         const bool more = d + 1 < kVOffsets;
@@ -606,6 +621,15 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
 #pragma unroll
                         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
                 }
+            }
+            // result rows: the second sign flip of D A D
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                V4 sr;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) sr[r] = sg[min(w * RB + rb, KB - 1) * 16 + mfma_row(T(0), l, r)];
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] *= sr;
             }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)

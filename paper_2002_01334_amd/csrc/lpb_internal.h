@@ -18,6 +18,10 @@ constexpr int kTileMinLevel = 4;  // free-space levels kTileMinLevel..kTileMaxLe
 constexpr int kTileMaxLevel = 8;  // (coarser grids are mostly boundary: their pairs go to the batched kernel)
 constexpr int kTilePB = 4;        // parents per axis of an M2L tile (4^3 parents -> 64 target boxes)
 constexpr int kVOffsets = 189;    // V-list offsets of one child octant
+// Tiled levels store one operator per offset with non-negative components;
+// the offset (sx dx, sy dy, sz dz) uses it between sign flips D = diag(+-1)
+// of both the source and the result (reflection bits: 1 x, 2 y, 4 z).
+constexpr int kReflShift = 28;
 
 enum OpType { OP_M2M = 0, OP_L2L = 1, OP_M2L_FREE = 2, OP_M2L_REACT = 3 };
 
@@ -97,7 +101,7 @@ struct RKey {
 struct TileFL {
     int fmm, level, nside;
     int grid_off;     // into grid_me / grid_le (nside^3 entries each)
-    int optab_off;    // into optab (343 entries: offset code -> operator)
+    int optab_off;    // into optab (343 entries: offset code -> operator | reflection << kReflShift)
 };
 struct Tile {
     int fl, octant, px0, py0, pz0;

@@ -331,7 +331,11 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
             for (int dy = -3; dy <= 3; ++dy)
                 for (int dz = -3; dz <= 3; ++dz) {
                     if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-                    P.optab[t.optab_off + ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)] = free_op(lv, dx, dy, dz);
+                    // reflection symmetry of the translation (real-form harmonics map to
+                    // +- themselves under x, y or z -> -x, -y, -z): A_{sigma d} = D A_d D
+                    const int refl = (dx < 0 ? 1 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 4 : 0);
+                    P.optab[t.optab_off + ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)] =
+                        free_op(lv, std::abs(dx), std::abs(dy), std::abs(dz)) | (refl << kReflShift);
                 }
         int fl = (int)P.tfl.size();
         P.tfl.push_back(t);
@@ -370,6 +374,11 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                             if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
                             auto it = SB[lv].idx.find(cellkey(sx, sy, sz));
                             if (it == SB[lv].idx.end()) continue;
+                            if (tiled) {   // the tile's operator table covers it
+                                P.n_m2l_tile_pairs++;
+                                P.n_m2l_pairs++;
+                                continue;
+                            }
                             int op;
                             if (F.kind == 0) {
                                 op = free_op(lv, dx, dy, dz);
@@ -405,8 +414,7 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                                     opmap[key] = op;
                                 } else op = f->second;
                             }
-                            if (!tiled) S.m2l_by_le[le].push_back({ST.off[lv] + it->second, op});
-                            else P.n_m2l_tile_pairs++;
+                            S.m2l_by_le[le].push_back({ST.off[lv] + it->second, op});
                             P.n_m2l_pairs++;
                         }
                     }
