@@ -78,10 +78,10 @@ LPB_HD void bessel_k_all(int nmax, double x, double* out)
 
 // Index of the real-form coefficient vector: degree n occupies [n^2, n^2+2n];
 // Re of order m at n^2 + (m ? 2m-1 : 0), Im of order m > 0 at n^2 + 2m.
-LPB_HD int ire(int n, int m) { return n * n + (m ? 2 * m - 1 : 0); }
-LPB_HD int iim(int n, int m) { return n * n + 2 * m; }
+LPB_HD constexpr int ire(int n, int m) { return n * n + (m ? 2 * m - 1 : 0); }
+LPB_HD constexpr int iim(int n, int m) { return n * n + 2 * m; }
 // packed (n, m >= 0) index
-LPB_HD int ipk(int n, int m) { return n * (n + 1) / 2 + m; }
+LPB_HD constexpr int ipk(int n, int m) { return n * (n + 1) / 2 + m; }
 
 // Regular solid harmonics R_n^m(v) = |v|^n Y_n^m(v^), 0 <= m <= n <= p,
 // written to re/im at packed index ipk(n,m), from
