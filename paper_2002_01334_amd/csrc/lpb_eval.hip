@@ -749,8 +749,13 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
         for (int i = 0; i < D; ++i) loadA(Aw, i, ring[i]);
     }
     fetch(0);
+    // products of up to GRP consecutive offsets of one reflection class chain in
+    // the MFMA accumulators; the row signs and the compensated sum follow per run
+    constexpr int GRP = (sizeof(T) == 4) ? 4 : 1;
+    int run = 0;
     for (int d = 0; d < kVOffsets; ++d) {
-        const T* sg = A.refl_sign + (size_t)(opent(d) >> kReflShift) * KP;
+        const int cls = opent(d) >> kReflShift;
+        const T* sg = A.refl_sign + (size_t)cls * KP;
         __syncthreads();   // every wave is done with the previous offset's B
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
@@ -761,11 +766,14 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
         const bool more = d + 1 < kVOffsets;
         const T* Awn = more ? opA(d + 1) : Aw;
         if (more) fetch(d + 1);   // next offset's sources load during this offset's products
+        const bool flush = !more || run + 1 == GRP || (opent(d + 1) >> kReflShift) != cls;
         if (w < NWACT) {          // wave-uniform; the product loop itself has no branches
+            if (run == 0) {
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
+                for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+            }
 #pragma unroll
             for (int s4 = 0; s4 < KB; ++s4) {
                 V4 a4[RB];
@@ -785,29 +793,32 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
                         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
                 }
             }
-            // result rows: the second sign flip of D A D
+            if (flush) {
+                // result rows: the second sign flip of D A D
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) {
-                V4 sr;
+                for (int rb = 0; rb < RB; ++rb) {
+                    V4 sr;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) sr[r] = sg[min(w * RB + rb, KB - 1) * 16 + mfma_row(T(0), l, r)];
+                    for (int r = 0; r < 4; ++r) sr[r] = sg[min(w * RB + rb, KB - 1) * 16 + mfma_row(T(0), l, r)];
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] *= sr;
-            }
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-                for (int cb = 0; cb < CB; ++cb) {
-                    if (sizeof(T) == 4) {
-                        V4 y = acc[rb][cb] - cmp[rb][cb];
-                        V4 t = tot[rb][cb] + y;
-                        cmp[rb][cb] = (t - tot[rb][cb]) - y;
-                        tot[rb][cb] = t;
-                    } else {
-                        tot[rb][cb] += acc[rb][cb];
-                    }
+                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] *= sr;
                 }
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb) {
+                        if (sizeof(T) == 4) {
+                            V4 y = acc[rb][cb] - cmp[rb][cb];
+                            V4 t = tot[rb][cb] + y;
+                            cmp[rb][cb] = (t - tot[rb][cb]) - y;
+                            tot[rb][cb] = t;
+                        } else {
+                            tot[rb][cb] += acc[rb][cb];
+                        }
+                    }
+            }
         }
+        run = flush ? 0 : run + 1;
         Aw = Awn;
     }
     if (w >= NWACT) return;

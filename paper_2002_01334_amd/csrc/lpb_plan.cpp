@@ -503,15 +503,21 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.ops.clear(); P.rkeys.clear();
     P.tfl.clear(); P.tiles.clear(); P.grid_me.clear(); P.grid_le.clear(); P.optab.clear();
     P.n_p2p_pairs = P.n_react_p2p_pairs = P.n_m2l_pairs = P.n_m2l_tile_pairs = 0;
+    // V-list offsets of each child octant, grouped by reflection class (the
+    // tiled kernel applies the sign flips once per run of equal class)
     P.oct_codes.clear();
     for (int o = 0; o < 8; ++o) {
         int ox = (o >> 2) & 1, oy = (o >> 1) & 1, oz = o & 1;
+        std::vector<std::pair<int, int>> cl;
         for (int dx = -2 - ox; dx <= 3 - ox; ++dx)
             for (int dy = -2 - oy; dy <= 3 - oy; ++dy)
                 for (int dz = -2 - oz; dz <= 3 - oz; ++dz) {
                     if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-                    P.oct_codes.push_back(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
+                    int refl = (dx < 0 ? 1 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 4 : 0);
+                    cl.push_back({refl, ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)});
                 }
+        std::stable_sort(cl.begin(), cl.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
+        for (auto& c : cl) P.oct_codes.push_back(c.second);
     }
     Staging S;
 
