@@ -64,40 +64,65 @@ def _time_evals(ctx, torch, run, steps, warmup):
     return float(np.mean(evals)), stage, wall
 
 
-def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup):
-    dev = torch.device("cuda:0")
-    t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device=dev) for k in ("x", "y", "z", "q")}
-    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=1,
-                      stream=torch.cuda.current_stream().cuda_stream)
-    ctx.set_layers(prob.eps, prob.lam, prob.d)
-    t0 = time.perf_counter()
-    ctx.build_tree(t["x"], t["y"], t["z"])
-    t_build = time.perf_counter() - t0
-    phi = torch.empty_like(t["q"])
-    ms, stage, wall = _time_evals(ctx, torch, lambda: ctx.evaluate(t["q"], phi), steps, warmup)
-    out = phi.cpu().numpy()
+def _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps):
+    """The timed evaluations use the captured passes (graph = 1, autotuned
+    schedules, no per-stage events); a second context launches the passes one
+    by one with events between stages for the stage breakdown."""
+    stream = torch.cuda.current_stream().cuda_stream
+    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=0, graph=1, autotune=1, stream=stream)
+    t_build = setup(ctx)
+    ms, _, wall = _time_evals(ctx, torch, lambda: run_one(ctx), steps, warmup)
+    out = run_one(ctx)
     stats = ctx.stats()
     ctx.close()
-    return {"wall_s": wall, "eval_ms": ms, "stage_ms": stage, "stats": stats, "t_build_s": t_build, "phi": out}
+    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=1, graph=0, autotune=0, stream=stream)
+    setup(ctx)
+    ms_eager, stage, _ = _time_evals(ctx, torch, lambda: run_one(ctx), stage_steps, 1)
+    ctx.close()
+    return {"wall_s": wall, "eval_ms": ms, "eval_ms_eager": ms_eager, "stage_ms": stage, "stats": stats,
+            "t_build_s": t_build, "phi": out}
 
 
-def time_batch(lpb, torch, probs, p, leaf_cap, precision, steps, warmup):
+def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup, stage_steps=3):
+    dev = torch.device("cuda:0")
+    t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device=dev) for k in ("x", "y", "z", "q")}
+    phi = torch.empty_like(t["q"])
+
+    def setup(ctx):
+        ctx.set_layers(prob.eps, prob.lam, prob.d)
+        t0 = time.perf_counter()
+        ctx.build_tree(t["x"], t["y"], t["z"])
+        return time.perf_counter() - t0
+
+    def run_one(ctx):
+        ctx.evaluate(t["q"], phi)
+        return phi
+
+    r = _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps)
+    r["phi"] = r["phi"].cpu().numpy()
+    return r
+
+
+def time_batch(lpb, torch, probs, p, leaf_cap, precision, steps, warmup, stage_steps=2):
     dev = torch.device("cuda:0")
     ts = [{k: torch.tensor(getattr(pr, k), dtype=torch.float64, device=dev) for k in ("x", "y", "z", "q")}
           for pr in probs]
-    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=1,
-                      stream=torch.cuda.current_stream().cuda_stream)
-    ctx.set_systems([pr.eps for pr in probs], [pr.lam for pr in probs], [pr.d for pr in probs])
-    t0 = time.perf_counter()
-    ctx.build_trees([t["x"] for t in ts], [t["y"] for t in ts], [t["z"] for t in ts])
-    t_build = time.perf_counter() - t0
     outs = [torch.empty_like(t["q"]) for t in ts]
     qs = [t["q"] for t in ts]
-    ms, stage, wall = _time_evals(ctx, torch, lambda: ctx.evaluate_batch(qs, outs), steps, warmup)
-    res = [o.cpu().numpy() for o in outs]
-    stats = ctx.stats()
-    ctx.close()
-    return {"wall_s": wall, "eval_ms": ms, "stage_ms": stage, "stats": stats, "t_build_s": t_build, "phi": res}
+
+    def setup(ctx):
+        ctx.set_systems([pr.eps for pr in probs], [pr.lam for pr in probs], [pr.d for pr in probs])
+        t0 = time.perf_counter()
+        ctx.build_trees([t["x"] for t in ts], [t["y"] for t in ts], [t["z"] for t in ts])
+        return time.perf_counter() - t0
+
+    def run_one(ctx):
+        ctx.evaluate_batch(qs, outs)
+        return outs
+
+    r = _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps)
+    r["phi"] = [o.cpu().numpy() for o in r["phi"]]
+    return r
 
 
 def cpu_baseline(probs, p, leaf_cap, what):
@@ -255,6 +280,8 @@ def main():
         "speedup_vs_fp64": fp64["eval_ms"] / ms,
         "rel_err_vs_fp64": max(rel),
         "wall_ms_per_step": mixed["wall_s"] * 1e3,
+        "eager_ms_per_step": mixed["eval_ms_eager"],
+        "schedules": {"tile": st["tile_schedule"], "batch": st["batch_schedule"], "tune_ms": st["t_tune_ms"]},
         "stage_ms": {k: round(v, 4) for k, v in stage.items()},
         "fp64_stage_ms": {k: round(v, 4) for k, v in fp64["stage_ms"].items()},
         "setup": {"tree_build_s": mixed["t_build_s"], "opgen_ms": st["t_opgen_ms"], "n_m2l_pairs": st["n_m2l_pairs"],

@@ -72,6 +72,12 @@ typedef struct {
     void* stream;           /* hipStream_t for all work; NULL = null stream */
     int stages;             /* diagnostics: bit 0 far field (P2M..L2P), bit 1 near field; default 3 (both) */
     int timing;             /* 1 = record stream events between stages (lpb_stats.t_stage_ms); default 0 */
+    int graph;              /* 1 = capture the evaluation passes in a HIP graph on the first evaluate after
+                               a tree or operator change and replay it; ignored while timing = 1 (the
+                               per-stage events need the passes launched one by one); default 1 */
+    int autotune;           /* 1 = time the candidate block-to-work schedules of the matrix-core M2L
+                               kernels on the first evaluate after a change and keep the fastest
+                               (results do not depend on the choice); default 1 */
 } lpb_options;
 
 typedef struct {
@@ -91,6 +97,10 @@ typedef struct {
      * [4] list M2L (reaction, deep levels), [5] L2L, [6] L2P,
      * [7] free-space near field, [8] reaction near field, [9] component sum */
     double t_stage_ms[10];
+    int tile_schedule;      /* schedule chosen for the tiled M2L: 0 linear, 1 blocks of one XCD take a
+                               contiguous run of tiles (tiles sharing operators share that XCD's L2) */
+    int batch_schedule;     /* the same choice for the batched translations */
+    double t_tune_ms;       /* time spent by the last schedule autotuning */
 } lpb_stats;
 
 /* Fill *opt with the defaults listed above.  Never fails. */
@@ -110,15 +120,23 @@ lpb_status lpb_set_layers(lpb_ctx* ctx, int n_layers, const double* eps, const d
                           const double* interfaces);
 
 /* Set the charge positions of one system (host or device, n doubles each)
- * and build the plan: the layer of every charge, the images (equivalent
- * polarization coordinates, eq. equivpolarcoord) of every reaction
- * component, and one uniform octree per FMM: root cube = bounding cube of
- * the layer (free space) or a cube whose mid-plane is the interface between
- * targets and images (reaction); depth = smallest level at which sources
- * and targets both average at most leaf_cap per non-empty box; V-lists and
- * U-lists as in the classic FMM.  Requires lpb_set_layers first (the layer
- * of a charge depends on the interfaces).  Errors: LPB_ERANGE if a charge
- * lies within iface_tol of an interface, LPB_ENUMERIC for NaN/Inf. */
+ * and build the plan: the layer of every charge, the equivalent polarization
+ * coordinates (eq. equivpolarcoord) of every reaction component, and uniform
+ * octrees.  Free space: one tree per layer, root cube = bounding cube of the
+ * layer's charges, depth = smallest level at which the layer averages at
+ * most leaf_cap charges per non-empty box.  Reaction components: in the
+ * frame of a component (its interface at z = 0, targets above, mirrored in z
+ * when the interface is the upper one of the target layer) targets sit at
+ * height +tau and equivalent sources at -tau', tau being the distance of a
+ * charge to an interface of its own layer; all components of the medium
+ * share one root cube (x, y centre of all charges, z centre on the
+ * interface, half side = the largest tau or half x, y extent) and one depth
+ * (largest per-set occupancy depth, raised by at most 3 levels until the box
+ * side is no larger than the smallest tau), so each (layer, side) point set
+ * has one source and one target tree shared by the components using it.
+ * V-lists and U-lists as in the classic FMM.  Requires lpb_set_layers first
+ * (the layer of a charge depends on the interfaces).  Errors: LPB_ERANGE if a
+ * charge lies within iface_tol of an interface, LPB_ENUMERIC for NaN/Inf. */
 lpb_status lpb_build_tree(lpb_ctx* ctx, int64_t n, const double* x, const double* y, const double* z, int on_device);
 
 /* Evaluate Phi at every charge (input order) for charges q[n]; q and phi are
@@ -147,18 +165,22 @@ lpb_status lpb_get_stats(const lpb_ctx* ctx, lpb_stats* stats);
  * desc[5] = depth H; root[4] = centre x, y, z and half side R;
  * if tkeys/skeys are not NULL they receive, for the targets / sources of
  * that FMM in increasing charge-index order, the Morton key of their leaf at
- * level H (cell index per axis = floor(((x - cx) + R) / (2R) * 2^16) clamped
- * to [0, 65535], shifted right by 16 - H; bits interleaved x, y, z from the
- * most significant level down); *nt, *ns receive the counts.  Host memory. */
+ * level H (cell index per axis = floor((w + R) / (2R) * 2^16) clamped to
+ * [0, 65535], shifted right by 16 - H, with w = x - cx, y - cy and, for free
+ * space, z - cz; for a reaction component w_z = +tau (targets) or -tau'
+ * (sources), and the z cell is mirrored (2^H - 1 - c) when a = 2; bits
+ * interleaved x, y, z from the most significant level down); *nt, *ns
+ * receive the counts.  Host memory. */
 lpb_status lpb_fmm_info(const lpb_ctx* ctx, int sys, int fmm, int* desc, double* root, int64_t* nt, int64_t* ns,
                         uint64_t* tkeys, uint64_t* skeys);
 
-/* Diagnostic: copy the per-component potentials of the last evaluate to
- * host memory out[nslots * n_total] (component slot k of charge i at
- * out[k * n_total + i], charges of all systems concatenated in system order;
- * slot 0 is the free-space part, slots 1.. the reaction components that
- * target the charge's layer in the order of Algorithm 2).  *nslots receives
- * the slot count; out may be NULL to query it. */
+/* Diagnostic: copy the partial potentials of the last evaluate to host
+ * memory out[nslots * n_total] (slot k of charge i at out[k * n_total + i],
+ * charges of all systems concatenated in system order; slot 0 is the
+ * free-space part, slot 1 the sum of the reaction components through the
+ * lower interface of the charge's layer (a = 1), slot 2 through the upper
+ * one (a = 2); nslots = 1 for single-layer media).  *nslots receives the
+ * slot count; out may be NULL to query it. */
 lpb_status lpb_debug_parts(const lpb_ctx* ctx, double* out, int* nslots);
 
 /* Message of the last failed call on ctx (owned by ctx).  ctx == NULL gives

@@ -54,9 +54,22 @@ struct lpb_ctx {
     lpb_stats stats{};
     hipEvent_t ev0 = nullptr, ev1 = nullptr;
     hipEvent_t evs[11] = {};
+    // captured evaluation passes (options.graph)
+    hipStream_t own_stream = nullptr;   // capture needs a stream other than the null stream
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    bool tune_needed = true;
 };
 
 namespace {
+
+void drop_graph(lpb_ctx* c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    c->gexec = nullptr;
+    c->graph = nullptr;
+}
 
 lpb_status fail(lpb_ctx* c, lpb_status s, const std::string& msg)
 {
@@ -426,6 +439,8 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
 lpb_status build_and_upload(lpb_ctx* c)
 {
     auto t0 = std::chrono::steady_clock::now();
+    drop_graph(c);
+    c->tune_needed = true;
     free_bufs(c->plan_bufs);
     free_bufs(c->op_bufs);
     c->ops_dirty = true;
@@ -454,6 +469,8 @@ lpb_status build_and_upload(lpb_ctx* c)
 lpb_status generate_operators(lpb_ctx* c)
 {
     Plan& P = c->plan;
+    drop_graph(c);
+    c->tune_needed = true;
     free_bufs(c->op_bufs);
     const int K = P.K, Kp = (P.p + 1) * (P.p + 2) / 2;
     lpb_status s;
@@ -536,15 +553,84 @@ lpb_status generate_operators(lpb_ctx* c)
     return LPB_OK;
 }
 
-lpb_status run_eval(lpb_ctx* c)
+// Schedule autotuning: time each block -> work schedule of the two
+// matrix-core stages (3 launches each, best of 3) and keep the fastest.
+// The schedules permute which block computes which work item only.
+template <typename T>
+lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
 {
+    auto t0 = std::chrono::steady_clock::now();
+    int* field[2] = {&A.tile_sched, &A.batch_sched};
+    for (int which = 0; which < 2; ++which) {
+        float best = 1e30f;
+        int pick = 0;
+        for (int sc = 0; sc < 2; ++sc) {
+            *field[which] = sc;
+            float tmin = 1e30f;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+                hipError_t e = stage_run<T>(A, c->sched, which, c->stream);
+                if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+                HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+                HIPCHK(c, hipEventSynchronize(c->ev1));
+                float ms = 0.f;
+                HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+                tmin = std::min(tmin, ms);
+            }
+            if (tmin < best) {
+                best = tmin;
+                pick = sc;
+            }
+        }
+        *field[which] = pick;
+    }
+    c->stats.tile_schedule = A.tile_sched;
+    c->stats.batch_schedule = A.batch_sched;
+    c->stats.t_tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return LPB_OK;
+}
+
+template <typename T>
+lpb_status run_eval_t(lpb_ctx* c, EvalArgs<T>& A)
+{
+    if (c->tune_needed) {
+        if (c->opt.autotune) {
+            lpb_status s = autotune<T>(c, A);
+            if (s != LPB_OK) return s;
+        }
+        c->tune_needed = false;
+        drop_graph(c);
+    }
+    const bool use_graph = c->opt.graph && !c->opt.timing;
+    if (use_graph && !c->gexec) {
+        // every pass is a kernel (no memset nodes); the schedules and buffers
+        // it captures stay fixed until the next tree or operator change
+        HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, nullptr);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(c->stream, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return fail(c, LPB_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+        }
+        c->graph = g;
+        HIPCHK(c, hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0));
+    }
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    hipEvent_t* ev = c->opt.timing ? c->evs : nullptr;
-    hipError_t e = (c->opt.precision == LPB_MIXED) ? eval_run<float>(c->a32, c->sched, c->opt.stages, c->stream, ev)
-                                                   : eval_run<double>(c->a64, c->sched, c->opt.stages, c->stream, ev);
-    if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    if (use_graph) {
+        HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    } else {
+        hipEvent_t* ev = c->opt.timing ? c->evs : nullptr;
+        hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, ev);
+        if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    }
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     return LPB_OK;
+}
+
+lpb_status run_eval(lpb_ctx* c)
+{
+    return (c->opt.precision == LPB_MIXED) ? run_eval_t<float>(c, c->a32) : run_eval_t<double>(c, c->a64);
 }
 
 }  // namespace
@@ -564,6 +650,8 @@ void lpb_default_options(lpb_options* opt)
     opt->stream = nullptr;
     opt->stages = 3;
     opt->timing = 0;
+    opt->graph = 1;
+    opt->autotune = 1;
 }
 
 lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
@@ -587,6 +675,12 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     c->stream = (hipStream_t)o.stream;
     e = hipSetDevice(o.device);
     if (e != hipSuccess) return fail(nullptr, LPB_EDEVICE, hipGetErrorString(e));
+    if (o.graph && !c->stream) {
+        // graphs cannot be captured on the null stream: use a blocking stream of
+        // our own (it orders itself with the null stream)
+        if (hipStreamCreate(&c->own_stream) != hipSuccess) return fail(nullptr, LPB_EDEVICE, "stream create failed");
+        c->stream = c->own_stream;
+    }
     if (opgen_upload_constants() != hipSuccess) return fail(nullptr, LPB_EDEVICE, "constant upload failed");
     make_btab(o.p, c->btab);
     make_gtab(o.p, c->gtab);
@@ -809,6 +903,8 @@ void lpb_destroy(lpb_ctx* c)
     free_bufs(c->op_bufs);
     for (DevBuf* b : {&c->d_btab, &c->d_gtab, &c->d_glx, &c->d_glw, &c->d_flag})
         if (b->ptr) (void)hipFree(b->ptr);
+    drop_graph(c);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (auto& e : c->evs)

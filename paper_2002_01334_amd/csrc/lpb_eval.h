@@ -58,6 +58,8 @@ struct EvalArgs {
     // 1/it_n(lam h) per FMM and level for the source (ith_s) and target (ith_t) lambda
     const double *bes_tab, *ith_s, *ith_t;
     const int* swz_index;       // op -> position in pool_swz
+    // block -> work schedules of the matrix-core kernels (see sched_index)
+    int tile_sched, batch_sched;
 };
 
 struct EvalSched {
@@ -69,5 +71,11 @@ struct EvalSched {
 
 template <typename T>
 hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev);
+
+// One matrix-core stage alone, for schedule tuning: which = 0 the tiled M2L,
+// 1 the batched translations (M2M, untiled M2L, L2L).  Leaves ME/LE/scratch
+// contents that the next full evaluation overwrites.
+template <typename T>
+hipError_t stage_run(const EvalArgs<T>& A, const EvalSched& S, int which, hipStream_t st);
 
 }  // namespace lpb

@@ -177,6 +177,17 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 // expansions staged in LDS, the operator streamed from memory in the MFMA
 // operand layout.  Four waves split the 16-row blocks of the output; results
 // accumulate in registers over all 189 offsets and are added to LE once.
+// Block -> work item: schedule 0 is linear; schedule 1 gives the blocks of one
+// XCD (blocks are dispatched round robin over the 8 XCDs) a contiguous run of
+// work items, so items that share operators share that XCD's L2.  Both are
+// bijections of [0, n), so results do not depend on the schedule.
+__device__ inline int sched_index(int b, int n, int sched)
+{
+    if (sched == 0) return b;
+    const int x = b & 7, k = b >> 3, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + k;
+}
+
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
@@ -267,7 +278,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
     T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
     __shared__ int s_le[NT];
     const int K = A.K, KP = A.KP, KB = KP / 16;
-    const Tile tile = A.tiles[blockIdx.x];
+    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched)];
     const TileFL fl = A.tfl[tile.fl];
     const int nside = fl.nside;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -578,7 +589,7 @@ template <typename T, int RB>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
                                                  const int* __restrict__ dst, int wbase, int mode, int K, int KP,
-                                                 const T* __restrict__ pool_swz, int zrow)
+                                                 const T* __restrict__ pool_swz, int zrow, int sched)
 {
     typedef typename Vec4<T>::type V4;
     constexpr int NT = 64, CB = 4, GMAX = 4 * RB;
@@ -586,7 +597,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     extern __shared__ unsigned char smem_raw[];
     T* Bs = reinterpret_cast<T*>(smem_raw);   // [KP][NTP]
     const int KB = KP / 16;
-    const int wi = wbase + blockIdx.x;
+    const int wi = wbase + sched_index(blockIdx.x, gridDim.x, sched);
     const int t0 = term_ptr[wi], t1 = term_ptr[wi + 1];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     const int gj = tid >> 2, gpart = tid & 3;
@@ -645,7 +656,7 @@ static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, in
     const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
     dim3 g(w1 - w0), b(256);
 #define LPB_BATCHED(R) \
-    hipLaunchKernelGGL((k_batched<T, R>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, A.K, A.KP, A.pool_swz, zrow)
+    hipLaunchKernelGGL((k_batched<T, R>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched)
     switch (RB) {
     case 1: LPB_BATCHED(1); break;
     case 2: LPB_BATCHED(2); break;
@@ -690,7 +701,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
     T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
     __shared__ int s_le[NT];
     const int K = A.K;
-    const Tile tile = A.tiles[blockIdx.x];
+    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched)];
     const TileFL fl = A.tfl[tile.fl];
     const int nside = fl.nside;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -1271,5 +1282,20 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
 
 template hipError_t eval_run<double>(const EvalArgs<double>&, const EvalSched&, int, hipStream_t, hipEvent_t*);
 template hipError_t eval_run<float>(const EvalArgs<float>&, const EvalSched&, int, hipStream_t, hipEvent_t*);
+
+template <typename T>
+hipError_t stage_run(const EvalArgs<T>& A, const EvalSched& S, int which, hipStream_t st)
+{
+    if (which == 0) {
+        if (A.n_tiles > 0) launch_m2l_tile<T>(A, st);
+    } else {
+        for (int l = kMaxDepth; l >= 0; --l) launch_batched<T>(A, S.bm2m_lv[l], S.bm2m_lv[l + 1], A.me, A.n_me, A.me, 0, st);
+        launch_batched<T>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
+        for (int l = 0; l <= kMaxDepth; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.n_le, A.le, 1, st);
+    }
+    return hipGetLastError();
+}
+template hipError_t stage_run<double>(const EvalArgs<double>&, const EvalSched&, int, hipStream_t);
+template hipError_t stage_run<float>(const EvalArgs<float>&, const EvalSched&, int, hipStream_t);
 
 }  // namespace lpb

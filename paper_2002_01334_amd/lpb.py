@@ -27,13 +27,14 @@ _PD = ctypes.POINTER(ctypes.c_double)
 
 class Options(ctypes.Structure):
     _fields_ = [("p", _I), ("leaf_cap", _I), ("precision", _I), ("quad_tol", _D), ("iface_tol", _D),
-                ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I)]
+                ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I), ("graph", _I), ("autotune", _I)]
 
 
 class Stats(ctypes.Structure):
     _fields_ = [("n_fmm", _I), ("max_depth", _I), ("n_m2l_pairs", _L), ("n_m2l_tile_pairs", _L), ("n_p2p_pairs", _L),
                 ("n_react_p2p_pairs", _L), ("n_operators", _L), ("operator_bytes", _L),
-                ("t_build_ms", _D), ("t_opgen_ms", _D), ("t_eval_ms", _D), ("t_stage_ms", _D * 10)]
+                ("t_build_ms", _D), ("t_opgen_ms", _D), ("t_eval_ms", _D), ("t_stage_ms", _D * 10),
+                ("tile_schedule", _I), ("batch_schedule", _I), ("t_tune_ms", _D)]
 
     STAGES = ["setup", "p2m", "m2m", "m2l_tile", "m2l_list", "l2l", "l2p", "p2p_free", "p2p_react", "sum"]
 
@@ -117,7 +118,7 @@ class Context:
     """One lpb context (one GPU, one stream)."""
 
     def __init__(self, p=10, leaf_cap=50, precision=LPB_FP64, quad_tol=1e-16, iface_tol=1e-9, device=0,
-                 stream=None, stages=3, timing=0):
+                 stream=None, stages=3, timing=0, graph=1, autotune=1):
         L = load()
         opt = Options()
         L.lpb_default_options(ctypes.byref(opt))
@@ -130,6 +131,8 @@ class Context:
         opt.stream = stream
         opt.stages = stages
         opt.timing = timing
+        opt.graph = graph
+        opt.autotune = autotune
         h = _P()
         rc = L.lpb_create(ctypes.byref(opt), ctypes.byref(h))
         if rc != LPB_OK:
