@@ -1029,23 +1029,29 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
 // side h.  The first U-list leaf is the target's own (the r = 0 self pair is
 // excluded there only); terms are summed in groups of four and the group
 // sums are added with Kahan compensation.
-__device__ inline float p2p_term32(float4 hs, float4 ls, float xh, float yh, float zh, float xl, float yl, float zl,
-                                   float lamk)
+// positions are pre-scaled by s = lambda log2(e): with r' = s r the term is
+// q e^{-lambda r} / r = s q 2^{-r'} / r' (the factor s is applied once per
+// target); the hardware 2^x is used directly (terms below 2^-126 relative to
+// q / r' are negligible, so its flush of denormal results does not matter)
+__device__ inline float p2p_term32(float4 hs, float4 ls, float xh, float yh, float zh, float xl, float yl, float zl)
 {
     float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y), dz = (zh - hs.z) + (zl - ls.z);
     float r2 = dx * dx + dy * dy + dz * dz;
     float ri = __frsqrt_rn(r2);
-    return hs.w * exp2f(-lamk * (r2 * ri)) * ri;
+    return hs.w * __builtin_amdgcn_exp2f(-(r2 * ri)) * ri;
 }
 
 __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
 {
+    // the hi/lo splits of targets and sources must round identically (a pair
+    // at the same point must give exactly zero), so no multiply-add fusion here
+#pragma clang fp contract(off)
     constexpr int SMAX = 256;
     __shared__ float4 sh[SMAX];   // x, y, z (hi) and q
     __shared__ float4 sl[SMAX];   // x, y, z (lo)
     const int leaf = A.p2p_free_leaves[blockIdx.x];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
-    const float lamk = (float)(F.lam_t * 1.4426950408889634);
+    const double sc = F.lam_t * 1.4426950408889634;   // lambda log2(e)
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
@@ -1054,8 +1060,12 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
     for (int base = t0; base < t1; base += 32) {
         const int j = base + tl;
         const bool act = j < t1;
-        const float xh = act ? A.t_ux[j] : 0.f, yh = act ? A.t_uy[j] : 0.f, zh = act ? A.t_uz[j] : 0.f;
-        const float xl = act ? A.t_lx[j] : 0.f, yl = act ? A.t_ly[j] : 0.f, zl = act ? A.t_lz[j] : 0.f;
+        // target offset (hi + lo), scaled in FP64 and split again
+        const double TX = act ? ((double)A.t_ux[j] + (double)A.t_lx[j]) * sc : 0.0;
+        const double TY = act ? ((double)A.t_uy[j] + (double)A.t_ly[j]) * sc : 0.0;
+        const double TZ = act ? ((double)A.t_uz[j] + (double)A.t_lz[j]) * sc : 0.0;
+        const float xh = (float)TX, yh = (float)TY, zh = (float)TZ;
+        const float xl = (float)(TX - (double)xh), yl = (float)(TY - (double)yh), zl = (float)(TZ - (double)zh);
         float sum = 0.f, comp = 0.f;
         auto kahan = [&](float v) {
             float y = v - comp;
@@ -1075,9 +1085,9 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
                 const double ox = A.sl_ctr[3 * sl_i] - tcx, oy = A.sl_ctr[3 * sl_i + 1] - tcy,
                              oz = A.sl_ctr[3 * sl_i + 2] - tcz;
                 for (int i = lane; i < take; i += 64) {
-                    const double X = ((double)A.s_ux[s + i] + (double)A.s_lx[s + i]) + ox;
-                    const double Y = ((double)A.s_uy[s + i] + (double)A.s_ly[s + i]) + oy;
-                    const double Z = ((double)A.s_uz[s + i] + (double)A.s_lz[s + i]) + oz;
+                    const double X = (((double)A.s_ux[s + i] + (double)A.s_lx[s + i]) + ox) * sc;
+                    const double Y = (((double)A.s_uy[s + i] + (double)A.s_ly[s + i]) + oy) * sc;
+                    const double Z = (((double)A.s_uz[s + i] + (double)A.s_lz[s + i]) + oz) * sc;
                     const float hx = (float)X, hy = (float)Y, hz = (float)Z;
                     sh[n + i] = make_float4(hx, hy, hz, A.qs[s + i]);
                     sl[n + i] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), 0.f);
@@ -1097,23 +1107,23 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
                     const float4 hs = sh[jj], ls = sl[jj];
                     float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y), dz = (zh - hs.z) + (zl - ls.z);
                     float r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 > 0.f) kahan(p2p_term32(hs, ls, xh, yh, zh, xl, yl, zl, lamk));
+                    if (r2 > 0.f) kahan(p2p_term32(hs, ls, xh, yh, zh, xl, yl, zl));
                 }
                 int jj = ns + ((half - ns) & 1);
                 for (; jj + 6 < n; jj += 8) {
-                    float g = p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl, lamk) +
-                              p2p_term32(sh[jj + 2], sl[jj + 2], xh, yh, zh, xl, yl, zl, lamk);
-                    g += p2p_term32(sh[jj + 4], sl[jj + 4], xh, yh, zh, xl, yl, zl, lamk) +
-                         p2p_term32(sh[jj + 6], sl[jj + 6], xh, yh, zh, xl, yl, zl, lamk);
+                    float g = p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl) +
+                              p2p_term32(sh[jj + 2], sl[jj + 2], xh, yh, zh, xl, yl, zl);
+                    g += p2p_term32(sh[jj + 4], sl[jj + 4], xh, yh, zh, xl, yl, zl) +
+                         p2p_term32(sh[jj + 6], sl[jj + 6], xh, yh, zh, xl, yl, zl);
                     kahan(g);
                 }
-                for (; jj < n; jj += 2) kahan(p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl, lamk));
+                for (; jj < n; jj += 2) kahan(p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl));
             }
             staged += n;
         }
         // combine the two halves (lane l and l+32 share a target)
         const float other = __shfl_xor(sum - comp, 32, 64);
-        if (act && half == 0) A.parts[A.t_out[j]] += ((double)(sum - comp) + (double)other) / (4.0 * LPB_PI * F.eps_t);
+        if (act && half == 0) A.parts[A.t_out[j]] += ((double)(sum - comp) + (double)other) * sc / (4.0 * LPB_PI * F.eps_t);
     }
 }
 
