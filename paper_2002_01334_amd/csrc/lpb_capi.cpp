@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -371,9 +372,32 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     std::vector<int> p2m, l2p, pfree, rleaf, rslot, m2lb;
     for (size_t i = 0; i < P.sl_me.size(); ++i)
         if (P.sl_me[i] >= 0) p2m.push_back((int)i);
+    // free-space near field: work items of up to 64 targets of one leaf (dense
+    // leaves split over several blocks), most source-heavy first
+    std::vector<int> pfree_t0;
+    {
+        std::vector<std::array<int64_t, 3>> wl;   // (-cost class, leaf, first target)
+        for (size_t i = 0; i < P.tl_le.size(); ++i) {
+            if (P.p2p_ptr[i + 1] == P.p2p_ptr[i]) continue;
+            int64_t ns = 0;
+            for (int k = P.p2p_ptr[i]; k < P.p2p_ptr[i + 1]; ++k) ns += P.sl_start[P.p2p_src[k] + 1] - P.sl_start[P.p2p_src[k]];
+            for (int t = P.tl_start[i]; t < P.tl_start[i + 1]; t += 64) {
+                // cost class: floor(log2(pairs)); within a class the leaf order (locality) is kept
+                int64_t pairs = ns * std::min(64, P.tl_start[i + 1] - t), cls = 0;
+                while ((pairs >> (cls + 1)) > 0) ++cls;
+                wl.push_back({-cls, (int64_t)i, (int64_t)t});
+            }
+        }
+        std::stable_sort(wl.begin(), wl.end(), [](const std::array<int64_t, 3>& a, const std::array<int64_t, 3>& b) {
+            return a[0] < b[0];
+        });
+        for (auto& w : wl) {
+            pfree.push_back((int)w[1]);
+            pfree_t0.push_back((int)w[2]);
+        }
+    }
     for (size_t i = 0; i < P.tl_le.size(); ++i) {
         if (P.tl_le[i] >= 0) l2p.push_back((int)i);
-        if (P.p2p_ptr[i + 1] > P.p2p_ptr[i]) pfree.push_back((int)i);
         if (P.rp_ptr[i + 1] > P.rp_ptr[i])
             for (int j = P.tl_start[i]; j < P.tl_start[i + 1]; ++j) {
                 rleaf.push_back((int)i);
@@ -385,6 +409,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(p2m_leaves, p2m);
     UP(l2p_leaves, l2p);
     UP(p2p_free_leaves, pfree);
+    UP(p2p_free_t0, pfree_t0);
     UP(react_tgt_leaf, rleaf);
     UP(react_tgt_slot, rslot);
     UP(m2l_boxes, m2lb);

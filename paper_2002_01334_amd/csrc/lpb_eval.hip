@@ -951,11 +951,11 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
 // Free-space near field (eq. freereactioncomponents, j != i):
 //   Phi_i += sum_{j in U(i), j != i} q_j e^{-lam r}/(4 pi eps r)
 // (the self term is the pair at distance 0; charges must be distinct points)
-// One 64-lane block per target leaf.  All U-list sources (up to 1024 at a
-// time) are staged in LDS with their offset from the target leaf centre;
-// two lanes share a target and split the sources, and combine at the end.
-// FP32: hardware exp2/rsqrt and Kahan-compensated sums.
-__device__ inline float pair_kernel(float r2, float lam_log2e) { float ri = __frsqrt_rn(r2); return exp2f(-lam_log2e * (r2 * ri)) * ri; }
+// One 64-lane block per work item of up to 64 targets of one leaf (dense
+// leaves span several items).  All U-list sources (up to SMAX at a time)
+// are staged in LDS with their offset from the target leaf centre; two lanes
+// share a target and split the sources, and combine at the end.  This is the
+// FP64 form (the FP32 one follows).
 __device__ inline double pair_kernel(double r2, double lam) { double r = sqrt(r2); return exp(-lam * r) / r; }
 
 template <typename T>
@@ -966,7 +966,7 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
     const int leaf = A.p2p_free_leaves[blockIdx.x];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const T lamk = (sizeof(T) == 4) ? (T)(F.lam_t * 1.4426950408889634) : (T)F.lam_t;
-    const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
+    const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + 64);
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
     const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
@@ -1052,7 +1052,7 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
     const int leaf = A.p2p_free_leaves[blockIdx.x];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double sc = F.lam_t * 1.4426950408889634;   // lambda log2(e)
-    const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
+    const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + 64);
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
     const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
