@@ -293,6 +293,8 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(bw_op, P.bw_op);
     UP(bw_src, P.bw_src);
     UP(bw_dst, P.bw_dst);
+    UP(bw_xc, P.bw_xc);
+    UP(bw_xa, P.bw_xa);
     UP(m2l_ptr, P.m2l_ptr);
     UP(m2l_src, P.m2l_src);
     UP(m2l_op, P.m2l_op);

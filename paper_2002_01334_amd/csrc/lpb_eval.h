@@ -36,6 +36,8 @@ struct EvalArgs {
     const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;
     // batched translations (M2M, L2L, untiled V-list pairs): see Plan
     const int *bw_term_ptr, *bw_op, *bw_src, *bw_dst;
+    const int* bw_xc;           // per column transform code (-1 none, 0..7 reflection, kXfRotate rotation)
+    const double* bw_xa;        // per column rotation angle
     T* m2l_scratch;     // one KP row per untiled V-list pair
     const int *p2p_ptr, *p2p_src;
     const int *rp_ptr, *rp_fmm, *rp_src;   // reaction near field: per target leaf, (FMM, source leaf)

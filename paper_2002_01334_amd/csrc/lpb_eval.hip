@@ -585,11 +585,55 @@ __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A)
 // and stores y_j (mode 0) or adds it (mode 1) to row dst[j] of `out`.
 // Sources are gathered into LDS as in the tiled M2L, the next term's sources
 // load during the current term's products.
-template <typename T, int RB>
+// In-LDS per-column transform of a staged block B[k][j] (KP rows, NTP
+// stride): reflection signs D (code 0..7) or the rotation of every order-m
+// (Re, Im) pair by +m phi (sources) or -m phi (results) (code kXfRotate).
+// Every thread of the 256 takes column j = tid & 63 and a quarter of the rows.
+// cs[m * 128 + j] = cos(m phi_j), cs[m * 128 + 64 + j] = sin(m phi_j), m = 1..p
+template <typename T>
+__device__ inline void column_trig(T* cs, int p, int code, double phi)
+{
+    const int j = threadIdx.x & 63, part = threadIdx.x >> 6;
+    if (code != kXfRotate) return;
+    for (int m = 1 + part; m <= p; m += 4) {
+        double sd, cd;
+        sincos((double)m * phi, &sd, &cd);
+        cs[m * 128 + j] = (T)cd;
+        cs[m * 128 + 64 + j] = (T)sd;
+    }
+}
+
+template <typename T>
+__device__ inline void column_xform(T* Bs, int NTP, int p, int K, int KP, int code, const T* cs, const T* __restrict__ refl,
+                                    bool result)
+{
+    const int j = threadIdx.x & 63, part = threadIdx.x >> 6;
+    if (code < 0) return;
+    if (code < kXfRotate) {
+        const T* sg = refl + (size_t)code * KP;
+        for (int k = part; k < K; k += 4) Bs[k * NTP + j] *= sg[k];
+        return;
+    }
+    int q = 0;
+    for (int n = 1; n <= p; ++n)
+        for (int m = 1; m <= n; ++m, ++q) {
+            if ((q & 3) != part) continue;
+            const T c = cs[m * 128 + j], sn = result ? -cs[m * 128 + 64 + j] : cs[m * 128 + 64 + j];
+            T& re = Bs[ire(n, m) * NTP + j];
+            T& im = Bs[iim(n, m) * NTP + j];
+            const T a = re, b = im;
+            re = a * c - b * sn;
+            im = a * sn + b * c;
+        }
+}
+
+template <typename T, int RB, bool XF>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
                                                  const int* __restrict__ dst, int wbase, int mode, int K, int KP,
-                                                 const T* __restrict__ pool_swz, int zrow, int sched)
+                                                 const T* __restrict__ pool_swz, int zrow, int sched,
+                                                 const int* __restrict__ xcode, const double* __restrict__ xang,
+                                                 const T* __restrict__ refl, int p)
 {
     typedef typename Vec4<T>::type V4;
     constexpr int NT = 64, CB = 4, GMAX = 4 * RB;
@@ -607,6 +651,10 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
     V4 greg[GMAX];
+    // XF: per-column transform code and, for rotations, cos / sin (m phi) after B in LDS
+    T* trig = Bs + (size_t)KP * NTP;
+    const int xc = XF ? xcode[(size_t)wi * NT + (tid & 63)] : -1;
+    if (XF) column_trig<T>(trig, p, xc, xang[(size_t)wi * NT + (tid & 63)]);
     auto fetch = [&](int t) {
         const int sidx = term_src[(size_t)t * NT + gj];
         const T* src = in + (size_t)(sidx < 0 ? zrow : sidx) * KP + 4 * gpart;   // missing: the zero row
@@ -624,10 +672,39 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
             }
         }
         __syncthreads();
+        if (XF) {
+            // sources into the frame of the stored operator
+            column_xform<T>(Bs, NTP, p, K, KP, xc, trig, refl, false);
+            __syncthreads();
+        }
         const T* Aw = pool_swz + (size_t)term_op[t] * KP * KP;
         if (t + 1 < t1) fetch(t + 1);
         mma_block<T, RB, CB>(Aw, Bs, NTP, KB, w, l, acc);
         accumulate<T, RB, CB>(acc, tot, cmp);
+    }
+    if (XF) {
+        // results back from the operator's frame, through LDS, then stored row-contiguously
+        __syncthreads();
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            int rbg = w * RB + rb;
+            if (rbg >= KB) continue;
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) Bs[(rbg * 16 + mfma_row(T(0), l, r)) * NTP + cb * 16 + (l & 15)] = tot[rb][cb][r];
+        }
+        __syncthreads();
+        column_xform<T>(Bs, NTP, p, K, KP, xc, trig, refl, true);
+        __syncthreads();
+        for (int e = tid; e < NT * K; e += 256) {
+            const int j = e / K, row = e - j * K;
+            const int d = dst[(size_t)wi * NT + j];
+            if (d < 0) continue;
+            if (mode == 0) out[(size_t)d * KP + row] = Bs[row * NTP + j];
+            else out[(size_t)d * KP + row] += Bs[row * NTP + j];
+        }
+        return;
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
@@ -648,15 +725,16 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     }
 }
 
-template <typename T>
-static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, int zrow, T* out, int mode, hipStream_t st)
+template <typename T, bool XF>
+static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, int zrow, T* out, int mode, hipStream_t st)
 {
     if (w1 <= w0) return;
     const int KB = A.KP / 16, RB = (KB + 3) / 4;
-    const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
+    const size_t sm = sizeof(T) * ((size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8)) + (XF ? (size_t)(A.p + 1) * 128 : 0));
     dim3 g(w1 - w0), b(256);
-#define LPB_BATCHED(R) \
-    hipLaunchKernelGGL((k_batched<T, R>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched)
+#define LPB_BATCHED(R)                                                                                                    \
+    hipLaunchKernelGGL((k_batched<T, R, XF>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, \
+                       A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.bw_xa, A.refl_sign, A.p)
     switch (RB) {
     case 1: LPB_BATCHED(1); break;
     case 2: LPB_BATCHED(2); break;
@@ -667,6 +745,11 @@ static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, in
     default: LPB_BATCHED(7); break;
     }
 #undef LPB_BATCHED
+}
+template <typename T>
+static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, int zrow, T* out, int mode, hipStream_t st)
+{
+    launch_batched_x<T, false>(A, w0, w1, in, zrow, out, mode, st);
 }
 
 // V-list pairs outside the tiled levels: LE[box] += sum of the box's pair rows
@@ -1249,7 +1332,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     if (far && A.n_tiles > 0) launch_m2l_tile<T>(A, st);
     LPB_MARK(4);
     if (far && S.bm2l_w1 > S.bm2l_w0) {
-        launch_batched<T>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
+        launch_batched_x<T, true>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
         hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(128), 0, st, A);
     }
     LPB_MARK(5);
@@ -1300,7 +1383,7 @@ hipError_t stage_run(const EvalArgs<T>& A, const EvalSched& S, int which, hipStr
         if (A.n_tiles > 0) launch_m2l_tile<T>(A, st);
     } else {
         for (int l = kMaxDepth; l >= 0; --l) launch_batched<T>(A, S.bm2m_lv[l], S.bm2m_lv[l + 1], A.me, A.n_me, A.me, 0, st);
-        launch_batched<T>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
+        launch_batched_x<T, true>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
         for (int l = 0; l <= kMaxDepth; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.n_le, A.le, 1, st);
     }
     return hipGetLastError();

@@ -22,6 +22,13 @@ constexpr int kVOffsets = 189;    // V-list offsets of one child octant
 // the offset (sx dx, sy dy, sz dz) uses it between sign flips D = diag(+-1)
 // of both the source and the result (reflection bits: 1 x, 2 y, 4 z).
 constexpr int kReflShift = 28;
+// Untiled V-list pairs share operators the same way per pair: free-space
+// pairs by reflection (code 0..7, A_d = D A_|d| D) and reaction pairs by
+// rotation about z (code kXfRotate): the reaction translation depends on the
+// azimuth phi of c_t - c_s only through e^{i(mu - m) phi}, so
+// T(phi) = diag(e^{-i m phi}) T(0) diag(e^{i mu phi}) and one operator per
+// (level, rho, z_t, z_s) serves every direction.
+constexpr int kXfRotate = 8;
 
 enum OpType { OP_M2M = 0, OP_L2L = 1, OP_M2L_FREE = 2, OP_M2L_REACT = 3 };
 
@@ -132,10 +139,15 @@ struct Plan {
     int n_me = 0, n_le = 0;
     // M2L: CSR by target LE box
     std::vector<int> m2l_ptr, m2l_src, m2l_op;   // m2l_ptr has n_le+1
+    // per pair: how the pair's operator relates to the stored one (see kXfRotate)
+    std::vector<int> m2l_xc;
+    std::vector<double> m2l_xa;
     // batched dense translations on the matrix cores: work item w has terms
     // [bw_term_ptr[w], bw_term_ptr[w+1]), term t = operator bw_op[t] and 64
     // source rows bw_src[64 t + j]; 64 destination rows bw_dst[64 w + j] (-1: none)
     std::vector<int> bw_term_ptr, bw_op, bw_src, bw_dst;
+    std::vector<int> bw_xc;      // per column: -1 none, 0..7 reflection code, kXfRotate rotation by bw_xa
+    std::vector<double> bw_xa;
     std::vector<int> bm2m_lv, bl2l_lv;   // work items of M2M (parent level) / L2L (child level) l: [v[l], v[l+1])
     int bm2l_w0 = 0, bm2l_w1 = 0;        // V-list pairs outside the tiled levels, grouped by operator;
                                          // destination = the pair's position in m2l_src (scratch row)

@@ -97,12 +97,16 @@ struct BWork {
     std::vector<int> op;    // per term
     std::vector<int> src;   // 64 per term
     std::array<int, 64> dst;
+    std::array<int, 64> xc;      // per column transform code (-1 none)
+    std::array<double, 64> xa;   // rotation angle
+    BWork() { xc.fill(-1); xa.fill(0.0); }
 };
 
 // Staging shared by the tree and list builders.
 struct Staging {
     std::vector<std::vector<BWork>> bm2m{(size_t)kMaxDepth + 1}, bl2l{(size_t)kMaxDepth + 1};
-    std::vector<std::vector<std::pair<int, int>>> m2l_by_le;    // per LE box: (source ME, op)
+    struct M2LPair { int src, op, xc; double xa; };
+    std::vector<std::vector<M2LPair>> m2l_by_le;                // per LE box
     std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: free-space source leaves
     std::vector<std::vector<std::pair<int, int>>> rp_by_tl;     // per target leaf: (reaction FMM, source leaf)
     std::vector<double> s_ux, s_uy, s_uz, t_ux, t_uy, t_uz;
@@ -379,42 +383,40 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                                 P.n_m2l_pairs++;
                                 continue;
                             }
-                            int op;
+                            int op, xc;
+                            double xa = 0.0;
                             if (F.kind == 0) {
-                                op = free_op(lv, dx, dy, dz);
+                                // one operator per offset with non-negative components, D A D for the others
+                                op = free_op(lv, std::abs(dx), std::abs(dy), std::abs(dz));
+                                xc = (dx < 0 ? 1 : 0) | (dy < 0 ? 2 : 0) | (dz < 0 ? 4 : 0);
                             } else {
-                                uint64_t key = ((uint64_t)lv << 48) | ((uint64_t)(dx + 3) << 40) | ((uint64_t)(dy + 3) << 32) |
-                                               ((uint64_t)tz << 16) | (uint64_t)sz;
-                                auto f = opmap.find(key);
-                                if (f == opmap.end()) {
-                                    int d2 = dx * dx + dy * dy;
-                                    uint64_t rk = ((uint64_t)lv << 48) | ((uint64_t)d2 << 32) | ((uint64_t)tz << 16) | (uint64_t)sz;
-                                    int rki;
-                                    auto g = rkmap.find(rk);
-                                    if (g == rkmap.end()) {
-                                        RKey r{};
-                                        r.fmm = fid;
-                                        r.level = lv;
-                                        r.rho = h * std::sqrt((double)d2);
-                                        r.zt = centre(lv, tz);
-                                        r.zs = centre(lv, sz);
-                                        r.S = h;
-                                        rki = (int)P.rkeys.size();
-                                        P.rkeys.push_back(r);
-                                        rkmap[rk] = rki;
-                                    } else rki = g->second;
+                                // one operator per (level, rho, z_t, z_s) at phi = 0, rotated per pair
+                                const int d2 = dx * dx + dy * dy;
+                                const uint64_t rk = ((uint64_t)lv << 48) | ((uint64_t)d2 << 32) | ((uint64_t)tz << 16) | (uint64_t)sz;
+                                auto g = rkmap.find(rk);
+                                if (g == rkmap.end()) {
+                                    RKey r{};
+                                    r.fmm = fid;
+                                    r.level = lv;
+                                    r.rho = h * std::sqrt((double)d2);
+                                    r.zt = centre(lv, tz);
+                                    r.zs = centre(lv, sz);
+                                    r.S = h;
+                                    P.rkeys.push_back(r);
                                     OpDesc d{};
                                     d.type = OP_M2L_REACT;
                                     d.fmm = fid;
                                     d.level = lv;
-                                    d.rkey = rki;
-                                    d.phi = (dx == 0 && dy == 0) ? 0.0 : std::atan2((double)-dy, (double)-dx);
+                                    d.rkey = (int)P.rkeys.size() - 1;
+                                    d.phi = 0.0;
                                     op = (int)P.ops.size();
                                     P.ops.push_back(d);
-                                    opmap[key] = op;
-                                } else op = f->second;
+                                    rkmap[rk] = op;
+                                } else op = g->second;
+                                xc = kXfRotate;
+                                xa = (dx == 0 && dy == 0) ? 0.0 : std::atan2((double)-dy, (double)-dx);
                             }
-                            S.m2l_by_le[le].push_back({ST.off[lv] + it->second, op});
+                            S.m2l_by_le[le].push_back({ST.off[lv] + it->second, op, xc, xa});
                             P.n_m2l_pairs++;
                         }
                     }
@@ -691,22 +693,26 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         P.t_u[2 * S.t_ux.size() + i] = S.t_uz[i];
     }
     for (size_t i = 0; i < P.t_out.size(); ++i) P.t_out[i] = (int)(P.t_out[i] * P.ncharges + P.t_cidx[i]);
-    P.m2l_ptr.assign(1, 0); P.m2l_src.clear(); P.m2l_op.clear();
+    P.m2l_ptr.assign(1, 0); P.m2l_src.clear(); P.m2l_op.clear(); P.m2l_xc.clear(); P.m2l_xa.clear();
     S.m2l_by_le.resize(P.n_le);
     for (int i = 0; i < P.n_le; ++i) {
         for (auto& e : S.m2l_by_le[i]) {
-            P.m2l_src.push_back(e.first);
-            P.m2l_op.push_back(e.second);
+            P.m2l_src.push_back(e.src);
+            P.m2l_op.push_back(e.op);
+            P.m2l_xc.push_back(e.xc);
+            P.m2l_xa.push_back(e.xa);
         }
         P.m2l_ptr.push_back((int)P.m2l_src.size());
     }
     // batched work items: M2M and L2L per level, then the V-list pairs outside
     // the tiled levels grouped by operator
-    P.bw_term_ptr.assign(1, 0); P.bw_op.clear(); P.bw_src.clear(); P.bw_dst.clear();
+    P.bw_term_ptr.assign(1, 0); P.bw_op.clear(); P.bw_src.clear(); P.bw_dst.clear(); P.bw_xc.clear(); P.bw_xa.clear();
     auto push_work = [&](const BWork& wk) {
         P.bw_op.insert(P.bw_op.end(), wk.op.begin(), wk.op.end());
         P.bw_src.insert(P.bw_src.end(), wk.src.begin(), wk.src.end());
         P.bw_dst.insert(P.bw_dst.end(), wk.dst.begin(), wk.dst.end());
+        P.bw_xc.insert(P.bw_xc.end(), wk.xc.begin(), wk.xc.end());
+        P.bw_xa.insert(P.bw_xa.end(), wk.xa.begin(), wk.xa.end());
         P.bw_term_ptr.push_back((int)P.bw_op.size());
     };
     P.bm2m_lv.assign(kMaxDepth + 2, 0);
@@ -736,6 +742,8 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
             for (size_t j = i; j < e; ++j) {
                 wk.src[j - i] = P.m2l_src[byop[j].second];
                 wk.dst[j - i] = byop[j].second;
+                wk.xc[j - i] = P.m2l_xc[byop[j].second];
+                wk.xa[j - i] = P.m2l_xa[byop[j].second];
             }
             push_work(wk);
             i = e;
