@@ -97,8 +97,9 @@ typedef struct {
      * [4] list M2L (reaction, deep levels), [5] L2L, [6] L2P,
      * [7] free-space near field, [8] reaction near field, [9] component sum */
     double t_stage_ms[10];
-    int tile_schedule;      /* schedule chosen for the tiled M2L: 0 linear, 1 blocks of one XCD take a
-                               contiguous run of tiles (tiles sharing operators share that XCD's L2) */
+    int tile_schedule;      /* schedule chosen for the tiled M2L: bit 0 = 0 linear, 1 blocks of one XCD take a
+                               contiguous run of tiles (tiles sharing operators share that XCD's L2); bit 1 =
+                               blocks of one wave per 16-row block instead of four waves */
     int batch_schedule;     /* the same choice for the batched translations */
     double t_tune_ms;       /* time spent by the last schedule autotuning */
 } lpb_stats;

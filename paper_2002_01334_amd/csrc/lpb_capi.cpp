@@ -582,7 +582,8 @@ lpb_status generate_operators(lpb_ctx* c)
 
 // Schedule autotuning: time each block -> work schedule of the two
 // matrix-core stages (3 launches each, best of 3) and keep the fastest.
-// The schedules permute which block computes which work item only.
+// The candidates permute which block computes which work item, or (tiled
+// M2L) split the same products over more waves; results do not change.
 template <typename T>
 lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
 {
@@ -591,7 +592,8 @@ lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
     for (int which = 0; which < 2; ++which) {
         float best = 1e30f;
         int pick = 0;
-        for (int sc = 0; sc < 2; ++sc) {
+        const int ncand = which == 0 ? 4 : 2;   // tiled M2L: schedule bit 0, wide-block variant bit 1
+        for (int sc = 0; sc < ncand; ++sc) {
             *field[which] = sc;
             float tmin = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {

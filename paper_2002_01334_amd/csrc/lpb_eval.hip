@@ -278,7 +278,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
     T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
     __shared__ int s_le[NT];
     const int K = A.K, KP = A.KP, KB = KP / 16;
-    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched)];
+    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched & 1)];
     const TileFL fl = A.tfl[tile.fl];
     const int nside = fl.nside;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -770,21 +770,26 @@ __global__ void k_m2l_reduce(EvalArgs<T> A)
 // time (p <= 15): the 16-column slabs of the operator stream through a ring
 // of D register slabs, so every load is issued D slabs (D * RB * 4 MFMAs)
 // ahead of its use, continuing across offsets into the next operator.
-template <typename T, int KB>
-__global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
+// RBW = 0: four waves, each owning ceil(KB/4) row blocks; RBW = 1: KB waves
+// of one row block each (more waves per CU to hide latency, same arithmetic
+// per output element in the same order, so both give identical results).
+template <typename T, int KB, int RBW>
+__global__ void __launch_bounds__(RBW == 1 ? 64 * KB : 256) k_m2l_tile_kb(EvalArgs<T> A)
 {
     typedef typename Vec4<T>::type V4;
-    constexpr int RB = (KB + 3) / 4;
+    constexpr int NWT = (RBW == 1) ? KB : 4;              // waves per block
+    constexpr int RB = (RBW == 1) ? 1 : (KB + 3) / 4;     // row blocks per wave
     constexpr int NWACT = (KB + RB - 1) / RB;   // waves that own row blocks (the others only gather)
-    constexpr int D = (sizeof(T) == 4 && RB <= 2) ? ((KB % 4 == 0) ? 4 : ((KB % 2 == 0) ? 2 : 1))
-                                                  : ((KB % 2 == 0) ? 2 : 1);
+    constexpr int NV = 4 * KB / NWT;                       // staged 4-vectors per thread and offset
+    constexpr int D = (RBW == 0 && sizeof(T) == 4 && RB <= 2) ? ((KB % 4 == 0) ? 4 : ((KB % 2 == 0) ? 2 : 1))
+                                                               : ((KB % 2 == 0) ? 2 : 1);
     constexpr int NT = 64, CB = 4, KP = 16 * KB;
     constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);   // padded LDS row (bank spread)
     extern __shared__ unsigned char smem_raw[];
     T* Bs = reinterpret_cast<T*>(smem_raw);               // [KP][NTP]
     __shared__ int s_le[NT];
     const int K = A.K;
-    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched)];
+    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched & 1)];
     const TileFL fl = A.tfl[tile.fl];
     const int nside = fl.nside;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -806,12 +811,12 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
                         ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
     }
     __syncthreads();
-    const int gj = tid >> 2, gpart = tid & 3;
+    const int gj = tid / NWT, gpart = tid % NWT;   // column and 4-vector part of the gather
     int gtx, gty, gtz;
     tcoord(gj, gtx, gty, gtz);
     const bool gvalid = s_le[gj] >= 0;
     const int* codes = A.oct_codes + tile.octant * kVOffsets;
-    V4 greg[KB];
+    V4 greg[NV];
     auto fetch = [&](int d) {
         const int code = codes[d];
         const int sx = gtx + code / 49 - 3, sy = gty + (code / 7) % 7 - 3, sz = gtz + code % 7 - 3;
@@ -821,7 +826,7 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
         // a missing source reads the zero row
         const T* src = A.me + (size_t)(me < 0 ? A.n_me : me) * KP + 4 * gpart;
 #pragma unroll
-        for (int i = 0; i < KB; ++i) greg[i] = *reinterpret_cast<const V4*>(src + 16 * i);
+        for (int i = 0; i < NV; ++i) greg[i] = *reinterpret_cast<const V4*>(src + 4 * NWT * i);
     };
     auto opent = [&](int d) { return A.optab[fl.optab_off + codes[d]]; };
     auto opA = [&](int d) {
@@ -852,9 +857,12 @@ __global__ void __launch_bounds__(256) k_m2l_tile_kb(EvalArgs<T> A)
         const T* sg = A.refl_sign + (size_t)cls * KP;
         __syncthreads();   // every wave is done with the previous offset's B
 #pragma unroll
-        for (int i = 0; i < KB; ++i) {
+        for (int i = 0; i < NV; ++i) {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e] * sg[16 * i + 4 * gpart + e];
+            for (int e = 0; e < 4; ++e) {
+                const int k = 4 * (NWT * i + gpart) + e;
+                Bs[k * NTP + gj] = greg[i][e] * sg[k];
+            }
         }
         __syncthreads();
         const bool more = d + 1 < kVOffsets;
@@ -940,8 +948,13 @@ static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
     const int KB = A.KP / 16, RB = (KB + 3) / 4;
     const size_t sm = sizeof(T) * (size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8));
     dim3 g(A.n_tiles), b(256);
-#define LPB_TKB(N) \
-    case N: hipLaunchKernelGGL((k_m2l_tile_kb<T, N>), g, b, sm, st, A); return;
+    // variant bit of the schedule: KB waves of one row block each
+    const bool wide = (A.tile_sched >> 1) & 1;
+#define LPB_TKB(N)                                                                                  \
+    case N:                                                                                         \
+        if (wide) hipLaunchKernelGGL((k_m2l_tile_kb<T, N, 1>), g, dim3(64 * N), sm, st, A);         \
+        else hipLaunchKernelGGL((k_m2l_tile_kb<T, N, 0>), g, b, sm, st, A);                         \
+        return;
     switch (KB) {
         LPB_TKB(1) LPB_TKB(2) LPB_TKB(3) LPB_TKB(4) LPB_TKB(5) LPB_TKB(6)
         LPB_TKB(7) LPB_TKB(8) LPB_TKB(9) LPB_TKB(10) LPB_TKB(11) LPB_TKB(12)
