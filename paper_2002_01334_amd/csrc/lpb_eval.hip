@@ -1129,19 +1129,28 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
 // q e^{-lambda r} / r = s q 2^{-r'} / r' (the factor s is applied once per
 // target); the hardware 2^x is used directly (terms below 2^-126 relative to
 // q / r' are negligible, so its flush of denormal results does not matter)
-__device__ inline float p2p_term32(float4 hs, float4 ls, float xh, float yh, float zh, float xl, float yl, float zl)
+// The hi parts alone (offsets below 1.5 h per axis, h the leaf side) give a
+// distance to within 3.1e-7 h, i.e. 5e-6 of r at worst for r >= h/16, where
+// such rounding errors of independent pairs largely cancel in the sum; only a
+// pair closer than h/16 takes the lo parts.  Sources are taken four at a time: hi-part distances first, and the
+// lo parts only in the (rare) groups holding such a pair.
+__device__ inline float p2p_term32(float w, float r2)
 {
-    float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y), dz = (zh - hs.z) + (zl - ls.z);
-    float r2 = dx * dx + dy * dy + dz * dz;
-    float ri = __frsqrt_rn(r2);
-    return hs.w * __builtin_amdgcn_exp2f(-(r2 * ri)) * ri;
+    const float ri = __frsqrt_rn(r2);
+    return w * __builtin_amdgcn_exp2f(-(r2 * ri)) * ri;
+}
+
+// The hi/lo splits of targets and sources must round identically (a pair at
+// one point must give exactly zero): the scaled position is rounded to FP64
+// on its own, never fused into the subtraction that forms the lo part.
+__device__ inline double mul_rn(double a, double b)
+{
+#pragma clang fp contract(off)
+    return a * b;
 }
 
 __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
 {
-    // the hi/lo splits of targets and sources must round identically (a pair
-    // at the same point must give exactly zero), so no multiply-add fusion here
-#pragma clang fp contract(off)
     constexpr int SMAX = 256;
     __shared__ float4 sh[SMAX];   // x, y, z (hi) and q
     __shared__ float4 sl[SMAX];   // x, y, z (lo)
@@ -1149,6 +1158,7 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double sc = F.lam_t * 1.4426950408889634;   // lambda log2(e)
     const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + 64);
+    const float thr2 = (float)((A.tl_h[leaf] * sc / 16.0) * (A.tl_h[leaf] * sc / 16.0));
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
     const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
@@ -1157,9 +1167,9 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
         const int j = base + tl;
         const bool act = j < t1;
         // target offset (hi + lo), scaled in FP64 and split again
-        const double TX = act ? ((double)A.t_ux[j] + (double)A.t_lx[j]) * sc : 0.0;
-        const double TY = act ? ((double)A.t_uy[j] + (double)A.t_ly[j]) * sc : 0.0;
-        const double TZ = act ? ((double)A.t_uz[j] + (double)A.t_lz[j]) * sc : 0.0;
+        const double TX = act ? mul_rn((double)A.t_ux[j] + (double)A.t_lx[j], sc) : 0.0;
+        const double TY = act ? mul_rn((double)A.t_uy[j] + (double)A.t_ly[j], sc) : 0.0;
+        const double TZ = act ? mul_rn((double)A.t_uz[j] + (double)A.t_lz[j], sc) : 0.0;
         const float xh = (float)TX, yh = (float)TY, zh = (float)TZ;
         const float xl = (float)(TX - (double)xh), yl = (float)(TY - (double)yh), zl = (float)(TZ - (double)zh);
         float sum = 0.f, comp = 0.f;
@@ -1181,9 +1191,9 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
                 const double ox = A.sl_ctr[3 * sl_i] - tcx, oy = A.sl_ctr[3 * sl_i + 1] - tcy,
                              oz = A.sl_ctr[3 * sl_i + 2] - tcz;
                 for (int i = lane; i < take; i += 64) {
-                    const double X = (((double)A.s_ux[s + i] + (double)A.s_lx[s + i]) + ox) * sc;
-                    const double Y = (((double)A.s_uy[s + i] + (double)A.s_ly[s + i]) + oy) * sc;
-                    const double Z = (((double)A.s_uz[s + i] + (double)A.s_lz[s + i]) + oz) * sc;
+                    const double X = mul_rn(((double)A.s_ux[s + i] + (double)A.s_lx[s + i]) + ox, sc);
+                    const double Y = mul_rn(((double)A.s_uy[s + i] + (double)A.s_ly[s + i]) + oy, sc);
+                    const double Z = mul_rn(((double)A.s_uz[s + i] + (double)A.s_lz[s + i]) + oz, sc);
                     const float hx = (float)X, hy = (float)Y, hz = (float)Z;
                     sh[n + i] = make_float4(hx, hy, hz, A.qs[s + i]);
                     sl[n + i] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), 0.f);
@@ -1199,21 +1209,34 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
             if (act) {
                 // staged sources below nself belong to the target's own leaf
                 const int ns = min(max(nself - staged, 0), n);
+                auto full_r2 = [&](int i) {
+                    const float4 hs = sh[i], ls = sl[i];
+                    const float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y),
+                                dz = (zh - hs.z) + (zl - ls.z);
+                    return dx * dx + dy * dy + dz * dz;
+                };
                 for (int jj = half; jj < ns; jj += 2) {
-                    const float4 hs = sh[jj], ls = sl[jj];
-                    float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y), dz = (zh - hs.z) + (zl - ls.z);
-                    float r2 = dx * dx + dy * dy + dz * dz;
-                    if (r2 > 0.f) kahan(p2p_term32(hs, ls, xh, yh, zh, xl, yl, zl));
+                    const float r2 = full_r2(jj);
+                    if (r2 > 0.f) kahan(p2p_term32(sh[jj].w, r2));
                 }
                 int jj = ns + ((half - ns) & 1);
                 for (; jj + 6 < n; jj += 8) {
-                    float g = p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl) +
-                              p2p_term32(sh[jj + 2], sl[jj + 2], xh, yh, zh, xl, yl, zl);
-                    g += p2p_term32(sh[jj + 4], sl[jj + 4], xh, yh, zh, xl, yl, zl) +
-                         p2p_term32(sh[jj + 6], sl[jj + 6], xh, yh, zh, xl, yl, zl);
-                    kahan(g);
+                    float w[4], r2[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const float4 hs = sh[jj + 2 * u];
+                        const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
+                        w[u] = hs.w;
+                        r2[u] = dx * dx + dy * dy + dz * dz;
+                    }
+                    if (fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3])) < thr2) {
+#pragma unroll
+                        for (int u = 0; u < 4; ++u) r2[u] = full_r2(jj + 2 * u);
+                    }
+                    kahan((p2p_term32(w[0], r2[0]) + p2p_term32(w[1], r2[1])) +
+                          (p2p_term32(w[2], r2[2]) + p2p_term32(w[3], r2[3])));
                 }
-                for (; jj < n; jj += 2) kahan(p2p_term32(sh[jj], sl[jj], xh, yh, zh, xl, yl, zl));
+                for (; jj < n; jj += 2) kahan(p2p_term32(sh[jj].w, full_r2(jj)));
             }
             staged += n;
         }
