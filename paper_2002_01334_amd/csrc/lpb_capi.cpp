@@ -245,6 +245,22 @@ lpb_status upload_points(lpb_ctx* c, const std::vector<double>& u3, int n, const
     return LPB_OK;
 }
 
+// Coefficients in sign-class order (natural order within a class), each
+// class padded with -1 entries to a multiple of 16.
+std::vector<int> class_rowmap(int p)
+{
+    std::vector<int> r;
+    for (int cl = 0; cl < 8; ++cl) {
+        for (int n = 0; n <= p; ++n)
+            for (int m = 0; m <= n; ++m) {
+                if (coef_class(n, m, 0) == cl) r.push_back(ire(n, m));
+                if (m > 0 && coef_class(n, m, 1) == cl) r.push_back(iim(n, m));
+            }
+        while (r.size() % 16) r.push_back(-1);
+    }
+    return r;
+}
+
 template <typename T>
 lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
 {
@@ -326,6 +342,18 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     }
     UP(oct_codes, P.oct_codes);
     UP(swz_index, P.swz_index);
+    UP(orb_codes, P.orb_codes);
+    UP(orb_index, P.orb_index);
+    UP(orb_rows, class_rowmap(P.p));
+    {
+        std::vector<int> kc(A.KP, 0);
+        for (int n = 0; n <= P.p; ++n)
+            for (int m = 0; m <= n; ++m) {
+                kc[ire(n, m)] = coef_class(n, m, 0);
+                if (m > 0) kc[iim(n, m)] = coef_class(n, m, 1);
+            }
+        UP(orb_kcls, kc);
+    }
     {
         // solid-harmonic recurrence tables (see lpb_math.h)
         std::vector<T> amm(P.p + 1), al((P.p + 1) * (P.p + 2) / 2, T(0)), be((P.p + 1) * (P.p + 2) / 2, T(0));
@@ -545,8 +573,22 @@ lpb_status generate_operators(lpb_ctx* c)
     g.d_swz_ops = dswz;
     g.d_swz64 = nullptr;
     g.d_swz32 = nullptr;
+    g.n_orb = 0;
+    g.NRB = class_row_blocks(P.p);
+    g.d_orb_ops = nullptr;
+    g.d_rowmap = nullptr;
+    g.d_orb32 = nullptr;
     if (c->opt.precision == LPB_MIXED) {
         if ((s = dalloc<float>(c, c->op_bufs, (size_t)g.n_swz * g.KP * g.KP, &g.d_swz32)) != LPB_OK) return s;
+        if (P.p >= kOrbitMinP && P.p <= kOrbitMaxP && !P.orb_ops.empty()) {
+            int *dob, *drm;
+            g.n_orb = (int)P.orb_ops.size();
+            if ((s = upload(c, c->op_bufs, P.orb_ops, &dob)) != LPB_OK) return s;
+            if ((s = upload(c, c->op_bufs, class_rowmap(P.p), &drm)) != LPB_OK) return s;
+            g.d_orb_ops = dob;
+            g.d_rowmap = drm;
+            if ((s = dalloc<float>(c, c->op_bufs, (size_t)g.n_orb * g.NRB * 16 * g.KP, &g.d_orb32)) != LPB_OK) return s;
+        }
     } else {
         if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_swz * g.KP * g.KP, &g.d_swz64)) != LPB_OK) return s;
     }
@@ -571,7 +613,9 @@ lpb_status generate_operators(lpb_ctx* c)
         }
     if (c->opt.precision == LPB_MIXED) {
         c->a32.pool_swz = g.d_swz32;
-        c->stats.operator_bytes = (int64_t)g.n_swz * g.KP * g.KP * (int64_t)sizeof(float);
+        c->a32.pool_orb = g.d_orb32;
+        c->stats.operator_bytes = ((int64_t)g.n_swz * g.KP * g.KP + (int64_t)g.n_orb * g.NRB * 16 * g.KP) *
+                                  (int64_t)sizeof(float);
     } else {
         c->a64.pool_swz = g.d_swz64;
         c->stats.operator_bytes = (int64_t)g.n_swz * g.KP * g.KP * (int64_t)sizeof(double);

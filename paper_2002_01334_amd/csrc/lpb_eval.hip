@@ -942,6 +942,210 @@ __global__ void __launch_bounds__(RBW == 1 ? 64 * KB : 256) k_m2l_tile_kb(EvalAr
     }
 }
 
+// Tiled M2L by reflection orbits (FP32, p >= kOrbitMinP).  The 189 V-list
+// offsets of a child octant fall into 56 orbits {sigma d} of the canonical
+// offset d = (|dx|,|dy|,|dz|) under the reflections sigma of the axes, and
+// A_{sigma d} = D_sigma A_d D_sigma with D_sigma = diag(chi_sigma(e_k)), e_k the
+// sign class of coefficient k and chi_sigma(e) = (-1)^|sigma & e|.  For the
+// result rows of class c therefore
+//   sum_sigma (D_sigma A_d D_sigma x_sigma)_c = A_d[c, :] B^(c),
+//   B^(c)_k = sum_sigma chi_sigma(c) chi_sigma(e_k) x_sigma,k = W_{c ^ e_k, k},
+// W the Walsh-Hadamard transform over sigma of the member sources: one
+// product per orbit instead of one per member.  The operands hold the result
+// rows in class order (orb_rows), so every 16-row block has one class and
+// reads its own B^(c).
+// The work runs in (orbit, 16-coefficient slab) steps through a double
+// buffer in LDS.  Four producer waves gather the member sources three steps
+// ahead, transform them and write W_g to class slab g ^ e_k of the next
+// step's buffer; 4 CS consumer waves multiply the current buffer on the
+// matrix cores (wave: the 16 targets of column block w & 3 and the row blocks
+// of group w >> 2), their operand fragments loaded DA steps ahead.  Each
+// orbit's products go to the result with Kahan compensation.
+template <int P, int CS, int DA>
+__global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
+{
+    typedef Vec4<float>::type V4;
+    typedef int I4 __attribute__((ext_vector_type(4)));
+    constexpr int K = (P + 1) * (P + 1), KB = (K + 15) / 16, KP = 16 * KB;
+    constexpr int NRB = class_row_blocks(P), RBW = (NRB + CS - 1) / CS;
+    constexpr int OPSZ = NRB * KB * 256;     // floats of one operator
+    constexpr int BUF = 8 * 16 * 64 * 4;     // bytes of one staging buffer: [class][k][target]
+    constexpr int NIT = kOrbits * KB;        // steps (even: kOrbits is)
+    extern __shared__ unsigned char smem_raw[];
+    __shared__ int s_le[64];
+    __shared__ int s_aoff[kOrbits];
+    const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched & 1)];
+    const TileFL fl = A.tfl[tile.fl];
+    const int nside = fl.nside;
+    const int tid = threadIdx.x, l = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
+    const int* orb = A.orb_codes + tile.octant * (kOrbits * kOrbitSlots);
+    auto tcoord = [&](int j, int& tx, int& ty, int& tz) {
+        tx = 2 * (tile.px0 + (j >> 4)) + ox;
+        ty = 2 * (tile.py0 + ((j >> 2) & 3)) + oy;
+        tz = 2 * (tile.pz0 + (j & 3)) + oz;
+    };
+    if (tid < 64) {
+        int tx, ty, tz;
+        tcoord(tid, tx, ty, tz);
+        s_le[tid] = (tx < nside && ty < nside && tz < nside)
+                        ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
+    } else if (tid < 64 + kOrbits) {
+        const int q = tid - 64;
+        const int op = A.optab[fl.optab_off + orb[q * kOrbitSlots + 8]] & ((1 << kReflShift) - 1);
+        s_aoff[q] = A.orb_index[op];
+    }
+    __syncthreads();
+    // position of target j in row k of a class slab: the producers' writes
+    // (lanes over 16 targets and 4 k) and the consumers' reads (lanes over 16
+    // targets and 4 other k) both fall on distinct banks
+    auto swz = [](int k) { return 16 * ((k & 3) ^ ((k >> 2) & 3)); };
+    if (w < 4 * CS) {
+        // ---- consumer ----
+        const int cb = w & 3, rh = w >> 2, g = l >> 4, jj = l & 15;
+        int boff[4];
+#pragma unroll
+        for (int ss = 0; ss < 4; ++ss) boff[ss] = (4 * ss + g) * 64 + ((16 * cb + jj) ^ swz(4 * ss + g));
+        int cls[RBW];
+        bool live[RBW];
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            live[i] = rh * RBW + i < NRB;
+            cls[i] = class_of_row_block(P, min(rh * RBW + i, NRB - 1));
+        }
+        V4 acc[RBW], tot[RBW], cmp[RBW], ra[DA][RBW];
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) acc[i] = tot[i] = cmp[i] = V4{0, 0, 0, 0};
+        auto loadA = [&](int t, V4 (&dst)[RBW]) {
+            const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ;
+            const int s = t % KB;
+#pragma unroll
+            for (int i = 0; i < RBW; ++i) {
+                const int rbg = min(rh * RBW + i, NRB - 1);
+                dst[i] = *reinterpret_cast<const V4*>(Ao + (((size_t)rbg * KB + s) * 64 + l) * 4);
+            }
+        };
+#pragma unroll
+        for (int d = 0; d < DA; ++d) loadA(d, ra[d]);
+        __syncthreads();
+        auto cstep = [&](int it, int par, V4 (&rr)[RBW]) {
+            const float* Bb = reinterpret_cast<const float*>(smem_raw + par * BUF);
+#pragma unroll
+            for (int i = 0; i < RBW; ++i) {
+                if (!live[i]) continue;
+                const float* Bc = Bb + cls[i] * 1024;
+#pragma unroll
+                for (int ss = 0; ss < 4; ++ss) acc[i] = mfma16(rr[i][ss], Bc[boff[ss]], acc[i]);
+            }
+            if (it + DA < NIT) loadA(it + DA, rr);
+            if (it % KB == KB - 1) {
+#pragma unroll
+                for (int i = 0; i < RBW; ++i) {
+                    const V4 y = acc[i] - cmp[i];
+                    const V4 t = tot[i] + y;
+                    cmp[i] = (t - tot[i]) - y;
+                    tot[i] = t;
+                    acc[i] = V4{0, 0, 0, 0};
+                }
+            }
+            __syncthreads();
+        };
+        for (int it = 0; it < NIT; it += 2) {
+            cstep(it, 0, ra[0]);
+            cstep(it + 1, 1, ra[DA - 1]);
+        }
+        const int j = 16 * cb + jj, le = s_le[j];
+        if (le < 0) return;
+#pragma unroll
+        for (int i = 0; i < RBW; ++i) {
+            if (!live[i]) continue;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int nat = A.orb_rows[16 * (rh * RBW + i) + 4 * g + r];
+                if (nat >= 0) A.le[(size_t)le * KP + nat] += tot[i][r] - cmp[i][r];
+            }
+        }
+    } else {
+        // ---- producer: item = target gj, slab coefficients 4 gq .. 4 gq + 3 ----
+        const int pt = tid - 256 * CS, gj = pt >> 2, gq = pt & 3;
+        int gtx, gty, gtz;
+        tcoord(gj, gtx, gty, gtz);
+        const bool gvalid = s_le[gj] >= 0;
+        int mr[8], mrn[8], pm = 0, pmn = 0;
+        auto resolve = [&](int q, int (&m)[8], int& pmask) {
+            pmask = 0;
+#pragma unroll
+            for (int sg = 0; sg < 8; ++sg) {
+                const int code = orb[q * kOrbitSlots + sg];
+                m[sg] = A.n_me;   // a missing source reads the zero row
+                if (code >= 0) {
+                    pmask |= 1 << sg;
+                    const int sx = gtx + code / 49 - 3, sy = gty + (code / 7) % 7 - 3, sz = gtz + code % 7 - 3;
+                    if (gvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside) {
+                        const int me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
+                        if (me >= 0) m[sg] = me;
+                    }
+                }
+            }
+        };
+        V4 xr[2][8];
+        I4 ekr[2];
+        // gather step t (members of its orbit) into register slot xs
+        auto load = [&](int t, V4 (&xs)[8], I4& ek) {
+            const int s = t % KB;
+            if (s == 0 && t > 0) {
+#pragma unroll
+                for (int sg = 0; sg < 8; ++sg) mr[sg] = mrn[sg];
+                pm = pmn;
+                if (t / KB + 1 < kOrbits) resolve(t / KB + 1, mrn, pmn);
+            }
+#pragma unroll
+            for (int sg = 0; sg < 8; ++sg) {
+                if ((pm >> sg) & 1) xs[sg] = *reinterpret_cast<const V4*>(A.me + (size_t)mr[sg] * KP + 16 * s + 4 * gq);
+                else xs[sg] = V4{0, 0, 0, 0};
+            }
+            ek = *reinterpret_cast<const I4*>(A.orb_kcls + 16 * s + 4 * gq);
+        };
+        auto stage = [&](V4 (&xs)[8], const I4& ek, int buf) {
+#pragma unroll
+            for (int b = 1; b < 8; b <<= 1)
+#pragma unroll
+                for (int sg = 0; sg < 8; ++sg)
+                    if (!(sg & b)) {
+                        const V4 u = xs[sg], v = xs[sg | b];
+                        xs[sg] = u + v;
+                        xs[sg | b] = u - v;
+                    }
+            unsigned char* base = smem_raw + buf * BUF;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int kl = 4 * gq + e;
+                const int a0 = (ek[e] << 12) + kl * 256 + ((gj ^ swz(kl)) << 2);
+#pragma unroll
+                for (int cg = 0; cg < 8; ++cg) *reinterpret_cast<float*>(base + (a0 ^ (cg << 12))) = xs[cg][e];
+            }
+        };
+        resolve(0, mr, pm);
+        if (kOrbits > 1) resolve(1, mrn, pmn);
+        load(0, xr[0], ekr[0]);
+        stage(xr[0], ekr[0], 0);
+        load(1, xr[1], ekr[1]);
+        load(2, xr[0], ekr[0]);
+        __syncthreads();
+        // step it: stage step it + 1 into the other buffer, gather step it + 3
+        auto pstep = [&](int it, V4 (&xs)[8], I4& ek, int nbuf) {
+            if (it + 1 < NIT) stage(xs, ek, nbuf);
+            if (it + 3 < NIT) load(it + 3, xs, ek);
+            __syncthreads();
+        };
+        for (int it = 0; it < NIT; it += 2) {
+            pstep(it, xr[1], ekr[1], 1);
+            pstep(it + 1, xr[0], ekr[0], 0);
+        }
+    }
+}
+
 template <typename T>
 static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
 {
@@ -950,6 +1154,22 @@ static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
     dim3 g(A.n_tiles), b(256);
     // variant bit of the schedule: KB waves of one row block each
     const bool wide = (A.tile_sched >> 1) & 1;
+    if constexpr (sizeof(T) == 4) {
+        if (A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP) {
+            const size_t smo = 2 * 8 * 16 * 64 * sizeof(float);
+#define LPB_ORB(PP, CS, DA)                                                                                        \
+    case PP:                                                                                                       \
+        hipLaunchKernelGGL((k_m2l_orbit<PP, CS, DA>), g, dim3(256 * CS + 256), smo, st, A);                        \
+        return;
+            switch (A.p) {
+                LPB_ORB(5, 1, 2) LPB_ORB(6, 1, 2) LPB_ORB(7, 1, 2) LPB_ORB(8, 1, 2) LPB_ORB(9, 1, 2)
+                LPB_ORB(10, 1, 2) LPB_ORB(11, 1, 2) LPB_ORB(12, 2, 1) LPB_ORB(13, 2, 1) LPB_ORB(14, 2, 1)
+                LPB_ORB(15, 2, 1)
+            default: break;
+            }
+#undef LPB_ORB
+        }
+    }
 #define LPB_TKB(N)                                                                                  \
     case N:                                                                                         \
         if (wide) hipLaunchKernelGGL((k_m2l_tile_kb<T, N, 1>), g, dim3(64 * N), sm, st, A);         \

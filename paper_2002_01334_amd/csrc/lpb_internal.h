@@ -29,6 +29,14 @@ constexpr int kReflShift = 28;
 // T(phi) = diag(e^{-i m phi}) T(0) diag(e^{i mu phi}) and one operator per
 // (level, rho, z_t, z_s) serves every direction.
 constexpr int kXfRotate = 8;
+// The 189 offsets of a child octant form 56 orbits under those reflections
+// (canonical offset (|dx|,|dy|,|dz|)); an orbit has at most 8 members, one per
+// reflection code.  orb_codes holds per octant and orbit the member offset
+// codes by reflection code (-1 where absent) and the canonical code.
+constexpr int kOrbits = 56;
+constexpr int kOrbitSlots = 9;
+constexpr int kOrbitMinP = 5;   // below, class padding outweighs the saving
+constexpr int kOrbitMaxP = 15;
 
 enum OpType { OP_M2M = 0, OP_L2L = 1, OP_M2L_FREE = 2, OP_M2L_REACT = 3 };
 
@@ -164,6 +172,9 @@ struct Plan {
     std::vector<Tile> tiles;
     std::vector<int> grid_me, grid_le, optab;
     std::vector<int> oct_codes;    // 8 x 189 offset codes ((dx+3)*7+(dy+3))*7+(dz+3)
+    std::vector<int> orb_codes;    // 8 x kOrbits x kOrbitSlots (see kOrbits)
+    std::vector<int> orb_ops;      // canonical operators of the tiled levels
+    std::vector<int> orb_index;    // op -> position in orb_ops, -1 if none
     std::vector<int> swz_ops;      // operators stored in the MFMA operand layout (all of them)
     std::vector<int> swz_index;    // op -> position in swz_ops
 };

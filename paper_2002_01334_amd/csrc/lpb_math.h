@@ -83,6 +83,40 @@ LPB_HD constexpr int iim(int n, int m) { return n * n + 2 * m; }
 // packed (n, m >= 0) index
 LPB_HD constexpr int ipk(int n, int m) { return n * (n + 1) / 2 + m; }
 
+// Sign class of a real-form coefficient under the reflections of the axes:
+// bit 0 set if it changes sign under x -> -x (Re: m odd, Im: m even), bit 1
+// under y -> -y (the Im parts), bit 2 under z -> -z (n + m odd).
+LPB_HD constexpr int coef_class(int n, int m, int im)
+{
+    return (im ? 1 - (m & 1) : (m & 1)) | (im ? 2 : 0) | (((n + m) & 1) << 2);
+}
+LPB_HD constexpr int class_size(int p, int c)
+{
+    int s = 0;
+    for (int n = 0; n <= p; ++n)
+        for (int m = 0; m <= n; ++m) {
+            s += coef_class(n, m, 0) == c;
+            if (m > 0) s += coef_class(n, m, 1) == c;
+        }
+    return s;
+}
+// Rows ordered by sign class, each class padded to a multiple of 16: the
+// number of 16-row blocks, and the class of block rb.
+LPB_HD constexpr int class_row_blocks(int p)
+{
+    int b = 0;
+    for (int c = 0; c < 8; ++c) b += (class_size(p, c) + 15) / 16;
+    return b;
+}
+LPB_HD constexpr int class_of_row_block(int p, int rb)
+{
+    for (int c = 0; c < 8; ++c) {
+        rb -= (class_size(p, c) + 15) / 16;
+        if (rb < 0) return c;
+    }
+    return 7;
+}
+
 // Regular solid harmonics R_n^m(v) = |v|^n Y_n^m(v^), 0 <= m <= n <= p,
 // written to re/im at packed index ipk(n,m), from
 //   R_m^m = A_m (x + i y)^m,  A_m = A_{m-1} sqrt((2m+1)/(2m)), A_0 = 1/sqrt(4 pi),

@@ -31,6 +31,13 @@ struct OpgenInputs {
     const int* d_swz_ops;
     double* d_swz64;          // FP64 mode
     float* d_swz32;           // mixed mode
+    // canonical operators of the tiled levels for the orbit kernel (mixed
+    // mode): rows in sign-class order (d_rowmap: row -> coefficient, -1 pad),
+    // NRB 16-row blocks, same operand layout
+    int n_orb, NRB;
+    const int* d_orb_ops;
+    const int* d_rowmap;
+    float* d_orb32;
 };
 
 hipError_t opgen_upload_constants();

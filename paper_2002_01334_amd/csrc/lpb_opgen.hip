@@ -459,6 +459,25 @@ __global__ void k_swizzle(int K, int KP, int nsw, const int* __restrict__ ops, c
     out[idx] = (T)v;
 }
 
+// The same layout with the rows permuted (rowmap: operand row -> result
+// coefficient, -1 for a zero padding row), NRB row blocks.
+__global__ void k_swizzle_rows(int K, int KP, int NRB, int nsw, const int* __restrict__ ops,
+                               const int* __restrict__ rowmap, const double* __restrict__ pool, float* __restrict__ out)
+{
+    const int KB = KP / 16;
+    size_t per = (size_t)NRB * 16 * KP;
+    size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= per * nsw) return;
+    int o = (int)(idx / per);
+    size_t e = idx % per;
+    int ss = (int)(e & 3), lane = (int)((e >> 2) & 63);
+    size_t rest = e >> 8;
+    int s4 = (int)(rest % KB), rb = (int)(rest / KB);
+    int row = rowmap[16 * rb + (lane & 15)], k = 16 * s4 + 4 * ss + (lane >> 4);
+    double v = (row >= 0 && k < K) ? pool[(size_t)ops[o] * K * K + (size_t)k * K + row] : 0.0;
+    out[idx] = (float)v;
+}
+
 __global__ void k_to_float(size_t n, const double* __restrict__ a, float* __restrict__ b)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -546,6 +565,12 @@ hipError_t opgen_run(const OpgenInputs& in, hipStream_t st)
         else
             hipLaunchKernelGGL(k_swizzle<double>, dim3(blocks), dim3(256), 0, st, K, in.KP, in.n_swz, in.d_swz_ops,
                                in.d_pool, in.d_swz64);
+    }
+    if (in.n_orb > 0 && in.d_orb32) {
+        size_t n = (size_t)in.NRB * 16 * in.KP * in.n_orb;
+        unsigned blocks = (unsigned)((n + 255) / 256);
+        hipLaunchKernelGGL(k_swizzle_rows, dim3(blocks), dim3(256), 0, st, K, in.KP, in.NRB, in.n_orb, in.d_orb_ops,
+                           in.d_rowmap, in.d_pool, in.d_orb32);
     }
     return hipGetLastError();
 }

@@ -521,6 +521,27 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         std::stable_sort(cl.begin(), cl.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
         for (auto& c : cl) P.oct_codes.push_back(c.second);
     }
+    P.orb_codes.clear();
+    for (int o = 0; o < 8; ++o) {
+        const int oo[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
+        for (int a = 0; a <= 3; ++a)
+            for (int b = 0; b <= 3; ++b)
+                for (int c = 0; c <= 3; ++c) {
+                    if (a <= 1 && b <= 1 && c <= 1) continue;
+                    const int ad[3] = {a, b, c};
+                    for (int sg = 0; sg < 8; ++sg) {
+                        int d[3], ok = 1;
+                        for (int ax = 0; ax < 3; ++ax) {
+                            const bool neg = (sg >> ax) & 1;
+                            if (neg && ad[ax] == 0) ok = 0;   // the reflection leaves the offset as it is
+                            d[ax] = neg ? -ad[ax] : ad[ax];
+                            if (d[ax] < -2 - oo[ax] || d[ax] > 3 - oo[ax]) ok = 0;
+                        }
+                        P.orb_codes.push_back(ok ? ((d[0] + 3) * 7 + (d[1] + 3)) * 7 + (d[2] + 3) : -1);
+                    }
+                    P.orb_codes.push_back(((a + 3) * 7 + (b + 3)) * 7 + (c + 3));
+                }
+    }
     Staging S;
 
     for (int s = 0; s < P.nsys; ++s) {
@@ -750,6 +771,17 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         }
     }
     P.bm2l_w1 = (int)P.bw_term_ptr.size() - 1;
+    // canonical operators of the tiled levels (the orbit kernel's operands)
+    P.orb_ops.clear();
+    P.orb_index.assign(P.ops.size(), -1);
+    for (const TileFL& t : P.tfl)
+        for (int q = 0; q < kOrbits; ++q) {
+            const int op = P.optab[t.optab_off + P.orb_codes[q * kOrbitSlots + 8]] & ((1 << kReflShift) - 1);
+            if (P.orb_index[op] < 0) {
+                P.orb_index[op] = (int)P.orb_ops.size();
+                P.orb_ops.push_back(op);
+            }
+        }
     // every operator is stored in the MFMA operand layout
     P.swz_ops.resize(P.ops.size());
     P.swz_index.resize(P.ops.size());
