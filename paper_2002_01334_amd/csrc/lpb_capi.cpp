@@ -342,7 +342,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     }
     UP(oct_codes, P.oct_codes);
     UP(swz_index, P.swz_index);
-    UP(orb_codes, P.orb_codes);
+    UP(orb_tab, P.orb_tab);
     UP(orb_index, P.orb_index);
     UP(orb_rows, class_rowmap(P.p));
     {

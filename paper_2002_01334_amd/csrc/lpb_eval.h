@@ -61,10 +61,10 @@ struct EvalArgs {
     // 1/it_n(lam h) per FMM and level for the source (ith_s) and target (ith_t) lambda
     const double *bes_tab, *ith_s, *ith_t;
     const int* swz_index;       // op -> position in pool_swz
-    // tiled M2L by reflection orbits (FP32, p >= kOrbitMinP): member offset
-    // codes, op -> canonical operator position in pool_orb (rows in sign-class
-    // order), and operand row -> coefficient (-1 padding)
-    const int *orb_codes, *orb_index, *orb_rows;
+    // tiled M2L by reflection orbits (FP32, p >= kOrbitMinP): orbit table
+    // (see kOrbits), op -> canonical operator position in pool_orb (rows in
+    // sign-class order), and operand row -> coefficient (-1 padding)
+    const int *orb_tab, *orb_index, *orb_rows;
     const int* orb_kcls;        // sign class of each coefficient (KP entries, padding 0)
     const T* pool_orb;
     // block -> work schedules of the matrix-core kernels (see sched_index)

@@ -5,6 +5,8 @@
 // ratios are always formed in double.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lpb_eval.h"
 
 namespace lpb {
@@ -951,16 +953,19 @@ __global__ void __launch_bounds__(RBW == 1 ? 64 * KB : 256) k_m2l_tile_kb(EvalAr
 //   sum_sigma (D_sigma A_d D_sigma x_sigma)_c = A_d[c, :] B^(c),
 //   B^(c)_k = sum_sigma chi_sigma(c) chi_sigma(e_k) x_sigma,k = W_{c ^ e_k, k},
 // W the Walsh-Hadamard transform over sigma of the member sources: one
-// product per orbit instead of one per member.  The operands hold the result
-// rows in class order (orb_rows), so every 16-row block has one class and
-// reads its own B^(c).
+// product per orbit instead of one per member.  With the members
+// deposit(j, both) | minus (see kOrbits), W_g = (-1)^|g & minus| Wc_j(g), Wc
+// the transform over the nb both-axes only (nb 2^nb additions per value).
+// The operands hold the result rows in class order (orb_rows), so every
+// 16-row block has one class and reads its own B^(c).
 // The work runs in (orbit, 16-coefficient slab) steps through a double
 // buffer in LDS.  Four producer waves gather the member sources three steps
-// ahead, transform them and write W_g to class slab g ^ e_k of the next
-// step's buffer; 4 CS consumer waves multiply the current buffer on the
-// matrix cores (wave: the 16 targets of column block w & 3 and the row blocks
-// of group w >> 2), their operand fragments loaded DA steps ahead.  Each
-// orbit's products go to the result with Kahan compensation.
+// ahead (rows from a local grid of the tile's source boxes), transform them
+// and write W_g to class slab g ^ e_k of the next step's buffer; 4 CS
+// consumer waves multiply the current buffer on the matrix cores (wave: the
+// 16 targets of column block w & 3 and the row blocks of group w >> 2), their
+// operand fragments loaded DA steps ahead.  Each orbit's products go to the
+// result with Kahan compensation.
 template <int P, int CS, int DA>
 __global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
 {
@@ -971,30 +976,39 @@ __global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
     constexpr int OPSZ = NRB * KB * 256;     // floats of one operator
     constexpr int BUF = 8 * 16 * 64 * 4;     // bytes of one staging buffer: [class][k][target]
     constexpr int NIT = kOrbits * KB;        // steps (even: kOrbits is)
+    constexpr int NG = kOrbGrid * kOrbGrid * kOrbGrid;
     extern __shared__ unsigned char smem_raw[];
-    __shared__ int s_le[64];
-    __shared__ int s_aoff[kOrbits];
+    int* s_grid = reinterpret_cast<int*>(smem_raw + 2 * BUF);   // ME row of each local source box
+    int* s_tab = s_grid + NG;                                    // the octant's orbit table
+    int* s_le = s_tab + kOrbits * kOrbTab;                       // LE row of each target (-1 none)
+    int* s_aoff = s_le + 64;                                     // operator of each orbit
     const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched & 1)];
     const TileFL fl = A.tfl[tile.fl];
     const int nside = fl.nside;
     const int tid = threadIdx.x, l = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
-    const int* orb = A.orb_codes + tile.octant * (kOrbits * kOrbitSlots);
-    auto tcoord = [&](int j, int& tx, int& ty, int& tz) {
-        tx = 2 * (tile.px0 + (j >> 4)) + ox;
-        ty = 2 * (tile.py0 + ((j >> 2) & 3)) + oy;
-        tz = 2 * (tile.pz0 + (j & 3)) + oz;
-    };
-    if (tid < 64) {
-        int tx, ty, tz;
-        tcoord(tid, tx, ty, tz);
-        s_le[tid] = (tx < nside && ty < nside && tz < nside)
-                        ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
-    } else if (tid < 64 + kOrbits) {
-        const int q = tid - 64;
-        const int op = A.optab[fl.optab_off + orb[q * kOrbitSlots + 8]] & ((1 << kReflShift) - 1);
-        s_aoff[q] = A.orb_index[op];
+    const int* tab = A.orb_tab + tile.octant * (kOrbits * kOrbTab);
+    {
+        const int gx0 = 2 * tile.px0 + ox - 3, gy0 = 2 * tile.py0 + oy - 3, gz0 = 2 * tile.pz0 + oz - 3;
+        for (int i = tid; i < NG; i += blockDim.x) {
+            const int sx = gx0 + i / (kOrbGrid * kOrbGrid), sy = gy0 + (i / kOrbGrid) % kOrbGrid, sz = gz0 + i % kOrbGrid;
+            int me = -1;
+            if (sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
+                me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
+            s_grid[i] = me < 0 ? A.n_me : me;   // a missing source reads the zero row
+        }
+        for (int i = tid; i < kOrbits * kOrbTab; i += blockDim.x) s_tab[i] = tab[i];
+        if (tid < 64) {
+            const int tx = 2 * (tile.px0 + (tid >> 4)) + ox, ty = 2 * (tile.py0 + ((tid >> 2) & 3)) + oy,
+                      tz = 2 * (tile.pz0 + (tid & 3)) + oz;
+            s_le[tid] = (tx < nside && ty < nside && tz < nside)
+                            ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
+        } else if (tid < 64 + kOrbits) {
+            const int q = tid - 64;
+            const int op = A.optab[fl.optab_off + tab[q * kOrbTab + 17]] & ((1 << kReflShift) - 1);
+            s_aoff[q] = A.orb_index[op];
+        }
     }
     __syncthreads();
     // position of target j in row k of a class slab: the producers' writes
@@ -1069,73 +1083,101 @@ __global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
     } else {
         // ---- producer: item = target gj, slab coefficients 4 gq .. 4 gq + 3 ----
         const int pt = tid - 256 * CS, gj = pt >> 2, gq = pt & 3;
-        int gtx, gty, gtz;
-        tcoord(gj, gtx, gty, gtz);
-        const bool gvalid = s_le[gj] >= 0;
-        int mr[8], mrn[8], pm = 0, pmn = 0;
-        auto resolve = [&](int q, int (&m)[8], int& pmask) {
-            pmask = 0;
+        const int tli = ((2 * (gj >> 4)) * kOrbGrid + 2 * ((gj >> 2) & 3)) * kOrbGrid + 2 * (gj & 3);
+        const char* mebase = reinterpret_cast<const char*>(A.me);
+        // orbit of the steps being gathered: member count and row byte offsets
+        unsigned off[8];
+        int nmL = 1;
+        auto lorbit = [&](int q) {
+            const int* row = s_tab + q * kOrbTab;
+            nmL = 1 << (__builtin_amdgcn_readfirstlane(row[0]) & 15);
 #pragma unroll
-            for (int sg = 0; sg < 8; ++sg) {
-                const int code = orb[q * kOrbitSlots + sg];
-                m[sg] = A.n_me;   // a missing source reads the zero row
-                if (code >= 0) {
-                    pmask |= 1 << sg;
-                    const int sx = gtx + code / 49 - 3, sy = gty + (code / 7) % 7 - 3, sz = gtz + code % 7 - 3;
-                    if (gvalid && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside) {
-                        const int me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
-                        if (me >= 0) m[sg] = me;
-                    }
-                }
+            for (int j = 0; j < 8; ++j)
+                if (j < nmL) off[j] = (unsigned)s_grid[tli + row[1 + j]] * (unsigned)(KP * 4) + 16u * gq;
+        };
+        // orbit of the step being staged: transform size, output classes and signs
+        int codeS = 0, wa[8], ws[8];
+        auto sorbit = [&](int q) {
+            const int* row = s_tab + q * kOrbTab;
+            const int h = __builtin_amdgcn_readfirstlane(row[0]);
+            codeS = (h & 15) + 4 * (h >> 4);
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int e = __builtin_amdgcn_readfirstlane(row[9 + i]);
+                wa[i] = e & 0x7000;
+                ws[i] = e & (int)0x80000000;
             }
         };
         V4 xr[2][8];
         I4 ekr[2];
-        // gather step t (members of its orbit) into register slot xs
         auto load = [&](int t, V4 (&xs)[8], I4& ek) {
             const int s = t % KB;
-            if (s == 0 && t > 0) {
+            if (s == 0) lorbit(t / KB);
+            const char* b = mebase + 64 * s;
 #pragma unroll
-                for (int sg = 0; sg < 8; ++sg) mr[sg] = mrn[sg];
-                pm = pmn;
-                if (t / KB + 1 < kOrbits) resolve(t / KB + 1, mrn, pmn);
-            }
-#pragma unroll
-            for (int sg = 0; sg < 8; ++sg) {
-                if ((pm >> sg) & 1) xs[sg] = *reinterpret_cast<const V4*>(A.me + (size_t)mr[sg] * KP + 16 * s + 4 * gq);
-                else xs[sg] = V4{0, 0, 0, 0};
-            }
+            for (int j = 0; j < 8; ++j)
+                if (j < nmL) xs[j] = *reinterpret_cast<const V4*>(b + off[j]);
             ek = *reinterpret_cast<const I4*>(A.orb_kcls + 16 * s + 4 * gq);
         };
-        auto stage = [&](V4 (&xs)[8], const I4& ek, int buf) {
+        // LDS byte address of the dynamic buffer (the kernel has no static LDS,
+        // so it is 0, a multiple of 32 KiB: class bits 12..14 can be XORed into
+        // absolute addresses)
+        typedef __attribute__((address_space(3))) float lds_float;
+        typedef __attribute__((address_space(3))) unsigned char lds_byte;
+        const unsigned lbase = (unsigned)(size_t)(lds_byte*)smem_raw;
+        auto stage_nb = [&](auto nbc, auto negc, const V4 (&xs)[8], const unsigned (&a0)[4]) {
+            constexpr int NB = decltype(nbc)::value;
+            constexpr bool NEG = decltype(negc)::value;
+            constexpr int M = 1 << NB;
+            V4 y[M];
 #pragma unroll
-            for (int b = 1; b < 8; b <<= 1)
+            for (int j = 0; j < M; ++j) y[j] = xs[j];
 #pragma unroll
-                for (int sg = 0; sg < 8; ++sg)
-                    if (!(sg & b)) {
-                        const V4 u = xs[sg], v = xs[sg | b];
-                        xs[sg] = u + v;
-                        xs[sg | b] = u - v;
+            for (int b = 0; b < NB; ++b)
+#pragma unroll
+                for (int j = 0; j < M; ++j)
+                    if (!((j >> b) & 1)) {
+                        const V4 u = y[j], v = y[j | (1 << b)];
+                        y[j] = u + v;
+                        y[j | (1 << b)] = u - v;
                     }
-            unsigned char* base = smem_raw + buf * BUF;
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int i = 0; i < 8; ++i) {
+                    float v = y[i & (M - 1)][e];
+                    if (NEG) v = __int_as_float(__float_as_int(v) ^ ws[i]);
+                    *(lds_float*)(size_t)(a0[e] ^ (unsigned)wa[i]) = v;
+                }
+        };
+        auto stage = [&](int t, const V4 (&xs)[8], const I4& ek, int buf) {
+            if (t % KB == 0) sorbit(t / KB);
+            unsigned a0[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 const int kl = 4 * gq + e;
-                const int a0 = (ek[e] << 12) + kl * 256 + ((gj ^ swz(kl)) << 2);
-#pragma unroll
-                for (int cg = 0; cg < 8; ++cg) *reinterpret_cast<float*>(base + (a0 ^ (cg << 12))) = xs[cg][e];
+                a0[e] = lbase + (unsigned)(buf * BUF + (ek[e] << 12) + kl * 256 + ((gj ^ swz(kl)) << 2));
+            }
+            typedef std::integral_constant<bool, false> F;
+            typedef std::integral_constant<bool, true> T;
+            switch (codeS) {
+            case 0: stage_nb(std::integral_constant<int, 0>{}, F{}, xs, a0); break;
+            case 1: stage_nb(std::integral_constant<int, 1>{}, F{}, xs, a0); break;
+            case 2: stage_nb(std::integral_constant<int, 2>{}, F{}, xs, a0); break;
+            case 3: stage_nb(std::integral_constant<int, 3>{}, F{}, xs, a0); break;
+            case 4: stage_nb(std::integral_constant<int, 0>{}, T{}, xs, a0); break;
+            case 5: stage_nb(std::integral_constant<int, 1>{}, T{}, xs, a0); break;
+            default: stage_nb(std::integral_constant<int, 2>{}, T{}, xs, a0); break;
             }
         };
-        resolve(0, mr, pm);
-        if (kOrbits > 1) resolve(1, mrn, pmn);
         load(0, xr[0], ekr[0]);
-        stage(xr[0], ekr[0], 0);
+        stage(0, xr[0], ekr[0], 0);
         load(1, xr[1], ekr[1]);
         load(2, xr[0], ekr[0]);
         __syncthreads();
         // step it: stage step it + 1 into the other buffer, gather step it + 3
         auto pstep = [&](int it, V4 (&xs)[8], I4& ek, int nbuf) {
-            if (it + 1 < NIT) stage(xs, ek, nbuf);
+            if (it + 1 < NIT) stage(it + 1, xs, ek, nbuf);
             if (it + 3 < NIT) load(it + 3, xs, ek);
             __syncthreads();
         };
@@ -1155,8 +1197,11 @@ static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
     // variant bit of the schedule: KB waves of one row block each
     const bool wide = (A.tile_sched >> 1) & 1;
     if constexpr (sizeof(T) == 4) {
-        if (A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP) {
-            const size_t smo = 2 * 8 * 16 * 64 * sizeof(float);
+        // (row byte offsets of the expansions are 32-bit in the orbit kernel)
+        if (A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP &&
+            (size_t)(A.n_me + 1) * A.KP * sizeof(float) < ((size_t)1 << 32)) {
+            const size_t smo = 2 * 8 * 16 * 64 * sizeof(float) +
+                               sizeof(int) * (kOrbGrid * kOrbGrid * kOrbGrid + kOrbits * kOrbTab + 64 + kOrbits);
 #define LPB_ORB(PP, CS, DA)                                                                                        \
     case PP:                                                                                                       \
         hipLaunchKernelGGL((k_m2l_orbit<PP, CS, DA>), g, dim3(256 * CS + 256), smo, st, A);                        \

@@ -30,11 +30,21 @@ constexpr int kReflShift = 28;
 // (level, rho, z_t, z_s) serves every direction.
 constexpr int kXfRotate = 8;
 // The 189 offsets of a child octant form 56 orbits under those reflections
-// (canonical offset (|dx|,|dy|,|dz|)); an orbit has at most 8 members, one per
-// reflection code.  orb_codes holds per octant and orbit the member offset
-// codes by reflection code (-1 where absent) and the canonical code.
+// (canonical offset (|dx|,|dy|,|dz|)).  Per axis an orbit has both signs
+// ("both" axes, 1 or 2 away) or one (0, or 3 on the side the octant allows).
+// orb_tab holds per octant and orbit kOrbTab entries:
+//   [0]      nb | neg << 4: nb the number of both-axes, neg set if a one-sign
+//            axis has the negative sign;
+//   [1..8]   the 2^nb members in compact order j (member reflection code
+//            deposit(j, both) | minus), as offsets in the 13^3 local source
+//            grid of a tile, ((dx+3) 13 + dy+3) 13 + dz+3;
+//   [9..16]  for the transform outputs (j + (t << nb)): class g << 12 with the
+//            sign (-1)^|g & minus| in bit 31, g = deposit(j, both) |
+//            deposit(t, one-sign axes);
+//   [17]     the canonical offset code ((a+3) 7 + b+3) 7 + c+3.
 constexpr int kOrbits = 56;
-constexpr int kOrbitSlots = 9;
+constexpr int kOrbTab = 18;
+constexpr int kOrbGrid = 13;    // local source grid of a tile (4 parents x 2 + 6 halo per axis)
 constexpr int kOrbitMinP = 5;   // below, class padding outweighs the saving
 constexpr int kOrbitMaxP = 15;
 
@@ -172,7 +182,7 @@ struct Plan {
     std::vector<Tile> tiles;
     std::vector<int> grid_me, grid_le, optab;
     std::vector<int> oct_codes;    // 8 x 189 offset codes ((dx+3)*7+(dy+3))*7+(dz+3)
-    std::vector<int> orb_codes;    // 8 x kOrbits x kOrbitSlots (see kOrbits)
+    std::vector<int> orb_tab;      // 8 x kOrbits x kOrbTab (see kOrbits)
     std::vector<int> orb_ops;      // canonical operators of the tiled levels
     std::vector<int> orb_index;    // op -> position in orb_ops, -1 if none
     std::vector<int> swz_ops;      // operators stored in the MFMA operand layout (all of them)

@@ -521,7 +521,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         std::stable_sort(cl.begin(), cl.end(), [](const std::pair<int, int>& a, const std::pair<int, int>& b) { return a.first < b.first; });
         for (auto& c : cl) P.oct_codes.push_back(c.second);
     }
-    P.orb_codes.clear();
+    P.orb_tab.clear();
     for (int o = 0; o < 8; ++o) {
         const int oo[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
         for (int a = 0; a <= 3; ++a)
@@ -529,17 +529,43 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                 for (int c = 0; c <= 3; ++c) {
                     if (a <= 1 && b <= 1 && c <= 1) continue;
                     const int ad[3] = {a, b, c};
-                    for (int sg = 0; sg < 8; ++sg) {
-                        int d[3], ok = 1;
-                        for (int ax = 0; ax < 3; ++ax) {
-                            const bool neg = (sg >> ax) & 1;
-                            if (neg && ad[ax] == 0) ok = 0;   // the reflection leaves the offset as it is
-                            d[ax] = neg ? -ad[ax] : ad[ax];
-                            if (d[ax] < -2 - oo[ax] || d[ax] > 3 - oo[ax]) ok = 0;
-                        }
-                        P.orb_codes.push_back(ok ? ((d[0] + 3) * 7 + (d[1] + 3)) * 7 + (d[2] + 3) : -1);
+                    int both = 0, minus = 0;
+                    for (int ax = 0; ax < 3; ++ax) {
+                        // signs of this axis inside the octant's offset range [-2 - o, 3 - o]
+                        const bool pos = ad[ax] <= 3 - oo[ax];
+                        const bool neg = ad[ax] > 0 && -ad[ax] >= -2 - oo[ax];
+                        if (pos && neg) both |= 1 << ax;
+                        else if (neg) minus |= 1 << ax;
                     }
-                    P.orb_codes.push_back(((a + 3) * 7 + (b + 3)) * 7 + (c + 3));
+                    const int one = 7 & ~both;
+                    auto deposit = [](int v, int mask) {
+                        int r = 0;
+                        for (int bit = 0; bit < 3; ++bit)
+                            if ((mask >> bit) & 1) {
+                                if (v & 1) r |= 1 << bit;
+                                v >>= 1;
+                            }
+                        return r;
+                    };
+                    int nb = 0;
+                    for (int ax = 0; ax < 3; ++ax) nb += (both >> ax) & 1;
+                    int row[kOrbTab] = {};
+                    row[0] = nb | ((minus != 0) << 4);
+                    for (int j = 0; j < (1 << nb); ++j) {
+                        const int sg = deposit(j, both) | minus;
+                        int d[3];
+                        for (int ax = 0; ax < 3; ++ax) d[ax] = ((sg >> ax) & 1) ? -ad[ax] : ad[ax];
+                        row[1 + j] = ((d[0] + 3) * kOrbGrid + (d[1] + 3)) * kOrbGrid + (d[2] + 3);
+                    }
+                    for (int t = 0; t < (1 << (3 - nb)); ++t)
+                        for (int j = 0; j < (1 << nb); ++j) {
+                            const int g = deposit(j, both) | deposit(t, one);
+                            int par = 0;
+                            for (int bit = 0; bit < 3; ++bit) par ^= ((g & minus) >> bit) & 1;
+                            row[9 + j + (t << nb)] = (int)(((unsigned)par << 31) | ((unsigned)g << 12));
+                        }
+                    row[17] = ((a + 3) * 7 + (b + 3)) * 7 + (c + 3);
+                    P.orb_tab.insert(P.orb_tab.end(), row, row + kOrbTab);
                 }
     }
     Staging S;
@@ -776,7 +802,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.orb_index.assign(P.ops.size(), -1);
     for (const TileFL& t : P.tfl)
         for (int q = 0; q < kOrbits; ++q) {
-            const int op = P.optab[t.optab_off + P.orb_codes[q * kOrbitSlots + 8]] & ((1 << kReflShift) - 1);
+            const int op = P.optab[t.optab_off + P.orb_tab[q * kOrbTab + 17]] & ((1 << kReflShift) - 1);
             if (P.orb_index[op] < 0) {
                 P.orb_index[op] = (int)P.orb_ops.size();
                 P.orb_ops.push_back(op);
