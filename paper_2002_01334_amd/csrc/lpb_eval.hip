@@ -951,42 +951,94 @@ __global__ void __launch_bounds__(RBW == 1 ? 64 * KB : 256) k_m2l_tile_kb(EvalAr
 // sign class of coefficient k and chi_sigma(e) = (-1)^|sigma & e|.  For the
 // result rows of class c therefore
 //   sum_sigma (D_sigma A_d D_sigma x_sigma)_c = A_d[c, :] B^(c),
-//   B^(c)_k = sum_sigma chi_sigma(c) chi_sigma(e_k) x_sigma,k = W_{c ^ e_k, k},
-// W the Walsh-Hadamard transform over sigma of the member sources: one
-// product per orbit instead of one per member.  With the members
-// deposit(j, both) | minus (see kOrbits), W_g = (-1)^|g & minus| Wc_j(g), Wc
-// the transform over the nb both-axes only (nb 2^nb additions per value).
-// The operands hold the result rows in class order (orb_rows), so every
-// 16-row block has one class and reads its own B^(c).
-// The work runs in (orbit, 16-coefficient slab) steps through a double
-// buffer in LDS.  Four producer waves gather the member sources three steps
-// ahead (rows from a local grid of the tile's source boxes), transform them
-// and write W_g to class slab g ^ e_k of the next step's buffer; 4 CS
-// consumer waves multiply the current buffer on the matrix cores (wave: the
-// 16 targets of column block w & 3 and the row blocks of group w >> 2), their
-// operand fragments loaded DA steps ahead.  Each orbit's products go to the
-// result with Kahan compensation.
-template <int P, int CS, int DA>
-__global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
+//   B^(c) = sum_sigma chi_sigma(c) x'_sigma,   x'_sigma = D_sigma x_sigma:
+// one product per orbit instead of one per member.  With the members
+// sigma_j = deposit(j, both) | minus (see kOrbits),
+//   B^(c) = (-1)^|c & minus| Wc[extract(c, both)],
+//   Wc[m] = D_minus sum_j (-1)^|j & m| prod_{axes b of j} D_b x_j,
+// a Walsh-Hadamard transform over the nb both-axes whose butterflies carry
+// the per-coefficient axis signs (t v for the upper input); the class sign
+// (-1)^|c & minus| multiplies the orbit's product before it is added.  The
+// operands hold the result rows in class order (orb_rows), so every 16-row
+// block has one class.
+// Each wave owns 16 targets of the tile (a 16-column block of the product)
+// and every row block: per (orbit, 16-coefficient slab) step each lane loads
+// four consecutive coefficients of its target's member sources (the B
+// operand of four products, the operand layout arranged to match), forms the
+// transforms in registers and issues the products; loads run two steps
+// ahead.  No data is shared between waves, so the waves never wait for each
+// other.  Each orbit's products go to the result with Kahan compensation.
+template <int P, int MASK>
+__device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], const int (&ek)[4], int minus,
+                                           const Vec4<float>::type (&ra)[class_row_blocks(P)],
+                                           Vec4<float>::type (&acc)[class_row_blocks(P)])
 {
     typedef Vec4<float>::type V4;
     typedef int I4 __attribute__((ext_vector_type(4)));
+    constexpr int NRB = class_row_blocks(P);
+    constexpr int NB = (MASK & 1) + ((MASK >> 1) & 1) + ((MASK >> 2) & 1);
+    constexpr int M = 1 << NB;
+    constexpr int AX[3] = {(MASK & 1) ? 0 : ((MASK & 2) ? 1 : 2), (MASK & 1) ? ((MASK & 2) ? 1 : 2) : 2, 2};
+    V4 y[M];
+#pragma unroll
+    for (int j = 0; j < M; ++j) y[j] = xs[j];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        // sign of the 4 coefficients under the reflection of axis AX[b]
+        I4 t;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = ((ek[e] >> AX[b]) & 1) << 31;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+            if (!((j >> b) & 1)) {
+                const V4 u = y[j];
+                V4 v = y[j | (1 << b)];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) v[e] = __int_as_float(__float_as_int(v[e]) ^ t[e]);
+                y[j] = u + v;
+                y[j | (1 << b)] = u - v;
+            }
+    }
+    if (minus) {
+        I4 t;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = (__builtin_popcount(ek[e] & minus) & 1) << 31;
+#pragma unroll
+        for (int j = 0; j < M; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) y[j][e] = __int_as_float(__float_as_int(y[j][e]) ^ t[e]);
+    }
+    // class c of row block rb reads Wc[extract(c, both)]
+    auto ext = [](int c) {
+        int m = 0, o = 0;
+        for (int bit = 0; bit < 3; ++bit)
+            if ((MASK >> bit) & 1) m |= ((c >> bit) & 1) << o++;
+        return m;
+    };
+#pragma unroll
+    for (int ss = 0; ss < 4; ++ss)
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) acc[rb] = mfma16(ra[rb][ss], y[ext(class_of_row_block(P, rb))][ss], acc[rb]);
+}
+
+template <int P>
+__global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
+{
+    typedef Vec4<float>::type V4;
     constexpr int K = (P + 1) * (P + 1), KB = (K + 15) / 16, KP = 16 * KB;
-    constexpr int NRB = class_row_blocks(P), RBW = (NRB + CS - 1) / CS;
+    constexpr int NRB = class_row_blocks(P);
     constexpr int OPSZ = NRB * KB * 256;     // floats of one operator
-    constexpr int BUF = 8 * 16 * 64 * 4;     // bytes of one staging buffer: [class][k][target]
     constexpr int NIT = kOrbits * KB;        // steps (even: kOrbits is)
     constexpr int NG = kOrbGrid * kOrbGrid * kOrbGrid;
-    extern __shared__ unsigned char smem_raw[];
-    int* s_grid = reinterpret_cast<int*>(smem_raw + 2 * BUF);   // ME row of each local source box
-    int* s_tab = s_grid + NG;                                    // the octant's orbit table
-    int* s_le = s_tab + kOrbits * kOrbTab;                       // LE row of each target (-1 none)
-    int* s_aoff = s_le + 64;                                     // operator of each orbit
+    __shared__ int s_grid[NG];               // ME row of each local source box
+    __shared__ int s_tab[kOrbits * kOrbTab]; // the octant's orbit table
+    __shared__ int s_kcls[KP];               // sign class of each coefficient
+    __shared__ int s_le[64];                 // LE row of each target (-1 none)
+    __shared__ int s_aoff[kOrbits];          // operator of each orbit
     const Tile tile = A.tiles[sched_index(blockIdx.x, gridDim.x, A.tile_sched & 1)];
     const TileFL fl = A.tfl[tile.fl];
     const int nside = fl.nside;
     const int tid = threadIdx.x, l = tid & 63;
-    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
     const int* tab = A.orb_tab + tile.octant * (kOrbits * kOrbTab);
     {
@@ -999,6 +1051,7 @@ __global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
             s_grid[i] = me < 0 ? A.n_me : me;   // a missing source reads the zero row
         }
         for (int i = tid; i < kOrbits * kOrbTab; i += blockDim.x) s_tab[i] = tab[i];
+        for (int i = tid; i < KP; i += blockDim.x) s_kcls[i] = A.orb_kcls[i];
         if (tid < 64) {
             const int tx = 2 * (tile.px0 + (tid >> 4)) + ox, ty = 2 * (tile.py0 + ((tid >> 2) & 3)) + oy,
                       tz = 2 * (tile.pz0 + (tid & 3)) + oz;
@@ -1011,181 +1064,105 @@ __global__ void __launch_bounds__(256 * CS + 256) k_m2l_orbit(EvalArgs<float> A)
         }
     }
     __syncthreads();
-    // position of target j in row k of a class slab: the producers' writes
-    // (lanes over 16 targets and 4 k) and the consumers' reads (lanes over 16
-    // targets and 4 other k) both fall on distinct banks
-    auto swz = [](int k) { return 16 * ((k & 3) ^ ((k >> 2) & 3)); };
-    if (w < 4 * CS) {
-        // ---- consumer ----
-        const int cb = w & 3, rh = w >> 2, g = l >> 4, jj = l & 15;
-        int boff[4];
+    const int cb = tid >> 6, g = l >> 4, jj = l & 15, j = 16 * cb + jj;
+    const int tli = ((2 * (j >> 4)) * kOrbGrid + 2 * ((j >> 2) & 3)) * kOrbGrid + 2 * (j & 3);
+    const char* mebase = reinterpret_cast<const char*>(A.me);
+    const unsigned zoff = (unsigned)A.n_me * (unsigned)(KP * 4) + 16u * g;
+    // member row byte offsets of the orbit being gathered (absent members read
+    // the zero row: every step issues the same loads)
+    unsigned off[8];
+    auto lorbit = [&](int q) {
+        const int* row = s_tab + q * kOrbTab;
+        const int nm = 1 << (__builtin_amdgcn_readfirstlane(row[0]) & 15);
 #pragma unroll
-        for (int ss = 0; ss < 4; ++ss) boff[ss] = (4 * ss + g) * 64 + ((16 * cb + jj) ^ swz(4 * ss + g));
-        int cls[RBW];
-        bool live[RBW];
+        for (int m = 0; m < 8; ++m)
+            off[m] = (m < nm) ? (unsigned)s_grid[tli + row[1 + m]] * (unsigned)(KP * 4) + 16u * g : zoff;
+    };
+    V4 xr[2][8], ra[2][NRB];
+    auto load = [&](int t, V4 (&xs)[8], V4 (&as)[NRB]) {
+        const int s = t % KB;
+        if (s == 0) lorbit(t / KB);
+        const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ + (size_t)s * 256 + 4 * l;
 #pragma unroll
-        for (int i = 0; i < RBW; ++i) {
-            live[i] = rh * RBW + i < NRB;
-            cls[i] = class_of_row_block(P, min(rh * RBW + i, NRB - 1));
-        }
-        V4 acc[RBW], tot[RBW], cmp[RBW], ra[DA][RBW];
+        for (int rb = 0; rb < NRB; ++rb) as[rb] = *reinterpret_cast<const V4*>(Ao + (size_t)rb * (KB * 256));
+        const char* b = mebase + 64 * s;
 #pragma unroll
-        for (int i = 0; i < RBW; ++i) acc[i] = tot[i] = cmp[i] = V4{0, 0, 0, 0};
-        auto loadA = [&](int t, V4 (&dst)[RBW]) {
-            const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ;
-            const int s = t % KB;
+        for (int m = 0; m < 8; ++m) xs[m] = *reinterpret_cast<const V4*>(b + off[m]);
+    };
+    V4 acc[NRB], tot[NRB], cmp[NRB];
 #pragma unroll
-            for (int i = 0; i < RBW; ++i) {
-                const int rbg = min(rh * RBW + i, NRB - 1);
-                dst[i] = *reinterpret_cast<const V4*>(Ao + (((size_t)rbg * KB + s) * 64 + l) * 4);
-            }
-        };
-#pragma unroll
-        for (int d = 0; d < DA; ++d) loadA(d, ra[d]);
-        __syncthreads();
-        auto cstep = [&](int it, int par, V4 (&rr)[RBW]) {
-            const float* Bb = reinterpret_cast<const float*>(smem_raw + par * BUF);
-#pragma unroll
-            for (int i = 0; i < RBW; ++i) {
-                if (!live[i]) continue;
-                const float* Bc = Bb + cls[i] * 1024;
-#pragma unroll
-                for (int ss = 0; ss < 4; ++ss) acc[i] = mfma16(rr[i][ss], Bc[boff[ss]], acc[i]);
-            }
-            if (it + DA < NIT) loadA(it + DA, rr);
-            if (it % KB == KB - 1) {
-#pragma unroll
-                for (int i = 0; i < RBW; ++i) {
-                    const V4 y = acc[i] - cmp[i];
-                    const V4 t = tot[i] + y;
-                    cmp[i] = (t - tot[i]) - y;
-                    tot[i] = t;
-                    acc[i] = V4{0, 0, 0, 0};
-                }
-            }
-            __syncthreads();
-        };
-        for (int it = 0; it < NIT; it += 2) {
-            cstep(it, 0, ra[0]);
-            cstep(it + 1, 1, ra[DA - 1]);
-        }
-        const int j = 16 * cb + jj, le = s_le[j];
-        if (le < 0) return;
-#pragma unroll
-        for (int i = 0; i < RBW; ++i) {
-            if (!live[i]) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int nat = A.orb_rows[16 * (rh * RBW + i) + 4 * g + r];
-                if (nat >= 0) A.le[(size_t)le * KP + nat] += tot[i][r] - cmp[i][r];
-            }
-        }
-    } else {
-        // ---- producer: item = target gj, slab coefficients 4 gq .. 4 gq + 3 ----
-        const int pt = tid - 256 * CS, gj = pt >> 2, gq = pt & 3;
-        const int tli = ((2 * (gj >> 4)) * kOrbGrid + 2 * ((gj >> 2) & 3)) * kOrbGrid + 2 * (gj & 3);
-        const char* mebase = reinterpret_cast<const char*>(A.me);
-        // orbit of the steps being gathered: member count and row byte offsets
-        unsigned off[8];
-        int nmL = 1;
-        auto lorbit = [&](int q) {
+    for (int rb = 0; rb < NRB; ++rb) acc[rb] = tot[rb] = cmp[rb] = V4{0, 0, 0, 0};
+    load(0, xr[0], ra[0]);
+    load(1, xr[1], ra[1]);
+    int mask = 0, minus = 0;   // both-axes and one-sign negative axes of the orbit being multiplied
+    auto step = [&](int t, V4 (&xs)[8], V4 (&as)[NRB]) {
+        const int q = t / KB, s = t % KB;
+        if (s == 0) {
             const int* row = s_tab + q * kOrbTab;
-            nmL = 1 << (__builtin_amdgcn_readfirstlane(row[0]) & 15);
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j < nmL) off[j] = (unsigned)s_grid[tli + row[1 + j]] * (unsigned)(KP * 4) + 16u * gq;
-        };
-        // orbit of the step being staged: transform size, output classes and signs
-        int codeS = 0, wa[8], ws[8];
-        auto sorbit = [&](int q) {
-            const int* row = s_tab + q * kOrbTab;
+            // both-axes: the classes g of the transform outputs j = 1, 2, 4 (t = 0)
             const int h = __builtin_amdgcn_readfirstlane(row[0]);
-            codeS = (h & 15) + 4 * (h >> 4);
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                const int e = __builtin_amdgcn_readfirstlane(row[9 + i]);
-                wa[i] = e & 0x7000;
-                ws[i] = e & (int)0x80000000;
-            }
-        };
-        V4 xr[2][8];
-        I4 ekr[2];
-        auto load = [&](int t, V4 (&xs)[8], I4& ek) {
-            const int s = t % KB;
-            if (s == 0) lorbit(t / KB);
-            const char* b = mebase + 64 * s;
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (j < nmL) xs[j] = *reinterpret_cast<const V4*>(b + off[j]);
-            ek = *reinterpret_cast<const I4*>(A.orb_kcls + 16 * s + 4 * gq);
-        };
-        // LDS byte address of the dynamic buffer (the kernel has no static LDS,
-        // so it is 0, a multiple of 32 KiB: class bits 12..14 can be XORed into
-        // absolute addresses)
-        typedef __attribute__((address_space(3))) float lds_float;
-        typedef __attribute__((address_space(3))) unsigned char lds_byte;
-        const unsigned lbase = (unsigned)(size_t)(lds_byte*)smem_raw;
-        auto stage_nb = [&](auto nbc, auto negc, const V4 (&xs)[8], const unsigned (&a0)[4]) {
-            constexpr int NB = decltype(nbc)::value;
-            constexpr bool NEG = decltype(negc)::value;
-            constexpr int M = 1 << NB;
-            V4 y[M];
-#pragma unroll
-            for (int j = 0; j < M; ++j) y[j] = xs[j];
-#pragma unroll
-            for (int b = 0; b < NB; ++b)
-#pragma unroll
-                for (int j = 0; j < M; ++j)
-                    if (!((j >> b) & 1)) {
-                        const V4 u = y[j], v = y[j | (1 << b)];
-                        y[j] = u + v;
-                        y[j | (1 << b)] = u - v;
+            const int nb = h & 15;
+            mask = 0;
+            for (int bit = 0; bit < nb; ++bit) mask |= (__builtin_amdgcn_readfirstlane(row[9 + (1 << bit)]) >> 12) & 7;
+            // negative one-sign axes: the sign bits of the outputs give |g & minus| per class
+            minus = 0;
+            for (int ax = 0; ax < 3; ++ax) {
+                if ((mask >> ax) & 1) continue;
+                // output index of class (1 << ax): t bit for that axis
+                int tb = 0, o = 0;
+                for (int bit = 0; bit < 3; ++bit)
+                    if (!((mask >> bit) & 1)) {
+                        if (bit == ax) tb = 1 << o;
+                        ++o;
                     }
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) {
-                    float v = y[i & (M - 1)][e];
-                    if (NEG) v = __int_as_float(__float_as_int(v) ^ ws[i]);
-                    *(lds_float*)(size_t)(a0[e] ^ (unsigned)wa[i]) = v;
-                }
-        };
-        auto stage = [&](int t, const V4 (&xs)[8], const I4& ek, int buf) {
-            if (t % KB == 0) sorbit(t / KB);
-            unsigned a0[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int kl = 4 * gq + e;
-                a0[e] = lbase + (unsigned)(buf * BUF + (ek[e] << 12) + kl * 256 + ((gj ^ swz(kl)) << 2));
+                const int e = __builtin_amdgcn_readfirstlane(row[9 + (tb << nb)]);
+                if (e < 0) minus |= 1 << ax;
             }
-            typedef std::integral_constant<bool, false> F;
-            typedef std::integral_constant<bool, true> T;
-            switch (codeS) {
-            case 0: stage_nb(std::integral_constant<int, 0>{}, F{}, xs, a0); break;
-            case 1: stage_nb(std::integral_constant<int, 1>{}, F{}, xs, a0); break;
-            case 2: stage_nb(std::integral_constant<int, 2>{}, F{}, xs, a0); break;
-            case 3: stage_nb(std::integral_constant<int, 3>{}, F{}, xs, a0); break;
-            case 4: stage_nb(std::integral_constant<int, 0>{}, T{}, xs, a0); break;
-            case 5: stage_nb(std::integral_constant<int, 1>{}, T{}, xs, a0); break;
-            default: stage_nb(std::integral_constant<int, 2>{}, T{}, xs, a0); break;
-            }
-        };
-        load(0, xr[0], ekr[0]);
-        stage(0, xr[0], ekr[0], 0);
-        load(1, xr[1], ekr[1]);
-        load(2, xr[0], ekr[0]);
-        __syncthreads();
-        // step it: stage step it + 1 into the other buffer, gather step it + 3
-        auto pstep = [&](int it, V4 (&xs)[8], I4& ek, int nbuf) {
-            if (it + 1 < NIT) stage(it + 1, xs, ek, nbuf);
-            if (it + 3 < NIT) load(it + 3, xs, ek);
-            __syncthreads();
-        };
-        for (int it = 0; it < NIT; it += 2) {
-            pstep(it, xr[1], ekr[1], 1);
-            pstep(it + 1, xr[0], ekr[0], 0);
         }
+        int ek[4];
+        {
+            const int* kc = s_kcls + 16 * s + 4 * g;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) ek[e] = kc[e];
+        }
+        switch (mask) {
+        case 0: orbit_step<P, 0>(xs, ek, minus, as, acc); break;
+        case 1: orbit_step<P, 1>(xs, ek, minus, as, acc); break;
+        case 2: orbit_step<P, 2>(xs, ek, minus, as, acc); break;
+        case 3: orbit_step<P, 3>(xs, ek, minus, as, acc); break;
+        case 4: orbit_step<P, 4>(xs, ek, minus, as, acc); break;
+        case 5: orbit_step<P, 5>(xs, ek, minus, as, acc); break;
+        case 6: orbit_step<P, 6>(xs, ek, minus, as, acc); break;
+        default: orbit_step<P, 7>(xs, ek, minus, as, acc); break;
+        }
+        load(min(t + 2, NIT - 1), xs, as);   // (the last steps re-gather a valid step: fixed load count)
+        if (s == KB - 1) {
+#pragma unroll
+            for (int rb = 0; rb < NRB; ++rb) {
+                // class sign (-1)^|c & minus| of the orbit's product
+                const bool neg = __builtin_popcount(class_of_row_block(P, rb) & minus) & 1;
+                const V4 pr = neg ? -acc[rb] : acc[rb];
+                const V4 yk = pr - cmp[rb];
+                const V4 tk = tot[rb] + yk;
+                cmp[rb] = (tk - tot[rb]) - yk;
+                tot[rb] = tk;
+                acc[rb] = V4{0, 0, 0, 0};
+            }
+        }
+    };
+    for (int t = 0; t < NIT; t += 2) {
+        step(t, xr[0], ra[0]);
+        step(t + 1, xr[1], ra[1]);
     }
+    const int le = s_le[j];
+    if (le < 0) return;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int nat = A.orb_rows[16 * rb + 4 * g + r];
+            if (nat >= 0) A.le[(size_t)le * KP + nat] += tot[rb][r] - cmp[rb][r];
+        }
 }
 
 template <typename T>
@@ -1200,16 +1177,13 @@ static void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
         // (row byte offsets of the expansions are 32-bit in the orbit kernel)
         if (A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP &&
             (size_t)(A.n_me + 1) * A.KP * sizeof(float) < ((size_t)1 << 32)) {
-            const size_t smo = 2 * 8 * 16 * 64 * sizeof(float) +
-                               sizeof(int) * (kOrbGrid * kOrbGrid * kOrbGrid + kOrbits * kOrbTab + 64 + kOrbits);
-#define LPB_ORB(PP, CS, DA)                                                                                        \
+#define LPB_ORB(PP)                                                                                                \
     case PP:                                                                                                       \
-        hipLaunchKernelGGL((k_m2l_orbit<PP, CS, DA>), g, dim3(256 * CS + 256), smo, st, A);                        \
+        hipLaunchKernelGGL((k_m2l_orbit<PP>), g, dim3(256), 0, st, A);                                             \
         return;
             switch (A.p) {
-                LPB_ORB(5, 1, 2) LPB_ORB(6, 1, 2) LPB_ORB(7, 1, 2) LPB_ORB(8, 1, 2) LPB_ORB(9, 1, 2)
-                LPB_ORB(10, 1, 2) LPB_ORB(11, 1, 2) LPB_ORB(12, 2, 1) LPB_ORB(13, 2, 1) LPB_ORB(14, 2, 1)
-                LPB_ORB(15, 2, 1)
+                LPB_ORB(5) LPB_ORB(6) LPB_ORB(7) LPB_ORB(8) LPB_ORB(9) LPB_ORB(10)
+                LPB_ORB(11) LPB_ORB(12) LPB_ORB(13) LPB_ORB(14) LPB_ORB(15)
             default: break;
             }
 #undef LPB_ORB

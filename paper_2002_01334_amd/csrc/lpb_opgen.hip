@@ -460,7 +460,9 @@ __global__ void k_swizzle(int K, int KP, int nsw, const int* __restrict__ ops, c
 }
 
 // The same layout with the rows permuted (rowmap: operand row -> result
-// coefficient, -1 for a zero padding row), NRB row blocks.
+// coefficient, -1 for a zero padding row), NRB row blocks, and the four
+// coefficients a lane holds for the four products of a 16-coefficient slab
+// consecutive (product ss, lane l: coefficient 16 s4 + 4 (l / 16) + ss).
 __global__ void k_swizzle_rows(int K, int KP, int NRB, int nsw, const int* __restrict__ ops,
                                const int* __restrict__ rowmap, const double* __restrict__ pool, float* __restrict__ out)
 {
@@ -473,7 +475,7 @@ __global__ void k_swizzle_rows(int K, int KP, int NRB, int nsw, const int* __res
     int ss = (int)(e & 3), lane = (int)((e >> 2) & 63);
     size_t rest = e >> 8;
     int s4 = (int)(rest % KB), rb = (int)(rest / KB);
-    int row = rowmap[16 * rb + (lane & 15)], k = 16 * s4 + 4 * ss + (lane >> 4);
+    int row = rowmap[16 * rb + (lane & 15)], k = 16 * s4 + 4 * (lane >> 4) + ss;
     double v = (row >= 0 && k < K) ? pool[(size_t)ops[o] * K * K + (size_t)k * K + row] : 0.0;
     out[idx] = (float)v;
 }
