@@ -969,7 +969,7 @@ __global__ void __launch_bounds__(RBW == 1 ? 64 * KB : 256) k_m2l_tile_kb(EvalAr
 // ahead.  No data is shared between waves, so the waves never wait for each
 // other.  Each orbit's products go to the result with Kahan compensation.
 template <int P, int MASK>
-__device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], const int (&ek)[4], int minus,
+__device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], const int __attribute__((ext_vector_type(4))) ek, int minus,
                                            const Vec4<float>::type (&ra)[class_row_blocks(P)],
                                            Vec4<float>::type (&acc)[class_row_blocks(P)])
 {
@@ -1078,8 +1078,11 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         for (int m = 0; m < 8; ++m)
             off[m] = (m < nm) ? (unsigned)s_grid[tli + row[1 + m]] * (unsigned)(KP * 4) + 16u * g : zoff;
     };
+    typedef int I4 __attribute__((ext_vector_type(4)));
     V4 xr[2][8], ra[2][NRB];
-    auto load = [&](int t, V4 (&xs)[8], V4 (&as)[NRB]) {
+    I4 er[2];
+    // gather step t: operand slab, member sources, coefficient classes
+    auto load = [&](int t, V4 (&xs)[8], V4 (&as)[NRB], I4& ek) {
         const int s = t % KB;
         if (s == 0) lorbit(t / KB);
         const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ + (size_t)s * 256 + 4 * l;
@@ -1088,71 +1091,73 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         const char* b = mebase + 64 * s;
 #pragma unroll
         for (int m = 0; m < 8; ++m) xs[m] = *reinterpret_cast<const V4*>(b + off[m]);
+        ek = *reinterpret_cast<const I4*>(s_kcls + 16 * s + 4 * g);
     };
     V4 acc[NRB], tot[NRB], cmp[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) acc[rb] = tot[rb] = cmp[rb] = V4{0, 0, 0, 0};
-    load(0, xr[0], ra[0]);
-    load(1, xr[1], ra[1]);
-    int mask = 0, minus = 0;   // both-axes and one-sign negative axes of the orbit being multiplied
-    auto step = [&](int t, V4 (&xs)[8], V4 (&as)[NRB]) {
-        const int q = t / KB, s = t % KB;
-        if (s == 0) {
-            const int* row = s_tab + q * kOrbTab;
-            // both-axes: the classes g of the transform outputs j = 1, 2, 4 (t = 0)
-            const int h = __builtin_amdgcn_readfirstlane(row[0]);
-            const int nb = h & 15;
-            mask = 0;
-            for (int bit = 0; bit < nb; ++bit) mask |= (__builtin_amdgcn_readfirstlane(row[9 + (1 << bit)]) >> 12) & 7;
-            // negative one-sign axes: the sign bits of the outputs give |g & minus| per class
-            minus = 0;
-            for (int ax = 0; ax < 3; ++ax) {
-                if ((mask >> ax) & 1) continue;
-                // output index of class (1 << ax): t bit for that axis
-                int tb = 0, o = 0;
-                for (int bit = 0; bit < 3; ++bit)
-                    if (!((mask >> bit) & 1)) {
-                        if (bit == ax) tb = 1 << o;
-                        ++o;
-                    }
-                const int e = __builtin_amdgcn_readfirstlane(row[9 + (tb << nb)]);
-                if (e < 0) minus |= 1 << ax;
-            }
-        }
-        int ek[4];
-        {
-            const int* kc = s_kcls + 16 * s + 4 * g;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) ek[e] = kc[e];
-        }
-        switch (mask) {
-        case 0: orbit_step<P, 0>(xs, ek, minus, as, acc); break;
-        case 1: orbit_step<P, 1>(xs, ek, minus, as, acc); break;
-        case 2: orbit_step<P, 2>(xs, ek, minus, as, acc); break;
-        case 3: orbit_step<P, 3>(xs, ek, minus, as, acc); break;
-        case 4: orbit_step<P, 4>(xs, ek, minus, as, acc); break;
-        case 5: orbit_step<P, 5>(xs, ek, minus, as, acc); break;
-        case 6: orbit_step<P, 6>(xs, ek, minus, as, acc); break;
-        default: orbit_step<P, 7>(xs, ek, minus, as, acc); break;
-        }
-        load(min(t + 2, NIT - 1), xs, as);   // (the last steps re-gather a valid step: fixed load count)
-        if (s == KB - 1) {
-#pragma unroll
-            for (int rb = 0; rb < NRB; ++rb) {
-                // class sign (-1)^|c & minus| of the orbit's product
-                const bool neg = __builtin_popcount(class_of_row_block(P, rb) & minus) & 1;
-                const V4 pr = neg ? -acc[rb] : acc[rb];
-                const V4 yk = pr - cmp[rb];
-                const V4 tk = tot[rb] + yk;
-                cmp[rb] = (tk - tot[rb]) - yk;
-                tot[rb] = tk;
-                acc[rb] = V4{0, 0, 0, 0};
+    load(0, xr[0], ra[0], er[0]);
+    load(1, xr[1], ra[1], er[1]);
+    // one orbit: its KB steps with the transform specialised for its both-axes
+    // (steps of one orbit form one straight code path, so the transforms of a
+    // step can overlap the products of the previous one); step t uses register
+    // slot t & 1 and refills it with step t + 2 (the last steps re-gather a
+    // valid step: a fixed load count)
+    auto run = [&](auto maskc, auto parc, int q, int minus) {
+        constexpr int MASK = decltype(maskc)::value, PAR = decltype(parc)::value;
+        const int t0 = q * KB;
+        for (int s = 0; s < KB; s += 2) {
+            orbit_step<P, MASK>(xr[PAR], er[PAR], minus, ra[PAR], acc);
+            load(min(t0 + s + 2, NIT - 1), xr[PAR], ra[PAR], er[PAR]);
+            if (s + 1 < KB) {
+                orbit_step<P, MASK>(xr[PAR ^ 1], er[PAR ^ 1], minus, ra[PAR ^ 1], acc);
+                load(min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[PAR ^ 1], er[PAR ^ 1]);
             }
         }
     };
-    for (int t = 0; t < NIT; t += 2) {
-        step(t, xr[0], ra[0]);
-        step(t + 1, xr[1], ra[1]);
+    for (int q = 0; q < kOrbits; ++q) {
+        const int* row = s_tab + q * kOrbTab;
+        // both-axes: the classes of the transform outputs 1, 2, 4 (one-sign bits 0)
+        const int h = __builtin_amdgcn_readfirstlane(row[0]);
+        const int nb = h & 15;
+        int mask = 0;
+        for (int bit = 0; bit < nb; ++bit) mask |= (__builtin_amdgcn_readfirstlane(row[9 + (1 << bit)]) >> 12) & 7;
+        // negative one-sign axes: the sign of the output of class (1 << axis)
+        int minus = 0;
+        for (int ax = 0; ax < 3; ++ax) {
+            if ((mask >> ax) & 1) continue;
+            int tb = 0, o = 0;
+            for (int bit = 0; bit < 3; ++bit)
+                if (!((mask >> bit) & 1)) {
+                    if (bit == ax) tb = 1 << o;
+                    ++o;
+                }
+            if (__builtin_amdgcn_readfirstlane(row[9 + (tb << nb)]) < 0) minus |= 1 << ax;
+        }
+        const int par = (KB & 1) ? (q & 1) : 0;   // slot of the orbit's first step
+        typedef std::integral_constant<int, 0> Z;
+        typedef std::integral_constant<int, 1> O;
+#define LPB_RUN(M)                                                                       \
+    case M:                                                                              \
+        if ((KB & 1) && par) run(std::integral_constant<int, M>{}, O{}, q, minus);       \
+        else run(std::integral_constant<int, M>{}, Z{}, q, minus);                       \
+        break;
+        switch (mask) {
+            LPB_RUN(0) LPB_RUN(1) LPB_RUN(2) LPB_RUN(3) LPB_RUN(4) LPB_RUN(5) LPB_RUN(6) LPB_RUN(7)
+        default: break;
+        }
+#undef LPB_RUN
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) {
+            // class sign (-1)^|c & minus| of the orbit's product
+            const bool neg = __builtin_popcount(class_of_row_block(P, rb) & minus) & 1;
+            const V4 pr = neg ? -acc[rb] : acc[rb];
+            const V4 yk = pr - cmp[rb];
+            const V4 tk = tot[rb] + yk;
+            cmp[rb] = (tk - tot[rb]) - yk;
+            tot[rb] = tk;
+            acc[rb] = V4{0, 0, 0, 0};
+        }
     }
     const int le = s_le[j];
     if (le < 0) return;
