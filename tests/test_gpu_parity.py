@@ -338,6 +338,24 @@ def test_full_size_p15_mixed_vs_fp64(lpb):
     assert e <= 1e-6
 
 
+@pytest.mark.parametrize("p", [5, 7, 9, 11, 13, 14])
+def test_tiled_orders_mixed_vs_fp64(lpb, p):
+    """Expansion orders of the orbit form of the tiled M2L (odd and even
+    numbers of 16-coefficient slabs, one or two row blocks per sign class) on
+    a tree with tiled levels (2e5 charges): mixed vs FP64 within 1e-6 per
+    layer (the FP64 run takes the per-offset form)."""
+    prob = inputs.three_layer(66_667, seed=3)
+    ctx, phi64 = run(lpb, prob, p, 50, device=True)
+    st = ctx.stats()
+    ctx.close()
+    assert st["n_m2l_tile_pairs"] > 0
+    ctx, phi32 = run(lpb, prob, p, 50, precision=lpb.LPB_MIXED, device=True)
+    ctx.close()
+    e = err2(phi32, phi64, prob.layer)
+    print(f"p={p}: mixed vs FP64 {e:.3e}")
+    assert e <= 1e-6
+
+
 def test_reaction_near_field_next_to_interfaces(lpb):
     """Charges within 2e-3 of an interface keep reaction U-list pairs (the
     separation depth is capped), so the reaction near field is exercised; FP64
