@@ -1106,12 +1106,17 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     auto run = [&](auto maskc, auto parc, int q, int minus) {
         constexpr int MASK = decltype(maskc)::value, PAR = decltype(parc)::value;
         const int t0 = q * KB;
+        // (the scheduling fences keep each step's transforms after its own loads'
+        // wait: hoisted into the previous step they would wait for the loads
+        // just issued)
         for (int s = 0; s < KB; s += 2) {
             orbit_step<P, MASK>(xr[PAR], er[PAR], minus, ra[PAR], acc);
             load(min(t0 + s + 2, NIT - 1), xr[PAR], ra[PAR], er[PAR]);
+            __builtin_amdgcn_sched_barrier(0);
             if (s + 1 < KB) {
                 orbit_step<P, MASK>(xr[PAR ^ 1], er[PAR ^ 1], minus, ra[PAR ^ 1], acc);
                 load(min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[PAR ^ 1], er[PAR ^ 1]);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
     };
