@@ -243,8 +243,14 @@ def main():
     K = (p + 1) ** 2
     stage = mixed["stage_ms"]
     # dominant kernel and its algorithmic work per launch (one launch per evaluation)
+    # tiled M2L, orbit form (mixed precision, 5 <= p <= 15): one K x K product per
+    # (target box, reflection orbit), 64 boxes and 56 orbits per tile
+    orbit_form = 5 <= p <= 15
+    tile_units = 56 * 64 * st["n_m2l_tiles"] if orbit_form else st["n_m2l_tile_pairs"]
     work = {
-        "m2l_tile": (2.0 * K * K * st["n_m2l_tile_pairs"], "mfma", "2K^2 flops per V-list pair (real-form dense product)"),
+        "m2l_tile": (2.0 * K * K * tile_units, "mfma",
+                     "2K^2 flops per (target box, reflection orbit) product" if orbit_form
+                     else "2K^2 flops per V-list pair (real-form dense product)"),
         "p2p_free": (FLOPS_PER_P2P_PAIR * (st["n_p2p_pairs"] - st["n_react_p2p_pairs"]), "alu",
                      "20 flops per charge pair"),
     }

@@ -99,9 +99,11 @@ typedef struct {
     double t_stage_ms[10];
     int tile_schedule;      /* schedule chosen for the tiled M2L: bit 0 = 0 linear, 1 blocks of one XCD take a
                                contiguous run of tiles (tiles sharing operators share that XCD's L2); bit 1 =
-                               blocks of one wave per 16-row block instead of four waves */
+                               blocks of one wave per 16-row block instead of four waves (per-offset form only:
+                               FP64, or mixed precision with p < 5 or p > 15) */
     int batch_schedule;     /* the same choice for the batched translations */
     double t_tune_ms;       /* time spent by the last schedule autotuning */
+    int64_t n_m2l_tiles;    /* tiles (64 target boxes, one child octant) of the tiled M2L */
 } lpb_stats;
 
 /* Fill *opt with the defaults listed above.  Never fails. */

@@ -514,6 +514,7 @@ lpb_status build_and_upload(lpb_ctx* c)
     c->stats.max_depth = P.max_depth;
     c->stats.n_m2l_pairs = P.n_m2l_pairs;
     c->stats.n_m2l_tile_pairs = P.n_m2l_tile_pairs;
+    c->stats.n_m2l_tiles = (int64_t)P.tiles.size();
     c->stats.n_p2p_pairs = P.n_p2p_pairs;
     c->stats.n_react_p2p_pairs = P.n_react_p2p_pairs;
     c->stats.n_operators = (int64_t)P.ops.size();
