@@ -1079,15 +1079,22 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
             off[m] = (m < nm) ? (unsigned)s_grid[tli + row[1 + m]] * (unsigned)(KP * 4) + 16u * g : zoff;
     };
     typedef int I4 __attribute__((ext_vector_type(4)));
-    V4 xr[2][8], ra[2][NRB];
+    // operand slabs: gathered two steps ahead (DA = 2) while the registers
+    // allow, one step ahead for the larger orders (they come mostly from L2)
+    constexpr int DA = (NRB <= 9) ? 2 : 1;
+    V4 xr[2][8], ra[DA][NRB];
     I4 er[2];
-    // gather step t: operand slab, member sources, coefficient classes
+    auto load_a = [&](int t, V4 (&as)[NRB]) {
+        const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ + (size_t)(t % KB) * 256 + 4 * l;
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) as[rb] = *reinterpret_cast<const V4*>(Ao + (size_t)rb * (KB * 256));
+    };
+    // gather step t: member sources and coefficient classes (and, with DA = 2,
+    // its operand slab)
     auto load = [&](int t, V4 (&xs)[8], V4 (&as)[NRB], I4& ek) {
         const int s = t % KB;
         if (s == 0) lorbit(t / KB);
-        const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ + (size_t)s * 256 + 4 * l;
-#pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) as[rb] = *reinterpret_cast<const V4*>(Ao + (size_t)rb * (KB * 256));
+        if constexpr (DA == 2) load_a(t, as);
         const char* b = mebase + 64 * s;
 #pragma unroll
         for (int m = 0; m < 8; ++m) xs[m] = *reinterpret_cast<const V4*>(b + off[m]);
@@ -1097,7 +1104,8 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) acc[rb] = tot[rb] = cmp[rb] = V4{0, 0, 0, 0};
     load(0, xr[0], ra[0], er[0]);
-    load(1, xr[1], ra[1], er[1]);
+    load(1, xr[1], ra[DA - 1], er[1]);
+    if constexpr (DA == 1) load_a(0, ra[0]);
     // one orbit: its KB steps with the transform specialised for its both-axes
     // (steps of one orbit form one straight code path, so the transforms of a
     // step can overlap the products of the previous one); step t uses register
@@ -1109,13 +1117,16 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         // (the scheduling fences keep each step's transforms after its own loads'
         // wait: hoisted into the previous step they would wait for the loads
         // just issued)
+        constexpr int A0 = (DA == 2) ? PAR : 0, A1 = (DA == 2) ? (PAR ^ 1) : 0;
         for (int s = 0; s < KB; s += 2) {
-            orbit_step<P, MASK>(xr[PAR], er[PAR], minus, ra[PAR], acc);
-            load(min(t0 + s + 2, NIT - 1), xr[PAR], ra[PAR], er[PAR]);
+            orbit_step<P, MASK>(xr[PAR], er[PAR], minus, ra[A0], acc);
+            if constexpr (DA == 1) load_a(min(t0 + s + 1, NIT - 1), ra[0]);
+            load(min(t0 + s + 2, NIT - 1), xr[PAR], ra[A0], er[PAR]);
             __builtin_amdgcn_sched_barrier(0);
             if (s + 1 < KB) {
-                orbit_step<P, MASK>(xr[PAR ^ 1], er[PAR ^ 1], minus, ra[PAR ^ 1], acc);
-                load(min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[PAR ^ 1], er[PAR ^ 1]);
+                orbit_step<P, MASK>(xr[PAR ^ 1], er[PAR ^ 1], minus, ra[A1], acc);
+                if constexpr (DA == 1) load_a(min(t0 + s + 2, NIT - 1), ra[0]);
+                load(min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[A1], er[PAR ^ 1]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
