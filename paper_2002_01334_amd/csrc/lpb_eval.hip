@@ -1601,7 +1601,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     };
     // P2M / L2P with the order fixed at compile time where it is specialised
     bool p_fixed = false;
-    if constexpr (sizeof(T) == 4) p_fixed = p >= 2 && p <= 12;
+    if constexpr (sizeof(T) == 4) p_fixed = p >= 2 && p <= 15;
     if (far && S.n_p2m > 0) {
         if constexpr (sizeof(T) == 4) {
             if (p_fixed) {
@@ -1609,7 +1609,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     case PP: hipLaunchKernelGGL(k_p2m_p<PP>, dim3(S.n_p2m), dim3(64), 0, st, A); break;
                 switch (p) {
                     LPB_P2M(2) LPB_P2M(3) LPB_P2M(4) LPB_P2M(5) LPB_P2M(6) LPB_P2M(7) LPB_P2M(8) LPB_P2M(9)
-                    LPB_P2M(10) LPB_P2M(11) LPB_P2M(12)
+                    LPB_P2M(10) LPB_P2M(11) LPB_P2M(12) LPB_P2M(13) LPB_P2M(14) LPB_P2M(15)
                 default: break;
                 }
 #undef LPB_P2M
@@ -1641,7 +1641,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     case PP: hipLaunchKernelGGL(k_l2p_p<PP>, dim3(S.n_l2p), dim3(64), 0, st, A); break;
                 switch (p) {
                     LPB_L2P(2) LPB_L2P(3) LPB_L2P(4) LPB_L2P(5) LPB_L2P(6) LPB_L2P(7) LPB_L2P(8) LPB_L2P(9)
-                    LPB_L2P(10) LPB_L2P(11) LPB_L2P(12)
+                    LPB_L2P(10) LPB_L2P(11) LPB_L2P(12) LPB_L2P(13) LPB_L2P(14) LPB_L2P(15)
                 default: break;
                 }
 #undef LPB_L2P
