@@ -1042,26 +1042,50 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     const int ox = (tile.octant >> 2) & 1, oy = (tile.octant >> 1) & 1, oz = tile.octant & 1;
     const int* tab = A.orb_tab + tile.octant * (kOrbits * kOrbTab);
     {
+        // every gather of the set-up is issued before the first LDS store, so
+        // the independent loads are in flight together
+        constexpr int NTH = 256, NGL = (NG + NTH - 1) / NTH, NTL = (kOrbits * kOrbTab + NTH - 1) / NTH;
+        static_assert(KP <= NTH, "one coefficient class per thread");
         const int gx0 = 2 * tile.px0 + ox - 3, gy0 = 2 * tile.py0 + oy - 3, gz0 = 2 * tile.pz0 + oz - 3;
-        for (int i = tid; i < NG; i += blockDim.x) {
+        int gv[NGL], tv[NTL];
+#pragma unroll
+        for (int k = 0; k < NGL; ++k) {
+            const int i = tid + k * NTH;
             const int sx = gx0 + i / (kOrbGrid * kOrbGrid), sy = gy0 + (i / kOrbGrid) % kOrbGrid, sz = gz0 + i % kOrbGrid;
-            int me = -1;
-            if (sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
-                me = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
-            s_grid[i] = me < 0 ? A.n_me : me;   // a missing source reads the zero row
+            gv[k] = -1;
+            if (i < NG && sx >= 0 && sy >= 0 && sz >= 0 && sx < nside && sy < nside && sz < nside)
+                gv[k] = A.grid_me[fl.grid_off + ((size_t)sx * nside + sy) * nside + sz];
         }
-        for (int i = tid; i < kOrbits * kOrbTab; i += blockDim.x) s_tab[i] = tab[i];
-        for (int i = tid; i < KP; i += blockDim.x) s_kcls[i] = A.orb_kcls[i];
+#pragma unroll
+        for (int k = 0; k < NTL; ++k) {
+            const int i = tid + k * NTH;
+            tv[k] = (i < kOrbits * kOrbTab) ? tab[i] : 0;
+        }
+        const int kv = (tid < KP) ? A.orb_kcls[tid] : 0;
+        int lv = -1;
         if (tid < 64) {
             const int tx = 2 * (tile.px0 + (tid >> 4)) + ox, ty = 2 * (tile.py0 + ((tid >> 2) & 3)) + oy,
                       tz = 2 * (tile.pz0 + (tid & 3)) + oz;
-            s_le[tid] = (tx < nside && ty < nside && tz < nside)
-                            ? A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz] : -1;
+            if (tx < nside && ty < nside && tz < nside)
+                lv = A.grid_le[fl.grid_off + ((size_t)tx * nside + ty) * nside + tz];
         } else if (tid < 64 + kOrbits) {
             const int q = tid - 64;
             const int op = A.optab[fl.optab_off + tab[q * kOrbTab + 17]] & ((1 << kReflShift) - 1);
-            s_aoff[q] = A.orb_index[op];
+            lv = A.orb_index[op];
         }
+#pragma unroll
+        for (int k = 0; k < NGL; ++k) {
+            const int i = tid + k * NTH;
+            if (i < NG) s_grid[i] = gv[k] < 0 ? A.n_me : gv[k];   // a missing source reads the zero row
+        }
+#pragma unroll
+        for (int k = 0; k < NTL; ++k) {
+            const int i = tid + k * NTH;
+            if (i < kOrbits * kOrbTab) s_tab[i] = tv[k];
+        }
+        if (tid < KP) s_kcls[tid] = kv;
+        if (tid < 64) s_le[tid] = lv;
+        else if (tid < 64 + kOrbits) s_aoff[tid - 64] = lv;
     }
     __syncthreads();
     const int cb = tid >> 6, g = l >> 4, jj = l & 15, j = 16 * cb + jj;
@@ -1132,24 +1156,9 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         }
     };
     for (int q = 0; q < kOrbits; ++q) {
-        const int* row = s_tab + q * kOrbTab;
-        // both-axes: the classes of the transform outputs 1, 2, 4 (one-sign bits 0)
-        const int h = __builtin_amdgcn_readfirstlane(row[0]);
-        const int nb = h & 15;
-        int mask = 0;
-        for (int bit = 0; bit < nb; ++bit) mask |= (__builtin_amdgcn_readfirstlane(row[9 + (1 << bit)]) >> 12) & 7;
-        // negative one-sign axes: the sign of the output of class (1 << axis)
-        int minus = 0;
-        for (int ax = 0; ax < 3; ++ax) {
-            if ((mask >> ax) & 1) continue;
-            int tb = 0, o = 0;
-            for (int bit = 0; bit < 3; ++bit)
-                if (!((mask >> bit) & 1)) {
-                    if (bit == ax) tb = 1 << o;
-                    ++o;
-                }
-            if (__builtin_amdgcn_readfirstlane(row[9 + (tb << nb)]) < 0) minus |= 1 << ax;
-        }
+        // both-axes and negative one-sign axes of the orbit
+        const int h = __builtin_amdgcn_readfirstlane(s_tab[q * kOrbTab]);
+        const int mask = (h >> 4) & 7, minus = (h >> 7) & 7;
         const int par = (KB & 1) ? (q & 1) : 0;   // slot of the orbit's first step
         typedef std::integral_constant<int, 0> Z;
         typedef std::integral_constant<int, 1> O;
@@ -1177,13 +1186,24 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     }
     const int le = s_le[j];
     if (le < 0) return;
+    // all row indices, then all current LE values, then the stores (loads in
+    // flight together)
+    int nat[NRB][4];
+    float cur[NRB][4];
+    float* lr = A.le + (size_t)le * KP;
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int nat = A.orb_rows[16 * rb + 4 * g + r];
-            if (nat >= 0) A.le[(size_t)le * KP + nat] += tot[rb][r] - cmp[rb][r];
-        }
+        for (int r = 0; r < 4; ++r) nat[rb][r] = A.orb_rows[16 * rb + 4 * g + r];
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cur[rb][r] = nat[rb][r] >= 0 ? lr[nat[rb][r]] : 0.0f;
+#pragma unroll
+    for (int rb = 0; rb < NRB; ++rb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (nat[rb][r] >= 0) lr[nat[rb][r]] = cur[rb][r] + (tot[rb][r] - cmp[rb][r]);
 }
 
 template <typename T>

@@ -33,8 +33,9 @@ constexpr int kXfRotate = 8;
 // (canonical offset (|dx|,|dy|,|dz|)).  Per axis an orbit has both signs
 // ("both" axes, 1 or 2 away) or one (0, or 3 on the side the octant allows).
 // orb_tab holds per octant and orbit kOrbTab entries:
-//   [0]      nb | neg << 4: nb the number of both-axes, neg set if a one-sign
-//            axis has the negative sign;
+//   [0]      nb | both << 4 | minus << 7: nb the number of both-axes, both
+//            their mask, minus the mask of the one-sign axes whose sign is
+//            negative;
 //   [1..8]   the 2^nb members in compact order j (member reflection code
 //            deposit(j, both) | minus), as offsets in the 13^3 local source
 //            grid of a tile, ((dx+3) 13 + dy+3) 13 + dz+3;

@@ -550,7 +550,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                     int nb = 0;
                     for (int ax = 0; ax < 3; ++ax) nb += (both >> ax) & 1;
                     int row[kOrbTab] = {};
-                    row[0] = nb | ((minus != 0) << 4);
+                    row[0] = nb | (both << 4) | (minus << 7);
                     for (int j = 0; j < (1 << nb); ++j) {
                         const int sg = deposit(j, both) | minus;
                         int d[3];
