@@ -966,7 +966,8 @@ __global__ void __launch_bounds__(RBW == 1 ? 64 * KB : 256) k_m2l_tile_kb(EvalAr
 // four consecutive coefficients of its target's member sources (the B
 // operand of four products, the operand layout arranged to match), forms the
 // transforms in registers and issues the products; loads run two steps
-// ahead.  No data is shared between waves, so the waves never wait for each
+// ahead.  The orbits come in groups of one both-axes mask (kOrbGroupMask), so
+// each gather loads exactly the members its orbit has.  No data is shared between waves, so the waves never wait for each
 // other.  Each orbit's products go to the result with Kahan compensation.
 template <int P, int MASK>
 __device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], const int __attribute__((ext_vector_type(4))) ek, int minus,
@@ -1092,14 +1093,17 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     const int tli = ((2 * (j >> 4)) * kOrbGrid + 2 * ((j >> 2) & 3)) * kOrbGrid + 2 * (j & 3);
     const char* mebase = reinterpret_cast<const char*>(A.me);
     const unsigned zoff = (unsigned)A.n_me * (unsigned)(KP * 4) + 16u * g;
-    // member row byte offsets of the orbit being gathered (absent members read
-    // the zero row: every step issues the same loads)
+    // member row byte offsets of the orbit being gathered, its first CNT
+    // members: the orbit groups fix the member count at compile time, and the
+    // last orbit of a group also gathers the first steps of the next group's
+    // first orbit, which has no more members (its absent ones read the zero row)
     unsigned off[8];
-    auto lorbit = [&](int q) {
+    auto lorbit = [&](auto cntc, int q) {
+        constexpr int CNT = decltype(cntc)::value;
         const int* row = s_tab + q * kOrbTab;
         const int nm = 1 << (__builtin_amdgcn_readfirstlane(row[0]) & 15);
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
+        for (int m = 0; m < CNT; ++m)
             off[m] = (m < nm) ? (unsigned)s_grid[tli + row[1 + m]] * (unsigned)(KP * 4) + 16u * g : zoff;
     };
     typedef int I4 __attribute__((ext_vector_type(4)));
@@ -1113,30 +1117,33 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb) as[rb] = *reinterpret_cast<const V4*>(Ao + (size_t)rb * (KB * 256));
     };
-    // gather step t: member sources and coefficient classes (and, with DA = 2,
-    // its operand slab)
-    auto load = [&](int t, V4 (&xs)[8], V4 (&as)[NRB], I4& ek) {
+    // gather step t: its first CNT member sources and the coefficient classes
+    // (and, with DA = 2, its operand slab)
+    auto load = [&](auto cntc, int t, V4 (&xs)[8], V4 (&as)[NRB], I4& ek) {
+        constexpr int CNT = decltype(cntc)::value;
         const int s = t % KB;
-        if (s == 0) lorbit(t / KB);
+        if (s == 0) lorbit(cntc, t / KB);
         if constexpr (DA == 2) load_a(t, as);
         const char* b = mebase + 64 * s;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) xs[m] = *reinterpret_cast<const V4*>(b + off[m]);
+        for (int m = 0; m < CNT; ++m) xs[m] = *reinterpret_cast<const V4*>(b + off[m]);
         ek = *reinterpret_cast<const I4*>(s_kcls + 16 * s + 4 * g);
     };
     V4 acc[NRB], tot[NRB], cmp[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) acc[rb] = tot[rb] = cmp[rb] = V4{0, 0, 0, 0};
-    load(0, xr[0], ra[0], er[0]);
-    load(1, xr[1], ra[DA - 1], er[1]);
+    typedef std::integral_constant<int, 1 << __builtin_popcount(kOrbGroupMask[0])> NM0;
+    load(NM0{}, 0, xr[0], ra[0], er[0]);
+    load(NM0{}, 1, xr[1], ra[DA - 1], er[1]);
     if constexpr (DA == 1) load_a(0, ra[0]);
     // one orbit: its KB steps with the transform specialised for its both-axes
     // (steps of one orbit form one straight code path, so the transforms of a
     // step can overlap the products of the previous one); step t uses register
     // slot t & 1 and refills it with step t + 2 (the last steps re-gather a
-    // valid step: a fixed load count)
+    // valid step)
     auto run = [&](auto maskc, auto parc, int q, int minus) {
         constexpr int MASK = decltype(maskc)::value, PAR = decltype(parc)::value;
+        typedef std::integral_constant<int, 1 << __builtin_popcount(MASK)> NM;
         const int t0 = q * KB;
         // (the scheduling fences keep each step's transforms after its own loads'
         // wait: hoisted into the previous step they would wait for the loads
@@ -1145,33 +1152,20 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         for (int s = 0; s < KB; s += 2) {
             orbit_step<P, MASK>(xr[PAR], er[PAR], minus, ra[A0], acc);
             if constexpr (DA == 1) load_a(min(t0 + s + 1, NIT - 1), ra[0]);
-            load(min(t0 + s + 2, NIT - 1), xr[PAR], ra[A0], er[PAR]);
+            load(NM{}, min(t0 + s + 2, NIT - 1), xr[PAR], ra[A0], er[PAR]);
             __builtin_amdgcn_sched_barrier(0);
             if (s + 1 < KB) {
                 orbit_step<P, MASK>(xr[PAR ^ 1], er[PAR ^ 1], minus, ra[A1], acc);
                 if constexpr (DA == 1) load_a(min(t0 + s + 2, NIT - 1), ra[0]);
-                load(min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[A1], er[PAR ^ 1]);
+                load(NM{}, min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[A1], er[PAR ^ 1]);
                 __builtin_amdgcn_sched_barrier(0);
             }
         }
     };
-    for (int q = 0; q < kOrbits; ++q) {
-        // both-axes and negative one-sign axes of the orbit
-        const int h = __builtin_amdgcn_readfirstlane(s_tab[q * kOrbTab]);
-        const int mask = (h >> 4) & 7, minus = (h >> 7) & 7;
-        const int par = (KB & 1) ? (q & 1) : 0;   // slot of the orbit's first step
-        typedef std::integral_constant<int, 0> Z;
-        typedef std::integral_constant<int, 1> O;
-#define LPB_RUN(M)                                                                       \
-    case M:                                                                              \
-        if ((KB & 1) && par) run(std::integral_constant<int, M>{}, O{}, q, minus);       \
-        else run(std::integral_constant<int, M>{}, Z{}, q, minus);                       \
-        break;
-        switch (mask) {
-            LPB_RUN(0) LPB_RUN(1) LPB_RUN(2) LPB_RUN(3) LPB_RUN(4) LPB_RUN(5) LPB_RUN(6) LPB_RUN(7)
-        default: break;
-        }
-#undef LPB_RUN
+    auto orbit = [&](auto maskc, auto parc, int q) {
+        // negative one-sign axes of the orbit
+        const int minus = (__builtin_amdgcn_readfirstlane(s_tab[q * kOrbTab]) >> 7) & 7;
+        run(maskc, parc, q, minus);
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb) {
             // class sign (-1)^|c & minus| of the orbit's product
@@ -1183,7 +1177,33 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
             tot[rb] = tk;
             acc[rb] = V4{0, 0, 0, 0};
         }
-    }
+    };
+    // the orbit groups in table order; with odd KB the first step of orbit q
+    // uses slot q & 1
+    auto group = [&](auto gic) {
+        constexpr int GI = decltype(gic)::value;
+        typedef std::integral_constant<int, kOrbGroupMask[GI]> MC;
+        const int q0 = GI * kOrbGroup;
+        if constexpr (KB & 1) {
+            constexpr int P0 = (GI * kOrbGroup) & 1;
+            for (int k = 0;; ++k) {
+                orbit(MC{}, std::integral_constant<int, P0>{}, q0 + 2 * k);
+                if (2 * k + 1 >= kOrbGroup) break;
+                orbit(MC{}, std::integral_constant<int, P0 ^ 1>{}, q0 + 2 * k + 1);
+            }
+        } else {
+            for (int k = 0; k < kOrbGroup; ++k) orbit(MC{}, std::integral_constant<int, 0>{}, q0 + k);
+        }
+    };
+    static_assert(kOrbits == 8 * kOrbGroup, "eight orbit groups");
+    group(std::integral_constant<int, 0>{});
+    group(std::integral_constant<int, 1>{});
+    group(std::integral_constant<int, 2>{});
+    group(std::integral_constant<int, 3>{});
+    group(std::integral_constant<int, 4>{});
+    group(std::integral_constant<int, 5>{});
+    group(std::integral_constant<int, 6>{});
+    group(std::integral_constant<int, 7>{});
     const int le = s_le[j];
     if (le < 0) return;
     // all row indices, then all current LE values, then the stores (loads in

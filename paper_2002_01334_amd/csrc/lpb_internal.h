@@ -43,8 +43,13 @@ constexpr int kXfRotate = 8;
 //            sign (-1)^|g & minus| in bit 31, g = deposit(j, both) |
 //            deposit(t, one-sign axes);
 //   [17]     the canonical offset code ((a+3) 7 + b+3) 7 + c+3.
+// The table lists the orbits of an octant in 8 groups of kOrbGroup, one per
+// both-axes mask (which does not depend on the octant), in the order
+// kOrbGroupMask: member counts 8, 4, 4, 4, 2, 2, 2, 1 never increase.
 constexpr int kOrbits = 56;
 constexpr int kOrbTab = 18;
+constexpr int kOrbGroup = 7;
+constexpr int kOrbGroupMask[8] = {7, 6, 5, 3, 4, 2, 1, 0};
 constexpr int kOrbGrid = 13;    // local source grid of a tile (4 parents x 2 + 6 halo per axis)
 constexpr int kOrbitMinP = 5;   // below, class padding outweighs the saving
 constexpr int kOrbitMaxP = 15;

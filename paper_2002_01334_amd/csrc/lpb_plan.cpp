@@ -524,6 +524,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.orb_tab.clear();
     for (int o = 0; o < 8; ++o) {
         const int oo[3] = {(o >> 2) & 1, (o >> 1) & 1, o & 1};
+        std::vector<std::pair<int, std::vector<int>>> rows;   // (group rank, row)
         for (int a = 0; a <= 3; ++a)
             for (int b = 0; b <= 3; ++b)
                 for (int c = 0; c <= 3; ++c) {
@@ -565,8 +566,16 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                             row[9 + j + (t << nb)] = (int)(((unsigned)par << 31) | ((unsigned)g << 12));
                         }
                     row[17] = ((a + 3) * 7 + (b + 3)) * 7 + (c + 3);
-                    P.orb_tab.insert(P.orb_tab.end(), row, row + kOrbTab);
+                    int rank = 0;
+                    while (kOrbGroupMask[rank] != both) ++rank;
+                    rows.emplace_back(rank, std::vector<int>(row, row + kOrbTab));
                 }
+        std::stable_sort(rows.begin(), rows.end(),
+                         [](const std::pair<int, std::vector<int>>& x, const std::pair<int, std::vector<int>>& y) { return x.first < y.first; });
+        for (size_t q = 0; q < rows.size(); ++q) {
+            if (rows.size() != (size_t)kOrbits || rows[q].first != (int)q / kOrbGroup) return "orbit groups: unexpected sizes";
+            P.orb_tab.insert(P.orb_tab.end(), rows[q].second.begin(), rows[q].second.end());
+        }
     }
     Staging S;
 
