@@ -13,10 +13,14 @@ operator generation).  The plain FP64 GPU path is timed beside it
 reported (rel_err_vs_fp64, gate 1e-6).
 
 Other workloads (--workload): clustered (1e5 charges per layer, half of them
-Gaussian with sigma 0.1 about the cube centre; default p = 6) and batch (256
+Gaussian with sigma 0.1 about the cube centre; default p = 6), batch (256
 independent systems of uneven sizes and random media evaluated by one batched
-call; default p = 8).  --p overrides the order (e.g. 15 on the default
-workload).
+call; default p = 8) and paper (the paper's own test problem: eps = (1, 8.6,
+20.5), lambda = (1.2, 0.5, 2.1), charges uniform in the three P_4-shaped
+bodies, --charges total, default 2,861,288, the largest count of its timing
+table; default p = 5, the table's order; the table's 36-core CPU time for the
+same count is quoted as context).  --p overrides the order (e.g. 15 on the
+default workload).
 """
 from __future__ import annotations
 
@@ -35,8 +39,11 @@ sys.path.insert(0, ROOT)
 # peaks (MI355X, published): HBM 8 TB/s; vector FP32 157.3 TFLOP/s; vector FP64 78.6 TFLOP/s
 PEAK_FP32 = 157.3
 PEAK_FP64 = 78.6
-# algorithmic flops per unit of work of each stage (see DESIGN.md)
+# algorithmic flops per unit of work of each stage
 FLOPS_PER_P2P_PAIR = 20.0
+# the paper's timing table (Table 1), 36 cores: N -> (free-space s, reaction s)
+PAPER_TABLE1 = {618_256: (2.042, 1.639), 1_128_556: (4.308, 4.459), 1_862_568: (14.94, 6.104),
+                2_861_288: (15.21, 7.673)}
 
 
 def err2_per_layer(a, b, layer):
@@ -166,10 +173,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=("uniform", "clustered", "batch"), default="uniform",
+    ap.add_argument("--workload", choices=("uniform", "clustered", "batch", "paper"), default="uniform",
                     help="uniform: 1e6 charges per layer in unit cubes (default); clustered: 1e5 per layer, half "
-                         "Gaussian (sigma 0.1); batch: 256 independent systems of uneven sizes")
+                         "Gaussian (sigma 0.1); batch: 256 independent systems of uneven sizes; paper: the paper's "
+                         "test problem (P_4-shaped bodies, its media)")
     ap.add_argument("--per-layer", type=int, default=None)
+    ap.add_argument("--charges", type=int, default=2_861_288, help="total charges of the paper workload")
     ap.add_argument("--systems", type=int, default=256)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--leaf-cap", type=int, default=50)
@@ -181,12 +190,13 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the path would shard by "
-              "assigning independent FMMs to GPUs, see DESIGN.md", file=sys.stderr)
+              "assigning independent FMMs (and systems of a batch) to GPUs and summing the output slots with "
+              "one reduce", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
-    p = args.p if args.p is not None else {"uniform": 10, "clustered": 6, "batch": 8}[wl]
+    p = args.p if args.p is not None else {"uniform": 10, "clustered": 6, "batch": 8, "paper": 5}[wl]
     per_layer = args.per_layer if args.per_layer is not None else {"uniform": 1_000_000, "clustered": 100_000,
-                                                                   "batch": 0}[wl]
+                                                                   "batch": 0, "paper": 0}[wl]
 
     import torch
 
@@ -223,11 +233,17 @@ def main():
         sample_what = f"the first {len(sample)} systems of the batch"
     else:
         clustered = wl == "clustered"
-        prob = inputs.three_layer(per_layer, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)
+        if wl == "paper":
+            prob = inputs.paper_domains(args.charges, seed=0)
+            counts = "+".join(str(int((prob.layer == l).sum())) for l in range(3))
+            desc = (f"the paper's test problem: eps=(1,8.6,20.5) lambda=(1.2,0.5,2.1) d=(0,-1.2), {counts} charges "
+                    "uniform in the P_4-shaped bodies (a=0.1,0.15,0.05; centres z=0.6,-0.6,-1.8), q~U[-1,1], seed 0")
+        else:
+            prob = inputs.three_layer(per_layer, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)
+            desc = (f"3-layer medium eps=(1,2,4) lambda=(1.2,1.5,2.0) d=(0,-1.2), {per_layer}/layer "
+                    + ("50% uniform + 50% Gaussian (sigma 0.1) in unit cubes" if clustered else "uniform unit cubes")
+                    + ", q~U[-1,1], seed 0")
         ntot = prob.n
-        desc = (f"3-layer medium eps=(1,2,4) lambda=(1.2,1.5,2.0) d=(0,-1.2), {per_layer}/layer "
-                + ("50% uniform + 50% Gaussian (sigma 0.1) in unit cubes" if clustered else "uniform unit cubes")
-                + ", q~U[-1,1], seed 0")
         print(f"[bench] workload: 3 layers, {ntot} charges, p={p}", file=sys.stderr, flush=True)
         mixed = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup)
         print(f"[bench] mixed: {mixed['eval_ms']:.2f} ms/eval, stages {mixed['stage_ms']}", file=sys.stderr, flush=True)
@@ -236,8 +252,12 @@ def main():
         rel_layers = err2_per_layer(mixed["phi"], fp64["phi"], prob.layer)
         rel = rel_layers
         cs = args.cpu_sample or (200_000 if not clustered else 100_000)
-        sample = [inputs.three_layer(cs, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)]
-        sample_what = f"the same recipe at {cs} charges per layer"
+        if wl == "paper":
+            sample = [inputs.paper_domains(3 * cs, seed=0)]
+            sample_what = f"the same recipe at {3 * cs} charges"
+        else:
+            sample = [inputs.three_layer(cs, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)]
+            sample_what = f"the same recipe at {cs} charges per layer"
 
     st = mixed["stats"]
     K = (p + 1) ** 2
@@ -298,6 +318,12 @@ def main():
     }
     if rel_layers is not None:
         line["rel_err_vs_fp64_per_layer"] = rel_layers
+    if wl == "paper" and ntot in PAPER_TABLE1:
+        free_s, react_s = PAPER_TABLE1[ntot]
+        line["paper_context"] = {
+            "what": "the paper's timing table, 36 cores of 2x Xeon E5-2699 v4 (DASHMM, CPU), same N and p = 5; "
+                    "other hardware, context only",
+            "free_s": free_s, "reaction_s": react_s, "charges_per_s": ntot / (free_s + react_s)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sample, p, args.leaf_cap, sample_what)
     print(json.dumps(line), flush=True)

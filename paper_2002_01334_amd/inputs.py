@@ -149,6 +149,66 @@ def batch_system(k: int, nmin: float = 1e3, nmax: float = 5e4) -> LayeredProblem
                           np.concatenate(zs), np.concatenate(qs), np.concatenate(ls))
 
 
+# The paper's own test problem (Sec. 4): three layers with interfaces z = 0 and
+# -1.2, eps = (1, 8.6, 20.5), lambda = (1.2, 0.5, 2.1); charges uniform inside
+# the bodies r(theta) = 0.5 - a + (a/8)(35 cos^4 - 30 cos^2 + 3)(theta) (a
+# P_4-modulated sphere of polar radius 0.5) with a = 0.1, 0.15, 0.05, shifted
+# to the centres (0, 0, 0.6), (0, 0, -0.6), (0, 0, -1.8).
+PAPER_EPS = (1.0, 8.6, 20.5)
+PAPER_LAM = (1.2, 0.5, 2.1)
+PAPER_A = (0.1, 0.15, 0.05)
+PAPER_ZC = (0.6, -0.6, -1.8)
+# total charge counts of the paper's timing table
+PAPER_N = (618_256, 1_128_556, 1_862_568, 2_861_288)
+
+
+def p4_radius(a: float, c):
+    """Radius of the body at cos(theta) = c."""
+    c2 = np.asarray(c, float) ** 2
+    return 0.5 - a + (a / 8.0) * (35.0 * c2 * c2 - 30.0 * c2 + 3.0)
+
+
+def p4_volume(a: float) -> float:
+    """Volume (2 pi / 3) int_{-1}^{1} r(c)^3 dc (a polynomial of degree 12 in
+    c, exact with 8 Gauss-Legendre nodes; 16 are used)."""
+    c, w = np.polynomial.legendre.leggauss(16)
+    return float(2.0 * np.pi / 3.0 * np.sum(w * p4_radius(a, c) ** 3))
+
+
+def paper_domains(n_total=None, seed: int = 0, per_layer=None) -> LayeredProblem:
+    """Charges of the paper's test problem: n_total split over the layers in
+    proportion to the body volumes (equal density; the remainder goes to
+    layer 0), or the per-layer counts given.  Candidates uniform in the cube
+    of side 1 about each centre (draws x, y, z, q per candidate, layers in
+    order from one stream) are kept when inside the body; q ~ U[-1, 1] (the
+    paper does not state the charges)."""
+    if per_layer is None:
+        vol = [p4_volume(a) for a in PAPER_A]
+        per_layer = [int(n_total * v / sum(vol)) for v in vol]
+        per_layer[0] += n_total - sum(per_layer)
+    rng = SplitMix64(seed)
+    xs, ys, zs, qs, ls = [], [], [], [], []
+    for l, n in enumerate(per_layer):
+        a, zc = PAPER_A[l], PAPER_ZC[l]
+        frac = p4_volume(a)             # the cube has volume 1
+        out = np.empty((n, 4))
+        filled = 0
+        while filled < n:
+            need = n - filled
+            m = int(need / frac * 1.05) + 16
+            u = rng.uniform(4 * m).reshape(m, 4) - 0.5
+            rho = np.sqrt(u[:, 0] ** 2 + u[:, 1] ** 2 + u[:, 2] ** 2)
+            ok = rho < p4_radius(a, u[:, 2] / np.maximum(rho, 1e-300))
+            acc = u[ok][:need]
+            out[filled:filled + len(acc)] = acc
+            filled += len(acc)
+        xs.append(out[:, 0]); ys.append(out[:, 1]); zs.append(zc + out[:, 2]); qs.append(2.0 * out[:, 3])
+        ls.append(np.full(n, l, np.int32))
+    return LayeredProblem(np.array(PAPER_EPS), np.array(PAPER_LAM), np.array(D3, float),
+                          np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(qs),
+                          np.concatenate(ls))
+
+
 def sample_targets(prob: LayeredProblem, per_layer: int, seed: int = 1) -> np.ndarray:
     """per_layer distinct charge indices from each layer (sorted)."""
     rng = SplitMix64(seed)

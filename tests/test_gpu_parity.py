@@ -1,6 +1,6 @@
 """GPU parity tests: the HIP path through the C ABI against the CPU oracle.
 
-Bars (derived in the design doc): FP64 GPU vs oracle FMM on the same tree, relative
+Bars (from the arithmetic of each path): FP64 GPU vs oracle FMM on the same tree, relative
 l2 error per layer and per output slot <= 1e-10; tree structure bit-exact;
 GPU FP64 vs oracle direct sum within the truncation error of p; mixed
 precision vs FP64 <= 1e-6; batched vs single-system FP64 bit-identical.
@@ -297,6 +297,50 @@ def test_c3_clustered_mixed_vs_fp64_and_direct(lpb, c3, p, tol):
     print(f"C3 p={p}: mixed vs FP64 {e_mixed:.3e}, FP64 vs direct (sampled) {e_direct:.3e}")
     assert e_mixed <= 1e-6
     assert e_direct <= tol
+
+
+@pytest.fixture(scope="module")
+def paper_small():
+    """The paper's test problem (Sec. 4) at its accuracy-test size, 912 + 640 +
+    1296 charges in the P_4-shaped bodies with its media, and the oracle direct
+    sum at 16 sampled targets per layer."""
+    prob = inputs.paper_domains(per_layer=(912, 640, 1296), seed=0)
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    idx = inputs.sample_targets(prob, 16, seed=1)
+    return prob, ly, idx, O.direct_sum(ly, prob.x, prob.y, prob.z, prob.q, targets=idx)
+
+
+def test_paper_problem_oracle_fmm_convergence_and_mixed(lpb, paper_small):
+    prob, ly, idx, direct = paper_small
+    # p = 5, the order of the paper's timing table: FP64 equals the oracle FMM on the same tree
+    ctx, phi5 = run(lpb, prob, 5, 50)
+    ctx.close()
+    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 5, leaf_cap=50)
+    assert err2(phi5, ref, prob.layer) <= 1e-10
+    ctx, phi32 = run(lpb, prob, 5, 50, precision=lpb.LPB_MIXED)
+    ctx.close()
+    assert err2(phi32, phi5, prob.layer) <= 1e-6
+    # truncation error against the direct sum falls with p (deeper tree: leaf cap 8)
+    errs = []
+    for p in (3, 5, 8, 10):
+        ctx, phi = run(lpb, prob, p, 8)
+        ctx.close()
+        errs.append(err2(phi[idx], direct, prob.layer[idx]))
+    print("paper problem, FP64 vs direct (sampled) at p = 3, 5, 8, 10:", ["%.2e" % e for e in errs])
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert errs[0] < 1e-2 and errs[-1] < 1e-5 and errs[-1] < errs[0] / 100, errs
+
+
+def test_paper_problem_full_size_mixed_vs_fp64(lpb):
+    """The paper's largest timing-table count, 2,861,288 charges, at p = 5."""
+    prob = inputs.paper_domains(2_861_288, seed=0)
+    ctx, phi64 = run(lpb, prob, 5, 50, device=True)
+    ctx.close()
+    ctx, phi32 = run(lpb, prob, 5, 50, precision=lpb.LPB_MIXED, device=True)
+    ctx.close()
+    e = err2(phi32, phi64, prob.layer)
+    print(f"paper problem 2,861,288 charges p=5: mixed vs FP64 {e:.3e}")
+    assert e <= 1e-6
 
 
 def test_c4_batch_mixed_vs_fp64_per_system():
