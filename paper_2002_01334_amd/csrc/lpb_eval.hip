@@ -1091,7 +1091,9 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     __syncthreads();
     const int cb = tid >> 6, g = l >> 4, jj = l & 15, j = 16 * cb + jj;
     const int tli = ((2 * (j >> 4)) * kOrbGrid + 2 * ((j >> 2) & 3)) * kOrbGrid + 2 * (j & 3);
-    const char* mebase = reinterpret_cast<const char*>(A.me);
+    // the expansions (with the zero row) span under 2^32 bytes: the launch checks it
+    const __amdgpu_buffer_rsrc_t rme =
+        __builtin_amdgcn_make_buffer_rsrc(A.me, 0, (int)((unsigned)(A.n_me + 1) * (unsigned)(KP * 4)), 0x00020000);
     const unsigned zoff = (unsigned)A.n_me * (unsigned)(KP * 4) + 16u * g;
     // member row byte offsets of the orbit being gathered, its first CNT
     // members: the orbit groups fix the member count at compile time, and the
@@ -1112,10 +1114,17 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     constexpr int DA = (NRB <= 9) ? 2 : 1;
     V4 xr[2][8], ra[DA][NRB];
     I4 er[2];
+    // operand and member gathers are buffer loads: wave-uniform bases and
+    // offsets in scalar registers, one fixed 32-bit lane offset, so a gather
+    // costs no vector address arithmetic
+    const unsigned lane16 = 16u * l;
     auto load_a = [&](int t, V4 (&as)[NRB]) {
-        const float* Ao = A.pool_orb + (size_t)s_aoff[t / KB] * OPSZ + (size_t)(t % KB) * 256 + 4 * l;
+        const int q = t / KB, s = t % KB;
+        const float* Ao = A.pool_orb + (size_t)__builtin_amdgcn_readfirstlane(s_aoff[q]) * OPSZ;
+        const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Ao), 0, OPSZ * 4, 0x00020000);
 #pragma unroll
-        for (int rb = 0; rb < NRB; ++rb) as[rb] = *reinterpret_cast<const V4*>(Ao + (size_t)rb * (KB * 256));
+        for (int rb = 0; rb < NRB; ++rb)
+            as[rb] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(ra_, lane16, (rb * KB + s) * 1024, 0));
     };
     // gather step t: its first CNT member sources and the coefficient classes
     // (and, with DA = 2, its operand slab)
@@ -1124,9 +1133,8 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         const int s = t % KB;
         if (s == 0) lorbit(cntc, t / KB);
         if constexpr (DA == 2) load_a(t, as);
-        const char* b = mebase + 64 * s;
 #pragma unroll
-        for (int m = 0; m < CNT; ++m) xs[m] = *reinterpret_cast<const V4*>(b + off[m]);
+        for (int m = 0; m < CNT; ++m) xs[m] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rme, off[m], 64 * s, 0));
         ek = *reinterpret_cast<const I4*>(s_kcls + 16 * s + 4 * g);
     };
     V4 acc[NRB], tot[NRB], cmp[NRB];
