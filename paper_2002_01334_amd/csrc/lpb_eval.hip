@@ -506,22 +506,26 @@ __device__ inline void solid_harmonics(float x, float y, float z, F&& f)
     }
 }
 
+// Two leaves per 64-lane block (a leaf holds about half a wave of sources):
+// half h = lane >> 5 takes leaf 2 blockIdx.x + h, its sources 32 at a time;
+// lane i then sums coefficient c0 + i of both halves' rows.
 template <int P>
-__global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A)
+__global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A, int n_leaves)
 {
     constexpr int K = (P + 1) * (P + 1);
     __shared__ float red[64][65];
-    const int leaf = A.p2m_leaves[blockIdx.x];
-    const int me = A.sl_me[leaf];
+    const int lane = threadIdx.x, h = lane >> 5, hl = lane & 31;
+    const int w = 2 * blockIdx.x + h;
+    const bool on = w < n_leaves;
+    const int leaf = on ? A.p2m_leaves[w] : A.p2m_leaves[2 * blockIdx.x];
     const FmmDev& F = A.fmm[A.sl_fmm[leaf]];
     const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
-    const int lane = threadIdx.x;
-    const int s0 = A.sl_start[leaf], s1 = A.sl_start[leaf + 1];
+    const int s0 = A.sl_start[leaf], s1 = on ? A.sl_start[leaf + 1] : s0;
     const float hinv = (float)(1.0 / A.sl_h[leaf]);
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.f;
-    for (int j = s0 + lane; j < s1; j += 64) {
+    for (int j = s0 + hl; j < s1; j += 32) {
         const float ux = A.s_ux[j], uy = A.s_uy[j], uz = A.s_uz[j];
         const double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         float g[P + 1];
@@ -533,6 +537,8 @@ __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A)
                                if (m > 0) acc[iim(n, m)] -= g[n] * im;
                            });
     }
+    const int w1 = 2 * blockIdx.x + 1;
+    const int me0 = A.sl_me[A.p2m_leaves[2 * blockIdx.x]], me1 = w1 < n_leaves ? A.sl_me[A.p2m_leaves[w1]] : -1;
 #pragma unroll
     for (int c0 = 0; c0 < K; c0 += 64) {
 #pragma unroll
@@ -540,29 +546,42 @@ __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A)
             if (c0 + i < K) red[i][lane] = acc[c0 + i];
         __syncthreads();
         if (c0 + lane < K) {
-            float t = 0.f;
+            float t0 = 0.f, t1 = 0.f;
 #pragma unroll 16
-            for (int jj = 0; jj < 64; ++jj) t += red[lane][jj];
-            A.me[(size_t)me * A.KP + c0 + lane] = t;
+            for (int jj = 0; jj < 32; ++jj) {
+                t0 += red[lane][jj];
+                t1 += red[lane][32 + jj];
+            }
+            A.me[(size_t)me0 * A.KP + c0 + lane] = t0;
+            if (me1 >= 0) A.me[(size_t)me1 * A.KP + c0 + lane] = t1;
         }
         __syncthreads();
     }
 }
 
+// Two leaves per 64-lane block (a leaf holds about half a wave of targets):
+// half h = lane >> 5 takes leaf 2 blockIdx.x + h, its targets 32 at a time.
 template <int P>
-__global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A)
+__global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A, int n_leaves)
 {
     constexpr int K = (P + 1) * (P + 1);
-    __shared__ float Ls[K];   // the leaf's local expansion, read at uniform addresses
-    const int leaf = A.l2p_leaves[blockIdx.x];
-    const int le = A.tl_le[leaf];
+    __shared__ float Ls[2][K];   // the leaves' local expansions, read at half-uniform addresses
+    const int h = threadIdx.x >> 5, hl = threadIdx.x & 31;
+    const int w = 2 * blockIdx.x + h;
+    const bool on = w < n_leaves;
+    const int leaf = on ? A.l2p_leaves[w] : 0;
+    if (on) {
+        const int le = A.tl_le[leaf];
+        for (int k = hl; k < K; k += 32) Ls[h][k] = A.le[(size_t)le * A.KP + k];
+    }
+    __syncthreads();
+    if (!on) return;
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double* __restrict__ ith = A.ith_t + ((size_t)A.tl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
-    for (int k = threadIdx.x; k < K; k += 64) Ls[k] = A.le[(size_t)le * A.KP + k];
-    __syncthreads();
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const float hinv = (float)(1.0 / A.tl_h[leaf]);
-    for (int j = t0 + threadIdx.x; j < t1; j += 64) {
+    const float* L = Ls[h];
+    for (int j = t0 + hl; j < t1; j += 32) {
         const float ux = A.t_ux[j], uy = A.t_uy[j], uz = A.t_uz[j];
         const double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         float g[P + 1];
@@ -571,8 +590,8 @@ __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A)
         float phi = 0.f;
         solid_harmonics<P>(ux * hinv, uy * hinv, uz * hinv,
                            [&](int n, int m, float re, float im) {
-                               if (m == 0) phi += g[n] * (Ls[ire(n, 0)] * re);
-                               else phi += 2.f * g[n] * (Ls[ire(n, m)] * re - Ls[iim(n, m)] * im);
+                               if (m == 0) phi += g[n] * (L[ire(n, 0)] * re);
+                               else phi += 2.f * g[n] * (L[ire(n, m)] * re - L[iim(n, m)] * im);
                            });
         A.parts[A.t_out[j]] = (double)phi * F.far_factor;
     }
@@ -1654,7 +1673,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
         if constexpr (sizeof(T) == 4) {
             if (p_fixed) {
 #define LPB_P2M(PP) \
-    case PP: hipLaunchKernelGGL(k_p2m_p<PP>, dim3(S.n_p2m), dim3(64), 0, st, A); break;
+    case PP: hipLaunchKernelGGL(k_p2m_p<PP>, dim3((S.n_p2m + 1) / 2), dim3(64), 0, st, A, S.n_p2m); break;
                 switch (p) {
                     LPB_P2M(2) LPB_P2M(3) LPB_P2M(4) LPB_P2M(5) LPB_P2M(6) LPB_P2M(7) LPB_P2M(8) LPB_P2M(9)
                     LPB_P2M(10) LPB_P2M(11) LPB_P2M(12) LPB_P2M(13) LPB_P2M(14) LPB_P2M(15)
@@ -1686,7 +1705,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
         if constexpr (sizeof(T) == 4) {
             if (p_fixed) {
 #define LPB_L2P(PP) \
-    case PP: hipLaunchKernelGGL(k_l2p_p<PP>, dim3(S.n_l2p), dim3(64), 0, st, A); break;
+    case PP: hipLaunchKernelGGL(k_l2p_p<PP>, dim3((S.n_l2p + 1) / 2), dim3(64), 0, st, A, S.n_l2p); break;
                 switch (p) {
                     LPB_L2P(2) LPB_L2P(3) LPB_L2P(4) LPB_L2P(5) LPB_L2P(6) LPB_L2P(7) LPB_L2P(8) LPB_L2P(9)
                     LPB_L2P(10) LPB_L2P(11) LPB_L2P(12) LPB_L2P(13) LPB_L2P(14) LPB_L2P(15)
