@@ -1450,7 +1450,7 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
 // difference of two close points keeps its relative accuracy: FP32 positions
 // alone would lose eps32 * h / r of it for a pair at distance r in a leaf of
 // side h.  The first U-list leaf is the target's own (the r = 0 self pair is
-// excluded there only); terms are summed in groups of four and the group
+// excluded there only); terms are summed in groups of eight or four and the group
 // sums are added with Kahan compensation.
 // positions are pre-scaled by s = lambda log2(e): with r' = s r the term is
 // q e^{-lambda r} / r = s q 2^{-r'} / r' (the factor s is applied once per
@@ -1459,8 +1459,8 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
 // The hi parts alone (offsets below 1.5 h per axis, h the leaf side) give a
 // distance to within 3.1e-7 h, i.e. 5e-6 of r at worst for r >= h/16, where
 // such rounding errors of independent pairs largely cancel in the sum; only a
-// pair closer than h/16 takes the lo parts.  Sources are taken four at a time: hi-part distances first, and the
-// lo parts only in the (rare) groups holding such a pair.
+// pair closer than h/16 takes the lo parts.  Sources are taken eight (then four) at a time: hi-part distances
+// first, and the lo parts only in the (rare) groups holding such a pair.
 __device__ inline float p2p_term32(float w, float r2)
 {
     const float ri = __frsqrt_rn(r2);
@@ -1547,6 +1547,26 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
                     if (r2 > 0.f) kahan(p2p_term32(sh[jj].w, r2));
                 }
                 int jj = ns + ((half - ns) & 1);
+                for (; jj + 14 < n; jj += 16) {
+                    float w[8], r2[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const float4 hs = sh[jj + 2 * u];
+                        const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
+                        w[u] = hs.w;
+                        r2[u] = dx * dx + dy * dy + dz * dz;
+                    }
+                    const float mn = fminf(fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3])),
+                                           fminf(fminf(r2[4], r2[5]), fminf(r2[6], r2[7])));
+                    if (mn < thr2) {
+#pragma unroll
+                        for (int u = 0; u < 8; ++u) r2[u] = full_r2(jj + 2 * u);
+                    }
+                    kahan(((p2p_term32(w[0], r2[0]) + p2p_term32(w[1], r2[1])) +
+                           (p2p_term32(w[2], r2[2]) + p2p_term32(w[3], r2[3]))) +
+                          ((p2p_term32(w[4], r2[4]) + p2p_term32(w[5], r2[5])) +
+                           (p2p_term32(w[6], r2[6]) + p2p_term32(w[7], r2[7]))));
+                }
                 for (; jj + 6 < n; jj += 8) {
                     float w[4], r2[4];
 #pragma unroll
