@@ -1546,12 +1546,16 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
                     const float r2 = full_r2(jj);
                     if (r2 > 0.f) kahan(p2p_term32(sh[jj].w, r2));
                 }
-                int jj = ns + ((half - ns) & 1);
-                for (; jj + 14 < n; jj += 16) {
+                // the main loop's counter is wave-uniform (each half starts at
+                // its own parity within it); the tails continue per lane
+                const int par = (half - ns) & 1;
+                const float4* shp = sh + par;
+                int ju = ns;
+                for (; ju + 15 < n; ju += 16) {
                     float w[8], r2[8];
 #pragma unroll
                     for (int u = 0; u < 8; ++u) {
-                        const float4 hs = sh[jj + 2 * u];
+                        const float4 hs = shp[ju + 2 * u];
                         const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
                         w[u] = hs.w;
                         r2[u] = dx * dx + dy * dy + dz * dz;
@@ -1560,13 +1564,14 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
                                            fminf(fminf(r2[4], r2[5]), fminf(r2[6], r2[7])));
                     if (mn < thr2) {
 #pragma unroll
-                        for (int u = 0; u < 8; ++u) r2[u] = full_r2(jj + 2 * u);
+                        for (int u = 0; u < 8; ++u) r2[u] = full_r2(ju + par + 2 * u);
                     }
                     kahan(((p2p_term32(w[0], r2[0]) + p2p_term32(w[1], r2[1])) +
                            (p2p_term32(w[2], r2[2]) + p2p_term32(w[3], r2[3]))) +
                           ((p2p_term32(w[4], r2[4]) + p2p_term32(w[5], r2[5])) +
                            (p2p_term32(w[6], r2[6]) + p2p_term32(w[7], r2[7]))));
                 }
+                int jj = ju + par;
                 for (; jj + 6 < n; jj += 8) {
                     float w[4], r2[4];
 #pragma unroll
