@@ -781,8 +781,18 @@ __global__ void k_m2l_reduce(EvalArgs<T> A)
     const int le = A.m2l_boxes[blockIdx.x];
     const int k0 = A.m2l_ptr[le], k1 = A.m2l_ptr[le + 1];
     for (int row = threadIdx.x; row < A.K; row += blockDim.x) {
+        // four rows' loads in flight at a time; the sum keeps list order
         T s = T(0);
-        for (int k = k0; k < k1; ++k) s += A.m2l_scratch[(size_t)k * A.KP + row];
+        int k = k0;
+        for (; k + 4 <= k1; k += 4) {
+            const T a0 = A.m2l_scratch[(size_t)k * A.KP + row], a1 = A.m2l_scratch[(size_t)(k + 1) * A.KP + row],
+                    a2 = A.m2l_scratch[(size_t)(k + 2) * A.KP + row], a3 = A.m2l_scratch[(size_t)(k + 3) * A.KP + row];
+            s += a0;
+            s += a1;
+            s += a2;
+            s += a3;
+        }
+        for (; k < k1; ++k) s += A.m2l_scratch[(size_t)k * A.KP + row];
         A.le[(size_t)le * A.KP + row] += s;
     }
 }
