@@ -207,8 +207,8 @@ __device__ inline int mfma_row(float, int l, int r) { return 4 * (l >> 4) + r; }
 __device__ inline int mfma_row(double, int l, int r) { return (l >> 4) + 4 * r; }
 
 // acc[rb][cb] = A (rows 16 (w RB + rb) ..) x B (LDS, columns 16 cb ..), with
-// A in the swizzled operand layout (the next 16-column slab of A loads while
-// the current one is multiplied)
+// A in the swizzled operand layout (16-column slabs of A load two slabs
+// ahead of the one being multiplied)
 template <typename T, int RB, int CB>
 __device__ __attribute__((always_inline)) inline void mma_block(const T* __restrict__ Aw, const T* Bs, int NTP, int KB, int w, int l,
                                  typename Vec4<T>::type (&acc)[RB][CB])
@@ -219,21 +219,14 @@ __device__ __attribute__((always_inline)) inline void mma_block(const T* __restr
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
     // row blocks past KB repeat the last one (their rows are >= K, never stored)
-    V4 an[RB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        int rbg = min(w * RB + rb, KB - 1);
-        an[rb] = *reinterpret_cast<const V4*>(Aw + ((size_t)rbg * KB * 64 + l) * 4);
-    }
-    for (int s4 = 0; s4 < KB; ++s4) {
-        V4 a4[RB];
-        const int s4n = min(s4 + 1, KB - 1);
+    auto load = [&](V4 (&a)[RB], int s4) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            a4[rb] = an[rb];
-            int rbg = min(w * RB + rb, KB - 1);
-            an[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + s4n) * 64 + l) * 4);
+            const int rbg = min(w * RB + rb, KB - 1);
+            a[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + min(s4, KB - 1)) * 64 + l) * 4);
         }
+    };
+    auto slab = [&](const V4 (&a4)[RB], int s4) {
 #pragma unroll
         for (int ss = 0; ss < 4; ++ss) {
             const int kk = 16 * s4 + 4 * ss + (l >> 4);
@@ -244,6 +237,22 @@ __device__ __attribute__((always_inline)) inline void mma_block(const T* __restr
             for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
                 for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
+        }
+    };
+    V4 a0[RB], a1[RB];
+    load(a0, 0);
+    load(a1, 1);
+    for (int s4 = 0; s4 < KB; s4 += 2) {
+        V4 c[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) c[rb] = a0[rb];
+        load(a0, s4 + 2);
+        slab(c, s4);
+        if (s4 + 1 < KB) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) c[rb] = a1[rb];
+            load(a1, s4 + 3);
+            slab(c, s4 + 1);
         }
     }
 }
