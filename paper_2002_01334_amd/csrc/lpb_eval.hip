@@ -425,11 +425,11 @@ __global__ void __launch_bounds__(256) k_m2l_tile(EvalArgs<T> A)
 }
 
 // ---------------------------------------------------------------------------
-// P2M and L2P with the order P fixed at compile time (FP32 path, 2 <= P <= 12):
-// one lane per charge, the Bessel ratios and every solid harmonic in
-// registers (fully unrolled recurrences, table coefficients read at uniform
-// addresses); P2M reduces the lanes' coefficient rows through LDS once per
-// leaf, 64 coefficients at a time.
+// P2M and L2P with the order P fixed at compile time (FP32 path, 2 <= P <= 15):
+// one lane per charge, half a wave per leaf, the Bessel ratios and every
+// solid harmonic in registers (fully unrolled recurrences, table coefficients
+// read at uniform addresses); P2M reduces the lanes' coefficient rows through
+// LDS once per pair of leaves, 64 coefficients at a time.
 template <int P>
 __device__ inline void bessel_ratio_reg(double t, const double* __restrict__ tb, const double* __restrict__ ith, float scale,
                                         float (&g)[P + 1])
