@@ -657,7 +657,9 @@ __device__ inline void column_xform(T* Bs, int NTP, int p, int K, int KP, int co
         }
 }
 
-template <typename T, int RB, bool XF>
+// RBF = ceil(KB / 4): the row blocks per wave of a whole item, which also
+// sizes the source staging; GY blocks along y split them (RB per wave each).
+template <typename T, int RBF, bool XF, int GY>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
                                                  const int* __restrict__ dst, int wbase, int mode, int K, int KP,
@@ -666,7 +668,9 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
                                                  const T* __restrict__ refl, int p)
 {
     typedef typename Vec4<T>::type V4;
-    constexpr int NT = 64, CB = 4, GMAX = 4 * RB;
+    static_assert(GY == 1 || !XF, "results with a transform need whole columns");
+    constexpr int RB = (RBF + GY - 1) / GY;
+    constexpr int NT = 64, CB = 4, GMAX = 4 * RBF;
     constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);
     extern __shared__ unsigned char smem_raw[];
     T* Bs = reinterpret_cast<T*>(smem_raw);   // [KP][NTP]
@@ -674,6 +678,9 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     const int wi = wbase + sched_index(blockIdx.x, gridDim.x, sched);
     const int t0 = term_ptr[wi], t1 = term_ptr[wi + 1];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    // row-block group of this wave: blocks of a work item along y split the
+    // output rows (every block stages all of the sources)
+    const int wy = (GY > 1 ? (int)blockIdx.y * 4 : 0) + w;
     const int gj = tid >> 2, gpart = tid & 3;
     V4 acc[RB][CB], tot[RB][CB], cmp[RB][CB];
 #pragma unroll
@@ -709,7 +716,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
         }
         const T* Aw = pool_swz + (size_t)term_op[t] * KP * KP;
         if (t + 1 < t1) fetch(t + 1);
-        mma_block<T, RB, CB>(Aw, Bs, NTP, KB, w, l, acc);
+        mma_block<T, RB, CB>(Aw, Bs, NTP, KB, wy, l, acc);
         accumulate<T, RB, CB>(acc, tot, cmp);
     }
     if (XF) {
@@ -738,7 +745,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb) {
-        int rbg = w * RB + rb;
+        int rbg = wy * RB + rb;
         if (rbg >= KB) continue;
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) {
@@ -759,11 +766,22 @@ template <typename T, bool XF>
 static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, int zrow, T* out, int mode, hipStream_t st)
 {
     if (w1 <= w0) return;
-    const int KB = A.KP / 16, RB = (KB + 3) / 4;
+    // few work items (coarse levels) leave most CUs idle: split the output
+    // row blocks of each item over two blocks (y), each staging the sources
+    const int KB = A.KP / 16, n = w1 - w0;
+    const int RB = (KB + 3) / 4;
+    const int gy = (!XF && n < 512 && RB >= 2) ? 2 : 1;
     const size_t sm = sizeof(T) * ((size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8)) + (XF ? (size_t)(A.p + 1) * 128 : 0));
-    dim3 g(w1 - w0), b(256);
-#define LPB_BATCHED(R)                                                                                                    \
-    hipLaunchKernelGGL((k_batched<T, R, XF>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, \
+    dim3 g(n, gy), b(256);
+#define LPB_BATCHED(R)                                                                                                      \
+    if constexpr (!XF) {                                                                                                    \
+        if (gy == 2) {                                                                                                      \
+            hipLaunchKernelGGL((k_batched<T, R, XF, 2>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, \
+                               w0, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.bw_xa, A.refl_sign, A.p);   \
+            break;                                                                                                          \
+        }                                                                                                                   \
+    }                                                                                                                       \
+    hipLaunchKernelGGL((k_batched<T, R, XF, 1>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, \
                        A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.bw_xa, A.refl_sign, A.p)
     switch (RB) {
     case 1: LPB_BATCHED(1); break;
