@@ -1504,6 +1504,13 @@ __device__ inline float p2p_term32(float w, float r2)
     return w * __builtin_amdgcn_exp2f(-(r2 * ri)) * ri;
 }
 
+// acc + the same term, as one fused multiply-add (w / r' times 2^{-r'})
+__device__ inline float p2p_fma32(float w, float r2, float acc)
+{
+    const float ri = __frsqrt_rn(r2);
+    return fmaf(w * ri, __builtin_amdgcn_exp2f(-(r2 * ri)), acc);
+}
+
 // The hi/lo splits of targets and sources must round identically (a pair at
 // one point must give exactly zero): the scaled position is rounded to FP64
 // on its own, never fused into the subtraction that forms the lo part.
@@ -1603,10 +1610,10 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
 #pragma unroll
                         for (int u = 0; u < 8; ++u) r2[u] = full_r2(ju + par + 2 * u);
                     }
-                    kahan(((p2p_term32(w[0], r2[0]) + p2p_term32(w[1], r2[1])) +
-                           (p2p_term32(w[2], r2[2]) + p2p_term32(w[3], r2[3]))) +
-                          ((p2p_term32(w[4], r2[4]) + p2p_term32(w[5], r2[5])) +
-                           (p2p_term32(w[6], r2[6]) + p2p_term32(w[7], r2[7]))));
+                    float s8 = 0.f;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) s8 = p2p_fma32(w[u], r2[u], s8);
+                    kahan(s8);
                 }
                 int jj = ju + par;
                 for (; jj + 6 < n; jj += 8) {
