@@ -59,11 +59,15 @@ typedef enum {
 
 typedef enum { LPB_FP64 = 0, LPB_MIXED = 1 } lpb_precision;
 
-#define LPB_MAX_P 20
+#define LPB_MAX_P 20        /* largest order in mixed precision */
+#define LPB_MAX_P_FP64 15   /* largest order in FP64: the matrix-core translation kernels stage a
+                               64-column FP64 operand slab per block in LDS, (p+1)^2 rows padded to
+                               16, and above p = 15 that exceeds the 160 KiB of one workgroup */
 #define LPB_MAX_LAYERS 9
 
 typedef struct {
-    int p;                  /* expansion order: degrees n = 0..p (1 <= p <= LPB_MAX_P); default 10 */
+    int p;                  /* expansion order: degrees n = 0..p (1 <= p <= LPB_MAX_P in mixed precision,
+                               1 <= p <= LPB_MAX_P_FP64 in FP64); default 10 */
     int leaf_cap;           /* target mean charges per leaf (tree depth rule, see lpb_build_tree); default 50 */
     int precision;          /* lpb_precision; default LPB_FP64 */
     double quad_tol;        /* relative cut of the Sommerfeld quadrature envelope; default 1e-16 */
@@ -110,7 +114,8 @@ typedef struct {
 void lpb_default_options(lpb_options* opt);
 
 /* Create a context on opt->device.  opt may be NULL (defaults).
- * Errors: LPB_EINVAL (out == NULL), LPB_ERANGE (p, leaf_cap), LPB_EDEVICE,
+ * Errors: LPB_EINVAL (out == NULL), LPB_ERANGE (p outside 1..LPB_MAX_P, or above
+ * LPB_MAX_P_FP64 with precision LPB_FP64; leaf_cap < 1), LPB_EDEVICE,
  * LPB_ENOMEM.  On error *out is NULL. */
 lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out);
 

@@ -65,6 +65,7 @@ def lib():
             "orc_reaction_chain": (_D, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _PD, _PD, _PD, _PD, _PI]),
             "orc_reaction_I_pair": (None, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D,
                                            _I, _I, _I, _I, _PD]),
+            "orc_reaction_I_both": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D, _PD, _PD, _PD, _PD]),
             "orc_sommerfeld_table": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _D, _D, _D, _D, _I, _I, _PD]),
             "orc_legendre_product": (None, [_I, _I, _I, _I, _D, _D, _D, _PD]),
             "orc_plm_beyond": (None, [_I, _I, _D, _PD]),
@@ -254,6 +255,22 @@ def reaction_I_pair(ly: Layers, l, lp, a, b, p, rho, zt, zs, S, n, m, nu, mu):
     lib().orc_reaction_I_pair(_p(ly.eps), _p(ly.lam), _p(ly.d), ly.L, l, lp, a, b, p, float(rho), float(zt),
                               float(zs), float(S), n, m, nu, mu, _p(out))
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def reaction_I_both(ly: Layers, l, lp, a, b, p, rho, zt, zs, S):
+    """Whole I matrix of a reaction M2L (rows (n,m), columns (nu,mu)) by the
+    recurrence path and by direct quadrature, the quadrature of the direct
+    integrand's modulus and the rounding scale of the recurrence path;
+    returns (rec, dir, dabs, rbound, unstable)."""
+    K = (p + 1) ** 2
+    rec = np.zeros(2 * K * K)
+    dr = np.zeros(2 * K * K)
+    da = np.zeros(K * K)
+    rb = np.zeros(K * K)
+    u = lib().orc_reaction_I_both(_p(ly.eps), _p(ly.lam), _p(ly.d), ly.L, l, lp, a, b, p, float(rho), float(zt),
+                                  float(zs), float(S), _p(rec), _p(dr), _p(da), _p(rb))
+    c = lambda v: (v[:K * K] + 1j * v[K * K:]).reshape(K, K)
+    return c(rec), c(dr), da.reshape(K, K), rb.reshape(K, K), u
 
 
 def sommerfeld_table(ly: Layers, l, lp, a, b, rho, zt, zs, S, nmax, mode):

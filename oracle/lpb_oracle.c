@@ -887,7 +887,8 @@ static cplx plm_big(int n, int m, double w, double lrho_over_lam)
     return tau_sign(m) * cnm(n, am) * root * val;
 }
 
-static cplx reaction_I_direct_one(const rcomp_t* C, int n, int m, int nu, int mu, double rho, double zt, double zs)
+static cplx reaction_I_direct_one(const rcomp_t* C, int n, int m, int nu, int mu, double rho, double zt, double zs,
+                                  double* absint)
 {
     const layers_t* Ly = &C->Ly;
     double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
@@ -898,8 +899,10 @@ static cplx reaction_I_direct_one(const rcomp_t* C, int n, int m, int nu, int mu
         double t = nd.x[k];
         double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
         cplx Q = plm_big(n, m, lz / lt, t / lt) * plm_big(nu, mu, lzp / ls, t / ls);
-        acc += nd.w[k] * t * jn(mu - m, t * rho) * zkern(C, lz, lzp, zt, zs) *
-               sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz * Q;
+        double f = nd.w[k] * t * jn(mu - m, t * rho) * zkern(C, lz, lzp, zt, zs) *
+                   sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz;
+        acc += f * Q;
+        if (absint) *absint += fabs(f) * cabs(Q);
     }
     free_nodes(&nd);
     return ipow(mu - m) * acc;
@@ -1802,13 +1805,120 @@ void orc_reaction_I_pair(const double* eps, const double* lam, const double* d, 
     ctab_t CT;
     ctab_init(&CT, p, lam[l], lam[lp]);
     cplx v = assemble_I(&CT, tab, nmax, S, n, m, nu, mu);
-    cplx w = reaction_I_direct_one(&C, n, m, nu, mu, rho, zt, zs);
+    cplx w = reaction_I_direct_one(&C, n, m, nu, mu, rho, zt, zs, NULL);
     out[0] = creal(v);
     out[1] = cimag(v);
     out[2] = creal(w);
     out[3] = cimag(w);
     free(tab);
     free(CT.v);
+}
+
+/* Rounding scale of the recurrence path (running error analysis): the same
+ * steps as sommerfeld_table and assemble_I applied to moduli, |a - b| ->
+ * |a| + |b|, starting from the quadrature of the moduli of the initial-value
+ * integrands.  The rounding error of every table entry and of every I entry
+ * is a modest multiple of 1e-16 times this scale; it grows where the forward
+ * recurrence in m amplifies earlier entries (large m at small rho / S). */
+static void reaction_I_bound(const rcomp_t* C, const ctab_t* CT, int p, double rho, double zt, double zs, double S,
+                             double* B)
+{
+    const layers_t* Ly = &C->Ly;
+    int nmax = 2 * p + 3, N1 = nmax + 1, K = (p + 1) * (p + 1);
+    double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
+    double* tab = (double*)calloc((size_t)4 * N1 * N1, sizeof(double));
+    nodes_t nd;
+    build_nodes(&nd, rho, zsep(C, zt, zs), nmax, layers_lam_min(Ly), layers_dmax(Ly), ORC_TOL);
+    for (int k = 0; k < nd.n; ++k) {
+        double t = nd.x[k];
+        double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+        double base = fabs(nd.w[k] * zkern(C, lz, lzp, zt, zs) * sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz);
+        double j0 = fabs(jn(0, t * rho)), j1 = fabs(jn(1, t * rho));
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                double f = base * (i ? lt / lz : 1.0) * (j ? ls / lzp : 1.0);
+                double* T = tab + (size_t)(i * 2 + j) * N1 * N1;
+                double pw = 1.0;
+                for (int n = 0; n <= nmax; ++n) {
+                    T[n * N1 + 0] += f * pw * j0 / fact(n);
+                    if (n >= 1) T[n * N1 + 1] += f * pw * j1 / sqrt(fact(n + 1) * fact(n - 1));
+                    pw *= t * S;
+                }
+            }
+    }
+    free_nodes(&nd);
+    for (int ij = 0; ij < 4 && rho > 0.0; ++ij) {
+        double* T = tab + (size_t)ij * N1 * N1;
+        for (int m = 1; m < nmax; ++m)
+            for (int n = m + 1; n <= nmax; ++n)
+                T[n * N1 + m + 1] = 2.0 * m / a_n(n + m) * (S / rho) * T[(n - 1) * N1 + m] +
+                                    a_n(n - m) / a_n(n + m) * T[n * N1 + m - 1];
+    }
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m)
+            for (int nu = 0; nu <= p; ++nu)
+                for (int mu = -nu; mu <= nu; ++mu) {
+                    int i = (n + iabs(m)) % 2, j = (nu + iabs(mu)) % 2;
+                    int r = (n + iabs(m)) / 2, rp = (nu + iabs(mu)) / 2;
+                    const double* T = tab + (size_t)(i * 2 + j) * N1 * N1;
+                    const cplx* cv = &CT->v[((size_t)idx_nm(n, m) * K + idx_nm(nu, mu)) * (CT->smax + 1)];
+                    double acc = 0.0;
+                    for (int s = 0; s <= (n - r) + (nu - rp); ++s) {
+                        int Nn = iabs(m) + iabs(mu) + 2 * s + 1;
+                        acc += cabs(cv[s]) * T[Nn * N1 + iabs(mu - m)] / pow(S, Nn);
+                    }
+                    B[(size_t)idx_nm(n, m) * K + idx_nm(nu, mu)] = acc;
+                }
+    free(tab);
+}
+
+/* The same cross-check for the whole K x K matrix, K = (p+1)^2, rows (n,m)
+ * and columns (nu,mu) in the order n^2+n+m: rec = the recurrence path
+ * (eqs. M2Ltable, recurrence1, metoletableform), dir = direct quadrature of
+ * eq. uniformintegral with Q = P^_n^m P^_nu^mu, each [K*K] re then [K*K] im;
+ * dabs[K*K] = the same quadrature of the integrand's modulus (the scale of
+ * the rounding error of an oscillatory quadrature); rbound[K*K] = the
+ * rounding scale of the recurrence path (reaction_I_bound).  Returns 1 if
+ * the recurrence stability bound was violated. */
+int orc_reaction_I_both(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
+                        int p, double rho, double zt, double zs, double S, double* rec, double* dir, double* dabs,
+                        double* rbound)
+{
+    rcomp_t C;
+    fill_layers(&C.Ly, L + 1, eps, lam, d);
+    C.l = l;
+    C.lp = lp;
+    C.a = a;
+    C.b = b;
+    int K = (p + 1) * (p + 1);
+    cplx* Im = (cplx*)malloc(sizeof(cplx) * (size_t)K * K);
+    ctab_t CT;
+    ctab_init(&CT, p, lam[l], lam[lp]);
+    int unstable = 0;
+    reaction_I_matrix(&C, &CT, p, rho, zt, zs, S, Im, &unstable);
+    reaction_I_bound(&C, &CT, p, rho, zt, zs, S, rbound);
+    for (int k = 0; k < K * K; ++k) {
+        rec[k] = creal(Im[k]);
+        rec[(size_t)K * K + k] = cimag(Im[k]);
+    }
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int r = 0; r < K; ++r) {
+        int n = (int)sqrt((double)r), m = r - n * n - n;
+        for (int nu = 0; nu <= p; ++nu)
+            for (int mu = -nu; mu <= nu; ++mu) {
+                int c = idx_nm(nu, mu);
+                double ab = 0.0;
+                cplx w = reaction_I_direct_one(&C, n, m, nu, mu, rho, zt, zs, &ab);
+                dabs[(size_t)r * K + c] = ab;
+                dir[(size_t)r * K + c] = creal(w);
+                dir[(size_t)K * K + (size_t)r * K + c] = cimag(w);
+            }
+    }
+    free(Im);
+    free(CT.v);
+    return unstable;
 }
 
 /* Raw scaled Sommerfeld table (for the recurrence pins):

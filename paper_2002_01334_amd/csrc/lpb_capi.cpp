@@ -735,9 +735,11 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     lpb_options o;
     lpb_default_options(&o);
     if (opt) o = *opt;
-    if (o.p < 1 || o.p > LPB_MAX_P) return fail(nullptr, LPB_ERANGE, "p out of range");
-    if (o.leaf_cap < 1) return fail(nullptr, LPB_ERANGE, "leaf_cap must be >= 1");
     if (o.precision != LPB_FP64 && o.precision != LPB_MIXED) return fail(nullptr, LPB_EINVAL, "bad precision");
+    if (o.p < 1 || o.p > LPB_MAX_P) return fail(nullptr, LPB_ERANGE, "p out of range");
+    if (o.precision == LPB_FP64 && o.p > LPB_MAX_P_FP64)
+        return fail(nullptr, LPB_ERANGE, "p above LPB_MAX_P_FP64 in FP64 (the FP64 operand slab of a block would exceed LDS)");
+    if (o.leaf_cap < 1) return fail(nullptr, LPB_ERANGE, "leaf_cap must be >= 1");
     if (!(o.quad_tol > 0.0 && o.quad_tol < 1e-3)) return fail(nullptr, LPB_EINVAL, "quad_tol out of range");
     if (!(o.iface_tol >= 0.0)) return fail(nullptr, LPB_EINVAL, "iface_tol must be >= 0");
     int ndev = 0;
