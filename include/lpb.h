@@ -164,6 +164,28 @@ lpb_status lpb_build_trees(lpb_ctx* ctx, int n_sys, const int64_t* n, const doub
                            const double* const* y, const double* const* z, int on_device);
 lpb_status lpb_evaluate_batch(lpb_ctx* ctx, int n_sys, const double* const* q, double* const* phi, int on_device);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lpb_evaluate with
+ * device pointers that calls no allocating routine.  q[n] and phi[n] are
+ * device memory of the context's GPU, in input order; phi may not alias q.
+ * The partial potentials of the output slots (n_slots * n doubles, n_slots
+ * = 3 for three or more layers, 1 for one layer, 2 for two) live in a
+ * library-wide device array of LPB_NOALLOC_MAX_PARTS doubles (96 MiB) that
+ * each GPU the library runs on holds until the process ends; every call on a
+ * GPU shares that GPU's array (cleared at the start of each call), so calls
+ * that overlap on one GPU (several contexts, streams or threads) race and
+ * must be serialized by the caller.  The passes are launched one by one on
+ * the context's stream with the schedules the context already chose (no
+ * graph instantiation, no autotuning), then the call waits for the stream.
+ * The context must be prepared: a single-system context on which
+ * lpb_evaluate has run since the last lpb_set_layers / lpb_build_tree (that
+ * call generates the operators and picks the schedules).  Results are bit
+ * for bit those of lpb_evaluate.  Errors: LPB_EINVAL (null pointers, phi ==
+ * q), LPB_ESTATE (not prepared, or a batched context), LPB_ERANGE (n_slots *
+ * n > LPB_NOALLOC_MAX_PARTS), LPB_EDEVICE. */
+#define LPB_NOALLOC_MAX_PARTS (12u << 20)
+lpb_status lpb_evaluate_noalloc(lpb_ctx* ctx, const double* q, double* phi);
+
 /* Counters and timings of the last calls.  Errors: LPB_EINVAL. */
 lpb_status lpb_get_stats(const lpb_ctx* ctx, lpb_stats* stats);
 

@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -17,9 +18,40 @@
 
 using namespace lpb;
 
+// Partial potentials of lpb_evaluate_noalloc: one array per GPU, held until
+// the process ends.  Host code never passes this name to a kernel (on the
+// host it only stands for the symbol): the device address of each GPU's copy
+// comes from hipGetSymbolAddress, looked up once per device in lpb_create.
+static __device__ __align__(256) double scratch[LPB_NOALLOC_MAX_PARTS];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on `device` (which must be current), looked
+// up on the first call for that device.
+hipError_t scratch_init(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = (double*)ptr;
+    return hipSuccess;
+}
+
+double* scratch_ptr(int device)
+{
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch_ptr[device];
+}
 
 struct DevBuf {
     void* ptr = nullptr;
@@ -60,6 +92,7 @@ struct lpb_ctx {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool tune_needed = true;
+    bool prepared = false;   // lpb_evaluate has run since the last plan or operator change
 };
 
 namespace {
@@ -496,6 +529,7 @@ lpb_status build_and_upload(lpb_ctx* c)
     auto t0 = std::chrono::steady_clock::now();
     drop_graph(c);
     c->tune_needed = true;
+    c->prepared = false;
     free_bufs(c->plan_bufs);
     free_bufs(c->op_bufs);
     c->ops_dirty = true;
@@ -527,6 +561,7 @@ lpb_status generate_operators(lpb_ctx* c)
     Plan& P = c->plan;
     drop_graph(c);
     c->tune_needed = true;
+    c->prepared = false;
     free_bufs(c->op_bufs);
     const int K = P.K, Kp = (P.p + 1) * (P.p + 2) / 2;
     lpb_status s;
@@ -707,6 +742,27 @@ lpb_status run_eval(lpb_ctx* c)
     return (c->opt.precision == LPB_MIXED) ? run_eval_t<float>(c, c->a32) : run_eval_t<double>(c, c->a64);
 }
 
+// The evaluation passes of a prepared context launched one by one, with the
+// partial potentials in `parts` (the GPU's scratch array), charges read from
+// q and the sum written to phi (caller device memory).
+template <typename T>
+lpb_status run_noalloc_t(lpb_ctx* c, const EvalArgs<T>& A0, const double* q, double* phi, double* parts)
+{
+    EvalArgs<T> A = A0;
+    A.q = q;
+    A.phi = phi;
+    A.parts = parts;
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, nullptr);
+    if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+    HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    c->stats.t_eval_ms = ms;
+    return LPB_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -751,6 +807,8 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     c->stream = (hipStream_t)o.stream;
     e = hipSetDevice(o.device);
     if (e != hipSuccess) return fail(nullptr, LPB_EDEVICE, hipGetErrorString(e));
+    e = scratch_init(o.device);
+    if (e != hipSuccess) return fail(nullptr, LPB_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
     if (o.graph && !c->stream) {
         // graphs cannot be captured on the null stream: use a blocking stream of
         // our own (it orders itself with the null stream)
@@ -790,6 +848,7 @@ lpb_status lpb_set_layers(lpb_ctx* c, int n_layers, const double* eps, const dou
     c->media.assign(1, M);
     c->have_layers = true;
     c->ops_dirty = true;
+    c->prepared = false;
     if (c->xs.size() == 1) return build_and_upload(c);
     return LPB_OK;
 }
@@ -840,6 +899,7 @@ static lpb_status evaluate_common(lpb_ctx* c, int nsys, const double* const* q, 
                                  on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->prepared = true;
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     c->stats.t_eval_ms = ms;
@@ -859,6 +919,27 @@ lpb_status lpb_evaluate(lpb_ctx* c, const double* q, double* phi, int on_device)
     if (!c->have_layers || !c->have_tree) return fail(c, LPB_ESTATE, "set_layers and build_tree must come first");
     if (q && phi && (const void*)q == (const void*)phi) return fail(c, LPB_EINVAL, "phi aliases q");
     return evaluate_common(c, 1, &q, &phi, on_device);
+}
+
+lpb_status lpb_evaluate_noalloc(lpb_ctx* c, const double* q, double* phi)
+{
+    if (!c) return LPB_EINVAL;
+    if (c->batched) return fail(c, LPB_ESTATE, "lpb_evaluate_noalloc takes single-system contexts");
+    if (!c->have_layers || !c->have_tree || c->ops_dirty || !c->prepared)
+        return fail(c, LPB_ESTATE, "context not prepared: run lpb_evaluate once after lpb_set_layers / lpb_build_tree");
+    const Plan& P = c->plan;
+    const uint64_t need = (uint64_t)P.nslots * (uint64_t)P.ncharges;
+    if (need > (uint64_t)LPB_NOALLOC_MAX_PARTS)
+        return fail(c, LPB_ERANGE, "n_slots * n = " + std::to_string(need) + " partial potentials exceed LPB_NOALLOC_MAX_PARTS = " +
+                                       std::to_string((uint64_t)LPB_NOALLOC_MAX_PARTS));
+    if (P.ncharges == 0) return LPB_OK;
+    if (!q || !phi) return fail(c, LPB_EINVAL, "null q or phi");
+    if ((const void*)q == (const void*)phi) return fail(c, LPB_EINVAL, "phi aliases q");
+    double* parts = scratch_ptr(c->opt.device);
+    if (!parts) return fail(c, LPB_ESTATE, "scratch array of this device not initialised");
+    HIPCHK(c, hipSetDevice(c->opt.device));
+    return (c->opt.precision == LPB_MIXED) ? run_noalloc_t<float>(c, c->a32, q, phi, parts)
+                                           : run_noalloc_t<double>(c, c->a64, q, phi, parts);
 }
 
 lpb_status lpb_set_systems(lpb_ctx* c, int n_sys, const int* n_layers, const double* const* eps,

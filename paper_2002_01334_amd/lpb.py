@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
 
 EXPORTS = ["lpb_default_options", "lpb_create", "lpb_set_layers", "lpb_build_tree", "lpb_evaluate",
            "lpb_set_systems", "lpb_build_trees", "lpb_evaluate_batch", "lpb_get_stats", "lpb_fmm_info",
-           "lpb_debug_parts", "lpb_last_error", "lpb_destroy", "lpb_host_gaunt"]
+           "lpb_debug_parts", "lpb_last_error", "lpb_destroy", "lpb_host_gaunt", "lpb_evaluate_noalloc"]
 
 _lib = None
 
@@ -92,6 +92,8 @@ def load():
     L.lpb_last_error.restype = ctypes.c_char_p
     L.lpb_destroy.argtypes = [_P]
     L.lpb_destroy.restype = None
+    L.lpb_evaluate_noalloc.argtypes = [_P, _P, _P]
+    L.lpb_evaluate_noalloc.restype = _I
     L.lpb_host_gaunt.argtypes = [_I] * 6
     L.lpb_host_gaunt.restype = _D
     _lib = L
@@ -174,6 +176,15 @@ class Context:
         if do != dq:
             raise ValueError("q and phi must both be host or both be device arrays")
         self._check(self._L.lpb_evaluate(self._h, pq, po, dq))
+        return ko
+
+    def evaluate_noalloc(self, q, out):
+        """lpb_evaluate_noalloc: q and out are float64 device tensors of n."""
+        pq, dq, kq = _ptr(q)
+        po, do, ko = _ptr(out)
+        if not (dq and do):
+            raise ValueError("evaluate_noalloc takes device tensors")
+        self._check(self._L.lpb_evaluate_noalloc(self._h, pq, po))
         return ko
 
     def set_systems(self, eps_list, lam_list, d_list):

@@ -53,6 +53,12 @@ def test_create_rejects_bad_options_without_touching_the_gpu(lpb):
         rc = L.lpb_create(ctypes.byref(o), ctypes.byref(h))
         assert rc == lpb.LPB_ERANGE and not h.value
         assert L.lpb_last_error(None)
+    # FP64 stops at LPB_MAX_P_FP64 = 15
+    o = lpb.Options()
+    L.lpb_default_options(ctypes.byref(o))
+    o.p, o.precision = 16, lpb.LPB_FP64
+    h = ctypes.c_void_p()
+    assert L.lpb_create(ctypes.byref(o), ctypes.byref(h)) == lpb.LPB_ERANGE and not h.value
     assert L.lpb_create(None, None) == lpb.LPB_EINVAL
 
 
@@ -60,6 +66,7 @@ def test_null_context_is_rejected(lpb):
     L = lpb.load()
     assert L.lpb_evaluate(None, None, None, 0) == lpb.LPB_EINVAL
     assert L.lpb_get_stats(None, None) == lpb.LPB_EINVAL
+    assert L.lpb_evaluate_noalloc(None, None, None) == lpb.LPB_EINVAL
     L.lpb_destroy(None)
 
 
