@@ -36,10 +36,17 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# peaks (MI355X, published): HBM 8 TB/s; vector FP32 157.3 TFLOP/s; vector FP64 78.6 TFLOP/s
+# peaks (MI355X, published): HBM 8 TB/s; matrix cores FP32 157.3 TFLOP/s, FP64 78.6 TFLOP/s.
+# Vector ALU: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz = 78.6 TFLOP/s for FP32 without
+# packed instructions (the library is built with packed FP32 disabled; the published 157.3 counts them)
+# and for FP64.
 PEAK_FP32 = 157.3
 PEAK_FP64 = 78.6
-# algorithmic flops per unit of work of each stage
+PEAK_VALU = 78.6
+PEAK_HBM_GBS = 8000.0
+# algorithmic work per unit of each stage: 20 flops per near-field charge pair (distance, rsqrt, exp2,
+# product, sum); about 8K flops per charge and expansion in P2M and L2P (Bessel and solid-harmonic
+# recurrences and the K coefficients); 2K^2 flops per real-form dense K x K product
 FLOPS_PER_P2P_PAIR = 20.0
 # the paper's timing table (Table 1), 36 cores: N -> (free-space s, reaction s)
 PAPER_TABLE1 = {618_256: (2.042, 1.639), 1_128_556: (4.308, 4.459), 1_862_568: (14.94, 6.104),
@@ -132,12 +139,23 @@ def time_batch(lpb, torch, probs, p, leaf_cap, precision, steps, warmup, stage_s
     return r
 
 
-def cpu_baseline(probs, p, leaf_cap, what):
-    """The oracle FMM (plain C, FP64, OpenMP) on a bounded sample of the workload."""
+def shrink(prob, k):
+    """Every k-th charge of a problem (same recipe, 1/k of the density)."""
+    import dataclasses
+
+    return dataclasses.replace(prob, **{f: getattr(prob, f)[::k].copy() for f in ("x", "y", "z", "q", "layer")})
+
+
+def cpu_baseline(probs, p, leaf_cap, what, cores=None):
+    """The oracle FMM (plain C, FP64, OpenMP) on a bounded sample of the
+    workload.  Its cost is linear in the number of charges at a fixed leaf
+    occupancy (the tree deepens with N), so charges/s carries over to the
+    full-size workload of the same recipe."""
     import oracle
 
     # the host share of one GPU is at most 16 threads, whatever the machine reports
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    if cores is None:
+        cores = max(1, min(16, len(os.sched_getaffinity(0))))
     n = 0
     t0 = time.perf_counter()
     for prob in probs:
@@ -149,23 +167,86 @@ def cpu_baseline(probs, p, leaf_cap, what):
             "sample": f"oracle CPU FMM (FP64, OpenMP) on {what}: {n} charges, p={p}, leaf cap {leaf_cap}; {dt:.1f} s"}
 
 
+def kernel_sources_sha():
+    """sha256 over the evaluation kernels' sources (csrc/*.hip and *.h, sorted)."""
+    d = os.path.join(ROOT, "paper_2002_01334_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            h.update(f.encode())
+            h.update(open(os.path.join(d, f), "rb").read())
+    return h.hexdigest()
+
+
 def kernel_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary,
-    if the evaluation kernels' source is unchanged since it was taken."""
+    if the kernels' sources are unchanged since it was taken."""
     prof = os.path.join(ROOT, "profiles", "hbm_traffic_3layer_3e6_p10.md")
-    src = os.path.join(ROOT, "paper_2002_01334_amd", "csrc", "lpb_eval.hip")
     try:
         text = open(prof).read()
         blk = json.loads(text.split("```json", 1)[1].split("```", 1)[0])
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     except (OSError, IndexError, ValueError):
         return None
-    if blk.get("source_sha256") != sha:
+    if blk.get("source_sha256") != kernel_sources_sha():
         return None
     for k in blk.get("kernels", []):
         if k["stage"] == kernel:
             return k["bytes_per_launch"]
     return None
+
+
+def stage_work(st, p, precision_mixed=True):
+    """Algorithmic work of every stage of one evaluation: (flops, bytes,
+    flop peak in TFLOP/s, unit "mfma" or "alu", description).  The tiled M2L counts one product per
+    (target box, reflection orbit) in its orbit form (mixed precision, 5 <= p
+    <= 15), one per V-list pair otherwise."""
+    K = (p + 1) ** 2
+    fb = 4 if precision_mixed else 8
+    mfma = PEAK_FP32 if precision_mixed else PEAK_FP64
+    orbit_form = precision_mixed and 5 <= p <= 15
+    tile_units = 56 * 64 * st["n_m2l_tiles"] if orbit_form else st["n_m2l_tile_pairs"]
+    list_pairs = st["n_m2l_pairs"] - st["n_m2l_tile_pairs"]
+    return {
+        "m2l_tile": (2.0 * K * K * tile_units, 0.0, mfma, "mfma",
+                     "2K^2 flops per (target box, reflection orbit) product" if orbit_form
+                     else "2K^2 flops per V-list pair (real-form dense product)"),
+        "m2l_list": (2.0 * K * K * list_pairs, float(st["n_m2l_list_ops"]) * K * K * fb, mfma, "mfma",
+                     "2K^2 flops per untiled V-list pair; each distinct operator (K^2 reals) read once"),
+        "p2p_free": (FLOPS_PER_P2P_PAIR * (st["n_p2p_pairs"] - st["n_react_p2p_pairs"]), 0.0, PEAK_VALU, "alu",
+                     "20 flops per near-field charge pair"),
+        "p2m": (8.0 * K * st["n_p2m_points"], 0.0, PEAK_VALU, "alu", "8K flops per charge expansion"),
+        "l2p": (8.0 * K * st["n_l2p_points"], 0.0, PEAK_VALU, "alu", "8K flops per charge evaluation"),
+        "m2m": (2.0 * K * K * st["n_m2m_links"], 0.0, mfma, "mfma", "2K^2 flops per child link"),
+        "l2l": (2.0 * K * K * st["n_l2l_links"], 0.0, mfma, "mfma", "2K^2 flops per child link"),
+    }
+
+
+def roofline(st, stage_ms, p, precision_mixed=True, traffic_ok=False):
+    """Per-stage roofline fractions and the object of the stage that takes
+    the most time: the ideal time of a stage is the larger of its flops at the
+    flop peak of its unit and its bytes at the HBM peak; frac = ideal /
+    measured; `achieved` is given in the unit of the binding resource."""
+    work = stage_work(st, p, precision_mixed)
+    per = {}
+    for k, (fl, by, peak, unit, what) in work.items():
+        t = stage_ms.get(k, 0.0)
+        if t <= 0.0 or (fl == 0.0 and by == 0.0):
+            continue
+        t_fl = fl / (peak * 1e12)
+        t_by = by / (PEAK_HBM_GBS * 1e9)
+        per[k] = {"ms": t, "frac": max(t_fl, t_by) / (t * 1e-3), "bound": "hbm" if t_by > t_fl else unit}
+    dom = max(per, key=lambda k: per[k]["ms"])
+    fl, by, peak, _, what = work[dom]
+    t = stage_ms[dom] * 1e-3
+    if per[dom]["bound"] == "hbm":
+        obj = {"kernel": dom, "bound": "hbm", "achieved": by / t / 1e9, "peak": PEAK_HBM_GBS, "unit": "GB/s"}
+    else:
+        obj = {"kernel": dom, "bound": per[dom]["bound"], "achieved": fl / t / 1e12, "peak": peak, "unit": "TFLOP/s"}
+    obj["frac"] = obj["achieved"] / obj["peak"]
+    obj["traffic"] = kernel_traffic(dom) if traffic_ok else None
+    obj["work"] = f"{fl:.4g} algorithmic flops" + (f" and {by:.4g} bytes" if by else "") + f" per launch ({what})"
+    obj["stages"] = {k: {"frac": round(v["frac"], 4), "bound": v["bound"]} for k, v in per.items()}
+    return obj
 
 
 def main():
@@ -260,31 +341,10 @@ def main():
             sample_what = f"the same recipe at {cs} charges per layer"
 
     st = mixed["stats"]
-    K = (p + 1) ** 2
-    stage = mixed["stage_ms"]
-    # dominant kernel and its algorithmic work per launch (one launch per evaluation)
-    # tiled M2L, orbit form (mixed precision, 5 <= p <= 15): one K x K product per
-    # (target box, reflection orbit), 64 boxes and 56 orbits per tile
-    orbit_form = 5 <= p <= 15
-    tile_units = 56 * 64 * st["n_m2l_tiles"] if orbit_form else st["n_m2l_tile_pairs"]
-    work = {
-        "m2l_tile": (2.0 * K * K * tile_units, "mfma",
-                     "2K^2 flops per (target box, reflection orbit) product" if orbit_form
-                     else "2K^2 flops per V-list pair (real-form dense product)"),
-        "p2p_free": (FLOPS_PER_P2P_PAIR * (st["n_p2p_pairs"] - st["n_react_p2p_pairs"]), "alu",
-                     "20 flops per charge pair"),
-    }
-    dom = max(work, key=lambda k: stage.get(k, 0.0))
-    flops, bound, per = work[dom]
-    achieved = flops / (stage[dom] * 1e-3) / 1e12
-    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": PEAK_FP32, "unit": "TFLOP/s",
-            "frac": achieved / PEAK_FP32,
-            "traffic": kernel_traffic(dom) if (wl == "uniform" and per_layer == 1_000_000 and p == 10) else None,
-            "work": f"{flops:.4g} algorithmic flops per launch ({per})"}
-    fp64_roof = {"kernel": "m2l_tile",
-                 "achieved": 2.0 * K * K * st["n_m2l_tile_pairs"] / (max(fp64["stage_ms"]["m2l_tile"], 1e-9) * 1e-3) / 1e12,
-                 "peak": PEAK_FP64, "unit": "TFLOP/s"}
-    fp64_roof["frac"] = fp64_roof["achieved"] / PEAK_FP64
+    headline = wl == "uniform" and per_layer == 1_000_000 and p == 10
+    roof = roofline(st, mixed["stage_ms"], p, True, traffic_ok=headline)
+    fp64_roof = roofline(fp64["stats"], fp64["stage_ms"], p, False)
+    fp64_roof.pop("traffic", None)
 
     ms = mixed["eval_ms"]
     line = {
@@ -308,7 +368,7 @@ def main():
         "wall_ms_per_step": mixed["wall_s"] * 1e3,
         "eager_ms_per_step": mixed["eval_ms_eager"],
         "schedules": {"tile": st["tile_schedule"], "batch": st["batch_schedule"], "tune_ms": st["t_tune_ms"]},
-        "stage_ms": {k: round(v, 4) for k, v in stage.items()},
+        "stage_ms": {k: round(v, 4) for k, v in mixed["stage_ms"].items()},
         "fp64_stage_ms": {k: round(v, 4) for k, v in fp64["stage_ms"].items()},
         "setup": {"tree_build_s": mixed["t_build_s"], "opgen_ms": st["t_opgen_ms"], "n_m2l_pairs": st["n_m2l_pairs"],
                   "n_p2p_pairs": st["n_p2p_pairs"], "n_operators": st["n_operators"],
@@ -324,9 +384,19 @@ def main():
             "what": "the paper's timing table, 36 cores of 2x Xeon E5-2699 v4 (DASHMM, CPU), same N and p = 5; "
                     "other hardware, context only",
             "free_s": free_s, "reaction_s": react_s, "charges_per_s": ntot / (free_s + react_s)}
+    gate = max(rel) <= 1e-6
+    line["gate"] = {"rel_err_max": max(rel), "bar": 1e-6, "pass": bool(gate)}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(sample, p, args.leaf_cap, sample_what)
+        if wl != "batch":
+            # the same oracle on one host core, on a tenth of the sample
+            small = [shrink(pr, 10) for pr in sample]
+            line["cpu_baseline_1core"] = cpu_baseline(small, p, args.leaf_cap, sample_what + " (every 10th charge)",
+                                                      cores=1)
     print(json.dumps(line), flush=True)
+    if not gate:
+        print(f"[bench] mixed-precision error {max(rel):.3e} above the 1e-6 bar", file=sys.stderr, flush=True)
+        sys.exit(3)
 
 
 if __name__ == "__main__":

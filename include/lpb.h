@@ -108,6 +108,12 @@ typedef struct {
     int batch_schedule;     /* the same choice for the batched translations */
     double t_tune_ms;       /* time spent by the last schedule autotuning */
     int64_t n_m2l_tiles;    /* tiles (64 target boxes, one child octant) of the tiled M2L */
+    /* units of work of each stage (the plan's counts, for work models):
+     * P2M charge expansions (every source point of every source tree), L2P
+     * charge evaluations (every target point of every target tree), M2M and
+     * L2L child links, distinct operators of the V-list pairs outside the
+     * tiled levels (their products run in the batched kernel) */
+    int64_t n_p2m_points, n_l2p_points, n_m2m_links, n_l2l_links, n_m2l_list_ops;
 } lpb_stats;
 
 /* Fill *opt with the defaults listed above.  Never fails. */

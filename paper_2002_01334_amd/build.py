@@ -10,7 +10,11 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblpbfmm.so")
 
-HIP_SOURCES = ["lpb_opgen.hip", "lpb_eval.hip"]
+# (the longest compiles first; the orbit orders and the fixed-KB products are
+# split over several translation units so that they compile in parallel)
+HIP_SOURCES = ["lpb_m2l_orbit_d.hip", "lpb_m2l_orbit_c.hip", "lpb_m2l_orbit_b.hip", "lpb_m2l_orbit_a.hip",
+               "lpb_m2l_tile_kb32.hip", "lpb_m2l_tile_kb64.hip", "lpb_m2l_tile.hip", "lpb_eval.hip",
+               "lpb_p2m_l2p.hip", "lpb_opgen.hip"]
 CXX_SOURCES = ["lpb_plan.cpp", "lpb_capi.cpp"]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for all device code
@@ -24,7 +28,7 @@ def _run(cmd, verbose):
     subprocess.check_call(cmd)
 
 
-def build(verbose: bool = False, jobs: int = 4) -> str:
+def build(verbose: bool = False, jobs: int = 8) -> str:
     os.makedirs(BUILD, exist_ok=True)
     procs = []
     objs = []

@@ -552,6 +552,24 @@ lpb_status build_and_upload(lpb_ctx* c)
     c->stats.n_p2p_pairs = P.n_p2p_pairs;
     c->stats.n_react_p2p_pairs = P.n_react_p2p_pairs;
     c->stats.n_operators = (int64_t)P.ops.size();
+    {
+        // links of the batched M2M / L2L items (valid source rows) and the
+        // distinct operators of the untiled V-list pairs
+        auto links = [&](int w0, int w1) {
+            int64_t k = 0;
+            for (int w = w0; w < w1; ++w)
+                for (int t = P.bw_term_ptr[w]; t < P.bw_term_ptr[w + 1]; ++t)
+                    for (int j = 0; j < 64; ++j) k += (P.bw_src[64 * (size_t)t + j] >= 0 && P.bw_dst[64 * (size_t)w + j] >= 0);
+            return k;
+        };
+        c->stats.n_m2m_links = links(P.bm2m_lv[0], P.bm2m_lv[kMaxDepth + 1]);
+        c->stats.n_l2l_links = links(P.bl2l_lv[0], P.bl2l_lv[kMaxDepth + 1]);
+        std::vector<int> ops(P.m2l_op);
+        std::sort(ops.begin(), ops.end());
+        c->stats.n_m2l_list_ops = (int64_t)(std::unique(ops.begin(), ops.end()) - ops.begin());
+        c->stats.n_p2m_points = (int64_t)P.s_cidx.size();
+        c->stats.n_l2p_points = (int64_t)P.t_cidx.size();
+    }
     c->stats.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return LPB_OK;
 }

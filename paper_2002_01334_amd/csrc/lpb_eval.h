@@ -81,6 +81,18 @@ struct EvalSched {
 template <typename T>
 hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev);
 
+// Launchers of kernels that live in their own translation units: the tiled
+// free-space M2L (all forms) and P2M / L2P with the order fixed at compile
+// time (FP32, 2 <= p <= 15; nothing is launched for other p).
+template <typename T>
+void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st);
+template <int P>
+void launch_m2l_orbit_p(const EvalArgs<float>& A, hipStream_t st);   // kOrbitMinP <= P <= kOrbitMaxP
+template <typename T>
+bool launch_m2l_tile_kb(const EvalArgs<T>& A, bool wide, hipStream_t st);
+void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st);
+void launch_l2p_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st);
+
 // One matrix-core stage alone, for schedule tuning: which = 0 the tiled M2L,
 // 1 the batched translations (M2M, untiled M2L, L2L).  Leaves ME/LE/scratch
 // contents that the next full evaluation overwrites.

@@ -34,7 +34,9 @@ class Stats(ctypes.Structure):
     _fields_ = [("n_fmm", _I), ("max_depth", _I), ("n_m2l_pairs", _L), ("n_m2l_tile_pairs", _L), ("n_p2p_pairs", _L),
                 ("n_react_p2p_pairs", _L), ("n_operators", _L), ("operator_bytes", _L),
                 ("t_build_ms", _D), ("t_opgen_ms", _D), ("t_eval_ms", _D), ("t_stage_ms", _D * 10),
-                ("tile_schedule", _I), ("batch_schedule", _I), ("t_tune_ms", _D), ("n_m2l_tiles", _L)]
+                ("tile_schedule", _I), ("batch_schedule", _I), ("t_tune_ms", _D), ("n_m2l_tiles", _L),
+                ("n_p2m_points", _L), ("n_l2p_points", _L), ("n_m2m_links", _L), ("n_l2l_links", _L),
+                ("n_m2l_list_ops", _L)]
 
     STAGES = ["setup", "p2m", "m2m", "m2l_tile", "m2l_list", "l2l", "l2p", "p2p_free", "p2p_react", "sum"]
 
