@@ -82,6 +82,21 @@ typedef struct {
     int autotune;           /* 1 = time the candidate block-to-work schedules of the matrix-core M2L
                                kernels on the first evaluate after a change and keep the fastest
                                (results do not depend on the choice); default 1 */
+    /* Device-memory hook (e.g. a framework's caching allocator).  When alloc is
+     * not NULL, every device buffer the context holds (tables, tree, lists,
+     * expansions, operators, partial potentials) comes from
+     * alloc(bytes, alloc_user), which must return memory of the context's GPU
+     * aligned to at least 256 bytes, or NULL when it cannot (the call then
+     * fails with LPB_ENOMEM and the context keeps no partial state); each
+     * buffer goes back through free(ptr, alloc_user) when the context drops
+     * it (a rebuild of the plan or operators, lpb_destroy, or a failed
+     * lpb_create).  free must be set with alloc.  Both are called on the
+     * thread that calls the library, between kernels of the context's
+     * stream, which is synchronized before a buffer is returned.  NULL
+     * (default): hipMalloc / hipFree. */
+    void* (*alloc)(size_t bytes, void* alloc_user);
+    void (*free)(void* ptr, void* alloc_user);
+    void* alloc_user;
 } lpb_options;
 
 typedef struct {
@@ -120,9 +135,10 @@ typedef struct {
 void lpb_default_options(lpb_options* opt);
 
 /* Create a context on opt->device.  opt may be NULL (defaults).
- * Errors: LPB_EINVAL (out == NULL), LPB_ERANGE (p outside 1..LPB_MAX_P, or above
- * LPB_MAX_P_FP64 with precision LPB_FP64; leaf_cap < 1), LPB_EDEVICE,
- * LPB_ENOMEM.  On error *out is NULL. */
+ * Errors: LPB_EINVAL (out == NULL, alloc without free), LPB_ERANGE (p outside
+ * 1..LPB_MAX_P, or above LPB_MAX_P_FP64 with precision LPB_FP64; leaf_cap < 1),
+ * LPB_EDEVICE, LPB_ENOMEM (the allocator refused the context's tables).  On
+ * error *out is NULL and everything allocated so far has been released. */
 lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out);
 
 /* Set the layered medium (Sec. 2.1): n_layers = L+1 layers (1..LPB_MAX_LAYERS),
@@ -175,7 +191,7 @@ lpb_status lpb_evaluate_batch(lpb_ctx* ctx, int n_sys, const double* const* q, d
  * device pointers that calls no allocating routine.  q[n] and phi[n] are
  * device memory of the context's GPU, in input order; phi may not alias q.
  * The partial potentials of the output slots (n_slots * n doubles, n_slots
- * = 3 for three or more layers, 1 for one layer, 2 for two) live in a
+ * = 1 for a single layer, 3 otherwise) live in a
  * library-wide device array of LPB_NOALLOC_MAX_PARTS doubles (96 MiB) that
  * each GPU the library runs on holds until the process ends; every call on a
  * GPU shares that GPU's array (cleared at the start of each call), so calls

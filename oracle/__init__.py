@@ -55,6 +55,7 @@ def lib():
             "orc_gaunt": (_D, [_I, _I, _I, _I, _I, _I]),
             "orc_gauss_legendre": (None, [_I, _PD, _PD]),
             "orc_sigma3": (_D, [_PD, _PD, _D, _D, _I, _I, _I, _I, _D]),
+            "orc_sigma_stack": (_D, [_I, _PD, _PD, _PD, _I, _I, _I, _I, _D]),
             "orc_reaction_u": (_D, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _D, _D, _D, _D, _D, _D]),
             "orc_direct_sum": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _PD, _L, _PL, _PD, _I]),
             "orc_fmm": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _PD, _I, _I, _I, _PD, _PD, _PD]),
@@ -140,6 +141,11 @@ def gauss_legendre(n):
 
 def sigma3(ly: Layers, l, lp, a, b, lrho):
     return lib().orc_sigma3(_p(ly.eps), _p(ly.lam), float(ly.d[0]), float(ly.d[1]), l, lp, a, b, float(lrho))
+
+
+def sigma_stack(ly: Layers, l, lp, a, b, lrho):
+    """sigma^{ab}_{l lp}(lrho) of any stack by the generalized reflection recursion."""
+    return lib().orc_sigma_stack(ly.nlayers, _p(ly.eps), _p(ly.lam), _p(ly.d), l, lp, a, b, float(lrho))
 
 
 def plm_beyond(n, m, w):

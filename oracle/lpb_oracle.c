@@ -310,9 +310,89 @@ double orc_sigma3(const double* eps, const double* lam, double d0, double d1, in
 #undef SKEY
 }
 
+/* Reaction densities of a general stack (Sec. 2.1: eqs. greenfuncomponent,
+ * totaldensity; the paper writes sigma out only for three layers) by
+ * generalized reflection and transmission coefficients.  For one lrho, with
+ * zeta_k = sqrt(lam_k^2 + lrho^2), Y_k = eps_k zeta_k and h_k = d_{k-1} - d_k,
+ * the spectral field in layer k is the source term (k = lp)
+ * e^{-zeta |z - z'|} / (eps_lp zeta_lp) plus an up-going wave
+ * P_k e^{-zeta_k (z - d_k)} and a down-going wave Q_k e^{-zeta_k (d_{k-1} - z)};
+ * sigma^{1b}_{l lp} and sigma^{2b}_{l lp} are the coefficients of the source
+ * exponentials X_1 = e^{-zeta_lp (z' - d_lp)}, X_2 = e^{-zeta_lp (d_{lp-1} - z')}
+ * in zeta_l P_l and zeta_l Q_l.  Continuity of u and eps du/dz at each
+ * interface gives, looking down from layer k at d_k (a down-going wave of unit
+ * amplitude there), the reflected amplitude
+ *   Rd_k = (Y_k - W) / (Y_k + W),  W = Y_{k+1} (1 - g) / (1 + g),
+ *   g = e^{-2 zeta_{k+1} h_{k+1}} Rd_{k+1}   (Rd_L = 0, g = 0 into layer L),
+ * and the transmitted down-going amplitude Td_k = (1 + Rd_k) / (1 + g) in
+ * layer k+1; looking up at d_{k-1} the same with the layers above (Ru_0 = 0).
+ * In the source layer P = Rd (x1 + Q E), Q = Ru (x2 + P E), E = e^{-zeta h},
+ * x_b = X_b / (eps zeta); the waves leaving it are carried through the
+ * layers below (down-going amplitude at the top of each, times Td) and above
+ * (up-going amplitude at the bottom of each, times Tu).  Every factor is at
+ * most 1 in modulus, so nothing overflows at large lrho.  Returns NAN for an
+ * invalid (l, lp, a, b). */
+static int comp_valid(const layers_t* Ly, int l, int lp, int a, int b);
+
+static double sigma_stack(const layers_t* Ly, int l, int lp, int a, int b, double lrho)
+{
+    const int L = Ly->L;
+    double zt[ORC_MAXL + 1], Y[ORC_MAXL + 1], E[ORC_MAXL + 1];
+    double Rd[ORC_MAXL + 1], Td[ORC_MAXL + 1], Ru[ORC_MAXL + 1], Tu[ORC_MAXL + 1];
+    if (!comp_valid(Ly, l, lp, a, b)) return NAN;
+    for (int k = 0; k <= L; ++k) {
+        zt[k] = sqrt(Ly->lam[k] * Ly->lam[k] + lrho * lrho);
+        Y[k] = Ly->eps[k] * zt[k];
+        /* attenuation across layer k (unbounded top and bottom layers: 0) */
+        E[k] = (k == 0 || k == L) ? 0.0 : exp(-zt[k] * (Ly->d[k - 1] - Ly->d[k]));
+    }
+    Rd[L] = 0.0;
+    Td[L] = 0.0;
+    for (int k = L - 1; k >= 0; --k) {
+        double g = E[k + 1] * E[k + 1] * Rd[k + 1];
+        double W = Y[k + 1] * (1.0 - g) / (1.0 + g);
+        Rd[k] = (Y[k] - W) / (Y[k] + W);
+        Td[k] = (1.0 + Rd[k]) / (1.0 + g);
+    }
+    Ru[0] = 0.0;
+    Tu[0] = 0.0;
+    for (int k = 1; k <= L; ++k) {
+        double g = E[k - 1] * E[k - 1] * Ru[k - 1];
+        double W = Y[k - 1] * (1.0 - g) / (1.0 + g);
+        Ru[k] = (Y[k] - W) / (Y[k] + W);
+        Tu[k] = (1.0 + Ru[k]) / (1.0 + g);
+    }
+    /* unit source exponential of side b */
+    double x1 = (b == 1) ? 1.0 / Y[lp] : 0.0, x2 = (b == 2) ? 1.0 / Y[lp] : 0.0;
+    double Es = E[lp], den = 1.0 - Rd[lp] * Ru[lp] * Es * Es;
+    double P = (Rd[lp] * x1 + Rd[lp] * Ru[lp] * Es * x2) / den;
+    double Q = (Ru[lp] * x2 + Ru[lp] * Rd[lp] * Es * x1) / den;
+    double Pl = 0.0, Ql = 0.0;
+    if (l == lp) {
+        Pl = P;
+        Ql = Q;
+    } else if (l > lp) {
+        /* down-going amplitude at the top of layer lp+1, then layer by layer */
+        double t = Td[lp] * (x1 + Q * Es);
+        for (int k = lp + 1; k < l; ++k) t = Td[k] * t * E[k];
+        Ql = t;
+        Pl = Rd[l] * t * E[l];
+    } else {
+        /* up-going amplitude at the bottom of layer lp-1, then layer by layer */
+        double u = Tu[lp] * (x2 + P * Es);
+        for (int k = lp - 1; k > l; --k) u = Tu[k] * u * E[k];
+        Pl = u;
+        Ql = Ru[l] * u * E[l];
+    }
+    return zt[l] * (a == 1 ? Pl : Ql);
+}
+
+
 static double sigma(const layers_t* Ly, int l, int lp, int a, int b, double lrho)
 {
-    return orc_sigma3(Ly->eps, Ly->lam, Ly->d[0], Ly->d[1], l, lp, a, b, lrho);
+    /* three layers: the paper's closed forms; any other stack: the recursion */
+    if (Ly->L == 2) return orc_sigma3(Ly->eps, Ly->lam, Ly->d[0], Ly->d[1], l, lp, a, b, lrho);
+    return sigma_stack(Ly, l, lp, a, b, lrho);
 }
 
 /* A reaction component (l, lp, a, b) exists iff a=1 -> l<L, a=2 -> l>0,
@@ -434,13 +514,14 @@ double orc_reaction_u(const double* eps, const double* lam, const double* d, int
                       double x, double y, double z, double xp, double yp, double zp)
 {
     layers_t Ly;
+    if (L < 1 || L > ORC_MAXL) return NAN;
     Ly.L = L;
     for (int k = 0; k <= L; ++k) {
         Ly.eps[k] = eps[k];
         Ly.lam[k] = lam[k];
     }
     for (int k = 0; k < L; ++k) Ly.d[k] = d[k];
-    if (L != 2 || !comp_valid(&Ly, l, lp, a, b)) return NAN;
+    if (!comp_valid(&Ly, l, lp, a, b)) return NAN;
     double rho = hypot(x - xp, y - yp);
     double tt = tau_t(&Ly, l, a, z), ts = tau_s(&Ly, lp, b, zp);
     nodes_t nd;
@@ -474,13 +555,22 @@ static int fill_layers(layers_t* Ly, int nlayers, const double* eps, const doubl
     return 0;
 }
 
+/* sigma^{ab}_{l lp}(lrho) of a stack of nlayers layers by the generalized
+ * reflection recursion (any number of layers, three included). */
+double orc_sigma_stack(int nlayers, const double* eps, const double* lam, const double* d, int l, int lp, int a,
+                       int b, double lrho)
+{
+    layers_t Ly;
+    if (fill_layers(&Ly, nlayers, eps, lam, d) || Ly.L < 1) return NAN;
+    return sigma_stack(&Ly, l, lp, a, b, lrho);
+}
+
 int orc_direct_sum(int nlayers, const double* eps, const double* lam, const double* d, int64_t n, const double* x,
                    const double* y, const double* z, const double* q, int64_t nt, const int64_t* tidx, double* phi,
                    int nthreads)
 {
     layers_t Ly;
     if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
-    if (Ly.L != 2 && Ly.L != 0) return -2;
     int* lay = (int*)malloc(sizeof(int) * n);
     for (int64_t j = 0; j < n; ++j) lay[j] = layer_of(&Ly, z[j]);
     double lmin = layers_lam_min(&Ly), dmax = layers_dmax(&Ly);
@@ -1561,7 +1651,6 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
 {
     layers_t Ly;
     if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
-    if (Ly.L != 2 && Ly.L != 0) return -2;
     if (p < 0 || p > ORC_PMAX || leaf_cap < 1) return -3;
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
@@ -1758,7 +1847,7 @@ double orc_reaction_chain(const double* eps, const double* lam, const double* d,
     C.lp = lp;
     C.a = a;
     C.b = b;
-    if (L != 2 || !comp_valid(&C.Ly, l, lp, a, b)) return NAN;
+    if (L < 1 || L > ORC_MAXL || !comp_valid(&C.Ly, l, lp, a, b)) return NAN;
     int K = (p + 1) * (p + 1);
     double ts = tau_s(&C.Ly, lp, b, rs[2]);
     double zimg = (a == 1) ? C.Ly.d[l] - ts : C.Ly.d[l - 1] + ts;

@@ -120,10 +120,34 @@ lpb_status fail(lpb_ctx* c, lpb_status s, const std::string& msg)
                         std::string(#call) + ": " + hipGetErrorString(e_));                          \
     } while (0)
 
-void free_bufs(std::vector<DevBuf>& v)
+// Device memory of a context: the caller's allocator hook when set, else
+// hipMalloc / hipFree.  Buffers are only returned after the context's stream
+// has drained (no kernel still reads them).
+void* dev_alloc(lpb_ctx* c, size_t bytes)
 {
-    for (auto& b : v)
-        if (b.ptr) (void)hipFree(b.ptr);
+    if (c->opt.alloc) return c->opt.alloc(bytes, c->opt.alloc_user);
+    void* p = nullptr;
+    return hipMalloc(&p, bytes) == hipSuccess ? p : nullptr;
+}
+
+void dev_free(lpb_ctx* c, void* p)
+{
+    if (!p) return;
+    if (c->opt.alloc) c->opt.free(p, c->opt.alloc_user);
+    else (void)hipFree(p);
+}
+
+void free_buf(lpb_ctx* c, DevBuf& b)
+{
+    dev_free(c, b.ptr);
+    b.ptr = nullptr;
+    b.bytes = 0;
+}
+
+void free_bufs(lpb_ctx* c, std::vector<DevBuf>& v)
+{
+    if (!v.empty()) (void)hipStreamSynchronize(c->stream);
+    for (auto& b : v) free_buf(c, b);
     v.clear();
 }
 
@@ -132,9 +156,8 @@ lpb_status dalloc(lpb_ctx* c, std::vector<DevBuf>& pool, size_t n, T** out)
 {
     *out = nullptr;
     size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
-    void* p = nullptr;
-    hipError_t e = hipMalloc(&p, bytes);
-    if (e != hipSuccess) return fail(c, LPB_ENOMEM, std::string("hipMalloc(") + std::to_string(bytes) + "): " + hipGetErrorString(e));
+    void* p = dev_alloc(c, bytes);
+    if (!p) return fail(c, LPB_ENOMEM, "device allocation of " + std::to_string(bytes) + " bytes failed");
     pool.push_back({p, bytes});
     *out = (T*)p;
     return LPB_OK;
@@ -530,8 +553,8 @@ lpb_status build_and_upload(lpb_ctx* c)
     drop_graph(c);
     c->tune_needed = true;
     c->prepared = false;
-    free_bufs(c->plan_bufs);
-    free_bufs(c->op_bufs);
+    free_bufs(c, c->plan_bufs);
+    free_bufs(c, c->op_bufs);
     c->ops_dirty = true;
     c->have_tree = false;
     Plan& P = c->plan;
@@ -542,7 +565,10 @@ lpb_status build_and_upload(lpb_ctx* c)
     std::string msg = build_plan(P, c->media, c->xs, c->ys, c->zs, c->opt.iface_tol, &st);
     if (st != LPB_OK) return fail(c, (lpb_status)st, msg);
     lpb_status s = (c->opt.precision == LPB_MIXED) ? fill_args<float>(c, c->a32) : fill_args<double>(c, c->a64);
-    if (s != LPB_OK) return s;
+    if (s != LPB_OK) {
+        free_bufs(c, c->plan_bufs);
+        return s;
+    }
     c->have_tree = true;
     c->stats.n_fmm = (int)P.fmm.size();
     c->stats.max_depth = P.max_depth;
@@ -574,13 +600,23 @@ lpb_status build_and_upload(lpb_ctx* c)
     return LPB_OK;
 }
 
+lpb_status generate_operators_impl(lpb_ctx* c);
+
+// Operators of the current plan; on failure no operator buffer is kept.
 lpb_status generate_operators(lpb_ctx* c)
+{
+    lpb_status s = generate_operators_impl(c);
+    if (s != LPB_OK) free_bufs(c, c->op_bufs);
+    return s;
+}
+
+lpb_status generate_operators_impl(lpb_ctx* c)
 {
     Plan& P = c->plan;
     drop_graph(c);
     c->tune_needed = true;
     c->prepared = false;
-    free_bufs(c->op_bufs);
+    free_bufs(c, c->op_bufs);
     const int K = P.K, Kp = (P.p + 1) * (P.p + 2) / 2;
     lpb_status s;
     std::vector<int> freel, reactl, rfl, rfidx(P.fmm.size(), -1);
@@ -661,10 +697,7 @@ lpb_status generate_operators(lpb_ctx* c)
     // the kernels read the operators in the MFMA operand layout only; the
     // FP64 master copy is no longer needed
     for (auto& b : c->op_bufs)
-        if (b.ptr == (void*)g.d_pool) {
-            (void)hipFree(b.ptr);
-            b.ptr = nullptr;
-        }
+        if (b.ptr == (void*)g.d_pool) free_buf(c, b);
     if (c->opt.precision == LPB_MIXED) {
         c->a32.pool_swz = g.d_swz32;
         c->a32.pool_orb = g.d_orb32;
@@ -816,11 +849,17 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (o.leaf_cap < 1) return fail(nullptr, LPB_ERANGE, "leaf_cap must be >= 1");
     if (!(o.quad_tol > 0.0 && o.quad_tol < 1e-3)) return fail(nullptr, LPB_EINVAL, "quad_tol out of range");
     if (!(o.iface_tol >= 0.0)) return fail(nullptr, LPB_EINVAL, "iface_tol must be >= 0");
+    if (!o.alloc != !o.free) return fail(nullptr, LPB_EINVAL, "alloc and free must be set together");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(nullptr, LPB_EDEVICE, "no HIP device available");
     if (o.device < 0 || o.device >= ndev) return fail(nullptr, LPB_EINVAL, "device ordinal out of range");
-    std::unique_ptr<lpb_ctx> c(new lpb_ctx());
+    // on failure below, everything the context holds so far is released
+    struct Releaser {
+        lpb_ctx* c;
+        ~Releaser() { if (c) lpb_destroy(c); }
+    } guard{new lpb_ctx()};
+    lpb_ctx* c = guard.c;
     c->opt = o;
     c->stream = (hipStream_t)o.stream;
     e = hipSetDevice(o.device);
@@ -836,22 +875,31 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (opgen_upload_constants() != hipSuccess) return fail(nullptr, LPB_EDEVICE, "constant upload failed");
     make_btab(o.p, c->btab);
     make_gtab(o.p, c->gtab);
-    auto up = [&](const std::vector<double>& v, DevBuf& b) -> bool {
+    auto up = [&](const std::vector<double>& v, DevBuf& b) -> lpb_status {
         b.bytes = v.size() * sizeof(double);
-        if (hipMalloc(&b.ptr, std::max<size_t>(b.bytes, 8)) != hipSuccess) return false;
-        return hipMemcpy(b.ptr, v.data(), b.bytes, hipMemcpyHostToDevice) == hipSuccess;
+        b.ptr = dev_alloc(c, std::max<size_t>(b.bytes, 8));
+        if (!b.ptr) return LPB_ENOMEM;
+        return hipMemcpy(b.ptr, v.data(), b.bytes, hipMemcpyHostToDevice) == hipSuccess ? LPB_OK : LPB_EDEVICE;
     };
     double glx[20], glw[20];
     gauss_legendre20(glx, glw);
-    if (!up(c->btab, c->d_btab) || !up(c->gtab, c->d_gtab) || !up(std::vector<double>(glx, glx + 20), c->d_glx) ||
-        !up(std::vector<double>(glw, glw + 20), c->d_glw))
-        return fail(nullptr, LPB_ENOMEM, "table upload failed");
-    if (hipMalloc(&c->d_flag.ptr, 64) != hipSuccess) return fail(nullptr, LPB_ENOMEM, "flag alloc failed");
+    for (auto t : {std::make_pair(&c->btab, &c->d_btab), std::make_pair(&c->gtab, &c->d_gtab)}) {
+        lpb_status s = up(*t.first, *t.second);
+        if (s != LPB_OK) return fail(nullptr, s, "table upload failed");
+    }
+    {
+        lpb_status s = up(std::vector<double>(glx, glx + 20), c->d_glx);
+        if (s == LPB_OK) s = up(std::vector<double>(glw, glw + 20), c->d_glw);
+        if (s != LPB_OK) return fail(nullptr, s, "table upload failed");
+    }
+    c->d_flag.ptr = dev_alloc(c, 256);
+    if (!c->d_flag.ptr) return fail(nullptr, LPB_ENOMEM, "flag alloc failed");
     if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess)
         return fail(nullptr, LPB_EDEVICE, "event create failed");
     for (auto& e : c->evs)
         if (hipEventCreate(&e) != hipSuccess) return fail(nullptr, LPB_EDEVICE, "event create failed");
-    *out = c.release();
+    *out = c;
+    guard.c = nullptr;
     return LPB_OK;
 }
 
@@ -1074,11 +1122,10 @@ void lpb_destroy(lpb_ctx* c)
     if (!c) return;
     (void)hipSetDevice(c->opt.device);
     (void)hipDeviceSynchronize();
-    free_bufs(c->plan_bufs);
-    free_bufs(c->op_bufs);
-    for (DevBuf* b : {&c->d_btab, &c->d_gtab, &c->d_glx, &c->d_glw, &c->d_flag})
-        if (b->ptr) (void)hipFree(b->ptr);
     drop_graph(c);
+    free_bufs(c, c->plan_bufs);
+    free_bufs(c, c->op_bufs);
+    for (DevBuf* b : {&c->d_btab, &c->d_gtab, &c->d_glx, &c->d_glw, &c->d_flag}) free_buf(c, *b);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);

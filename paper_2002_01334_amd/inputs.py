@@ -123,6 +123,35 @@ def three_layer(per_layer, seed: int = 0, clustered_fraction: float = 0.0, sigma
                           np.concatenate(ls))
 
 
+# A stack of up to five layers (general L, Sec. 2.1): interfaces every 1.2
+# below z = 0; the first three layers are the three-layer medium above.
+STACK_EPS = (1.0, 2.0, 4.0, 8.0, 3.0)
+STACK_LAM = (1.2, 1.5, 2.0, 0.8, 1.1)
+
+
+def stack(per_layer, nlayers: int, seed: int = 0) -> LayeredProblem:
+    """nlayers layers, interfaces z = 0, -1.2, -2.4, ...; eps and lambda the
+    first nlayers of STACK_EPS / STACK_LAM; per layer (an int or nlayers ints)
+    charges uniform in x, y in [-0.5, 0.5] and z in the 1.0-thick slab of the
+    layer at 0.1 clearance from its interfaces (the unbounded top and bottom
+    layers: 0.1 to 1.1 away from their interface); q ~ U[-1, 1], draws x, y,
+    z, q per charge, layers in order from one stream (three layers give
+    three_layer's charges)."""
+    if np.isscalar(per_layer):
+        per_layer = (int(per_layer),) * nlayers
+    d = np.array([round(-1.2 * k, 12) + 0.0 for k in range(nlayers - 1)])
+    rng = SplitMix64(seed)
+    xs, ys, zs, qs, ls = [], [], [], [], []
+    for l, n in enumerate(per_layer):
+        hi = 1.1 if l == 0 else round(d[l - 1] - 0.1, 12)
+        lo = round(hi - 1.0, 12)
+        x, y, z, q = _uniform_block(rng, n, (-0.5, -0.5, lo), (0.5, 0.5, hi))
+        xs.append(x); ys.append(y); zs.append(z); qs.append(q); ls.append(np.full(n, l, np.int32))
+    return LayeredProblem(np.array(STACK_EPS[:nlayers], float), np.array(STACK_LAM[:nlayers], float), d,
+                          np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(qs),
+                          np.concatenate(ls))
+
+
 def batch_system(k: int, nmin: float = 1e3, nmax: float = 5e4) -> LayeredProblem:
     """System k of the batched workload: seed 1000+k; N_total log-uniform in
     [nmin, nmax], split floor(N/3) per layer with the remainder in layer 0;

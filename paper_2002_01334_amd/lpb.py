@@ -25,9 +25,32 @@ _P = ctypes.c_void_p
 _PD = ctypes.POINTER(ctypes.c_double)
 
 
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
 class Options(ctypes.Structure):
     _fields_ = [("p", _I), ("leaf_cap", _I), ("precision", _I), ("quad_tol", _D), ("iface_tol", _D),
-                ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I), ("graph", _I), ("autotune", _I)]
+                ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I), ("graph", _I), ("autotune", _I),
+                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", _P)]
+
+
+class Allocator:
+    """Device-memory hook of lpb_options: alloc(nbytes) -> int pointer (0 when
+    it cannot) and free(ptr), wrapped as C callbacks (kept alive with the
+    context that uses them)."""
+
+    def __init__(self, alloc, free):
+        self.c_alloc = ALLOC_FN(lambda n, user: alloc(int(n)) or None)
+        self.c_free = FREE_FN(lambda ptr, user: free(int(ptr)))
+
+
+def torch_allocator(device=0, stream=None):
+    """An Allocator backed by PyTorch's caching allocator on `device`."""
+    import torch
+
+    return Allocator(lambda n: torch.cuda.caching_allocator_alloc(n, device=device, stream=stream),
+                     torch.cuda.caching_allocator_delete)
 
 
 class Stats(ctypes.Structure):
@@ -122,10 +145,14 @@ class Context:
     """One lpb context (one GPU, one stream)."""
 
     def __init__(self, p=10, leaf_cap=50, precision=LPB_FP64, quad_tol=1e-16, iface_tol=1e-9, device=0,
-                 stream=None, stages=3, timing=0, graph=1, autotune=1):
+                 stream=None, stages=3, timing=0, graph=1, autotune=1, allocator=None):
         L = load()
         opt = Options()
         L.lpb_default_options(ctypes.byref(opt))
+        self._allocator = allocator
+        if allocator is not None:
+            opt.alloc = allocator.c_alloc
+            opt.free = allocator.c_free
         opt.p = p
         opt.leaf_cap = leaf_cap
         opt.precision = precision

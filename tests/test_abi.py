@@ -59,6 +59,12 @@ def test_create_rejects_bad_options_without_touching_the_gpu(lpb):
     o.p, o.precision = 16, lpb.LPB_FP64
     h = ctypes.c_void_p()
     assert L.lpb_create(ctypes.byref(o), ctypes.byref(h)) == lpb.LPB_ERANGE and not h.value
+    # an allocator hook needs both functions
+    o = lpb.Options()
+    L.lpb_default_options(ctypes.byref(o))
+    o.alloc = lpb.ALLOC_FN(lambda n, user: None)
+    h = ctypes.c_void_p()
+    assert L.lpb_create(ctypes.byref(o), ctypes.byref(h)) == lpb.LPB_EINVAL and not h.value
     assert L.lpb_create(None, None) == lpb.LPB_EINVAL
 
 
