@@ -109,3 +109,38 @@ def test_refusing_allocator_gives_enomem_without_leaks(lpb):
         assert len(al.live) <= n_create + (n_build if k > n_create + n_build else 0)
         ctx.close()
         assert al.live == {}, k
+
+
+def test_memory_the_library_does_not_write_is_never_read(lpb):
+    """Every buffer of these contexts starts as 0xFF bytes (NaN in FP32 and
+    FP64): results must equal those of fresh hipMalloc memory bit for bit, in
+    both precisions, captured and eager, on a tree with tiled levels and on
+    one with reaction near-field pairs."""
+    import ctypes
+
+    import torch
+
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemset.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t]
+
+    def poisoned(n):
+        ptr = torch.cuda.caching_allocator_alloc(n, device=0)
+        assert hip.hipMemset(ptr, 0xFF, n) == 0 and hip.hipDeviceSynchronize() == 0
+        return ptr
+
+    hook = lpb.Allocator(poisoned, torch.cuda.caching_allocator_delete)
+    near = inputs.three_layer(150, seed=11)
+    for i, zz in {0: 0.002, 150: -0.003, 151: -1.198, 300: -1.202}.items():
+        near.z[i] = zz
+    for prob, p, cap in ((inputs.three_layer(10_000, seed=0), 7, 8), (near, 6, 8)):
+        for precision in (0, 1):
+            for graph in (1, 0):
+                out = []
+                for alloc in (None, hook):
+                    ctx = lpb.Context(p=p, leaf_cap=cap, precision=precision, graph=graph, autotune=graph,
+                                      allocator=alloc)
+                    ctx.set_layers(prob.eps, prob.lam, prob.d)
+                    ctx.build_tree(prob.x, prob.y, prob.z)
+                    out.append(ctx.evaluate(prob.q))
+                    ctx.close()
+                assert np.all(np.isfinite(out[1])) and np.array_equal(out[0], out[1]), (p, precision, graph)

@@ -366,7 +366,12 @@ def test_c4_batch_mixed_vs_fp64_per_system():
     assert worst <= 1e-6
     for k in (0, 7, 31):
         ctx, phi = run(L, probs[k], 8, 50)
+        st = ctx.stats()
         ctx.close()
+        if not np.array_equal(phi, o64[k]):
+            d = np.abs(phi - o64[k])
+            print(f"system {k}: {int((d > 0).sum())} of {len(d)} differ, max rel {d.max() / np.abs(phi).max():.3e}, "
+                  f"schedules {st['tile_schedule']},{st['batch_schedule']}")
         assert np.array_equal(phi, o64[k]), k
 
 
