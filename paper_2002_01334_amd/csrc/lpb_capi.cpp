@@ -458,28 +458,48 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     std::vector<int> p2m, l2p, pfree, rleaf, rslot, m2lb;
     for (size_t i = 0; i < P.sl_me.size(); ++i)
         if (P.sl_me[i] >= 0) p2m.push_back((int)i);
-    // free-space near field: work items of up to 64 targets of one leaf (dense
-    // leaves split over several blocks), most source-heavy first
-    std::vector<int> pfree_t0;
+    // free-space near field: a work item is T targets of one leaf on T x S
+    // lanes of a 64-lane block, each target's sources split S ways.  A leaf of
+    // n targets takes P items of T = ceil(n / P) targets, S = min(4, 64 / T),
+    // with P minimising the lane-passes over the sources P / S (ties: fewer
+    // items), so that few lanes idle (a leaf of 40 takes 2 items of 20 x 3
+    // instead of 2 passes of 32 lanes); most source-heavy items first
+    std::vector<int> pfree_t0, pfree_ts;
     {
-        std::vector<std::array<int64_t, 3>> wl;   // (-cost class, leaf, first target)
+        std::vector<std::array<int64_t, 4>> wl;   // (-cost class, leaf, first target, T | S << 8)
         for (size_t i = 0; i < P.tl_le.size(); ++i) {
             if (P.p2p_ptr[i + 1] == P.p2p_ptr[i]) continue;
             int64_t ns = 0;
             for (int k = P.p2p_ptr[i]; k < P.p2p_ptr[i + 1]; ++k) ns += P.sl_start[P.p2p_src[k] + 1] - P.sl_start[P.p2p_src[k]];
-            for (int t = P.tl_start[i]; t < P.tl_start[i + 1]; t += 64) {
-                // cost class: floor(log2(pairs)); within a class the leaf order (locality) is kept
-                int64_t pairs = ns * std::min(64, P.tl_start[i + 1] - t), cls = 0;
-                while ((pairs >> (cls + 1)) > 0) ++cls;
-                wl.push_back({-cls, (int64_t)i, (int64_t)t});
+            const int n = P.tl_start[i + 1] - P.tl_start[i];
+            int bestP = 1, bestS = 1;
+            double best = 1e30;
+            for (int np = 1; np <= 64 && np <= n; ++np) {
+                const int nt = (n + np - 1) / np;
+                if (nt > 64) continue;
+                const int S = std::max(1, std::min(4, 64 / nt));
+                const double cost = (double)np / S;
+                if (cost < best - 1e-12) {
+                    best = cost;
+                    bestP = np;
+                    bestS = S;
+                }
+            }
+            const int nt = (n + bestP - 1) / bestP;
+            for (int t = P.tl_start[i]; t < P.tl_start[i + 1]; t += nt) {
+                // cost class: floor(log2(lane passes)); within a class the leaf order (locality) is kept
+                int64_t passes = (ns + bestS - 1) / bestS, cls = 0;
+                while ((passes >> (cls + 1)) > 0) ++cls;
+                wl.push_back({-cls, (int64_t)i, (int64_t)t, (int64_t)(nt | (bestS << 8))});
             }
         }
-        std::stable_sort(wl.begin(), wl.end(), [](const std::array<int64_t, 3>& a, const std::array<int64_t, 3>& b) {
+        std::stable_sort(wl.begin(), wl.end(), [](const std::array<int64_t, 4>& a, const std::array<int64_t, 4>& b) {
             return a[0] < b[0];
         });
         for (auto& w : wl) {
             pfree.push_back((int)w[1]);
             pfree_t0.push_back((int)w[2]);
+            pfree_ts.push_back((int)w[3]);
         }
     }
     for (size_t i = 0; i < P.tl_le.size(); ++i) {
@@ -496,6 +516,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(l2p_leaves, l2p);
     UP(p2p_free_leaves, pfree);
     UP(p2p_free_t0, pfree_t0);
+    UP(p2p_free_ts, pfree_ts);
     UP(react_tgt_leaf, rleaf);
     UP(react_tgt_slot, rslot);
     UP(m2l_boxes, m2lb);

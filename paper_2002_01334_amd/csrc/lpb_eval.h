@@ -32,7 +32,8 @@ struct EvalArgs {
     int n_le, n_me;
     // work lists
     const int *p2m_leaves, *l2p_leaves, *p2p_free_leaves;
-    const int* p2p_free_t0;     // first target of each free near-field work item (up to 64 targets)
+    const int* p2p_free_t0;     // first target of each free near-field work item
+    const int* p2p_free_ts;     // its target count T (<= 64) | source splits S << 8 (T S <= 64 lanes)
     const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;
     // batched translations (M2M, L2L, untiled V-list pairs): see Plan
     const int *bw_term_ptr, *bw_op, *bw_src, *bw_dst;

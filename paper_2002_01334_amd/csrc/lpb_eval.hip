@@ -430,7 +430,7 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
     const int leaf = A.p2p_free_leaves[blockIdx.x];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const T lamk = (sizeof(T) == 4) ? (T)(F.lam_t * 1.4426950408889634) : (T)F.lam_t;
-    const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + 64);
+    const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + (A.p2p_free_ts[blockIdx.x] & 255));
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
     const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
@@ -532,118 +532,123 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
     const int leaf = A.p2p_free_leaves[blockIdx.x];
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
     const double sc = F.lam_t * 1.4426950408889634;   // lambda log2(e)
-    const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + 64);
+    // T targets on T x S lanes: lane = target tl + T * split s; split s takes
+    // the staged sources j = s (mod S)
+    const int ts = A.p2p_free_ts[blockIdx.x], T = ts & 255, S = ts >> 8;
+    const int t0 = A.p2p_free_t0[blockIdx.x], t1 = min(A.tl_start[leaf + 1], t0 + T);
     const float thr2 = (float)((A.tl_h[leaf] * sc / 16.0) * (A.tl_h[leaf] * sc / 16.0));
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
-    const int lane = threadIdx.x, half = lane >> 5, tl = lane & 31;
+    const int lane = threadIdx.x, s = lane / T, tl = lane - s * T;
     const int k0 = A.p2p_ptr[leaf], k1 = A.p2p_ptr[leaf + 1];
     const int nself = A.sl_start[A.p2p_src[k0] + 1] - A.sl_start[A.p2p_src[k0]];
-    for (int base = t0; base < t1; base += 32) {
-        const int j = base + tl;
-        const bool act = j < t1;
-        // target offset (hi + lo), scaled in FP64 and split again
-        const double TX = act ? mul_rn((double)A.t_ux[j] + (double)A.t_lx[j], sc) : 0.0;
-        const double TY = act ? mul_rn((double)A.t_uy[j] + (double)A.t_ly[j], sc) : 0.0;
-        const double TZ = act ? mul_rn((double)A.t_uz[j] + (double)A.t_lz[j], sc) : 0.0;
-        const float xh = (float)TX, yh = (float)TY, zh = (float)TZ;
-        const float xl = (float)(TX - (double)xh), yl = (float)(TY - (double)yh), zl = (float)(TZ - (double)zh);
-        float sum = 0.f, comp = 0.f;
-        auto kahan = [&](float v) {
-            float y = v - comp;
-            float t = sum + y;
-            comp = (t - sum) - y;
-            sum = t;
-        };
-        int k = k0, s = A.sl_start[A.p2p_src[k0]], staged = 0;
-        while (k < k1) {
-            // stage up to SMAX sources, continuing across source leaves
-            int n = 0;
-            __syncthreads();
-            while (k < k1 && n < SMAX) {
-                const int sl_i = A.p2p_src[k];
-                const int se = A.sl_start[sl_i + 1];
-                const int take = min(se - s, SMAX - n);
-                const double ox = A.sl_ctr[3 * sl_i] - tcx, oy = A.sl_ctr[3 * sl_i + 1] - tcy,
-                             oz = A.sl_ctr[3 * sl_i + 2] - tcz;
-                for (int i = lane; i < take; i += 64) {
-                    const double X = mul_rn(((double)A.s_ux[s + i] + (double)A.s_lx[s + i]) + ox, sc);
-                    const double Y = mul_rn(((double)A.s_uy[s + i] + (double)A.s_ly[s + i]) + oy, sc);
-                    const double Z = mul_rn(((double)A.s_uz[s + i] + (double)A.s_lz[s + i]) + oz, sc);
-                    const float hx = (float)X, hy = (float)Y, hz = (float)Z;
-                    sh[n + i] = make_float4(hx, hy, hz, A.qs[s + i]);
-                    sl[n + i] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), 0.f);
-                }
-                n += take;
-                s += take;
-                if (s >= se) {
-                    ++k;
-                    if (k < k1) s = A.sl_start[A.p2p_src[k]];
-                }
+    const int j = t0 + tl;
+    const bool act = s < S && j < t1;
+    // target offset (hi + lo), scaled in FP64 and split again
+    const double TX = act ? mul_rn((double)A.t_ux[j] + (double)A.t_lx[j], sc) : 0.0;
+    const double TY = act ? mul_rn((double)A.t_uy[j] + (double)A.t_ly[j], sc) : 0.0;
+    const double TZ = act ? mul_rn((double)A.t_uz[j] + (double)A.t_lz[j], sc) : 0.0;
+    const float xh = (float)TX, yh = (float)TY, zh = (float)TZ;
+    const float xl = (float)(TX - (double)xh), yl = (float)(TY - (double)yh), zl = (float)(TZ - (double)zh);
+    float sum = 0.f, comp = 0.f;
+    auto kahan = [&](float v) {
+        float y = v - comp;
+        float t = sum + y;
+        comp = (t - sum) - y;
+        sum = t;
+    };
+    int k = k0, src = A.sl_start[A.p2p_src[k0]], staged = 0;
+    while (k < k1) {
+        // stage up to SMAX sources, continuing across source leaves
+        int n = 0;
+        __syncthreads();
+        while (k < k1 && n < SMAX) {
+            const int sl_i = A.p2p_src[k];
+            const int se = A.sl_start[sl_i + 1];
+            const int take = min(se - src, SMAX - n);
+            const double ox = A.sl_ctr[3 * sl_i] - tcx, oy = A.sl_ctr[3 * sl_i + 1] - tcy, oz = A.sl_ctr[3 * sl_i + 2] - tcz;
+            for (int i = lane; i < take; i += 64) {
+                const double X = mul_rn(((double)A.s_ux[src + i] + (double)A.s_lx[src + i]) + ox, sc);
+                const double Y = mul_rn(((double)A.s_uy[src + i] + (double)A.s_ly[src + i]) + oy, sc);
+                const double Z = mul_rn(((double)A.s_uz[src + i] + (double)A.s_lz[src + i]) + oz, sc);
+                const float hx = (float)X, hy = (float)Y, hz = (float)Z;
+                sh[n + i] = make_float4(hx, hy, hz, A.qs[src + i]);
+                sl[n + i] = make_float4((float)(X - (double)hx), (float)(Y - (double)hy), (float)(Z - (double)hz), 0.f);
             }
-            __syncthreads();
-            if (act) {
-                // staged sources below nself belong to the target's own leaf
-                const int ns = min(max(nself - staged, 0), n);
-                auto full_r2 = [&](int i) {
-                    const float4 hs = sh[i], ls = sl[i];
-                    const float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y),
-                                dz = (zh - hs.z) + (zl - ls.z);
-                    return dx * dx + dy * dy + dz * dz;
-                };
-                for (int jj = half; jj < ns; jj += 2) {
-                    const float r2 = full_r2(jj);
-                    if (r2 > 0.f) kahan(p2p_term32(sh[jj].w, r2));
-                }
-                // the main loop's counter is wave-uniform (each half starts at
-                // its own parity within it); the tails continue per lane
-                const int par = (half - ns) & 1;
-                const float4* shp = sh + par;
-                int ju = ns;
-                for (; ju + 15 < n; ju += 16) {
-                    float w[8], r2[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const float4 hs = shp[ju + 2 * u];
-                        const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
-                        w[u] = hs.w;
-                        r2[u] = dx * dx + dy * dy + dz * dz;
-                    }
-                    const float mn = fminf(fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3])),
-                                           fminf(fminf(r2[4], r2[5]), fminf(r2[6], r2[7])));
-                    if (mn < thr2) {
-#pragma unroll
-                        for (int u = 0; u < 8; ++u) r2[u] = full_r2(ju + par + 2 * u);
-                    }
-                    float s8 = 0.f;
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) s8 = p2p_fma32(w[u], r2[u], s8);
-                    kahan(s8);
-                }
-                int jj = ju + par;
-                for (; jj + 6 < n; jj += 8) {
-                    float w[4], r2[4];
-#pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        const float4 hs = sh[jj + 2 * u];
-                        const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
-                        w[u] = hs.w;
-                        r2[u] = dx * dx + dy * dy + dz * dz;
-                    }
-                    if (fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3])) < thr2) {
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) r2[u] = full_r2(jj + 2 * u);
-                    }
-                    kahan((p2p_term32(w[0], r2[0]) + p2p_term32(w[1], r2[1])) +
-                          (p2p_term32(w[2], r2[2]) + p2p_term32(w[3], r2[3])));
-                }
-                for (; jj < n; jj += 2) kahan(p2p_term32(sh[jj].w, full_r2(jj)));
+            n += take;
+            src += take;
+            if (src >= se) {
+                ++k;
+                if (k < k1) src = A.sl_start[A.p2p_src[k]];
             }
-            staged += n;
         }
-        // combine the two halves (lane l and l+32 share a target)
-        const float other = __shfl_xor(sum - comp, 32, 64);
-        if (act && half == 0) A.parts[A.t_out[j]] += ((double)(sum - comp) + (double)other) * sc / (4.0 * LPB_PI * F.eps_t);
+        __syncthreads();
+        if (act) {
+            // staged sources below nself belong to the target's own leaf
+            const int ns = min(max(nself - staged, 0), n);
+            auto full_r2 = [&](int i) {
+                const float4 hs = sh[i], ls = sl[i];
+                const float dx = (xh - hs.x) + (xl - ls.x), dy = (yh - hs.y) + (yl - ls.y),
+                            dz = (zh - hs.z) + (zl - ls.z);
+                return dx * dx + dy * dy + dz * dz;
+            };
+            for (int jj = s; jj < ns; jj += S) {
+                const float r2 = full_r2(jj);
+                if (r2 > 0.f) kahan(p2p_term32(sh[jj].w, r2));
+            }
+            // the main loop's counter is wave-uniform (each split starts at its
+            // own residue within it); the tails continue per lane
+            const int par = ((s - ns) % S + S) % S;
+            const float4* shp = sh + par;
+            int ju = ns;
+            for (; ju + 8 * S - 1 < n; ju += 8 * S) {
+                float w[8], r2[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const float4 hs = shp[ju + S * u];
+                    const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
+                    w[u] = hs.w;
+                    r2[u] = dx * dx + dy * dy + dz * dz;
+                }
+                const float mn = fminf(fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3])),
+                                       fminf(fminf(r2[4], r2[5]), fminf(r2[6], r2[7])));
+                if (mn < thr2) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) r2[u] = full_r2(ju + par + S * u);
+                }
+                float s8 = 0.f;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) s8 = p2p_fma32(w[u], r2[u], s8);
+                kahan(s8);
+            }
+            int jj = ju + par;
+            for (; jj + 3 * S < n; jj += 4 * S) {
+                float w[4], r2[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 hs = sh[jj + S * u];
+                    const float dx = xh - hs.x, dy = yh - hs.y, dz = zh - hs.z;
+                    w[u] = hs.w;
+                    r2[u] = dx * dx + dy * dy + dz * dz;
+                }
+                if (fminf(fminf(r2[0], r2[1]), fminf(r2[2], r2[3])) < thr2) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) r2[u] = full_r2(jj + S * u);
+                }
+                kahan((p2p_term32(w[0], r2[0]) + p2p_term32(w[1], r2[1])) +
+                      (p2p_term32(w[2], r2[2]) + p2p_term32(w[3], r2[3])));
+            }
+            for (; jj < n; jj += S) kahan(p2p_term32(sh[jj].w, full_r2(jj)));
+        }
+        staged += n;
     }
+    // the S partial sums of a target, added in split order (FP64)
+    const float mine = sum - comp;
+    double tot = (double)mine;
+    for (int q = 1; q < 4; ++q) {
+        const float other = __shfl(mine, min(tl + q * T, 63), 64);
+        if (q < S) tot += (double)other;
+    }
+    if (act && s == 0) A.parts[A.t_out[j]] += tot * sc / (4.0 * LPB_PI * F.eps_t);
 }
 
 // ---------------------------------------------------------------------------
