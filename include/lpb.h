@@ -82,6 +82,8 @@ typedef struct {
     int autotune;           /* 1 = time the candidate block-to-work schedules of the matrix-core M2L
                                kernels on the first evaluate after a change and keep the fastest
                                (results do not depend on the choice); default 1 */
+    int schedule;           /* with autotune = 0, the schedules to use: tile | batch << 4, with the codes of
+                               lpb_stats.tile_schedule (0..3) and batch_schedule (0..7); default 0 */
     /* Device-memory hook (e.g. a framework's caching allocator).  When alloc is
      * not NULL, every device buffer the context holds (tables, tree, lists,
      * expansions, operators, partial potentials) comes from
@@ -120,7 +122,10 @@ typedef struct {
                                contiguous run of tiles (tiles sharing operators share that XCD's L2); bit 1 =
                                blocks of one wave per 16-row block instead of four waves (per-offset form only:
                                FP64, or mixed precision with p < 5 or p > 15) */
-    int batch_schedule;     /* the same choice for the batched translations */
+    int batch_schedule;     /* the choice for the batched translations (M2M, L2L, untiled M2L): bit 0 as
+                               above; bits 1-2 = 0 one block per work item, k = 1..3 a grid of 256 x 2^k
+                               resident blocks that loop over the items, each gathering the next item's
+                               sources during the current product */
     double t_tune_ms;       /* time spent by the last schedule autotuning */
     int64_t n_m2l_tiles;    /* tiles (64 target boxes, one child octant) of the tiled M2L */
     /* units of work of each stage (the plan's counts, for work models):
@@ -135,7 +140,7 @@ typedef struct {
 void lpb_default_options(lpb_options* opt);
 
 /* Create a context on opt->device.  opt may be NULL (defaults).
- * Errors: LPB_EINVAL (out == NULL, alloc without free), LPB_ERANGE (p outside
+ * Errors: LPB_EINVAL (out == NULL, alloc without free, schedule codes out of range), LPB_ERANGE (p outside
  * 1..LPB_MAX_P, or above LPB_MAX_P_FP64 with precision LPB_FP64; leaf_cap < 1),
  * LPB_EDEVICE, LPB_ENOMEM (the allocator refused the context's tables).  On
  * error *out is NULL and everything allocated so far has been released. */

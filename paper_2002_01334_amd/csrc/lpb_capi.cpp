@@ -366,10 +366,28 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     UP(bw_src, P.bw_src);
     UP(bw_dst, P.bw_dst);
     UP(bw_xc, P.bw_xc);
-    UP(bw_xa, P.bw_xa);
+    {
+        // cos and sin (m phi), m = 0..p, of the kXfDirs V-list directions:
+        // e^{i phi} = (-dx - i dy) / |(dx, dy)| (phi = 0 for dx = dy = 0), powers in long double
+        std::vector<T> rt((size_t)kXfDirs * (P.p + 1) * 2);
+        for (int dir = 0; dir < kXfDirs; ++dir) {
+            const long double dx = dir / 7 - 3, dy = dir % 7 - 3, r = std::sqrt(dx * dx + dy * dy);
+            const long double c1 = r > 0 ? -dx / r : 1.0L, s1 = r > 0 ? -dy / r : 0.0L;
+            long double c = 1.0L, sn = 0.0L;
+            for (int m = 0; m <= P.p; ++m) {
+                rt[((size_t)dir * (P.p + 1) + m) * 2] = (T)c;
+                rt[((size_t)dir * (P.p + 1) + m) * 2 + 1] = (T)sn;
+                const long double c2 = c * c1 - sn * s1;
+                sn = sn * c1 + c * s1;
+                c = c2;
+            }
+        }
+        UP(rot_tab, rt);
+    }
     UP(m2l_ptr, P.m2l_ptr);
     UP(m2l_src, P.m2l_src);
     UP(m2l_op, P.m2l_op);
+    UP(m2l_xc, P.m2l_xc);
     UP(p2p_ptr, P.p2p_ptr);
     UP(p2p_src, P.p2p_src);
     UP(rp_ptr, P.rp_ptr);
@@ -744,7 +762,9 @@ lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
     for (int which = 0; which < 2; ++which) {
         float best = 1e30f;
         int pick = 0;
-        const int ncand = which == 0 ? 4 : 2;   // tiled M2L: schedule bit 0, wide-block variant bit 1
+        // tiled M2L: schedule bit 0, wide-block variant bit 1; batched translations:
+        // order bit 0, resident-block grid bits 1-2
+        const int ncand = which == 0 ? 4 : 8;
         for (int sc = 0; sc < ncand; ++sc) {
             *field[which] = sc;
             float tmin = 1e30f;
@@ -778,6 +798,11 @@ lpb_status run_eval_t(lpb_ctx* c, EvalArgs<T>& A)
         if (c->opt.autotune) {
             lpb_status s = autotune<T>(c, A);
             if (s != LPB_OK) return s;
+        } else {
+            A.tile_sched = c->opt.schedule & 15;
+            A.batch_sched = (c->opt.schedule >> 4) & 15;
+            c->stats.tile_schedule = A.tile_sched;
+            c->stats.batch_schedule = A.batch_sched;
         }
         c->tune_needed = false;
         drop_graph(c);
@@ -871,6 +896,8 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (!(o.quad_tol > 0.0 && o.quad_tol < 1e-3)) return fail(nullptr, LPB_EINVAL, "quad_tol out of range");
     if (!(o.iface_tol >= 0.0)) return fail(nullptr, LPB_EINVAL, "iface_tol must be >= 0");
     if (!o.alloc != !o.free) return fail(nullptr, LPB_EINVAL, "alloc and free must be set together");
+    if (o.schedule < 0 || (o.schedule & 15) > 3 || (o.schedule >> 4) > 7)
+        return fail(nullptr, LPB_EINVAL, "schedule codes out of range");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(nullptr, LPB_EDEVICE, "no HIP device available");

@@ -35,10 +35,11 @@ struct EvalArgs {
     const int* p2p_free_t0;     // first target of each free near-field work item
     const int* p2p_free_ts;     // its target count T (<= 64) | source splits S << 8 (T S <= 64 lanes)
     const int *m2l_boxes, *m2l_ptr, *m2l_src, *m2l_op;
+    const int* m2l_xc;          // per untiled V-list pair: result transform (0..7 reflection, kXfRotate + dir rotation)
     // batched translations (M2M, L2L, untiled V-list pairs): see Plan
     const int *bw_term_ptr, *bw_op, *bw_src, *bw_dst;
-    const int* bw_xc;           // per column transform code (-1 none, 0..7 reflection, kXfRotate rotation)
-    const double* bw_xa;        // per column rotation angle
+    const int* bw_xc;           // per column transform code (-1 none, 0..7 reflection, kXfRotate + dir rotation)
+    const T* rot_tab;           // [kXfDirs][p+1][2]: cos, sin (m phi) of each V-list direction
     T* m2l_scratch;     // one KP row per untiled V-list pair
     const int *p2p_ptr, *p2p_src;
     const int *rp_ptr, *rp_fmm, *rp_src;   // reaction near field: per target leaf, (FMM, source leaf)

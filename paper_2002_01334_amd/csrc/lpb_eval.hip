@@ -5,6 +5,7 @@
 // ratios are always formed in double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lpb_eval_dev.h"
@@ -130,19 +131,20 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
 // load during the current term's products.
 // In-LDS per-column transform of a staged block B[k][j] (KP rows, NTP
 // stride): reflection signs D (code 0..7) or the rotation of every order-m
-// (Re, Im) pair by +m phi (sources) or -m phi (results) (code kXfRotate).
+// (Re, Im) pair by +m phi (sources) or -m phi (results) (code kXfRotate +
+// dir, phi the azimuth of the V-list direction dir).
 // Every thread of the 256 takes column j = tid & 63 and a quarter of the rows.
-// cs[m * 128 + j] = cos(m phi_j), cs[m * 128 + 64 + j] = sin(m phi_j), m = 1..p
+// cs[m * 128 + j] = cos(m phi_j), cs[m * 128 + 64 + j] = sin(m phi_j), m = 1..p,
+// copied from the direction table rot[dir][m][cos, sin]
 template <typename T>
-__device__ inline void column_trig(T* cs, int p, int code, double phi)
+__device__ inline void column_trig(T* cs, int p, int code, const T* __restrict__ rot)
 {
     const int j = threadIdx.x & 63, part = threadIdx.x >> 6;
-    if (code != kXfRotate) return;
+    if (code < kXfRotate) return;
+    const T* r = rot + (size_t)(code - kXfRotate) * (p + 1) * 2;
     for (int m = 1 + part; m <= p; m += 4) {
-        double sd, cd;
-        sincos((double)m * phi, &sd, &cd);
-        cs[m * 128 + j] = (T)cd;
-        cs[m * 128 + 64 + j] = (T)sd;
+        cs[m * 128 + j] = r[2 * m];
+        cs[m * 128 + 64 + j] = r[2 * m + 1];
     }
 }
 
@@ -157,27 +159,39 @@ __device__ inline void column_xform(T* Bs, int NTP, int p, int K, int KP, int co
         for (int k = part; k < K; k += 4) Bs[k * NTP + j] *= sg[k];
         return;
     }
-    int q = 0;
-    for (int n = 1; n <= p; ++n)
-        for (int m = 1; m <= n; ++m, ++q) {
-            if ((q & 3) != part) continue;
-            const T c = cs[m * 128 + j], sn = result ? -cs[m * 128 + 64 + j] : cs[m * 128 + 64 + j];
-            T& re = Bs[ire(n, m) * NTP + j];
-            T& im = Bs[iim(n, m) * NTP + j];
-            const T a = re, b = im;
-            re = a * c - b * sn;
-            im = a * sn + b * c;
-        }
+    // the (n, m >= 1) pairs in order n = 1.., m = 1..n; this thread takes
+    // every fourth, starting at number `part`
+    int n = 1, m = 1;
+    for (int k = 0; k < part; ++k)
+        if (++m > n) { ++n; m = 1; }
+    while (n <= p) {
+        const T c = cs[m * 128 + j], sn = result ? -cs[m * 128 + 64 + j] : cs[m * 128 + 64 + j];
+        T& re = Bs[ire(n, m) * NTP + j];
+        T& im = Bs[iim(n, m) * NTP + j];
+        const T a = re, b = im;
+        re = a * c - b * sn;
+        im = a * sn + b * c;
+        for (int k = 0; k < 4; ++k)
+            if (++m > n) { ++n; m = 1; }
+    }
 }
 
 // RBF = ceil(KB / 4): the row blocks per wave of a whole item, which also
 // sizes the source staging; GY blocks along y split them (RB per wave each).
+// XF (untiled V-list pairs): the sources are brought into the frame of the
+// stored operator here; the results stay in that frame (the reduction over a
+// box's pairs applies the inverse transform).
+// A block takes the work items it, it + gridDim.x, ... of the launch (one
+// each when the grid covers them all; a smaller grid keeps its blocks
+// resident and gathers the next item's first sources during the current
+// item's last product and write-back).  Items are independent, so results
+// do not depend on the grid or the order.
 template <typename T, int RBF, bool XF, int GY>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
-                                                 const int* __restrict__ dst, int wbase, int mode, int K, int KP,
-                                                 const T* __restrict__ pool_swz, int zrow, int sched,
-                                                 const int* __restrict__ xcode, const double* __restrict__ xang,
+                                                 const int* __restrict__ dst, int wbase, int nitems, int mode, int K,
+                                                 int KP, const T* __restrict__ pool_swz, int zrow, int sched,
+                                                 const int* __restrict__ xcode, const T* __restrict__ rot,
                                                  const T* __restrict__ refl, int p)
 {
     typedef typename Vec4<T>::type V4;
@@ -188,88 +202,82 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     extern __shared__ unsigned char smem_raw[];
     T* Bs = reinterpret_cast<T*>(smem_raw);   // [KP][NTP]
     const int KB = KP / 16;
-    const int wi = wbase + sched_index(blockIdx.x, gridDim.x, sched);
-    const int t0 = term_ptr[wi], t1 = term_ptr[wi + 1];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     // row-block group of this wave: blocks of a work item along y split the
     // output rows (every block stages all of the sources)
     const int wy = (GY > 1 ? (int)blockIdx.y * 4 : 0) + w;
-    const int gj = tid >> 2, gpart = tid & 3;
+    // source staging: thread (column gj, part gpart) moves coefficients
+    // 16 i + 4 gpart + e of column gj; the lanes of a wave take 64 columns, so
+    // their LDS stores fall in distinct banks
+    const int gj = tid & 63, gpart = tid >> 6;
     V4 acc[RB][CB], tot[RB][CB], cmp[RB][CB];
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
     V4 greg[GMAX];
     // XF: per-column transform code and, for rotations, cos / sin (m phi) after B in LDS
     T* trig = Bs + (size_t)KP * NTP;
-    const int xc = XF ? xcode[(size_t)wi * NT + (tid & 63)] : -1;
-    if (XF) column_trig<T>(trig, p, xc, xang[(size_t)wi * NT + (tid & 63)]);
     auto fetch = [&](int t) {
         const int sidx = term_src[(size_t)t * NT + gj];
         const T* src = in + (size_t)(sidx < 0 ? zrow : sidx) * KP + 4 * gpart;   // missing: the zero row
 #pragma unroll
         for (int i = 0; i < GMAX; ++i) greg[i] = (i < KB) ? *reinterpret_cast<const V4*>(src + 16 * i) : V4{0, 0, 0, 0};
     };
-    if (t0 < t1) fetch(t0);
-    for (int t = t0; t < t1; ++t) {
-        __syncthreads();
+    auto item = [&](int it) { return wbase + sched_index(it, nitems, sched & 1); };
+    bool staged_next = false;
+    for (int it = blockIdx.x; it < nitems; it += gridDim.x) {
+        const int wi = item(it);
+        const int t0 = term_ptr[wi], t1 = term_ptr[wi + 1];
+        const int nit = it + (int)gridDim.x;
 #pragma unroll
-        for (int i = 0; i < GMAX; ++i) {
-            if (i < KB) {
+        for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-                for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
-            }
-        }
-        __syncthreads();
-        if (XF) {
-            // sources into the frame of the stored operator
-            column_xform<T>(Bs, NTP, p, K, KP, xc, trig, refl, false);
+            for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
+        const int xc = XF ? xcode[(size_t)wi * NT + (tid & 63)] : -1;
+        if (XF) column_trig<T>(trig, p, xc, rot);
+        if (t0 < t1 && !staged_next) fetch(t0);
+        staged_next = false;
+        for (int t = t0; t < t1; ++t) {
             __syncthreads();
+#pragma unroll
+            for (int i = 0; i < GMAX; ++i) {
+                if (i < KB) {
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Bs[(16 * i + 4 * gpart + e) * NTP + gj] = greg[i][e];
+                }
+            }
+            __syncthreads();
+            if (XF) {
+                // sources into the frame of the stored operator
+                column_xform<T>(Bs, NTP, p, K, KP, xc, trig, refl, false);
+                __syncthreads();
+            }
+            const T* Aw = pool_swz + (size_t)term_op[t] * KP * KP;
+            if (t + 1 < t1) {
+                fetch(t + 1);
+            } else if (nit < nitems) {
+                // the next item's first sources load during this product
+                const int nwi = item(nit);
+                if (term_ptr[nwi] < term_ptr[nwi + 1]) {
+                    fetch(term_ptr[nwi]);
+                    staged_next = true;
+                }
+            }
+            mma_block<T, RB, CB>(Aw, Bs, NTP, KB, wy, l, acc);
+            accumulate<T, RB, CB>(acc, tot, cmp);
         }
-        const T* Aw = pool_swz + (size_t)term_op[t] * KP * KP;
-        if (t + 1 < t1) fetch(t + 1);
-        mma_block<T, RB, CB>(Aw, Bs, NTP, KB, wy, l, acc);
-        accumulate<T, RB, CB>(acc, tot, cmp);
-    }
-    if (XF) {
-        // results back from the operator's frame, through LDS, then stored row-contiguously
-        __syncthreads();
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
-            int rbg = w * RB + rb;
+            int rbg = wy * RB + rb;
             if (rbg >= KB) continue;
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb)
+            for (int cb = 0; cb < CB; ++cb) {
+                const int d = dst[(size_t)wi * NT + cb * 16 + (l & 15)];
+                if (d < 0) continue;
 #pragma unroll
-                for (int r = 0; r < 4; ++r) Bs[(rbg * 16 + mfma_row(T(0), l, r)) * NTP + cb * 16 + (l & 15)] = tot[rb][cb][r];
-        }
-        __syncthreads();
-        column_xform<T>(Bs, NTP, p, K, KP, xc, trig, refl, true);
-        __syncthreads();
-        for (int e = tid; e < NT * K; e += 256) {
-            const int j = e / K, row = e - j * K;
-            const int d = dst[(size_t)wi * NT + j];
-            if (d < 0) continue;
-            if (mode == 0) out[(size_t)d * KP + row] = Bs[row * NTP + j];
-            else out[(size_t)d * KP + row] += Bs[row * NTP + j];
-        }
-        return;
-    }
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) {
-        int rbg = wy * RB + rb;
-        if (rbg >= KB) continue;
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-            const int d = dst[(size_t)wi * NT + cb * 16 + (l & 15)];
-            if (d < 0) continue;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                int row = rbg * 16 + mfma_row(T(0), l, r);
-                if (row >= K) continue;
-                if (mode == 0) out[(size_t)d * KP + row] = tot[rb][cb][r];
-                else out[(size_t)d * KP + row] += tot[rb][cb][r];
+                for (int r = 0; r < 4; ++r) {
+                    int row = rbg * 16 + mfma_row(T(0), l, r);
+                    if (row >= K) continue;
+                    if (mode == 0) out[(size_t)d * KP + row] = tot[rb][cb][r];
+                    else out[(size_t)d * KP + row] += tot[rb][cb][r];
+                }
             }
         }
     }
@@ -285,17 +293,21 @@ static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, 
     const int RB = (KB + 3) / 4;
     const int gy = (!XF && n < 512 && RB >= 2) ? 2 : 1;
     const size_t sm = sizeof(T) * ((size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8)) + (XF ? (size_t)(A.p + 1) * 128 : 0));
-    dim3 g(n, gy), b(256);
+    // schedule bits 1-2: 0 one block per item, else 256 CUs x {2, 4, 8} resident blocks looping over the items
+    const int pers = (A.batch_sched >> 1) & 3;
+    const int gx = pers == 0 ? n : std::min(n, 256 * (1 << pers));
+    dim3 g(gx, gy), b(256);
 #define LPB_BATCHED(R)                                                                                                      \
     if constexpr (!XF) {                                                                                                    \
         if (gy == 2) {                                                                                                      \
             hipLaunchKernelGGL((k_batched<T, R, XF, 2>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, \
-                               w0, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.bw_xa, A.refl_sign, A.p);   \
+                               w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab, A.refl_sign,  \
+                               A.p);                                                                                        \
             break;                                                                                                          \
         }                                                                                                                   \
     }                                                                                                                       \
-    hipLaunchKernelGGL((k_batched<T, R, XF, 1>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, mode, \
-                       A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.bw_xa, A.refl_sign, A.p)
+    hipLaunchKernelGGL((k_batched<T, R, XF, 1>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, n, \
+                       mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab, A.refl_sign, A.p)
     switch (RB) {
     case 1: LPB_BATCHED(1); break;
     case 2: LPB_BATCHED(2); break;
@@ -314,14 +326,25 @@ static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, in
 }
 
 // V-list pairs outside the tiled levels: LE[box] += sum of the box's pair rows
-// of the scratch, in list order (deterministic); in FP32 the sum is
-// compensated (Kahan), so it keeps the error of a single pair's product
+// of the scratch, in list order (deterministic), each brought back from the
+// frame of its stored operator (reflection signs, or the rotation of every
+// order-m (Re, Im) pair by -m phi, which needs the partner row of the pair).
+// A thread takes one coefficient row, four pairs' loads in flight at a time.
+// In FP32 the sum is compensated (Kahan), so it keeps the error of a single
+// pair's product.
 template <typename T>
 __global__ void k_m2l_reduce(EvalArgs<T> A)
 {
     const int le = A.m2l_boxes[blockIdx.x];
     const int k0 = A.m2l_ptr[le], k1 = A.m2l_ptr[le + 1];
+    const int p = A.p;
     for (int row = threadIdx.x; row < A.K; row += blockDim.x) {
+        // (n, m) of the row, whether it is the Im part, and its partner row
+        int n = 0;
+        while ((n + 1) * (n + 1) <= row) ++n;
+        const int idx = row - n * n, m = (idx + 1) / 2;
+        const bool im_row = m > 0 && (idx & 1) == 0;
+        const int partner = m == 0 ? row : (im_row ? row - 1 : row + 1);
         T s = T(0), c = T(0);
         auto add = [&](T a) {
             if constexpr (sizeof(T) == 4) {
@@ -332,17 +355,28 @@ __global__ void k_m2l_reduce(EvalArgs<T> A)
                 s += a;
             }
         };
-        // four rows' loads in flight at a time; the sum keeps list order
+        auto term = [&](int code, T own, T other) {
+            if (code < kXfRotate) return own * A.refl_sign[(size_t)code * A.KP + row];
+            if (m == 0) return own;
+            const T* r = A.rot_tab + ((size_t)(code - kXfRotate) * (p + 1) + m) * 2;
+            // Re' = Re c + Im s, Im' = Im c - Re s
+            return im_row ? own * r[0] - other * r[1] : own * r[0] + other * r[1];
+        };
         int k = k0;
         for (; k + 4 <= k1; k += 4) {
-            const T a0 = A.m2l_scratch[(size_t)k * A.KP + row], a1 = A.m2l_scratch[(size_t)(k + 1) * A.KP + row],
-                    a2 = A.m2l_scratch[(size_t)(k + 2) * A.KP + row], a3 = A.m2l_scratch[(size_t)(k + 3) * A.KP + row];
-            add(a0);
-            add(a1);
-            add(a2);
-            add(a3);
+            int code[4];
+            T own[4], other[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                code[u] = A.m2l_xc[k + u];
+                own[u] = A.m2l_scratch[(size_t)(k + u) * A.KP + row];
+                other[u] = A.m2l_scratch[(size_t)(k + u) * A.KP + partner];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) add(term(code[u], own[u], other[u]));
         }
-        for (; k < k1; ++k) add(A.m2l_scratch[(size_t)k * A.KP + row]);
+        for (; k < k1; ++k)
+            add(term(A.m2l_xc[k], A.m2l_scratch[(size_t)k * A.KP + row], A.m2l_scratch[(size_t)k * A.KP + partner]));
         A.le[(size_t)le * A.KP + row] += s;
     }
 }

@@ -108,12 +108,13 @@ __device__ __attribute__((always_inline)) inline void mma_block(const T* __restr
     for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
-    // row blocks past KB repeat the last one (their rows are >= K, never stored)
+    // row blocks past KB (their rows are >= K, never stored) are skipped: the
+    // test is wave-uniform
     auto load = [&](V4 (&a)[RB], int s4) {
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
             const int rbg = min(w * RB + rb, KB - 1);
-            a[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + min(s4, KB - 1)) * 64 + l) * 4);
+            if (w * RB + rb < KB) a[rb] = *reinterpret_cast<const V4*>(Aw + (((size_t)rbg * KB + min(s4, KB - 1)) * 64 + l) * 4);
         }
     };
     auto slab = [&](const V4 (&a4)[RB], int s4) {
@@ -125,8 +126,10 @@ __device__ __attribute__((always_inline)) inline void mma_block(const T* __restr
             for (int cb = 0; cb < CB; ++cb) b[cb] = Bs[kk * NTP + cb * 16 + (l & 15)];
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
+                if (w * RB + rb < KB) {
 #pragma unroll
-                for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
+                    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma16(a4[rb][ss], b[cb], acc[rb][cb]);
+                }
         }
     };
     V4 a0[RB], a1[RB];

@@ -24,11 +24,15 @@ constexpr int kVOffsets = 189;    // V-list offsets of one child octant
 constexpr int kReflShift = 28;
 // Untiled V-list pairs share operators the same way per pair: free-space
 // pairs by reflection (code 0..7, A_d = D A_|d| D) and reaction pairs by
-// rotation about z (code kXfRotate): the reaction translation depends on the
-// azimuth phi of c_t - c_s only through e^{i(mu - m) phi}, so
+// rotation about z (codes kXfRotate + dir): the reaction translation depends
+// on the azimuth phi of c_t - c_s only through e^{i(mu - m) phi}, so
 // T(phi) = diag(e^{-i m phi}) T(0) diag(e^{i mu phi}) and one operator per
-// (level, rho, z_t, z_s) serves every direction.
+// (level, rho, z_t, z_s) serves every direction.  A V-list source box sits
+// (dx, dy) cells from its target box with |dx|, |dy| <= 3, so phi =
+// atan2(-dy, -dx) takes one of kXfDirs values, dir = (dx + 3) 7 + (dy + 3),
+// and cos / sin (m phi) come from a table (EvalArgs::rot_tab).
 constexpr int kXfRotate = 8;
+constexpr int kXfDirs = 49;
 // The 189 offsets of a child octant form 56 orbits under those reflections
 // (canonical offset (|dx|,|dy|,|dz|)).  Per axis an orbit has both signs
 // ("both" axes, 1 or 2 away) or one (0, or 3 on the side the octant allows).
@@ -165,13 +169,11 @@ struct Plan {
     std::vector<int> m2l_ptr, m2l_src, m2l_op;   // m2l_ptr has n_le+1
     // per pair: how the pair's operator relates to the stored one (see kXfRotate)
     std::vector<int> m2l_xc;
-    std::vector<double> m2l_xa;
     // batched dense translations on the matrix cores: work item w has terms
     // [bw_term_ptr[w], bw_term_ptr[w+1]), term t = operator bw_op[t] and 64
     // source rows bw_src[64 t + j]; 64 destination rows bw_dst[64 w + j] (-1: none)
     std::vector<int> bw_term_ptr, bw_op, bw_src, bw_dst;
-    std::vector<int> bw_xc;      // per column: -1 none, 0..7 reflection code, kXfRotate rotation by bw_xa
-    std::vector<double> bw_xa;
+    std::vector<int> bw_xc;      // per column: -1 none, 0..7 reflection code, kXfRotate + dir rotation
     std::vector<int> bm2m_lv, bl2l_lv;   // work items of M2M (parent level) / L2L (child level) l: [v[l], v[l+1])
     int bm2l_w0 = 0, bm2l_w1 = 0;        // V-list pairs outside the tiled levels, grouped by operator;
                                          // destination = the pair's position in m2l_src (scratch row)

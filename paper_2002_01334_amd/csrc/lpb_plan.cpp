@@ -81,7 +81,24 @@ struct BoxSet {
     // level-l boxes of one point set: canonical cell coords sorted by Morton key
     std::vector<uint64_t> mkey;
     std::vector<int> ix, iy, iz;
-    std::unordered_map<uint64_t, int> idx;   // cellkey -> position
+    // cell -> position: a dense grid up to kDenseSide^3 cells, a hash map beyond
+    static constexpr int kDenseSide = 128;
+    int nside = 0;
+    std::vector<int> dense;
+    std::unordered_map<uint64_t, int> idx;
+    void insert(int a, int b, int c, int pos)
+    {
+        if (nside <= kDenseSide) dense[((size_t)a * nside + b) * nside + c] = pos;
+        else idx[cellkey(a, b, c)] = pos;
+    }
+    // position of cell (a, b, c), -1 if empty or outside the grid
+    int find(int a, int b, int c) const
+    {
+        if (a < 0 || b < 0 || c < 0 || a >= nside || b >= nside || c >= nside) return -1;
+        if (nside <= kDenseSide) return dense[((size_t)a * nside + b) * nside + c];
+        auto it = idx.find(cellkey(a, b, c));
+        return it == idx.end() ? -1 : it->second;
+    }
 };
 
 // One point set on its uniform octree, as built into the plan.
@@ -98,15 +115,14 @@ struct BWork {
     std::vector<int> src;   // 64 per term
     std::array<int, 64> dst;
     std::array<int, 64> xc;      // per column transform code (-1 none)
-    std::array<double, 64> xa;   // rotation angle
-    BWork() { xc.fill(-1); xa.fill(0.0); }
+    BWork() { xc.fill(-1); }
 };
 
 // Staging shared by the tree and list builders.
 struct Staging {
     std::vector<std::vector<BWork>> bm2m{(size_t)kMaxDepth + 1}, bl2l{(size_t)kMaxDepth + 1};
-    struct M2LPair { int src, op, xc; double xa; };
-    std::vector<std::vector<M2LPair>> m2l_by_le;                // per LE box
+    struct M2LPair { int le, src, op, xc; };
+    std::vector<M2LPair> m2l_pairs;                             // untiled V-list pairs in list order (grouped by LE box at the end)
     std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: free-space source leaves
     std::vector<std::vector<std::pair<int, int>>> rp_by_tl;     // per target leaf: (reaction FMM, source leaf)
     std::vector<double> s_ux, s_uy, s_uz, t_ux, t_uy, t_uz;
@@ -129,13 +145,44 @@ inline int depth_rule(const std::vector<Pt>& V, int cap)
     return kMaxDepth;
 }
 
+// fine cells and keys of a point set, then the set sorted by (key, charge
+// index): a stable LSD radix sort of the 48-bit keys (three 16-bit digits)
+// when the set arrives in charge-index order (it always does), else a
+// comparison sort
 void set_cells(std::vector<Pt>& V, double R)
 {
-    for (auto& q : V) {
+    bool in_order = true;
+    for (size_t i = 0; i < V.size(); ++i) {
+        Pt& q = V[i];
         for (int d = 0; d < 3; ++d) q.c[d] = fine_cell(q.w[d], 0.0, R);
         q.fkey = morton_fine(q.c[0], q.c[1], q.c[2]);
+        if (i > 0 && V[i - 1].cidx >= q.cidx) in_order = false;
     }
-    std::sort(V.begin(), V.end(), [](const Pt& A, const Pt& B) { return A.fkey != B.fkey ? A.fkey < B.fkey : A.cidx < B.cidx; });
+    if (!in_order || V.size() < 2048) {
+        std::sort(V.begin(), V.end(), [](const Pt& A, const Pt& B) { return A.fkey != B.fkey ? A.fkey < B.fkey : A.cidx < B.cidx; });
+        return;
+    }
+    // keys sorted with the point's position carried along
+    const size_t n = V.size();
+    std::vector<std::pair<uint64_t, uint32_t>> a(n), b(n);
+    for (size_t i = 0; i < n; ++i) a[i] = {V[i].fkey, (uint32_t)i};
+    std::vector<uint32_t> cnt(1 << 16);
+    for (int pass = 0; pass < 3; ++pass) {
+        const int sh = 16 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        for (size_t i = 0; i < n; ++i) cnt[(a[i].first >> sh) & 0xffff]++;
+        uint32_t run = 0;
+        for (auto& c : cnt) {
+            const uint32_t t = c;
+            c = run;
+            run += t;
+        }
+        for (size_t i = 0; i < n; ++i) b[cnt[(a[i].first >> sh) & 0xffff]++] = a[i];
+        a.swap(b);
+    }
+    std::vector<Pt> W(n);
+    for (size_t i = 0; i < n; ++i) W[i] = V[a[i].second];
+    V.swap(W);
 }
 
 // Add one tree (boxes, leaves, points, and its M2M or L2L operators and lists)
@@ -147,10 +194,12 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
     for (int lv = 0; lv <= H; ++lv) {
         int sh = kCellBits - lv;
         BoxSet& bs = T.B[lv];
+        bs.nside = 1 << lv;
+        if (bs.nside <= BoxSet::kDenseSide) bs.dense.assign((size_t)bs.nside * bs.nside * bs.nside, -1);
         for (size_t i = 0; i < V.size(); ++i) {
             if (i > 0 && (V[i].fkey >> (3 * sh)) == (V[i - 1].fkey >> (3 * sh))) continue;
             uint32_t a = V[i].c[0] >> sh, b = V[i].c[1] >> sh, c = V[i].c[2] >> sh;
-            bs.idx[cellkey(a, b, c)] = (int)bs.mkey.size();
+            bs.insert((int)a, (int)b, (int)c, (int)bs.mkey.size());
             bs.mkey.push_back(V[i].fkey >> (3 * sh));
             bs.ix.push_back((int)a);
             bs.iy.push_back((int)b);
@@ -173,7 +222,6 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
             P.n_me += n;
         }
     }
-    if (target) S.m2l_by_le.resize(P.n_le);
     auto hlev = [&](int lv) { return 2.0 * R / (double)(1 << lv); };
     auto centre = [&](int lv, int i) { return -R + (i + 0.5) * hlev(lv); };   // canonical, relative to the root centre
     const int shH = kCellBits - H;
@@ -182,7 +230,7 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
     int cur = -1;
     for (size_t k = 0; k < V.size(); ++k) {
         uint32_t a = V[k].c[0] >> shH, b = V[k].c[1] >> shH, c = V[k].c[2] >> shH;
-        int bi = T.B[H].idx[cellkey(a, b, c)];
+        int bi = T.B[H].find((int)a, (int)b, (int)c);
         if (bi != cur) {
             if (target) {
                 if (cur >= 0) P.tl_start.push_back((int)P.t_cidx.size());
@@ -256,7 +304,7 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
                     for (size_t j = 0; j < 64 && c0 + j < byo[o].size(); ++j) {
                         int k = byo[o][c0 + j];
                         int ix = T.B[lv].ix[k], iy = T.B[lv].iy[k], iz = T.B[lv].iz[k];
-                        wk.src[j] = T.off[lv - 1] + T.B[lv - 1].idx.at(cellkey(ix >> 1, iy >> 1, iz >> 1));
+                        wk.src[j] = T.off[lv - 1] + T.B[lv - 1].find(ix >> 1, iy >> 1, iz >> 1);
                         wk.dst[j] = T.off[lv] + k;
                     }
                     S.bl2l[lv].push_back(std::move(wk));
@@ -273,8 +321,8 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
                     int px = T.B[lv].ix[k], py = T.B[lv].iy[k], pz = T.B[lv].iz[k];
                     wk.dst[j] = T.off[lv] + k;
                     for (int o = 0; o < 8; ++o) {
-                        auto it = T.B[lv + 1].idx.find(cellkey(2 * px + ((o >> 2) & 1), 2 * py + ((o >> 1) & 1), 2 * pz + (o & 1)));
-                        if (it != T.B[lv + 1].idx.end()) wk.src[64 * o + j] = T.off[lv + 1] + it->second;
+                        const int ch = T.B[lv + 1].find(2 * px + ((o >> 2) & 1), 2 * py + ((o >> 1) & 1), 2 * pz + (o & 1));
+                        if (ch >= 0) wk.src[64 * o + j] = T.off[lv + 1] + ch;
                     }
                 }
                 S.bm2m[lv].push_back(std::move(wk));
@@ -294,11 +342,18 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
     auto centre = [&](int lv, int i) { return -R + (i + 0.5) * hlev(lv); };
     const std::vector<BoxSet>& SB = ST.B;
     const std::vector<BoxSet>& TB = TT.B;
-    std::unordered_map<uint64_t, int> opmap, rkmap;
+    // operator de-duplication: free-space operators per (level, offset), 343
+    // offsets per level; reaction operators per (level, rho^2 / h^2, z cells),
+    // where the z cells of a V-list pair lie within 3 of the interface plane
+    // (targets above it, images below), so a small table per level serves
+    // them, with a hash map as fallback
+    std::vector<int> opmap((size_t)(kMaxDepth + 1) * 343, -1);
+    constexpr int kRkD2 = 19, kRkZ = 4;
+    std::vector<int> rktab((size_t)(kMaxDepth + 1) * kRkD2 * kRkZ * kRkZ, -1);
+    std::unordered_map<uint64_t, int> rkmap;
     auto free_op = [&](int lv, int dx, int dy, int dz) {
-        uint64_t key = ((uint64_t)lv << 16) | (uint64_t)(((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3));
-        auto f = opmap.find(key);
-        if (f != opmap.end()) return f->second;
+        int& slot = opmap[(size_t)lv * 343 + ((dx + 3) * 7 + (dy + 3)) * 7 + (dz + 3)];
+        if (slot >= 0) return slot;
         double h = hlev(lv);
         OpDesc d{};
         d.type = OP_M2L_FREE;
@@ -310,7 +365,7 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         d.bz = -dz * h;
         int op = (int)P.ops.size();
         P.ops.push_back(d);
-        opmap[key] = op;
+        slot = op;
         return op;
     };
     // tiled levels of a free-space FMM: dense grids, operator table, tiles
@@ -376,15 +431,14 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                             int sx = 2 * qx + ((o >> 2) & 1), sy = 2 * qy + ((o >> 1) & 1), sz = 2 * qz + (o & 1);
                             int dx = sx - tx, dy = sy - ty, dz = sz - tz;
                             if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
-                            auto it = SB[lv].idx.find(cellkey(sx, sy, sz));
-                            if (it == SB[lv].idx.end()) continue;
+                            const int sbox = SB[lv].find(sx, sy, sz);
+                            if (sbox < 0) continue;
                             if (tiled) {   // the tile's operator table covers it
                                 P.n_m2l_tile_pairs++;
                                 P.n_m2l_pairs++;
                                 continue;
                             }
                             int op, xc;
-                            double xa = 0.0;
                             if (F.kind == 0) {
                                 // one operator per offset with non-negative components, D A D for the others
                                 op = free_op(lv, std::abs(dx), std::abs(dy), std::abs(dz));
@@ -392,9 +446,17 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                             } else {
                                 // one operator per (level, rho, z_t, z_s) at phi = 0, rotated per pair
                                 const int d2 = dx * dx + dy * dy;
+                                const int zt_i = tz - nside / 2, zs_i = nside / 2 - 1 - sz;
+                                int* rslot = nullptr;
+                                if (d2 < kRkD2 && zt_i >= 0 && zt_i < kRkZ && zs_i >= 0 && zs_i < kRkZ)
+                                    rslot = &rktab[(((size_t)lv * kRkD2 + d2) * kRkZ + zt_i) * kRkZ + zs_i];
                                 const uint64_t rk = ((uint64_t)lv << 48) | ((uint64_t)d2 << 32) | ((uint64_t)tz << 16) | (uint64_t)sz;
-                                auto g = rkmap.find(rk);
-                                if (g == rkmap.end()) {
+                                int found = rslot ? *rslot : -1;
+                                if (!rslot) {
+                                    auto g = rkmap.find(rk);
+                                    if (g != rkmap.end()) found = g->second;
+                                }
+                                if (found < 0) {
                                     RKey r{};
                                     r.fmm = fid;
                                     r.level = lv;
@@ -411,12 +473,12 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                                     d.phi = 0.0;
                                     op = (int)P.ops.size();
                                     P.ops.push_back(d);
-                                    rkmap[rk] = op;
-                                } else op = g->second;
-                                xc = kXfRotate;
-                                xa = (dx == 0 && dy == 0) ? 0.0 : std::atan2((double)-dy, (double)-dx);
+                                    if (rslot) *rslot = op;
+                                    else rkmap[rk] = op;
+                                } else op = found;
+                                xc = kXfRotate + (dx + 3) * 7 + (dy + 3);
                             }
-                            S.m2l_by_le[le].push_back({ST.off[lv] + it->second, op, xc, xa});
+                            S.m2l_pairs.push_back({le, ST.off[lv] + sbox, op, xc});
                             P.n_m2l_pairs++;
                         }
                     }
@@ -436,9 +498,9 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         for (const auto& du : kUOrder) {
                     int sx = tx + du[0], sy = ty + du[1], sz = tz + du[2];
                     if (sx < 0 || sy < 0 || sz < 0 || sx >= nside || sy >= nside || sz >= nside) continue;
-                    auto it = SB[H].idx.find(cellkey(sx, sy, sz));
-                    if (it == SB[H].idx.end()) continue;
-                    int sl = ST.leaf0 + it->second;
+                    const int sbox = SB[H].find(sx, sy, sz);
+                    if (sbox < 0) continue;
+                    int sl = ST.leaf0 + sbox;
                     int64_t pairs = (int64_t)nt * (P.sl_start[sl + 1] - P.sl_start[sl]);
                     P.n_p2p_pairs += pairs;
                     if (F.kind == 0) S.p2p_by_tl[tl].push_back(sl);
@@ -749,26 +811,32 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         P.t_u[2 * S.t_ux.size() + i] = S.t_uz[i];
     }
     for (size_t i = 0; i < P.t_out.size(); ++i) P.t_out[i] = (int)(P.t_out[i] * P.ncharges + P.t_cidx[i]);
-    P.m2l_ptr.assign(1, 0); P.m2l_src.clear(); P.m2l_op.clear(); P.m2l_xc.clear(); P.m2l_xa.clear();
-    S.m2l_by_le.resize(P.n_le);
-    for (int i = 0; i < P.n_le; ++i) {
-        for (auto& e : S.m2l_by_le[i]) {
-            P.m2l_src.push_back(e.src);
-            P.m2l_op.push_back(e.op);
-            P.m2l_xc.push_back(e.xc);
-            P.m2l_xa.push_back(e.xa);
+    // CSR by LE box, each box's pairs in the order they were listed (a stable
+    // counting sort of the pair list by box)
+    P.m2l_ptr.assign((size_t)P.n_le + 1, 0);
+    for (const auto& e : S.m2l_pairs) P.m2l_ptr[e.le + 1]++;
+    for (int i = 0; i < P.n_le; ++i) P.m2l_ptr[i + 1] += P.m2l_ptr[i];
+    P.m2l_src.resize(S.m2l_pairs.size());
+    P.m2l_op.resize(S.m2l_pairs.size());
+    P.m2l_xc.resize(S.m2l_pairs.size());
+    {
+        std::vector<int> fill(P.m2l_ptr.begin(), P.m2l_ptr.end() - 1);
+        for (const auto& e : S.m2l_pairs) {
+            const int k = fill[e.le]++;
+            P.m2l_src[k] = e.src;
+            P.m2l_op[k] = e.op;
+            P.m2l_xc[k] = e.xc;
         }
-        P.m2l_ptr.push_back((int)P.m2l_src.size());
     }
+    S.m2l_pairs = std::vector<Staging::M2LPair>();
     // batched work items: M2M and L2L per level, then the V-list pairs outside
     // the tiled levels grouped by operator
-    P.bw_term_ptr.assign(1, 0); P.bw_op.clear(); P.bw_src.clear(); P.bw_dst.clear(); P.bw_xc.clear(); P.bw_xa.clear();
+    P.bw_term_ptr.assign(1, 0); P.bw_op.clear(); P.bw_src.clear(); P.bw_dst.clear(); P.bw_xc.clear();
     auto push_work = [&](const BWork& wk) {
         P.bw_op.insert(P.bw_op.end(), wk.op.begin(), wk.op.end());
         P.bw_src.insert(P.bw_src.end(), wk.src.begin(), wk.src.end());
         P.bw_dst.insert(P.bw_dst.end(), wk.dst.begin(), wk.dst.end());
         P.bw_xc.insert(P.bw_xc.end(), wk.xc.begin(), wk.xc.end());
-        P.bw_xa.insert(P.bw_xa.end(), wk.xa.begin(), wk.xa.end());
         P.bw_term_ptr.push_back((int)P.bw_op.size());
     };
     P.bm2m_lv.assign(kMaxDepth + 2, 0);
@@ -799,7 +867,6 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                 wk.src[j - i] = P.m2l_src[byop[j].second];
                 wk.dst[j - i] = byop[j].second;
                 wk.xc[j - i] = P.m2l_xc[byop[j].second];
-                wk.xa[j - i] = P.m2l_xa[byop[j].second];
             }
             push_work(wk);
             i = e;

@@ -32,7 +32,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Options(ctypes.Structure):
     _fields_ = [("p", _I), ("leaf_cap", _I), ("precision", _I), ("quad_tol", _D), ("iface_tol", _D),
                 ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I), ("graph", _I), ("autotune", _I),
-                ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", _P)]
+                ("schedule", _I), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", _P)]
 
 
 class Allocator:
@@ -145,7 +145,7 @@ class Context:
     """One lpb context (one GPU, one stream)."""
 
     def __init__(self, p=10, leaf_cap=50, precision=LPB_FP64, quad_tol=1e-16, iface_tol=1e-9, device=0,
-                 stream=None, stages=3, timing=0, graph=1, autotune=1, allocator=None):
+                 stream=None, stages=3, timing=0, graph=1, autotune=1, schedule=0, allocator=None):
         L = load()
         opt = Options()
         L.lpb_default_options(ctypes.byref(opt))
@@ -164,6 +164,7 @@ class Context:
         opt.timing = timing
         opt.graph = graph
         opt.autotune = autotune
+        opt.schedule = schedule
         h = _P()
         rc = L.lpb_create(ctypes.byref(opt), ctypes.byref(h))
         if rc != LPB_OK:

@@ -9,6 +9,7 @@ import numpy as np
 import pytest
 
 import oracle as O
+from lpbtest import err2, run, slot_map
 from paper_2002_01334_amd import inputs
 
 pytestmark = pytest.mark.gpu
@@ -23,43 +24,6 @@ def lpb():
 
     m.load()
     return m
-
-
-def err2(a, b, layer, nl=3):
-    out = []
-    for l in range(nl):
-        m = layer == l
-        if m.sum() == 0:
-            continue
-        nb = np.linalg.norm(b[m])
-        out.append(np.linalg.norm(a[m] - b[m]) / nb if nb > 0 else np.linalg.norm(a[m]))
-    return max(out)
-
-
-def slot_map(nl):
-    """Output slot of each component: 0 free space, a (1 or 2) for the reaction
-    components through the lower / upper interface of the target's layer, whose
-    target trees (and local expansions) the library shares."""
-    m = {}
-    for c in range(O.num_components(nl)):
-        kind, l, lp, a, b = O.component(nl, c)
-        m[c] = (l, 0 if kind == 0 else a)
-    return m
-
-
-def run(lpb, prob, p, leaf_cap, precision=0, device=False):
-    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision)
-    ctx.set_layers(prob.eps, prob.lam, prob.d)
-    if device:
-        import torch
-
-        t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device="cuda:0") for k in "xyzq"}
-        ctx.build_tree(t["x"], t["y"], t["z"])
-        phi = ctx.evaluate(t["q"]).cpu().numpy()
-    else:
-        ctx.build_tree(prob.x, prob.y, prob.z)
-        phi = ctx.evaluate(prob.q)
-    return ctx, phi
 
 
 @pytest.fixture(scope="module")
@@ -433,6 +397,25 @@ def test_reaction_near_field_next_to_interfaces(lpb):
 
 
 @pytest.mark.parametrize("precision", [0, 1])
+def test_every_schedule_gives_the_same_bits(lpb, precision):
+    """All 4 x 8 block-to-work schedules of the matrix-core kernels (tiled M2L:
+    order and wide variant; batched translations: order and resident-block
+    grid) on a tree with tiled levels and reaction pairs: identical results."""
+    prob = inputs.three_layer(12_000, seed=2)
+    ref = None
+    for tile in range(4):
+        for batch in range(8):
+            ctx, phi = run(lpb, prob, 9, 20, precision=precision, autotune=0, schedule=tile | (batch << 4))
+            st = ctx.stats()
+            ctx.close()
+            assert (st["tile_schedule"], st["batch_schedule"]) == (tile, batch)
+            if ref is None:
+                ref = phi
+                assert st["n_m2l_tile_pairs"] > 0
+            assert np.array_equal(phi, ref), (tile, batch)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
     """Captured evaluation (graph = 1, autotuned schedules) against eager
     launches with the linear schedules: several replays with different
@@ -456,7 +439,7 @@ def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
             torch.cuda.synchronize()
             assert np.array_equal(a, b), rep
     st = g.stats()
-    assert st["tile_schedule"] in range(4) and st["batch_schedule"] in (0, 1)
+    assert st["tile_schedule"] in range(4) and st["batch_schedule"] in range(8)
     # a new tree invalidates the captured passes
     prob2 = inputs.three_layer(7_000, seed=5)
     for c in (g, e):
