@@ -32,8 +32,12 @@ namespace lpb {
 // operand of four products, the operand layout arranged to match), forms the
 // transforms in registers and issues the products; loads run two steps
 // ahead.  The orbits come in groups of one both-axes mask (kOrbGroupMask), so
-// each gather loads exactly the members its orbit has.  No data is shared between waves, so the waves never wait for each
-// other.  Each orbit's products go to the result with Kahan compensation.
+// each gather loads exactly the members its orbit has.  The operator slab of
+// a step is the same for the four waves: up to p = 10 it is copied once per
+// block into a ring of three LDS slots (buffer loads straight to LDS, a
+// barrier per step) and the kernel runs two blocks per CU; above, each wave
+// gathers it into registers.  Each orbit's products go to the result with
+// Kahan compensation.
 template <int P, int MASK>
 __device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], const int __attribute__((ext_vector_type(4))) ek, int minus,
                                            const Vec4<float>::type (&ra)[class_row_blocks(P)],
@@ -87,8 +91,23 @@ __device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], con
         for (int rb = 0; rb < NRB; ++rb) acc[rb] = mfma16(ra[rb][ss], y[ext(class_of_row_block(P, rb))][ss], acc[rb]);
 }
 
+// Orders whose operand slab (NRB row blocks of 1 KiB per step) is staged in
+// LDS and shared by the four waves of a block, two blocks per CU: the slab
+// is read from L2 once per block instead of once per wave, and the second
+// block's waves keep the matrix cores busy while the first block's waves wait
+// at the per-step barrier.  Larger orders keep the operands in registers.
 template <int P>
-__global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
+constexpr bool orbit_lds_operands() { return class_row_blocks(P) <= 9; }
+
+// s_waitcnt immediate that waits until at most n vector memory operations are
+// outstanding and for every LDS operation (gfx9 encoding: vmcnt low bits
+// [3:0], expcnt [6:4] left at its maximum, lgkmcnt [11:8], vmcnt high bits
+// [15:14])
+constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | (7 << 4) | (0 << 8) | ((n >> 4) << 14); }
+
+template <int P>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(orbit_lds_operands<P>() ? 2 : 1)))
+k_m2l_orbit(EvalArgs<float> A)
 {
     typedef Vec4<float>::type V4;
     constexpr int K = (P + 1) * (P + 1), KB = (K + 15) / 16, KP = 16 * KB;
@@ -96,6 +115,10 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     constexpr int OPSZ = NRB * KB * 256;     // floats of one operator
     constexpr int NIT = kOrbits * KB;        // steps (even: kOrbits is)
     constexpr int NG = kOrbGrid * kOrbGrid * kOrbGrid;
+    constexpr bool LA = orbit_lds_operands<P>();
+    constexpr int NLA = (NRB + 3) / 4;       // row blocks each wave stages per step
+    constexpr int SLAB = 4 * NLA * 256;      // floats of one staged slab (blocks past NRB unused)
+    __shared__ float s_a[LA ? 3 * SLAB : 4]; // ring of three staged slabs
     __shared__ int s_grid[NG];               // ME row of each local source box
     __shared__ int s_tab[kOrbits * kOrbTab]; // the octant's orbit table
     __shared__ int s_kcls[KP];               // sign class of each coefficient
@@ -164,19 +187,24 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     // members: the orbit groups fix the member count at compile time, and the
     // last orbit of a group also gathers the first steps of the next group's
     // first orbit, which has no more members (its absent ones read the zero row)
+    // (and the negative one-sign axes of that orbit, in mnext)
     unsigned off[8];
+    int mnext = 0;
     auto lorbit = [&](auto cntc, int q) {
         constexpr int CNT = decltype(cntc)::value;
         const int* row = s_tab + q * kOrbTab;
-        const int nm = 1 << (__builtin_amdgcn_readfirstlane(row[0]) & 15);
+        const int r0 = __builtin_amdgcn_readfirstlane(row[0]);
+        const int nm = 1 << (r0 & 15);
+        mnext = (r0 >> 7) & 7;
 #pragma unroll
         for (int m = 0; m < CNT; ++m)
             off[m] = (m < nm) ? (unsigned)s_grid[tli + row[1 + m]] * (unsigned)(KP * 4) + 16u * g : zoff;
     };
     typedef int I4 __attribute__((ext_vector_type(4)));
-    // operand slabs: gathered two steps ahead (DA = 2) while the registers
-    // allow, one step ahead for the larger orders (they come mostly from L2)
-    constexpr int DA = (NRB <= 9) ? 2 : 1;
+    // operand slabs (register path): gathered two steps ahead (DA = 2) while
+    // the registers allow, one step ahead for the larger orders (they come
+    // mostly from L2)
+    constexpr int DA = (LA || NRB > 9) ? 1 : 2;
     V4 xr[2][8], ra[DA][NRB];
     I4 er[2];
     // operand and member gathers are buffer loads: wave-uniform bases and
@@ -191,24 +219,71 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         for (int rb = 0; rb < NRB; ++rb)
             as[rb] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(ra_, lane16, (rb * KB + s) * 1024, 0));
     };
+    // LDS path: wave cb copies row blocks cb, cb + 4, ... of step t's slab
+    // straight into ring slot `slot` (buffer loads to LDS, 16 bytes per lane
+    // at 16 l); block numbers past NRB copy block 0 into the unused tail
+    auto stage_a = [&](int t, int slot) {
+        const int q = t / KB, s = t % KB;
+        const float* Ao = A.pool_orb + (size_t)__builtin_amdgcn_readfirstlane(s_aoff[q]) * OPSZ;
+        const __amdgpu_buffer_rsrc_t ra_ = __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(Ao), 0, OPSZ * 4, 0x00020000);
+        float* dst = s_a + slot * SLAB;
+#pragma unroll
+        for (int i = 0; i < NLA; ++i) {
+            const int b = __builtin_amdgcn_readfirstlane(cb + 4 * i);
+            const int bs = b < NRB ? b : 0;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra_, (__attribute__((address_space(3))) void*)(dst + b * 256), 16,
+                                                     lane16, (bs * KB + s) * 1024, 0, 0);
+        }
+    };
     // gather step t: its first CNT member sources and the coefficient classes
     // (and, with DA = 2, its operand slab)
     auto load = [&](auto cntc, int t, V4 (&xs)[8], V4 (&as)[NRB], I4& ek) {
         constexpr int CNT = decltype(cntc)::value;
         const int s = t % KB;
-        if (s == 0) lorbit(cntc, t / KB);
+        if constexpr (!LA) {
+            if (s == 0) lorbit(cntc, t / KB);
+        }
         if constexpr (DA == 2) load_a(t, as);
 #pragma unroll
         for (int m = 0; m < CNT; ++m) xs[m] = __builtin_bit_cast(V4, __builtin_amdgcn_raw_buffer_load_b128(rme, off[m], 64 * s, 0));
-        ek = *reinterpret_cast<const I4*>(s_kcls + 16 * s + 4 * g);
+        // (LDS path: from global memory, since an LDS read issued after a
+        // slab copy would wait for that copy)
+        if constexpr (LA) ek = *reinterpret_cast<const I4*>(A.orb_kcls + 16 * s + 4 * g);
+        else ek = *reinterpret_cast<const I4*>(s_kcls + 16 * s + 4 * g);
     };
     V4 acc[NRB], tot[NRB], cmp[NRB];
 #pragma unroll
     for (int rb = 0; rb < NRB; ++rb) acc[rb] = tot[rb] = cmp[rb] = V4{0, 0, 0, 0};
     typedef std::integral_constant<int, 1 << __builtin_popcount(kOrbGroupMask[0])> NM0;
+    if constexpr (LA) {
+        lorbit(NM0{}, 0);
+        stage_a(0, 0);
+    }
     load(NM0{}, 0, xr[0], ra[0], er[0]);
+    if constexpr (LA) stage_a(1, 1);
     load(NM0{}, 1, xr[1], ra[DA - 1], er[1]);
-    if constexpr (DA == 1) load_a(0, ra[0]);
+    if constexpr (DA == 1 && !LA) load_a(0, ra[0]);
+    // LDS path, at step t: wait until step t's slab is in LDS (each step
+    // issues NLA slab copies, then NM member gathers and one class load, and
+    // the member counts never grow from one orbit group to the next) and
+    // every wave is done with slot (t + 2) mod 3 (read at step t - 1); read
+    // step t's slab; look up the member rows when step t + 2 starts an orbit
+    // (LDS reads go before the next copy is issued: the compiler makes an LDS
+    // read wait for every copy to LDS in flight); copy step t + 2's slab
+    auto sync_read = [&](auto nmc, int t, V4 (&as)[NRB]) {
+        constexpr int NM = decltype(nmc)::value;
+        static_assert(NLA + 2 * NM + 2 <= 63, "vmcnt range");
+        __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(NLA + 2 * NM + 2));
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+        __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+        const float* src = s_a + (t % 3) * SLAB + 4 * l;
+#pragma unroll
+        for (int rb = 0; rb < NRB; ++rb) as[rb] = *reinterpret_cast<const V4*>(src + 256 * rb);
+        const int tn = min(t + 2, NIT - 1);
+        if (tn % KB == 0) lorbit(nmc, tn / KB);
+        stage_a(tn, (t + 2) % 3);
+    };
     // one orbit: its KB steps with the transform specialised for its both-axes
     // (steps of one orbit form one straight code path, so the transforms of a
     // step can overlap the products of the previous one); step t uses register
@@ -218,26 +293,30 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
         constexpr int MASK = decltype(maskc)::value, PAR = decltype(parc)::value;
         typedef std::integral_constant<int, 1 << __builtin_popcount(MASK)> NM;
         const int t0 = q * KB;
-        // (the scheduling fences keep each step's transforms after its own loads'
-        // wait: hoisted into the previous step they would wait for the loads
-        // just issued)
+        // (register path: the scheduling fences keep each step's transforms
+        // after its own loads' wait: hoisted into the previous step they would
+        // wait for the loads just issued; the LDS path's barriers order the
+        // steps already)
         constexpr int A0 = (DA == 2) ? PAR : 0, A1 = (DA == 2) ? (PAR ^ 1) : 0;
         for (int s = 0; s < KB; s += 2) {
+            if constexpr (LA) sync_read(NM{}, t0 + s, ra[0]);
             orbit_step<P, MASK>(xr[PAR], er[PAR], minus, ra[A0], acc);
-            if constexpr (DA == 1) load_a(min(t0 + s + 1, NIT - 1), ra[0]);
+            if constexpr (DA == 1 && !LA) load_a(min(t0 + s + 1, NIT - 1), ra[0]);
             load(NM{}, min(t0 + s + 2, NIT - 1), xr[PAR], ra[A0], er[PAR]);
-            __builtin_amdgcn_sched_barrier(0);
+            if constexpr (!LA) __builtin_amdgcn_sched_barrier(0);
             if (s + 1 < KB) {
+                if constexpr (LA) sync_read(NM{}, t0 + s + 1, ra[0]);
                 orbit_step<P, MASK>(xr[PAR ^ 1], er[PAR ^ 1], minus, ra[A1], acc);
-                if constexpr (DA == 1) load_a(min(t0 + s + 2, NIT - 1), ra[0]);
+                if constexpr (DA == 1 && !LA) load_a(min(t0 + s + 2, NIT - 1), ra[0]);
                 load(NM{}, min(t0 + s + 3, NIT - 1), xr[PAR ^ 1], ra[A1], er[PAR ^ 1]);
-                __builtin_amdgcn_sched_barrier(0);
+                if constexpr (!LA) __builtin_amdgcn_sched_barrier(0);
             }
         }
     };
     auto orbit = [&](auto maskc, auto parc, int q) {
-        // negative one-sign axes of the orbit
-        const int minus = (__builtin_amdgcn_readfirstlane(s_tab[q * kOrbTab]) >> 7) & 7;
+        // negative one-sign axes of the orbit (looked up with its member rows,
+        // two steps before it starts)
+        const int minus = mnext;
         run(maskc, parc, q, minus);
 #pragma unroll
         for (int rb = 0; rb < NRB; ++rb) {
@@ -277,6 +356,8 @@ __global__ void __launch_bounds__(256) k_m2l_orbit(EvalArgs<float> A)
     group(std::integral_constant<int, 5>{});
     group(std::integral_constant<int, 6>{});
     group(std::integral_constant<int, 7>{});
+    // the last slab copies (of steps past the end) land before the wave ends
+    if constexpr (LA) __builtin_amdgcn_s_waitcnt(waitcnt_vm_lgkm0(0));
     const int le = s_le[j];
     if (le < 0) return;
     // all row indices, then all current LE values, then the stores (loads in
