@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "lpb_eval.h"
+#include "lpb_tree_dev.h"
 #include "lpb_internal.h"
 #include "lpb_opgen.h"
 
@@ -273,33 +274,6 @@ lpb_status up_field(lpb_ctx* c, const F*& field, const std::vector<V>& vec)
     return s;
 }
 
-template <typename T>
-lpb_status upload_points(lpb_ctx* c, const std::vector<double>& u3, int n, const T** x, const T** y, const T** z,
-                         const T** lx, const T** ly, const T** lz)
-{
-    // FP32: hi = (float)u and lo = (float)(u - hi), so hi + lo carries u to ~2^-48 relative
-    const T** hi[3] = {x, y, z};
-    const T** lo[3] = {lx, ly, lz};
-    lpb_status s;
-    for (int d = 0; d < 3; ++d) {
-        std::vector<T> h(n), l(n);
-        for (int i = 0; i < n; ++i) {
-            double u = u3[(size_t)d * n + i];
-            h[i] = (T)u;
-            l[i] = (T)(u - (double)h[i]);
-        }
-        T* ph;
-        if ((s = upload(c, c->plan_bufs, h, &ph)) != LPB_OK) return s;
-        *hi[d] = ph;
-        *lo[d] = nullptr;
-        if (sizeof(T) == 4) {
-            T* pl;
-            if ((s = upload(c, c->plan_bufs, l, &pl)) != LPB_OK) return s;
-            *lo[d] = pl;
-        }
-    }
-    return LPB_OK;
-}
 
 // Coefficients in sign-class order (natural order within a class), each
 // class padded with -1 entries to a multiple of 16.
@@ -318,7 +292,7 @@ std::vector<int> class_rowmap(int p)
 }
 
 template <typename T>
-lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
+lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
 {
     Plan& P = c->plan;
     lpb_status s;
@@ -328,7 +302,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     A.KP = (P.K + 15) / 16 * 16;
     A.nslots = P.nslots;
     A.ncharges = P.ncharges;
-    A.n_src = (int)P.s_cidx.size();
+    A.n_src = (int)P.n_spts;
     A.quad_tol = c->opt.quad_tol;
     // FMM records
     std::vector<FmmDev> fd(P.fmm.size());
@@ -348,14 +322,11 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     A.media = dmed;
 #define UP(field, vec)                                                     \
     if ((s = up_field(c, A.field, vec)) != LPB_OK) return s;
-    UP(s_cidx, P.s_cidx);
     UP(sl_start, P.sl_start);
     UP(sl_me, P.sl_me);
     UP(sl_fmm, P.sl_fmm);
     UP(sl_h, P.sl_h);
     UP(sl_ctr, P.sl_ctr);
-    UP(t_cidx, P.t_cidx);
-    UP(t_out, P.t_out);
     UP(tl_start, P.tl_start);
     UP(tl_le, P.tl_le);
     UP(tl_fmm, P.tl_fmm);
@@ -550,14 +521,33 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A)
     }
     c->sched.bm2l_w0 = P.bm2l_w0;
     c->sched.bm2l_w1 = P.bm2l_w1;
-    if ((s = upload_points<T>(c, P.s_u, (int)P.s_cidx.size(), &A.s_ux, &A.s_uy, &A.s_uz, &A.s_lx, &A.s_ly, &A.s_lz)) !=
-        LPB_OK)
-        return s;
-    if ((s = upload_points<T>(c, P.t_u, (int)P.t_cidx.size(), &A.t_ux, &A.t_uy, &A.t_uz, &A.t_lx, &A.t_ly, &A.t_lz)) !=
-        LPB_OK)
-        return s;
+    // the points, from the builder's sets
+    {
+        int *scidx, *tcidx, *tout;
+        T* su[6] = {};
+        T* tu[6] = {};
+        const size_t ns = (size_t)P.n_spts, nt = (size_t)P.n_tpts;
+        if ((s = dalloc<int>(c, c->plan_bufs, ns, &scidx)) != LPB_OK) return s;
+        if ((s = dalloc<int>(c, c->plan_bufs, nt, &tcidx)) != LPB_OK) return s;
+        if ((s = dalloc<int>(c, c->plan_bufs, nt, &tout)) != LPB_OK) return s;
+        for (int d = 0; d < (sizeof(T) == 4 ? 6 : 3); ++d) {
+            if ((s = dalloc<T>(c, c->plan_bufs, ns, &su[d])) != LPB_OK) return s;
+            if ((s = dalloc<T>(c, c->plan_bufs, nt, &tu[d])) != LPB_OK) return s;
+        }
+        std::string msg;
+        if (!pb.gather<T>(P.s_sets, nullptr, P.ncharges, P.n_spts, scidx, nullptr, su[0], su[1], su[2], su[3], su[4], su[5],
+                          msg) ||
+            !pb.gather<T>(P.t_sets, &P.t_set_slot, P.ncharges, P.n_tpts, tcidx, tout, tu[0], tu[1], tu[2], tu[3], tu[4],
+                          tu[5], msg))
+            return fail(c, (lpb_status)pb.failure(), msg);
+        A.s_cidx = scidx;
+        A.t_cidx = tcidx;
+        A.t_out = tout;
+        A.s_ux = su[0]; A.s_uy = su[1]; A.s_uz = su[2]; A.s_lx = su[3]; A.s_ly = su[4]; A.s_lz = su[5];
+        A.t_ux = tu[0]; A.t_uy = tu[1]; A.t_uz = tu[2]; A.t_lx = tu[3]; A.t_ly = tu[4]; A.t_lz = tu[5];
+    }
     T* qs;
-    if ((s = dalloc<T>(c, c->plan_bufs, P.s_cidx.size(), &qs)) != LPB_OK) return s;
+    if ((s = dalloc<T>(c, c->plan_bufs, (size_t)P.n_spts, &qs)) != LPB_OK) return s;
     A.qs = qs;
     T *me, *le;
     // one extra zero row after the last box of each (missing sources of the batched products read it)
@@ -601,9 +591,14 @@ lpb_status build_and_upload(lpb_ctx* c)
     P.K = (P.p + 1) * (P.p + 1);
     P.leaf_cap = c->opt.leaf_cap;
     int st = 0;
-    std::string msg = build_plan(P, c->media, c->xs, c->ys, c->zs, c->opt.iface_tol, &st);
+    // the points go through the device builder (its buffers are the
+    // context's, returned when it goes out of scope)
+    DevPointBuilder pb(c->stream, [c](size_t b) { return dev_alloc(c, b); }, [c](void* p) { dev_free(c, p); });
+    std::string msg;
+    if (!pb.set_coords(c->xs, c->ys, c->zs, msg)) return fail(c, (lpb_status)pb.failure(), msg);
+    msg = build_plan(P, c->media, c->xs, c->ys, c->zs, c->opt.iface_tol, pb, &st);
     if (st != LPB_OK) return fail(c, (lpb_status)st, msg);
-    lpb_status s = (c->opt.precision == LPB_MIXED) ? fill_args<float>(c, c->a32) : fill_args<double>(c, c->a64);
+    lpb_status s = (c->opt.precision == LPB_MIXED) ? fill_args<float>(c, c->a32, pb) : fill_args<double>(c, c->a64, pb);
     if (s != LPB_OK) {
         free_bufs(c, c->plan_bufs);
         return s;
@@ -632,8 +627,8 @@ lpb_status build_and_upload(lpb_ctx* c)
         std::vector<int> ops(P.m2l_op);
         std::sort(ops.begin(), ops.end());
         c->stats.n_m2l_list_ops = (int64_t)(std::unique(ops.begin(), ops.end()) - ops.begin());
-        c->stats.n_p2m_points = (int64_t)P.s_cidx.size();
-        c->stats.n_l2p_points = (int64_t)P.t_cidx.size();
+        c->stats.n_p2m_points = P.n_spts;
+        c->stats.n_l2p_points = P.n_tpts;
     }
     c->stats.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return LPB_OK;
@@ -1135,16 +1130,25 @@ lpb_status lpb_fmm_info(const lpb_ctx* c, int sys, int fmm, int* desc, double* r
     if (ns) *ns = F.nsrc;
     // leaf keys of the points of this FMM's trees (leaves are contiguous per
     // tree), in the FMM's original orientation, ordered by charge index
-    auto gather = [&](const TreeDesc& T, const std::vector<int>& lstart, const std::vector<int>& cidx,
+    // (the charge indices of the tree's points come from the device)
+    auto gather = [&](const TreeDesc& T, const std::vector<int>& lstart, const int* dcidx,
                       const std::vector<uint64_t>& lcell, uint64_t* out) {
+        if (T.nleaf == 0) return true;
+        const int p0 = lstart[T.leaf0], p1 = lstart[T.leaf0 + T.nleaf];
+        std::vector<int> cidx(p1 - p0);
+        if (hipMemcpy(cidx.data(), dcidx + p0, cidx.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return false;
         std::vector<std::pair<int, uint64_t>> v;
         for (int l = T.leaf0; l < T.leaf0 + T.nleaf; ++l)
-            for (int j = lstart[l]; j < lstart[l + 1]; ++j) v.push_back({cidx[j], leaf_key(lcell[j], F.H, F.flip)});
+            for (int j = lstart[l]; j < lstart[l + 1]; ++j) v.push_back({cidx[j - p0], leaf_key(lcell[l], F.H, F.flip)});
         std::sort(v.begin(), v.end());
         for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].second;
+        return true;
     };
-    if (tkeys) gather(P.trees[F.tgt_tree], P.tl_start, P.t_cidx, P.t_lcell, tkeys);
-    if (skeys) gather(P.trees[F.src_tree], P.sl_start, P.s_cidx, P.s_lcell, skeys);
+    const bool mixed = c->opt.precision == LPB_MIXED;
+    if (tkeys && !gather(P.trees[F.tgt_tree], P.tl_start, mixed ? c->a32.t_cidx : c->a64.t_cidx, P.tl_cell, tkeys))
+        return LPB_EDEVICE;
+    if (skeys && !gather(P.trees[F.src_tree], P.sl_start, mixed ? c->a32.s_cidx : c->a64.s_cidx, P.sl_cell, skeys))
+        return LPB_EDEVICE;
     return LPB_OK;
 }
 

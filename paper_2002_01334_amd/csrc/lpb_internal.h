@@ -153,16 +153,17 @@ struct Plan {
     int nslots = 1;                        // output slots per charge
     int64_t ncharges = 0;
     int max_depth = 0;
-    // points (sources and targets sorted by FMM, then leaf)
-    std::vector<int> s_cidx, t_cidx;       // global charge index
-    std::vector<double> s_u, t_u;          // 3 x n, relative to the leaf centre (canonical frame), SoA
-    std::vector<int> t_out;                // index into parts: slot * ncharges + cidx
+    // points (sources and targets sorted by FMM, then leaf): they stay on the
+    // device; the plan lists the point sets of the builder (PointBuilder
+    // handles) in tree order, each target set with its output slot
+    int64_t n_spts = 0, n_tpts = 0;
+    std::vector<int> s_sets, t_sets, t_set_slot;
     // leaves
     std::vector<int> sl_start, sl_me, sl_fmm, sl_tree;    // source leaves (sl_start has n+1); sl_fmm: representative
     std::vector<int> tl_start, tl_le, tl_fmm, tl_tree;    // target leaves
     std::vector<double> sl_h, tl_h;                       // leaf box side
     std::vector<double> sl_ctr, tl_ctr;                   // leaf centres (canonical local frame), 3 per leaf
-    std::vector<uint64_t> s_lcell, t_lcell;               // leaf cell of each point (canonical, diagnostics)
+    std::vector<uint64_t> sl_cell, tl_cell;               // leaf cells (canonical, diagnostics)
     // boxes
     int n_me = 0, n_le = 0;
     // M2L: CSR by target LE box
@@ -197,10 +198,54 @@ struct Plan {
     std::vector<int> swz_index;    // op -> position in swz_ops
 };
 
-// Build the plan for all systems (host).  Returns an error message or "".
+// Canonical frame of a point set: w = (x - ax, y - ay, wz) with wz = z - az
+// for a free-space set (mode 0); for a reaction set (mode 1) t = z - az on
+// side 1 (az = d_l) or az - z on side 2 (az = d_{l-1}), and wz = t for its
+// targets, -t for its images.
+struct SetFrame {
+    int mode, side, target;
+    double ax, ay, az;
+};
+
+// The per-point part of the plan builder: canonical coordinates, fine cells
+// and keys, the sort, the leaves and each point's offset from its leaf
+// centre.  The points stay with the builder; the plan gets counts, leaf keys
+// and leaf starts.
+class PointBuilder {
+public:
+    virtual ~PointBuilder() = default;
+    // Sort the points `members` (indices into system sys, increasing; global
+    // charge index coff + member) by the Morton key of their fine cell in
+    // frame F with root half side R, equal keys in charge order; counts[l] =
+    // distinct level-l cells, l = 0..kMaxDepth.  Returns a handle >= 0, or -1
+    // with msg set.
+    virtual int keys(int sys, int64_t coff, const std::vector<int>& members, const SetFrame& F, double R,
+                     int counts[kMaxDepth + 1], std::string& msg) = 0;
+    // The set's leaves at depth H (leaf_key: level-H Morton keys in order,
+    // leaf_start: first point of each leaf); computes the points' offsets from
+    // their leaf centres.  False with msg set on failure.
+    virtual bool leaves(int handle, int H, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_start,
+                        std::string& msg) = 0;
+    // lpb_status of the last failure (LPB_ENOMEM or LPB_EDEVICE)
+    virtual int failure() const = 0;
+};
+
+// Build the plan for all systems (boxes, lists and operators on the host,
+// points through `pb`).  Returns an error message or "".
 std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vector<std::vector<double>>& xs,
                        const std::vector<std::vector<double>>& ys, const std::vector<std::vector<double>>& zs,
-                       double iface_tol, int* status);
+                       double iface_tol, PointBuilder& pb, int* status);
+
+// level-l cell coordinates of a level-l Morton key (bits x, y, z interleaved)
+inline uint32_t morton_compact3(uint64_t x)
+{
+    x &= 0x249249249249ull;
+    x = (x | (x >> 2)) & 0x0c30c30c30c3ull;
+    x = (x | (x >> 4)) & 0x00f00f00f00full;
+    x = (x | (x >> 8)) & 0x0000ff0000ffull;
+    x = (x | (x >> 16)) & 0xffffull;
+    return (uint32_t)x;
+}
 
 // Layer of height z: number of interfaces above z.
 inline int layer_of(const Medium& m, double z)

@@ -32,15 +32,6 @@ namespace lpb {
 
 namespace {
 
-uint32_t fine_cell(double x, double c, double R)
-{
-    double t = ((x - c) + R) / (2.0 * R);
-    double f = std::floor(t * 65536.0);
-    if (!(f >= 0.0)) f = 0.0;
-    if (f > 65535.0) f = 65535.0;
-    return (uint32_t)f;
-}
-
 // Morton key of a level-l cell: bits interleaved x, y, z from the top level down.
 uint64_t morton(uint32_t ix, uint32_t iy, uint32_t iz, int l)
 {
@@ -51,31 +42,10 @@ uint64_t morton(uint32_t ix, uint32_t iy, uint32_t iz, int l)
     return k;
 }
 
-// spread the low 16 bits of v to every third bit
-inline uint64_t spread3(uint32_t v)
-{
-    uint64_t x = v & 0xffffu;
-    x = (x | (x << 16)) & 0x0000ff0000ffull;
-    x = (x | (x << 8)) & 0x00f00f00f00full;
-    x = (x | (x << 4)) & 0x0c30c30c30c3ull;
-    x = (x | (x << 2)) & 0x249249249249ull;
-    return x;
-}
-
-// Morton key of a fine cell (16 levels): same bit order as morton(.., 16)
-inline uint64_t morton_fine(uint32_t ix, uint32_t iy, uint32_t iz) { return (spread3(ix) << 2) | (spread3(iy) << 1) | spread3(iz); }
-
 inline uint64_t cellkey(int ix, int iy, int iz)
 {
     return ((uint64_t)(uint32_t)ix << 42) | ((uint64_t)(uint32_t)iy << 21) | (uint64_t)(uint32_t)iz;
 }
-
-struct Pt {
-    uint64_t fkey;   // Morton key of the fine cell (canonical frame)
-    uint32_t c[3];   // fine cells (canonical frame)
-    double w[3];     // canonical coordinates relative to the root centre
-    int cidx;        // global charge index
-};
 
 struct BoxSet {
     // level-l boxes of one point set: canonical cell coords sorted by Morton key
@@ -125,85 +95,45 @@ struct Staging {
     std::vector<M2LPair> m2l_pairs;                             // untiled V-list pairs in list order (grouped by LE box at the end)
     std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: free-space source leaves
     std::vector<std::vector<std::pair<int, int>>> rp_by_tl;     // per target leaf: (reaction FMM, source leaf)
-    std::vector<double> s_ux, s_uy, s_uz, t_ux, t_uy, t_uz;
 };
 
-inline int count_level(const std::vector<Pt>& V, int lv)
-{
-    int sh = 3 * (kCellBits - lv);
-    int n = V.empty() ? 0 : 1;
-    for (size_t i = 1; i < V.size(); ++i)
-        if ((V[i].fkey >> sh) != (V[i - 1].fkey >> sh)) ++n;
-    return n;
-}
+// A point set after the builder's sort: its handle, size and leaves.
+struct PtsInfo {
+    int handle = -1, n = 0;
+    int counts[kMaxDepth + 1] = {};
+    std::vector<uint64_t> lkey;   // level-H Morton key of each leaf
+    std::vector<int> lstart;      // first point of each leaf
+};
 
-// smallest level (<= kMaxDepth) at which N <= cap * (non-empty boxes); V sorted by fkey
-inline int depth_rule(const std::vector<Pt>& V, int cap)
+// smallest level (<= kMaxDepth) at which N <= cap * (non-empty boxes)
+inline int depth_rule(const PtsInfo& V, int cap)
 {
     for (int lv = 0; lv < kMaxDepth; ++lv)
-        if ((int64_t)V.size() <= (int64_t)cap * count_level(V, lv)) return lv;
+        if ((int64_t)V.n <= (int64_t)cap * V.counts[lv]) return lv;
     return kMaxDepth;
-}
-
-// fine cells and keys of a point set, then the set sorted by (key, charge
-// index): a stable LSD radix sort of the 48-bit keys (three 16-bit digits)
-// when the set arrives in charge-index order (it always does), else a
-// comparison sort
-void set_cells(std::vector<Pt>& V, double R)
-{
-    bool in_order = true;
-    for (size_t i = 0; i < V.size(); ++i) {
-        Pt& q = V[i];
-        for (int d = 0; d < 3; ++d) q.c[d] = fine_cell(q.w[d], 0.0, R);
-        q.fkey = morton_fine(q.c[0], q.c[1], q.c[2]);
-        if (i > 0 && V[i - 1].cidx >= q.cidx) in_order = false;
-    }
-    if (!in_order || V.size() < 2048) {
-        std::sort(V.begin(), V.end(), [](const Pt& A, const Pt& B) { return A.fkey != B.fkey ? A.fkey < B.fkey : A.cidx < B.cidx; });
-        return;
-    }
-    // keys sorted with the point's position carried along
-    const size_t n = V.size();
-    std::vector<std::pair<uint64_t, uint32_t>> a(n), b(n);
-    for (size_t i = 0; i < n; ++i) a[i] = {V[i].fkey, (uint32_t)i};
-    std::vector<uint32_t> cnt(1 << 16);
-    for (int pass = 0; pass < 3; ++pass) {
-        const int sh = 16 * pass;
-        std::fill(cnt.begin(), cnt.end(), 0u);
-        for (size_t i = 0; i < n; ++i) cnt[(a[i].first >> sh) & 0xffff]++;
-        uint32_t run = 0;
-        for (auto& c : cnt) {
-            const uint32_t t = c;
-            c = run;
-            run += t;
-        }
-        for (size_t i = 0; i < n; ++i) b[cnt[(a[i].first >> sh) & 0xffff]++] = a[i];
-        a.swap(b);
-    }
-    std::vector<Pt> W(n);
-    for (size_t i = 0; i < n; ++i) W[i] = V[a[i].second];
-    V.swap(W);
 }
 
 // Add one tree (boxes, leaves, points, and its M2M or L2L operators and lists)
 // to the plan.  rep: the FMM whose lambda and root the tree's operators use.
-void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bool target, int rep, int slot,
-              TreeB& T)
+void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool target, int rep, int slot, TreeB& T)
 {
+    // the level-l boxes are the distinct prefixes of the leaf keys, in key order
+    const size_t nl = V.lkey.size();
     T.B.assign(H + 1, BoxSet{});
     for (int lv = 0; lv <= H; ++lv) {
-        int sh = kCellBits - lv;
+        const int sh = 3 * (H - lv);
         BoxSet& bs = T.B[lv];
         bs.nside = 1 << lv;
         if (bs.nside <= BoxSet::kDenseSide) bs.dense.assign((size_t)bs.nside * bs.nside * bs.nside, -1);
-        for (size_t i = 0; i < V.size(); ++i) {
-            if (i > 0 && (V[i].fkey >> (3 * sh)) == (V[i - 1].fkey >> (3 * sh))) continue;
-            uint32_t a = V[i].c[0] >> sh, b = V[i].c[1] >> sh, c = V[i].c[2] >> sh;
-            bs.insert((int)a, (int)b, (int)c, (int)bs.mkey.size());
-            bs.mkey.push_back(V[i].fkey >> (3 * sh));
-            bs.ix.push_back((int)a);
-            bs.iy.push_back((int)b);
-            bs.iz.push_back((int)c);
+        for (size_t i = 0; i < nl; ++i) {
+            const uint64_t k = V.lkey[i] >> sh;
+            if (i > 0 && (V.lkey[i - 1] >> sh) == k) continue;
+            const int a = (int)morton_compact3(k >> 2), b = (int)morton_compact3(k >> 1), c = (int)morton_compact3(k);
+            bs.insert(a, b, c, (int)bs.mkey.size());
+            bs.mkey.push_back(k);
+            bs.ix.push_back(a);
+            bs.iy.push_back(b);
+            bs.iz.push_back(c);
         }
     }
     T.id = (int)P.trees.size();
@@ -224,46 +154,31 @@ void add_tree(Plan& P, Staging& S, const std::vector<Pt>& V, int H, double R, bo
     }
     auto hlev = [&](int lv) { return 2.0 * R / (double)(1 << lv); };
     auto centre = [&](int lv, int i) { return -R + (i + 0.5) * hlev(lv); };   // canonical, relative to the root centre
-    const int shH = kCellBits - H;
-    // leaves and points
+    // leaves (leaf k is level-H box k); the points stay with the builder
+    // (at most three point sets per charge on each side, and build_plan caps
+    // the charges at 2^31 / 4: point indices fit in 32 bits)
+    const int64_t g0 = target ? P.n_tpts : P.n_spts;
+    std::vector<int>& lstart = target ? P.tl_start : P.sl_start;
     T.leaf0 = target ? (int)P.tl_le.size() : (int)P.sl_me.size();
-    int cur = -1;
-    for (size_t k = 0; k < V.size(); ++k) {
-        uint32_t a = V[k].c[0] >> shH, b = V[k].c[1] >> shH, c = V[k].c[2] >> shH;
-        int bi = T.B[H].find((int)a, (int)b, (int)c);
-        if (bi != cur) {
-            if (target) {
-                if (cur >= 0) P.tl_start.push_back((int)P.t_cidx.size());
-                P.tl_le.push_back(H >= 2 ? T.off[H] + bi : -1);
-                P.tl_fmm.push_back(rep);
-                P.tl_tree.push_back(T.id);
-                P.tl_h.push_back(hlev(H));
-                for (uint32_t v : {a, b, c}) P.tl_ctr.push_back(centre(H, (int)v));
-            } else {
-                if (cur >= 0) P.sl_start.push_back((int)P.s_cidx.size());
-                P.sl_me.push_back(H >= 2 ? T.off[H] + bi : -1);
-                P.sl_fmm.push_back(rep);
-                P.sl_tree.push_back(T.id);
-                P.sl_h.push_back(hlev(H));
-                for (uint32_t v : {a, b, c}) P.sl_ctr.push_back(centre(H, (int)v));
-            }
-            cur = bi;
-        }
-        double ux = V[k].w[0] - centre(H, (int)a), uy = V[k].w[1] - centre(H, (int)b), uz = V[k].w[2] - centre(H, (int)c);
-        if (target) {
-            P.t_cidx.push_back(V[k].cidx);
-            P.t_lcell.push_back(cellkey(a, b, c));
-            P.t_out.push_back(slot);   // finalised with ncharges
-            S.t_ux.push_back(ux); S.t_uy.push_back(uy); S.t_uz.push_back(uz);
-        } else {
-            P.s_cidx.push_back(V[k].cidx);
-            P.s_lcell.push_back(cellkey(a, b, c));
-            S.s_ux.push_back(ux); S.s_uy.push_back(uy); S.s_uz.push_back(uz);
-        }
+    for (size_t k = 0; k < nl; ++k) {
+        const int a = T.B[H].ix[k], b = T.B[H].iy[k], c = T.B[H].iz[k];
+        if (k > 0) lstart.push_back((int)(g0 + V.lstart[k]));
+        std::vector<int>& le = target ? P.tl_le : P.sl_me;
+        le.push_back(H >= 2 ? T.off[H] + (int)k : -1);
+        (target ? P.tl_fmm : P.sl_fmm).push_back(rep);
+        (target ? P.tl_tree : P.sl_tree).push_back(T.id);
+        (target ? P.tl_h : P.sl_h).push_back(hlev(H));
+        for (int v : {a, b, c}) (target ? P.tl_ctr : P.sl_ctr).push_back(centre(H, v));
+        (target ? P.tl_cell : P.sl_cell).push_back(cellkey(a, b, c));
     }
-    if (!V.empty()) {
-        if (target) P.tl_start.push_back((int)P.t_cidx.size());
-        else P.sl_start.push_back((int)P.s_cidx.size());
+    if (V.n > 0) lstart.push_back((int)(g0 + V.n));
+    if (target) {
+        P.t_sets.push_back(V.handle);
+        P.t_set_slot.push_back(slot);
+        P.n_tpts += V.n;
+    } else {
+        P.s_sets.push_back(V.handle);
+        P.n_spts += V.n;
     }
     T.nleaf = (target ? (int)P.tl_le.size() : (int)P.sl_me.size()) - T.leaf0;
     td.leaf0 = T.leaf0;
@@ -516,7 +431,7 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
 
 std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vector<std::vector<double>>& xs,
                        const std::vector<std::vector<double>>& ys, const std::vector<std::vector<double>>& zs,
-                       double iface_tol, int* status)
+                       double iface_tol, PointBuilder& pb, int* status)
 {
     const int cap = P.leaf_cap;
     *status = LPB_OK;
@@ -559,10 +474,11 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     }
 
     // ---- accumulators of the plan ----
-    P.s_cidx.clear(); P.t_cidx.clear(); P.s_u.clear(); P.t_u.clear(); P.t_out.clear();
+    P.n_spts = P.n_tpts = 0;
+    P.s_sets.clear(); P.t_sets.clear(); P.t_set_slot.clear();
     P.sl_start.assign(1, 0); P.sl_me.clear(); P.sl_fmm.clear(); P.sl_tree.clear(); P.sl_h.clear();
     P.tl_start.assign(1, 0); P.tl_le.clear(); P.tl_fmm.clear(); P.tl_tree.clear(); P.tl_h.clear();
-    P.sl_ctr.clear(); P.tl_ctr.clear(); P.s_lcell.clear(); P.t_lcell.clear();
+    P.sl_ctr.clear(); P.tl_ctr.clear(); P.sl_cell.clear(); P.tl_cell.clear();
     P.n_me = P.n_le = 0;
     P.ops.clear(); P.rkeys.clear();
     P.tfl.clear(); P.tiles.clear(); P.grid_me.clear(); P.grid_le.clear(); P.optab.clear();
@@ -678,16 +594,19 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
             double r = 0.0;
             for (int d = 0; d < 3; ++d) r = std::max(r, 0.5 * (hi[d] - lo[d]));
             F.R = r > 0 ? r : 0.5;
-            std::vector<Pt> V(mem.size());
-            for (size_t k = 0; k < mem.size(); ++k) {
-                int i = mem[k];
-                V[k].w[0] = xs[s][i] - F.cx;
-                V[k].w[1] = ys[s][i] - F.cy;
-                V[k].w[2] = zs[s][i] - F.cz;
-                V[k].cidx = (int)(coff + i);
+            PtsInfo V;
+            std::string msg;
+            V.n = (int)mem.size();
+            V.handle = pb.keys(s, coff, mem, SetFrame{0, 0, 0, F.cx, F.cy, F.cz}, F.R, V.counts, msg);
+            if (V.handle < 0) {
+                *status = pb.failure();
+                return msg;
             }
-            set_cells(V, F.R);
             F.H = depth_rule(V, cap);
+            if (!pb.leaves(V.handle, F.H, V.lkey, V.lstart, msg)) {
+                *status = pb.failure();
+                return msg;
+            }
             P.max_depth = std::max(P.max_depth, F.H);
             const int fid = (int)P.fmm.size();
             P.fmm.push_back(F);
@@ -730,23 +649,21 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         r = std::max(r, 0.5 * (hi[1] - lo[1]));
         const double R = r > 0 ? r : 0.5;
         // point sets: [l][sd][0 = images at -tau, 1 = targets at +tau]
-        std::vector<std::array<std::array<std::vector<Pt>, 2>, 3>> sets(L + 1);
+        std::vector<std::array<std::array<PtsInfo, 2>, 3>> sets(L + 1);
         int H = 0;
         for (int l = 0; l <= L; ++l)
             for (int sd = 1; sd <= 2; ++sd) {
                 if (!side_ok(l, sd) || members[l].empty()) continue;
                 for (int tg = 0; tg < 2; ++tg) {
-                    auto& V = sets[l][sd][tg];
-                    V.resize(members[l].size());
-                    for (size_t k = 0; k < members[l].size(); ++k) {
-                        int i = members[l][k];
-                        double t = tau(l, sd, zs[s][i]);
-                        V[k].w[0] = xs[s][i] - gcx;
-                        V[k].w[1] = ys[s][i] - gcy;
-                        V[k].w[2] = tg ? t : -t;
-                        V[k].cidx = (int)(coff + i);
+                    PtsInfo& V = sets[l][sd][tg];
+                    std::string msg;
+                    V.n = (int)members[l].size();
+                    V.handle = pb.keys(s, coff, members[l], SetFrame{1, sd, tg, gcx, gcy, sd == 1 ? m.d[l] : m.d[l - 1]}, R,
+                                       V.counts, msg);
+                    if (V.handle < 0) {
+                        *status = pb.failure();
+                        return msg;
                     }
-                    set_cells(V, R);
                     H = std::max(H, depth_rule(V, cap));
                 }
             }
@@ -760,6 +677,16 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
             H = std::max(H, hs);
         }
         P.max_depth = std::max(P.max_depth, H);
+        for (int l = 0; l <= L; ++l)
+            for (int sd = 1; sd <= 2; ++sd)
+                for (int tg = 0; tg < 2; ++tg) {
+                    PtsInfo& V = sets[l][sd][tg];
+                    std::string msg;
+                    if (V.handle >= 0 && !pb.leaves(V.handle, H, V.lkey, V.lstart, msg)) {
+                        *status = pb.failure();
+                        return msg;
+                    }
+                }
         // components in Algorithm 2 order
         std::vector<int> comp_fid;
         for (int a = 1; a <= 2; ++a)
@@ -798,19 +725,6 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         }
     }
     // ---- finalise flattened arrays ----
-    P.s_u.resize(3 * S.s_ux.size());
-    for (size_t i = 0; i < S.s_ux.size(); ++i) {
-        P.s_u[i] = S.s_ux[i];
-        P.s_u[S.s_ux.size() + i] = S.s_uy[i];
-        P.s_u[2 * S.s_ux.size() + i] = S.s_uz[i];
-    }
-    P.t_u.resize(3 * S.t_ux.size());
-    for (size_t i = 0; i < S.t_ux.size(); ++i) {
-        P.t_u[i] = S.t_ux[i];
-        P.t_u[S.t_ux.size() + i] = S.t_uy[i];
-        P.t_u[2 * S.t_ux.size() + i] = S.t_uz[i];
-    }
-    for (size_t i = 0; i < P.t_out.size(); ++i) P.t_out[i] = (int)(P.t_out[i] * P.ncharges + P.t_cidx[i]);
     // CSR by LE box, each box's pairs in the order they were listed (a stable
     // counting sort of the pair list by box)
     P.m2l_ptr.assign((size_t)P.n_le + 1, 0);
