@@ -335,24 +335,63 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         const bool tiled = lv >= tiled_min && lv <= tiled_max;
         int nside = 1 << lv;
         double h = hlev(lv);
+        if (tiled) {
+            // the tiles' operator tables cover these pairs: only their number
+            // is needed, the non-empty source boxes among the children of the
+            // parent's neighbours less those adjacent to the target, from
+            // prefix sums of the source occupancy grid
+            const int n1 = nside + 1;
+            std::vector<int> ps((size_t)n1 * n1 * n1, 0);
+            auto at = [&](int x, int y, int z) -> int& { return ps[((size_t)x * n1 + y) * n1 + z]; };
+            for (int x = 0; x < nside; ++x)
+                for (int y = 0; y < nside; ++y)
+                    for (int z = 0; z < nside; ++z)
+                        at(x + 1, y + 1, z + 1) = (SB[lv].find(x, y, z) >= 0 ? 1 : 0) + at(x, y + 1, z + 1) + at(x + 1, y, z + 1) +
+                                                  at(x + 1, y + 1, z) - at(x, y, z + 1) - at(x, y + 1, z) - at(x + 1, y, z) +
+                                                  at(x, y, z);
+            auto box = [&](int x0, int x1, int y0, int y1, int z0, int z1) {
+                x0 = std::max(x0, 0); y0 = std::max(y0, 0); z0 = std::max(z0, 0);
+                x1 = std::min(x1, nside - 1) + 1; y1 = std::min(y1, nside - 1) + 1; z1 = std::min(z1, nside - 1) + 1;
+                if (x0 >= x1 || y0 >= y1 || z0 >= z1) return (int64_t)0;
+                return (int64_t)at(x1, y1, z1) - at(x0, y1, z1) - at(x1, y0, z1) - at(x1, y1, z0) + at(x0, y0, z1) +
+                       at(x0, y1, z0) + at(x1, y0, z0) - at(x0, y0, z0);
+            };
+            for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
+                const int tx = TB[lv].ix[k], ty = TB[lv].iy[k], tz = TB[lv].iz[k];
+                const int px = 2 * (tx >> 1), py = 2 * (ty >> 1), pz = 2 * (tz >> 1);
+                const int64_t np = box(px - 2, px + 3, py - 2, py + 3, pz - 2, pz + 3) -
+                                   box(tx - 1, tx + 1, ty - 1, ty + 1, tz - 1, tz + 1);
+                P.n_m2l_tile_pairs += np;
+                P.n_m2l_pairs += np;
+            }
+            continue;
+        }
+        // parents whose children can hold source boxes: those within the
+        // cell range of the level's source boxes (a reaction FMM's images all
+        // lie below the interface plane, so most targets have no V-list)
+        int qlo[3] = {nside, nside, nside}, qhi[3] = {-1, -1, -1};
+        for (size_t i = 0; i < SB[lv].mkey.size(); ++i) {
+            const int c[3] = {SB[lv].ix[i] >> 1, SB[lv].iy[i] >> 1, SB[lv].iz[i] >> 1};
+            for (int d = 0; d < 3; ++d) {
+                qlo[d] = std::min(qlo[d], c[d]);
+                qhi[d] = std::max(qhi[d], c[d]);
+            }
+        }
         for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
             int tx = TB[lv].ix[k], ty = TB[lv].iy[k], tz = TB[lv].iz[k];
             int le = TT.off[lv] + k;
-            for (int qx = (tx >> 1) - 1; qx <= (tx >> 1) + 1; ++qx)
-                for (int qy = (ty >> 1) - 1; qy <= (ty >> 1) + 1; ++qy)
-                    for (int qz = (tz >> 1) - 1; qz <= (tz >> 1) + 1; ++qz) {
-                        if (qx < 0 || qy < 0 || qz < 0 || qx >= nside / 2 || qy >= nside / 2 || qz >= nside / 2) continue;
+            const int qx0 = std::max((tx >> 1) - 1, qlo[0]), qx1 = std::min((tx >> 1) + 1, qhi[0]);
+            const int qy0 = std::max((ty >> 1) - 1, qlo[1]), qy1 = std::min((ty >> 1) + 1, qhi[1]);
+            const int qz0 = std::max((tz >> 1) - 1, qlo[2]), qz1 = std::min((tz >> 1) + 1, qhi[2]);
+            for (int qx = qx0; qx <= qx1; ++qx)
+                for (int qy = qy0; qy <= qy1; ++qy)
+                    for (int qz = qz0; qz <= qz1; ++qz) {
                         for (int o = 0; o < 8; ++o) {
                             int sx = 2 * qx + ((o >> 2) & 1), sy = 2 * qy + ((o >> 1) & 1), sz = 2 * qz + (o & 1);
                             int dx = sx - tx, dy = sy - ty, dz = sz - tz;
                             if (std::abs(dx) <= 1 && std::abs(dy) <= 1 && std::abs(dz) <= 1) continue;
                             const int sbox = SB[lv].find(sx, sy, sz);
                             if (sbox < 0) continue;
-                            if (tiled) {   // the tile's operator table covers it
-                                P.n_m2l_tile_pairs++;
-                                P.n_m2l_pairs++;
-                                continue;
-                            }
                             int op, xc;
                             if (F.kind == 0) {
                                 // one operator per offset with non-negative components, D A D for the others
@@ -406,10 +445,21 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         {0, 0, 0},   {-1, -1, -1}, {-1, -1, 0}, {-1, -1, 1}, {-1, 0, -1}, {-1, 0, 0}, {-1, 0, 1}, {-1, 1, -1}, {-1, 1, 0},
         {-1, 1, 1},  {0, -1, -1},  {0, -1, 0},  {0, -1, 1},  {0, 0, -1},  {0, 0, 1},  {0, 1, -1}, {0, 1, 0},   {0, 1, 1},
         {1, -1, -1}, {1, -1, 0},   {1, -1, 1},  {1, 0, -1},  {1, 0, 0},   {1, 0, 1},  {1, 1, -1}, {1, 1, 0},   {1, 1, 1}};
+    int ulo[3] = {nside, nside, nside}, uhi[3] = {-1, -1, -1};
+    for (size_t i = 0; i < SB[H].mkey.size(); ++i) {
+        const int c[3] = {SB[H].ix[i], SB[H].iy[i], SB[H].iz[i]};
+        for (int d = 0; d < 3; ++d) {
+            ulo[d] = std::min(ulo[d], c[d]);
+            uhi[d] = std::max(uhi[d], c[d]);
+        }
+    }
     for (int k = 0; k < TT.nleaf; ++k) {
         int tx = TB[H].ix[k], ty = TB[H].iy[k], tz = TB[H].iz[k];
         int tl = TT.leaf0 + k;
         int nt = P.tl_start[tl + 1] - P.tl_start[tl];
+        // (no source leaf within one cell: empty U-list)
+        if (tx + 1 < ulo[0] || tx - 1 > uhi[0] || ty + 1 < ulo[1] || ty - 1 > uhi[1] || tz + 1 < ulo[2] || tz - 1 > uhi[2])
+            continue;
         for (const auto& du : kUOrder) {
                     int sx = tx + du[0], sy = ty + du[1], sz = tz + du[2];
                     if (sx < 0 || sy < 0 || sz < 0 || sx >= nside || sy >= nside || sz >= nside) continue;
