@@ -236,6 +236,18 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                        const std::vector<std::vector<double>>& ys, const std::vector<std::vector<double>>& zs,
                        double iface_tol, PointBuilder& pb, int* status);
 
+// the low 16 bits of v spread to every third bit (a level-l Morton key is
+// spread3(ix) << 2 | spread3(iy) << 1 | spread3(iz))
+inline uint64_t morton_spread3(uint32_t v)
+{
+    uint64_t x = v & 0xffffu;
+    x = (x | (x << 16)) & 0x0000ff0000ffull;
+    x = (x | (x << 8)) & 0x00f00f00f00full;
+    x = (x | (x << 4)) & 0x0c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x249249249249ull;
+    return x;
+}
+
 // level-l cell coordinates of a level-l Morton key (bits x, y, z interleaved)
 inline uint32_t morton_compact3(uint64_t x)
 {

@@ -51,23 +51,32 @@ struct BoxSet {
     // level-l boxes of one point set: canonical cell coords sorted by Morton key
     std::vector<uint64_t> mkey;
     std::vector<int> ix, iy, iz;
-    // cell -> position: a dense grid up to kDenseSide^3 cells, a hash map beyond
+    // cell -> position: a dense grid while it has at most kDenseRatio cells
+    // per box (and at most kDenseSide^3), else a binary search of the keys
     static constexpr int kDenseSide = 128;
+    static constexpr size_t kDenseRatio = 64;
     int nside = 0;
+    bool use_dense = false;
     std::vector<int> dense;
-    std::unordered_map<uint64_t, int> idx;
+    void init(int lv, size_t nbox)
+    {
+        nside = 1 << lv;
+        const size_t cells = (size_t)nside * nside * nside;
+        use_dense = nside <= kDenseSide && cells <= std::max<size_t>(4096, kDenseRatio * nbox);
+        if (use_dense) dense.assign(cells, -1);
+    }
     void insert(int a, int b, int c, int pos)
     {
-        if (nside <= kDenseSide) dense[((size_t)a * nside + b) * nside + c] = pos;
-        else idx[cellkey(a, b, c)] = pos;
+        if (use_dense) dense[((size_t)a * nside + b) * nside + c] = pos;
     }
     // position of cell (a, b, c), -1 if empty or outside the grid
     int find(int a, int b, int c) const
     {
         if (a < 0 || b < 0 || c < 0 || a >= nside || b >= nside || c >= nside) return -1;
-        if (nside <= kDenseSide) return dense[((size_t)a * nside + b) * nside + c];
-        auto it = idx.find(cellkey(a, b, c));
-        return it == idx.end() ? -1 : it->second;
+        if (use_dense) return dense[((size_t)a * nside + b) * nside + c];
+        const uint64_t k = (morton_spread3((uint32_t)a) << 2) | (morton_spread3((uint32_t)b) << 1) | morton_spread3((uint32_t)c);
+        auto it = std::lower_bound(mkey.begin(), mkey.end(), k);
+        return (it != mkey.end() && *it == k) ? (int)(it - mkey.begin()) : -1;
     }
 };
 
@@ -123,8 +132,9 @@ void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool targe
     for (int lv = 0; lv <= H; ++lv) {
         const int sh = 3 * (H - lv);
         BoxSet& bs = T.B[lv];
-        bs.nside = 1 << lv;
-        if (bs.nside <= BoxSet::kDenseSide) bs.dense.assign((size_t)bs.nside * bs.nside * bs.nside, -1);
+        size_t nb = 0;
+        for (size_t i = 0; i < nl; ++i) nb += (i == 0 || (V.lkey[i - 1] >> sh) != (V.lkey[i] >> sh));
+        bs.init(lv, nb);
         for (size_t i = 0; i < nl; ++i) {
             const uint64_t k = V.lkey[i] >> sh;
             if (i > 0 && (V.lkey[i - 1] >> sh) == k) continue;
@@ -343,12 +353,16 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
             const int n1 = nside + 1;
             std::vector<int> ps((size_t)n1 * n1 * n1, 0);
             auto at = [&](int x, int y, int z) -> int& { return ps[((size_t)x * n1 + y) * n1 + z]; };
-            for (int x = 0; x < nside; ++x)
-                for (int y = 0; y < nside; ++y)
-                    for (int z = 0; z < nside; ++z)
-                        at(x + 1, y + 1, z + 1) = (SB[lv].find(x, y, z) >= 0 ? 1 : 0) + at(x, y + 1, z + 1) + at(x + 1, y, z + 1) +
-                                                  at(x + 1, y + 1, z) - at(x, y, z + 1) - at(x, y + 1, z) - at(x + 1, y, z) +
-                                                  at(x, y, z);
+            for (size_t i = 0; i < SB[lv].mkey.size(); ++i) at(SB[lv].ix[i] + 1, SB[lv].iy[i] + 1, SB[lv].iz[i] + 1) = 1;
+            for (int x = 1; x <= nside; ++x)
+                for (int y = 1; y <= nside; ++y)
+                    for (int z = 1; z <= nside; ++z) at(x, y, z) += at(x, y, z - 1);
+            for (int x = 1; x <= nside; ++x)
+                for (int y = 1; y <= nside; ++y)
+                    for (int z = 1; z <= nside; ++z) at(x, y, z) += at(x, y - 1, z);
+            for (int x = 1; x <= nside; ++x)
+                for (int y = 1; y <= nside; ++y)
+                    for (int z = 1; z <= nside; ++z) at(x, y, z) += at(x - 1, y, z);
             auto box = [&](int x0, int x1, int y0, int y1, int z0, int z1) {
                 x0 = std::max(x0, 0); y0 = std::max(y0, 0); z0 = std::max(z0, 0);
                 x1 = std::min(x1, nside - 1) + 1; y1 = std::min(y1, nside - 1) + 1; z1 = std::min(z1, nside - 1) + 1;
@@ -817,22 +831,44 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.bl2l_lv[kMaxDepth + 1] = (int)P.bw_term_ptr.size() - 1;
     P.bm2l_w0 = (int)P.bw_term_ptr.size() - 1;
     {
-        std::vector<std::pair<int, int>> byop(P.m2l_op.size());   // (op, pair position)
-        for (size_t k = 0; k < P.m2l_op.size(); ++k) byop[k] = {P.m2l_op[k], (int)k};
-        std::sort(byop.begin(), byop.end());
+        // (op, pair position) in increasing order: a counting sort by operator
+        // (stable, so positions stay increasing within an operator)
+        std::vector<std::pair<int, int>> byop(P.m2l_op.size());
+        {
+            std::vector<int> start(P.ops.size() + 1, 0);
+            for (int op : P.m2l_op) start[op + 1]++;
+            for (size_t i = 0; i < P.ops.size(); ++i) start[i + 1] += start[i];
+            for (size_t k = 0; k < P.m2l_op.size(); ++k) byop[start[P.m2l_op[k]]++] = {P.m2l_op[k], (int)k};
+        }
+        // one term of up to 64 pairs per item, written straight into the arrays
+        {
+            size_t items = 0;
+            for (size_t i = 0; i < byop.size();) {
+                size_t e = i;
+                while (e < byop.size() && e - i < 64 && byop[e].first == byop[i].first) ++e;
+                ++items;
+                i = e;
+            }
+            P.bw_op.reserve(P.bw_op.size() + items);
+            P.bw_term_ptr.reserve(P.bw_term_ptr.size() + items);
+            P.bw_src.reserve(P.bw_src.size() + 64 * items);
+            P.bw_dst.reserve(P.bw_dst.size() + 64 * items);
+            P.bw_xc.reserve(P.bw_xc.size() + 64 * items);
+        }
         for (size_t i = 0; i < byop.size();) {
             size_t e = i;
             while (e < byop.size() && e - i < 64 && byop[e].first == byop[i].first) ++e;
-            BWork wk;
-            wk.dst.fill(-1);
-            wk.op.assign(1, byop[i].first);
-            wk.src.assign(64, -1);
+            P.bw_op.push_back(byop[i].first);
+            const size_t s0 = P.bw_src.size(), d0 = P.bw_dst.size();
+            P.bw_src.resize(s0 + 64, -1);
+            P.bw_dst.resize(d0 + 64, -1);
+            P.bw_xc.resize(d0 + 64, -1);
             for (size_t j = i; j < e; ++j) {
-                wk.src[j - i] = P.m2l_src[byop[j].second];
-                wk.dst[j - i] = byop[j].second;
-                wk.xc[j - i] = P.m2l_xc[byop[j].second];
+                P.bw_src[s0 + j - i] = P.m2l_src[byop[j].second];
+                P.bw_dst[d0 + j - i] = byop[j].second;
+                P.bw_xc[d0 + j - i] = P.m2l_xc[byop[j].second];
             }
-            push_work(wk);
+            P.bw_term_ptr.push_back((int)P.bw_op.size());
             i = e;
         }
     }

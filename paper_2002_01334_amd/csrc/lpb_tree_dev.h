@@ -47,6 +47,11 @@ private:
     };
     void* get(size_t bytes);
     void put(void*& p);
+    // temporaries of one kind, kept and grown from set to set
+    enum { kKeyIn, kIdx, kCnt, kSortTmp, kFlag, kPos, kLeafKey, kLeafStart, kScanTmp, kScratchKinds };
+    void* scratch(int kind, size_t bytes);
+    void* scr_[kScratchKinds] = {};
+    size_t scr_bytes_[kScratchKinds] = {};
     bool check(hipError_t e, const char* what, std::string& msg);
     hipStream_t st_;
     std::function<void*(size_t)> alloc_;

@@ -169,6 +169,21 @@ DevPointBuilder::~DevPointBuilder()
     for (auto* v : {&x_, &y_, &z_})
         for (double* q : *v)
             if (q) free_(q);
+    for (void* q : scr_)
+        if (q) free_(q);
+}
+
+void* DevPointBuilder::scratch(int kind, size_t bytes)
+{
+    if (scr_[kind] && scr_bytes_[kind] >= bytes) return scr_[kind];
+    if (scr_[kind]) {
+        (void)hipStreamSynchronize(st_);   // (nothing in flight may still use it)
+        free_(scr_[kind]);
+    }
+    bytes = std::max<size_t>(bytes, 4096);
+    scr_[kind] = get(bytes);
+    scr_bytes_[kind] = scr_[kind] ? bytes : 0;
+    return scr_[kind];
 }
 
 void* DevPointBuilder::get(size_t bytes)
@@ -229,9 +244,9 @@ int DevPointBuilder::keys(int sys, int64_t coff, const std::vector<int>& members
     s.key = (uint64_t*)get(n * sizeof(uint64_t));
     s.perm = (int*)get(n * sizeof(int));
     s.w = (double*)get(3 * (size_t)n * sizeof(double));
-    uint64_t* kin = (uint64_t*)get(n * sizeof(uint64_t));
-    int* idx = (int*)get(n * sizeof(int));
-    int* cnt = (int*)get((kMaxDepth + 1) * sizeof(int));
+    uint64_t* kin = (uint64_t*)scratch(kKeyIn, n * sizeof(uint64_t));
+    int* idx = (int*)scratch(kIdx, n * sizeof(int));
+    int* cnt = (int*)scratch(kCnt, (kMaxDepth + 1) * sizeof(int));
     void* tmp = nullptr;
     bool ok = s.members && s.key && s.perm && s.w && kin && idx && cnt;
     if (!ok) msg = "point builder: device allocation failed";
@@ -248,7 +263,7 @@ int DevPointBuilder::keys(int sys, int64_t coff, const std::vector<int>& members
         if (ok) ok = check(rocprim::radix_sort_pairs(nullptr, tb, kin, s.key, idx, s.perm, (unsigned)n, 0, 48, st_),
                            "sort size", msg);
         if (ok) {
-            tmp = get(tb);
+            tmp = scratch(kSortTmp, tb);
             if (!tmp) {
                 ok = false;
                 msg = "point builder: device allocation failed";
@@ -265,8 +280,6 @@ int DevPointBuilder::keys(int sys, int64_t coff, const std::vector<int>& members
     if (ok) ok = check(hipMemcpyAsync(counts, cnt, (kMaxDepth + 1) * sizeof(int), hipMemcpyDeviceToHost, st_),
                        "count download", msg);
     if (ok) ok = check(hipStreamSynchronize(st_), "keys", msg);
-    void* t[] = {kin, idx, cnt, tmp};
-    for (void*& q : t) put(q);
     return ok ? handle : -1;
 }
 
@@ -279,10 +292,10 @@ bool DevPointBuilder::leaves(int handle, int H, std::vector<uint64_t>& leaf_key,
     leaf_key.clear();
     leaf_start.clear();
     if (n == 0) return true;
-    int* flag = (int*)get(n * sizeof(int));
-    int* pos = (int*)get(n * sizeof(int));
-    uint64_t* lk = (uint64_t*)get(n * sizeof(uint64_t));
-    int* ls = (int*)get(n * sizeof(int));
+    int* flag = (int*)scratch(kFlag, n * sizeof(int));
+    int* pos = (int*)scratch(kPos, n * sizeof(int));
+    uint64_t* lk = (uint64_t*)scratch(kLeafKey, n * sizeof(uint64_t));
+    int* ls = (int*)scratch(kLeafStart, n * sizeof(int));
     s.cidx = (int*)get(n * sizeof(int));
     s.u = (double*)get(3 * (size_t)n * sizeof(double));
     void* tmp = nullptr;
@@ -297,7 +310,7 @@ bool DevPointBuilder::leaves(int handle, int H, std::vector<uint64_t>& leaf_key,
     if (ok) ok = check(rocprim::inclusive_scan(nullptr, tb, flag, pos, (size_t)n, rocprim::plus<int>(), st_), "scan size",
                        msg);
     if (ok) {
-        tmp = get(tb);
+        tmp = scratch(kScanTmp, tb);
         if (!tmp) {
             ok = false;
             msg = "point builder: device allocation failed";
@@ -320,8 +333,6 @@ bool DevPointBuilder::leaves(int handle, int H, std::vector<uint64_t>& leaf_key,
                    "leaf download", msg) &&
              check(hipStreamSynchronize(st_), "leaves", msg);
     }
-    void* t[] = {flag, pos, lk, ls, tmp};
-    for (void*& q : t) put(q);
     // the sort state is no longer needed
     void* d[] = {s.key, s.perm, s.w, s.members};
     for (void*& q : d) put(q);
