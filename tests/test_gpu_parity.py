@@ -5,6 +5,8 @@ l2 error per layer and per output slot <= 1e-10; tree structure bit-exact;
 GPU FP64 vs oracle direct sum within the truncation error of p; mixed
 precision vs FP64 <= 1e-6; batched vs single-system FP64 bit-identical.
 """
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -46,6 +48,40 @@ def test_tree_matches_oracle(lpb, c1, leaf_cap):
         assert np.array_equal(info["root"], root)
         assert np.array_equal(info["tkeys"], tk) and np.array_equal(info["skeys"], sk)
     ctx.close()
+
+
+def _tree_keys_match(lpb, prob, leaf_cap):
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    ctx = lpb.Context(p=2, leaf_cap=leaf_cap)
+    ctx.set_layers(prob.eps, prob.lam, prob.d)
+    ctx.build_tree(prob.x, prob.y, prob.z)
+    for c in range(O.num_components(len(prob.eps))):
+        info = ctx.fmm_info(c, keys=True)
+        d, tk, sk, root = O.component_tree(ly, prob.x, prob.y, prob.z, c, leaf_cap=leaf_cap)
+        assert info["depth"] == d, c
+        assert np.array_equal(info["root"], root), c
+        assert np.array_equal(info["tkeys"], tk) and np.array_equal(info["skeys"], sk), c
+    ctx.close()
+
+
+def test_tree_keys_on_lattices_repeats_and_large_sets(lpb):
+    """The point sets are sorted, cut into leaves and offset on the device:
+    charges on lattice planes (cell faces at every level), charges repeated at
+    one position (equal keys, kept in charge order), and sets large enough for
+    a sort over many blocks give the oracle's leaf keys."""
+    rng = np.random.default_rng(5)
+    g = np.arange(17) / 16.0 - 0.5
+    xs, ys, zs = [], [], []
+    for zc in (0.6, -0.6, -1.8):
+        X, Y, Z = np.meshgrid(g, g, g * 0.9 + zc, indexing="ij")
+        xs.append(X.ravel()); ys.append(Y.ravel()); zs.append(Z.ravel())
+    x, y, z = (np.concatenate(v) for v in (xs, ys, zs))
+    rep = rng.integers(0, len(x), len(x) // 3)   # a third of the charges again, at the same positions
+    x, y, z = (np.concatenate([v, v[rep]]) for v in (x, y, z))
+    layer = np.where(z > 0, 0, np.where(z > -1.2, 1, 2))
+    lattice = dataclasses.replace(inputs.three_layer(10, seed=0), x=x, y=y, z=z, q=np.ones_like(x), layer=layer)
+    _tree_keys_match(lpb, lattice, 8)
+    _tree_keys_match(lpb, inputs.three_layer(150_000, seed=4), 50)
 
 
 @pytest.mark.parametrize("p,leaf_cap", [(4, 8), (10, 8), (10, 50), (6, 3)])
