@@ -90,6 +90,7 @@ struct lpb_ctx {
     hipEvent_t evs[11] = {};
     // captured evaluation passes (options.graph)
     hipStream_t own_stream = nullptr;   // capture needs a stream other than the null stream
+    EvalFork fork{};                    // side stream (default priority) and its events
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
     bool tune_needed = true;
@@ -807,7 +808,7 @@ lpb_status run_eval_t(lpb_ctx* c, EvalArgs<T>& A)
         // every pass is a kernel (no memset nodes); the schedules and buffers
         // it captures stay fixed until the next tree or operator change
         HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, nullptr);
+        hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, nullptr, &c->fork);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(c->stream, &g);
         if (e != hipSuccess || e2 != hipSuccess) {
@@ -822,7 +823,7 @@ lpb_status run_eval_t(lpb_ctx* c, EvalArgs<T>& A)
         HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
     } else {
         hipEvent_t* ev = c->opt.timing ? c->evs : nullptr;
-        hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, ev);
+        hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, ev, &c->fork);
         if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     }
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
@@ -845,7 +846,7 @@ lpb_status run_noalloc_t(lpb_ctx* c, const EvalArgs<T>& A0, const double* q, dou
     A.phi = phi;
     A.parts = parts;
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
-    hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, nullptr);
+    hipError_t e = eval_run<T>(A, c->sched, c->opt.stages, c->stream, nullptr, &c->fork);
     if (e != hipSuccess) return fail(c, LPB_EDEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
     HIPCHK(c, hipEventRecord(c->ev1, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -941,6 +942,10 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
         return fail(nullptr, LPB_EDEVICE, "event create failed");
     for (auto& e : c->evs)
         if (hipEventCreate(&e) != hipSuccess) return fail(nullptr, LPB_EDEVICE, "event create failed");
+    if (hipStreamCreateWithFlags(&c->fork.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork.join, hipEventDisableTiming) != hipSuccess)
+        return fail(nullptr, LPB_EDEVICE, "side stream create failed");
     *out = c;
     guard.c = nullptr;
     return LPB_OK;
@@ -1179,6 +1184,9 @@ void lpb_destroy(lpb_ctx* c)
     free_bufs(c, c->op_bufs);
     for (DevBuf* b : {&c->d_btab, &c->d_gtab, &c->d_glx, &c->d_glw, &c->d_flag}) free_buf(c, *b);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    if (c->fork.side) (void)hipStreamDestroy(c->fork.side);
+    if (c->fork.fork) (void)hipEventDestroy(c->fork.fork);
+    if (c->fork.join) (void)hipEventDestroy(c->fork.join);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (auto& e : c->evs)

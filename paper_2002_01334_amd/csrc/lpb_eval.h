@@ -80,8 +80,19 @@ struct EvalSched {
     int bm2l_w0, bm2l_w1;
 };
 
+// A second stream for the untiled V-list translations, which then run beside
+// the tiled M2L (they write other LE boxes): `fork` is recorded on the main
+// stream before them, `join` on the side stream after them.
+struct EvalFork {
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+// One evaluation.  With per-stage events (ev) or without a fork every pass
+// runs on st in order.
 template <typename T>
-hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev);
+hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev,
+                    const EvalFork* fk = nullptr);
 
 // Launchers of kernels that live in their own translation units: the tiled
 // free-space M2L (all forms) and P2M / L2P with the order fixed at compile

@@ -760,7 +760,8 @@ __global__ void k_sum(int64_t n, int nslots, const double* __restrict__ parts, d
 
 // ---------------------------------------------------------------------------
 template <typename T>
-hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev)
+hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStream_t st, hipEvent_t* ev,
+                    const EvalFork* fk)
 {
 #define LPB_MARK(k) \
     if (ev) (void)hipEventRecord(ev[k], st)
@@ -795,11 +796,27 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     for (int l = kMaxDepth; l >= 0 && far; --l) launch_batched<T>(A, S.bm2m_lv[l], S.bm2m_lv[l + 1], A.me, A.n_me, A.me, 0, st);
     // V-list translations (all levels), then the downward pass
     LPB_MARK(3);
+    // the untiled V-list pairs write LE boxes of other levels or trees than
+    // the tiled M2L: with a fork they run on the side stream beside it
+    const bool list = far && S.bm2l_w1 > S.bm2l_w0;
+    const bool split = list && fk && fk->side && !ev && A.n_tiles > 0;
+    auto run_list = [&](hipStream_t s) {
+        launch_batched_x<T, true>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, s);
+        hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(128), 0, s, A);
+    };
+    if (split) {
+        hipError_t e = hipEventRecord(fk->fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fk->side, fk->fork, 0);
+        if (e != hipSuccess) return e;
+        run_list(fk->side);
+        if ((e = hipEventRecord(fk->join, fk->side)) != hipSuccess) return e;
+    }
     if (far && A.n_tiles > 0) launch_m2l_tile<T>(A, st);
     LPB_MARK(4);
-    if (far && S.bm2l_w1 > S.bm2l_w0) {
-        launch_batched_x<T, true>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, st);
-        hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(128), 0, st, A);
+    if (list && !split) run_list(st);
+    if (split) {
+        hipError_t e = hipStreamWaitEvent(st, fk->join, 0);
+        if (e != hipSuccess) return e;
     }
     LPB_MARK(5);
     for (int l = 0; l <= kMaxDepth && far; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.n_le, A.le, 1, st);
@@ -830,8 +847,10 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     return hipGetLastError();
 }
 
-template hipError_t eval_run<double>(const EvalArgs<double>&, const EvalSched&, int, hipStream_t, hipEvent_t*);
-template hipError_t eval_run<float>(const EvalArgs<float>&, const EvalSched&, int, hipStream_t, hipEvent_t*);
+template hipError_t eval_run<double>(const EvalArgs<double>&, const EvalSched&, int, hipStream_t, hipEvent_t*,
+                                     const EvalFork*);
+template hipError_t eval_run<float>(const EvalArgs<float>&, const EvalSched&, int, hipStream_t, hipEvent_t*,
+                                    const EvalFork*);
 
 template <typename T>
 hipError_t stage_run(const EvalArgs<T>& A, const EvalSched& S, int which, hipStream_t st)

@@ -181,6 +181,10 @@ __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A, int n_leaves)
         float phi = 0.f;
         solid_harmonics<P>(ux * hinv, uy * hinv, uz * hinv,
                            [&](int n, int m, float re, float im) {
+                               // (a compiler barrier per order m keeps the LDS reads of the
+                               // expansion next to their use: hoisted together they held
+                               // K registers and cut the waves per SIMD from 8 to 3)
+                               if (n == m) asm volatile("" ::: "memory");
                                if (m == 0) phi += g[n] * (L[ire(n, 0)] * re);
                                else phi += 2.f * g[n] * (L[ire(n, m)] * re - L[iim(n, m)] * im);
                            });
