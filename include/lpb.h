@@ -81,9 +81,12 @@ typedef struct {
                                per-stage events need the passes launched one by one); default 1 */
     int autotune;           /* 1 = time the candidate block-to-work schedules of the matrix-core M2L
                                kernels on the first evaluate after a change and keep the fastest
-                               (results do not depend on the choice); default 1 */
+                               (results do not depend on the choice); 2 = also time the per-offset form
+                               of the tiled M2L against the reflection-orbit form (mixed precision,
+                               5 <= p <= 15: the two round differently, so results then depend on the
+                               choice, within the mixed-precision error); default 1 */
     int schedule;           /* with autotune = 0, the schedules to use: tile | batch << 4, with the codes of
-                               lpb_stats.tile_schedule (0..3) and batch_schedule (0..7); default 0 */
+                               lpb_stats.tile_schedule (0..15) and batch_schedule (0..7); default 0 */
     /* Device-memory hook (e.g. a framework's caching allocator).  When alloc is
      * not NULL, every device buffer the context holds (tables, tree, lists,
      * expansions, operators, partial potentials) comes from
@@ -118,10 +121,13 @@ typedef struct {
      * [4] list M2L (reaction, deep levels), [5] L2L, [6] L2P,
      * [7] free-space near field, [8] reaction near field, [9] component sum */
     double t_stage_ms[10];
-    int tile_schedule;      /* schedule chosen for the tiled M2L: bit 0 = 0 linear, 1 blocks of one XCD take a
-                               contiguous run of tiles (tiles sharing operators share that XCD's L2); bit 1 =
-                               blocks of one wave per 16-row block instead of four waves (per-offset form only:
-                               FP64, or mixed precision with p < 5 or p > 15) */
+    int tile_schedule;      /* schedule and form chosen for the tiled M2L: bit 0 = 0 linear, 1 blocks of one
+                               XCD take a contiguous run of tiles (tiles sharing operators share that XCD's
+                               L2); bit 1 = blocks of one wave per 16-row block instead of four waves
+                               (per-offset form); bit 2 = the per-offset form (one product per V-list offset)
+                               where the reflection-orbit form exists (mixed precision, 5 <= p <= 15; FP64
+                               and other orders always use the per-offset form); bit 3 = orbit form with its
+                               operator slabs in registers instead of LDS (p <= 10) */
     int batch_schedule;     /* the choice for the batched translations (M2M, L2L, untiled M2L): bit 0 as
                                above; bits 1-2 = 0 one block per work item, k = 1..3 a grid of 256 x 2^k
                                resident blocks that loop over the items, each gathering the next item's

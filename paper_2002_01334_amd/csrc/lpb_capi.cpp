@@ -755,13 +755,28 @@ lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
 {
     auto t0 = std::chrono::steady_clock::now();
     int* field[2] = {&A.tile_sched, &A.batch_sched};
+    // tiled M2L candidates: order bit 0 with, where the orbit form exists
+    // (mixed precision, kOrbitMinP <= p <= kOrbitMaxP), the orbit form with
+    // operands in LDS (up to p = 10) or in registers (bit 3) -- these give the
+    // same bits -- and, with autotune = 2, also the per-offset form (bit 2)
+    // with one or four waves per row block (bit 1), whose sums round
+    // differently; elsewhere the per-offset form's bits 0-1.  Batched
+    // translations: order bit 0, resident-block grid bits 1-2.
+    std::vector<int> tile_cands;
+    const bool orbit = sizeof(T) == 4 && A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP;
+    if (orbit) {
+        tile_cands = {0, 1};
+        if (class_row_blocks(A.p) <= 9) tile_cands.insert(tile_cands.end(), {8, 9});
+        if (c->opt.autotune == 2) tile_cands.insert(tile_cands.end(), {4, 5, 6, 7});
+    } else {
+        tile_cands = {0, 1, 2, 3};
+    }
     for (int which = 0; which < 2; ++which) {
         float best = 1e30f;
         int pick = 0;
-        // tiled M2L: schedule bit 0, wide-block variant bit 1; batched translations:
-        // order bit 0, resident-block grid bits 1-2
-        const int ncand = which == 0 ? 4 : 8;
-        for (int sc = 0; sc < ncand; ++sc) {
+        const int ncand = which == 0 ? (int)tile_cands.size() : 8;
+        for (int ci = 0; ci < ncand; ++ci) {
+            const int sc = which == 0 ? tile_cands[ci] : ci;
             *field[which] = sc;
             float tmin = 1e30f;
             for (int rep = 0; rep < 3; ++rep) {
@@ -892,7 +907,8 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (!(o.quad_tol > 0.0 && o.quad_tol < 1e-3)) return fail(nullptr, LPB_EINVAL, "quad_tol out of range");
     if (!(o.iface_tol >= 0.0)) return fail(nullptr, LPB_EINVAL, "iface_tol must be >= 0");
     if (!o.alloc != !o.free) return fail(nullptr, LPB_EINVAL, "alloc and free must be set together");
-    if (o.schedule < 0 || (o.schedule & 15) > 3 || (o.schedule >> 4) > 7)
+    if (o.autotune < 0 || o.autotune > 2) return fail(nullptr, LPB_EINVAL, "autotune must be 0, 1 or 2");
+    if (o.schedule < 0 || (o.schedule >> 4) > 7)
         return fail(nullptr, LPB_EINVAL, "schedule codes out of range");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);

@@ -105,8 +105,9 @@ constexpr bool orbit_lds_operands() { return class_row_blocks(P) <= 9; }
 // [15:14])
 constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | (7 << 4) | (0 << 8) | ((n >> 4) << 14); }
 
-template <int P>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(orbit_lds_operands<P>() ? 2 : 1)))
+// LA: operator slabs staged in LDS (orbit_lds_operands<P>() orders only)
+template <int P, bool LA>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LA ? 2 : 1)))
 k_m2l_orbit(EvalArgs<float> A)
 {
     typedef Vec4<float>::type V4;
@@ -115,7 +116,7 @@ k_m2l_orbit(EvalArgs<float> A)
     constexpr int OPSZ = NRB * KB * 256;     // floats of one operator
     constexpr int NIT = kOrbits * KB;        // steps (even: kOrbits is)
     constexpr int NG = kOrbGrid * kOrbGrid * kOrbGrid;
-    constexpr bool LA = orbit_lds_operands<P>();
+    static_assert(!LA || orbit_lds_operands<P>(), "LDS-staged operands up to 9 row blocks");
     constexpr int NLA = (NRB + 3) / 4;       // row blocks each wave stages per step
     constexpr int SLAB = 4 * NLA * 256;      // floats of one staged slab (blocks past NRB unused)
     __shared__ float s_a[LA ? 3 * SLAB : 4]; // ring of three staged slabs
@@ -381,10 +382,17 @@ k_m2l_orbit(EvalArgs<float> A)
 }
 
 
+// (tile schedule bit 3: operands in registers where LDS staging is available)
 template <int P>
 void launch_m2l_orbit_p(const EvalArgs<float>& A, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_m2l_orbit<P>), dim3(A.n_tiles), dim3(256), 0, st, A);
+    if constexpr (orbit_lds_operands<P>()) {
+        if (!((A.tile_sched >> 3) & 1)) {
+            hipLaunchKernelGGL((k_m2l_orbit<P, true>), dim3(A.n_tiles), dim3(256), 0, st, A);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_m2l_orbit<P, false>), dim3(A.n_tiles), dim3(256), 0, st, A);
 }
 
 }  // namespace lpb

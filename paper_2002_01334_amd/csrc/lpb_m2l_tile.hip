@@ -162,8 +162,9 @@ void launch_m2l_tile(const EvalArgs<T>& A, hipStream_t st)
     // variant bit of the schedule: KB waves of one row block each
     const bool wide = (A.tile_sched >> 1) & 1;
     if constexpr (sizeof(T) == 4) {
-        // (row byte offsets of the expansions are 32-bit in the orbit kernel)
-        if (A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP &&
+        // (row byte offsets of the expansions are 32-bit in the orbit kernel;
+        // schedule bit 2 asks for the per-offset form instead)
+        if (A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP && !((A.tile_sched >> 2) & 1) &&
             (size_t)(A.n_me + 1) * A.KP * sizeof(float) < ((size_t)1 << 32)) {
 #define LPB_ORB(PP) \
     case PP: launch_m2l_orbit_p<PP>(A, st); return;

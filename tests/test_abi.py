@@ -65,6 +65,13 @@ def test_create_rejects_bad_options_without_touching_the_gpu(lpb):
     o.alloc = lpb.ALLOC_FN(lambda n, user: None)
     h = ctypes.c_void_p()
     assert L.lpb_create(ctypes.byref(o), ctypes.byref(h)) == lpb.LPB_EINVAL and not h.value
+    # autotune is 0, 1 or 2; batch schedule codes stop at 7
+    for field, val in (("autotune", 3), ("autotune", -1), ("schedule", 8 << 4), ("schedule", -1)):
+        o = lpb.Options()
+        L.lpb_default_options(ctypes.byref(o))
+        setattr(o, field, val)
+        h = ctypes.c_void_p()
+        assert L.lpb_create(ctypes.byref(o), ctypes.byref(h)) == lpb.LPB_EINVAL and not h.value, (field, val)
     assert L.lpb_create(None, None) == lpb.LPB_EINVAL
 
 
