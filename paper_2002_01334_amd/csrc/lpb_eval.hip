@@ -186,7 +186,9 @@ __device__ inline void column_xform(T* Bs, int NTP, int p, int K, int KP, int co
 // resident and gathers the next item's first sources during the current
 // item's last product and write-back).  Items are independent, so results
 // do not depend on the grid or the order.
-template <typename T, int RBF, bool XF, int GY>
+// MT: items of several terms (M2M: one per child octant), summed with Kahan
+// compensation; single-term items (L2L, untiled M2L) store the product as is
+template <typename T, int RBF, bool XF, int GY, bool MT>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
                                                  const int* __restrict__ dst, int wbase, int nitems, int mode, int K,
@@ -229,7 +231,10 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int cb = 0; cb < CB; ++cb) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
+            for (int cb = 0; cb < CB; ++cb) {
+                if constexpr (MT) tot[rb][cb] = cmp[rb][cb] = V4{0, 0, 0, 0};
+                else acc[rb][cb] = V4{0, 0, 0, 0};
+            }
         const int xc = XF ? xcode[(size_t)wi * NT + (tid & 63)] : -1;
         if (XF) column_trig<T>(trig, p, xc, rot);
         if (t0 < t1 && !staged_next) fetch(t0);
@@ -261,7 +266,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
                 }
             }
             mma_block<T, RB, CB>(Aw, Bs, NTP, KB, wy, l, acc);
-            accumulate<T, RB, CB>(acc, tot, cmp);
+            if constexpr (MT) accumulate<T, RB, CB>(acc, tot, cmp);
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
@@ -275,8 +280,9 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
                 for (int r = 0; r < 4; ++r) {
                     int row = rbg * 16 + mfma_row(T(0), l, r);
                     if (row >= K) continue;
-                    if (mode == 0) out[(size_t)d * KP + row] = tot[rb][cb][r];
-                    else out[(size_t)d * KP + row] += tot[rb][cb][r];
+                    const T v = MT ? tot[rb][cb][r] : acc[rb][cb][r];
+                    if (mode == 0) out[(size_t)d * KP + row] = v;
+                    else out[(size_t)d * KP + row] += v;
                 }
             }
         }
@@ -297,17 +303,25 @@ static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, 
     const int pers = (A.batch_sched >> 1) & 3;
     const int gx = pers == 0 ? n : std::min(n, 256 * (1 << pers));
     dim3 g(gx, gy), b(256);
-#define LPB_BATCHED(R)                                                                                                      \
+#define LPB_BATCHED_MT(R, MT)                                                                                               \
     if constexpr (!XF) {                                                                                                    \
         if (gy == 2) {                                                                                                      \
-            hipLaunchKernelGGL((k_batched<T, R, XF, 2>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, \
-                               w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab, A.refl_sign,  \
-                               A.p);                                                                                        \
+            hipLaunchKernelGGL((k_batched<T, R, XF, 2, MT>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src,        \
+                               A.bw_dst, w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab,      \
+                               A.refl_sign, A.p);                                                                           \
             break;                                                                                                          \
         }                                                                                                                   \
     }                                                                                                                       \
-    hipLaunchKernelGGL((k_batched<T, R, XF, 1>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst, w0, n, \
-                       mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab, A.refl_sign, A.p)
+    hipLaunchKernelGGL((k_batched<T, R, XF, 1, MT>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst,     \
+                       w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab, A.refl_sign, A.p)
+    // M2M items sum eight terms (mode 0 without a transform); L2L and untiled
+    // M2L items have one
+#define LPB_BATCHED(R)                \
+    if (!XF && mode == 0) {           \
+        LPB_BATCHED_MT(R, true);      \
+    } else {                          \
+        LPB_BATCHED_MT(R, false);     \
+    }
     switch (RB) {
     case 1: LPB_BATCHED(1); break;
     case 2: LPB_BATCHED(2); break;
@@ -318,6 +332,7 @@ static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, 
     default: LPB_BATCHED(7); break;
     }
 #undef LPB_BATCHED
+#undef LPB_BATCHED_MT
 }
 template <typename T>
 static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, int zrow, T* out, int mode, hipStream_t st)
