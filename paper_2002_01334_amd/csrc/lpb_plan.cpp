@@ -102,8 +102,11 @@ struct Staging {
     std::vector<std::vector<BWork>> bm2m{(size_t)kMaxDepth + 1}, bl2l{(size_t)kMaxDepth + 1};
     struct M2LPair { int le, src, op, xc; };
     std::vector<M2LPair> m2l_pairs;                             // untiled V-list pairs in list order (grouped by LE box at the end)
-    std::vector<std::vector<int>> p2p_by_tl;                    // per target leaf: free-space source leaves
-    std::vector<std::vector<std::pair<int, int>>> rp_by_tl;     // per target leaf: (reaction FMM, source leaf)
+    // U-list entries in the order they are found: (target leaf, source leaf)
+    // for free space, (target leaf, reaction FMM, source leaf) for reactions;
+    // grouped by target leaf (stable) at the end
+    std::vector<std::array<int, 2>> p2p_pairs;
+    std::vector<std::array<int, 3>> rp_pairs;
 };
 
 // A point set after the builder's sort: its handle, size and leaves.
@@ -194,7 +197,6 @@ void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool targe
     td.leaf0 = T.leaf0;
     td.nleaf = T.nleaf;
     P.trees.push_back(td);
-    if (target) S.p2p_by_tl.resize(P.tl_le.size()), S.rp_by_tl.resize(P.tl_le.size());
     // translation operators (b = child centre - parent centre) and their lists
     int lo = target ? 3 : 2, hi = target ? H : H - 1;
     for (int lv = lo; lv <= hi; ++lv) {
@@ -482,9 +484,9 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                     int sl = ST.leaf0 + sbox;
                     int64_t pairs = (int64_t)nt * (P.sl_start[sl + 1] - P.sl_start[sl]);
                     P.n_p2p_pairs += pairs;
-                    if (F.kind == 0) S.p2p_by_tl[tl].push_back(sl);
+                    if (F.kind == 0) S.p2p_pairs.push_back({tl, sl});
                     else {
-                        S.rp_by_tl[tl].push_back({fid, sl});
+                        S.rp_pairs.push_back({tl, fid, sl});
                         P.n_react_p2p_pairs += pairs;
                     }
         }
@@ -888,18 +890,27 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.swz_ops.resize(P.ops.size());
     P.swz_index.resize(P.ops.size());
     for (size_t i = 0; i < P.ops.size(); ++i) P.swz_ops[i] = P.swz_index[i] = (int)i;
-    P.p2p_ptr.assign(1, 0); P.p2p_src.clear();
-    P.rp_ptr.assign(1, 0); P.rp_fmm.clear(); P.rp_src.clear();
-    S.p2p_by_tl.resize(P.tl_le.size());
-    S.rp_by_tl.resize(P.tl_le.size());
-    for (size_t t = 0; t < P.tl_le.size(); ++t) {
-        for (int sl : S.p2p_by_tl[t]) P.p2p_src.push_back(sl);
-        P.p2p_ptr.push_back((int)P.p2p_src.size());
-        for (auto& e : S.rp_by_tl[t]) {
-            P.rp_fmm.push_back(e.first);
-            P.rp_src.push_back(e.second);
+    // U-lists: CSR by target leaf, each leaf's entries in the order found (a
+    // stable counting sort)
+    {
+        const size_t nt = P.tl_le.size();
+        P.p2p_ptr.assign(nt + 1, 0);
+        for (const auto& e : S.p2p_pairs) P.p2p_ptr[e[0] + 1]++;
+        for (size_t t = 0; t < nt; ++t) P.p2p_ptr[t + 1] += P.p2p_ptr[t];
+        P.p2p_src.resize(S.p2p_pairs.size());
+        std::vector<int> fill(P.p2p_ptr.begin(), P.p2p_ptr.end() - 1);
+        for (const auto& e : S.p2p_pairs) P.p2p_src[fill[e[0]]++] = e[1];
+        P.rp_ptr.assign(nt + 1, 0);
+        for (const auto& e : S.rp_pairs) P.rp_ptr[e[0] + 1]++;
+        for (size_t t = 0; t < nt; ++t) P.rp_ptr[t + 1] += P.rp_ptr[t];
+        P.rp_fmm.resize(S.rp_pairs.size());
+        P.rp_src.resize(S.rp_pairs.size());
+        fill.assign(P.rp_ptr.begin(), P.rp_ptr.end() - 1);
+        for (const auto& e : S.rp_pairs) {
+            const int k = fill[e[0]]++;
+            P.rp_fmm[k] = e[1];
+            P.rp_src[k] = e[2];
         }
-        P.rp_ptr.push_back((int)P.rp_src.size());
     }
     return "";
 }
