@@ -563,7 +563,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
     A.n_me = P.n_me;
     T* scr = nullptr;
     if (!P.m2l_src.empty())
-        if ((s = dalloc<T>(c, c->plan_bufs, P.m2l_src.size() * (size_t)A.KP, &scr)) != LPB_OK) return s;
+        if ((s = dalloc<T>(c, c->plan_bufs, P.m2l_src.size() * (size_t)A.K, &scr)) != LPB_OK) return s;
     A.m2l_scratch = scr;
     double* parts;
     if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.nslots * P.ncharges, &parts)) != LPB_OK) return s;

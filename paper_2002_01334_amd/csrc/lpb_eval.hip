@@ -281,8 +281,10 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
                     int row = rbg * 16 + mfma_row(T(0), l, r);
                     if (row >= K) continue;
                     const T v = MT ? tot[rb][cb][r] : acc[rb][cb][r];
-                    if (mode == 0) out[(size_t)d * KP + row] = v;
-                    else out[(size_t)d * KP + row] += v;
+                    // (the untiled M2L's scratch rows are K long, the expansions KP)
+                    const size_t o = (size_t)d * (XF ? K : KP) + row;
+                    if (mode == 0) out[o] = v;
+                    else out[o] += v;
                 }
             }
         }
@@ -384,14 +386,14 @@ __global__ void k_m2l_reduce(EvalArgs<T> A)
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 code[u] = A.m2l_xc[k + u];
-                own[u] = A.m2l_scratch[(size_t)(k + u) * A.KP + row];
-                other[u] = A.m2l_scratch[(size_t)(k + u) * A.KP + partner];
+                own[u] = A.m2l_scratch[(size_t)(k + u) * A.K + row];
+                other[u] = A.m2l_scratch[(size_t)(k + u) * A.K + partner];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) add(term(code[u], own[u], other[u]));
         }
         for (; k < k1; ++k)
-            add(term(A.m2l_xc[k], A.m2l_scratch[(size_t)k * A.KP + row], A.m2l_scratch[(size_t)k * A.KP + partner]));
+            add(term(A.m2l_xc[k], A.m2l_scratch[(size_t)k * A.K + row], A.m2l_scratch[(size_t)k * A.K + partner]));
         A.le[(size_t)le * A.KP + row] += s;
     }
 }

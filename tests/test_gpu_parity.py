@@ -464,9 +464,10 @@ def test_every_schedule_gives_the_same_bits(lpb, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
     """Captured evaluation (graph = 1, autotuned schedules) against eager
-    launches with the linear schedules: several replays with different
-    charges, eager work of another context and host synchronisations in
-    between, and a re-capture after a new tree; every result bit-identical."""
+    launches with the linear schedules (with and without the side stream of
+    the untiled M2L): several replays with different charges, eager work of
+    another context and host synchronisations in between, and a re-capture
+    after a new tree; every result bit-identical."""
     import torch
 
     prob = inputs.three_layer(10_000, seed=0)
@@ -474,7 +475,10 @@ def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
     t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device=dev) for k in "xyzq"}
     g = lpb.Context(p=10, leaf_cap=50, precision=precision, graph=1, autotune=1)
     e = lpb.Context(p=10, leaf_cap=50, precision=precision, graph=0, autotune=0)
-    for c in (g, e):
+    # per-stage events: every pass on one stream (no side stream for the
+    # untiled M2L)
+    s = lpb.Context(p=10, leaf_cap=50, precision=precision, graph=0, autotune=0, timing=1)
+    for c in (g, e, s):
         c.set_layers(prob.eps, prob.lam, prob.d)
         c.build_tree(t["x"], t["y"], t["z"])
     qs = [t["q"], 2.0 * t["q"], torch.flip(t["q"], [0]).contiguous(), t["q"] * t["q"]]
@@ -484,6 +488,9 @@ def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
             b = e.evaluate(q).cpu().numpy()
             torch.cuda.synchronize()
             assert np.array_equal(a, b), rep
+            if rep == 0:
+                assert np.array_equal(s.evaluate(q).cpu().numpy(), b)
+    s.close()
     st = g.stats()
     assert st["tile_schedule"] in (0, 1, 2, 3, 8, 9) and st["batch_schedule"] in range(8)
     # a new tree invalidates the captured passes
