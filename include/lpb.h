@@ -127,7 +127,7 @@ typedef struct {
                                (per-offset form); bit 2 = the per-offset form (one product per V-list offset)
                                where the reflection-orbit form exists (mixed precision, 5 <= p <= 15; FP64
                                and other orders always use the per-offset form); bit 3 = orbit form with its
-                               operator slabs in registers instead of LDS (p <= 10) */
+                               operator slabs in registers instead of LDS */
     int batch_schedule;     /* the choice for the batched translations (M2M, L2L, untiled M2L): bit 0 as
                                above; bits 1-2 = 0 one block per work item, k = 1..3 a grid of 256 x 2^k
                                resident blocks that loop over the items, each gathering the next item's

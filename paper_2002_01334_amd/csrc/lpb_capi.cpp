@@ -757,7 +757,7 @@ lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
     int* field[2] = {&A.tile_sched, &A.batch_sched};
     // tiled M2L candidates: order bit 0 with, where the orbit form exists
     // (mixed precision, kOrbitMinP <= p <= kOrbitMaxP), the orbit form with
-    // operands in LDS (up to p = 10) or in registers (bit 3) -- these give the
+    // operands in LDS or in registers (bit 3) -- these give the
     // same bits -- and, with autotune = 2, also the per-offset form (bit 2)
     // with one or four waves per row block (bit 1), whose sums round
     // differently; elsewhere the per-offset form's bits 0-1.  Batched
@@ -765,8 +765,7 @@ lpb_status autotune(lpb_ctx* c, EvalArgs<T>& A)
     std::vector<int> tile_cands;
     const bool orbit = sizeof(T) == 4 && A.pool_orb && A.p >= kOrbitMinP && A.p <= kOrbitMaxP;
     if (orbit) {
-        tile_cands = {0, 1};
-        if (class_row_blocks(A.p) <= 9) tile_cands.insert(tile_cands.end(), {8, 9});
+        tile_cands = {0, 1, 8, 9};
         if (c->opt.autotune == 2) tile_cands.insert(tile_cands.end(), {4, 5, 6, 7});
     } else {
         tile_cands = {0, 1, 2, 3};

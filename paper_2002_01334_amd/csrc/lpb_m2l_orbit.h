@@ -33,9 +33,9 @@ namespace lpb {
 // transforms in registers and issues the products; loads run two steps
 // ahead.  The orbits come in groups of one both-axes mask (kOrbGroupMask), so
 // each gather loads exactly the members its orbit has.  The operator slab of
-// a step is the same for the four waves: up to p = 10 it is copied once per
-// block into a ring of three LDS slots (buffer loads straight to LDS, a
-// barrier per step) and the kernel runs two blocks per CU; above, each wave
+// a step is the same for the four waves: it is copied once per block into a
+// ring of three LDS slots (buffer loads straight to LDS, a barrier per step;
+// up to p = 10 two blocks per CU), or, as a tuned alternative, each wave
 // gathers it into registers.  Each orbit's products go to the result with
 // Kahan compensation.
 template <int P, int MASK>
@@ -91,11 +91,12 @@ __device__ __forceinline__ void orbit_step(const Vec4<float>::type (&xs)[8], con
         for (int rb = 0; rb < NRB; ++rb) acc[rb] = mfma16(ra[rb][ss], y[ext(class_of_row_block(P, rb))][ss], acc[rb]);
 }
 
-// Orders whose operand slab (NRB row blocks of 1 KiB per step) is staged in
-// LDS and shared by the four waves of a block, two blocks per CU: the slab
-// is read from L2 once per block instead of once per wave, and the second
-// block's waves keep the matrix cores busy while the first block's waves wait
-// at the per-step barrier.  Larger orders keep the operands in registers.
+// The operand slab of a step (NRB row blocks of 1 KiB) is staged in LDS and
+// shared by the four waves of a block: the slab is read from L2 once per
+// block instead of once per wave, and its registers are free.  Up to 9 row
+// blocks (p <= 10) two blocks share a CU, so the second block's waves keep the
+// matrix cores busy while the first block's waves wait at the per-step
+// barrier; above, one block per CU (the accumulators take the registers).
 template <int P>
 constexpr bool orbit_lds_operands() { return class_row_blocks(P) <= 9; }
 
@@ -105,9 +106,9 @@ constexpr bool orbit_lds_operands() { return class_row_blocks(P) <= 9; }
 // [15:14])
 constexpr int waitcnt_vm_lgkm0(int n) { return (n & 15) | (7 << 4) | (0 << 8) | ((n >> 4) << 14); }
 
-// LA: operator slabs staged in LDS (orbit_lds_operands<P>() orders only)
+// LA: operator slabs staged in LDS
 template <int P, bool LA>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LA ? 2 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(LA && orbit_lds_operands<P>() ? 2 : 1)))
 k_m2l_orbit(EvalArgs<float> A)
 {
     typedef Vec4<float>::type V4;
@@ -116,7 +117,6 @@ k_m2l_orbit(EvalArgs<float> A)
     constexpr int OPSZ = NRB * KB * 256;     // floats of one operator
     constexpr int NIT = kOrbits * KB;        // steps (even: kOrbits is)
     constexpr int NG = kOrbGrid * kOrbGrid * kOrbGrid;
-    static_assert(!LA || orbit_lds_operands<P>(), "LDS-staged operands up to 9 row blocks");
     constexpr int NLA = (NRB + 3) / 4;       // row blocks each wave stages per step
     constexpr int SLAB = 4 * NLA * 256;      // floats of one staged slab (blocks past NRB unused)
     __shared__ float s_a[LA ? 3 * SLAB : 4]; // ring of three staged slabs
@@ -382,17 +382,12 @@ k_m2l_orbit(EvalArgs<float> A)
 }
 
 
-// (tile schedule bit 3: operands in registers where LDS staging is available)
+// (tile schedule bit 3: operands gathered into registers instead of LDS)
 template <int P>
 void launch_m2l_orbit_p(const EvalArgs<float>& A, hipStream_t st)
 {
-    if constexpr (orbit_lds_operands<P>()) {
-        if (!((A.tile_sched >> 3) & 1)) {
-            hipLaunchKernelGGL((k_m2l_orbit<P, true>), dim3(A.n_tiles), dim3(256), 0, st, A);
-            return;
-        }
-    }
-    hipLaunchKernelGGL((k_m2l_orbit<P, false>), dim3(A.n_tiles), dim3(256), 0, st, A);
+    if ((A.tile_sched >> 3) & 1) hipLaunchKernelGGL((k_m2l_orbit<P, false>), dim3(A.n_tiles), dim3(256), 0, st, A);
+    else hipLaunchKernelGGL((k_m2l_orbit<P, true>), dim3(A.n_tiles), dim3(256), 0, st, A);
 }
 
 }  // namespace lpb
