@@ -68,6 +68,10 @@ def lib():
                                            _I, _I, _I, _I, _PD]),
             "orc_reaction_I_both": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D, _PD, _PD, _PD, _PD]),
             "orc_sommerfeld_table": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _D, _D, _D, _D, _I, _I, _PD]),
+            "orc_free_point_chain": (_D, [_I, _D, _PD, _PD, _PD, _I]),
+            "orc_reaction_point_chain": (_D, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _PD, _PD, _PD, _D, _I]),
+            "orc_reaction_I_point": (None, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D,
+                                            _I, _I, _I, _I, _PD]),
             "orc_legendre_product": (None, [_I, _I, _I, _I, _D, _D, _D, _PD]),
             "orc_plm_beyond": (None, [_I, _I, _D, _PD]),
             "orc_component_tree": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _I, _I, _PI, _PL, _PL,
@@ -260,6 +264,27 @@ def reaction_I_pair(ly: Layers, l, lp, a, b, p, rho, zt, zs, S, n, m, nu, mu):
     out = np.zeros(4)
     lib().orc_reaction_I_pair(_p(ly.eps), _p(ly.lam), _p(ly.d), ly.L, l, lp, a, b, p, float(rho), float(zt),
                               float(zs), float(S), n, m, nu, mu, _p(out))
+    return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def free_point_chain(p, lam, rs, c, r, mode):
+    """mode 0: ME of a unit source rs about c evaluated at r (M2P); mode 1: LE
+    about c formed from rs (P2L) evaluated at r."""
+    return lib().orc_free_point_chain(p, float(lam), _p(_f64(rs)), _p(_f64(c)), _p(_f64(r)), mode)
+
+
+def reaction_point_chain(ly: Layers, l, lp, a, b, p, rs, c, r, S, mode):
+    """Reaction component of a unit source rs: mode 0 = ME about the image-side
+    centre c evaluated at r (M2P); mode 1 = LE about the target-side centre c
+    formed from the image (P2L), evaluated at r."""
+    return lib().orc_reaction_point_chain(_p(ly.eps), _p(ly.lam), _p(ly.d), ly.L, l, lp, a, b, p, _p(_f64(rs)),
+                                          _p(_f64(c)), _p(_f64(r)), float(S), mode)
+
+
+def reaction_I_point(ly: Layers, l, lp, a, b, p, rho, zt, zs, S, n, m, nu, mu):
+    out = np.zeros(4)
+    lib().orc_reaction_I_point(_p(ly.eps), _p(ly.lam), _p(ly.d), ly.L, l, lp, a, b, p, float(rho), float(zt),
+                               float(zs), float(S), n, m, nu, mu, _p(out))
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
 
 

@@ -999,6 +999,173 @@ static cplx reaction_I_direct_one(const rcomp_t* C, int n, int m, int nu, int mu
 }
 
 /* ------------------------------------------------------------------------ */
+/* Point forms of the expansions, used by adaptive trees (Sec. 3.5, closing */
+/* remarks on adaptive trees): a multipole expansion evaluated at a target  */
+/* directly (M2P, W-list) and a local expansion formed from a source        */
+/* directly (P2L, X-list).                                                  */
+/* ------------------------------------------------------------------------ */
+
+/* free space, eq. freespace3dmulexp: sum_nm M_nm k_n(lam r_s) Y_n^m(r - c) */
+static double m2p_free_one(int p, double lam, const cplx* M, double dx, double dy, double dz)
+{
+    int K = (p + 1) * (p + 1);
+    cplx* Y = (cplx*)malloc(sizeof(cplx) * K);
+    ylm_c(p, dx, dy, dz, Y);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    cplx s = 0.0;
+    for (int n = 0; n <= p; ++n) {
+        double kn = orc_bessel_k(n, lam * r);
+        for (int m = -n; m <= n; ++m) s += M[idx_nm(n, m)] * kn * Y[idx_nm(n, m)];
+    }
+    free(Y);
+    return creal(s);
+}
+
+/* free space, eq. melecoeffree with the conjugate reading of Y_n^{-m}:
+ * L_nm += q 4 pi k_n(lam r'_t) conj(Y_n^m(r' - c)) */
+static void p2l_free_one(int p, double lam, double q, double dx, double dy, double dz, cplx* L)
+{
+    int K = (p + 1) * (p + 1);
+    cplx* Y = (cplx*)malloc(sizeof(cplx) * K);
+    ylm_c(p, dx, dy, dz, Y);
+    double r = sqrt(dx * dx + dy * dy + dz * dz);
+    for (int n = 0; n <= p; ++n) {
+        double kn = orc_bessel_k(n, lam * r);
+        for (int m = -n; m <= n; ++m) L[idx_nm(n, m)] += q * 4.0 * ORC_PI * kn * conj(Y[idx_nm(n, m)]);
+    }
+    free(Y);
+}
+
+/* Scaled Sommerfeld table S^n Sc_{nm,ij}(rho, zt, zs), 0 <= m <= n <= nmax, of
+ * a point and a box centre (layout as sommerfeld_table).  Here rho can take
+ * any value from 0 up, also below the box side S, so each entry is reached
+ * by the recurrence that is stable for it:
+ *   - initial values by quadrature: m = 0 (n = 0..nmax), m = 1 (n = 1..nmax)
+ *     and the whole row n = nmax;
+ *   - the forward recurrence (eq. recurrence1) for S^n Sc_{n,m+1} wherever
+ *     its bound 2m/a_{n+m} < rho/S holds, in increasing m;
+ *   - the backward recurrence (eq. backwardrecurrence1)
+ *       S^{n-1} Sc_{n-1,m} = (a_{n+m}/(2m)) (rho/S) S^n Sc_{n,m+1}
+ *                          + (a_{n-m}/(2m)) (rho/S) S^n Sc_{n,m-1}
+ *     for every other entry, row by row down from n = nmax.
+ * rho = 0: Sc_{n,m>0} = 0. */
+static void sommerfeld_table_pt(const rcomp_t* C, double rho, double zt, double zs, double S, int nmax, double* tab)
+{
+    const layers_t* Ly = &C->Ly;
+    int N1 = nmax + 1;
+    double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
+    memset(tab, 0, sizeof(double) * 4 * N1 * N1);
+    char* done = (char*)calloc((size_t)N1 * N1, 1);
+    nodes_t nd;
+    build_nodes(&nd, rho, zsep(C, zt, zs), nmax, layers_lam_min(Ly), layers_dmax(Ly), ORC_TOL);
+    for (int k = 0; k < nd.n; ++k) {
+        double t = nd.x[k];
+        double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+        double base = nd.w[k] * zkern(C, lz, lzp, zt, zs) * sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz;
+        double j0 = jn(0, t * rho), j1 = jn(1, t * rho);
+        double pwN = pow(t * S, nmax);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 2; ++j) {
+                double f = base * (i ? lt / lz : 1.0) * (j ? ls / lzp : 1.0);
+                double* T = tab + (size_t)(i * 2 + j) * N1 * N1;
+                double pw = 1.0; /* (t S)^n */
+                for (int n = 0; n <= nmax; ++n) {
+                    T[n * N1 + 0] += f * pw * j0 / fact(n);
+                    if (n >= 1) T[n * N1 + 1] += f * pw * j1 / sqrt(fact(n + 1) * fact(n - 1));
+                    pw *= t * S;
+                }
+                if (rho > 0.0)
+                    for (int m = 2; m <= nmax; ++m)
+                        T[nmax * N1 + m] += f * pwN * jn(m, t * rho) / sqrt(fact(nmax + m) * fact(nmax - m));
+            }
+    }
+    free_nodes(&nd);
+    for (int n = 0; n <= nmax; ++n) {
+        done[n * N1 + 0] = 1;
+        if (n >= 1) done[n * N1 + 1] = 1;
+    }
+    if (rho == 0.0) {
+        free(done);
+        return; /* the m >= 1 entries stay 0 (J_m(0) = 0) */
+    }
+    for (int m = 0; m <= nmax; ++m) done[nmax * N1 + m] = 1;
+    double x = rho / S;
+    /* forward, increasing m */
+    for (int m = 1; m < nmax; ++m)
+        for (int n = m + 1; n < nmax; ++n) {
+            if (!(2.0 * m / a_n(n + m) < x)) continue;
+            if (!done[(n - 1) * N1 + m] || !done[n * N1 + m - 1]) continue;
+            for (int ij = 0; ij < 4; ++ij) {
+                double* T = tab + (size_t)ij * N1 * N1;
+                T[n * N1 + m + 1] =
+                    2.0 * m / a_n(n + m) / x * T[(n - 1) * N1 + m] - a_n(n - m) / a_n(n + m) * T[n * N1 + m - 1];
+            }
+            done[n * N1 + m + 1] = 1;
+        }
+    /* backward, down from the row nmax */
+    for (int n = nmax; n >= 2; --n)
+        for (int m = 1; m <= n - 1; ++m) {
+            if (done[(n - 1) * N1 + m]) continue;
+            for (int ij = 0; ij < 4; ++ij) {
+                double* T = tab + (size_t)ij * N1 * N1;
+                T[(n - 1) * N1 + m] = a_n(n + m) / (2.0 * m) * x * T[n * N1 + m + 1] +
+                                      a_n(n - m) / (2.0 * m) * x * T[n * N1 + m - 1];
+            }
+            done[(n - 1) * N1 + m] = 1;
+        }
+    free(done);
+}
+
+/* Reaction ME evaluated at a target r (eq. melayerupgoingimage with the F~
+ * rows of eq. coefintable):
+ *   u~(r) = sum_{nu mu} M_{nu mu} F~_{nu mu}(r, c),
+ *   F~^{1b}_{nu mu} = e^{i mu phi} I^{1b}_{00,nu mu}(rho, z, z_c) / sqrt(4 pi),
+ *   F~^{2b}_{nu mu} = (-1)^{nu+mu} e^{i mu phi} I^{2b}_{00,nu mu}(rho, z, z_c) / sqrt(4 pi),
+ * (rho, phi) the polar coordinates of (x - c_x, y - c_y).  I_{00,nu mu} needs
+ * the table up to n = p + 2; S is the source box side. */
+static double m2p_react_one(const rcomp_t* C, const ctab_t* CT, int p, const cplx* M, double x, double y, double z,
+                            const double* c, double S)
+{
+    int nmax = p + 2;
+    double* tab = (double*)malloc(sizeof(double) * 4 * (nmax + 1) * (nmax + 1));
+    double rho = hypot(x - c[0], y - c[1]);
+    double phi = rho > 0.0 ? atan2(y - c[1], x - c[0]) : 0.0;
+    sommerfeld_table_pt(C, rho, z, c[2], S, nmax, tab);
+    cplx s = 0.0;
+    for (int nu = 0; nu <= p; ++nu)
+        for (int mu = -nu; mu <= nu; ++mu) {
+            double sg = (C->a == 1) ? 1.0 : sgn_pow(nu + iabs(mu));
+            s += sg * cexp(I * mu * phi) * assemble_I(CT, tab, nmax, S, 0, 0, nu, mu) * M[idx_nm(nu, mu)];
+        }
+    free(tab);
+    return creal(s) / sqrt(4.0 * ORC_PI);
+}
+
+/* Reaction LE about a target centre c from one image source at (x, y, z)
+ * with charge q (the L rows of eq. coefintable):
+ *   L^{1b}_nm += q (-1)^n sqrt(4 pi) e^{-i m phi} I^{1b}_{nm,00}(rho, z_c, z'),
+ *   L^{2b}_nm += q (-1)^m sqrt(4 pi) e^{-i m phi} I^{2b}_{nm,00}(rho, z_c, z'),
+ * (rho, phi) the polar coordinates of (c_x - x, c_y - y).  The 2b line is
+ * printed with the heights in the other order; every I takes the target-side
+ * height first, as in its definition and in the T rows. */
+static void p2l_react_one(const rcomp_t* C, const ctab_t* CT, int p, double q, double x, double y, double z,
+                          const double* c, double S, cplx* L)
+{
+    int nmax = p + 2;
+    double* tab = (double*)malloc(sizeof(double) * 4 * (nmax + 1) * (nmax + 1));
+    double rho = hypot(c[0] - x, c[1] - y);
+    double phi = rho > 0.0 ? atan2(c[1] - y, c[0] - x) : 0.0;
+    sommerfeld_table_pt(C, rho, c[2], z, S, nmax, tab);
+    for (int n = 0; n <= p; ++n)
+        for (int m = -n; m <= n; ++m) {
+            double sg = (C->a == 1) ? sgn_pow(n) : sgn_pow(iabs(m));
+            L[idx_nm(n, m)] +=
+                q * sg * sqrt(4.0 * ORC_PI) * cexp(-I * m * phi) * assemble_I(CT, tab, nmax, S, n, m, 0, 0);
+        }
+    free(tab);
+}
+
+/* ------------------------------------------------------------------------ */
 /* Tree (shared definition with the GPU library, written separately):      */
 /*  root cube (cx,cy,cz) +- R; fine cell of a point                         */
 /*    t = ((x - cx) + R) / (2R),  ix = clamp(floor(t * 2^16), 0, 2^16-1),   */
@@ -2012,7 +2179,8 @@ int orc_reaction_I_both(const double* eps, const double* lam, const double* d, i
 
 /* Raw scaled Sommerfeld table (for the recurrence pins):
  * out[((i*2+j)*(nmax+1)+n)*(nmax+1)+m] = S^n Sc_{nm,ij}; mode 0 = recurrence
- * path, mode 1 = every entry by direct quadrature of eq. M2Ltable. */
+ * path of the M2L operators, mode 1 = every entry by direct quadrature of
+ * eq. M2Ltable, mode 2 = the point table (forward and backward recurrences). */
 int orc_sommerfeld_table(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
                          double rho, double zt, double zs, double S, int nmax, int mode, double* out)
 {
@@ -2023,6 +2191,10 @@ int orc_sommerfeld_table(const double* eps, const double* lam, const double* d, 
     C.a = a;
     C.b = b;
     if (mode == 0) return sommerfeld_table(&C, rho, zt, zs, S, nmax, out);
+    if (mode == 2) {
+        sommerfeld_table_pt(&C, rho, zt, zs, S, nmax, out);
+        return 0;
+    }
     const layers_t* Ly = &C.Ly;
     int N1 = nmax + 1;
     double lt = Ly->lam[l], ls = Ly->lam[lp];
@@ -2170,4 +2342,85 @@ int orc_component_tree(int nlayers, const double* eps, const double* lam, const 
     free(Cs.cx);
     free(Ct.cx);
     return 0;
+}
+
+/* Point-form pins.  Free space: mode 0 forms the ME of a unit source rs about
+ * c and evaluates it at r (M2P); mode 1 forms the LE about c from rs (P2L)
+ * and evaluates it at r.  Returns the expansion value of k_0(lam |r - rs|). */
+double orc_free_point_chain(int p, double lam, const double* rs, const double* c, const double* r, int mode)
+{
+    int K = (p + 1) * (p + 1);
+    cplx* E = (cplx*)calloc(K, sizeof(cplx));
+    double v;
+    if (mode == 0) {
+        p2m_one(p, lam, 1.0, rs[0] - c[0], rs[1] - c[1], rs[2] - c[2], E);
+        v = m2p_free_one(p, lam, E, r[0] - c[0], r[1] - c[1], r[2] - c[2]);
+    } else {
+        p2l_free_one(p, lam, 1.0, rs[0] - c[0], rs[1] - c[1], rs[2] - c[2], E);
+        v = l2p_one(p, lam, E, r[0] - c[0], r[1] - c[1], r[2] - c[2]);
+    }
+    free(E);
+    return v;
+}
+
+/* Reaction component, single source rs (original coordinates; its image is
+ * formed here): mode 0 = ME about the image-side centre c evaluated at r
+ * (M2P); mode 1 = LE about the target-side centre c formed from the image
+ * (P2L), evaluated at r.  S is the box side that scales the table.  Returns
+ * the expansion value of u~^{ab}_{l lp}(r, r'). */
+double orc_reaction_point_chain(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a,
+                                int b, int p, const double* rs, const double* c, const double* r, double S, int mode)
+{
+    rcomp_t C;
+    fill_layers(&C.Ly, L + 1, eps, lam, d);
+    C.l = l;
+    C.lp = lp;
+    C.a = a;
+    C.b = b;
+    if (L < 1 || L > ORC_MAXL || !comp_valid(&C.Ly, l, lp, a, b)) return NAN;
+    int K = (p + 1) * (p + 1);
+    double ts = tau_s(&C.Ly, lp, b, rs[2]);
+    double zimg = (a == 1) ? C.Ly.d[l] - ts : C.Ly.d[l - 1] + ts;
+    ctab_t CT;
+    ctab_init(&CT, p, lam[l], lam[lp]);
+    cplx* E = (cplx*)calloc(K, sizeof(cplx));
+    double v;
+    if (mode == 0) {
+        p2m_one(p, lam[lp], 1.0, rs[0] - c[0], rs[1] - c[1], zimg - c[2], E);
+        v = m2p_react_one(&C, &CT, p, E, r[0], r[1], r[2], c, S);
+    } else {
+        p2l_react_one(&C, &CT, p, 1.0, rs[0], rs[1], zimg, c, S, E);
+        v = l2p_one(p, lam[l], E, r[0] - c[0], r[1] - c[1], r[2] - c[2]);
+    }
+    free(E);
+    free(CT.v);
+    return v;
+}
+
+/* Point-table pin: I_{nm,nu mu} at (rho, zt, zs) assembled from the point
+ * table (forward and backward recurrences, table up to n = p + 2, so (n, m)
+ * or (nu, mu) must be (0, 0)) and by direct quadrature with Q = P^ P^.
+ * out = [re_tab, im_tab, re_dir, im_dir]. */
+void orc_reaction_I_point(const double* eps, const double* lam, const double* d, int L, int l, int lp, int a, int b,
+                          int p, double rho, double zt, double zs, double S, int n, int m, int nu, int mu, double* out)
+{
+    rcomp_t C;
+    fill_layers(&C.Ly, L + 1, eps, lam, d);
+    C.l = l;
+    C.lp = lp;
+    C.a = a;
+    C.b = b;
+    int nmax = p + 2;
+    double* tab = (double*)malloc(sizeof(double) * 4 * (nmax + 1) * (nmax + 1));
+    sommerfeld_table_pt(&C, rho, zt, zs, S, nmax, tab);
+    ctab_t CT;
+    ctab_init(&CT, p, lam[l], lam[lp]);
+    cplx v = assemble_I(&CT, tab, nmax, S, n, m, nu, mu);
+    cplx w = reaction_I_direct_one(&C, n, m, nu, mu, rho, zt, zs, NULL);
+    out[0] = creal(v);
+    out[1] = cimag(v);
+    out[2] = creal(w);
+    out[3] = cimag(w);
+    free(tab);
+    free(CT.v);
 }
