@@ -28,6 +28,8 @@ _I = ctypes.c_int
 _L = ctypes.c_int64
 _PD = ctypes.POINTER(ctypes.c_double)
 _PI = ctypes.POINTER(ctypes.c_int)
+_PU32 = ctypes.POINTER(ctypes.c_uint32)
+_PLL = ctypes.POINTER(ctypes.c_longlong)
 _PL = ctypes.POINTER(ctypes.c_int64)
 _PU = ctypes.POINTER(ctypes.c_uint64)
 
@@ -58,7 +60,7 @@ def lib():
             "orc_sigma_stack": (_D, [_I, _PD, _PD, _PD, _I, _I, _I, _I, _D]),
             "orc_reaction_u": (_D, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _D, _D, _D, _D, _D, _D]),
             "orc_direct_sum": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _PD, _L, _PL, _PD, _I]),
-            "orc_fmm": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _PD, _I, _I, _I, _PD, _PD, _PD]),
+            "orc_fmm": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _PD, _I, _I, _I, _I, _PD, _PD, _PD]),
             "orc_num_components": (_I, [_I]),
             "orc_component": (_I, [_I, _I, _PI]),
             "orc_free_chain": (_D, [_I, _D, _PD, _PD, _PD, _PD, _PD, _PD, _I]),
@@ -69,13 +71,14 @@ def lib():
             "orc_reaction_I_both": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D, _PD, _PD, _PD, _PD]),
             "orc_sommerfeld_table": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _D, _D, _D, _D, _I, _I, _PD]),
             "orc_free_point_chain": (_D, [_I, _D, _PD, _PD, _PD, _I]),
+            "orc_list_coverage": (_I, [_I, _PU32, _I, _PU32, _I, _I, _I, _PI, _PLL]),
             "orc_reaction_point_chain": (_D, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _PD, _PD, _PD, _D, _I]),
             "orc_reaction_I_point": (None, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D,
                                             _I, _I, _I, _I, _PD]),
             "orc_legendre_product": (None, [_I, _I, _I, _I, _D, _D, _D, _PD]),
             "orc_plm_beyond": (None, [_I, _I, _D, _PD]),
-            "orc_component_tree": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _I, _I, _PI, _PL, _PL,
-                                        _PU, _PU, _PD]),
+            "orc_component_tree": (_I, [_I, _PD, _PD, _PD, _L, _PD, _PD, _PD, _I, _I, _I, _PI, _PL, _PL,
+                                        _PU, _PU, _PI, _PI, _PD]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -201,17 +204,19 @@ def component(nlayers, c):
     return tuple(out)
 
 
-def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False):
-    """CPU FMM (Algorithm 2).  Returns phi, and with components=True also
-    (comp_phi [ncomp, n], stats [ncomp, 6])."""
+def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False, adaptive=False):
+    """CPU FMM (Algorithm 2) on uniform trees, or on adaptive trees with W-
+    and X-lists.  Returns phi, and with components=True also (comp_phi
+    [ncomp, n], stats [ncomp, 8]: depth, target leaves, source leaves, V-list
+    pairs, direct point pairs, unstable flag, W-list pairs, X-list pairs)."""
     x, y, z, q = map(_f64, (x, y, z, q))
     n = len(x)
     nc = num_components(ly.nlayers)
     phi = np.zeros(n)
     cphi = np.zeros((nc, n)) if components else None
-    stats = np.zeros((nc, 6))
+    stats = np.zeros((nc, 8))
     rc = lib().orc_fmm(ly.nlayers, _p(ly.eps), _p(ly.lam), _p(ly.d), n, _p(x), _p(y), _p(z), _p(q),
-                       int(p), int(leaf_cap), int(nthreads), _p(phi),
+                       int(p), int(leaf_cap), 1 if adaptive else 0, int(nthreads), _p(phi),
                        _p(cphi) if components else None, _p(stats))
     if rc != 0:
         raise RuntimeError(f"orc_fmm failed: {rc}")
@@ -220,7 +225,10 @@ def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False):
     return phi
 
 
-def component_tree(ly: Layers, x, y, z, comp, leaf_cap=50):
+def component_tree(ly: Layers, x, y, z, comp, leaf_cap=50, adaptive=False):
+    """Depth, each target's and source's leaf key and the root (centre, half
+    side) of one component; adaptive=True also returns the leaf levels
+    (keys are then at each point's own leaf level)."""
     x, y, z = map(_f64, (x, y, z))
     n = len(x)
     depth = ctypes.c_int()
@@ -228,12 +236,18 @@ def component_tree(ly: Layers, x, y, z, comp, leaf_cap=50):
     ns = ctypes.c_int64()
     tk = np.zeros(n, dtype=np.uint64)
     sk = np.zeros(n, dtype=np.uint64)
+    tl = np.zeros(n + 1, dtype=np.int32)
+    sl = np.zeros(n + 1, dtype=np.int32)
     root = np.zeros(4)
     rc = lib().orc_component_tree(ly.nlayers, _p(ly.eps), _p(ly.lam), _p(ly.d), n, _p(x), _p(y), _p(z),
-                                  comp, leaf_cap, ctypes.byref(depth), ctypes.byref(nt), ctypes.byref(ns),
-                                  tk.ctypes.data_as(_PU), sk.ctypes.data_as(_PU), _p(root))
+                                  comp, leaf_cap, 1 if adaptive else 0, ctypes.byref(depth), ctypes.byref(nt),
+                                  ctypes.byref(ns), tk.ctypes.data_as(_PU), sk.ctypes.data_as(_PU),
+                                  tl.ctypes.data_as(_PI), sl.ctypes.data_as(_PI), _p(root))
     if rc != 0:
         raise RuntimeError("orc_component_tree failed")
+    if adaptive:
+        return (depth.value, tk[:nt.value].copy(), sk[:ns.value].copy(), root, tl[:nt.value].copy(),
+                sl[:ns.value].copy())
     return depth.value, tk[:nt.value].copy(), sk[:ns.value].copy(), root
 
 
@@ -265,6 +279,20 @@ def reaction_I_pair(ly: Layers, l, lp, a, b, p, rho, zt, zs, S, n, m, nu, mu):
     lib().orc_reaction_I_pair(_p(ly.eps), _p(ly.lam), _p(ly.d), ly.L, l, lp, a, b, p, float(rho), float(zt),
                               float(zs), float(S), n, m, nu, mu, _p(out))
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
+
+
+def list_coverage(scells, tcells, cap, adaptive=True, H=0):
+    """(cover [nt, ns], counts [V, U, W, X]) of the oracle's lists between
+    sources and targets given by fine cells ([n, 3] ints in 0..65535)."""
+    sc = np.ascontiguousarray(np.asarray(scells, dtype=np.uint32).T)
+    tc = np.ascontiguousarray(np.asarray(tcells, dtype=np.uint32).T)
+    ns, nt = sc.shape[1], tc.shape[1]
+    cover = np.zeros((nt, ns), dtype=np.int32)
+    counts = np.zeros(4, dtype=np.int64)
+    lib().orc_list_coverage(ns, sc.ctypes.data_as(_PU32), nt, tc.ctypes.data_as(_PU32), int(cap),
+                            1 if adaptive else 0, int(H), cover.ctypes.data_as(_PI),
+                            counts.ctypes.data_as(_PLL))
+    return cover, counts
 
 
 def free_point_chain(p, lam, rs, c, r, mode):

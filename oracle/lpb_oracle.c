@@ -28,6 +28,13 @@
  *     operators come from quadrature of the initial values, the forward
  *     recurrence (eq. recurrence1), the Legendre-product expansion
  *     (eq. metoletableform) and eq. coefintable.
+ *   - adaptive trees (Sec. 3.5, closing remarks): boxes divided while they
+ *     hold more than the leaf cap, U/V/W/X lists by a dual traversal of the
+ *     target and source trees, and the point forms on the W- and X-lists:
+ *     free-space M2P / P2L (eqs. freespace3dmulexp, melecoeffree) and
+ *     reaction M2P / P2L from the F~ and L rows of eq. coefintable, whose
+ *     Sommerfeld tables mix the forward and backward
+ *     (eq. backwardrecurrence1) recurrences.
  *
  * Readings of places where the printed text is garbled or silent are listed
  * at each use (sigma typos, index order of the translation sums, Gaunt
@@ -1169,11 +1176,14 @@ static void p2l_react_one(const rcomp_t* C, const ctab_t* CT, int p, double q, d
 /* Tree (shared definition with the GPU library, written separately):      */
 /*  root cube (cx,cy,cz) +- R; fine cell of a point                         */
 /*    t = ((x - cx) + R) / (2R),  ix = clamp(floor(t * 2^16), 0, 2^16-1),   */
-/*  level-l cell = fine cell >> (16 - l); depth H = the smallest l with     */
-/*  N_src <= cap * #non-empty source boxes(l) and the same for targets      */
-/*  (H <= 12); uniform depth; V-list at level l >= 2: non-empty source      */
-/*  boxes that are children of the neighbours of the target's parent and    */
-/*  not adjacent to the target; U-list at level H: adjacent or equal boxes. */
+/*  level-l cell = fine cell >> (16 - l).  Uniform trees: depth H = the    */
+/*  smallest l with N_src <= cap * #non-empty source boxes(l) and the same  */
+/*  for targets (H <= 12).  Adaptive trees: each point set divides a box    */
+/*  while it holds more than cap points (down to level 12).  V-list at      */
+/*  level l >= 2: existing source boxes that are children of the            */
+/*  neighbours of the target's parent and not adjacent to the target;       */
+/*  U-, W- and X-lists by the dual traversal (traverse() below); on uniform */
+/*  trees the U-list is the adjacent or equal boxes at level H.             */
 /* ------------------------------------------------------------------------ */
 static uint32_t fine_cell(double x, double c, double R)
 {
@@ -1252,7 +1262,7 @@ static void key_coords(uint64_t key, int level, int* ix, int* iy, int* iz)
 
 /* ------------------------------------------------------------------------ */
 /* One FMM (Algorithm 1 for a reaction component, the classic Yukawa FMM   */
-/* for a free-space component) on the uniform tree above.                  */
+/* for a free-space component) on the tree above: uniform, or adaptive.    */
 /* ------------------------------------------------------------------------ */
 typedef struct {
     int kind; /* 0 free, 1 reaction */
@@ -1264,7 +1274,7 @@ typedef struct {
 typedef struct {
     int depth;
     int nleaf_t, nleaf_s;
-    long long m2l_pairs, p2p_pairs;
+    long long m2l_pairs, p2p_pairs, w_pairs, x_pairs;
     int unstable;
 } fmmstat_t;
 
@@ -1276,24 +1286,194 @@ static int sort_by_key_cmp_idx(const void* a, const void* b)
     return x[1] < y[1] ? -1 : (x[1] > y[1] ? 1 : 0);
 }
 
-/* points of a leaf level grouped by box: order[] = point indices sorted by (key, index) */
-static void leaf_lists(const cells_t* C, int H, const boxlev_t* B, int* order, int* start)
+/* Points sorted by (fine key, index): order[k] and key[k] = the fine-cell
+ * Morton key (level ORC_HMAX) of the k-th point. */
+static void sort_points(const cells_t* C, int* order, uint64_t* key)
 {
     uint64_t* kv = (uint64_t*)malloc(sizeof(uint64_t) * 2 * (C->n > 0 ? C->n : 1));
-    int sh = ORC_HMAX - H;
     for (int i = 0; i < C->n; ++i) {
-        kv[2 * i] = morton_key(C->cx[i] >> sh, C->cy[i] >> sh, C->cz[i] >> sh, H);
+        kv[2 * i] = morton_key(C->cx[i], C->cy[i], C->cz[i], ORC_HMAX);
         kv[2 * i + 1] = (uint64_t)i;
     }
     qsort(kv, C->n, 2 * sizeof(uint64_t), sort_by_key_cmp_idx);
-    int b = 0;
-    start[0] = 0;
     for (int i = 0; i < C->n; ++i) {
+        key[i] = kv[2 * i];
         order[i] = (int)kv[2 * i + 1];
-        while (B->key[b] != kv[2 * i]) start[++b] = i;
     }
-    for (int k = b + 1; k <= B->nb; ++k) start[k] = C->n;
     free(kv);
+}
+
+/* Adaptive rule: a box is divided while it holds more than cap points and
+ * lies above ORC_MAXDEPTH, so a point's leaf is its first ancestor (from the
+ * root down) holding at most cap points.  lv[i] = leaf level of point i
+ * (key, order: the sorted points). */
+static void leaf_levels(int n, const int* order, const uint64_t* key, int cap, int* lv)
+{
+    for (int i = 0; i < n; ++i) lv[i] = -1;
+    for (int l = 0; l <= ORC_MAXDEPTH; ++l) {
+        int sh = 3 * (ORC_HMAX - l);
+        for (int k0 = 0; k0 < n;) {
+            int k1 = k0 + 1;
+            while (k1 < n && (key[k1] >> sh) == (key[k0] >> sh)) ++k1;
+            if (k1 - k0 <= cap || l == ORC_MAXDEPTH)
+                for (int k = k0; k < k1; ++k)
+                    if (lv[order[k]] < 0) lv[order[k]] = l;
+            k0 = k1;
+        }
+    }
+}
+
+/* distinct level-l cells of the points whose leaf level is at least l */
+static void level_boxes(const cells_t* C, const int* lv, int level, boxlev_t* B)
+{
+    uint64_t* k = (uint64_t*)malloc(sizeof(uint64_t) * (C->n > 0 ? C->n : 1));
+    int sh = ORC_HMAX - level, m = 0;
+    for (int i = 0; i < C->n; ++i)
+        if (lv[i] >= level) k[m++] = morton_key(C->cx[i] >> sh, C->cy[i] >> sh, C->cz[i] >> sh, level);
+    qsort(k, m, sizeof(uint64_t), cmp_u64);
+    int nb = 0;
+    for (int i = 0; i < m; ++i)
+        if (i == 0 || k[i] != k[i - 1]) k[nb++] = k[i];
+    B->nb = nb;
+    B->key = k;
+    B->start = NULL;
+}
+
+static int box_child(const boxlev_t* B, int H, int l, int b, int o)
+{
+    if (l >= H) return -1;
+    return find_box(&B[l + 1], (B[l].key[b] << 3) | (uint64_t)o);
+}
+
+static int box_is_leaf(const boxlev_t* B, int H, int l, int b)
+{
+    for (int o = 0; o < 8; ++o)
+        if (box_child(B, H, l, b, o) >= 0) return 0;
+    return 1;
+}
+
+/* the closed cubes of box (la, A[la].key[ia]) and box (lb, B[lb].key[ib])
+ * touch or overlap */
+static int boxes_adjacent(const boxlev_t* A, int la, int ia, const boxlev_t* B, int lb, int ib)
+{
+    int a[3], c[3];
+    key_coords(A[la].key[ia], la, &a[0], &a[1], &a[2]);
+    key_coords(B[lb].key[ib], lb, &c[0], &c[1], &c[2]);
+    int L = la > lb ? la : lb;
+    for (int k = 0; k < 3; ++k) {
+        long alo = (long)a[k] << (L - la), ahi = ((long)(a[k] + 1) << (L - la)) - 1;
+        long clo = (long)c[k] << (L - lb), chi = ((long)(c[k] + 1) << (L - lb)) - 1;
+        if (alo > chi + 1 || clo > ahi + 1) return 0;
+    }
+    return 1;
+}
+
+/* box pairs (target level, target box, source level, source box) */
+typedef struct {
+    int n, cap;
+    int* v;
+} plist_t;
+
+static void plist_push(plist_t* P, int tl, int tb, int sl, int sb)
+{
+    if (P->n == P->cap) {
+        P->cap = P->cap ? 2 * P->cap : 256;
+        P->v = (int*)realloc(P->v, sizeof(int) * 4 * P->cap);
+    }
+    int* e = P->v + 4 * P->n++;
+    e[0] = tl;
+    e[1] = tb;
+    e[2] = sl;
+    e[3] = sb;
+}
+
+/* Dual traversal of the target and source trees from a pair of adjacent
+ * boxes (levels below 2 count as adjacent: they carry no expansions).  Two
+ * leaves: U-list (direct).  A target leaf and a source box with children:
+ * the children that are not adjacent to the leaf go to its W-list (their
+ * multipole expansions are evaluated at its targets, M2P), the others are
+ * traversed further.  A source leaf and a target box with children:
+ * symmetrically the X-list (local expansions formed from the leaf's sources,
+ * P2L).  Two boxes with children (same level): child pairs that are not
+ * adjacent are the V-list (M2L, listed level by level from the box sets), the
+ * others are traversed further. */
+static void traverse(const boxlev_t* TB, const boxlev_t* SB, int H, int tl, int tb, int sl, int sb, plist_t* U,
+                     plist_t* W, plist_t* X)
+{
+    int tleaf = box_is_leaf(TB, H, tl, tb), sleaf = box_is_leaf(SB, H, sl, sb);
+    if (tleaf && sleaf) {
+        plist_push(U, tl, tb, sl, sb);
+        return;
+    }
+    if (tleaf) {
+        for (int o = 0; o < 8; ++o) {
+            int c = box_child(SB, H, sl, sb, o);
+            if (c < 0) continue;
+            if (sl + 1 < 2 || boxes_adjacent(TB, tl, tb, SB, sl + 1, c)) traverse(TB, SB, H, tl, tb, sl + 1, c, U, W, X);
+            else plist_push(W, tl, tb, sl + 1, c);
+        }
+        return;
+    }
+    if (sleaf) {
+        for (int o = 0; o < 8; ++o) {
+            int c = box_child(TB, H, tl, tb, o);
+            if (c < 0) continue;
+            if (tl + 1 < 2 || boxes_adjacent(TB, tl + 1, c, SB, sl, sb)) traverse(TB, SB, H, tl + 1, c, sl, sb, U, W, X);
+            else plist_push(X, tl + 1, c, sl, sb);
+        }
+        return;
+    }
+    for (int ot = 0; ot < 8; ++ot) {
+        int tc = box_child(TB, H, tl, tb, ot);
+        if (tc < 0) continue;
+        for (int os = 0; os < 8; ++os) {
+            int sc = box_child(SB, H, sl, sb, os);
+            if (sc < 0) continue;
+            if (tl + 1 < 2 || boxes_adjacent(TB, tl + 1, tc, SB, sl + 1, sc))
+                traverse(TB, SB, H, tl + 1, tc, sl + 1, sc, U, W, X);
+        }
+    }
+}
+
+/* first and one-past-last sorted point of box (l, k) */
+static void box_range(int n, const uint64_t* key, int l, uint64_t k, int* lo, int* hi)
+{
+    int sh = 3 * (ORC_HMAX - l);
+    uint64_t a = k << sh, b = (k + 1) << sh;
+    int x = 0, y = n;
+    while (x < y) {
+        int m = (x + y) / 2;
+        if (key[m] < a) x = m + 1;
+        else y = m;
+    }
+    *lo = x;
+    y = n;
+    while (x < y) {
+        int m = (x + y) / 2;
+        if (key[m] < b) x = m + 1;
+        else y = m;
+    }
+    *hi = x;
+}
+
+/* CSR of a pair list by (level, box) of its first pair of fields: the
+ * entries of target box (l, b) are idx[ptr[off[l] + b] .. ptr[off[l] + b + 1]),
+ * in list order. */
+static void plist_csr(const plist_t* P, const boxlev_t* TB, int H, int* off, int** ptr, int** idx)
+{
+    int tot = 0;
+    for (int l = 0; l <= H; ++l) {
+        off[l] = tot;
+        tot += TB[l].nb;
+    }
+    *ptr = (int*)calloc((size_t)tot + 1, sizeof(int));
+    *idx = (int*)malloc(sizeof(int) * (P->n > 0 ? P->n : 1));
+    for (int k = 0; k < P->n; ++k) (*ptr)[off[P->v[4 * k]] + P->v[4 * k + 1] + 1]++;
+    for (int k = 0; k < tot; ++k) (*ptr)[k + 1] += (*ptr)[k];
+    int* fill = (int*)malloc(sizeof(int) * (tot + 1));
+    memcpy(fill, *ptr, sizeof(int) * (tot + 1));
+    for (int k = 0; k < P->n; ++k) (*idx)[fill[off[P->v[4 * k]] + P->v[4 * k + 1]]++] = k;
+    free(fill);
 }
 
 static void box_center(double cx, double cy, double cz, double R, int level, int ix, int iy, int iz, double* c)
@@ -1304,11 +1484,59 @@ static void box_center(double cx, double cy, double cz, double R, int level, int
     c[2] = (cz - R) + (iz + 0.5) * h;
 }
 
+static void key_center(double cx, double cy, double cz, double R, int level, uint64_t key, double* c)
+{
+    int ix, iy, iz;
+    key_coords(key, level, &ix, &iy, &iz);
+    box_center(cx, cy, cz, R, level, ix, iy, iz, c);
+}
+
+/* direct part of one target from the sources [k0, k1) of the sorted order
+ * (free: the Green's function without the self term; reaction: u~^{ab} by
+ * quadrature of I_00, Algorithm 1's last step) */
+static double near_sum(const fmmspec_t* F, int i, const double* tx, const double* ty, const double* tz,
+                       const int64_t* tid, int k0, int k1, const int* sorder, const double* sx, const double* sy,
+                       const double* sz, const double* sq, const int64_t* sid, long long* npp)
+{
+    const layers_t* Ly = &F->rc.Ly;
+    double lmin = layers_lam_min(Ly), dmax = layers_dmax(Ly);
+    double acc = 0.0;
+    for (int ks = k0; ks < k1; ++ks) {
+        int j = sorder[ks];
+        if (F->kind == 0) {
+            if (sid[j] == tid[i]) continue;
+            double r = sqrt((tx[i] - sx[j]) * (tx[i] - sx[j]) + (ty[i] - sy[j]) * (ty[i] - sy[j]) +
+                            (tz[i] - sz[j]) * (tz[i] - sz[j]));
+            acc += sq[j] * green_free(F->lam_t, F->eps_t, r);
+        } else {
+            /* u~^{ab}(r, r'_ab) = I_00 with Q_00 = 1/(4 pi) (Algorithm 1, last step) */
+            const rcomp_t* C = &F->rc;
+            double rho = hypot(tx[i] - sx[j], ty[i] - sy[j]);
+            double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
+            nodes_t nd;
+            build_nodes(&nd, rho, zsep(C, tz[i], sz[j]), 1, lmin, dmax, ORC_TOL);
+            double s = 0.0;
+            for (int k = 0; k < nd.n; ++k) {
+                double t = nd.x[k];
+                double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+                s += nd.w[k] * t * jn(0, t * rho) * zkern(C, lz, lzp, tz[i], sz[j]) *
+                     sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz;
+            }
+            free_nodes(&nd);
+            acc += sq[j] * s / (4.0 * ORC_PI);
+        }
+        (*npp)++;
+    }
+    return acc;
+}
+
 /* pre_s, pre_t: fine cells of the sources and targets (computed here from the
- * coordinates and the root cube when NULL); Hfix >= 0 imposes the depth. */
-static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx, const double* sy, const double* sz,
-                   const double* sq, const int64_t* sid, int nt, const double* tx, const double* ty,
-                   const double* tz, const int64_t* tid, double cx, double cy, double cz, double R,
+ * coordinates and the root cube when NULL); Hfix >= 0 imposes the depth of a
+ * uniform tree; adaptive != 0 builds the adaptive trees instead (leaf rule
+ * above, separately for sources and targets) with W- and X-lists. */
+static int run_fmm(const fmmspec_t* F, int p, int cap, int adaptive, int ns, const double* sx, const double* sy,
+                   const double* sz, const double* sq, const int64_t* sid, int nt, const double* tx,
+                   const double* ty, const double* tz, const int64_t* tid, double cx, double cy, double cz, double R,
                    const cells_t* pre_s, const cells_t* pre_t, int Hfix,
                    const gaunt_tab_t* GT, const ctab_t* CT, double* phi, fmmstat_t* st)
 {
@@ -1335,28 +1563,68 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
         Ct.cy[i] = pre_t ? pre_t->cy[i] : fine_cell(ty[i], cy, R);
         Ct.cz[i] = pre_t ? pre_t->cz[i] : fine_cell(tz[i], cz, R);
     }
-    boxlev_t SB[ORC_MAXDEPTH + 1], TB[ORC_MAXDEPTH + 1];
-    int H = -1;
-    for (int l = 0; l <= ORC_MAXDEPTH; ++l) {
-        distinct_boxes(&Cs, l, &SB[l]);
-        distinct_boxes(&Ct, l, &TB[l]);
-        if (Hfix >= 0 ? l == Hfix
-                      : ((long long)ns <= (long long)cap * SB[l].nb && (long long)nt <= (long long)cap * TB[l].nb)) {
-            H = l;
-            break;
-        }
-    }
-    if (H < 0) H = ORC_MAXDEPTH;
-    st->depth = H;
-    st->nleaf_s = SB[H].nb;
-    st->nleaf_t = TB[H].nb;
-
     int* sorder = (int*)malloc(sizeof(int) * ns);
-    int* sstart = (int*)malloc(sizeof(int) * (SB[H].nb + 1));
     int* torder = (int*)malloc(sizeof(int) * nt);
-    int* tstart = (int*)malloc(sizeof(int) * (TB[H].nb + 1));
-    leaf_lists(&Cs, H, &SB[H], sorder, sstart);
-    leaf_lists(&Ct, H, &TB[H], torder, tstart);
+    uint64_t* skey = (uint64_t*)malloc(sizeof(uint64_t) * ns);
+    uint64_t* tkey = (uint64_t*)malloc(sizeof(uint64_t) * nt);
+    sort_points(&Cs, sorder, skey);
+    sort_points(&Ct, torder, tkey);
+    /* leaf level of every point */
+    int* slv = (int*)malloc(sizeof(int) * ns);
+    int* tlv = (int*)malloc(sizeof(int) * nt);
+    int H = -1;
+    if (adaptive) {
+        leaf_levels(ns, sorder, skey, cap, slv);
+        leaf_levels(nt, torder, tkey, cap, tlv);
+        for (int i = 0; i < ns; ++i) H = slv[i] > H ? slv[i] : H;
+        for (int i = 0; i < nt; ++i) H = tlv[i] > H ? tlv[i] : H;
+    } else {
+        for (int l = 0; l <= ORC_MAXDEPTH && H < 0; ++l) {
+            boxlev_t a, b;
+            distinct_boxes(&Cs, l, &a);
+            distinct_boxes(&Ct, l, &b);
+            if (Hfix >= 0 ? l == Hfix : ((long long)ns <= (long long)cap * a.nb && (long long)nt <= (long long)cap * b.nb))
+                H = l;
+            free(a.key);
+            free(b.key);
+        }
+        if (H < 0) H = ORC_MAXDEPTH;
+        for (int i = 0; i < ns; ++i) slv[i] = H;
+        for (int i = 0; i < nt; ++i) tlv[i] = H;
+    }
+    st->depth = H;
+    boxlev_t SB[ORC_MAXDEPTH + 1], TB[ORC_MAXDEPTH + 1];
+    for (int l = 0; l <= H; ++l) {
+        level_boxes(&Cs, slv, l, &SB[l]);
+        level_boxes(&Ct, tlv, l, &TB[l]);
+    }
+    /* leaves (level, box) of each tree, by level then Morton order */
+    int *sleaf = (int*)malloc(sizeof(int) * 2 * ns), *tleaf = (int*)malloc(sizeof(int) * 2 * nt);
+    int nsl = 0, ntl = 0;
+    for (int l = 0; l <= H; ++l) {
+        for (int b = 0; b < SB[l].nb; ++b)
+            if (box_is_leaf(SB, H, l, b)) {
+                sleaf[2 * nsl] = l;
+                sleaf[2 * nsl++ + 1] = b;
+            }
+        for (int b = 0; b < TB[l].nb; ++b)
+            if (box_is_leaf(TB, H, l, b)) {
+                tleaf[2 * ntl] = l;
+                tleaf[2 * ntl++ + 1] = b;
+            }
+    }
+    st->nleaf_s = nsl;
+    st->nleaf_t = ntl;
+    /* U-, W- and X-lists */
+    plist_t U = {0, 0, NULL}, W = {0, 0, NULL}, X = {0, 0, NULL};
+    traverse(TB, SB, H, 0, 0, 0, 0, &U, &W, &X);
+    st->w_pairs = W.n;
+    st->x_pairs = X.n;
+    int toff[ORC_MAXDEPTH + 1];
+    int *uptr, *uidx, *wptr, *widx, *xptr, *xidx;
+    plist_csr(&U, TB, H, toff, &uptr, &uidx);
+    plist_csr(&W, TB, H, toff, &wptr, &widx);
+    plist_csr(&X, TB, H, toff, &xptr, &xidx);
 
     /* ---------------- far field (levels >= 2) ---------------- */
     if (H >= 2) {
@@ -1370,14 +1638,16 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 4)
 #endif
-        for (int b = 0; b < SB[H].nb; ++b) {
-            int ix, iy, iz;
+        for (int e = 0; e < nsl; ++e) {
+            int l = sleaf[2 * e], b = sleaf[2 * e + 1];
+            if (l < 2) continue;
             double c[3];
-            key_coords(SB[H].key[b], H, &ix, &iy, &iz);
-            box_center(cx, cy, cz, R, H, ix, iy, iz, c);
-            for (int k = sstart[b]; k < sstart[b + 1]; ++k) {
+            int k0, k1;
+            key_center(cx, cy, cz, R, l, SB[l].key[b], c);
+            box_range(ns, skey, l, SB[l].key[b], &k0, &k1);
+            for (int k = k0; k < k1; ++k) {
                 int j = sorder[k];
-                p2m_one(p, F->lam_s, sq[j], sx[j] - c[0], sy[j] - c[1], sz[j] - c[2], &ME[H][(size_t)b * K]);
+                p2m_one(p, F->lam_s, sq[j], sx[j] - c[0], sy[j] - c[1], sz[j] - c[2], &ME[l][(size_t)b * K]);
             }
         }
         /* M2M, levels H-1 .. 2 (eq. metome) */
@@ -1401,7 +1671,7 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
                 }
             }
         }
-        /* downward pass: L2L from the parent, then the V-list M2L */
+        /* downward pass: L2L from the parent, the V-list M2L, the X-list P2L */
         for (int l = 2; l <= H; ++l) {
             double h = 2.0 * R / (double)(1 << l);
             if (l >= 3) {
@@ -1536,20 +1806,64 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
             free(krep);
             free(kused);
             free(iused);
+            /* X-list: local expansions formed from the sources of coarser
+             * leaves directly (eq. melecoeffree; reaction: the L rows of eq.
+             * coefintable with the point table, S = this box's side) */
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+            for (int b = 0; b < TB[l].nb; ++b) {
+                double c[3];
+                key_center(cx, cy, cz, R, l, TB[l].key[b], c);
+                for (int e = xptr[toff[l] + b]; e < xptr[toff[l] + b + 1]; ++e) {
+                    const int* v = X.v + 4 * xidx[e];
+                    int k0, k1;
+                    box_range(ns, skey, v[2], SB[v[2]].key[v[3]], &k0, &k1);
+                    for (int k = k0; k < k1; ++k) {
+                        int j = sorder[k];
+                        if (F->kind == 0)
+                            p2l_free_one(p, F->lam_t, sq[j], sx[j] - c[0], sy[j] - c[1], sz[j] - c[2],
+                                         &LE[l][(size_t)b * K]);
+                        else
+                            p2l_react_one(&F->rc, CT, p, sq[j], sx[j], sy[j], sz[j], c, h, &LE[l][(size_t)b * K]);
+                    }
+                }
+            }
         }
-        /* L2P at the leaves */
+        /* L2P at the leaves, then the W-list: multipole expansions of finer
+         * boxes evaluated at the leaf's targets directly (eq.
+         * freespace3dmulexp; reaction: the F~ rows of eq. coefintable with the
+         * point table, S = the source box's side) */
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 4)
 #endif
-        for (int b = 0; b < TB[H].nb; ++b) {
-            int ix, iy, iz;
-            double c[3];
-            key_coords(TB[H].key[b], H, &ix, &iy, &iz);
-            box_center(cx, cy, cz, R, H, ix, iy, iz, c);
-            for (int k = tstart[b]; k < tstart[b + 1]; ++k) {
-                int i = torder[k];
-                phi[i] += F->far_factor *
-                          l2p_one(p, F->lam_t, &LE[H][(size_t)b * K], tx[i] - c[0], ty[i] - c[1], tz[i] - c[2]);
+        for (int e = 0; e < ntl; ++e) {
+            int l = tleaf[2 * e], b = tleaf[2 * e + 1];
+            int k0, k1;
+            box_range(nt, tkey, l, TB[l].key[b], &k0, &k1);
+            if (l >= 2) {
+                double c[3];
+                key_center(cx, cy, cz, R, l, TB[l].key[b], c);
+                for (int k = k0; k < k1; ++k) {
+                    int i = torder[k];
+                    phi[i] += F->far_factor *
+                              l2p_one(p, F->lam_t, &LE[l][(size_t)b * K], tx[i] - c[0], ty[i] - c[1], tz[i] - c[2]);
+                }
+            }
+            for (int w = wptr[toff[l] + b]; w < wptr[toff[l] + b + 1]; ++w) {
+                const int* v = W.v + 4 * widx[w];
+                int sl = v[2], sb = v[3];
+                double c[3];
+                key_center(cx, cy, cz, R, sl, SB[sl].key[sb], c);
+                const cplx* M = &ME[sl][(size_t)sb * K];
+                for (int k = k0; k < k1; ++k) {
+                    int i = torder[k];
+                    if (F->kind == 0)
+                        phi[i] += F->far_factor * m2p_free_one(p, F->lam_s, M, tx[i] - c[0], ty[i] - c[1], tz[i] - c[2]);
+                    else
+                        phi[i] += m2p_react_one(&F->rc, CT, p, M, tx[i], ty[i], tz[i], c,
+                                                2.0 * R / (double)(1 << sl));
+                }
             }
         }
         free(Aop);
@@ -1559,56 +1873,24 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
         }
     }
 
-    /* ---------------- near field (U-list at level H) ---------------- */
-    const layers_t* Ly = &F->rc.Ly;
-    double lmin = layers_lam_min(Ly), dmax = layers_dmax(Ly);
-    int nside = 1 << H;
+    /* ---------------- near field (U-list) ---------------- */
     long long npp = 0;
 #ifdef _OPENMP
 #pragma omp parallel for schedule(dynamic, 1) reduction(+ : npp)
 #endif
-    for (int b = 0; b < TB[H].nb; ++b) {
-        int tx_, ty_, tz_;
-        key_coords(TB[H].key[b], H, &tx_, &ty_, &tz_);
-        for (int dx = -1; dx <= 1; ++dx)
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dz = -1; dz <= 1; ++dz) {
-                    int sx_ = tx_ + dx, sy_ = ty_ + dy, sz_ = tz_ + dz;
-                    if (sx_ < 0 || sy_ < 0 || sz_ < 0 || sx_ >= nside || sy_ >= nside || sz_ >= nside) continue;
-                    int sb = find_box(&SB[H], morton_key(sx_, sy_, sz_, H));
-                    if (sb < 0) continue;
-                    for (int kt = tstart[b]; kt < tstart[b + 1]; ++kt) {
-                        int i = torder[kt];
-                        double acc = 0.0;
-                        for (int ks = sstart[sb]; ks < sstart[sb + 1]; ++ks) {
-                            int j = sorder[ks];
-                            if (F->kind == 0) {
-                                if (sid[j] == tid[i]) continue;
-                                double r = sqrt((tx[i] - sx[j]) * (tx[i] - sx[j]) + (ty[i] - sy[j]) * (ty[i] - sy[j]) +
-                                                (tz[i] - sz[j]) * (tz[i] - sz[j]));
-                                acc += sq[j] * green_free(F->lam_t, F->eps_t, r);
-                            } else {
-                                /* u~^{ab}(r, r'_ab) = I_00 with Q_00 = 1/(4 pi) (Algorithm 1, last step) */
-                                const rcomp_t* C = &F->rc;
-                                double rho = hypot(tx[i] - sx[j], ty[i] - sy[j]);
-                                double lt = Ly->lam[C->l], ls = Ly->lam[C->lp];
-                                nodes_t nd;
-                                build_nodes(&nd, rho, zsep(C, tz[i], sz[j]), 1, lmin, dmax, ORC_TOL);
-                                double s = 0.0;
-                                for (int k = 0; k < nd.n; ++k) {
-                                    double t = nd.x[k];
-                                    double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
-                                    s += nd.w[k] * t * jn(0, t * rho) * zkern(C, lz, lzp, tz[i], sz[j]) *
-                                         sigma(Ly, C->l, C->lp, C->a, C->b, t) / lz;
-                                }
-                                free_nodes(&nd);
-                                acc += sq[j] * s / (4.0 * ORC_PI);
-                            }
-                            npp++;
-                        }
-                        phi[i] += acc;
-                    }
-                }
+    for (int e = 0; e < ntl; ++e) {
+        int l = tleaf[2 * e], b = tleaf[2 * e + 1];
+        int k0, k1;
+        box_range(nt, tkey, l, TB[l].key[b], &k0, &k1);
+        for (int u = uptr[toff[l] + b]; u < uptr[toff[l] + b + 1]; ++u) {
+            const int* v = U.v + 4 * uidx[u];
+            int s0, s1;
+            box_range(ns, skey, v[2], SB[v[2]].key[v[3]], &s0, &s1);
+            for (int k = k0; k < k1; ++k) {
+                int i = torder[k];
+                phi[i] += near_sum(F, i, tx, ty, tz, tid, s0, s1, sorder, sx, sy, sz, sq, sid, &npp);
+            }
+        }
     }
     st->p2p_pairs = npp;
 
@@ -1616,10 +1898,23 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int ns, const double* sx,
         free(SB[l].key);
         free(TB[l].key);
     }
+    free(U.v);
+    free(W.v);
+    free(X.v);
+    free(uptr);
+    free(uidx);
+    free(wptr);
+    free(widx);
+    free(xptr);
+    free(xidx);
+    free(sleaf);
+    free(tleaf);
+    free(slv);
+    free(tlv);
     free(sorder);
-    free(sstart);
     free(torder);
-    free(tstart);
+    free(skey);
+    free(tkey);
     free(Cs.cx);
     free(Ct.cx);
     return 0;
@@ -1813,8 +2108,8 @@ static void reaction_cells(const layers_t* Ly, const rgrid_t* G, int l, int lp, 
  * depth, target leaves, source leaves, M2L pairs, P2P pairs, recurrence
  * stability violation flag. */
 int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, int64_t n, const double* x,
-            const double* y, const double* z, const double* q, int p, int leaf_cap, int nthreads, double* phi,
-            double* comp_phi, double* stats)
+            const double* y, const double* z, const double* q, int p, int leaf_cap, int adaptive, int nthreads,
+            double* phi, double* comp_phi, double* stats)
 {
     layers_t Ly;
     if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
@@ -1901,7 +2196,7 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
         CT.v = NULL;
         if (kind == 1) ctab_init(&CT, p, Ly.lam[l], Ly.lam[lp]);
         fmmstat_t st;
-        run_fmm(&F, p, leaf_cap, ns, sx, sy, sz, sq, sid, nt, tx, ty, tz, tid, ctr[0], ctr[1], ctr[2], R,
+        run_fmm(&F, p, leaf_cap, adaptive, ns, sx, sy, sz, sq, sid, nt, tx, ty, tz, tid, ctr[0], ctr[1], ctr[2], R,
                 kind == 1 ? &Cs : NULL, kind == 1 ? &Ct : NULL, kind == 1 ? G.H : -1, &GT,
                 kind == 1 ? &CT : NULL, ph, &st);
         if (CT.v) free(CT.v);
@@ -1912,13 +2207,15 @@ int orc_fmm(int nlayers, const double* eps, const double* lam, const double* d, 
             if (comp_phi) comp_phi[(size_t)c * n + tid[k]] = ph[k];
         }
         if (stats) {
-            double* s = stats + (size_t)c * 6;
+            double* s = stats + (size_t)c * 8;
             s[0] = st.depth;
             s[1] = st.nleaf_t;
             s[2] = st.nleaf_s;
             s[3] = (double)st.m2l_pairs;
             s[4] = (double)st.p2p_pairs;
             s[5] = st.unstable;
+            s[6] = (double)st.w_pairs;
+            s[7] = (double)st.x_pairs;
         }
         free(buf);
         free(tid);
@@ -2250,8 +2547,9 @@ void orc_plm_beyond(int n, int m, double w, double* out)
 /* Tree summary of one component, for the tree-equality parity test:
  * out_depth, and for every target / source point its leaf Morton key. */
 int orc_component_tree(int nlayers, const double* eps, const double* lam, const double* d, int64_t n,
-                       const double* x, const double* y, const double* z, int comp, int leaf_cap, int* depth,
-                       int64_t* nt_out, int64_t* ns_out, uint64_t* tkeys, uint64_t* skeys, double* root)
+                       const double* x, const double* y, const double* z, int comp, int leaf_cap, int adaptive,
+                       int* depth, int64_t* nt_out, int64_t* ns_out, uint64_t* tkeys, uint64_t* skeys, int* tlev,
+                       int* slev, double* root)
 {
     layers_t Ly;
     if (fill_layers(&Ly, nlayers, eps, lam, d)) return -1;
@@ -2328,9 +2626,32 @@ int orc_component_tree(int nlayers, const double* eps, const double* lam, const 
         reaction_cells(&Ly, &G, l, lp, a, b, nt, tx, ty, tz, ns, sx, sy, szo, &Ct, &Cs);
     }
     free(lay);
-    int sh = ORC_HMAX - H;
-    for (int i = 0; i < nt; ++i) tkeys[i] = morton_key(Ct.cx[i] >> sh, Ct.cy[i] >> sh, Ct.cz[i] >> sh, H);
-    for (int i = 0; i < ns; ++i) skeys[i] = morton_key(Cs.cx[i] >> sh, Cs.cy[i] >> sh, Cs.cz[i] >> sh, H);
+    /* leaf level of each point: H (uniform) or the adaptive rule per set */
+    for (int i = 0; i < nt; ++i) tlev[i] = H;
+    for (int i = 0; i < ns; ++i) slev[i] = H;
+    if (adaptive) {
+        const cells_t* sets[2] = {&Ct, &Cs};
+        int* lvs[2] = {tlev, slev};
+        H = 0;
+        for (int t = 0; t < 2; ++t) {
+            int m = sets[t]->n;
+            int* order = (int*)malloc(sizeof(int) * (m + 1));
+            uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (m + 1));
+            sort_points(sets[t], order, key);
+            leaf_levels(m, order, key, leaf_cap, lvs[t]);
+            for (int i = 0; i < m; ++i) H = lvs[t][i] > H ? lvs[t][i] : H;
+            free(order);
+            free(key);
+        }
+    }
+    for (int i = 0; i < nt; ++i) {
+        int sh = ORC_HMAX - tlev[i];
+        tkeys[i] = morton_key(Ct.cx[i] >> sh, Ct.cy[i] >> sh, Ct.cz[i] >> sh, tlev[i]);
+    }
+    for (int i = 0; i < ns; ++i) {
+        int sh = ORC_HMAX - slev[i];
+        skeys[i] = morton_key(Cs.cx[i] >> sh, Cs.cy[i] >> sh, Cs.cz[i] >> sh, slev[i]);
+    }
     *depth = H;
     *nt_out = nt;
     *ns_out = ns;
@@ -2423,4 +2744,100 @@ void orc_reaction_I_point(const double* eps, const double* lam, const double* d,
     out[3] = cimag(w);
     free(tab);
     free(CT.v);
+}
+
+/* List pin: builds the trees (uniform at depth Hfix when adaptive = 0, else
+ * adaptive with leaf cap `cap`) and lists of run_fmm for sources and targets
+ * given by their fine cells (cx, cy, cz per point, 0..65535), and counts for
+ * every (target, source) pair how many list entries cover it: V (all targets
+ * under the target box and all sources under the source box), U, W and X.
+ * cover[i * ns + j] (sorted-order independent: indices are the inputs').
+ * counts[0..3] = number of V, U, W, X box pairs. */
+int orc_list_coverage(int ns, const uint32_t* scell, int nt, const uint32_t* tcell, int cap, int adaptive, int Hfix,
+                      int* cover, long long* counts)
+{
+    cells_t Cs, Ct;
+    Cs.n = ns;
+    Ct.n = nt;
+    Cs.cx = (uint32_t*)scell;
+    Cs.cy = Cs.cx + ns;
+    Cs.cz = Cs.cy + ns;
+    Ct.cx = (uint32_t*)tcell;
+    Ct.cy = Ct.cx + nt;
+    Ct.cz = Ct.cy + nt;
+    memset(cover, 0, sizeof(int) * (size_t)nt * ns);
+    memset(counts, 0, sizeof(long long) * 4);
+    if (ns == 0 || nt == 0) return 0;
+    int* sorder = (int*)malloc(sizeof(int) * ns);
+    int* torder = (int*)malloc(sizeof(int) * nt);
+    uint64_t* skey = (uint64_t*)malloc(sizeof(uint64_t) * ns);
+    uint64_t* tkey = (uint64_t*)malloc(sizeof(uint64_t) * nt);
+    sort_points(&Cs, sorder, skey);
+    sort_points(&Ct, torder, tkey);
+    int* slv = (int*)malloc(sizeof(int) * ns);
+    int* tlv = (int*)malloc(sizeof(int) * nt);
+    int H = 0;
+    if (adaptive) {
+        leaf_levels(ns, sorder, skey, cap, slv);
+        leaf_levels(nt, torder, tkey, cap, tlv);
+        for (int i = 0; i < ns; ++i) H = slv[i] > H ? slv[i] : H;
+        for (int i = 0; i < nt; ++i) H = tlv[i] > H ? tlv[i] : H;
+    } else {
+        H = Hfix;
+        for (int i = 0; i < ns; ++i) slv[i] = H;
+        for (int i = 0; i < nt; ++i) tlv[i] = H;
+    }
+    boxlev_t SB[ORC_MAXDEPTH + 1], TB[ORC_MAXDEPTH + 1];
+    for (int l = 0; l <= H; ++l) {
+        level_boxes(&Cs, slv, l, &SB[l]);
+        level_boxes(&Ct, tlv, l, &TB[l]);
+    }
+    plist_t U = {0, 0, NULL}, W = {0, 0, NULL}, X = {0, 0, NULL}, V = {0, 0, NULL};
+    traverse(TB, SB, H, 0, 0, 0, 0, &U, &W, &X);
+    /* V-list as run_fmm lists it: level l >= 2, children of the neighbours
+     * of the target's parent that are not adjacent to the target */
+    for (int l = 2; l <= H; ++l) {
+        int nside = 1 << l;
+        for (int b = 0; b < TB[l].nb; ++b) {
+            int tx_, ty_, tz_;
+            key_coords(TB[l].key[b], l, &tx_, &ty_, &tz_);
+            int px = tx_ >> 1, py = ty_ >> 1, pz = tz_ >> 1;
+            for (int qx = px - 1; qx <= px + 1; ++qx)
+                for (int qy = py - 1; qy <= py + 1; ++qy)
+                    for (int qz = pz - 1; qz <= pz + 1; ++qz) {
+                        if (qx < 0 || qy < 0 || qz < 0 || qx >= nside / 2 || qy >= nside / 2 || qz >= nside / 2)
+                            continue;
+                        for (int o = 0; o < 8; ++o) {
+                            int sx_ = 2 * qx + ((o >> 2) & 1), sy_ = 2 * qy + ((o >> 1) & 1), sz_ = 2 * qz + (o & 1);
+                            if (iabs(sx_ - tx_) <= 1 && iabs(sy_ - ty_) <= 1 && iabs(sz_ - tz_) <= 1) continue;
+                            int sb = find_box(&SB[l], morton_key(sx_, sy_, sz_, l));
+                            if (sb >= 0) plist_push(&V, l, b, l, sb);
+                        }
+                    }
+        }
+    }
+    plist_t* lists[4] = {&V, &U, &W, &X};
+    for (int t = 0; t < 4; ++t) {
+        counts[t] = lists[t]->n;
+        for (int e = 0; e < lists[t]->n; ++e) {
+            const int* v = lists[t]->v + 4 * e;
+            int t0, t1, s0, s1;
+            box_range(nt, tkey, v[0], TB[v[0]].key[v[1]], &t0, &t1);
+            box_range(ns, skey, v[2], SB[v[2]].key[v[3]], &s0, &s1);
+            for (int a = t0; a < t1; ++a)
+                for (int c = s0; c < s1; ++c) cover[(size_t)torder[a] * ns + sorder[c]]++;
+        }
+        free(lists[t]->v);
+    }
+    for (int l = 0; l <= H; ++l) {
+        free(SB[l].key);
+        free(TB[l].key);
+    }
+    free(sorder);
+    free(torder);
+    free(skey);
+    free(tkey);
+    free(slv);
+    free(tlv);
+    return 0;
 }

@@ -81,11 +81,11 @@ def _uniform_block(rng: SplitMix64, n: int, lo, hi):
     return x, y, z, q
 
 
-def _gauss_block(rng: SplitMix64, n: int, lo, hi, sigma: float):
-    """Gaussian about the cube centre, redrawn until inside the cube."""
+def _gauss_block(rng: SplitMix64, n: int, lo, hi, sigma: float, centre=None):
+    """Gaussian about the cube centre (or `centre`), redrawn until inside the cube."""
     lo = np.asarray(lo, float)
     hi = np.asarray(hi, float)
-    c = 0.5 * (lo + hi)
+    c = 0.5 * (lo + hi) if centre is None else np.asarray(centre, float)
     out = np.empty((n, 3))
     filled = 0
     while filled < n:
@@ -116,6 +116,36 @@ def three_layer(per_layer, seed: int = 0, clustered_fraction: float = 0.0, sigma
         x, y, z, q = _uniform_block(rng, n - nc, lo, hi)
         if nc:
             gx, gy, gz, gq = _gauss_block(rng, nc, lo, hi, sigma)
+            x, y, z, q = (np.concatenate(a) for a in ((x, gx), (y, gy), (z, gz), (q, gq)))
+        xs.append(x); ys.append(y); zs.append(z); qs.append(q); ls.append(np.full(n, l, np.int32))
+    return LayeredProblem(np.array(eps, float), np.array(lam, float), np.array(D3, float),
+                          np.concatenate(xs), np.concatenate(ys), np.concatenate(zs), np.concatenate(qs),
+                          np.concatenate(ls))
+
+
+def three_layer_interface_clusters(per_layer, seed: int = 0, sigma: float = 0.04, gap: float = 0.02,
+                                   eps=EPS3, lam=LAM3) -> LayeredProblem:
+    """Strongly clustered charges next to the interfaces (adaptive-tree
+    inputs): per layer half uniform in the layer's slab of the unit square
+    column, |x|, |y| <= 1/2, kept `gap` away from every interface (the top
+    and bottom slabs 1.08 thick), half Gaussian (sigma) about (0.1, -0.1,
+    z_c) with z_c = 0.05 + gap/2 from the interface below the top layer,
+    above and below the middle layer's nearest interface, redrawn until
+    inside the slab."""
+    if np.isscalar(per_layer):
+        per_layer = (int(per_layer),) * 3
+    rng = SplitMix64(seed)
+    top, mid = D3[0], D3[1]
+    slabs = [(top + gap, top + 1.1), (mid + gap, top - gap), (mid - 1.1, mid - gap)]
+    centres = [top + 0.05 + gap / 2, top - 0.05 - gap / 2, mid - 0.05 - gap / 2]
+    xs, ys, zs, qs, ls = [], [], [], [], []
+    for l, n in enumerate(per_layer):
+        lo = (-0.5, -0.5, slabs[l][0])
+        hi = (0.5, 0.5, slabs[l][1])
+        nc = n // 2
+        x, y, z, q = _uniform_block(rng, n - nc, lo, hi)
+        if nc:
+            gx, gy, gz, gq = _gauss_block(rng, nc, lo, hi, sigma, centre=(0.1, -0.1, centres[l]))
             x, y, z, q = (np.concatenate(a) for a in ((x, gx), (y, gy), (z, gz), (q, gq)))
         xs.append(x); ys.append(y); zs.append(z); qs.append(q); ls.append(np.full(n, l, np.int32))
     return LayeredProblem(np.array(eps, float), np.array(lam, float), np.array(D3, float),
