@@ -102,6 +102,20 @@ typedef struct {
     void* (*alloc)(size_t bytes, void* alloc_user);
     void (*free)(void* ptr, void* alloc_user);
     void* alloc_user;
+    /* Tree form (Sec. 3.5, closing remarks on adaptive trees).  0 (default):
+     * uniform trees, every leaf of an FMM at its depth (see lpb_build_tree).
+     * 1: adaptive trees: each point set (a layer's charges; a layer side's
+     * targets or equivalent polarization sources) divides a box while it holds
+     * more than leaf_cap points, down to level 12; the lists add W-list pairs
+     * (a finer source box's multipole expansion evaluated at a coarser leaf's
+     * targets, M2P) and X-list pairs (a coarser leaf's sources formed into a
+     * finer target box's local expansion, P2L).  Reaction M2P / P2L use point
+     * operators from the F~ and L rows of eq. coefintable, whose Sommerfeld
+     * tables combine the forward (eq. recurrence1) and backward
+     * (eq. backwardrecurrence1) recurrences; they are generated with the
+     * translation operators (FP64) and kept, K doubles per (point, box)
+     * pair.  Results converge to the same potential as on uniform trees. */
+    int adaptive;
 } lpb_options;
 
 typedef struct {
@@ -118,7 +132,7 @@ typedef struct {
     double t_eval_ms;       /* last lpb_evaluate, stream time between its first and last kernel */
     /* per-stage stream time of the last evaluate when options.timing = 1:
      * [0] charge gather + clears, [1] P2M, [2] M2M, [3] tiled M2L (free space),
-     * [4] list M2L (reaction, deep levels), [5] L2L, [6] L2P,
+     * [4] list M2L (reaction, deep levels) and X-list P2L, [5] L2L, [6] L2P and W-list M2P,
      * [7] free-space near field, [8] reaction near field, [9] component sum */
     double t_stage_ms[10];
     int tile_schedule;      /* schedule and form chosen for the tiled M2L: bit 0 = 0 linear, 1 blocks of one
@@ -140,6 +154,10 @@ typedef struct {
      * L2L child links, distinct operators of the V-list pairs outside the
      * tiled levels (their products run in the batched kernel) */
     int64_t n_p2m_points, n_l2p_points, n_m2m_links, n_l2l_links, n_m2l_list_ops;
+    /* adaptive trees (options.adaptive = 1): W-list and X-list box pairs, the
+     * target evaluations of the W-list pairs (M2P) and source formations of
+     * the X-list pairs (P2L), and the reaction point operators among them */
+    int64_t n_w_pairs, n_x_pairs, n_w_points, n_x_points, n_point_ops;
 } lpb_stats;
 
 /* Fill *opt with the defaults listed above.  Never fails. */
@@ -232,8 +250,9 @@ lpb_status lpb_get_stats(const lpb_ctx* ctx, lpb_stats* stats);
  * [0, 65535], shifted right by 16 - H, with w = x - cx, y - cy and, for free
  * space, z - cz; for a reaction component w_z = +tau (targets) or -tau'
  * (sources), and the z cell is mirrored (2^H - 1 - c) when a = 2; bits
- * interleaved x, y, z from the most significant level down); *nt, *ns
- * receive the counts.  Host memory. */
+ * interleaved x, y, z from the most significant level down); on adaptive
+ * trees the key is at the leaf's own level L (in place of H) and carries L in
+ * bits 58-61; *nt, *ns receive the counts.  Host memory. */
 lpb_status lpb_fmm_info(const lpb_ctx* ctx, int sys, int fmm, int* desc, double* root, int64_t* nt, int64_t* ns,
                         uint64_t* tkeys, uint64_t* skeys);
 

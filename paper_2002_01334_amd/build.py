@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "liblpbfmm.so")
 # split over several translation units so that they compile in parallel)
 HIP_SOURCES = ["lpb_m2l_orbit_d.hip", "lpb_m2l_orbit_c.hip", "lpb_m2l_orbit_b.hip", "lpb_m2l_orbit_a.hip",
                "lpb_m2l_tile_kb32.hip", "lpb_m2l_tile_kb64.hip", "lpb_m2l_tile.hip", "lpb_eval.hip",
-               "lpb_p2m_l2p.hip", "lpb_opgen.hip", "lpb_tree_dev.hip"]
+               "lpb_p2m_l2p.hip", "lpb_opgen.hip", "lpb_tree_dev.hip", "lpb_adaptive.hip"]
 CXX_SOURCES = ["lpb_plan.cpp", "lpb_capi.cpp"]
 ARCH = "gfx950"
 # packed FP32 instructions are disabled for all device code

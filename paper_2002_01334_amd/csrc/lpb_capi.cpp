@@ -333,6 +333,30 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
     UP(tl_fmm, P.tl_fmm);
     UP(tl_h, P.tl_h);
     UP(tl_ctr, P.tl_ctr);
+    UP(sl_lv, P.sl_lv);
+    UP(tl_lv, P.tl_lv);
+    {
+        // adaptive trees: W-list (M2P) per target leaf, X-list (P2L) per target box
+        std::vector<int> wl;
+        for (size_t i = 0; i + 1 < P.w_ptr.size(); ++i)
+            if (P.w_ptr[i + 1] > P.w_ptr[i]) wl.push_back((int)i);
+        UP(w_leaves, wl);
+        A.n_w_leaves = (int)wl.size();
+        A.n_x_boxes = (int)P.x_box_le.size();
+    }
+    UP(w_ptr, P.w_ptr);
+    UP(w_fmm, P.w_fmm);
+    UP(w_me, P.w_me);
+    UP(w_lv, P.w_lv);
+    UP(w_ctr, P.w_ctr);
+    UP(w_vec, P.w_vec);
+    UP(x_box_le, P.x_box_le);
+    UP(x_box_lv, P.x_box_lv);
+    UP(x_box_ptr, P.x_box_ptr);
+    UP(x_box_ctr, P.x_box_ctr);
+    UP(x_fmm, P.x_fmm);
+    UP(x_sl, P.x_sl);
+    UP(x_vec, P.x_vec);
     UP(bw_term_ptr, P.bw_term_ptr);
     UP(bw_op, P.bw_op);
     UP(bw_src, P.bw_src);
@@ -591,6 +615,7 @@ lpb_status build_and_upload(lpb_ctx* c)
     P.p = c->opt.p;
     P.K = (P.p + 1) * (P.p + 1);
     P.leaf_cap = c->opt.leaf_cap;
+    P.adaptive = c->opt.adaptive;
     int st = 0;
     // the points go through the device builder (its buffers are the
     // context's, returned when it goes out of scope)
@@ -630,6 +655,11 @@ lpb_status build_and_upload(lpb_ctx* c)
         c->stats.n_m2l_list_ops = (int64_t)(std::unique(ops.begin(), ops.end()) - ops.begin());
         c->stats.n_p2m_points = P.n_spts;
         c->stats.n_l2p_points = P.n_tpts;
+        c->stats.n_w_pairs = P.n_w_pairs;
+        c->stats.n_x_pairs = P.n_x_pairs;
+        c->stats.n_w_points = P.n_w_points;
+        c->stats.n_x_points = P.n_x_points;
+        c->stats.n_point_ops = (int64_t)P.pt_ops.size();
     }
     c->stats.t_build_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return LPB_OK;
@@ -717,6 +747,29 @@ lpb_status generate_operators_impl(lpb_ctx* c)
     } else {
         if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_swz * g.KP * g.KP, &g.d_swz64)) != LPB_OK) return s;
     }
+    // reaction point operators of adaptive trees (kept for the evaluations)
+    g.n_pt = (int)P.pt_ops.size();
+    g.d_pt_ops = nullptr;
+    g.d_pt_vec = nullptr;
+    g.pt_f32 = c->opt.precision == LPB_MIXED;
+    if (g.n_pt > 0) {
+        PointOp* dpo;
+        if ((s = upload(c, c->op_bufs, P.pt_ops, &dpo)) != LPB_OK) return s;
+        g.d_pt_ops = dpo;
+        if ((s = dalloc<double>(c, c->op_bufs, (size_t)g.n_pt * K, &g.d_pt_vec)) != LPB_OK) return s;
+        auto coords = [&](const auto& A) {
+            const void* t[6] = {A.t_ux, A.t_uy, A.t_uz, A.t_lx, A.t_ly, A.t_lz};
+            const void* u[6] = {A.s_ux, A.s_uy, A.s_uz, A.s_lx, A.s_ly, A.s_lz};
+            for (int d = 0; d < 6; ++d) {
+                g.t_u[d] = t[d];
+                g.s_u[d] = u[d];
+            }
+            g.tl_ctr = A.tl_ctr;
+            g.sl_ctr = A.sl_ctr;
+        };
+        if (c->opt.precision == LPB_MIXED) coords(c->a32);
+        else coords(c->a64);
+    }
     HIPCHK(c, hipMemsetAsync(g.d_flag, 0, sizeof(int), c->stream));
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));
     HIPCHK(c, opgen_run(g, c->stream));
@@ -733,6 +786,8 @@ lpb_status generate_operators_impl(lpb_ctx* c)
     // FP64 master copy is no longer needed
     for (auto& b : c->op_bufs)
         if (b.ptr == (void*)g.d_pool) free_buf(c, b);
+    c->a32.pt_vec = g.d_pt_vec;
+    c->a64.pt_vec = g.d_pt_vec;
     if (c->opt.precision == LPB_MIXED) {
         c->a32.pool_swz = g.d_swz32;
         c->a32.pool_orb = g.d_orb32;
@@ -909,6 +964,7 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (o.autotune < 0 || o.autotune > 2) return fail(nullptr, LPB_EINVAL, "autotune must be 0, 1 or 2");
     if (o.schedule < 0 || (o.schedule >> 4) > 7)
         return fail(nullptr, LPB_EINVAL, "schedule codes out of range");
+    if (o.adaptive != 0 && o.adaptive != 1) return fail(nullptr, LPB_EINVAL, "adaptive must be 0 or 1");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(nullptr, LPB_EDEVICE, "no HIP device available");
@@ -1152,22 +1208,26 @@ lpb_status lpb_fmm_info(const lpb_ctx* c, int sys, int fmm, int* desc, double* r
     // tree), in the FMM's original orientation, ordered by charge index
     // (the charge indices of the tree's points come from the device)
     auto gather = [&](const TreeDesc& T, const std::vector<int>& lstart, const int* dcidx,
-                      const std::vector<uint64_t>& lcell, uint64_t* out) {
+                      const std::vector<uint64_t>& lcell, const std::vector<int>& llv, uint64_t* out) {
         if (T.nleaf == 0) return true;
         const int p0 = lstart[T.leaf0], p1 = lstart[T.leaf0 + T.nleaf];
         std::vector<int> cidx(p1 - p0);
         if (hipMemcpy(cidx.data(), dcidx + p0, cidx.size() * sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return false;
         std::vector<std::pair<int, uint64_t>> v;
         for (int l = T.leaf0; l < T.leaf0 + T.nleaf; ++l)
-            for (int j = lstart[l]; j < lstart[l + 1]; ++j) v.push_back({cidx[j - p0], leaf_key(lcell[l], F.H, F.flip)});
+            for (int j = lstart[l]; j < lstart[l + 1]; ++j) {
+                const uint64_t key = P.adaptive ? leaf_key(lcell[l], llv[l], F.flip) | ((uint64_t)llv[l] << 58)
+                                                : leaf_key(lcell[l], F.H, F.flip);
+                v.push_back({cidx[j - p0], key});
+            }
         std::sort(v.begin(), v.end());
         for (size_t i = 0; i < v.size(); ++i) out[i] = v[i].second;
         return true;
     };
     const bool mixed = c->opt.precision == LPB_MIXED;
-    if (tkeys && !gather(P.trees[F.tgt_tree], P.tl_start, mixed ? c->a32.t_cidx : c->a64.t_cidx, P.tl_cell, tkeys))
+    if (tkeys && !gather(P.trees[F.tgt_tree], P.tl_start, mixed ? c->a32.t_cidx : c->a64.t_cidx, P.tl_cell, P.tl_lv, tkeys))
         return LPB_EDEVICE;
-    if (skeys && !gather(P.trees[F.src_tree], P.sl_start, mixed ? c->a32.s_cidx : c->a64.s_cidx, P.sl_cell, skeys))
+    if (skeys && !gather(P.trees[F.src_tree], P.sl_start, mixed ? c->a32.s_cidx : c->a64.s_cidx, P.sl_cell, P.sl_lv, skeys))
         return LPB_EDEVICE;
     return LPB_OK;
 }

@@ -71,6 +71,20 @@ struct EvalArgs {
     const T* pool_orb;
     // block -> work schedules of the matrix-core kernels (see sched_index)
     int tile_sched, batch_sched;
+    // leaf levels (the scale of a leaf's expansion), and the W- and X-lists
+    // of adaptive trees (see Plan): target leaves with W entries, X target
+    // boxes, reaction point operators (K doubles each)
+    const int *sl_lv, *tl_lv;
+    int n_w_leaves, n_x_boxes;
+    const int* w_leaves;
+    const int *w_ptr, *w_fmm, *w_me, *w_lv;
+    const double* w_ctr;
+    const int64_t* w_vec;
+    const int *x_box_le, *x_box_lv, *x_box_ptr;
+    const double* x_box_ctr;
+    const int *x_fmm, *x_sl;
+    const int64_t* x_vec;
+    const double* pt_vec;
 };
 
 struct EvalSched {
@@ -103,6 +117,11 @@ template <int P>
 void launch_m2l_orbit_p(const EvalArgs<float>& A, hipStream_t st);   // kOrbitMinP <= P <= kOrbitMaxP
 template <typename T>
 bool launch_m2l_tile_kb(const EvalArgs<T>& A, bool wide, hipStream_t st);
+// W-list M2P and X-list P2L of adaptive trees (nothing is launched without them)
+template <typename T>
+void launch_m2p(const EvalArgs<T>& A, hipStream_t st);
+template <typename T>
+void launch_p2l(const EvalArgs<T>& A, hipStream_t st);
 void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st);
 void launch_l2p_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st);
 

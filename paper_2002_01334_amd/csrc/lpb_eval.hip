@@ -51,7 +51,7 @@ __global__ void __launch_bounds__(64) k_p2m(EvalArgs<T> A, int CH)
     T* gl = coef + (size_t)K * CS;                             // [p+1][CH]
     const int lane = threadIdx.x;
     const double* __restrict__ tb = A.bes_tab;
-    const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
+    const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + A.sl_lv[leaf]) * (LPB_MAX_P + 1);
     const int s0 = A.sl_start[leaf], s1 = A.sl_start[leaf + 1];
     T acc[8];
 #pragma unroll
@@ -417,7 +417,7 @@ __global__ void __launch_bounds__(64) k_l2p(EvalArgs<T> A, int CH)
     const int lane = threadIdx.x;
     if (lane >= CH) return;
     const double* __restrict__ tb = A.bes_tab;
-    const double* __restrict__ ith = A.ith_t + ((size_t)A.tl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
+    const double* __restrict__ ith = A.ith_t + ((size_t)A.tl_fmm[leaf] * (kMaxDepth + 1) + A.tl_lv[leaf]) * (LPB_MAX_P + 1);
     const T* __restrict__ Ls = A.le + (size_t)le * A.KP;
     const T* __restrict__ amm_t = A.sh_amm;
     const T* __restrict__ al_t = A.sh_alpha;
@@ -835,6 +835,8 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
         hipError_t e = hipStreamWaitEvent(st, fk->join, 0);
         if (e != hipSuccess) return e;
     }
+    // X-lists of adaptive trees: local expansions from coarser leaves' sources
+    if (far) launch_p2l<T>(A, st);
     LPB_MARK(5);
     for (int l = 0; l <= kMaxDepth && far; ++l) launch_batched<T>(A, S.bl2l_lv[l], S.bl2l_lv[l + 1], A.le, A.n_le, A.le, 1, st);
     LPB_MARK(6);
@@ -847,6 +849,8 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
             hipLaunchKernelGGL(k_l2p<T>, dim3(S.n_l2p), dim3(64), sm, st, A, 64);
         }
     }
+    // W-lists of adaptive trees: finer boxes' expansions at the leaves' targets
+    if (far) launch_m2p<T>(A, st);
     // near field
     LPB_MARK(7);
     if (near && S.n_p2p_free > 0) {

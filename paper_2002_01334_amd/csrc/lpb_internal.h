@@ -130,6 +130,18 @@ struct RKey {
     double S;             // box side (scaling length of the paper's scaled integrals)
 };
 
+// Reaction point operator (adaptive trees, Sec. 3.5 closing remarks): for
+// kind 0 (M2P) the row that evaluates the scaled ME of a source box at one
+// target point, for kind 1 (P2L) the scaled LE of a target box due to one
+// unit source point; K doubles at `out`.  pt: the point (index into the
+// target or source arrays), leaf: its leaf; (bx, by, bz): the box centre and
+// h its side, canonical frame.
+struct PointOp {
+    int kind, fmm, pt, leaf;
+    double bx, by, bz, h;
+    int64_t out;
+};
+
 // Tiled free-space M2L: one record per (free FMM, level) with dense box grids,
 // and tiles of 64 target boxes sharing a child octant (so that all of them
 // have the same 189 V-list offsets and operators).
@@ -164,6 +176,7 @@ struct Plan {
     std::vector<double> sl_h, tl_h;                       // leaf box side
     std::vector<double> sl_ctr, tl_ctr;                   // leaf centres (canonical local frame), 3 per leaf
     std::vector<uint64_t> sl_cell, tl_cell;               // leaf cells (canonical, diagnostics)
+    std::vector<int> sl_lv, tl_lv;                        // leaf levels (all H on uniform trees)
     // boxes
     int n_me = 0, n_le = 0;
     // M2L: CSR by target LE box
@@ -183,6 +196,23 @@ struct Plan {
     std::vector<int> p2p_ptr, p2p_src;
     std::vector<int> rp_ptr, rp_fmm, rp_src;
     int64_t n_p2p_pairs = 0, n_react_p2p_pairs = 0, n_m2l_pairs = 0, n_m2l_tile_pairs = 0;
+    // adaptive trees: W-list (M2P) CSR by target leaf, entries (FMM, source
+    // ME box, its level, its centre in the canonical frame, first point
+    // operator or -1); X-list (P2L) per target LE box (w_* analogues x_box_*)
+    // with entries (FMM, source leaf, first point operator or -1).  Reaction
+    // entries evaluate precomputed point operators (one K-vector per target
+    // point of the leaf, or per source point of the leaf); free-space entries
+    // the closed forms.
+    int adaptive = 0;
+    std::vector<int> w_ptr, w_fmm, w_me, w_lv;
+    std::vector<double> w_ctr;
+    std::vector<int64_t> w_vec;
+    std::vector<int> x_box_le, x_box_lv, x_box_ptr;
+    std::vector<double> x_box_ctr;
+    std::vector<int> x_fmm, x_sl;
+    std::vector<int64_t> x_vec;
+    std::vector<PointOp> pt_ops;   // reaction point operators to generate
+    int64_t n_w_pairs = 0, n_x_pairs = 0, n_w_points = 0, n_x_points = 0;
     // operators
     std::vector<OpDesc> ops;
     std::vector<RKey> rkeys;
@@ -226,6 +256,12 @@ public:
     // their leaf centres.  False with msg set on failure.
     virtual bool leaves(int handle, int H, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_start,
                         std::string& msg) = 0;
+    // Adaptive leaves: boxes divided while they hold more than cap points
+    // (down to kMaxDepth); leaf_key at each leaf's own level leaf_lv, in
+    // Morton order, leaf_start its first point; computes the points' offsets
+    // from their leaf centres.  False with msg set on failure.
+    virtual bool leaves_adaptive(int handle, int cap, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
+                                 std::vector<int>& leaf_start, std::string& msg) = 0;
     // lpb_status of the last failure (LPB_ENOMEM or LPB_EDEVICE)
     virtual int failure() const = 0;
 };

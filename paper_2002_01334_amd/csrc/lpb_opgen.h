@@ -38,6 +38,15 @@ struct OpgenInputs {
     const int* d_orb_ops;
     const int* d_rowmap;
     float* d_orb32;
+    // reaction point operators of adaptive trees (K doubles each at
+    // PointOp::out): the points' offsets from their leaf centres (x, y, z;
+    // with FP32 coordinates also the low parts), the leaf centres
+    int n_pt;
+    const PointOp* d_pt_ops;
+    bool pt_f32;
+    const void *t_u[6], *s_u[6];
+    const double *tl_ctr, *sl_ctr;
+    double* d_pt_vec;
 };
 
 hipError_t opgen_upload_constants();

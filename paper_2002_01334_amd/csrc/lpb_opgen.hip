@@ -480,6 +480,208 @@ __global__ void k_swizzle_rows(int K, int KP, int NRB, int nsw, const int* __res
     out[idx] = (float)v;
 }
 
+// ---- reaction point operators of adaptive trees ---------------------------
+// (Sec. 3.5, closing remarks on adaptive trees.)  In the canonical frame (a =
+// 1 form) for one point and one box of side S:
+//   M2P (W-list; target r, source box centre c):  u~(r) = sum M_{nu mu} F~_{nu mu},
+//     F~_{nu mu} = e^{i mu phi} I_{00,nu mu}(rho, z, z_c) / sqrt(4 pi),  (rho, phi) of r - c;
+//   P2L (X-list; image r', target box centre c):  L_nm = sqrt(4 pi) (-1)^n e^{-i m phi} I_{nm,00}(rho, z_c, z'),
+//     (rho, phi) of c - r'  (the F~ and L rows of eq. coefintable, the L row being
+//     the T row of a unit charge at r': its ME about r' is M_00 = sqrt(4 pi)).
+// I from the D table (eq. metoletableform) and the scaled integrals
+// S^n Sc_{nm,ij} up to n = p + 2 (the largest index the rows (0,0) and
+// columns (0,0) reach).  rho may be below S here, so the table mixes the two
+// recurrences: initial values by quadrature for m = 0 and 1 (all n) and for
+// the row n = p + 2, the forward recurrence (eq. recurrence1) wherever its
+// bound 2m/a_{n+m} < rho/S holds, the backward recurrence (eq.
+// backwardrecurrence1) for the other entries, row by row down; only entries
+// with n - m odd enter I.  Output in the real form of the expansions (the
+// scaled ME Mh = M / (4 pi i_nu(lam_s S)) is dotted with the M2P row; the
+// P2L vector is the scaled Lh = i_n(lam_t S) L of a unit charge).
+#define LPB_PTN (LPB_MAX_P + 3)
+#define LPB_PTH ((LPB_PTN + 1) / 2)
+template <typename T>
+__global__ void __launch_bounds__(64) k_point_ops(int p, const PointOp* __restrict__ pops, const FmmDev* __restrict__ fmms,
+                                                  const Medium* __restrict__ media, const int* __restrict__ rf_index,
+                                                  const double* __restrict__ dtab, const T* __restrict__ tx,
+                                                  const T* __restrict__ ty, const T* __restrict__ tz,
+                                                  const T* __restrict__ tlx, const T* __restrict__ tly,
+                                                  const T* __restrict__ tlz, const T* __restrict__ sx,
+                                                  const T* __restrict__ sy, const T* __restrict__ sz,
+                                                  const T* __restrict__ slx, const T* __restrict__ sly,
+                                                  const T* __restrict__ slz, const double* __restrict__ tl_ctr,
+                                                  const double* __restrict__ sl_ctr, double tol,
+                                                  double* __restrict__ out, int* __restrict__ flag)
+{
+    __shared__ double panels[LPB_MAXPANEL + 1];
+    __shared__ int s_np;
+    __shared__ double tab[2][LPB_PTN][LPB_PTN];
+    __shared__ double sc[LPB_MAX_P + 1], sinv[LPB_PTN];
+    const PointOp& op = pops[blockIdx.x];
+    const FmmDev& F = fmms[op.fmm];
+    const Medium& Md = media[F.medium];
+    const int K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2, SM = p + 2;
+    const int N = p + 2;
+    const int lane = threadIdx.x;
+    // the point (canonical frame) and the geometry of the pair
+    double px, py, pz;
+    if (op.kind == 0) {
+        px = tl_ctr[3 * op.leaf] + (double)tx[op.pt] + (tlx ? (double)tlx[op.pt] : 0.0);
+        py = tl_ctr[3 * op.leaf + 1] + (double)ty[op.pt] + (tly ? (double)tly[op.pt] : 0.0);
+        pz = tl_ctr[3 * op.leaf + 2] + (double)tz[op.pt] + (tlz ? (double)tlz[op.pt] : 0.0);
+    } else {
+        px = sl_ctr[3 * op.leaf] + (double)sx[op.pt] + (slx ? (double)slx[op.pt] : 0.0);
+        py = sl_ctr[3 * op.leaf + 1] + (double)sy[op.pt] + (sly ? (double)sly[op.pt] : 0.0);
+        pz = sl_ctr[3 * op.leaf + 2] + (double)sz[op.pt] + (slz ? (double)slz[op.pt] : 0.0);
+    }
+    const double dx = op.kind == 0 ? px - op.bx : op.bx - px, dy = op.kind == 0 ? py - op.by : op.by - py;
+    const double rho = sqrt(dx * dx + dy * dy);
+    const double phi = rho > 0.0 ? atan2(dy, dx) : 0.0;
+    const double zt = op.kind == 0 ? pz : op.bz, zs = op.kind == 0 ? op.bz : pz;
+    const double S = op.h, c = zt - zs;
+    if (lane == 0) {
+        s_np = make_panels(rho, c, N, medium_lam_min(Md), medium_dmax(Md), tol, panels, LPB_MAXPANEL);
+        if (s_np < 0) atomicOr(flag, 1);
+    }
+    __syncthreads();
+    const int np = s_np;
+    // per lane: initial values of two tables (ij = 00 and, for M2P, 01; for
+    // P2L, 10): m = 0 at odd n, m = 1 at even n >= 2, row N at m >= 2 with N - m odd
+    double a0[2][LPB_PTH], a1[2][LPB_PTH], ar[2][LPB_PTH];
+    for (int q = 0; q < 2; ++q)
+        for (int k = 0; k < LPB_PTH; ++k) a0[q][k] = a1[q][k] = ar[q][k] = 0.0;
+    const double lt = F.lam_t, ls = F.lam_s;
+    for (int k = lane; k < (np > 0 ? np : 0) * LPB_NGL; k += 64) {
+        const int pn = k / LPB_NGL, qd = k % LPB_NGL;
+        const double x0 = panels[pn], x1 = panels[pn + 1];
+        const double t = x0 + 0.5 * (x1 - x0) * (c_gl_x[qd] + 1.0);
+        const double w = 0.5 * (x1 - x0) * c_gl_w[qd];
+        const double lz = sqrt(lt * lt + t * t), lzp = sqrt(ls * ls + t * t);
+        const double sg = sigma_transmission(Md.L, Md.eps, Md.lam, Md.d, F.l, F.lp, F.a, F.b, t);
+        const double f0 = w * exp(-lz * zt + lzp * zs) * sg / lz;
+        const double f[2] = {f0, op.kind == 0 ? f0 * ls / lzp : f0 * lt / lz};
+        const double j0v = j0(t * rho), j1v = j1(t * rho);
+        const double ts = t * S;
+        double pw = 1.0;
+        for (int n = 0; n <= N; ++n) {
+            for (int q = 0; q < 2; ++q) {
+                if (n & 1) a0[q][n >> 1] += f[q] * pw * j0v / c_fact[n];
+                else if (n >= 2) a1[q][(n >> 1) - 1] += f[q] * pw * j1v / sqrt(c_fact[n + 1] * c_fact[n - 1]);
+            }
+            if (n < N) pw *= ts;
+        }
+        if (rho > 0.0)
+            for (int m = 2; m <= N; ++m) {
+                if (((N - m) & 1) == 0) continue;
+                const double jm = jn(m, t * rho) * pw / sqrt(c_fact[N + m] * c_fact[N - m]);
+                for (int q = 0; q < 2; ++q) ar[q][m >> 1] += f[q] * jm;
+            }
+    }
+    // wave reductions (one wave per block), in a fixed order
+    for (int q = 0; q < 2; ++q)
+        for (int k = 0; k < LPB_PTH; ++k)
+            for (int off = 32; off > 0; off >>= 1) {
+                a0[q][k] += __shfl_xor(a0[q][k], off, 64);
+                a1[q][k] += __shfl_xor(a1[q][k], off, 64);
+                ar[q][k] += __shfl_xor(ar[q][k], off, 64);
+            }
+    if (lane == 0) {
+        for (int q = 0; q < 2; ++q) {
+            double(*Tq)[LPB_PTN] = tab[q];
+            bool done[LPB_PTN][LPB_PTN];
+            for (int n = 0; n <= N; ++n)
+                for (int m = 0; m <= N; ++m) {
+                    Tq[n][m] = 0.0;
+                    done[n][m] = false;
+                }
+            for (int n = 1; n <= N; n += 2) { Tq[n][0] = a0[q][n >> 1]; done[n][0] = true; }
+            for (int n = 2; n <= N; n += 2) { Tq[n][1] = a1[q][(n >> 1) - 1]; done[n][1] = true; }
+            if (rho > 0.0) {
+                for (int m = 2; m <= N; ++m)
+                    if ((N - m) & 1) { Tq[N][m] = ar[q][m >> 1]; done[N][m] = true; }
+                const double x = rho / S;
+                // forward, increasing m: (n, m+1) from (n-1, m) and (n, m-1), n - m even
+                for (int m = 1; m < N; ++m)
+                    for (int n = m + 1; n < N; ++n) {
+                        if (((n - m) & 1) != 0) continue;
+                        const double anm = sqrt((double)(n + m) * (n + m + 1));
+                        if (!(2.0 * m / anm < x) || !done[n - 1][m] || !done[n][m - 1]) continue;
+                        const double amn = sqrt((double)(n - m) * (n - m + 1));
+                        Tq[n][m + 1] = 2.0 * m / anm / x * Tq[n - 1][m] - amn / anm * Tq[n][m - 1];
+                        done[n][m + 1] = true;
+                    }
+                // backward, down from the row N: (n-1, m) from (n, m+1) and (n, m-1)
+                for (int n = N; n >= 2; --n)
+                    for (int m = 1; m <= n - 1; ++m) {
+                        if ((((n - 1) - m) & 1) == 0 || done[n - 1][m]) continue;
+                        const double anm = sqrt((double)(n + m) * (n + m + 1));
+                        const double amn = sqrt((double)(n - m) * (n - m + 1));
+                        Tq[n - 1][m] = anm / (2.0 * m) * x * Tq[n][m + 1] + amn / (2.0 * m) * x * Tq[n][m - 1];
+                        done[n - 1][m] = true;
+                    }
+            }
+        }
+        double buf[LPB_MAX_P + 2];
+        bessel_i_all(p, (op.kind == 0 ? ls : lt) * S, buf);
+        for (int n = 0; n <= p; ++n) sc[n] = buf[n];
+        for (int n = 0; n <= N; ++n) sinv[n] = pow(S, -(double)n);
+    }
+    __syncthreads();
+    const double* D = dtab + (size_t)rf_index[op.fmm] * Kp * K * SM;
+    double* o = out + op.out;
+    const double r4pi = 1.0 / sqrt(4.0 * LPB_PI);
+    if (op.kind == 0) {
+        // row (0,0) of D; columns (nu, +-mu); q = table of parity j = (nu + mu) & 1
+        for (int e = lane; e < Kp; e += 64) {
+            int nu = 0;
+            while ((nu + 1) * (nu + 2) / 2 <= e) ++nu;
+            const int mu = e - nu * (nu + 1) / 2;
+            const int q = (nu + mu) & 1;
+            const int rn = (nu + mu) / 2, smax = nu - rn;
+            double Fr[2] = {0.0, 0.0}, Fi[2] = {0.0, 0.0};
+            for (int sgn = 0; sgn < 2; ++sgn) {
+                if (sgn && mu == 0) continue;
+                const int m2 = sgn ? -mu : mu;
+                const double* Ds = D + ((size_t)0 * K + jk(nu, m2)) * SM;
+                double I = 0.0;
+                for (int s = 0; s <= smax; ++s) {
+                    const int Nn = mu + 2 * s + 1;
+                    I += Ds[s] * tab[q][Nn][mu] * sinv[Nn];
+                }
+                if (m2 < 0) I *= dsgn(mu);
+                Fr[sgn] = cos(m2 * phi) * I * r4pi;
+                Fi[sgn] = sin(m2 * phi) * I * r4pi;
+            }
+            const double f = 4.0 * LPB_PI * sc[nu];
+            if (mu == 0) {
+                o[ire(nu, 0)] = f * Fr[0];
+            } else {
+                o[ire(nu, mu)] = f * (Fr[0] + dsgn(mu) * Fr[1]);
+                o[iim(nu, mu)] = f * (-Fi[0] + dsgn(mu) * Fi[1]);
+            }
+        }
+    } else {
+        // rows (n, m >= 0) of D, column (0,0); q = table of parity i = (n + m) & 1
+        for (int e = lane; e < Kp; e += 64) {
+            int n = 0;
+            while ((n + 1) * (n + 2) / 2 <= e) ++n;
+            const int m = e - n * (n + 1) / 2;
+            const int q = (n + m) & 1;
+            const int rn = (n + m) / 2, smax = n - rn;
+            const double* Ds = D + ((size_t)e * K + jk(0, 0)) * SM;
+            double I = 0.0;
+            for (int s = 0; s <= smax; ++s) {
+                const int Nn = m + 2 * s + 1;
+                I += Ds[s] * tab[q][Nn][m] * sinv[Nn];
+            }
+            I *= dsgn(m);   // Sc_{N,-m} = (-1)^m Sc_{N,m}
+            const double f = sqrt(4.0 * LPB_PI) * dsgn(n) * I * sc[n];
+            o[ire(n, m)] = f * cos(m * phi);
+            if (m > 0) o[iim(n, m)] = -f * sin(m * phi);
+        }
+    }
+}
+
 __global__ void k_to_float(size_t n, const double* __restrict__ a, float* __restrict__ b)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -540,6 +742,22 @@ hipError_t opgen_run(const OpgenInputs& in, hipStream_t st)
         int blocks = (int)((total + 255) / 256);
         hipLaunchKernelGGL(k_dtable, dim3(blocks), dim3(256), 0, st, p, in.n_rf, in.d_rf_list, in.d_fmm, in.d_btab,
                            in.d_dtab);
+    }
+    if (in.n_pt > 0) {
+        if (in.pt_f32)
+            hipLaunchKernelGGL(k_point_ops<float>, dim3(in.n_pt), dim3(64), 0, st, p, in.d_pt_ops, in.d_fmm, in.d_media,
+                               in.d_rf_index, in.d_dtab, (const float*)in.t_u[0], (const float*)in.t_u[1],
+                               (const float*)in.t_u[2], (const float*)in.t_u[3], (const float*)in.t_u[4],
+                               (const float*)in.t_u[5], (const float*)in.s_u[0], (const float*)in.s_u[1],
+                               (const float*)in.s_u[2], (const float*)in.s_u[3], (const float*)in.s_u[4],
+                               (const float*)in.s_u[5], in.tl_ctr, in.sl_ctr, in.quad_tol, in.d_pt_vec, in.d_flag);
+        else
+            hipLaunchKernelGGL(k_point_ops<double>, dim3(in.n_pt), dim3(64), 0, st, p, in.d_pt_ops, in.d_fmm, in.d_media,
+                               in.d_rf_index, in.d_dtab, (const double*)in.t_u[0], (const double*)in.t_u[1],
+                               (const double*)in.t_u[2], (const double*)in.t_u[3], (const double*)in.t_u[4],
+                               (const double*)in.t_u[5], (const double*)in.s_u[0], (const double*)in.s_u[1],
+                               (const double*)in.s_u[2], (const double*)in.s_u[3], (const double*)in.s_u[4],
+                               (const double*)in.s_u[5], in.tl_ctr, in.sl_ctr, in.quad_tol, in.d_pt_vec, in.d_flag);
     }
     if (in.n_rkeys > 0) {
         hipLaunchKernelGGL(k_quad, dim3(in.n_rkeys, 4), dim3(256), 0, st, p, in.d_rkeys, in.d_fmm, in.d_media,

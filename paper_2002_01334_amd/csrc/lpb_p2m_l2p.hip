@@ -110,7 +110,7 @@ __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A, int n_leaves)
     const bool on = w < n_leaves;
     const int leaf = on ? A.p2m_leaves[w] : A.p2m_leaves[2 * blockIdx.x];
     const FmmDev& F = A.fmm[A.sl_fmm[leaf]];
-    const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
+    const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + A.sl_lv[leaf]) * (LPB_MAX_P + 1);
     const int s0 = A.sl_start[leaf], s1 = on ? A.sl_start[leaf + 1] : s0;
     const float hinv = (float)(1.0 / A.sl_h[leaf]);
     float acc[K];
@@ -168,7 +168,7 @@ __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A, int n_leaves)
     __syncthreads();
     if (!on) return;
     const FmmDev& F = A.fmm[A.tl_fmm[leaf]];
-    const double* __restrict__ ith = A.ith_t + ((size_t)A.tl_fmm[leaf] * (kMaxDepth + 1) + F.H) * (LPB_MAX_P + 1);
+    const double* __restrict__ ith = A.ith_t + ((size_t)A.tl_fmm[leaf] * (kMaxDepth + 1) + A.tl_lv[leaf]) * (LPB_MAX_P + 1);
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const float hinv = (float)(1.0 / A.tl_h[leaf]);
     const float* L = Ls[h];

@@ -24,6 +24,7 @@
 #include <array>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 
 #include "lpb_internal.h"
@@ -107,14 +108,28 @@ struct Staging {
     // grouped by target leaf (stable) at the end
     std::vector<std::array<int, 2>> p2p_pairs;
     std::vector<std::array<int, 3>> rp_pairs;
+    // adaptive trees: W-list (target leaf, FMM, source ME box, its level,
+    // centre) and X-list (target LE box, its level, centre, FMM, source leaf)
+    struct WPair { int tl, fmm, me, lv; double c[3]; };
+    struct XPair { int le, lv; double c[3]; int fmm, sl; };
+    std::vector<WPair> w_pairs;
+    std::vector<XPair> x_pairs;
 };
 
 // A point set after the builder's sort: its handle, size and leaves.
 struct PtsInfo {
     int handle = -1, n = 0;
     int counts[kMaxDepth + 1] = {};
-    std::vector<uint64_t> lkey;   // level-H Morton key of each leaf
+    std::vector<uint64_t> lkey;   // Morton key of each leaf at its level (H, or llv on adaptive trees)
     std::vector<int> lstart;      // first point of each leaf
+    std::vector<int> llv;         // adaptive trees: level of each leaf (empty: all at H)
+    int leaf_level(size_t k, int H) const { return llv.empty() ? H : llv[k]; }
+    int max_level() const
+    {
+        int m = 0;
+        for (int v : llv) m = std::max(m, v);
+        return m;
+    }
 };
 
 // smallest level (<= kMaxDepth) at which N <= cap * (non-empty boxes)
@@ -129,18 +144,38 @@ inline int depth_rule(const PtsInfo& V, int cap)
 // to the plan.  rep: the FMM whose lambda and root the tree's operators use.
 void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool target, int rep, int slot, TreeB& T)
 {
-    // the level-l boxes are the distinct prefixes of the leaf keys, in key order
+    // the level-l boxes are the distinct level-l prefixes of the keys of the
+    // leaves at level l or deeper, in key order
     const size_t nl = V.lkey.size();
     T.B.assign(H + 1, BoxSet{});
     for (int lv = 0; lv <= H; ++lv) {
-        const int sh = 3 * (H - lv);
         BoxSet& bs = T.B[lv];
+        auto prefix = [&](size_t i, uint64_t& k) {
+            const int L = V.leaf_level(i, H);
+            if (L < lv) return false;
+            k = V.lkey[i] >> (3 * (L - lv));
+            return true;
+        };
         size_t nb = 0;
-        for (size_t i = 0; i < nl; ++i) nb += (i == 0 || (V.lkey[i - 1] >> sh) != (V.lkey[i] >> sh));
+        {
+            bool have = false;
+            uint64_t prev = 0, k;
+            for (size_t i = 0; i < nl; ++i)
+                if (prefix(i, k)) {
+                    nb += !have || k != prev;
+                    have = true;
+                    prev = k;
+                }
+        }
         bs.init(lv, nb);
+        bool have = false;
+        uint64_t prev = 0;
         for (size_t i = 0; i < nl; ++i) {
-            const uint64_t k = V.lkey[i] >> sh;
-            if (i > 0 && (V.lkey[i - 1] >> sh) == k) continue;
+            uint64_t k;
+            if (!prefix(i, k)) continue;
+            if (have && k == prev) continue;
+            have = true;
+            prev = k;
             const int a = (int)morton_compact3(k >> 2), b = (int)morton_compact3(k >> 1), c = (int)morton_compact3(k);
             bs.insert(a, b, c, (int)bs.mkey.size());
             bs.mkey.push_back(k);
@@ -174,14 +209,18 @@ void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool targe
     std::vector<int>& lstart = target ? P.tl_start : P.sl_start;
     T.leaf0 = target ? (int)P.tl_le.size() : (int)P.sl_me.size();
     for (size_t k = 0; k < nl; ++k) {
-        const int a = T.B[H].ix[k], b = T.B[H].iy[k], c = T.B[H].iz[k];
+        const int L = V.leaf_level(k, H);
+        const uint64_t key = V.lkey[k];
+        const int a = (int)morton_compact3(key >> 2), b = (int)morton_compact3(key >> 1), c = (int)morton_compact3(key);
+        const int box = V.llv.empty() ? (int)k : T.B[L].find(a, b, c);
         if (k > 0) lstart.push_back((int)(g0 + V.lstart[k]));
         std::vector<int>& le = target ? P.tl_le : P.sl_me;
-        le.push_back(H >= 2 ? T.off[H] + (int)k : -1);
+        le.push_back(L >= 2 ? T.off[L] + box : -1);
         (target ? P.tl_fmm : P.sl_fmm).push_back(rep);
         (target ? P.tl_tree : P.sl_tree).push_back(T.id);
-        (target ? P.tl_h : P.sl_h).push_back(hlev(H));
-        for (int v : {a, b, c}) (target ? P.tl_ctr : P.sl_ctr).push_back(centre(H, v));
+        (target ? P.tl_h : P.sl_h).push_back(hlev(L));
+        (target ? P.tl_lv : P.sl_lv).push_back(L);
+        for (int v : {a, b, c}) (target ? P.tl_ctr : P.sl_ctr).push_back(centre(L, v));
         (target ? P.tl_cell : P.sl_cell).push_back(cellkey(a, b, c));
     }
     if (V.n > 0) lstart.push_back((int)(g0 + V.n));
@@ -237,14 +276,25 @@ void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool targe
                     S.bl2l[lv].push_back(std::move(wk));
                 }
         } else {
-            // M2M: 64 parents per work item, one term per child octant
-            for (int c0 = 0; c0 < n; c0 += 64) {
+            // M2M: 64 parents per work item, one term per child octant (on
+            // adaptive trees only the boxes with children: a leaf's expansion
+            // comes from its P2M)
+            std::vector<int> par;
+            for (int k = 0; k < n; ++k) {
+                const int px = T.B[lv].ix[k], py = T.B[lv].iy[k], pz = T.B[lv].iz[k];
+                bool any = false;
+                for (int o = 0; o < 8 && !any; ++o)
+                    any = T.B[lv + 1].find(2 * px + ((o >> 2) & 1), 2 * py + ((o >> 1) & 1), 2 * pz + (o & 1)) >= 0;
+                if (any) par.push_back(k);
+            }
+            const int npar = (int)par.size();
+            for (int c0 = 0; c0 < npar; c0 += 64) {
                 BWork wk;
                 wk.dst.fill(-1);
                 wk.op.assign(opo, opo + 8);
                 wk.src.assign(8 * 64, -1);
-                for (int j = 0; j < 64 && c0 + j < n; ++j) {
-                    int k = c0 + j;
+                for (int j = 0; j < 64 && c0 + j < npar; ++j) {
+                    int k = par[c0 + j];
                     int px = T.B[lv].ix[k], py = T.B[lv].iy[k], pz = T.B[lv].iz[k];
                     wk.dst[j] = T.off[lv] + k;
                     for (int o = 0; o < 8; ++o) {
@@ -255,6 +305,124 @@ void add_tree(Plan& P, Staging& S, const PtsInfo& V, int H, double R, bool targe
                 S.bm2m[lv].push_back(std::move(wk));
             }
         }
+    }
+}
+
+// U-, W- and X-lists of one FMM on adaptive trees, by a dual traversal of its
+// target and source trees from their roots (Sec. 3.5, closing remarks on
+// adaptive trees; the V-list is the same rule as on uniform trees and comes
+// from add_lists).  Pairs of adjacent boxes (levels below 2 count as
+// adjacent: they carry no expansions) are refined: two leaves form a U-list
+// pair; a target leaf and a source box with children: the children not
+// adjacent to the leaf join its W-list (M2P), the others are refined; a
+// source leaf and a target box with children: the children not adjacent to
+// the leaf get the leaf in their X-list (P2L), the others are refined; two
+// boxes with children: adjacent child pairs are refined (the others are
+// V-list pairs).  Every (target, source) pair is then covered exactly once.
+void adaptive_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
+{
+    const FmmDesc& F = P.fmm[fid];
+    const int H = F.H;
+    const double R = F.R;
+    auto hlev = [&](int lv) { return 2.0 * R / (double)(1 << lv); };
+    auto centre = [&](int lv, int i) { return -R + (i + 0.5) * hlev(lv); };
+    const std::vector<BoxSet>& SB = ST.B;
+    const std::vector<BoxSet>& TB = TT.B;
+    const int hs = (int)SB.size() - 1, ht = (int)TB.size() - 1;
+    // leaf index of each box (-1: the box has children)
+    auto leaf_map = [&](const TreeB& T, const std::vector<int>& lvv, const std::vector<uint64_t>& cell) {
+        std::vector<std::vector<int>> m(T.B.size());
+        for (size_t l = 0; l < T.B.size(); ++l) m[l].assign(T.B[l].mkey.size(), -1);
+        for (int i = T.leaf0; i < T.leaf0 + T.nleaf; ++i) {
+            const uint64_t c = cell[i];
+            const int a = (int)((c >> 42) & 0x1fffff), b = (int)((c >> 21) & 0x1fffff), z = (int)(c & 0x1fffff);
+            m[lvv[i]][T.B[lvv[i]].find(a, b, z)] = i;
+        }
+        return m;
+    };
+    const std::vector<std::vector<int>> sleaf = leaf_map(ST, P.sl_lv, P.sl_cell);
+    const std::vector<std::vector<int>> tleaf = leaf_map(TT, P.tl_lv, P.tl_cell);
+    auto child = [](const std::vector<BoxSet>& B, int hb, int lv, int b, int o) {
+        if (lv >= hb) return -1;
+        return B[lv + 1].find(2 * B[lv].ix[b] + ((o >> 2) & 1), 2 * B[lv].iy[b] + ((o >> 1) & 1), 2 * B[lv].iz[b] + (o & 1));
+    };
+    auto adjacent = [&](int lt, int bt, int ls, int bs) {
+        const int L = std::max(lt, ls);
+        const int ct[3] = {TB[lt].ix[bt], TB[lt].iy[bt], TB[lt].iz[bt]};
+        const int cs[3] = {SB[ls].ix[bs], SB[ls].iy[bs], SB[ls].iz[bs]};
+        for (int d = 0; d < 3; ++d) {
+            const int64_t tlo = (int64_t)ct[d] << (L - lt), thi = ((int64_t)(ct[d] + 1) << (L - lt)) - 1;
+            const int64_t slo = (int64_t)cs[d] << (L - ls), shi = ((int64_t)(cs[d] + 1) << (L - ls)) - 1;
+            if (tlo > shi + 1 || slo > thi + 1) return false;
+        }
+        return true;
+    };
+    std::vector<std::array<int, 2>> up;
+    auto u_pair = [&](int tl, int sl) {
+        const int64_t pairs = (int64_t)(P.tl_start[tl + 1] - P.tl_start[tl]) * (P.sl_start[sl + 1] - P.sl_start[sl]);
+        P.n_p2p_pairs += pairs;
+        if (F.kind == 1) P.n_react_p2p_pairs += pairs;
+        up.push_back({tl, sl});
+    };
+    std::function<void(int, int, int, int)> refine = [&](int lt, int bt, int ls, int bs) {
+        const int tl = tleaf[lt][bt], sl = sleaf[ls][bs];
+        if (tl >= 0 && sl >= 0) {
+            u_pair(tl, sl);
+            return;
+        }
+        if (tl >= 0) {
+            for (int o = 0; o < 8; ++o) {
+                const int c = child(SB, hs, ls, bs, o);
+                if (c < 0) continue;
+                if (ls + 1 < 2 || adjacent(lt, bt, ls + 1, c)) refine(lt, bt, ls + 1, c);
+                else {
+                    S.w_pairs.push_back({tl, fid, ST.off[ls + 1] + c, ls + 1,
+                                         {centre(ls + 1, SB[ls + 1].ix[c]), centre(ls + 1, SB[ls + 1].iy[c]),
+                                          centre(ls + 1, SB[ls + 1].iz[c])}});
+                    P.n_w_pairs++;
+                }
+            }
+            return;
+        }
+        if (sl >= 0) {
+            for (int o = 0; o < 8; ++o) {
+                const int c = child(TB, ht, lt, bt, o);
+                if (c < 0) continue;
+                if (lt + 1 < 2 || adjacent(lt + 1, c, ls, bs)) refine(lt + 1, c, ls, bs);
+                else {
+                    S.x_pairs.push_back({TT.off[lt + 1] + c, lt + 1,
+                                         {centre(lt + 1, TB[lt + 1].ix[c]), centre(lt + 1, TB[lt + 1].iy[c]),
+                                          centre(lt + 1, TB[lt + 1].iz[c])},
+                                         fid, sl});
+                    P.n_x_pairs++;
+                }
+            }
+            return;
+        }
+        for (int ot = 0; ot < 8; ++ot) {
+            const int ct = child(TB, ht, lt, bt, ot);
+            if (ct < 0) continue;
+            for (int os = 0; os < 8; ++os) {
+                const int cs = child(SB, hs, ls, bs, os);
+                if (cs < 0) continue;
+                if (lt + 1 < 2 || adjacent(lt + 1, ct, ls + 1, cs)) refine(lt + 1, ct, ls + 1, cs);
+            }
+        }
+    };
+    (void)H;
+    if (!SB.empty() && !TB.empty() && !SB[0].mkey.empty() && !TB[0].mkey.empty()) refine(0, 0, 0, 0);
+    // U-list entries grouped by target leaf; in free space (one point set,
+    // source leaf k = target leaf k) a leaf's own leaf comes first, as the
+    // near-field kernel expects
+    auto rank = [&](const std::array<int, 2>& e) {
+        const bool self = F.kind == 0 && e[1] - ST.leaf0 == e[0] - TT.leaf0;
+        return (int64_t)e[0] * 2 + (self ? 0 : 1);
+    };
+    std::stable_sort(up.begin(), up.end(),
+                     [&](const std::array<int, 2>& a, const std::array<int, 2>& b) { return rank(a) < rank(b); });
+    for (const auto& e : up) {
+        if (F.kind == 0) S.p2p_pairs.push_back({e[0], e[1]});
+        else S.rp_pairs.push_back({e[0], fid, e[1]});
     }
 }
 
@@ -453,6 +621,10 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                         }
                     }
         }
+    }
+    if (P.adaptive) {
+        adaptive_lists(P, S, fid, ST, TT);
+        return;
     }
     // U-lists at the leaf level (target leaf order equals the level-H box order);
     // the target's own box comes first
@@ -668,10 +840,18 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                 *status = pb.failure();
                 return msg;
             }
-            F.H = depth_rule(V, cap);
-            if (!pb.leaves(V.handle, F.H, V.lkey, V.lstart, msg)) {
-                *status = pb.failure();
-                return msg;
+            if (P.adaptive) {
+                if (!pb.leaves_adaptive(V.handle, cap, V.lkey, V.llv, V.lstart, msg)) {
+                    *status = pb.failure();
+                    return msg;
+                }
+                F.H = V.max_level();
+            } else {
+                F.H = depth_rule(V, cap);
+                if (!pb.leaves(V.handle, F.H, V.lkey, V.lstart, msg)) {
+                    *status = pb.failure();
+                    return msg;
+                }
             }
             P.max_depth = std::max(P.max_depth, F.H);
             const int fid = (int)P.fmm.size();
@@ -730,13 +910,14 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                         *status = pb.failure();
                         return msg;
                     }
-                    H = std::max(H, depth_rule(V, cap));
+                    if (!P.adaptive) H = std::max(H, depth_rule(V, cap));
                 }
             }
         // separation: leaves no wider than the smallest tau keep every target and
         // image one box away from the interface plane, so reaction U-lists are
-        // empty (Remark 1); at most 3 levels above the occupancy depth
-        {
+        // empty (Remark 1); at most 3 levels above the occupancy depth.
+        // Adaptive trees divide by occupancy alone, each set on its own.
+        if (!P.adaptive) {
             int hs = 0;
             while (hs < kMaxDepth && 2.0 * R / (double)(1 << hs) > tmin) ++hs;
             hs = std::min(hs, std::min(H + 3, kMaxDepth));
@@ -748,11 +929,15 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                 for (int tg = 0; tg < 2; ++tg) {
                     PtsInfo& V = sets[l][sd][tg];
                     std::string msg;
-                    if (V.handle >= 0 && !pb.leaves(V.handle, H, V.lkey, V.lstart, msg)) {
+                    if (V.handle < 0) continue;
+                    if (P.adaptive ? !pb.leaves_adaptive(V.handle, cap, V.lkey, V.llv, V.lstart, msg)
+                                   : !pb.leaves(V.handle, H, V.lkey, V.lstart, msg)) {
                         *status = pb.failure();
                         return msg;
                     }
+                    if (P.adaptive) H = std::max(H, V.max_level());
                 }
+        if (P.adaptive) P.max_depth = std::max(P.max_depth, H);
         // components in Algorithm 2 order
         std::vector<int> comp_fid;
         for (int a = 1; a <= 2; ++a)
@@ -890,6 +1075,84 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
     P.swz_ops.resize(P.ops.size());
     P.swz_index.resize(P.ops.size());
     for (size_t i = 0; i < P.ops.size(); ++i) P.swz_ops[i] = P.swz_index[i] = (int)i;
+    // W-lists: CSR by target leaf; X-lists: by target LE box (boxes in order of
+    // first appearance), entries in the order found; reaction entries get
+    // their point operators (one per point of the leaf on the point side)
+    {
+        const size_t nt = P.tl_le.size();
+        const int K = P.K;
+        P.w_ptr.assign(nt + 1, 0);
+        for (const auto& e : S.w_pairs) P.w_ptr[e.tl + 1]++;
+        for (size_t t = 0; t < nt; ++t) P.w_ptr[t + 1] += P.w_ptr[t];
+        const size_t nw = S.w_pairs.size();
+        P.w_fmm.resize(nw);
+        P.w_me.resize(nw);
+        P.w_lv.resize(nw);
+        P.w_ctr.resize(3 * nw);
+        P.w_vec.assign(nw, -1);
+        std::vector<int> fill(P.w_ptr.begin(), P.w_ptr.end() - 1);
+        int64_t vec = 0;
+        for (const auto& e : S.w_pairs) {
+            const int k = fill[e.tl]++;
+            P.w_fmm[k] = e.fmm;
+            P.w_me[k] = e.me;
+            P.w_lv[k] = e.lv;
+            for (int d = 0; d < 3; ++d) P.w_ctr[3 * k + d] = e.c[d];
+        }
+        for (size_t t = 0; t < nt; ++t)
+            for (int k = P.w_ptr[t]; k < P.w_ptr[t + 1]; ++k) {
+                const int n = P.tl_start[t + 1] - P.tl_start[t];
+                P.n_w_points += n;
+                if (P.fmm[P.w_fmm[k]].kind != 1) continue;
+                P.w_vec[k] = vec;
+                const double h = 2.0 * P.fmm[P.w_fmm[k]].R / (double)(1 << P.w_lv[k]);
+                for (int j = 0; j < n; ++j) {
+                    P.pt_ops.push_back({0, P.w_fmm[k], P.tl_start[t] + j, (int)t, P.w_ctr[3 * k], P.w_ctr[3 * k + 1],
+                                        P.w_ctr[3 * k + 2], h, vec});
+                    vec += K;
+                }
+            }
+        std::unordered_map<int, int> box_of;
+        std::vector<int> cnt;
+        for (const auto& e : S.x_pairs) {
+            auto it = box_of.find(e.le);
+            if (it == box_of.end()) {
+                box_of[e.le] = (int)P.x_box_le.size();
+                P.x_box_le.push_back(e.le);
+                P.x_box_lv.push_back(e.lv);
+                for (int d = 0; d < 3; ++d) P.x_box_ctr.push_back(e.c[d]);
+                cnt.push_back(0);
+            }
+            cnt[box_of[e.le]]++;
+        }
+        const size_t nb = P.x_box_le.size();
+        P.x_box_ptr.assign(nb + 1, 0);
+        for (size_t b = 0; b < nb; ++b) P.x_box_ptr[b + 1] = P.x_box_ptr[b] + cnt[b];
+        const size_t nx = S.x_pairs.size();
+        P.x_fmm.resize(nx);
+        P.x_sl.resize(nx);
+        P.x_vec.assign(nx, -1);
+        std::vector<int> xf(P.x_box_ptr.begin(), P.x_box_ptr.end() - 1);
+        for (const auto& e : S.x_pairs) {
+            const int k = xf[box_of[e.le]]++;
+            P.x_fmm[k] = e.fmm;
+            P.x_sl[k] = e.sl;
+        }
+        for (size_t b = 0; b < nb; ++b)
+            for (int k = P.x_box_ptr[b]; k < P.x_box_ptr[b + 1]; ++k) {
+                const int sl = P.x_sl[k];
+                const int n = P.sl_start[sl + 1] - P.sl_start[sl];
+                P.n_x_points += n;
+                if (P.fmm[P.x_fmm[k]].kind != 1) continue;
+                P.x_vec[k] = vec;
+                const double h = 2.0 * P.fmm[P.x_fmm[k]].R / (double)(1 << P.x_box_lv[b]);
+                for (int j = 0; j < n; ++j) {
+                    P.pt_ops.push_back({1, P.x_fmm[k], P.sl_start[sl] + j, sl, P.x_box_ctr[3 * b],
+                                        P.x_box_ctr[3 * b + 1], P.x_box_ctr[3 * b + 2], h, vec});
+                    vec += K;
+                }
+            }
+    }
     // U-lists: CSR by target leaf, each leaf's entries in the order found (a
     // stable counting sort)
     {

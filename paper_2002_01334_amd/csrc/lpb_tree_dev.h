@@ -24,6 +24,8 @@ public:
              int counts[kMaxDepth + 1], std::string& msg) override;
     bool leaves(int handle, int H, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_start,
                 std::string& msg) override;
+    bool leaves_adaptive(int handle, int cap, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
+                         std::vector<int>& leaf_start, std::string& msg) override;
     int failure() const override { return failure_; }
     // The sets `sets` (in order, n_total points) concatenated into the
     // evaluation arrays: charge index, offsets from the leaf centre (FP32: hi
@@ -48,7 +50,7 @@ private:
     void* get(size_t bytes);
     void put(void*& p);
     // temporaries of one kind, kept and grown from set to set
-    enum { kKeyIn, kIdx, kCnt, kSortTmp, kFlag, kPos, kLeafKey, kLeafStart, kScanTmp, kScratchKinds };
+    enum { kKeyIn, kIdx, kCnt, kSortTmp, kFlag, kPos, kLeafKey, kLeafStart, kScanTmp, kLeafLv, kScratchKinds };
     void* scratch(int kind, size_t bytes);
     void* scr_[kScratchKinds] = {};
     size_t scr_bytes_[kScratchKinds] = {};

@@ -9,6 +9,9 @@
 //   leaf centre: -R + (i + 0.5) (2R / 2^H) per axis.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <functional>
+
 #include <rocprim/device/device_radix_sort.hpp>
 #include <rocprim/device/device_scan.hpp>
 
@@ -112,6 +115,37 @@ __global__ void k_leaf_points(int n, const uint64_t* __restrict__ key, const int
         lkey[pos[i] - 1] = k >> (3 * (kCellBits - H));
         lstart[pos[i] - 1] = i;
     }
+    const int j = perm[i];
+    cidx[i] = (int)(coff + mem[j]);
+    const double h = 2.0 * R / (double)(1 << H);
+    const int shH = kCellBits - H;
+    const uint32_t c[3] = {compact3_dev(k >> 2) >> shH, compact3_dev(k >> 1) >> shH, compact3_dev(k) >> shH};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double ctr = -R + ((int)c[d] + 0.5) * h;
+        u[(size_t)d * n + i] = w[(size_t)d * n + j] - ctr;
+    }
+}
+
+// the same on adaptive leaves: a point's leaf is the last leaf starting at or
+// before its sorted position, at that leaf's own level
+__global__ void k_leaf_points_adaptive(int n, const uint64_t* __restrict__ key, int nleaf,
+                                       const int* __restrict__ lstart, const int* __restrict__ llv,
+                                       const int* __restrict__ perm, const int* __restrict__ mem, int64_t coff,
+                                       const double* __restrict__ w, double R, int* __restrict__ cidx,
+                                       double* __restrict__ u)
+{
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int lo = 0, hi = nleaf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (lstart[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    const int H = llv[lo];
+    const uint64_t k = key[i];
     const int j = perm[i];
     cidx[i] = (int)(coff + mem[j]);
     const double h = 2.0 * R / (double)(1 << H);
@@ -334,6 +368,64 @@ bool DevPointBuilder::leaves(int handle, int H, std::vector<uint64_t>& leaf_key,
              check(hipStreamSynchronize(st_), "leaves", msg);
     }
     // the sort state is no longer needed
+    void* d[] = {s.key, s.perm, s.w, s.members};
+    for (void*& q : d) put(q);
+    s.key = nullptr;
+    s.perm = nullptr;
+    s.w = nullptr;
+    s.members = nullptr;
+    return ok;
+}
+
+bool DevPointBuilder::leaves_adaptive(int handle, int cap, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
+                                      std::vector<int>& leaf_start, std::string& msg)
+{
+    Set& s = sets_[handle];
+    const int n = s.n;
+    leaf_key.clear();
+    leaf_lv.clear();
+    leaf_start.clear();
+    if (n == 0) return true;
+    std::vector<uint64_t> k(n);
+    if (!check(hipMemcpyAsync(k.data(), s.key, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st_), "key download", msg) ||
+        !check(hipStreamSynchronize(st_), "key download", msg))
+        return false;
+    // divide from the root down: a box of more than cap points (above
+    // kMaxDepth) is replaced by its non-empty children, in Morton order
+    std::function<void(int, int, int)> divide = [&](int a, int b, int lv) {
+        if (b - a <= cap || lv == kMaxDepth) {
+            leaf_key.push_back(k[a] >> (3 * (kCellBits - lv)));
+            leaf_lv.push_back(lv);
+            leaf_start.push_back(a);
+            return;
+        }
+        const int sh = 3 * (kCellBits - lv - 1);
+        for (int c = a; c < b;) {
+            const uint64_t last = (((k[c] >> sh) + 1) << sh) - 1;
+            const int e = (int)(std::upper_bound(k.begin() + c, k.begin() + b, last) - k.begin());
+            divide(c, e, lv + 1);
+            c = e;
+        }
+    };
+    divide(0, n, 0);
+    const int nleaf = (int)leaf_key.size();
+    int* ls = (int*)scratch(kLeafStart, nleaf * sizeof(int));
+    int* lv = (int*)scratch(kLeafLv, nleaf * sizeof(int));
+    s.cidx = (int*)get(n * sizeof(int));
+    s.u = (double*)get(3 * (size_t)n * sizeof(double));
+    bool ok = ls && lv && s.cidx && s.u;
+    if (!ok) msg = "point builder: device allocation failed";
+    if (ok)
+        ok = check(hipMemcpyAsync(ls, leaf_start.data(), nleaf * sizeof(int), hipMemcpyHostToDevice, st_),
+                   "leaf upload", msg) &&
+             check(hipMemcpyAsync(lv, leaf_lv.data(), nleaf * sizeof(int), hipMemcpyHostToDevice, st_), "leaf upload",
+                   msg);
+    if (ok) {
+        hipLaunchKernelGGL(k_leaf_points_adaptive, dim3(nblk(n, 256)), dim3(256), 0, st_, n, s.key, nleaf, ls, lv,
+                           s.perm, s.members, s.coff, s.w, s.R, s.cidx, s.u);
+        ok = check(hipGetLastError(), "leaf point kernel", msg);
+    }
+    if (ok) ok = check(hipStreamSynchronize(st_), "leaves", msg);
     void* d[] = {s.key, s.perm, s.w, s.members};
     for (void*& q : d) put(q);
     s.key = nullptr;

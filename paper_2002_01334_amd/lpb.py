@@ -32,7 +32,7 @@ FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
 class Options(ctypes.Structure):
     _fields_ = [("p", _I), ("leaf_cap", _I), ("precision", _I), ("quad_tol", _D), ("iface_tol", _D),
                 ("device", _I), ("stream", _P), ("stages", _I), ("timing", _I), ("graph", _I), ("autotune", _I),
-                ("schedule", _I), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", _P)]
+                ("schedule", _I), ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_user", _P), ("adaptive", _I)]
 
 
 class Allocator:
@@ -59,7 +59,8 @@ class Stats(ctypes.Structure):
                 ("t_build_ms", _D), ("t_opgen_ms", _D), ("t_eval_ms", _D), ("t_stage_ms", _D * 10),
                 ("tile_schedule", _I), ("batch_schedule", _I), ("t_tune_ms", _D), ("n_m2l_tiles", _L),
                 ("n_p2m_points", _L), ("n_l2p_points", _L), ("n_m2m_links", _L), ("n_l2l_links", _L),
-                ("n_m2l_list_ops", _L)]
+                ("n_m2l_list_ops", _L), ("n_w_pairs", _L), ("n_x_pairs", _L), ("n_w_points", _L),
+                ("n_x_points", _L), ("n_point_ops", _L)]
 
     STAGES = ["setup", "p2m", "m2m", "m2l_tile", "m2l_list", "l2l", "l2p", "p2p_free", "p2p_react", "sum"]
 
@@ -145,7 +146,7 @@ class Context:
     """One lpb context (one GPU, one stream)."""
 
     def __init__(self, p=10, leaf_cap=50, precision=LPB_FP64, quad_tol=1e-16, iface_tol=1e-9, device=0,
-                 stream=None, stages=3, timing=0, graph=1, autotune=1, schedule=0, allocator=None):
+                 stream=None, stages=3, timing=0, graph=1, autotune=1, schedule=0, allocator=None, adaptive=0):
         L = load()
         opt = Options()
         L.lpb_default_options(ctypes.byref(opt))
@@ -165,6 +166,7 @@ class Context:
         opt.graph = graph
         opt.autotune = autotune
         opt.schedule = schedule
+        opt.adaptive = int(adaptive)
         h = _P()
         rc = L.lpb_create(ctypes.byref(opt), ctypes.byref(h))
         if rc != LPB_OK:
