@@ -13,14 +13,15 @@ operator generation).  The plain FP64 GPU path is timed beside it
 reported (rel_err_vs_fp64, gate 1e-6).
 
 Other workloads (--workload): clustered (1e5 charges per layer, half of them
-Gaussian with sigma 0.1 about the cube centre; default p = 6), batch (256
+Gaussian with sigma 0.1 about the cube centre; default p = 6), interface (1e5
+per layer, half in tight clusters next to the interfaces; default p = 6), batch (256
 independent systems of uneven sizes and random media evaluated by one batched
 call; default p = 8) and paper (the paper's own test problem: eps = (1, 8.6,
 20.5), lambda = (1.2, 0.5, 2.1), charges uniform in the three P_4-shaped
 bodies, --charges total, default 2,861,288, the largest count of its timing
 table; default p = 5, the table's order; the table's 36-core CPU time for the
 same count is quoted as context).  --p overrides the order (e.g. 15 on the
-default workload).
+default workload); --adaptive evaluates on adaptive trees (W- and X-lists).
 """
 from __future__ import annotations
 
@@ -78,18 +79,20 @@ def _time_evals(ctx, torch, run, steps, warmup):
     return float(np.mean(evals)), stage, wall
 
 
-def _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps):
+def _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps, adaptive=0):
     """The timed evaluations use the captured passes (graph = 1, autotuned
     schedules, no per-stage events); a second context launches the passes one
     by one with events between stages for the stage breakdown."""
     stream = torch.cuda.current_stream().cuda_stream
-    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=0, graph=1, autotune=1, stream=stream)
+    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=0, graph=1, autotune=1, stream=stream,
+                      adaptive=adaptive)
     t_build = setup(ctx)
     ms, _, wall = _time_evals(ctx, torch, lambda: run_one(ctx), steps, warmup)
     out = run_one(ctx)
     stats = ctx.stats()
     ctx.close()
-    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=1, graph=0, autotune=0, stream=stream)
+    ctx = lpb.Context(p=p, leaf_cap=leaf_cap, precision=precision, timing=1, graph=0, autotune=0, stream=stream,
+                      adaptive=adaptive)
     setup(ctx)
     ms_eager, stage, _ = _time_evals(ctx, torch, lambda: run_one(ctx), stage_steps, 1)
     ctx.close()
@@ -97,7 +100,7 @@ def _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, war
             "t_build_s": t_build, "phi": out}
 
 
-def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup, stage_steps=3):
+def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup, stage_steps=3, adaptive=0):
     dev = torch.device("cuda:0")
     t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device=dev) for k in ("x", "y", "z", "q")}
     phi = torch.empty_like(t["q"])
@@ -112,7 +115,7 @@ def time_context(lpb, torch, prob, p, leaf_cap, precision, steps, warmup, stage_
         ctx.evaluate(t["q"], phi)
         return phi
 
-    r = _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps)
+    r = _run_contexts(lpb, torch, setup, run_one, p, leaf_cap, precision, steps, warmup, stage_steps, adaptive)
     r["phi"] = r["phi"].cpu().numpy()
     return r
 
@@ -146,7 +149,7 @@ def shrink(prob, k):
     return dataclasses.replace(prob, **{f: getattr(prob, f)[::k].copy() for f in ("x", "y", "z", "q", "layer")})
 
 
-def cpu_baseline(probs, p, leaf_cap, what, cores=None):
+def cpu_baseline(probs, p, leaf_cap, what, cores=None, adaptive=False):
     """The oracle FMM (plain C, FP64, OpenMP) on a bounded sample of the
     workload.  Its cost is linear in the number of charges at a fixed leaf
     occupancy (the tree deepens with N), so charges/s carries over to the
@@ -160,7 +163,7 @@ def cpu_baseline(probs, p, leaf_cap, what, cores=None):
     t0 = time.perf_counter()
     for prob in probs:
         ly = oracle.Layers(prob.eps, prob.lam, prob.d)
-        oracle.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=leaf_cap, nthreads=cores)
+        oracle.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=leaf_cap, nthreads=cores, adaptive=adaptive)
         n += prob.n
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "charges/s", "cores": cores, "kind": "oracle",
@@ -254,7 +257,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=("uniform", "clustered", "batch", "paper"), default="uniform",
+    ap.add_argument("--workload", choices=("uniform", "clustered", "interface", "batch", "paper"), default="uniform",
                     help="uniform: 1e6 charges per layer in unit cubes (default); clustered: 1e5 per layer, half "
                          "Gaussian (sigma 0.1); batch: 256 independent systems of uneven sizes; paper: the paper's "
                          "test problem (P_4-shaped bodies, its media)")
@@ -263,6 +266,8 @@ def main():
     ap.add_argument("--systems", type=int, default=256)
     ap.add_argument("--p", type=int, default=None)
     ap.add_argument("--leaf-cap", type=int, default=50)
+    ap.add_argument("--adaptive", action="store_true",
+                    help="adaptive trees with W- and X-lists (lpb_options.adaptive = 1; the oracle sample too)")
     ap.add_argument("--fp64-steps", type=int, default=5)
     ap.add_argument("--cpu-sample", type=int, default=None, help="charges per layer of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -275,9 +280,10 @@ def main():
               "one reduce", file=sys.stderr)
         sys.exit(2)
     wl = args.workload
-    p = args.p if args.p is not None else {"uniform": 10, "clustered": 6, "batch": 8, "paper": 5}[wl]
+    p = args.p if args.p is not None else {"uniform": 10, "clustered": 6, "interface": 6, "batch": 8, "paper": 5}[wl]
     per_layer = args.per_layer if args.per_layer is not None else {"uniform": 1_000_000, "clustered": 100_000,
-                                                                   "batch": 0, "paper": 0}[wl]
+                                                                   "interface": 100_000, "batch": 0, "paper": 0}[wl]
+    ad = 1 if args.adaptive else 0
 
     import torch
 
@@ -314,7 +320,12 @@ def main():
         sample_what = f"the first {len(sample)} systems of the batch"
     else:
         clustered = wl == "clustered"
-        if wl == "paper":
+        if wl == "interface":
+            prob = inputs.three_layer_interface_clusters(per_layer, seed=0)
+            desc = (f"3-layer medium eps=(1,2,4) lambda=(1.2,1.5,2.0) d=(0,-1.2), {per_layer}/layer, half uniform "
+                    "in the layer's slab (0.02 from the interfaces), half Gaussian (sigma 0.04) next to an interface, "
+                    "q~U[-1,1], seed 0")
+        elif wl == "paper":
             prob = inputs.paper_domains(args.charges, seed=0)
             counts = "+".join(str(int((prob.layer == l).sum())) for l in range(3))
             desc = (f"the paper's test problem: eps=(1,8.6,20.5) lambda=(1.2,0.5,2.1) d=(0,-1.2), {counts} charges "
@@ -326,9 +337,9 @@ def main():
                     + ", q~U[-1,1], seed 0")
         ntot = prob.n
         print(f"[bench] workload: 3 layers, {ntot} charges, p={p}", file=sys.stderr, flush=True)
-        mixed = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup)
+        mixed = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_MIXED, args.steps, args.warmup, adaptive=ad)
         print(f"[bench] mixed: {mixed['eval_ms']:.2f} ms/eval, stages {mixed['stage_ms']}", file=sys.stderr, flush=True)
-        fp64 = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_FP64, args.fp64_steps, 1)
+        fp64 = time_context(lpb, torch, prob, p, args.leaf_cap, lpb.LPB_FP64, args.fp64_steps, 1, adaptive=ad)
         print(f"[bench] fp64: {fp64['eval_ms']:.2f} ms/eval, stages {fp64['stage_ms']}", file=sys.stderr, flush=True)
         rel_layers = err2_per_layer(mixed["phi"], fp64["phi"], prob.layer)
         rel = rel_layers
@@ -336,6 +347,9 @@ def main():
         if wl == "paper":
             sample = [inputs.paper_domains(3 * cs, seed=0)]
             sample_what = f"the same recipe at {3 * cs} charges"
+        elif wl == "interface":
+            sample = [inputs.three_layer_interface_clusters(cs, seed=0)]
+            sample_what = f"the same recipe at {cs} charges per layer"
         else:
             sample = [inputs.three_layer(cs, seed=0, clustered_fraction=0.5 if clustered else 0.0, sigma=0.1)]
             sample_what = f"the same recipe at {cs} charges per layer"
@@ -360,7 +374,8 @@ def main():
         "vs_baseline": None,
         "dtype": "f32+f64",
         "data": "synthetic",
-        "config": {"workload": desc, "charges": ntot, "p": p, "leaf_cap": args.leaf_cap, "precision": "mixed"},
+        "config": {"workload": desc, "charges": ntot, "p": p, "leaf_cap": args.leaf_cap, "precision": "mixed",
+                   "tree": "adaptive" if ad else "uniform"},
         "fp64_value": ntot / (fp64["eval_ms"] * 1e-3),
         "fp64_ms_per_step": fp64["eval_ms"],
         "speedup_vs_fp64": fp64["eval_ms"] / ms,
@@ -371,6 +386,7 @@ def main():
         "stage_ms": {k: round(v, 4) for k, v in mixed["stage_ms"].items()},
         "fp64_stage_ms": {k: round(v, 4) for k, v in fp64["stage_ms"].items()},
         "setup": {"tree_build_s": mixed["t_build_s"], "opgen_ms": st["t_opgen_ms"], "n_m2l_pairs": st["n_m2l_pairs"],
+                  "n_w_pairs": st["n_w_pairs"], "n_x_pairs": st["n_x_pairs"], "n_point_ops": st["n_point_ops"],
                   "n_p2p_pairs": st["n_p2p_pairs"], "n_operators": st["n_operators"],
                   "operator_bytes": st["operator_bytes"], "max_depth": st["max_depth"]},
         "roofline": roof,
@@ -387,12 +403,12 @@ def main():
     gate = max(rel) <= 1e-6
     line["gate"] = {"rel_err_max": max(rel), "bar": 1e-6, "pass": bool(gate)}
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(sample, p, args.leaf_cap, sample_what)
+        line["cpu_baseline"] = cpu_baseline(sample, p, args.leaf_cap, sample_what, adaptive=bool(ad))
         if wl != "batch":
             # the same oracle on one host core, on a tenth of the sample
             small = [shrink(pr, 10) for pr in sample]
             line["cpu_baseline_1core"] = cpu_baseline(small, p, args.leaf_cap, sample_what + " (every 10th charge)",
-                                                      cores=1)
+                                                      cores=1, adaptive=bool(ad))
     print(json.dumps(line), flush=True)
     if not gate:
         print(f"[bench] mixed-precision error {max(rel):.3e} above the 1e-6 bar", file=sys.stderr, flush=True)

@@ -106,15 +106,21 @@ typedef struct {
      * uniform trees, every leaf of an FMM at its depth (see lpb_build_tree).
      * 1: adaptive trees: each point set (a layer's charges; a layer side's
      * targets or equivalent polarization sources) divides a box while it holds
-     * more than leaf_cap points, down to level 12; the lists add W-list pairs
-     * (a finer source box's multipole expansion evaluated at a coarser leaf's
-     * targets, M2P) and X-list pairs (a coarser leaf's sources formed into a
-     * finer target box's local expansion, P2L).  Reaction M2P / P2L use point
-     * operators from the F~ and L rows of eq. coefintable, whose Sommerfeld
-     * tables combine the forward (eq. recurrence1) and backward
-     * (eq. backwardrecurrence1) recurrences; they are generated with the
-     * translation operators (FP64) and kept, K doubles per (point, box)
-     * pair.  Results converge to the same potential as on uniform trees. */
+     * more than leaf_cap points, down to level 12, and the sets of the
+     * reaction components also divide a box while it is wider than the
+     * distance of its nearest point from the interface (fine cells), up to 3
+     * levels below the occupancy rule (the per-box form of the uniform trees'
+     * separation depth, which keeps most reaction near-field pairs away); the
+     * lists add W-list pairs (a finer source box's multipole expansion
+     * evaluated at a coarser leaf's targets, M2P) and X-list pairs (a coarser
+     * leaf's sources formed into a finer target box's local expansion, P2L).
+     * 2: adaptive trees by occupancy alone (more reaction near-field, W- and
+     * X-list pairs).  Reaction M2P / P2L use point operators from the F~ and
+     * L rows of eq. coefintable, whose Sommerfeld tables combine the forward
+     * (eq. recurrence1) and backward (eq. backwardrecurrence1) recurrences;
+     * they are generated with the translation operators (FP64) and kept, K
+     * doubles per (point, box) pair.  All forms converge to the same
+     * potential. */
     int adaptive;
 } lpb_options;
 

@@ -71,7 +71,7 @@ def lib():
             "orc_reaction_I_both": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D, _PD, _PD, _PD, _PD]),
             "orc_sommerfeld_table": (_I, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _D, _D, _D, _D, _I, _I, _PD]),
             "orc_free_point_chain": (_D, [_I, _D, _PD, _PD, _PD, _I]),
-            "orc_list_coverage": (_I, [_I, _PU32, _I, _PU32, _I, _I, _I, _PI, _PLL]),
+            "orc_list_coverage": (_I, [_I, _PU32, _I, _PU32, _I, _I, _I, _I, _PI, _PLL]),
             "orc_reaction_point_chain": (_D, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _PD, _PD, _PD, _D, _I]),
             "orc_reaction_I_point": (None, [_PD, _PD, _PD, _I, _I, _I, _I, _I, _I, _D, _D, _D, _D,
                                             _I, _I, _I, _I, _PD]),
@@ -204,9 +204,10 @@ def component(nlayers, c):
     return tuple(out)
 
 
-def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False, adaptive=False):
-    """CPU FMM (Algorithm 2) on uniform trees, or on adaptive trees with W-
-    and X-lists.  Returns phi, and with components=True also (comp_phi
+def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False, adaptive=0):
+    """CPU FMM (Algorithm 2) on uniform trees (adaptive 0), or on adaptive
+    trees with W- and X-lists (1: the reaction sets also divided near the
+    interface; 2: by occupancy alone).  Returns phi, and with components=True also (comp_phi
     [ncomp, n], stats [ncomp, 8]: depth, target leaves, source leaves, V-list
     pairs, direct point pairs, unstable flag, W-list pairs, X-list pairs)."""
     x, y, z, q = map(_f64, (x, y, z, q))
@@ -216,7 +217,7 @@ def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False, ad
     cphi = np.zeros((nc, n)) if components else None
     stats = np.zeros((nc, 8))
     rc = lib().orc_fmm(ly.nlayers, _p(ly.eps), _p(ly.lam), _p(ly.d), n, _p(x), _p(y), _p(z), _p(q),
-                       int(p), int(leaf_cap), 1 if adaptive else 0, int(nthreads), _p(phi),
+                       int(p), int(leaf_cap), int(adaptive), int(nthreads), _p(phi),
                        _p(cphi) if components else None, _p(stats))
     if rc != 0:
         raise RuntimeError(f"orc_fmm failed: {rc}")
@@ -225,7 +226,7 @@ def fmm(ly: Layers, x, y, z, q, p, leaf_cap=50, nthreads=0, components=False, ad
     return phi
 
 
-def component_tree(ly: Layers, x, y, z, comp, leaf_cap=50, adaptive=False):
+def component_tree(ly: Layers, x, y, z, comp, leaf_cap=50, adaptive=0):
     """Depth, each target's and source's leaf key and the root (centre, half
     side) of one component; adaptive=True also returns the leaf levels
     (keys are then at each point's own leaf level)."""
@@ -240,7 +241,7 @@ def component_tree(ly: Layers, x, y, z, comp, leaf_cap=50, adaptive=False):
     sl = np.zeros(n + 1, dtype=np.int32)
     root = np.zeros(4)
     rc = lib().orc_component_tree(ly.nlayers, _p(ly.eps), _p(ly.lam), _p(ly.d), n, _p(x), _p(y), _p(z),
-                                  comp, leaf_cap, 1 if adaptive else 0, ctypes.byref(depth), ctypes.byref(nt),
+                                  comp, leaf_cap, int(adaptive), ctypes.byref(depth), ctypes.byref(nt),
                                   ctypes.byref(ns), tk.ctypes.data_as(_PU), sk.ctypes.data_as(_PU),
                                   tl.ctypes.data_as(_PI), sl.ctypes.data_as(_PI), _p(root))
     if rc != 0:
@@ -281,16 +282,17 @@ def reaction_I_pair(ly: Layers, l, lp, a, b, p, rho, zt, zs, S, n, m, nu, mu):
     return out[0] + 1j * out[1], out[2] + 1j * out[3]
 
 
-def list_coverage(scells, tcells, cap, adaptive=True, H=0):
+def list_coverage(scells, tcells, cap, adaptive=True, H=0, sep=False):
     """(cover [nt, ns], counts [V, U, W, X]) of the oracle's lists between
-    sources and targets given by fine cells ([n, 3] ints in 0..65535)."""
+    sources and targets given by fine cells ([n, 3] ints in 0..65535); sep:
+    the reaction sets' separation rule."""
     sc = np.ascontiguousarray(np.asarray(scells, dtype=np.uint32).T)
     tc = np.ascontiguousarray(np.asarray(tcells, dtype=np.uint32).T)
     ns, nt = sc.shape[1], tc.shape[1]
     cover = np.zeros((nt, ns), dtype=np.int32)
     counts = np.zeros(4, dtype=np.int64)
     lib().orc_list_coverage(ns, sc.ctypes.data_as(_PU32), nt, tc.ctypes.data_as(_PU32), int(cap),
-                            1 if adaptive else 0, int(H), cover.ctypes.data_as(_PI),
+                            1 if adaptive else 0, 1 if sep else 0, int(H), cover.ctypes.data_as(_PI),
                             counts.ctypes.data_as(_PLL))
     return cover, counts
 

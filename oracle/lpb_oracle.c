@@ -1179,7 +1179,9 @@ static void p2l_react_one(const rcomp_t* C, const ctab_t* CT, int p, double q, d
 /*  level-l cell = fine cell >> (16 - l).  Uniform trees: depth H = the    */
 /*  smallest l with N_src <= cap * #non-empty source boxes(l) and the same  */
 /*  for targets (H <= 12).  Adaptive trees: each point set divides a box    */
-/*  while it holds more than cap points (down to level 12).  V-list at      */
+/*  while it holds more than cap points (down to level 12), a reaction      */
+/*  component's sets also while a box is wider than its nearest point's    */
+/*  distance from the interface (see divide_box).  V-list at                */
 /*  level l >= 2: existing source boxes that are children of the            */
 /*  neighbours of the target's parent and not adjacent to the target;       */
 /*  U-, W- and X-lists by the dual traversal (traverse() below); on uniform */
@@ -1303,24 +1305,56 @@ static void sort_points(const cells_t* C, int* order, uint64_t* key)
     free(kv);
 }
 
-/* Adaptive rule: a box is divided while it holds more than cap points and
- * lies above ORC_MAXDEPTH, so a point's leaf is its first ancestor (from the
- * root down) holding at most cap points.  lv[i] = leaf level of point i
- * (key, order: the sorted points). */
-static void leaf_levels(int n, const int* order, const uint64_t* key, int cap, int* lv)
+/* Adaptive rule: a box (above ORC_MAXDEPTH) is divided while it holds more
+ * than cap points; with sep != 0 (the sets of a reaction component, whose
+ * root is halved by the interface plane: fine z cells 32767 | 32768) a box
+ * is also divided while it is wider than the distance of its nearest point
+ * from the plane, both in fine cells, down to 3 levels below the level at
+ * which the occupancy rule stopped.  lv[i] = leaf level of point i (key,
+ * order: the sorted points). */
+static uint32_t plane_dist(uint64_t key)
 {
-    for (int i = 0; i < n; ++i) lv[i] = -1;
-    for (int l = 0; l <= ORC_MAXDEPTH; ++l) {
-        int sh = 3 * (ORC_HMAX - l);
-        for (int k0 = 0; k0 < n;) {
-            int k1 = k0 + 1;
-            while (k1 < n && (key[k1] >> sh) == (key[k0] >> sh)) ++k1;
-            if (k1 - k0 <= cap || l == ORC_MAXDEPTH)
-                for (int k = k0; k < k1; ++k)
-                    if (lv[order[k]] < 0) lv[order[k]] = l;
-            k0 = k1;
+    uint32_t cz = 0;
+    for (int bit = 0; bit < ORC_HMAX; ++bit) cz |= (uint32_t)((key >> (3 * bit)) & 1u) << bit;
+    return cz >= 32768u ? cz - 32768u : 32767u - cz;
+}
+
+static void divide_box(int k0, int k1, int l, int locc, const int* order, const uint64_t* key, int cap, int sep,
+                       int* lv)
+{
+    int split = 0;
+    if (l < ORC_MAXDEPTH) {
+        if (k1 - k0 > cap) {
+            split = 1;
+            locc = -1;
+        } else {
+            if (locc < 0) locc = l;
+            if (sep && l < locc + 3) {
+                uint32_t dmin = 0xffffffffu;
+                for (int k = k0; k < k1; ++k) {
+                    uint32_t d = plane_dist(key[k]);
+                    if (d < dmin) dmin = d;
+                }
+                split = (1u << (ORC_HMAX - l)) > dmin;
+            }
         }
     }
+    if (!split) {
+        for (int k = k0; k < k1; ++k) lv[order[k]] = l;
+        return;
+    }
+    int sh = 3 * (ORC_HMAX - l - 1);
+    for (int a = k0; a < k1;) {
+        int b = a + 1;
+        while (b < k1 && (key[b] >> sh) == (key[a] >> sh)) ++b;
+        divide_box(a, b, l + 1, locc, order, key, cap, sep, lv);
+        a = b;
+    }
+}
+
+static void leaf_levels(int n, const int* order, const uint64_t* key, int cap, int sep, int* lv)
+{
+    if (n > 0) divide_box(0, n, 0, -1, order, key, cap, sep, lv);
 }
 
 /* distinct level-l cells of the points whose leaf level is at least l */
@@ -1532,8 +1566,10 @@ static double near_sum(const fmmspec_t* F, int i, const double* tx, const double
 
 /* pre_s, pre_t: fine cells of the sources and targets (computed here from the
  * coordinates and the root cube when NULL); Hfix >= 0 imposes the depth of a
- * uniform tree; adaptive != 0 builds the adaptive trees instead (leaf rule
- * above, separately for sources and targets) with W- and X-lists. */
+ * uniform tree; adaptive = 1 builds the adaptive trees instead (leaf rule
+ * above, separately for sources and targets; a reaction component's sets
+ * with the separation rule) with W- and X-lists, adaptive = 2 the adaptive
+ * trees by occupancy alone. */
 static int run_fmm(const fmmspec_t* F, int p, int cap, int adaptive, int ns, const double* sx, const double* sy,
                    const double* sz, const double* sq, const int64_t* sid, int nt, const double* tx,
                    const double* ty, const double* tz, const int64_t* tid, double cx, double cy, double cz, double R,
@@ -1574,8 +1610,8 @@ static int run_fmm(const fmmspec_t* F, int p, int cap, int adaptive, int ns, con
     int* tlv = (int*)malloc(sizeof(int) * nt);
     int H = -1;
     if (adaptive) {
-        leaf_levels(ns, sorder, skey, cap, slv);
-        leaf_levels(nt, torder, tkey, cap, tlv);
+        leaf_levels(ns, sorder, skey, cap, adaptive == 1 && F->kind == 1, slv);
+        leaf_levels(nt, torder, tkey, cap, adaptive == 1 && F->kind == 1, tlv);
         for (int i = 0; i < ns; ++i) H = slv[i] > H ? slv[i] : H;
         for (int i = 0; i < nt; ++i) H = tlv[i] > H ? tlv[i] : H;
     } else {
@@ -2638,7 +2674,7 @@ int orc_component_tree(int nlayers, const double* eps, const double* lam, const 
             int* order = (int*)malloc(sizeof(int) * (m + 1));
             uint64_t* key = (uint64_t*)malloc(sizeof(uint64_t) * (m + 1));
             sort_points(sets[t], order, key);
-            leaf_levels(m, order, key, leaf_cap, lvs[t]);
+            leaf_levels(m, order, key, leaf_cap, adaptive == 1 && kind == 1, lvs[t]);
             for (int i = 0; i < m; ++i) H = lvs[t][i] > H ? lvs[t][i] : H;
             free(order);
             free(key);
@@ -2747,14 +2783,15 @@ void orc_reaction_I_point(const double* eps, const double* lam, const double* d,
 }
 
 /* List pin: builds the trees (uniform at depth Hfix when adaptive = 0, else
- * adaptive with leaf cap `cap`) and lists of run_fmm for sources and targets
+ * adaptive with leaf cap `cap`, sep as for a reaction component's sets) and
+ * lists of run_fmm for sources and targets
  * given by their fine cells (cx, cy, cz per point, 0..65535), and counts for
  * every (target, source) pair how many list entries cover it: V (all targets
  * under the target box and all sources under the source box), U, W and X.
  * cover[i * ns + j] (sorted-order independent: indices are the inputs').
  * counts[0..3] = number of V, U, W, X box pairs. */
-int orc_list_coverage(int ns, const uint32_t* scell, int nt, const uint32_t* tcell, int cap, int adaptive, int Hfix,
-                      int* cover, long long* counts)
+int orc_list_coverage(int ns, const uint32_t* scell, int nt, const uint32_t* tcell, int cap, int adaptive, int sep,
+                      int Hfix, int* cover, long long* counts)
 {
     cells_t Cs, Ct;
     Cs.n = ns;
@@ -2778,8 +2815,8 @@ int orc_list_coverage(int ns, const uint32_t* scell, int nt, const uint32_t* tce
     int* tlv = (int*)malloc(sizeof(int) * nt);
     int H = 0;
     if (adaptive) {
-        leaf_levels(ns, sorder, skey, cap, slv);
-        leaf_levels(nt, torder, tkey, cap, tlv);
+        leaf_levels(ns, sorder, skey, cap, sep, slv);
+        leaf_levels(nt, torder, tkey, cap, sep, tlv);
         for (int i = 0; i < ns; ++i) H = slv[i] > H ? slv[i] : H;
         for (int i = 0; i < nt; ++i) H = tlv[i] > H ? tlv[i] : H;
     } else {

@@ -20,34 +20,86 @@ namespace lpb {
 
 #define LPB_KMAX ((LPB_MAX_P + 1) * (LPB_MAX_P + 1))
 
+// Calls f(n, m, re, im) with Y_n^m(v) = re + i im for every n <= p, 0 <= m <= n,
+// at a unit vector v = (x, y, z), by the solid-harmonic recurrence
+// (coefficients amm[m], al / be at the packed index, FP64, in LDS)
+template <int P, typename Fn>
+__device__ __attribute__((always_inline)) inline void unit_harmonics(int p_rt, const double* amm, const double* al,
+                                                                     const double* be, double x, double y, double z,
+                                                                     Fn&& f)
+{
+    const int p = P > 0 ? P : p_rt;
+    double wr = 1.0, wi = 0.0;
+#pragma unroll
+    for (int m = 0; m <= p; ++m) {
+        if (m > 0) {
+            const double nr = wr * x - wi * y;
+            wi = wr * y + wi * x;
+            wr = nr;
+        }
+        double pr = amm[m] * wr, pi = amm[m] * wi;
+        f(m, m, pr, pi);
+        if (m + 1 > p) continue;
+        double qr = al[ipk(m + 1, m)] * z * pr, qi = al[ipk(m + 1, m)] * z * pi;
+        f(m + 1, m, qr, qi);
+#pragma unroll
+        for (int n = m + 2; n <= p; ++n) {
+            const double a = al[ipk(n, m)], b = be[ipk(n, m)];
+            const double sr = a * z * qr - b * pr, si = a * z * qi - b * pi;
+            f(n, m, sr, si);
+            pr = qr;
+            pi = qi;
+            qr = sr;
+            qi = si;
+        }
+    }
+}
+
+// k_n(x), n = 0..p (forward recurrence as bessel_k_all), unrolled for a
+// compile-time P so that the values stay in registers
+template <int P>
+__device__ __attribute__((always_inline)) inline void bessel_k_fixed(int p_rt, double x, double* out)
+{
+    const int p = P > 0 ? P : p_rt;
+    const double e = 0.5 * LPB_PI * exp(-x) / x, xi = 1.0 / x;
+    out[0] = e;
+    if (p >= 1) out[1] = e * (1.0 + xi);
+#pragma unroll
+    for (int n = 1; n < p; ++n) out[n + 1] = out[n - 1] + (2.0 * n + 1.0) * xi * out[n];
+}
+
 // M2P: one 64-lane block per target leaf with W-list entries, one lane per
 // target (64 at a time); the entry's expansion is staged in LDS in FP64.
-template <typename T>
+template <typename T, int P>
 __global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
 {
     extern __shared__ double sm_m2p[];
+    const int p = P > 0 ? P : A.p, K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2;
     double* M = sm_m2p;                 // K
-    double* sc = sm_m2p + A.K;          // p + 1: 4 pi i_n(lam h_s)
-    const int p = A.p, K = A.K;
+    double* tab = sm_m2p + K;           // amm[p+1], alpha[Kp], beta[Kp]
     const int leaf = A.w_leaves[blockIdx.x];
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const int e0 = A.w_ptr[leaf], e1 = A.w_ptr[leaf + 1];
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x;
+    for (int k = lane; k < p + 1 + 2 * Kp; k += 64) tab[k] = A.sh64[k];
+    const double *amm = tab, *al = tab + p + 1, *be = tab + p + 1 + Kp;
     for (int base = t0; base < t1; base += 64) {
         const int j = base + lane;
         const bool act = j < t1;
+        double ux = 0.0, uy = 0.0, uz = 0.0;
+        if (act) {
+            ux = (double)A.t_ux[j] + (A.t_lx ? (double)A.t_lx[j] : 0.0);
+            uy = (double)A.t_uy[j] + (A.t_ly ? (double)A.t_ly[j] : 0.0);
+            uz = (double)A.t_uz[j] + (A.t_lz ? (double)A.t_lz[j] : 0.0);
+        }
         double acc = 0.0;
         for (int e = e0; e < e1; ++e) {
-            const FmmDev& F = A.fmm[A.w_fmm[e]];
+            const int fid = A.w_fmm[e];
+            const FmmDev& F = A.fmm[fid];
             const int me = A.w_me[e];
             __syncthreads();
             for (int k = lane; k < K; k += 64) M[k] = (double)A.me[(size_t)me * A.KP + k];
-            if (lane == 0 && F.kind == 0) {
-                double buf[LPB_MAX_P + 2];
-                bessel_i_all(p, F.lam_s * (2.0 * F.R / (double)(1 << A.w_lv[e])), buf);
-                for (int n = 0; n <= p; ++n) sc[n] = 4.0 * LPB_PI * buf[n];
-            }
             __syncthreads();
             if (!act) continue;
             if (F.kind == 1) {
@@ -57,52 +109,18 @@ __global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
                 acc += s;
                 continue;
             }
-            // target offset from the source box centre
-            const double ux = (double)A.t_ux[j] + (A.t_lx ? (double)A.t_lx[j] : 0.0);
-            const double uy = (double)A.t_uy[j] + (A.t_ly ? (double)A.t_ly[j] : 0.0);
-            const double uz = (double)A.t_uz[j] + (A.t_lz ? (double)A.t_lz[j] : 0.0);
+            // free space: the target's offset from the source box centre
             const double vx = ux + (tcx - A.w_ctr[3 * e]), vy = uy + (tcy - A.w_ctr[3 * e + 1]),
                          vz = uz + (tcz - A.w_ctr[3 * e + 2]);
             const double r = sqrt(vx * vx + vy * vy + vz * vz);
-            double kn[LPB_MAX_P + 1];
-            bessel_k_all(p, F.lam_s * r, kn);
-            const double x = vx / r, y = vy / r, z = vz / r;
-            // Y_n^m(v^) = R_n^m(x, y, z) on the unit sphere, by the solid-harmonic recurrence
-            double s = 0.0, wr = 1.0, wi = 0.0, amm = 0.28209479177387814;
-            for (int m = 0; m <= p; ++m) {
-                if (m > 0) {
-                    const double nr = wr * x - wi * y;
-                    wi = wr * y + wi * x;
-                    wr = nr;
-                    amm *= sqrt((2.0 * m + 1.0) / (2.0 * m));
-                }
-                double pr = amm * wr, pi = amm * wi, qr = 0.0, qi = 0.0;
-                const double f = m ? 2.0 : 1.0;
-                for (int n = m; n <= p; ++n) {
-                    double cr, ci;
-                    if (n == m) {
-                        cr = pr;
-                        ci = pi;
-                    } else if (n == m + 1) {
-                        qr = sqrt(2.0 * m + 3.0) * z * pr;
-                        qi = sqrt(2.0 * m + 3.0) * z * pi;
-                        cr = qr;
-                        ci = qi;
-                    } else {
-                        const double nn = (double)n * n, mm = (double)m * m;
-                        const double a = sqrt((4.0 * nn - 1.0) / (nn - mm));
-                        const double b = sqrt(((n - 1.0) * (n - 1.0) - mm) * (2.0 * n + 1.0) / ((nn - mm) * (2.0 * n - 3.0)));
-                        cr = a * z * qr - b * pr;
-                        ci = a * z * qi - b * pi;
-                        pr = qr;
-                        pi = qi;
-                        qr = cr;
-                        qi = ci;
-                    }
-                    const double re = M[ire(n, m)], im = m ? M[iim(n, m)] : 0.0;
-                    s += f * sc[n] * kn[n] * (re * cr - im * ci);
-                }
-            }
+            double kn[(P > 0 ? P : LPB_MAX_P) + 1];
+            bessel_k_fixed<P>(p, F.lam_s * r, kn);
+            const double* sc = A.fin_s + ((size_t)fid * (kMaxDepth + 1) + A.w_lv[e]) * (LPB_MAX_P + 1);
+            double s = 0.0;
+            unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
+                const double re = M[ire(n, m)], im = m ? M[iim(n, m)] : 0.0;
+                s += (m ? 2.0 : 1.0) * sc[n] * kn[n] * (re * cr - im * ci);
+            });
             acc += F.far_factor * s;
         }
         if (act) A.parts[A.t_out[j]] += acc;
@@ -113,23 +131,25 @@ __global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
 // per chunk of CH sources each lane forms its source's scaled row in LDS,
 // then lanes sum rows; reaction: each lane takes coefficients k and sums
 // q times the point operators over the leaf's sources.
-template <typename T>
-__global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A)
+template <typename T, int P>
+__global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A, int CH)
 {
-    constexpr int CH = 16;
     extern __shared__ double sm_p2l[];
-    const int p = A.p, K = A.K;
-    double* rows = sm_p2l;                        // [K][CH + 1]
-    double* sc = sm_p2l + (size_t)K * (CH + 1);   // p + 1: 4 pi i_n(lam h_t)
+    const int p = P > 0 ? P : A.p, K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2;
+    double* rows = sm_p2l;                          // [K][CH + 1]
+    double* tab = sm_p2l + (size_t)K * (CH + 1);    // amm, alpha, beta
     const int b = blockIdx.x;
     const int le = A.x_box_le[b];
     const double cx = A.x_box_ctr[3 * b], cy = A.x_box_ctr[3 * b + 1], cz = A.x_box_ctr[3 * b + 2];
     const int lane = threadIdx.x;
+    for (int k = lane; k < p + 1 + 2 * Kp; k += 64) tab[k] = A.sh64[k];
+    const double *amm = tab, *al = tab + p + 1, *be = tab + p + 1 + Kp;
     double acc[(LPB_KMAX + 63) / 64];
 #pragma unroll
     for (int kk = 0; kk < (LPB_KMAX + 63) / 64; ++kk) acc[kk] = 0.0;
     for (int e = A.x_box_ptr[b]; e < A.x_box_ptr[b + 1]; ++e) {
-        const FmmDev& F = A.fmm[A.x_fmm[e]];
+        const int fid = A.x_fmm[e];
+        const FmmDev& F = A.fmm[fid];
         const int sl = A.x_sl[e];
         const int s0 = A.sl_start[sl], s1 = A.sl_start[sl + 1];
         if (F.kind == 1) {
@@ -144,12 +164,7 @@ __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A)
             }
             continue;
         }
-        __syncthreads();
-        if (lane == 0) {
-            double buf[LPB_MAX_P + 2];
-            bessel_i_all(p, F.lam_t * (2.0 * F.R / (double)(1 << A.x_box_lv[b])), buf);
-            for (int n = 0; n <= p; ++n) sc[n] = 4.0 * LPB_PI * buf[n];
-        }
+        const double* sc = A.fin_t + ((size_t)fid * (kMaxDepth + 1) + A.x_box_lv[b]) * (LPB_MAX_P + 1);
         const double ox = A.sl_ctr[3 * sl] - cx, oy = A.sl_ctr[3 * sl + 1] - cy, oz = A.sl_ctr[3 * sl + 2] - cz;
         for (int base = s0; base < s1; base += CH) {
             __syncthreads();
@@ -159,45 +174,16 @@ __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A)
                 const double vy = (double)A.s_uy[j] + (A.s_ly ? (double)A.s_ly[j] : 0.0) + oy;
                 const double vz = (double)A.s_uz[j] + (A.s_lz ? (double)A.s_lz[j] : 0.0) + oz;
                 const double r = sqrt(vx * vx + vy * vy + vz * vz);
-                double kn[LPB_MAX_P + 1];
-                bessel_k_all(p, F.lam_t * r, kn);
+                double kn[(P > 0 ? P : LPB_MAX_P) + 1];
+                bessel_k_fixed<P>(p, F.lam_t * r, kn);
                 const double q = (double)A.qs[j];
-                const double x = vx / r, y = vy / r, z = vz / r;
-                double wr = 1.0, wi = 0.0, amm = 0.28209479177387814;
-                for (int m = 0; m <= p; ++m) {
-                    if (m > 0) {
-                        const double nr = wr * x - wi * y;
-                        wi = wr * y + wi * x;
-                        wr = nr;
-                        amm *= sqrt((2.0 * m + 1.0) / (2.0 * m));
-                    }
-                    double pr = amm * wr, pi = amm * wi, qr = 0.0, qi = 0.0;
-                    for (int n = m; n <= p; ++n) {
-                        double cr, ci;
-                        if (n == m) {
-                            cr = pr;
-                            ci = pi;
-                        } else if (n == m + 1) {
-                            qr = sqrt(2.0 * m + 3.0) * z * pr;
-                            qi = sqrt(2.0 * m + 3.0) * z * pi;
-                            cr = qr;
-                            ci = qi;
-                        } else {
-                            const double nn = (double)n * n, mm = (double)m * m;
-                            const double a = sqrt((4.0 * nn - 1.0) / (nn - mm));
-                            const double bb = sqrt(((n - 1.0) * (n - 1.0) - mm) * (2.0 * n + 1.0) / ((nn - mm) * (2.0 * n - 3.0)));
-                            cr = a * z * qr - bb * pr;
-                            ci = a * z * qi - bb * pi;
-                            pr = qr;
-                            pi = qi;
-                            qr = cr;
-                            qi = ci;
-                        }
-                        const double g = q * sc[n] * kn[n];
-                        rows[(size_t)ire(n, m) * (CH + 1) + lane] = g * cr;
-                        if (m > 0) rows[(size_t)iim(n, m) * (CH + 1) + lane] = -g * ci;
-                    }
-                }
+                double* row = rows + lane;
+                unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
+                    // Lh_nm += q i_n(lam h) 4 pi k_n conj(Y_n^m)
+                    const double g = q * sc[n] * kn[n];
+                    row[(size_t)ire(n, m) * (CH + 1)] = g * cr;
+                    if (m > 0) row[(size_t)iim(n, m) * (CH + 1)] = -g * ci;
+                });
             }
             __syncthreads();
             const int cnt = min(CH, s1 - base);
@@ -222,15 +208,36 @@ __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A)
 template <typename T>
 void launch_m2p(const EvalArgs<T>& A, hipStream_t st)
 {
-    if (A.n_w_leaves > 0)
-        hipLaunchKernelGGL(k_m2p<T>, dim3(A.n_w_leaves), dim3(64), sizeof(double) * (A.K + A.p + 1), st, A);
+    const int Kp = (A.p + 1) * (A.p + 2) / 2;
+    if (A.n_w_leaves <= 0) return;
+    const size_t sm = sizeof(double) * (A.K + A.p + 1 + 2 * Kp);
+#define LPB_M2P(PP) \
+    case PP: hipLaunchKernelGGL((k_m2p<T, PP>), dim3(A.n_w_leaves), dim3(64), sm, st, A); break;
+    switch (A.p) {
+        LPB_M2P(2) LPB_M2P(3) LPB_M2P(4) LPB_M2P(5) LPB_M2P(6) LPB_M2P(7) LPB_M2P(8) LPB_M2P(9) LPB_M2P(10)
+        LPB_M2P(11) LPB_M2P(12) LPB_M2P(13) LPB_M2P(14) LPB_M2P(15)
+    default: hipLaunchKernelGGL((k_m2p<T, 0>), dim3(A.n_w_leaves), dim3(64), sm, st, A); break;
+    }
+#undef LPB_M2P
 }
 
 template <typename T>
 void launch_p2l(const EvalArgs<T>& A, hipStream_t st)
 {
-    if (A.n_x_boxes > 0)
-        hipLaunchKernelGGL(k_p2l<T>, dim3(A.n_x_boxes), dim3(64), sizeof(double) * ((size_t)A.K * 17 + A.p + 1), st, A);
+    // sources per row chunk: as many lanes as the LDS rows allow (<= 48 KiB)
+    const int Kp = (A.p + 1) * (A.p + 2) / 2;
+    if (A.n_x_boxes <= 0) return;
+    int ch = 64;
+    while (ch > 8 && sizeof(double) * (size_t)A.K * (ch + 1) > 48u * 1024u) ch >>= 1;
+    const size_t sm = sizeof(double) * ((size_t)A.K * (ch + 1) + A.p + 1 + 2 * Kp);
+#define LPB_P2L(PP) \
+    case PP: hipLaunchKernelGGL((k_p2l<T, PP>), dim3(A.n_x_boxes), dim3(64), sm, st, A, ch); break;
+    switch (A.p) {
+        LPB_P2L(2) LPB_P2L(3) LPB_P2L(4) LPB_P2L(5) LPB_P2L(6) LPB_P2L(7) LPB_P2L(8) LPB_P2L(9) LPB_P2L(10)
+        LPB_P2L(11) LPB_P2L(12) LPB_P2L(13) LPB_P2L(14) LPB_P2L(15)
+    default: hipLaunchKernelGGL((k_p2l<T, 0>), dim3(A.n_x_boxes), dim3(64), sm, st, A, ch); break;
+    }
+#undef LPB_P2L
 }
 
 template void launch_m2p<float>(const EvalArgs<float>&, hipStream_t);

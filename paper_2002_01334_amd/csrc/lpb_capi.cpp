@@ -441,6 +441,21 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
         UP(sh_amm, amm);
         UP(sh_alpha, al);
         UP(sh_beta, be);
+        const int Kp = (P.p + 1) * (P.p + 2) / 2;
+        std::vector<double> s64((size_t)P.p + 1 + 2 * Kp, 0.0);
+        double a64 = 0.28209479177387814;
+        for (int m = 0; m <= P.p; ++m) {
+            if (m > 0) a64 *= std::sqrt((2.0 * m + 1.0) / (2.0 * m));
+            s64[m] = a64;
+            if (m + 1 <= P.p) s64[P.p + 1 + ipk(m + 1, m)] = std::sqrt(2.0 * m + 3.0);
+            for (int n = m + 2; n <= P.p; ++n) {
+                double nn = (double)n * n, mm = (double)m * m;
+                s64[P.p + 1 + ipk(n, m)] = std::sqrt((4.0 * nn - 1.0) / (nn - mm));
+                s64[P.p + 1 + Kp + ipk(n, m)] =
+                    std::sqrt(((n - 1.0) * (n - 1.0) - mm) * (2.0 * n + 1.0) / ((nn - mm) * (2.0 * n - 3.0)));
+            }
+        }
+        UP(sh64, s64);
     }
     {
         // Bessel-ratio tables: factors of the it_n recurrence and series (p only) and
@@ -466,18 +481,32 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
         UP(bes_tab, tb);
         UP(ith_s, is);
         UP(ith_t, it);
+        // 4 pi i_n(lam h) of every FMM and level (the W- and X-list kernels)
+        std::vector<double> fs(P.fmm.size() * per, 0.0), ft(P.fmm.size() * per, 0.0);
+        for (size_t f = 0; f < P.fmm.size(); ++f)
+            for (int lv = 0; lv <= kMaxDepth; ++lv) {
+                double h = 2.0 * P.fmm[f].R / (double)(1 << lv);
+                bessel_i_all(P.p, P.fmm[f].lam_s * h, buf);
+                for (int n = 0; n <= P.p; ++n) fs[f * per + lv * (LPB_MAX_P + 1) + n] = 4.0 * LPB_PI * buf[n];
+                bessel_i_all(P.p, P.fmm[f].lam_t * h, buf);
+                for (int n = 0; n <= P.p; ++n) ft[f * per + lv * (LPB_MAX_P + 1) + n] = 4.0 * LPB_PI * buf[n];
+            }
+        UP(fin_s, fs);
+        UP(fin_t, ft);
     }
     A.n_tiles = (int)P.tiles.size();
     // work lists
     std::vector<int> p2m, l2p, pfree, rleaf, rslot, m2lb;
     for (size_t i = 0; i < P.sl_me.size(); ++i)
         if (P.sl_me[i] >= 0) p2m.push_back((int)i);
-    // free-space near field: a work item is T targets of one leaf on T x S
+    // free-space near field: a work item is T <= 64 targets of one leaf on T x S
     // lanes of a 64-lane block, each target's sources split S ways.  A leaf of
-    // n targets takes P items of T = ceil(n / P) targets, S = min(4, 64 / T),
-    // with P minimising the lane-passes over the sources P / S (ties: fewer
-    // items), so that few lanes idle (a leaf of 40 takes 2 items of 20 x 3
-    // instead of 2 passes of 32 lanes); most source-heavy items first
+    // n targets takes P >= ceil(n / 64) items of T = ceil(n / P) targets,
+    // S = min(4, 64 / T), with P minimising the lane-passes over the sources
+    // P / S (ties: fewer items), so that few lanes idle (a leaf of 40 takes 2
+    // items of 20 x 3 instead of 2 passes of 32 lanes); most source-heavy
+    // items first.  (S saturates at T <= 16, so P beyond ceil(n / 16) never
+    // helps.)
     std::vector<int> pfree_t0, pfree_ts;
     {
         std::vector<std::array<int64_t, 4>> wl;   // (-cost class, leaf, first target, T | S << 8)
@@ -488,7 +517,9 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
             const int n = P.tl_start[i + 1] - P.tl_start[i];
             int bestP = 1, bestS = 1;
             double best = 1e30;
-            for (int np = 1; np <= 64 && np <= n; ++np) {
+            const int np0 = std::max(1, (n + 63) / 64), np1 = std::min(n, (n + 15) / 16 + 1);
+            bestP = np0;
+            for (int np = np0; np <= np1; ++np) {
                 const int nt = (n + np - 1) / np;
                 if (nt > 64) continue;
                 const int S = std::max(1, std::min(4, 64 / nt));
@@ -964,7 +995,7 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
     if (o.autotune < 0 || o.autotune > 2) return fail(nullptr, LPB_EINVAL, "autotune must be 0, 1 or 2");
     if (o.schedule < 0 || (o.schedule >> 4) > 7)
         return fail(nullptr, LPB_EINVAL, "schedule codes out of range");
-    if (o.adaptive != 0 && o.adaptive != 1) return fail(nullptr, LPB_EINVAL, "adaptive must be 0 or 1");
+    if (o.adaptive < 0 || o.adaptive > 2) return fail(nullptr, LPB_EINVAL, "adaptive must be 0, 1 or 2");
     int ndev = 0;
     hipError_t e = hipGetDeviceCount(&ndev);
     if (e != hipSuccess || ndev <= 0) return fail(nullptr, LPB_EDEVICE, "no HIP device available");

@@ -85,6 +85,10 @@ struct EvalArgs {
     const int *x_fmm, *x_sl;
     const int64_t* x_vec;
     const double* pt_vec;
+    // 4 pi i_n(lam h) per FMM and level (source-side lambda for M2P, target
+    // side for P2L), (kMaxDepth + 1) x (LPB_MAX_P + 1) per FMM, and the
+    // solid-harmonic recurrence coefficients in FP64 (amm[p+1], alpha[Kp], beta[Kp])
+    const double *fin_s, *fin_t, *sh64;
 };
 
 struct EvalSched {

@@ -203,7 +203,7 @@ struct Plan {
     // entries evaluate precomputed point operators (one K-vector per target
     // point of the leaf, or per source point of the leaf); free-space entries
     // the closed forms.
-    int adaptive = 0;
+    int adaptive = 0;   // 0 uniform, 1 adaptive (with the reaction sets' separation rule), 2 occupancy only
     std::vector<int> w_ptr, w_fmm, w_me, w_lv;
     std::vector<double> w_ctr;
     std::vector<int64_t> w_vec;
@@ -256,12 +256,16 @@ public:
     // their leaf centres.  False with msg set on failure.
     virtual bool leaves(int handle, int H, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_start,
                         std::string& msg) = 0;
-    // Adaptive leaves: boxes divided while they hold more than cap points
-    // (down to kMaxDepth); leaf_key at each leaf's own level leaf_lv, in
-    // Morton order, leaf_start its first point; computes the points' offsets
-    // from their leaf centres.  False with msg set on failure.
-    virtual bool leaves_adaptive(int handle, int cap, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
-                                 std::vector<int>& leaf_start, std::string& msg) = 0;
+    // Adaptive leaves: boxes divided while they hold more than cap points,
+    // and with sep (a reaction set) while they are wider than the distance
+    // of their nearest point from the interface plane, up to 3 levels below
+    // the occupancy rule's (all down to kMaxDepth; distances and widths in
+    // fine cells, the plane between z cells 32767 and 32768); leaf_key at
+    // each leaf's own level leaf_lv, in Morton order, leaf_start its first
+    // point; computes the points' offsets from their leaf centres.  False
+    // with msg set on failure.
+    virtual bool leaves_adaptive(int handle, int cap, bool sep, std::vector<uint64_t>& leaf_key,
+                                 std::vector<int>& leaf_lv, std::vector<int>& leaf_start, std::string& msg) = 0;
     // lpb_status of the last failure (LPB_ENOMEM or LPB_EDEVICE)
     virtual int failure() const = 0;
 };

@@ -841,7 +841,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                 return msg;
             }
             if (P.adaptive) {
-                if (!pb.leaves_adaptive(V.handle, cap, V.lkey, V.llv, V.lstart, msg)) {
+                if (!pb.leaves_adaptive(V.handle, cap, false, V.lkey, V.llv, V.lstart, msg)) {
                     *status = pb.failure();
                     return msg;
                 }
@@ -916,7 +916,8 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
         // separation: leaves no wider than the smallest tau keep every target and
         // image one box away from the interface plane, so reaction U-lists are
         // empty (Remark 1); at most 3 levels above the occupancy depth.
-        // Adaptive trees divide by occupancy alone, each set on its own.
+        // Adaptive trees divide each set on its own: by occupancy and (mode 1)
+        // by the same separation per box, up to 3 levels below occupancy.
         if (!P.adaptive) {
             int hs = 0;
             while (hs < kMaxDepth && 2.0 * R / (double)(1 << hs) > tmin) ++hs;
@@ -930,7 +931,7 @@ std::string build_plan(Plan& P, const std::vector<Medium>& media, const std::vec
                     PtsInfo& V = sets[l][sd][tg];
                     std::string msg;
                     if (V.handle < 0) continue;
-                    if (P.adaptive ? !pb.leaves_adaptive(V.handle, cap, V.lkey, V.llv, V.lstart, msg)
+                    if (P.adaptive ? !pb.leaves_adaptive(V.handle, cap, P.adaptive == 1, V.lkey, V.llv, V.lstart, msg)
                                    : !pb.leaves(V.handle, H, V.lkey, V.lstart, msg)) {
                         *status = pb.failure();
                         return msg;

@@ -24,7 +24,7 @@ public:
              int counts[kMaxDepth + 1], std::string& msg) override;
     bool leaves(int handle, int H, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_start,
                 std::string& msg) override;
-    bool leaves_adaptive(int handle, int cap, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
+    bool leaves_adaptive(int handle, int cap, bool sep, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
                          std::vector<int>& leaf_start, std::string& msg) override;
     int failure() const override { return failure_; }
     // The sets `sets` (in order, n_total points) concatenated into the

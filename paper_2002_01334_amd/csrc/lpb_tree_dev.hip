@@ -377,8 +377,8 @@ bool DevPointBuilder::leaves(int handle, int H, std::vector<uint64_t>& leaf_key,
     return ok;
 }
 
-bool DevPointBuilder::leaves_adaptive(int handle, int cap, std::vector<uint64_t>& leaf_key, std::vector<int>& leaf_lv,
-                                      std::vector<int>& leaf_start, std::string& msg)
+bool DevPointBuilder::leaves_adaptive(int handle, int cap, bool sep, std::vector<uint64_t>& leaf_key,
+                                      std::vector<int>& leaf_lv, std::vector<int>& leaf_start, std::string& msg)
 {
     Set& s = sets_[handle];
     const int n = s.n;
@@ -390,10 +390,31 @@ bool DevPointBuilder::leaves_adaptive(int handle, int cap, std::vector<uint64_t>
     if (!check(hipMemcpyAsync(k.data(), s.key, n * sizeof(uint64_t), hipMemcpyDeviceToHost, st_), "key download", msg) ||
         !check(hipStreamSynchronize(st_), "key download", msg))
         return false;
-    // divide from the root down: a box of more than cap points (above
-    // kMaxDepth) is replaced by its non-empty children, in Morton order
-    std::function<void(int, int, int)> divide = [&](int a, int b, int lv) {
-        if (b - a <= cap || lv == kMaxDepth) {
+    // divide from the root down (above kMaxDepth) a box of more than cap
+    // points, and with sep a box that is wider than the distance of its
+    // nearest point from the interface plane, up to 3 levels below the level
+    // where the occupancy rule stopped (the plane lies between fine cells
+    // 32767 and 32768 in z); a divided box is replaced by its non-empty
+    // children, in Morton order
+    std::function<void(int, int, int, int)> divide = [&](int a, int b, int lv, int locc) {
+        bool split = false;
+        if (lv < kMaxDepth) {
+            if (b - a > cap) {
+                split = true;
+                locc = -1;
+            } else {
+                if (locc < 0) locc = lv;
+                if (sep && lv < locc + 3) {
+                    uint32_t dmin = 0xffffffffu;
+                    for (int i = a; i < b; ++i) {
+                        const uint32_t cz = morton_compact3(k[i]);
+                        dmin = std::min(dmin, cz >= 32768u ? cz - 32768u : 32767u - cz);
+                    }
+                    split = (1u << (kCellBits - lv)) > dmin;
+                }
+            }
+        }
+        if (!split) {
             leaf_key.push_back(k[a] >> (3 * (kCellBits - lv)));
             leaf_lv.push_back(lv);
             leaf_start.push_back(a);
@@ -403,11 +424,11 @@ bool DevPointBuilder::leaves_adaptive(int handle, int cap, std::vector<uint64_t>
         for (int c = a; c < b;) {
             const uint64_t last = (((k[c] >> sh) + 1) << sh) - 1;
             const int e = (int)(std::upper_bound(k.begin() + c, k.begin() + b, last) - k.begin());
-            divide(c, e, lv + 1);
+            divide(c, e, lv + 1, locc);
             c = e;
         }
     };
-    divide(0, n, 0);
+    divide(0, n, 0, -1);
     const int nleaf = (int)leaf_key.size();
     int* ls = (int*)scratch(kLeafStart, nleaf * sizeof(int));
     int* lv = (int*)scratch(kLeafLv, nleaf * sizeof(int));

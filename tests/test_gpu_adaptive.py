@@ -31,15 +31,16 @@ def clustered():
     return inputs.three_layer_interface_clusters(120, seed=5)
 
 
-def test_adaptive_leaves_match_oracle(lpb, clustered):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_adaptive_leaves_match_oracle(lpb, clustered, mode):
     prob = clustered
     ly = O.Layers(prob.eps, prob.lam, prob.d)
-    ctx = lpb.Context(p=2, leaf_cap=10, adaptive=1)
+    ctx = lpb.Context(p=2, leaf_cap=10, adaptive=mode)
     ctx.set_layers(prob.eps, prob.lam, prob.d)
     ctx.build_tree(prob.x, prob.y, prob.z)
     for c in range(O.num_components(3)):
         info = ctx.fmm_info(c, keys=True)
-        d, tk, sk, root, tl, sl = O.component_tree(ly, prob.x, prob.y, prob.z, c, leaf_cap=10, adaptive=True)
+        d, tk, sk, root, tl, sl = O.component_tree(ly, prob.x, prob.y, prob.z, c, leaf_cap=10, adaptive=mode)
         assert np.array_equal(info["root"], root), c
         tkey = tk | (tl.astype(np.uint64) << np.uint64(58))
         skey = sk | (sl.astype(np.uint64) << np.uint64(58))
@@ -47,17 +48,22 @@ def test_adaptive_leaves_match_oracle(lpb, clustered):
     ctx.close()
 
 
-@pytest.mark.parametrize("p", [4, 7])
-def test_adaptive_fp64_matches_oracle_fmm_per_slot(lpb, clustered, p):
+@pytest.mark.parametrize("p,mode", [(4, 2), (7, 2), (7, 1)])
+def test_adaptive_fp64_matches_oracle_fmm_per_slot(lpb, clustered, p, mode):
+    # mode 2 (occupancy alone) puts thousands of reaction (point, box) pairs on the W- and
+    # X-lists; mode 1 (reaction sets also divided near the interface) few or none
     prob = clustered
     ly = O.Layers(prob.eps, prob.lam, prob.d)
-    ctx, phi = run(lpb, prob, p, 10, adaptive=1)
+    ctx, phi = run(lpb, prob, p, 10, adaptive=mode)
     parts = ctx.debug_parts()
     st = ctx.stats()
     ctx.close()
-    print(f"adaptive p={p}: W {st['n_w_pairs']} X {st['n_x_pairs']} point ops {st['n_point_ops']}", flush=True)
-    assert st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0 and st["n_point_ops"] > 0
-    ref, cphi, ost = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=10, components=True, adaptive=True)
+    print(f"adaptive {mode} p={p}: W {st['n_w_pairs']} X {st['n_x_pairs']} point ops {st['n_point_ops']}",
+          flush=True)
+    assert st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0
+    if mode == 2:
+        assert st["n_point_ops"] > 1000
+    ref, cphi, ost = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, p, leaf_cap=10, components=True, adaptive=mode)
     assert st["n_w_pairs"] == int(ost[:, 6].sum()) and st["n_x_pairs"] == int(ost[:, 7].sum())
     assert st["n_m2l_pairs"] == int(ost[:, 3].sum())
     assert st["n_p2p_pairs"] == int(ost[:, 4].sum()) + prob.n
@@ -66,15 +72,16 @@ def test_adaptive_fp64_matches_oracle_fmm_per_slot(lpb, clustered, p):
         assert e <= 1e-10, (key, e)
 
 
-def test_adaptive_mixed_matches_fp64_and_oracle(lpb, clustered):
+@pytest.mark.parametrize("mode", [1, 2])
+def test_adaptive_mixed_matches_fp64_and_oracle(lpb, clustered, mode):
     prob = clustered
     ly = O.Layers(prob.eps, prob.lam, prob.d)
-    ctx, phi64 = run(lpb, prob, 7, 10, adaptive=1)
+    ctx, phi64 = run(lpb, prob, 7, 10, adaptive=mode)
     ctx.close()
-    ctx, phi32 = run(lpb, prob, 7, 10, precision=lpb.LPB_MIXED, adaptive=1)
+    ctx, phi32 = run(lpb, prob, 7, 10, precision=lpb.LPB_MIXED, adaptive=mode)
     ctx.close()
     assert err2(phi32, phi64, prob.layer) <= 1e-6
-    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 7, leaf_cap=10, adaptive=True)
+    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 7, leaf_cap=10, adaptive=mode)
     assert err2(phi32, ref, prob.layer) <= 1e-6
 
 
@@ -97,7 +104,7 @@ def test_adaptive_free_space_tiled_levels(lpb):
         st = ctx.stats()
         ctx.close()
         assert st["n_m2l_tile_pairs"] > 0 and st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0
-    ref = O.fmm(ly, x, y, z, q, 8, leaf_cap=12, adaptive=True)
+    ref = O.fmm(ly, x, y, z, q, 8, leaf_cap=12, adaptive=1)
     layer = np.zeros(n, dtype=int)
     assert err2(out[lpb.LPB_FP64], ref, layer, 1) <= 1e-10
     assert err2(out[lpb.LPB_MIXED], out[lpb.LPB_FP64], layer, 1) <= 1e-6
