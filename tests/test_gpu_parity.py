@@ -501,3 +501,26 @@ def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
         assert np.array_equal(g.evaluate(q), e.evaluate(q))
     g.close()
     e.close()
+
+
+def test_near_field_of_leaves_above_4096_targets(lpb):
+    # one medium, 9000 of 10^4 charges in a cluster far smaller than any box at
+    # the depth the leaf cap 6000 allows: a leaf holds more than 4096 targets,
+    # so its near field is split over more than 64 work items of <= 64 targets
+    rng = np.random.default_rng(3)
+    n = 10000
+    P = np.vstack([rng.uniform(-1, 1, (1000, 3)), rng.normal(0.2, 1e-3, (9000, 3))])
+    x, y, z = P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy()
+    q = rng.uniform(-1, 1, n)
+    ly = O.Layers([2.0], [0.8], [])
+    out = {}
+    for prec in (lpb.LPB_FP64, lpb.LPB_MIXED):
+        ctx = lpb.Context(p=4, leaf_cap=6000, precision=prec)
+        ctx.set_layers([2.0], [0.8], [])
+        ctx.build_tree(x, y, z)
+        out[prec] = ctx.evaluate(q)
+        ctx.close()
+    ref = O.fmm(ly, x, y, z, q, 4, leaf_cap=6000)
+    layer = np.zeros(n, dtype=int)
+    assert err2(out[lpb.LPB_FP64], ref, layer, 1) <= 1e-10
+    assert err2(out[lpb.LPB_MIXED], out[lpb.LPB_FP64], layer, 1) <= 1e-6
