@@ -108,3 +108,28 @@ def test_adaptive_free_space_tiled_levels(lpb):
     layer = np.zeros(n, dtype=int)
     assert err2(out[lpb.LPB_FP64], ref, layer, 1) <= 1e-10
     assert err2(out[lpb.LPB_MIXED], out[lpb.LPB_FP64], layer, 1) <= 1e-6
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_adaptive_batch_matches_single_systems_bitwise(lpb, mode):
+    # three interface-clustered systems with different media in one batched
+    # evaluation on adaptive trees: each system's potential bit for bit that
+    # of its own context (the W/X lists and point operators of every system
+    # share the stage launches)
+    probs = [inputs.three_layer_interface_clusters(n, seed=s) for n, s in ((90, 3), (60, 4), (120, 5))]
+    probs[1].eps = np.array([2.0, 30.0, 5.0])
+    probs[1].lam = np.array([0.7, 2.5, 1.1])
+    singles = []
+    for pr in probs:
+        ctx, phi = run(lpb, pr, 6, 8, adaptive=mode)
+        ctx.close()
+        singles.append(phi)
+    ctx = lpb.Context(p=6, leaf_cap=8, adaptive=mode)
+    ctx.set_systems([p.eps for p in probs], [p.lam for p in probs], [p.d for p in probs])
+    ctx.build_trees([p.x for p in probs], [p.y for p in probs], [p.z for p in probs])
+    outs = ctx.evaluate_batch([p.q for p in probs])
+    st = ctx.stats()
+    ctx.close()
+    assert st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0
+    for a, b in zip(outs, singles):
+        assert np.array_equal(a, b)
