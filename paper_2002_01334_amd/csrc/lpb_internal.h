@@ -17,6 +17,7 @@ constexpr int kCellBits = 16;   // fine cell bits per axis
 constexpr int kTileMinLevel = 4;  // free-space levels kTileMinLevel..kTileMaxLevel use the tiled MFMA M2L
 constexpr int kTileMaxLevel = 8;  // (coarser grids are mostly boundary: their pairs go to the batched kernel)
 constexpr int kTilePB = 4;        // parents per axis of an M2L tile (4^3 parents -> 64 target boxes)
+constexpr int kTileMinBoxes = 16; // tiles with fewer target boxes give their pairs to the batched list
 constexpr int kVOffsets = 189;    // V-list offsets of one child octant
 // Tiled levels store one operator per offset with non-negative components;
 // the offset (sx dx, sy dy, sz dz) uses it between sign flips D = diag(+-1)

@@ -464,6 +464,8 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         return op;
     };
     // tiled levels of a free-space FMM: dense grids, operator table, tiles
+    // (in_tile[lv][box]: the target box belongs to a tile)
+    std::vector<std::vector<char>> in_tile(kMaxDepth + 1);
     const int tiled_min = std::max(2, kTileMinLevel);
     const int tiled_max = (F.kind == 0) ? std::min(H, kTileMaxLevel) : 1;
     for (int lv = tiled_min; lv <= tiled_max; ++lv) {
@@ -494,21 +496,29 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
         int fl = (int)P.tfl.size();
         P.tfl.push_back(t);
         int np = nside / 2;
+        std::vector<char>& mark = in_tile[lv];
+        mark.assign(TB[lv].mkey.size(), 0);
+        std::vector<int> boxes;
         for (int bx = 0; bx < np; bx += kTilePB)
             for (int by = 0; by < np; by += kTilePB)
                 for (int bz = 0; bz < np; bz += kTilePB)
                     for (int o = 0; o < 8; ++o) {
-                        bool any = false;
-                        for (int i = 0; i < kTilePB && !any; ++i)
-                            for (int j = 0; j < kTilePB && !any; ++j)
-                                for (int k = 0; k < kTilePB && !any; ++k) {
+                        boxes.clear();
+                        for (int i = 0; i < kTilePB; ++i)
+                            for (int j = 0; j < kTilePB; ++j)
+                                for (int k = 0; k < kTilePB; ++k) {
                                     int tx = 2 * (bx + i) + ((o >> 2) & 1), ty = 2 * (by + j) + ((o >> 1) & 1),
                                         tz = 2 * (bz + k) + (o & 1);
-                                    if (tx < nside && ty < nside && tz < nside &&
-                                        P.grid_le[t.grid_off + ((size_t)tx * nside + ty) * nside + tz] >= 0)
-                                        any = true;
+                                    if (tx < nside && ty < nside && tz < nside) {
+                                        const int le = P.grid_le[t.grid_off + ((size_t)tx * nside + ty) * nside + tz];
+                                        if (le >= 0) boxes.push_back(le - TT.off[lv]);
+                                    }
                                 }
-                        if (any) P.tiles.push_back({fl, o, bx, by, bz});
+                        // a sparse tile's products are mostly padding: its target boxes'
+                        // pairs go to the batched list instead
+                        if ((int)boxes.size() < kTileMinBoxes) continue;
+                        P.tiles.push_back({fl, o, bx, by, bz});
+                        for (int b : boxes) mark[b] = 1;
                     }
     }
     for (int lv = 2; lv <= H; ++lv) {
@@ -540,7 +550,12 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                 return (int64_t)at(x1, y1, z1) - at(x0, y1, z1) - at(x1, y0, z1) - at(x1, y1, z0) + at(x0, y0, z1) +
                        at(x0, y1, z0) + at(x1, y0, z0) - at(x0, y0, z0);
             };
+            bool all = true;
             for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
+                if (!in_tile[lv][k]) {
+                    all = false;
+                    continue;
+                }
                 const int tx = TB[lv].ix[k], ty = TB[lv].iy[k], tz = TB[lv].iz[k];
                 const int px = 2 * (tx >> 1), py = 2 * (ty >> 1), pz = 2 * (tz >> 1);
                 const int64_t np = box(px - 2, px + 3, py - 2, py + 3, pz - 2, pz + 3) -
@@ -548,7 +563,8 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
                 P.n_m2l_tile_pairs += np;
                 P.n_m2l_pairs += np;
             }
-            continue;
+            if (all) continue;
+            // the boxes of sparse tiles: listed below like an untiled level
         }
         // parents whose children can hold source boxes: those within the
         // cell range of the level's source boxes (a reaction FMM's images all
@@ -562,6 +578,7 @@ void add_lists(Plan& P, Staging& S, int fid, const TreeB& ST, const TreeB& TT)
             }
         }
         for (int k = 0; k < (int)TB[lv].mkey.size(); ++k) {
+            if (tiled && in_tile[lv][k]) continue;
             int tx = TB[lv].ix[k], ty = TB[lv].iy[k], tz = TB[lv].iz[k];
             int le = TT.off[lv] + k;
             const int qx0 = std::max((tx >> 1) - 1, qlo[0]), qx1 = std::min((tx >> 1) + 1, qhi[0]);
