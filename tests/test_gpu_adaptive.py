@@ -133,3 +133,34 @@ def test_adaptive_batch_matches_single_systems_bitwise(lpb, mode):
     assert st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0
     for a, b in zip(outs, singles):
         assert np.array_equal(a, b)
+
+
+def test_adaptive_four_layer_stack_fp64_matches_oracle(lpb):
+    # general L (Sec. 2.1): a 4-layer stack on adaptive trees (occupancy alone, so the
+    # reaction W/X lists of all 4 L^2 = 36 components are busy), FP64 against the oracle
+    prob = inputs.stack(70, 4, seed=2)
+    ly = O.Layers(prob.eps, prob.lam, prob.d)
+    ctx, phi = run(lpb, prob, 5, 6, adaptive=2)
+    st = ctx.stats()
+    ctx.close()
+    assert st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0
+    ref = O.fmm(ly, prob.x, prob.y, prob.z, prob.q, 5, leaf_cap=6, adaptive=2)
+    assert err2(phi, ref, prob.layer, 4) <= 1e-10
+
+
+def test_adaptive_orders_beyond_the_fixed_kernels(lpb):
+    # p = 17 (mixed only): the W/X kernels with the order read at run time, one medium
+    rng = np.random.default_rng(12)
+    n = 6000
+    P = np.vstack([rng.uniform(-1, 1, (n // 2, 3)), np.clip(rng.normal(-0.2, 0.04, (n - n // 2, 3)), -1, 1)])
+    x, y, z = P[:, 0].copy(), P[:, 1].copy(), P[:, 2].copy()
+    q = rng.uniform(-1, 1, n)
+    ctx = lpb.Context(p=17, leaf_cap=10, precision=lpb.LPB_MIXED, adaptive=1)
+    ctx.set_layers([2.0], [0.8], [])
+    ctx.build_tree(x, y, z)
+    phi = ctx.evaluate(q)
+    st = ctx.stats()
+    ctx.close()
+    assert st["n_w_pairs"] > 0 and st["n_x_pairs"] > 0
+    ref = O.fmm(O.Layers([2.0], [0.8], []), x, y, z, q, 17, leaf_cap=10, adaptive=1)
+    assert err2(phi, ref, np.zeros(n, dtype=int), 1) <= 1e-6
