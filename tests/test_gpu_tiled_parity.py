@@ -76,12 +76,15 @@ def test_tiled_m2l_fp64_and_mixed_vs_oracle_fmm(lpb, tree, p):
 
 
 def sparse_lattice(seed, n=400):
-    """One charge near the centre of each of n random cells of a 16^3 lattice
-    over [-1, 1]^3 (plus the two corner cells, which fix the bounding cube):
-    with leaf cap 1 no two charges share a level-4 box, so the tree has depth
-    4 with few V-list pairs."""
+    """One charge near the centre of each of n random cells of the 8^3 corner
+    block of a 16^3 lattice over [-1, 1]^3 (plus the far corner cell, which
+    with the near one fixes the bounding cube): with leaf cap 1 no two charges
+    share a level-4 box, so the tree has depth 4 with few V-list pairs, and the
+    8^3 block's M2L tiles hold about 50 of their 64 target boxes (tiles of
+    fewer than 16 give their pairs to the batched list)."""
     rng = np.random.default_rng(seed)
-    cells = np.unique(np.concatenate([rng.choice(16**3, n, replace=False), [0, 16**3 - 1]]))
+    blk = rng.choice(8**3, n, replace=False)
+    cells = np.unique(np.concatenate([(blk // 64) * 256 + ((blk // 8) % 8) * 16 + blk % 8, [0, 16**3 - 1]]))
     ijk = (cells // 256, (cells // 16) % 16, cells % 16)
     x, y, z = [-1 + (2 * i + 1) / 16.0 + rng.uniform(-0.01, 0.01, len(cells)) for i in ijk]
     return x, y, z, rng.uniform(-1, 1, len(cells))
