@@ -69,24 +69,25 @@ __device__ __attribute__((always_inline)) inline void bessel_k_fixed(int p_rt, d
 }
 
 // M2P: one 64-lane block per target leaf with W-list entries, one lane per
-// target (64 at a time); the entry's expansion is staged in LDS in FP64.
+// target (64 at a time), every lane reading the entry's expansion itself.
 template <typename T, int P>
 __global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
 {
     extern __shared__ double sm_m2p[];
     const int p = P > 0 ? P : A.p, K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2;
-    double* M = sm_m2p;                 // K
-    double* tab = sm_m2p + K;           // amm[p+1], alpha[Kp], beta[Kp]
+    double* tab = sm_m2p;               // amm[p+1], alpha[Kp], beta[Kp]
     const int leaf = A.w_leaves[blockIdx.x];
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const int e0 = A.w_ptr[leaf], e1 = A.w_ptr[leaf + 1];
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
     const int lane = threadIdx.x;
     for (int k = lane; k < p + 1 + 2 * Kp; k += 64) tab[k] = A.sh64[k];
+    __syncthreads();
     const double *amm = tab, *al = tab + p + 1, *be = tab + p + 1 + Kp;
     for (int base = t0; base < t1; base += 64) {
         const int j = base + lane;
         const bool act = j < t1;
+        if (!act) break;
         double ux = 0.0, uy = 0.0, uz = 0.0;
         if (act) {
             ux = (double)A.t_ux[j] + (A.t_lx ? (double)A.t_lx[j] : 0.0);
@@ -97,15 +98,13 @@ __global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
         for (int e = e0; e < e1; ++e) {
             const int fid = A.w_fmm[e];
             const FmmDev& F = A.fmm[fid];
-            const int me = A.w_me[e];
-            __syncthreads();
-            for (int k = lane; k < K; k += 64) M[k] = (double)A.me[(size_t)me * A.KP + k];
-            __syncthreads();
-            if (!act) continue;
+            // the entry's expansion: the same addresses in every lane (read
+            // through the caches, no staging or barriers)
+            const T* __restrict__ M = A.me + (size_t)A.w_me[e] * A.KP;
             if (F.kind == 1) {
                 const double* v = A.pt_vec + A.w_vec[e] + (int64_t)(j - t0) * K;
                 double s = 0.0;
-                for (int k = 0; k < K; ++k) s += v[k] * M[k];
+                for (int k = 0; k < K; ++k) s += v[k] * (double)M[k];
                 acc += s;
                 continue;
             }
@@ -118,12 +117,12 @@ __global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
             const double* sc = A.fin_s + ((size_t)fid * (kMaxDepth + 1) + A.w_lv[e]) * (LPB_MAX_P + 1);
             double s = 0.0;
             unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
-                const double re = M[ire(n, m)], im = m ? M[iim(n, m)] : 0.0;
+                const double re = (double)M[ire(n, m)], im = m ? (double)M[iim(n, m)] : 0.0;
                 s += (m ? 2.0 : 1.0) * sc[n] * kn[n] * (re * cr - im * ci);
             });
             acc += F.far_factor * s;
         }
-        if (act) A.parts[A.t_out[j]] += acc;
+        A.parts[A.t_out[j]] += acc;
     }
 }
 
@@ -210,7 +209,7 @@ void launch_m2p(const EvalArgs<T>& A, hipStream_t st)
 {
     const int Kp = (A.p + 1) * (A.p + 2) / 2;
     if (A.n_w_leaves <= 0) return;
-    const size_t sm = sizeof(double) * (A.K + A.p + 1 + 2 * Kp);
+    const size_t sm = sizeof(double) * (A.p + 1 + 2 * Kp);
 #define LPB_M2P(PP) \
     case PP: hipLaunchKernelGGL((k_m2p<T, PP>), dim3(A.n_w_leaves), dim3(64), sm, st, A); break;
     switch (A.p) {

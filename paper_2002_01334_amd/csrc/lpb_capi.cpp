@@ -362,10 +362,10 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
     UP(bw_src, P.bw_src);
     UP(bw_dst, P.bw_dst);
     UP(bw_xc, P.bw_xc);
+    // cos and sin (m phi), m = 0..p, of the kXfDirs V-list directions:
+    // e^{i phi} = (-dx - i dy) / |(dx, dy)| (phi = 0 for dx = dy = 0), powers in long double
+    std::vector<T> rt((size_t)kXfDirs * (P.p + 1) * 2);
     {
-        // cos and sin (m phi), m = 0..p, of the kXfDirs V-list directions:
-        // e^{i phi} = (-dx - i dy) / |(dx, dy)| (phi = 0 for dx = dy = 0), powers in long double
-        std::vector<T> rt((size_t)kXfDirs * (P.p + 1) * 2);
         for (int dir = 0; dir < kXfDirs; ++dir) {
             const long double dx = dir / 7 - 3, dy = dir % 7 - 3, r = std::sqrt(dx * dx + dy * dy);
             const long double c1 = r > 0 ? -dx / r : 1.0L, s1 = r > 0 ? -dy / r : 0.0L;
@@ -409,6 +409,27 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
                     if (m > 0) sg[(size_t)code * A.KP + iim(n, m)] = (T)im;
                 }
         UP(refl_sign, sg);
+        // the same transforms per (code, row) as one multiply-add,
+        // row' = a row + b partner row: reflections (sign, 0), rotations
+        // (1, 0) at m = 0, else (cos, sin) on Re rows, (cos, -sin) on Im rows
+        std::vector<T> ab((size_t)(kXfRotate + kXfDirs) * P.K * 2, T(0));
+        for (int code = 0; code < kXfRotate + kXfDirs; ++code)
+            for (int n = 0; n <= P.p; ++n)
+                for (int m = 0; m <= n; ++m) {
+                    T* re = &ab[((size_t)code * P.K + ire(n, m)) * 2];
+                    T* im = m > 0 ? &ab[((size_t)code * P.K + iim(n, m)) * 2] : nullptr;
+                    if (code < kXfRotate) {
+                        re[0] = sg[(size_t)code * A.KP + ire(n, m)];
+                        if (im) im[0] = sg[(size_t)code * A.KP + iim(n, m)];
+                    } else if (m == 0) {
+                        re[0] = T(1);
+                    } else {
+                        const T* r = &rt[((size_t)(code - kXfRotate) * (P.p + 1) + m) * 2];
+                        re[0] = r[0]; re[1] = r[1];
+                        im[0] = r[0]; im[1] = -r[1];
+                    }
+                }
+        UP(xf_ab, ab);
     }
     UP(oct_codes, P.oct_codes);
     UP(swz_index, P.swz_index);

@@ -40,6 +40,8 @@ struct EvalArgs {
     const int *bw_term_ptr, *bw_op, *bw_src, *bw_dst;
     const int* bw_xc;           // per column transform code (-1 none, 0..7 reflection, kXfRotate + dir rotation)
     const T* rot_tab;           // [kXfDirs][p+1][2]: cos, sin (m phi) of each V-list direction
+    const T* xf_ab;             // [kXfRotate + kXfDirs][K][2]: (a, b) with row' = a row + b partner row,
+                                //   the frame change of each transform code per coefficient row
     T* m2l_scratch;     // one row of K per untiled V-list pair
     const int *p2p_ptr, *p2p_src;
     const int *rp_ptr, *rp_fmm, *rp_src;   // reaction near field: per target leaf, (FMM, source leaf)

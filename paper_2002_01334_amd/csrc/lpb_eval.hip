@@ -176,8 +176,11 @@ __device__ inline void column_xform(T* Bs, int NTP, int p, int K, int KP, int co
     }
 }
 
-// RBF = ceil(KB / 4): the row blocks per wave of a whole item, which also
-// sizes the source staging; GY blocks along y split them (RB per wave each).
+// RBF = ceil(KB / (4 / WC)): the row blocks per wave of a whole item, which
+// also sizes the source staging; GY blocks along y split them (RB per wave
+// each).  WC = 2 arranges the four waves as 2 x 2 (row blocks x halves of
+// the 64 columns), so that KB = 2 or 6 row blocks give every wave the same
+// number of products (with WC = 1 one wave of four would idle); FP32 only.
 // XF (untiled V-list pairs): the sources are brought into the frame of the
 // stored operator here; the results stay in that frame (the reduction over a
 // box's pairs applies the inverse transform).
@@ -188,7 +191,7 @@ __device__ inline void column_xform(T* Bs, int NTP, int p, int K, int KP, int co
 // do not depend on the grid or the order.
 // MT: items of several terms (M2M: one per child octant), summed with Kahan
 // compensation; single-term items (L2L, untiled M2L) store the product as is
-template <typename T, int RBF, bool XF, int GY, bool MT>
+template <typename T, int RBF, bool XF, int GY, bool MT, int WC>
 __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* out, const int* __restrict__ term_ptr,
                                                  const int* __restrict__ term_op, const int* __restrict__ term_src,
                                                  const int* __restrict__ dst, int wbase, int nitems, int mode, int K,
@@ -198,8 +201,9 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
 {
     typedef typename Vec4<T>::type V4;
     static_assert(GY == 1 || !XF, "results with a transform need whole columns");
+    static_assert(WC == 1 || (WC == 2 && GY == 1), "column halves only with whole items per block");
     constexpr int RB = (RBF + GY - 1) / GY;
-    constexpr int NT = 64, CB = 4, GMAX = 4 * RBF;
+    constexpr int NT = 64, CB = 4 / WC, GMAX = (4 / WC) * RBF;
     constexpr int NTP = NT + (sizeof(T) == 4 ? 16 : 8);
     extern __shared__ unsigned char smem_raw[];
     T* Bs = reinterpret_cast<T*>(smem_raw);   // [KP][NTP]
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     // row-block group of this wave: blocks of a work item along y split the
     // output rows (every block stages all of the sources)
-    const int wy = (GY > 1 ? (int)blockIdx.y * 4 : 0) + w;
+    const int wy = (GY > 1 ? (int)blockIdx.y * 4 : 0) + w / WC, wc = w % WC;
     // source staging: thread (column gj, part gpart) moves coefficients
     // 16 i + 4 gpart + e of column gj; the lanes of a wave take 64 columns, so
     // their LDS stores fall in distinct banks
@@ -265,7 +269,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
                     staged_next = true;
                 }
             }
-            mma_block<T, RB, CB>(Aw, Bs, NTP, KB, wy, l, acc);
+            mma_block<T, RB, CB>(Aw, Bs + wc * CB * 16, NTP, KB, wy, l, acc);
             if constexpr (MT) accumulate<T, RB, CB>(acc, tot, cmp);
         }
 #pragma unroll
@@ -274,7 +278,7 @@ __global__ void __launch_bounds__(256) k_batched(const T* __restrict__ in, T* ou
             if (rbg >= KB) continue;
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
-                const int d = dst[(size_t)wi * NT + cb * 16 + (l & 15)];
+                const int d = dst[(size_t)wi * NT + (wc * CB + cb) * 16 + (l & 15)];
                 if (d < 0) continue;
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -298,8 +302,12 @@ static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, 
     // few work items (coarse levels) leave most CUs idle: split the output
     // row blocks of each item over two blocks (y), each staging the sources
     const int KB = A.KP / 16, n = w1 - w0;
-    const int RB = (KB + 3) / 4;
+    int RB = (KB + 3) / 4;
     const int gy = (!XF && n < 512 && RB >= 2) ? 2 : 1;
+    // FP32, KB = 2 or 6: waves as 2 x 2 (rows x column halves), KB / 2 row
+    // blocks each (in FP64 the three blocks' registers cost occupancy)
+    const bool wc2 = sizeof(T) == 4 && gy == 1 && (KB == 2 || KB == 6);
+    if (wc2) RB = (KB + 1) / 2;
     const size_t sm = sizeof(T) * ((size_t)A.KP * (64 + (sizeof(T) == 4 ? 16 : 8)) + (XF ? (size_t)(A.p + 1) * 128 : 0));
     // schedule bits 1-2: 0 one block per item, else 256 CUs x {2, 4, 8} resident blocks looping over the items
     const int pers = (A.batch_sched >> 1) & 3;
@@ -308,13 +316,21 @@ static void launch_batched_x(const EvalArgs<T>& A, int w0, int w1, const T* in, 
 #define LPB_BATCHED_MT(R, MT)                                                                                               \
     if constexpr (!XF) {                                                                                                    \
         if (gy == 2) {                                                                                                      \
-            hipLaunchKernelGGL((k_batched<T, R, XF, 2, MT>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src,        \
+            hipLaunchKernelGGL((k_batched<T, R, XF, 2, MT, 1>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src,     \
                                A.bw_dst, w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab,      \
                                A.refl_sign, A.p);                                                                           \
             break;                                                                                                          \
         }                                                                                                                   \
     }                                                                                                                       \
-    hipLaunchKernelGGL((k_batched<T, R, XF, 1, MT>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst,     \
+    if constexpr (sizeof(T) == 4 && (R == 1 || R == 3)) {                                                                   \
+        if (wc2) {                                                                                                          \
+            hipLaunchKernelGGL((k_batched<T, R, XF, 1, MT, 2>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src,     \
+                               A.bw_dst, w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab,      \
+                               A.refl_sign, A.p);                                                                           \
+            break;                                                                                                          \
+        }                                                                                                                   \
+    }                                                                                                                       \
+    hipLaunchKernelGGL((k_batched<T, R, XF, 1, MT, 1>), g, b, sm, st, in, out, A.bw_term_ptr, A.bw_op, A.bw_src, A.bw_dst,  \
                        w0, n, mode, A.K, A.KP, A.pool_swz, zrow, A.batch_sched, A.bw_xc, A.rot_tab, A.refl_sign, A.p)
     // M2M items sum eight terms (mode 0 without a transform); L2L and untiled
     // M2L items have one
@@ -343,25 +359,38 @@ static void launch_batched(const EvalArgs<T>& A, int w0, int w1, const T* in, in
 }
 
 // V-list pairs outside the tiled levels: LE[box] += sum of the box's pair rows
-// of the scratch, in list order (deterministic), each brought back from the
-// frame of its stored operator (reflection signs, or the rotation of every
-// order-m (Re, Im) pair by -m phi, which needs the partner row of the pair).
-// A thread takes one coefficient row, four pairs' loads in flight at a time.
-// In FP32 the sum is compensated (Kahan), so it keeps the error of a single
+// of the scratch, each brought back from the frame of its stored operator
+// (reflection signs, or the rotation of every order-m (Re, Im) pair by
+// -m phi): row' = a row + b partner row with (a, b) from a table per
+// transform code and row.  A 256-thread block per box: lane l of wave w
+// takes row 64 c + l (c = 0, 1, ... over the rows) and the chunks of eight
+// consecutive pairs w, w + 4, ... of the box's list in order (the last
+// pairs one by one), a chunk's loads in flight together; the
+// partner row (the neighbouring row, always in the same 64-row chunk for
+// p <= 20) comes from the neighbouring lane.  Wave 0 then adds the other
+// waves' sums in wave order, so the result does not depend on timing.  In
+// FP32 the sums are compensated (Kahan), so they keep the error of a single
 // pair's product.
 template <typename T>
-__global__ void k_m2l_reduce(EvalArgs<T> A)
+__global__ void __launch_bounds__(256) k_m2l_reduce(EvalArgs<T> A)
 {
+    typedef typename Vec2<T>::type V2;
+    constexpr int G = 4, U = 8;
+    __shared__ T part[2][G - 1][64];
     const int le = A.m2l_boxes[blockIdx.x];
     const int k0 = A.m2l_ptr[le], k1 = A.m2l_ptr[le + 1];
-    const int p = A.p;
-    for (int row = threadIdx.x; row < A.K; row += blockDim.x) {
-        // (n, m) of the row, whether it is the Im part, and its partner row
+    const int K = A.K;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), l = threadIdx.x & 63;
+    const V2* __restrict__ xf = reinterpret_cast<const V2*>(A.xf_ab);
+    for (int rc = 0; rc < K; rc += 64) {
+        const int row = rc + l;
+        const bool live = row < K;
+        // the partner row of an order-m (Re, Im) pair: (n^2 + 2m - 1, n^2 + 2m)
         int n = 0;
         while ((n + 1) * (n + 1) <= row) ++n;
-        const int idx = row - n * n, m = (idx + 1) / 2;
-        const bool im_row = m > 0 && (idx & 1) == 0;
-        const int partner = m == 0 ? row : (im_row ? row - 1 : row + 1);
+        const int idx = row - n * n;
+        const int plane = idx == 0 ? l : ((idx & 1) ? l + 1 : l - 1);
+        const int rr = live ? row : 0;
         T s = T(0), c = T(0);
         auto add = [&](T a) {
             if constexpr (sizeof(T) == 4) {
@@ -372,29 +401,50 @@ __global__ void k_m2l_reduce(EvalArgs<T> A)
                 s += a;
             }
         };
-        auto term = [&](int code, T own, T other) {
-            if (code < kXfRotate) return own * A.refl_sign[(size_t)code * A.KP + row];
-            if (m == 0) return own;
-            const T* r = A.rot_tab + ((size_t)(code - kXfRotate) * (p + 1) + m) * 2;
-            // Re' = Re c + Im s, Im' = Im c - Re s
-            return im_row ? own * r[0] - other * r[1] : own * r[0] + other * r[1];
-        };
-        int k = k0;
-        for (; k + 4 <= k1; k += 4) {
-            int code[4];
-            T own[4], other[4];
+        // chunks of U consecutive pairs, chunk i to wave i mod G; then the
+        // last pairs one by one, pair j to wave j mod G
+        const int nfull = (k1 - k0) / U;
+        for (int ci = w; ci < nfull; ci += G) {
+            const int k = k0 + ci * U;
+            int code[U];
+            T own[U];
+            V2 ab[U];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                code[u] = A.m2l_xc[k + u];
-                own[u] = A.m2l_scratch[(size_t)(k + u) * A.K + row];
-                other[u] = A.m2l_scratch[(size_t)(k + u) * A.K + partner];
+            for (int u = 0; u < U; ++u) code[u] = A.m2l_xc[k + u];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                own[u] = A.m2l_scratch[(size_t)(k + u) * K + rr];
+                ab[u] = xf[(size_t)code[u] * K + rr];
             }
 #pragma unroll
-            for (int u = 0; u < 4; ++u) add(term(code[u], own[u], other[u]));
+            for (int u = 0; u < U; ++u) {
+                if (!live) own[u] = T(0);
+                const T other = __shfl(own[u], plane);
+                add(own[u] * ab[u].x + other * ab[u].y);
+            }
         }
-        for (; k < k1; ++k)
-            add(term(A.m2l_xc[k], A.m2l_scratch[(size_t)k * A.K + row], A.m2l_scratch[(size_t)k * A.K + partner]));
-        A.le[(size_t)le * A.KP + row] += s;
+        for (int k = k0 + nfull * U + w; k < k1; k += G) {
+            const V2 ab = xf[(size_t)A.m2l_xc[k] * K + rr];
+            T own = A.m2l_scratch[(size_t)k * K + rr];
+            if (!live) own = T(0);
+            const T other = __shfl(own, plane);
+            add(own * ab.x + other * ab.y);
+        }
+        if (w > 0) {
+            part[0][w - 1][l] = s;
+            part[1][w - 1][l] = c;
+        }
+        __syncthreads();
+        if (w == 0 && live) {
+            // a wave's compensated sum is s - c
+#pragma unroll
+            for (int g = 0; g < G - 1; ++g) {
+                add(part[0][g][l]);
+                if constexpr (sizeof(T) == 4) add(-part[1][g][l]);
+            }
+            A.le[(size_t)le * A.KP + row] += s;
+        }
+        __syncthreads();
     }
 }
 
@@ -819,7 +869,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     const bool split = list && fk && fk->side && !ev && A.n_tiles > 0;
     auto run_list = [&](hipStream_t s) {
         launch_batched_x<T, true>(A, S.bm2l_w0, S.bm2l_w1, A.me, A.n_me, A.m2l_scratch, 0, s);
-        hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(128), 0, s, A);
+        hipLaunchKernelGGL(k_m2l_reduce<T>, dim3(S.n_m2l_boxes), dim3(256), 0, s, A);
     };
     if (split) {
         hipError_t e = hipEventRecord(fk->fork, st);

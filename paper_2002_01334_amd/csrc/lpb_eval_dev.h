@@ -83,6 +83,9 @@ __device__ inline int sched_index(int b, int n, int sched)
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { typedef float type __attribute__((ext_vector_type(4))); };
 template <> struct Vec4<double> { typedef double type __attribute__((ext_vector_type(4))); };
+template <typename T> struct Vec2;
+template <> struct Vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
 
 __device__ inline Vec4<float>::type mfma16(float a, float b, Vec4<float>::type c)
 {
