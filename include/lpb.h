@@ -225,8 +225,9 @@ lpb_status lpb_evaluate_batch(lpb_ctx* ctx, int n_sys, const double* const* q, d
  * tight serving loops, harnesses that forbid hipMalloc): lpb_evaluate with
  * device pointers that calls no allocating routine.  q[n] and phi[n] are
  * device memory of the context's GPU, in input order; phi may not alias q.
- * The partial potentials of the output slots (n_slots * n doubles, n_slots
- * = 1 for a single layer, 3 otherwise) live in a
+ * The partial potentials of the output slots (n_slots * n doubles: the
+ * component slots, 1 for a single layer, 3 otherwise, and one for the
+ * free-space near field, so n_slots = 2 or 4) live in a
  * library-wide device array of LPB_NOALLOC_MAX_PARTS doubles (96 MiB) that
  * each GPU the library runs on holds until the process ends; every call on a
  * GPU shares that GPU's array (cleared at the start of each call), so calls

@@ -301,8 +301,11 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
     A.p = P.p;
     A.K = P.K;
     A.KP = (P.K + 15) / 16 * 16;
-    A.nslots = P.nslots;
+    // the component slots, then the free-space near field's slot (added to
+    // slot 0 by the final sum)
+    A.nslots = P.nslots + 1;
     A.ncharges = P.ncharges;
+    A.near_off = (int64_t)P.nslots * P.ncharges;
     A.n_src = (int)P.n_spts;
     A.quad_tol = c->opt.quad_tol;
     // FMM records
@@ -642,7 +645,7 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
         if ((s = dalloc<T>(c, c->plan_bufs, P.m2l_src.size() * (size_t)A.K, &scr)) != LPB_OK) return s;
     A.m2l_scratch = scr;
     double* parts;
-    if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.nslots * P.ncharges, &parts)) != LPB_OK) return s;
+    if ((s = dalloc<double>(c, c->plan_bufs, (size_t)(P.nslots + 1) * P.ncharges, &parts)) != LPB_OK) return s;
     A.parts = parts;
     if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.ncharges, &c->d_q)) != LPB_OK) return s;
     if ((s = dalloc<double>(c, c->plan_bufs, (size_t)P.ncharges, &c->d_phi)) != LPB_OK) return s;
@@ -1067,7 +1070,10 @@ lpb_status lpb_create(const lpb_options* opt, lpb_ctx** out)
         if (hipEventCreate(&e) != hipSuccess) return fail(nullptr, LPB_EDEVICE, "event create failed");
     if (hipStreamCreateWithFlags(&c->fork.side, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->fork.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&c->fork.join, hipEventDisableTiming) != hipSuccess)
+        hipEventCreateWithFlags(&c->fork.join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->fork.near, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork.near_fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->fork.near_join, hipEventDisableTiming) != hipSuccess)
         return fail(nullptr, LPB_EDEVICE, "side stream create failed");
     *out = c;
     guard.c = nullptr;
@@ -1165,7 +1171,7 @@ lpb_status lpb_evaluate_noalloc(lpb_ctx* c, const double* q, double* phi)
     if (!c->have_layers || !c->have_tree || c->ops_dirty || !c->prepared)
         return fail(c, LPB_ESTATE, "context not prepared: run lpb_evaluate once after lpb_set_layers / lpb_build_tree");
     const Plan& P = c->plan;
-    const uint64_t need = (uint64_t)P.nslots * (uint64_t)P.ncharges;
+    const uint64_t need = (uint64_t)(P.nslots + 1) * (uint64_t)P.ncharges;
     if (need > (uint64_t)LPB_NOALLOC_MAX_PARTS)
         return fail(c, LPB_ERANGE, "n_slots * n = " + std::to_string(need) + " partial potentials exceed LPB_NOALLOC_MAX_PARTS = " +
                                        std::to_string((uint64_t)LPB_NOALLOC_MAX_PARTS));
@@ -1290,8 +1296,13 @@ lpb_status lpb_debug_parts(const lpb_ctx* c, double* out, int* nslots)
     *nslots = c->plan.nslots;
     if (!out || !c->have_tree) return LPB_OK;
     const double* parts = (c->opt.precision == LPB_MIXED) ? c->a32.parts : c->a64.parts;
-    size_t n = (size_t)c->plan.nslots * c->plan.ncharges;
-    if (n && hipMemcpy(out, parts, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return LPB_EDEVICE;
+    const size_t nc = (size_t)c->plan.ncharges, n = (size_t)c->plan.nslots * nc;
+    if (!n) return LPB_OK;
+    if (hipMemcpy(out, parts, n * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return LPB_EDEVICE;
+    // the free-space near field's own slot, added to slot 0
+    std::vector<double> near(nc);
+    if (hipMemcpy(near.data(), parts + n, nc * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess) return LPB_EDEVICE;
+    for (size_t i = 0; i < nc; ++i) out[i] += near[i];
     return LPB_OK;
 }
 
@@ -1314,6 +1325,9 @@ void lpb_destroy(lpb_ctx* c)
     if (c->fork.side) (void)hipStreamDestroy(c->fork.side);
     if (c->fork.fork) (void)hipEventDestroy(c->fork.fork);
     if (c->fork.join) (void)hipEventDestroy(c->fork.join);
+    if (c->fork.near) (void)hipStreamDestroy(c->fork.near);
+    if (c->fork.near_fork) (void)hipEventDestroy(c->fork.near_fork);
+    if (c->fork.near_join) (void)hipEventDestroy(c->fork.near_join);
     if (c->ev0) (void)hipEventDestroy(c->ev0);
     if (c->ev1) (void)hipEventDestroy(c->ev1);
     for (auto& e : c->evs)

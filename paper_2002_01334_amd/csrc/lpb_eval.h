@@ -9,6 +9,7 @@ struct EvalArgs {
     int p, K, nslots;
     int KP;             // padded coefficient stride of ME/LE rows (multiple of 16, >= K)
     int64_t ncharges;
+    int64_t near_off;           // start of the free-space near-field slot in parts (after the component slots)
     const FmmDev* fmm;
     const Medium* media;
     // sources (sorted by FMM, leaf)
@@ -102,10 +103,15 @@ struct EvalSched {
 
 // A second stream for the untiled V-list translations, which then run beside
 // the tiled M2L (they write other LE boxes): `fork` is recorded on the main
-// stream before them, `join` on the side stream after them.
+// stream before them, `join` on the side stream after them.  A third stream
+// takes the free-space near field, which writes a slot of its own and so runs
+// beside the whole far field (`near_fork` after the charges are gathered and
+// the slots cleared, `near_join` before the slots are summed).
 struct EvalFork {
     hipStream_t side = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t near = nullptr;
+    hipEvent_t near_fork = nullptr, near_join = nullptr;
 };
 
 // One evaluation.  With per-stage events (ev) or without a fork every pass

@@ -583,7 +583,7 @@ __global__ void __launch_bounds__(64) k_p2p_free(EvalArgs<T> A)
         }
         // combine the two halves (lane l and l+32 share a target)
         T other = __shfl_xor(sum - comp, 32, 64);
-        if (act && half == 0) A.parts[A.t_out[j]] += ((double)(sum - comp) + (double)other) / (4.0 * LPB_PI * F.eps_t);
+        if (act && half == 0) A.parts[A.near_off + A.t_out[j]] += ((double)(sum - comp) + (double)other) / (4.0 * LPB_PI * F.eps_t);
     }
 }
 
@@ -749,7 +749,7 @@ __global__ void __launch_bounds__(64) k_p2p_free32(EvalArgs<float> A)
         const float other = __shfl(mine, min(tl + q * T, 63), 64);
         if (q < S) tot += (double)other;
     }
-    if (act && s == 0) A.parts[A.t_out[j]] += tot * sc / (4.0 * LPB_PI * F.eps_t);
+    if (act && s == 0) A.parts[A.near_off + A.t_out[j]] += tot * sc / (4.0 * LPB_PI * F.eps_t);
 }
 
 // ---------------------------------------------------------------------------
@@ -838,6 +838,19 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     hipLaunchKernelGGL(k_zero<double>, dim3(1024), dim3(256), 0, st, (size_t)A.nslots * A.ncharges, A.parts);
     if (A.n_le > 0) hipLaunchKernelGGL(k_zero<T>, dim3(1024), dim3(256), 0, st, (size_t)A.n_le * A.KP, A.le);
     const bool far = stages & 1, near = stages & 2;
+    // the free-space near field (its own slot) on the third stream beside the far field
+    const bool near_split = near && S.n_p2p_free > 0 && far && fk && fk->near && !ev;
+    auto run_near_free = [&](hipStream_t s) {
+        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL(k_p2p_free32, dim3(S.n_p2p_free), dim3(64), 0, s, A);
+        else hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, s, A);
+    };
+    if (near_split) {
+        hipError_t e = hipEventRecord(fk->near_fork, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fk->near, fk->near_fork, 0);
+        if (e != hipSuccess) return e;
+        run_near_free(fk->near);
+        if ((e = hipEventRecord(fk->near_join, fk->near)) != hipSuccess) return e;
+    }
     LPB_MARK(1);
     // upward pass
     // point chunks sized so that a block's LDS stays under 24 KB (several blocks per CU)
@@ -903,14 +916,15 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     if (far) launch_m2p<T>(A, st);
     // near field
     LPB_MARK(7);
-    if (near && S.n_p2p_free > 0) {
-        if constexpr (sizeof(T) == 4) hipLaunchKernelGGL(k_p2p_free32, dim3(S.n_p2p_free), dim3(64), 0, st, A);
-        else hipLaunchKernelGGL(k_p2p_free<T>, dim3(S.n_p2p_free), dim3(64), 0, st, A);
-    }
+    if (near && S.n_p2p_free > 0 && !near_split) run_near_free(st);
     LPB_MARK(8);
     if (near && A.n_react_targets > 0)
         hipLaunchKernelGGL(k_p2p_react<T>, dim3((A.n_react_targets + 63) / 64), dim3(64), 0, st, A);
     LPB_MARK(9);
+    if (near_split) {
+        hipError_t e = hipStreamWaitEvent(st, fk->near_join, 0);
+        if (e != hipSuccess) return e;
+    }
     if (A.ncharges > 0)
         hipLaunchKernelGGL(k_sum, dim3((unsigned)((A.ncharges + 255) / 256)), dim3(256), 0, st, A.ncharges, A.nslots, A.parts, A.phi);
     LPB_MARK(10);
