@@ -25,7 +25,11 @@
  *    tells which (1 = device memory of the context's GPU, 0 = host memory).
  *    The caller owns every array it passes and the library never frees it.
  *  - A context belongs to one GPU and one HIP stream (lpb_options.stream,
- *    NULL = the null stream).  Calls on one context are not thread-safe.
+ *    NULL = the null stream).  An evaluation forks two internal streams of
+ *    the context (default priority) from it, for the untiled V-list
+ *    translations and the free-space near field, and joins them back on it
+ *    before its last kernel, so all of its work is ordered on the caller's
+ *    stream.  Calls on one context are not thread-safe.
  *  - Call order: lpb_set_layers, then lpb_build_tree, then lpb_evaluate
  *    (repeatable with new charges).  Calling lpb_set_layers again rebuilds
  *    the plan for the stored charge positions; lpb_build_tree again replaces
@@ -233,8 +237,9 @@ lpb_status lpb_evaluate_batch(lpb_ctx* ctx, int n_sys, const double* const* q, d
  * GPU shares that GPU's array (cleared at the start of each call), so calls
  * that overlap on one GPU (several contexts, streams or threads) race and
  * must be serialized by the caller.  The passes are launched one by one on
- * the context's stream with the schedules the context already chose (no
- * graph instantiation, no autotuning), then the call waits for the stream.
+ * the context's stream (and its two internal streams, joined back) with the
+ * schedules the context already chose (no graph instantiation, no
+ * autotuning), then the call waits for the stream.
  * The context must be prepared: a single-system context on which
  * lpb_evaluate has run since the last lpb_set_layers / lpb_build_tree (that
  * call generates the operators and picks the schedules).  Results are bit
