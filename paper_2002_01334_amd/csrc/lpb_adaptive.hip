@@ -68,61 +68,70 @@ __device__ __attribute__((always_inline)) inline void bessel_k_fixed(int p_rt, d
     for (int n = 1; n < p; ++n) out[n + 1] = out[n - 1] + (2.0 * n + 1.0) * xi * out[n];
 }
 
-// M2P: one 64-lane block per target leaf with W-list entries, one lane per
-// target (64 at a time), every lane reading the entry's expansion itself.
+// M2P: one 256-thread block per target leaf with W-list entries, one lane
+// per target (64 at a time); wave w takes the entries w, w + 4, ... in
+// order, every lane reading the entry's expansion itself, and wave 0 adds
+// the other waves' sums in wave order.
 template <typename T, int P>
-__global__ void __launch_bounds__(64) k_m2p(EvalArgs<T> A)
+__global__ void __launch_bounds__(256) k_m2p(EvalArgs<T> A)
 {
+    constexpr int G = 4;
     extern __shared__ double sm_m2p[];
     const int p = P > 0 ? P : A.p, K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2;
-    double* tab = sm_m2p;               // amm[p+1], alpha[Kp], beta[Kp]
+    double* tab = sm_m2p;                        // amm[p+1], alpha[Kp], beta[Kp]
+    double* part = sm_m2p + p + 1 + 2 * Kp;      // [G - 1][64]: the other waves' sums
     const int leaf = A.w_leaves[blockIdx.x];
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const int e0 = A.w_ptr[leaf], e1 = A.w_ptr[leaf + 1];
     const double tcx = A.tl_ctr[3 * leaf], tcy = A.tl_ctr[3 * leaf + 1], tcz = A.tl_ctr[3 * leaf + 2];
-    const int lane = threadIdx.x;
-    for (int k = lane; k < p + 1 + 2 * Kp; k += 64) tab[k] = A.sh64[k];
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    for (int k = threadIdx.x; k < p + 1 + 2 * Kp; k += 64 * G) tab[k] = A.sh64[k];
     __syncthreads();
     const double *amm = tab, *al = tab + p + 1, *be = tab + p + 1 + Kp;
     for (int base = t0; base < t1; base += 64) {
         const int j = base + lane;
         const bool act = j < t1;
-        if (!act) break;
-        double ux = 0.0, uy = 0.0, uz = 0.0;
-        if (act) {
-            ux = (double)A.t_ux[j] + (A.t_lx ? (double)A.t_lx[j] : 0.0);
-            uy = (double)A.t_uy[j] + (A.t_ly ? (double)A.t_ly[j] : 0.0);
-            uz = (double)A.t_uz[j] + (A.t_lz ? (double)A.t_lz[j] : 0.0);
-        }
         double acc = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const int fid = A.w_fmm[e];
-            const FmmDev& F = A.fmm[fid];
-            // the entry's expansion: the same addresses in every lane (read
-            // through the caches, no staging or barriers)
-            const T* __restrict__ M = A.me + (size_t)A.w_me[e] * A.KP;
-            if (F.kind == 1) {
-                const double* v = A.pt_vec + A.w_vec[e] + (int64_t)(j - t0) * K;
+        if (act) {
+            const double ux = (double)A.t_ux[j] + (A.t_lx ? (double)A.t_lx[j] : 0.0);
+            const double uy = (double)A.t_uy[j] + (A.t_ly ? (double)A.t_ly[j] : 0.0);
+            const double uz = (double)A.t_uz[j] + (A.t_lz ? (double)A.t_lz[j] : 0.0);
+            for (int e = e0 + w; e < e1; e += G) {
+                const int fid = A.w_fmm[e];
+                const FmmDev& F = A.fmm[fid];
+                // the entry's expansion: the same addresses in every lane
+                // (read through the caches, no staging or barriers)
+                const T* __restrict__ M = A.me + (size_t)A.w_me[e] * A.KP;
+                if (F.kind == 1) {
+                    const double* v = A.pt_vec + A.w_vec[e] + (int64_t)(j - t0) * K;
+                    double s = 0.0;
+                    for (int k = 0; k < K; ++k) s += v[k] * (double)M[k];
+                    acc += s;
+                    continue;
+                }
+                // free space: the target's offset from the source box centre
+                const double vx = ux + (tcx - A.w_ctr[3 * e]), vy = uy + (tcy - A.w_ctr[3 * e + 1]),
+                             vz = uz + (tcz - A.w_ctr[3 * e + 2]);
+                const double r = sqrt(vx * vx + vy * vy + vz * vz);
+                double kn[(P > 0 ? P : LPB_MAX_P) + 1];
+                bessel_k_fixed<P>(p, F.lam_s * r, kn);
+                const double* sc = A.fin_s + ((size_t)fid * (kMaxDepth + 1) + A.w_lv[e]) * (LPB_MAX_P + 1);
                 double s = 0.0;
-                for (int k = 0; k < K; ++k) s += v[k] * (double)M[k];
-                acc += s;
-                continue;
+                unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
+                    const double re = (double)M[ire(n, m)], im = m ? (double)M[iim(n, m)] : 0.0;
+                    s += (m ? 2.0 : 1.0) * sc[n] * kn[n] * (re * cr - im * ci);
+                });
+                acc += F.far_factor * s;
             }
-            // free space: the target's offset from the source box centre
-            const double vx = ux + (tcx - A.w_ctr[3 * e]), vy = uy + (tcy - A.w_ctr[3 * e + 1]),
-                         vz = uz + (tcz - A.w_ctr[3 * e + 2]);
-            const double r = sqrt(vx * vx + vy * vy + vz * vz);
-            double kn[(P > 0 ? P : LPB_MAX_P) + 1];
-            bessel_k_fixed<P>(p, F.lam_s * r, kn);
-            const double* sc = A.fin_s + ((size_t)fid * (kMaxDepth + 1) + A.w_lv[e]) * (LPB_MAX_P + 1);
-            double s = 0.0;
-            unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
-                const double re = (double)M[ire(n, m)], im = m ? (double)M[iim(n, m)] : 0.0;
-                s += (m ? 2.0 : 1.0) * sc[n] * kn[n] * (re * cr - im * ci);
-            });
-            acc += F.far_factor * s;
         }
-        A.parts[A.t_out[j]] += acc;
+        if (w > 0) part[(w - 1) * 64 + lane] = acc;
+        __syncthreads();
+        if (w == 0 && act) {
+#pragma unroll
+            for (int g = 0; g < G - 1; ++g) acc += part[g * 64 + lane];
+            A.parts[A.t_out[j]] += acc;
+        }
+        __syncthreads();
     }
 }
 
@@ -209,13 +218,13 @@ void launch_m2p(const EvalArgs<T>& A, hipStream_t st)
 {
     const int Kp = (A.p + 1) * (A.p + 2) / 2;
     if (A.n_w_leaves <= 0) return;
-    const size_t sm = sizeof(double) * (A.p + 1 + 2 * Kp);
+    const size_t sm = sizeof(double) * (A.p + 1 + 2 * Kp + 3 * 64);
 #define LPB_M2P(PP) \
-    case PP: hipLaunchKernelGGL((k_m2p<T, PP>), dim3(A.n_w_leaves), dim3(64), sm, st, A); break;
+    case PP: hipLaunchKernelGGL((k_m2p<T, PP>), dim3(A.n_w_leaves), dim3(256), sm, st, A); break;
     switch (A.p) {
         LPB_M2P(2) LPB_M2P(3) LPB_M2P(4) LPB_M2P(5) LPB_M2P(6) LPB_M2P(7) LPB_M2P(8) LPB_M2P(9) LPB_M2P(10)
         LPB_M2P(11) LPB_M2P(12) LPB_M2P(13) LPB_M2P(14) LPB_M2P(15)
-    default: hipLaunchKernelGGL((k_m2p<T, 0>), dim3(A.n_w_leaves), dim3(64), sm, st, A); break;
+    default: hipLaunchKernelGGL((k_m2p<T, 0>), dim3(A.n_w_leaves), dim3(256), sm, st, A); break;
     }
 #undef LPB_M2P
 }
