@@ -136,9 +136,10 @@ __global__ void __launch_bounds__(256) k_m2p(EvalArgs<T> A)
 }
 
 // P2L: one 64-lane block per target box with X-list entries.  Free space:
-// per chunk of CH sources each lane forms its source's scaled row in LDS,
-// then lanes sum rows; reaction: each lane takes coefficients k and sums
-// q times the point operators over the leaf's sources.
+// the sources of all the box's free-space entries in one sequence, per chunk
+// of CH of them each lane forms its source's scaled row in LDS, then lanes
+// sum rows; reaction: each lane takes coefficients k and sums q times the
+// point operators over the leaf's sources.
 template <typename T, int P>
 __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A, int CH)
 {
@@ -155,54 +156,69 @@ __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A, int CH)
     double acc[(LPB_KMAX + 63) / 64];
 #pragma unroll
     for (int kk = 0; kk < (LPB_KMAX + 63) / 64; ++kk) acc[kk] = 0.0;
-    for (int e = A.x_box_ptr[b]; e < A.x_box_ptr[b + 1]; ++e) {
-        const int fid = A.x_fmm[e];
-        const FmmDev& F = A.fmm[fid];
+    const int e0 = A.x_box_ptr[b], e1 = A.x_box_ptr[b + 1];
+    // free-space entries: their sources as one sequence (entry order), CH at
+    // a time, so that the lanes stay busy across entries with few sources
+    int tot = 0;
+    for (int e = e0; e < e1; ++e)
+        if (A.fmm[A.x_fmm[e]].kind != 1) tot += A.sl_start[A.x_sl[e] + 1] - A.sl_start[A.x_sl[e]];
+    for (int base = 0; base < tot; base += CH) {
+        __syncthreads();
+        if (lane < CH && base + lane < tot) {
+            // the entry and source of position base + lane
+            // (always found: base + lane < tot)
+            int e = e0, off = base + lane, sl = 0, fid = 0;
+            for (; e < e1; ++e) {
+                fid = A.x_fmm[e];
+                if (A.fmm[fid].kind == 1) continue;
+                sl = A.x_sl[e];
+                const int n = A.sl_start[sl + 1] - A.sl_start[sl];
+                if (off < n) break;
+                off -= n;
+            }
+            const FmmDev& F = A.fmm[fid];
+            const int j = A.sl_start[sl] + off;
+            const double* sc = A.fin_t + ((size_t)fid * (kMaxDepth + 1) + A.x_box_lv[b]) * (LPB_MAX_P + 1);
+            const double vx = (double)A.s_ux[j] + (A.s_lx ? (double)A.s_lx[j] : 0.0) + (A.sl_ctr[3 * sl] - cx);
+            const double vy = (double)A.s_uy[j] + (A.s_ly ? (double)A.s_ly[j] : 0.0) + (A.sl_ctr[3 * sl + 1] - cy);
+            const double vz = (double)A.s_uz[j] + (A.s_lz ? (double)A.s_lz[j] : 0.0) + (A.sl_ctr[3 * sl + 2] - cz);
+            const double r = sqrt(vx * vx + vy * vy + vz * vz);
+            double kn[(P > 0 ? P : LPB_MAX_P) + 1];
+            bessel_k_fixed<P>(p, F.lam_t * r, kn);
+            const double q = (double)A.qs[j];
+            double* row = rows + lane;
+            unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
+                // Lh_nm += q i_n(lam h) 4 pi k_n conj(Y_n^m)
+                const double g = q * sc[n] * kn[n];
+                row[(size_t)ire(n, m) * (CH + 1)] = g * cr;
+                if (m > 0) row[(size_t)iim(n, m) * (CH + 1)] = -g * ci;
+            });
+        }
+        __syncthreads();
+        const int cnt = min(CH, tot - base);
+#pragma unroll
+        for (int kk = 0; kk < (LPB_KMAX + 63) / 64; ++kk) {
+            const int k = lane + 64 * kk;
+            if (k < K) {
+                double s = 0.0;
+                for (int jj = 0; jj < cnt; ++jj) s += rows[(size_t)k * (CH + 1) + jj];
+                acc[kk] += s;
+            }
+        }
+    }
+    // reaction entries: each lane takes coefficients k over the leaf's sources
+    for (int e = e0; e < e1; ++e) {
+        const FmmDev& F = A.fmm[A.x_fmm[e]];
+        if (F.kind != 1) continue;
         const int sl = A.x_sl[e];
         const int s0 = A.sl_start[sl], s1 = A.sl_start[sl + 1];
-        if (F.kind == 1) {
-            const double* v = A.pt_vec + A.x_vec[e];
-            for (int j = s0; j < s1; ++j) {
-                const double q = (double)A.qs[j];
-#pragma unroll
-                for (int kk = 0; kk < (LPB_KMAX + 63) / 64; ++kk) {
-                    const int k = lane + 64 * kk;
-                    if (k < K) acc[kk] += q * v[(int64_t)(j - s0) * K + k];
-                }
-            }
-            continue;
-        }
-        const double* sc = A.fin_t + ((size_t)fid * (kMaxDepth + 1) + A.x_box_lv[b]) * (LPB_MAX_P + 1);
-        const double ox = A.sl_ctr[3 * sl] - cx, oy = A.sl_ctr[3 * sl + 1] - cy, oz = A.sl_ctr[3 * sl + 2] - cz;
-        for (int base = s0; base < s1; base += CH) {
-            __syncthreads();
-            const int j = base + lane;
-            if (lane < CH && j < s1) {
-                const double vx = (double)A.s_ux[j] + (A.s_lx ? (double)A.s_lx[j] : 0.0) + ox;
-                const double vy = (double)A.s_uy[j] + (A.s_ly ? (double)A.s_ly[j] : 0.0) + oy;
-                const double vz = (double)A.s_uz[j] + (A.s_lz ? (double)A.s_lz[j] : 0.0) + oz;
-                const double r = sqrt(vx * vx + vy * vy + vz * vz);
-                double kn[(P > 0 ? P : LPB_MAX_P) + 1];
-                bessel_k_fixed<P>(p, F.lam_t * r, kn);
-                const double q = (double)A.qs[j];
-                double* row = rows + lane;
-                unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
-                    // Lh_nm += q i_n(lam h) 4 pi k_n conj(Y_n^m)
-                    const double g = q * sc[n] * kn[n];
-                    row[(size_t)ire(n, m) * (CH + 1)] = g * cr;
-                    if (m > 0) row[(size_t)iim(n, m) * (CH + 1)] = -g * ci;
-                });
-            }
-            __syncthreads();
-            const int cnt = min(CH, s1 - base);
+        const double* v = A.pt_vec + A.x_vec[e];
+        for (int j = s0; j < s1; ++j) {
+            const double q = (double)A.qs[j];
 #pragma unroll
             for (int kk = 0; kk < (LPB_KMAX + 63) / 64; ++kk) {
                 const int k = lane + 64 * kk;
-                if (k < K) {
-                    double s = 0.0;
-                    for (int jj = 0; jj < cnt; ++jj) s += rows[(size_t)k * (CH + 1) + jj];
-                    acc[kk] += s;
-                }
+                if (k < K) acc[kk] += q * v[(int64_t)(j - s0) * K + k];
             }
         }
     }
