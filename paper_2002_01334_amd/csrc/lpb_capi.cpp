@@ -593,6 +593,19 @@ lpb_status fill_args(lpb_ctx* c, EvalArgs<T>& A, DevPointBuilder& pb)
     A.n_react_targets = (int)rleaf.size();
     c->sched.n_p2m = (int)p2m.size();
     c->sched.n_l2p = (int)l2p.size();
+    // leaves per 64-lane block of the fixed-order P2M / L2P: 64 / nl lanes per
+    // leaf, the choice with fewer lane-passes over the leaves' points
+    auto pick_nl = [](const std::vector<int>& leaves, const std::vector<int>& start) {
+        int64_t c2 = 0, c4 = 0;
+        for (int i : leaves) {
+            const int64_t n = start[i + 1] - start[i];
+            c2 += (n + 31) / 32 * 32;
+            c4 += (n + 15) / 16 * 16;
+        }
+        return c4 < c2 ? 4 : 2;
+    };
+    c->sched.p2m_nl = pick_nl(p2m, P.sl_start);
+    c->sched.l2p_nl = pick_nl(l2p, P.tl_start);
     c->sched.n_p2p_free = (int)pfree.size();
     c->sched.n_m2l_boxes = (int)m2lb.size();
     for (int l = 0; l <= kMaxDepth + 1; ++l) {

@@ -96,6 +96,7 @@ struct EvalArgs {
 
 struct EvalSched {
     int n_p2m, n_l2p, n_p2p_free, n_m2l_boxes;
+    int p2m_nl = 2, l2p_nl = 2;   // leaves per 64-lane block of the fixed-order P2M / L2P (2 or 4)
     int bm2m_lv[kMaxDepth + 2];
     int bl2l_lv[kMaxDepth + 2];
     int bm2l_w0, bm2l_w1;
@@ -134,8 +135,9 @@ template <typename T>
 void launch_m2p(const EvalArgs<T>& A, hipStream_t st);
 template <typename T>
 void launch_p2l(const EvalArgs<T>& A, hipStream_t st);
-void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st);
-void launch_l2p_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st);
+// (nl = 2 or 4 leaves per 64-lane block)
+void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, int nl, hipStream_t st);
+void launch_l2p_fixed(const EvalArgs<float>& A, int n_leaves, int nl, hipStream_t st);
 
 // One matrix-core stage alone, for schedule tuning: which = 0 the tiled M2L,
 // 1 the batched translations (M2M, untiled M2L, L2L).  Leaves ME/LE/scratch

@@ -864,7 +864,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     if constexpr (sizeof(T) == 4) p_fixed = p >= 2 && p <= 15;
     if (far && S.n_p2m > 0) {
         if constexpr (sizeof(T) == 4) {
-            if (p_fixed) launch_p2m_fixed(A, S.n_p2m, st);
+            if (p_fixed) launch_p2m_fixed(A, S.n_p2m, S.p2m_nl, st);
         }
         if (!p_fixed) {
             int ch = pick_ch(sizeof(T) * ((size_t)K + p + 1), sizeof(T) * (size_t)K);
@@ -905,7 +905,7 @@ hipError_t eval_run(const EvalArgs<T>& A, const EvalSched& S, int stages, hipStr
     LPB_MARK(6);
     if (far && S.n_l2p > 0) {
         if constexpr (sizeof(T) == 4) {
-            if (p_fixed) launch_l2p_fixed(A, S.n_l2p, st);
+            if (p_fixed) launch_l2p_fixed(A, S.n_l2p, S.l2p_nl, st);
         }
         if (!p_fixed) {
             size_t sm = sizeof(T) * (size_t)(p + 1) * 64;

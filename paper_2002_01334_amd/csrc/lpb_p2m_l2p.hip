@@ -97,18 +97,19 @@ __device__ inline void solid_harmonics(float x, float y, float z, F&& f)
     }
 }
 
-// Two leaves per 64-lane block (a leaf holds about half a wave of sources):
-// half h = lane >> 5 takes leaf 2 blockIdx.x + h, its sources 32 at a time;
-// lane i then sums coefficient c0 + i of both halves' rows.
-template <int P>
+// NL = 2 or 4 leaves per 64-lane block (a leaf holds about half or a quarter
+// of a wave of sources): slot h = lane / (64 / NL) takes leaf NL blockIdx.x + h,
+// its sources 64 / NL at a time; lane i then sums coefficient c0 + i of every
+// slot's rows.
+template <int P, int NL>
 __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A, int n_leaves)
 {
-    constexpr int K = (P + 1) * (P + 1);
+    constexpr int K = (P + 1) * (P + 1), LPL = 64 / NL;
     __shared__ float red[64][65];
-    const int lane = threadIdx.x, h = lane >> 5, hl = lane & 31;
-    const int w = 2 * blockIdx.x + h;
+    const int lane = threadIdx.x, h = lane / LPL, hl = lane % LPL;
+    const int w = NL * blockIdx.x + h;
     const bool on = w < n_leaves;
-    const int leaf = on ? A.p2m_leaves[w] : A.p2m_leaves[2 * blockIdx.x];
+    const int leaf = on ? A.p2m_leaves[w] : A.p2m_leaves[NL * blockIdx.x];
     const FmmDev& F = A.fmm[A.sl_fmm[leaf]];
     const double* __restrict__ ith = A.ith_s + ((size_t)A.sl_fmm[leaf] * (kMaxDepth + 1) + A.sl_lv[leaf]) * (LPB_MAX_P + 1);
     const int s0 = A.sl_start[leaf], s1 = on ? A.sl_start[leaf + 1] : s0;
@@ -116,7 +117,7 @@ __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A, int n_leaves)
     float acc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) acc[k] = 0.f;
-    for (int j = s0 + hl; j < s1; j += 32) {
+    for (int j = s0 + hl; j < s1; j += LPL) {
         const float ux = A.s_ux[j], uy = A.s_uy[j], uz = A.s_uz[j];
         const double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         float g[P + 1];
@@ -128,8 +129,12 @@ __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A, int n_leaves)
                                if (m > 0) acc[iim(n, m)] -= g[n] * im;
                            });
     }
-    const int w1 = 2 * blockIdx.x + 1;
-    const int me0 = A.sl_me[A.p2m_leaves[2 * blockIdx.x]], me1 = w1 < n_leaves ? A.sl_me[A.p2m_leaves[w1]] : -1;
+    int me[NL];
+#pragma unroll
+    for (int hh = 0; hh < NL; ++hh) {
+        const int wh = NL * blockIdx.x + hh;
+        me[hh] = wh < n_leaves ? A.sl_me[A.p2m_leaves[wh]] : -1;
+    }
 #pragma unroll
     for (int c0 = 0; c0 < K; c0 += 64) {
 #pragma unroll
@@ -137,33 +142,33 @@ __global__ void __launch_bounds__(64) k_p2m_p(EvalArgs<float> A, int n_leaves)
             if (c0 + i < K) red[i][lane] = acc[c0 + i];
         __syncthreads();
         if (c0 + lane < K) {
-            float t0 = 0.f, t1 = 0.f;
+#pragma unroll
+            for (int hh = 0; hh < NL; ++hh) {
+                float t = 0.f;
 #pragma unroll 16
-            for (int jj = 0; jj < 32; ++jj) {
-                t0 += red[lane][jj];
-                t1 += red[lane][32 + jj];
+                for (int jj = 0; jj < LPL; ++jj) t += red[lane][hh * LPL + jj];
+                if (me[hh] >= 0) A.me[(size_t)me[hh] * A.KP + c0 + lane] = t;
             }
-            A.me[(size_t)me0 * A.KP + c0 + lane] = t0;
-            if (me1 >= 0) A.me[(size_t)me1 * A.KP + c0 + lane] = t1;
         }
         __syncthreads();
     }
 }
 
-// Two leaves per 64-lane block (a leaf holds about half a wave of targets):
-// half h = lane >> 5 takes leaf 2 blockIdx.x + h, its targets 32 at a time.
-template <int P>
+// NL = 2 or 4 leaves per 64-lane block (a leaf holds about half or a quarter
+// of a wave of targets): slot h = lane / (64 / NL) takes leaf NL blockIdx.x + h,
+// its targets 64 / NL at a time.
+template <int P, int NL>
 __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A, int n_leaves)
 {
-    constexpr int K = (P + 1) * (P + 1);
-    __shared__ float Ls[2][K];   // the leaves' local expansions, read at half-uniform addresses
-    const int h = threadIdx.x >> 5, hl = threadIdx.x & 31;
-    const int w = 2 * blockIdx.x + h;
+    constexpr int K = (P + 1) * (P + 1), LPL = 64 / NL;
+    __shared__ float Ls[NL][K];   // the leaves' local expansions, read at slot-uniform addresses
+    const int h = threadIdx.x / LPL, hl = threadIdx.x % LPL;
+    const int w = NL * blockIdx.x + h;
     const bool on = w < n_leaves;
     const int leaf = on ? A.l2p_leaves[w] : 0;
     if (on) {
         const int le = A.tl_le[leaf];
-        for (int k = hl; k < K; k += 32) Ls[h][k] = A.le[(size_t)le * A.KP + k];
+        for (int k = hl; k < K; k += LPL) Ls[h][k] = A.le[(size_t)le * A.KP + k];
     }
     __syncthreads();
     if (!on) return;
@@ -172,7 +177,7 @@ __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A, int n_leaves)
     const int t0 = A.tl_start[leaf], t1 = A.tl_start[leaf + 1];
     const float hinv = (float)(1.0 / A.tl_h[leaf]);
     const float* L = Ls[h];
-    for (int j = t0 + hl; j < t1; j += 32) {
+    for (int j = t0 + hl; j < t1; j += LPL) {
         const float ux = A.t_ux[j], uy = A.t_uy[j], uz = A.t_uz[j];
         const double r2d = (double)ux * ux + (double)uy * uy + (double)uz * uz;
         float g[P + 1];
@@ -193,10 +198,13 @@ __global__ void __launch_bounds__(64) k_l2p_p(EvalArgs<float> A, int n_leaves)
 }
 
 
-void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st)
+void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, int nl, hipStream_t st)
 {
 #define LPB_P2M(PP) \
-    case PP: hipLaunchKernelGGL(k_p2m_p<PP>, dim3((n_leaves + 1) / 2), dim3(64), 0, st, A, n_leaves); break;
+    case PP:                                                                                                     \
+        if (nl == 4) hipLaunchKernelGGL((k_p2m_p<PP, 4>), dim3((n_leaves + 3) / 4), dim3(64), 0, st, A, n_leaves); \
+        else hipLaunchKernelGGL((k_p2m_p<PP, 2>), dim3((n_leaves + 1) / 2), dim3(64), 0, st, A, n_leaves);         \
+        break;
     switch (A.p) {
         LPB_P2M(2) LPB_P2M(3) LPB_P2M(4) LPB_P2M(5) LPB_P2M(6) LPB_P2M(7) LPB_P2M(8) LPB_P2M(9)
         LPB_P2M(10) LPB_P2M(11) LPB_P2M(12) LPB_P2M(13) LPB_P2M(14) LPB_P2M(15)
@@ -205,10 +213,13 @@ void launch_p2m_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st)
 #undef LPB_P2M
 }
 
-void launch_l2p_fixed(const EvalArgs<float>& A, int n_leaves, hipStream_t st)
+void launch_l2p_fixed(const EvalArgs<float>& A, int n_leaves, int nl, hipStream_t st)
 {
 #define LPB_L2P(PP) \
-    case PP: hipLaunchKernelGGL(k_l2p_p<PP>, dim3((n_leaves + 1) / 2), dim3(64), 0, st, A, n_leaves); break;
+    case PP:                                                                                                     \
+        if (nl == 4) hipLaunchKernelGGL((k_l2p_p<PP, 4>), dim3((n_leaves + 3) / 4), dim3(64), 0, st, A, n_leaves); \
+        else hipLaunchKernelGGL((k_l2p_p<PP, 2>), dim3((n_leaves + 1) / 2), dim3(64), 0, st, A, n_leaves);         \
+        break;
     switch (A.p) {
         LPB_L2P(2) LPB_L2P(3) LPB_L2P(4) LPB_L2P(5) LPB_L2P(6) LPB_L2P(7) LPB_L2P(8) LPB_L2P(9)
         LPB_L2P(10) LPB_L2P(11) LPB_L2P(12) LPB_L2P(13) LPB_L2P(14) LPB_L2P(15)
