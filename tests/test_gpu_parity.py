@@ -464,8 +464,9 @@ def test_every_schedule_gives_the_same_bits(lpb, precision):
 @pytest.mark.parametrize("precision", [0, 1])
 def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
     """Captured evaluation (graph = 1, autotuned schedules) against eager
-    launches with the linear schedules (with and without the side stream of
-    the untiled M2L): several replays with different charges, eager work of
+    launches with the linear schedules (with and without the side streams of
+    the untiled M2L and the free-space near field): several replays with
+    different charges, eager work of
     another context and host synchronisations in between, and a re-capture
     after a new tree; every result bit-identical."""
     import torch
@@ -475,8 +476,8 @@ def test_graph_replays_and_schedules_match_eager_bitwise(lpb, precision):
     t = {k: torch.tensor(getattr(prob, k), dtype=torch.float64, device=dev) for k in "xyzq"}
     g = lpb.Context(p=10, leaf_cap=50, precision=precision, graph=1, autotune=1)
     e = lpb.Context(p=10, leaf_cap=50, precision=precision, graph=0, autotune=0)
-    # per-stage events: every pass on one stream (no side stream for the
-    # untiled M2L)
+    # per-stage events: every pass on one stream (no side streams for the
+    # untiled M2L and the near field)
     s = lpb.Context(p=10, leaf_cap=50, precision=precision, graph=0, autotune=0, timing=1)
     for c in (g, e, s):
         c.set_layers(prob.eps, prob.lam, prob.d)
