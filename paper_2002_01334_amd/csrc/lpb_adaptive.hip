@@ -137,16 +137,17 @@ __global__ void __launch_bounds__(256) k_m2p(EvalArgs<T> A)
 
 // P2L: one 64-lane block per target box with X-list entries.  Free space:
 // the sources of all the box's free-space entries in one sequence, per chunk
-// of CH of them each lane forms its source's scaled row in LDS, then lanes
-// sum rows; reaction: each lane takes coefficients k and sums q times the
-// point operators over the leaf's sources.
+// of CH of them each lane forms its source's scaled row in LDS (FP64
+// arithmetic, the row stored in the precision of the expansions), then lanes
+// sum rows in FP64; reaction: each lane takes coefficients k and sums q
+// times the point operators over the leaf's sources.
 template <typename T, int P>
 __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A, int CH)
 {
     extern __shared__ double sm_p2l[];
     const int p = P > 0 ? P : A.p, K = (p + 1) * (p + 1), Kp = (p + 1) * (p + 2) / 2;
-    double* rows = sm_p2l;                          // [K][CH + 1]
-    double* tab = sm_p2l + (size_t)K * (CH + 1);    // amm, alpha, beta
+    double* tab = sm_p2l;                                        // amm, alpha, beta
+    T* rows = reinterpret_cast<T*>(sm_p2l + p + 1 + 2 * Kp);     // [K][CH + 1], in the precision of the expansions
     const int b = blockIdx.x;
     const int le = A.x_box_le[b];
     const double cx = A.x_box_ctr[3 * b], cy = A.x_box_ctr[3 * b + 1], cz = A.x_box_ctr[3 * b + 2];
@@ -186,12 +187,12 @@ __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A, int CH)
             double kn[(P > 0 ? P : LPB_MAX_P) + 1];
             bessel_k_fixed<P>(p, F.lam_t * r, kn);
             const double q = (double)A.qs[j];
-            double* row = rows + lane;
+            T* row = rows + lane;
             unit_harmonics<P>(p, amm, al, be, vx / r, vy / r, vz / r, [&](int n, int m, double cr, double ci) {
                 // Lh_nm += q i_n(lam h) 4 pi k_n conj(Y_n^m)
                 const double g = q * sc[n] * kn[n];
-                row[(size_t)ire(n, m) * (CH + 1)] = g * cr;
-                if (m > 0) row[(size_t)iim(n, m) * (CH + 1)] = -g * ci;
+                row[(size_t)ire(n, m) * (CH + 1)] = (T)(g * cr);
+                if (m > 0) row[(size_t)iim(n, m) * (CH + 1)] = (T)(-g * ci);
             });
         }
         __syncthreads();
@@ -201,7 +202,7 @@ __global__ void __launch_bounds__(64) k_p2l(EvalArgs<T> A, int CH)
             const int k = lane + 64 * kk;
             if (k < K) {
                 double s = 0.0;
-                for (int jj = 0; jj < cnt; ++jj) s += rows[(size_t)k * (CH + 1) + jj];
+                for (int jj = 0; jj < cnt; ++jj) s += (double)rows[(size_t)k * (CH + 1) + jj];
                 acc[kk] += s;
             }
         }
@@ -252,8 +253,8 @@ void launch_p2l(const EvalArgs<T>& A, hipStream_t st)
     const int Kp = (A.p + 1) * (A.p + 2) / 2;
     if (A.n_x_boxes <= 0) return;
     int ch = 64;
-    while (ch > 8 && sizeof(double) * (size_t)A.K * (ch + 1) > 48u * 1024u) ch >>= 1;
-    const size_t sm = sizeof(double) * ((size_t)A.K * (ch + 1) + A.p + 1 + 2 * Kp);
+    while (ch > 8 && sizeof(T) * (size_t)A.K * (ch + 1) > 48u * 1024u) ch >>= 1;
+    const size_t sm = sizeof(T) * (size_t)A.K * (ch + 1) + sizeof(double) * (A.p + 1 + 2 * Kp);
 #define LPB_P2L(PP) \
     case PP: hipLaunchKernelGGL((k_p2l<T, PP>), dim3(A.n_x_boxes), dim3(64), sm, st, A, ch); break;
     switch (A.p) {
